@@ -1,0 +1,284 @@
+"""ctypes binding of the FP64 CPU oracle (test infrastructure).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark import this package.  It turns a workload description (plain
+dicts from ``paper_2503_16955_amd.workloads``) into the oracle's own C
+structs and returns numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+MISS, ABSORBED, EXIT_REFLECTED, EXIT_TRANSMITTED, TRUNCATED = range(5)
+
+_SPEC = {"uniform": 0, "lines": 1, "table": 2}
+_GEOM = {"flat": 0, "cylinder": 1}
+_MDF = {"gaussian_vmf": 0, "lorentzian": 1, "pseudo_voigt": 2, "wrapped_lorentzian": 3,
+        "spherical_wrapped_lorentzian": 4}
+_IRC = {"gaussian": 0, "pseudo_voigt": 1, "table": 2, "lorentzian": 3, "box": 4}
+
+D3 = C.c_double * 3
+D8 = C.c_double * 8
+
+
+class Source(C.Structure):
+    _fields_ = [("origin", D3), ("axis", D3), ("b1", D3), ("half_angle", C.c_double),
+                ("spectrum", C.c_int32), ("n_lines", C.c_int32),
+                ("e_min", C.c_double), ("e_max", C.c_double),
+                ("line_e", D8), ("line_sigma", D8), ("line_w", D8),
+                ("background_w", C.c_double), ("n_bins", C.c_int32), ("pad_", C.c_int32),
+                ("bin_w", C.POINTER(C.c_double))]
+
+
+class Crystal(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("max_refl", C.c_int32),
+                ("centre", D3), ("normal", D3), ("e1", D3),
+                ("axis_pt", D3), ("axis_dir", D3), ("ref_dir", D3),
+                ("radius", C.c_double), ("phi_c", C.c_double), ("z_c", C.c_double),
+                ("length", C.c_double), ("width", C.c_double), ("thickness", C.c_double),
+                ("two_d", C.c_double), ("mu0", C.c_double), ("mfp", C.c_double)]
+
+
+class Mosaic(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("fwhm", C.c_double),
+                ("eta", C.c_double)]
+
+
+class Irc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_table", C.c_int32), ("peak", C.c_double),
+                ("shift", C.c_double), ("fwhm", C.c_double), ("fwhm_g", C.c_double),
+                ("fwhm_l", C.c_double), ("x_min", C.c_double), ("x_max", C.c_double),
+                ("table", C.POINTER(C.c_double))]
+
+
+class Detector(C.Structure):
+    _fields_ = [("centre", D3), ("normal", D3), ("u", D3), ("v", D3),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_double)]
+
+
+class Counters(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("emitted", "missed", "absorbed", "exit_reflected",
+                                          "exit_transmitted", "truncated", "detected",
+                                          "events", "reflections")]
+
+
+RECORD_DTYPE = np.dtype([("ray_id", "<u8"), ("energy", "<f8"), ("entry", "<f8", 3),
+                         ("end", "<f8", 3), ("dir", "<f8", 3), ("pix_i", "<i4"),
+                         ("pix_j", "<i4"), ("n_events", "<u4"), ("n_refl", "<u2"),
+                         ("status", "u1"), ("detected", "u1")])
+assert RECORD_DTYPE.itemsize == 104
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        P = C.POINTER
+        L.orc_philox4x32.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+        L.orc_philox4x64.argtypes = [P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+        L.orc_bragg_angle.restype = C.c_double
+        L.orc_bragg_angle.argtypes = [C.c_double, C.c_double]
+        L.orc_pvoigt_params.argtypes = [C.c_double, C.c_double, P(C.c_double), P(C.c_double)]
+        L.orc_irc_value.restype = C.c_double
+        L.orc_irc_value.argtypes = [P(Irc), C.c_double]
+        L.orc_mdf_sample.argtypes = [P(Mosaic), C.c_double, C.c_double, P(C.c_double),
+                                     P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.orc_source_sample.argtypes = [P(Source), C.c_uint64, C.c_uint64, P(C.c_double),
+                                        P(C.c_double), P(C.c_double)]
+        L.orc_exit_distance.restype = C.c_double
+        L.orc_exit_distance.argtypes = [P(Crystal), P(C.c_double), P(C.c_double)]
+        L.orc_trace.restype = C.c_int
+        L.orc_trace.argtypes = [P(Source), P(Crystal), P(Mosaic), P(Irc), P(Detector),
+                                C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
+                                C.c_void_p, C.c_void_p, C.c_void_p, P(Counters), C.c_void_p,
+                                C.c_int]
+        L.orc_trace_ids.restype = C.c_int
+        L.orc_trace_ids.argtypes = [P(Source), P(Crystal), P(Mosaic), P(Irc), P(Detector),
+                                    C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32,
+                                    C.c_void_p, C.c_void_p, C.c_int]
+        _lib = L
+    return _lib
+
+
+def _d3(v):
+    return D3(*[float(x) for x in v])
+
+
+class Structs:
+    """The oracle's C structs for one workload (keeps table buffers alive)."""
+
+    def __init__(self, w):
+        s, c, m, r, d = (w["source"], w["crystal"], w["mosaic"], w["rocking_curve"],
+                         w["detector"])
+        self.src = Source()
+        self.src.origin, self.src.axis, self.src.b1 = _d3(s["origin"]), _d3(s["axis"]), _d3(s["b1"])
+        self.src.half_angle = s["half_angle"]
+        self.src.spectrum = _SPEC[s["spectrum"]]
+        self.src.e_min, self.src.e_max = s.get("e_min", 0.0), s.get("e_max", 0.0)
+        lines = s.get("lines", [])
+        self.src.n_lines = len(lines)
+        for j, (e, sig, wt) in enumerate(lines):
+            self.src.line_e[j], self.src.line_sigma[j], self.src.line_w[j] = e, sig, wt
+        self.src.background_w = s.get("background_w", 0.0)
+        self._bins = np.ascontiguousarray(s.get("bin_weights", [1.0]), dtype=np.float64)
+        self.src.n_bins = len(self._bins) if s["spectrum"] == "table" else 0
+        self.src.bin_w = self._bins.ctypes.data_as(C.POINTER(C.c_double))
+
+        self.cr = Crystal()
+        self.cr.geometry = _GEOM[c["geometry"]]
+        self.cr.max_refl = c["max_refl"]
+        for key in ("centre", "normal", "e1", "axis_pt", "axis_dir", "ref_dir"):
+            if key in c:
+                setattr(self.cr, key, _d3(c[key]))
+        for key in ("radius", "phi_c", "z_c", "length", "width", "thickness", "two_d",
+                    "mu0", "mfp"):
+            if key in c:
+                setattr(self.cr, key, float(c[key]))
+
+        self.mo = Mosaic(kind=_MDF[m["kind"]], fwhm=m["fwhm"], eta=m.get("eta", 0.0))
+
+        self.irc = Irc(kind=_IRC[r["kind"]], peak=r.get("peak", 0.0), shift=r.get("shift", 0.0),
+                       fwhm=r.get("fwhm", 0.0), fwhm_g=r.get("fwhm_g", 0.0),
+                       fwhm_l=r.get("fwhm_l", 0.0), x_min=r.get("x_min", 0.0),
+                       x_max=r.get("x_max", 0.0))
+        self._table = np.ascontiguousarray(r.get("table", [0.0]), dtype=np.float64)
+        self.irc.n_table = len(self._table) if r["kind"] == "table" else 0
+        self.irc.table = self._table.ctypes.data_as(C.POINTER(C.c_double))
+
+        self.det = Detector(centre=_d3(d["centre"]), normal=_d3(d["normal"]), u=_d3(d["u"]),
+                            v=_d3(d["v"]), nx=d["nx"], ny=d["ny"], pitch=d["pitch"])
+
+    def args(self):
+        return (C.byref(self.src), C.byref(self.cr), C.byref(self.mo), C.byref(self.irc),
+                C.byref(self.det))
+
+
+def trace(w, first=0, n=None, seed=None, max_events=0, images=True, records=False,
+          margins=False, threads=0):
+    """Trace rays [first, first + n) of workload `w` on the CPU.
+
+    Returns a dict with ``counts`` (ny, nx) uint32, ``energy_mev`` (ny, nx)
+    uint64, ``counters`` (dict), and on request ``records`` (structured array)
+    and ``margins`` (float64)."""
+    n = int(w["n_rays"] if n is None else n)
+    seed = int(w["seed"] if seed is None else seed)
+    S = Structs(w)
+    nx, ny = w["detector"]["nx"], w["detector"]["ny"]
+    out = {}
+    counts = np.zeros((ny, nx), np.uint32) if images else None
+    energy = np.zeros((ny, nx), np.uint64) if images else None
+    recs = np.zeros(n, RECORD_DTYPE) if records else None
+    mg = np.zeros(n, np.float64) if margins else None
+    cnt = Counters()
+    ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+    rc = lib().orc_trace(*S.args(), first, n, seed, max_events, ptr(counts), ptr(energy),
+                         ptr(recs), C.byref(cnt), ptr(mg), threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the workload (code {rc})")
+    out["counters"] = {f: getattr(cnt, f) for f, _ in Counters._fields_}
+    if images:
+        out["counts"], out["energy_mev"] = counts, energy
+    if records:
+        out["records"] = recs
+    if margins:
+        out["margins"] = mg
+    return out
+
+
+def trace_ids(w, ids, seed=None, max_events=0, threads=0):
+    """Records and decision margins for an arbitrary list of ray ids."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    seed = int(w["seed"] if seed is None else seed)
+    S = Structs(w)
+    recs = np.zeros(len(ids), RECORD_DTYPE)
+    mg = np.zeros(len(ids), np.float64)
+    rc = lib().orc_trace_ids(*S.args(), ids.ctypes.data_as(C.c_void_p), len(ids), seed,
+                             max_events, recs.ctypes.data_as(C.c_void_p),
+                             mg.ctypes.data_as(C.c_void_p), threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the workload (code {rc})")
+    return recs, mg
+
+
+# ---- single-function access for unit pins ---------------------------------
+
+def philox4x32(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32(c, k, o)
+    return list(o)
+
+
+def philox4x64(ctr, key):
+    c = (C.c_uint64 * 4)(*ctr)
+    k = (C.c_uint64 * 2)(*key)
+    o = (C.c_uint64 * 4)()
+    lib().orc_philox4x64(c, k, o)
+    return list(o)
+
+
+def bragg_angle(energy_kev, two_d):
+    return lib().orc_bragg_angle(energy_kev, two_d)
+
+
+def pvoigt_params(fwhm_g, fwhm_l):
+    f, e = C.c_double(), C.c_double()
+    lib().orc_pvoigt_params(fwhm_g, fwhm_l, C.byref(f), C.byref(e))
+    return f.value, e.value
+
+
+def irc_value(rocking_curve, x):
+    w = {"source": {"origin": [0, 0, 0], "axis": [0, 0, 1], "b1": [1, 0, 0], "half_angle": 0,
+                    "spectrum": "uniform"},
+         "crystal": {"geometry": "flat", "max_refl": 0}, "mosaic": {"kind": "gaussian_vmf", "fwhm": 0},
+         "rocking_curve": rocking_curve,
+         "detector": {"centre": [0, 0, 0], "normal": [0, 0, 1], "u": [1, 0, 0], "v": [0, 1, 0],
+                      "nx": 1, "ny": 1, "pitch": 1}}
+    S = Structs(w)
+    xs = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    return np.array([lib().orc_irc_value(C.byref(S.irc), float(v)) for v in xs])
+
+
+def mdf_sample(mosaic, u2, u3, N=(0, 0, 1), e1=(1, 0, 0), e2=(0, 1, 0)):
+    m = Mosaic(kind=_MDF[mosaic["kind"]], fwhm=mosaic["fwhm"], eta=mosaic.get("eta", 0.0))
+    u2 = np.atleast_1d(np.asarray(u2, np.float64))
+    u3 = np.atleast_1d(np.asarray(u3, np.float64))
+    out = np.zeros((len(u2), 3))
+    n = D3()
+    a, b, c = _d3(N), _d3(e1), _d3(e2)
+    for i in range(len(u2)):
+        lib().orc_mdf_sample(C.byref(m), float(u2[i]), float(u3[i]), a, b, c, n)
+        out[i] = list(n)
+    return out
+
+
+def source_sample(w, ray_ids, seed=None):
+    seed = int(w["seed"] if seed is None else seed)
+    S = Structs(w)
+    ids = np.atleast_1d(np.asarray(ray_ids, np.uint64))
+    o = np.zeros((len(ids), 3))
+    k = np.zeros((len(ids), 3))
+    e = np.zeros(len(ids))
+    oo, kk, ee = D3(), D3(), C.c_double()
+    for i, r in enumerate(ids):
+        lib().orc_source_sample(C.byref(S.src), seed, int(r), oo, kk, C.byref(ee))
+        o[i], k[i], e[i] = list(oo), list(kk), ee.value
+    return o, k, e
+
+
+def exit_distance(w, p, k):
+    S = Structs(w)
+    return lib().orc_exit_distance(C.byref(S.cr), _d3(p), _d3(k))

@@ -1,0 +1,166 @@
+/*
+ * Reference (oracle) implementation of the per-ray mosaic-crystal transport
+ * of Gawne et al., "HEART: A New X-Ray Tracing Code for Mosaic Crystal
+ * Spectrometers" (arXiv 2503.16955).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, scalar FP64 CPU program
+ * that exists to check the GPU library.  Only the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it.  It shares no
+ * code, header, table or constant with the GPU library; the two agree only
+ * because both follow the same written model:
+ *
+ *   source (paper sec. 2.1) -> crystal entry (sec. 2.2, FlatCrystal /
+ *   CylinderCrystal) -> null-collision depth stepping under Beer-Lambert
+ *   absorption (sec. 2.2.3, Eq. AnyEvent and the absorb-or-reflect rule)
+ *   -> crystallite tilt drawn from the mosaic distribution (sec. 2.2.2,
+ *   Eqs. vMF/MF, SWL, WL) -> deviation from the Bragg angle (Eq. BraggLaw)
+ *   -> acceptance by the intrinsic rocking curve (sec. 2.2.1, pseudo-Voigt,
+ *   Eqs. Gaussian and Lorentz) -> specular reflection off the crystallite
+ *   (sec. 2.2.4, reflection equation) -> pixel detector (sec. 2.3).
+ *
+ * Units: lengths mm, angles rad, energies keV, lattice spacing Angstrom,
+ * attenuation 1/mm.  All arithmetic is IEEE double with glibc libm.
+ */
+#ifndef MOSAIC_ORACLE_H
+#define MOSAIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_SPEC_UNIFORM = 0, ORC_SPEC_LINES = 1, ORC_SPEC_TABLE = 2 };
+enum { ORC_GEOM_FLAT = 0, ORC_GEOM_CYLINDER = 1 };
+enum { ORC_MDF_VMF = 0, ORC_MDF_LORENTZ = 1, ORC_MDF_PVOIGT = 2,
+       ORC_MDF_WRAPPED_LORENTZ = 3, ORC_MDF_SPHERICAL_WRAPPED_LORENTZ = 4 };
+enum { ORC_IRC_GAUSS = 0, ORC_IRC_PVOIGT = 1, ORC_IRC_TABLE = 2,
+       ORC_IRC_LORENTZ = 3, ORC_IRC_BOX = 4 };
+enum { ORC_MISS = 0, ORC_ABSORBED = 1, ORC_EXIT_REFLECTED = 2,
+       ORC_EXIT_TRANSMITTED = 3, ORC_TRUNCATED = 4 };
+
+typedef struct orc_source {
+    double origin[3];
+    double axis[3];          /* cone axis (unit) */
+    double b1[3];            /* unit, orthogonal to axis; b2 = axis x b1 */
+    double half_angle;       /* cone half-angle */
+    int32_t spectrum;        /* ORC_SPEC_* */
+    int32_t n_lines;         /* <= 8 */
+    double e_min, e_max;     /* flat part / table range */
+    double line_e[8], line_sigma[8], line_w[8];
+    double background_w;
+    int32_t n_bins;          /* table spectrum */
+    int32_t pad_;
+    const double *bin_w;     /* n_bins weights (host) */
+} orc_source;
+
+typedef struct orc_crystal {
+    int32_t geometry;        /* ORC_GEOM_* */
+    int32_t max_refl;
+    /* flat: surface centre, outward normal, length axis */
+    double centre[3], normal[3], e1[3];
+    /* cylinder: point on axis, axis direction, azimuth reference (phi = 0) */
+    double axis_pt[3], axis_dir[3], ref_dir[3];
+    double radius, phi_c, z_c;
+    /* shared extents: length (along e1 / axis), width (along e2 / arc
+       length at the front radius), thickness */
+    double length, width, thickness;
+    double two_d;            /* Angstrom */
+    double mu0;              /* linear attenuation, 1/mm */
+    double mfp;              /* mean path between crystallite encounters, mm */
+} orc_crystal;
+
+typedef struct orc_mosaic {
+    int32_t kind;            /* ORC_MDF_* */
+    int32_t pad_;
+    double fwhm;             /* Gamma */
+    double eta;              /* Lorentzian fraction for ORC_MDF_PVOIGT */
+} orc_mosaic;
+
+typedef struct orc_irc {
+    int32_t kind;            /* ORC_IRC_* */
+    int32_t n_table;
+    double peak;             /* reflection probability at the curve maximum */
+    double shift;            /* Delta_M */
+    double fwhm;             /* Lambda (Gaussian, Lorentzian, box) */
+    double fwhm_g, fwhm_l;   /* pseudo-Voigt components */
+    double x_min, x_max;     /* table range */
+    const double *table;     /* n_table values (host) */
+} orc_irc;
+
+typedef struct orc_detector {
+    double centre[3], normal[3], u[3], v[3];
+    int32_t nx, ny;
+    double pitch;
+} orc_detector;
+
+/* One record per ray (104 bytes). */
+typedef struct orc_record {
+    uint64_t ray_id;
+    double energy;
+    double entry[3];
+    double end[3];
+    double dir[3];
+    int32_t pix_i, pix_j;
+    uint32_t n_events;
+    uint16_t n_refl;
+    uint8_t status;
+    uint8_t detected;
+} orc_record;
+
+typedef struct orc_counters {
+    uint64_t emitted, missed, absorbed, exit_reflected, exit_transmitted,
+             truncated, detected, events, reflections;
+} orc_counters;
+
+/* Philox4x32-10 and Philox4x64-10 (Salmon et al., SC'11). */
+void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Bragg angle (Eq. BraggLaw); returns -1 when hc/E exceeds 2d. */
+double orc_bragg_angle(double energy_kev, double two_d);
+
+/* Pseudo-Voigt total width and Lorentzian fraction from the component
+   widths (sec. 2.2.1). */
+void orc_pvoigt_params(double fwhm_g, double fwhm_l, double *fwhm, double *eta);
+
+/* Rocking-curve reflection probability r(x) at x = Delta - Delta_M. */
+double orc_irc_value(const orc_irc *irc, double x);
+
+/* Draw a crystallite normal about frame (N, e1, e2) from uniforms (u2, u3). */
+void orc_mdf_sample(const orc_mosaic *m, double u2, double u3,
+                    const double N[3], const double e1[3], const double e2[3],
+                    double n_out[3]);
+
+/* Source sample for one ray: origin, direction, energy. */
+void orc_source_sample(const orc_source *s, uint64_t seed, uint64_t ray_id,
+                       double o[3], double k[3], double *energy);
+
+/* Exit distance of a point inside the crystal moving along k. */
+double orc_exit_distance(const orc_crystal *c, const double p[3], const double k[3]);
+
+/* Trace rays [first, first + n).  counts / energy_mev / records / counters /
+   margins may each be NULL.  Images are accumulated into (not cleared).
+   records and margins are indexed by ray_id - first.  margins[i] is the
+   smallest decision margin met by ray i (a diagnostic for tie analysis).
+   n_threads <= 0 uses every online core.  Returns 0 or a negative error. */
+int orc_trace(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
+              const orc_irc *irc, const orc_detector *d,
+              uint64_t first, uint64_t n, uint64_t seed, uint32_t max_events,
+              uint32_t *counts, uint64_t *energy_mev,
+              orc_record *records, orc_counters *counters, double *margins,
+              int n_threads);
+
+/* Trace an arbitrary list of ray ids (no images); records[i], margins[i]
+   belong to ids[i]. */
+int orc_trace_ids(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
+                  const orc_irc *irc, const orc_detector *d,
+                  const uint64_t *ids, uint64_t n, uint64_t seed, uint32_t max_events,
+                  orc_record *records, double *margins, int n_threads);
+
+int orc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
