@@ -1,0 +1,150 @@
+#!/usr/bin/env python3
+"""Throughput of the per-ray mosaic-crystal transport on one MI355X.
+
+One step traces one batch of rays of the von Hamos HAPG(002) spectrometer
+(R = 80 mm, 100 x 30 mm, 40 um, pseudo-Voigt mosaic 0.1 deg with eta = 0.3,
+pseudo-Voigt rocking curve 50/8 urad, two lines at 8.048 / 8.028 keV on a flat
+7.8-8.2 keV background, up to 4 reflections, 2048 x 512 detector at 50 um):
+1e8 rays in FP64, images resident in HBM and accumulated step after step
+(step s traces ray ids [s N, (s + 1) N), so K steps are one K N-ray
+simulation).  The same steps are then run in FP32-mixed precision.
+
+Printed: one JSON line with rays/s (FP64 is `value`), events/s, the ALU
+roofline of the trace kernel (algorithmic VALU lane-operations per launch over
+the kernel's HIP-event duration on its stream, against 256 CUs x 64 lanes x
+2.4 GHz), and the FP64 CPU oracle timed on a bounded sample of the same
+workload on the host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/sec traced (FP32-mixed vs FP64) at matched image; serving p50/p99 latency"
+PEAK_CLOCK_HZ = 2.4e9            # MI355X peak engine clock
+LANES_PER_CU_PER_CLK = 64        # 4 SIMDs x 16 lanes: one VALU lane-op each per clock
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_precision(mrt, w, precision, steps, warmup, n, counts, energy):
+    import torch
+    first_base = 1 << 40          # warm-up rays come from a separate id range
+    for s in range(warmup):
+        mrt.trace(w, n_rays=n, first=first_base + s * n, precision=precision, counts=counts,
+                  energy=energy)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    per_step = []
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for s in range(steps):
+        out = mrt.trace(w, n_rays=n, first=s * n, precision=precision, counts=counts,
+                        energy=energy, accumulate=s > 0, stream=stream)
+        per_step.append(out["counters"])
+        log(f"{precision} step {s}: kernel {out['counters']['kernel_ms']:.2f} ms")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    return per_step, gpu_ms, wall
+
+
+def roofline(op_costs, w, precision, per_step, cus):
+    ops = [op_costs.algorithmic_ops(w, precision, c) for c in per_step]
+    ms = [c["kernel_ms"] for c in per_step]
+    achieved = sum(o / (m * 1e-3) for o, m in zip(ops, ms)) / len(ops) / 1e12
+    peak = cus * LANES_PER_CU_PER_CLK * PEAK_CLOCK_HZ / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": f"trace_kernel<{'double' if precision == 'fp64' else 'float'}, no records>",
+            "ops_per_launch": int(sum(ops) / len(ops)),
+            "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
+
+
+def cpu_baseline(w, n):
+    import oracle
+    threads = min(16, len(os.sched_getaffinity(0)))
+    log(f"oracle: {n} rays on {threads} threads")
+    t0 = time.perf_counter()
+    r = oracle.trace(w, first=0, n=n, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 1), "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"ray ids [0, {n}) of the same workload, FP64, images on, {dt:.2f} s",
+            "events": r["counters"]["events"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="von_hamos_hapg")
+    ap.add_argument("--rays", type=int, default=0, help="rays per step (0 = the workload's)")
+    ap.add_argument("--cpu-rays", type=int, default=10_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the transport shards by ray-id ranges with one "
+              "integer image reduce, but this build runs and reports a single MI355X only.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_16955_amd import mosaicrt as mrt
+    from paper_2503_16955_amd import op_costs
+    from paper_2503_16955_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = W.get(a.workload)
+    n = a.rays or w["n_rays"]
+    info = mrt.device_info()
+    log(f"device {info['name']} {info['arch']} CUs {info['compute_units']}")
+    counts, energy = mrt.alloc_images(w)
+
+    per64, gpu_ms64, wall64 = run_precision(mrt, w, "fp64", a.steps, a.warmup, n, counts, energy)
+    rays = n * a.steps
+    value = rays / (gpu_ms64 * 1e-3)
+    events64 = sum(c["events"] for c in per64)
+    res = {
+        "metric": METRIC, "value": round(value, 1), "unit": "rays/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(gpu_ms64 / a.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w['name']}: von Hamos HAPG(002) R=80 mm, PV mosaic 0.1 deg "
+                               "eta=0.3, PV rocking curve 50/8 urad, 2 lines + flat, "
+                               "max 4 reflections, 2048x512 px",
+                   "rays_per_step": n, "seed": w["seed"], "precision": "fp64",
+                   "parallelism": "1 GPU"},
+        "events_per_s": round(events64 / (gpu_ms64 * 1e-3), 1),
+        "wall_s": round(wall64, 3),
+        "roofline": roofline(op_costs, w, "fp64", per64, info["compute_units"]),
+        "counters_last_step": {k: v for k, v in per64[-1].items() if k != "kernel_ms"},
+    }
+    if not a.no_mixed:
+        pm, gms, wl = run_precision(mrt, w, "fp32_mixed", a.steps, a.warmup, n, counts, energy)
+        res["fp32_mixed"] = {
+            "value": round(rays / (gms * 1e-3), 1), "unit": "rays/s",
+            "ms_per_step": round(gms / a.steps, 4),
+            "events_per_s": round(sum(c["events"] for c in pm) / (gms * 1e-3), 1),
+            "speedup_vs_fp64": round(gpu_ms64 / gms, 3),
+            "roofline": roofline(op_costs, w, "fp32_mixed", pm, info["compute_units"]),
+        }
+    res["serving"] = None
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, a.cpu_rays)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

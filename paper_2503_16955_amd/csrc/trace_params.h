@@ -1,0 +1,89 @@
+// Launch parameters of the trace kernels, prepared on the host from the
+// public structs.  All geometry is expressed relative to a crystal-local
+// origin (the flat crystal's front-face centre, or the point of the cylinder
+// axis at z_c), which keeps coordinates small so that the FP32 path keeps
+// nanometre resolution inside the crystal.
+#pragma once
+#include <stdint.h>
+
+#include "mosaicrt.h"
+
+namespace mrt {
+
+constexpr int kMaxLines = 8;
+
+struct TraceParams {
+    // ---- source (sec. 2.1), local coordinates
+    double so[3];                 // source origin
+    double sa[3], sb1[3], sb2[3]; // cone axis and azimuth frame
+    double vmax;                  // 1 - cos(half_angle), as 2 sin^2(half_angle / 2)
+    int32_t spectrum, n_lines;
+    double e_min, e_span;         // e_span = e_max - e_min
+    double line_e[kMaxLines], line_sig[kMaxLines];
+    double line_cum[kMaxLines];   // running weight sums / total, lines in order
+    int32_t n_bins, pad0;
+    const double *bin_cdf;        // n_bins + 1 normalised prefix sums (device)
+
+    // ---- crystal (sec. 2.2)
+    int32_t geometry, max_refl;
+    double N[3], e1[3], e2[3];    // flat frame
+    double hl, hw, T;             // half length, half width, thickness
+    double ax[3];                 // cylinder axis (through the local origin)
+    double op[3], om[3];          // outward normals of the two azimuth edges
+    double R, R2, Ro2;            // front radius, R^2, (R + T)^2
+    double mu0, inv_mu0, inv_mu_tot, p_a, inv_1mpa;
+    double two_d;                 // lattice spacing 2d (Angstrom)
+    double origin[3];             // local origin in global coordinates
+
+    // ---- mosaic (sec. 2.2.2)
+    int32_t mdf, pad1;
+    double fwhm;
+    double m_eta, inv_eta, inv_1meta;
+    double vmf_s2, vmf_floor;     // s^2 and exp(-2 / s^2)
+    double lor_g;                 // Gamma / 2
+    double wl_half_g2, wl_z;      // g^2 / 2 and ln((g^2 + 4) / g^2)
+    double swl_k, swl_d;          // 4 sinh^2(Gamma / 4) and cosh(Gamma / 2) + 1
+
+    // ---- rocking curve (sec. 2.2.1)
+    int32_t irc, lut_n;
+    double shift;
+    double g_k;                   // 4 ln 2 / Lambda^2
+    double pv_eta, pv_gn, pv_ln, pv_h2, pv_inv_r0;
+    double lor_h2, box_half;
+    double lut_x0, lut_x1, lut_scale, lut_inv_max;
+    const double *lut;            // device
+
+    // ---- detector (sec. 2.3), local coordinates
+    double dP[3], dn[3], du[3], dv[3];
+    int32_t nx, ny;
+    double pitch, half_nx, half_ny;
+
+    // ---- run
+    uint64_t first, n, seed;
+    uint32_t key0[10], key1[10];  // Philox round keys
+    uint32_t max_events;
+    uint32_t chunk;               // ray ids a wave claims at a time
+    int32_t records_mode;
+    int32_t pad2;
+    uint64_t rec_cap;
+    uint32_t *counts;
+    unsigned long long *energy;
+    mrt_hit_record *records;
+    unsigned long long *dev_counters;   // kNumCounters entries
+    unsigned long long *chunk_counter;  // next unclaimed ray offset
+};
+
+// Device counter slots.
+enum {
+    kCMissed = 0, kCAbsorbed, kCExitReflected, kCExitTransmitted, kCTruncated, kCDetected,
+    kCEvents, kCReflections, kCRecords, kNumCounters
+};
+
+// Launch the trace kernel of the requested precision on `stream`.
+int launch_trace(const TraceParams &p, int precision, bool records, int grid, int block,
+                 size_t lds_bytes, void *stream);
+int launch_zero(void *ptr_u32, size_t n_words, void *stream);
+// Resident blocks per compute unit for the given kernel variant.
+int occupancy(int precision, bool records, int block, size_t lds_bytes, int *blocks_per_cu);
+
+}  // namespace mrt

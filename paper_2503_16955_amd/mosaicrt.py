@@ -1,0 +1,283 @@
+"""ctypes binding of ``libmosaicrt.so`` (the C-ABI declared in
+``include/mosaicrt.h``).
+
+Argument marshalling only: a workload description (plain dicts, see
+``workloads.py``) becomes the library's structs, torch supplies the device
+buffers and the HIP stream, and every step of the transport runs in the HIP
+kernels behind ``mrt_trace``.  There is no fallback: if the library is not
+built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmosaicrt.so")
+
+# ---- public enums (mosaicrt.h) ---------------------------------------------
+OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, EAGAIN, ECANCELED = range(7)
+STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ECAPACITY", "EAGAIN", "ECANCELED"]
+SPECTRUM = {"uniform": 0, "lines": 1, "table": 2}
+GEOMETRY = {"flat": 0, "cylinder": 1}
+MOSAIC = {"gaussian_vmf": 0, "lorentzian": 1, "pseudo_voigt": 2, "wrapped_lorentzian": 3,
+          "spherical_wrapped_lorentzian": 4}
+ROCKING = {"gaussian": 0, "pseudo_voigt": 1, "table": 2, "lorentzian": 3, "box": 4}
+PRECISION = {"fp64": 0, "fp32_mixed": 1}
+RECORDS = {None: 0, "none": 0, "all": 1, "detected": 2}
+MISS, ABSORBED, EXIT_REFLECTED, EXIT_TRANSMITTED, TRUNCATED = range(5)
+
+_D3 = C.c_double * 3
+_D8 = C.c_double * 8
+
+
+class MrtSource(C.Structure):
+    _fields_ = [("origin", _D3), ("axis", _D3), ("b1", _D3), ("half_angle", C.c_double),
+                ("spectrum", C.c_int32), ("n_lines", C.c_int32),
+                ("e_min", C.c_double), ("e_max", C.c_double),
+                ("line_e", _D8), ("line_sigma", _D8), ("line_w", _D8),
+                ("background_w", C.c_double), ("n_bins", C.c_int32), ("reserved", C.c_int32),
+                ("bin_w", C.POINTER(C.c_double))]
+
+
+class MrtCrystal(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("max_refl", C.c_int32),
+                ("centre", _D3), ("normal", _D3), ("e1", _D3),
+                ("axis_pt", _D3), ("axis_dir", _D3), ("ref_dir", _D3),
+                ("radius", C.c_double), ("phi_c", C.c_double), ("z_c", C.c_double),
+                ("length", C.c_double), ("width", C.c_double), ("thickness", C.c_double),
+                ("two_d", C.c_double), ("mu0", C.c_double), ("mfp", C.c_double)]
+
+
+class MrtMosaic(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("fwhm", C.c_double),
+                ("eta", C.c_double)]
+
+
+class MrtRockingCurve(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_table", C.c_int32), ("peak", C.c_double),
+                ("shift", C.c_double), ("fwhm", C.c_double), ("fwhm_g", C.c_double),
+                ("fwhm_l", C.c_double), ("x_min", C.c_double), ("x_max", C.c_double),
+                ("table", C.POINTER(C.c_double))]
+
+
+class MrtDetector(C.Structure):
+    _fields_ = [("centre", _D3), ("normal", _D3), ("u", _D3), ("v", _D3),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_double)]
+
+
+class MrtOptions(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("records_mode", C.c_int32),
+                ("max_events", C.c_uint32), ("accumulate", C.c_int32),
+                ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+
+
+COUNTER_FIELDS = ("emitted", "missed", "absorbed", "exit_reflected", "exit_transmitted",
+                  "truncated", "detected", "events", "reflections", "records")
+
+
+class MrtCounters(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in COUNTER_FIELDS] + [("kernel_ms", C.c_double)]
+
+
+class MrtDeviceInfo(C.Structure):
+    _fields_ = [("device", C.c_int32), ("compute_units", C.c_int32), ("clock_khz", C.c_int32),
+                ("lds_bytes_per_block", C.c_int32), ("name", C.c_char * 64),
+                ("arch", C.c_char * 64)]
+
+
+# mrt_hit_record, 104 bytes
+RECORD_DTYPE = np.dtype([("ray_id", "<u8"), ("energy", "<f8"), ("entry", "<f8", 3),
+                         ("end", "<f8", 3), ("dir", "<f8", 3), ("pix_i", "<i4"),
+                         ("pix_j", "<i4"), ("n_events", "<u4"), ("n_refl", "<u2"),
+                         ("status", "u1"), ("detected", "u1")])
+RECORD_BYTES = 104
+assert RECORD_DTYPE.itemsize == RECORD_BYTES
+
+# Every symbol the header declares.
+EXPORTS = ("mrt_trace", "mrt_get_device_info", "mrt_last_error", "mrt_version")
+
+
+class MosaicRTError(RuntimeError):
+    def __init__(self, status, message):
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load the library (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python paper_2503_16955_amd/build.py` (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    L.mrt_trace.restype = C.c_int
+    L.mrt_trace.argtypes = [P(MrtSource), P(MrtCrystal), P(MrtMosaic), P(MrtRockingCurve),
+                            P(MrtDetector), C.c_uint64, C.c_uint64, C.c_uint64, P(MrtOptions),
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, P(MrtCounters),
+                            C.c_void_p]
+    L.mrt_get_device_info.restype = C.c_int
+    L.mrt_get_device_info.argtypes = [P(MrtDeviceInfo)]
+    L.mrt_last_error.restype = C.c_char_p
+    L.mrt_last_error.argtypes = []
+    L.mrt_version.restype = C.c_int
+    L.mrt_version.argtypes = []
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load().mrt_last_error().decode()
+
+
+def _check(status):
+    if status != OK:
+        raise MosaicRTError(status, last_error())
+
+
+def _v3(x):
+    return _D3(*[float(a) for a in x])
+
+
+class Structs:
+    """The library's structs for one workload; keeps host tables alive for
+    the duration of a call."""
+
+    def __init__(self, w):
+        s, c, m, r, d = (w["source"], w["crystal"], w["mosaic"], w["rocking_curve"],
+                         w["detector"])
+        src = MrtSource()
+        src.origin, src.axis, src.b1 = _v3(s["origin"]), _v3(s["axis"]), _v3(s["b1"])
+        src.half_angle = float(s["half_angle"])
+        src.spectrum = SPECTRUM[s["spectrum"]]
+        src.e_min, src.e_max = float(s.get("e_min", 0.0)), float(s.get("e_max", 0.0))
+        lines = s.get("lines", [])
+        src.n_lines = len(lines)
+        for j, (e, sig, wt) in enumerate(lines):
+            src.line_e[j], src.line_sigma[j], src.line_w[j] = e, sig, wt
+        src.background_w = float(s.get("background_w", 0.0))
+        self._bins = np.ascontiguousarray(s.get("bin_weights", [1.0]), dtype=np.float64)
+        src.n_bins = len(self._bins) if s["spectrum"] == "table" else 0
+        src.bin_w = self._bins.ctypes.data_as(C.POINTER(C.c_double))
+        self.source = src
+
+        cr = MrtCrystal()
+        cr.geometry = GEOMETRY[c["geometry"]]
+        cr.max_refl = int(c["max_refl"])
+        for key in ("centre", "normal", "e1", "axis_pt", "axis_dir", "ref_dir"):
+            if key in c:
+                setattr(cr, key, _v3(c[key]))
+        for key in ("radius", "phi_c", "z_c", "length", "width", "thickness", "two_d", "mu0",
+                    "mfp"):
+            if key in c:
+                setattr(cr, key, float(c[key]))
+        self.crystal = cr
+
+        self.mosaic = MrtMosaic(kind=MOSAIC[m["kind"]], fwhm=float(m["fwhm"]),
+                                eta=float(m.get("eta", 0.0)))
+
+        rc = MrtRockingCurve(kind=ROCKING[r["kind"]], peak=float(r.get("peak", 0.0)),
+                             shift=float(r.get("shift", 0.0)), fwhm=float(r.get("fwhm", 0.0)),
+                             fwhm_g=float(r.get("fwhm_g", 0.0)), fwhm_l=float(r.get("fwhm_l", 0.0)),
+                             x_min=float(r.get("x_min", 0.0)), x_max=float(r.get("x_max", 0.0)))
+        self._table = np.ascontiguousarray(r.get("table", [0.0]), dtype=np.float64)
+        rc.n_table = len(self._table) if r["kind"] == "table" else 0
+        rc.table = self._table.ctypes.data_as(C.POINTER(C.c_double))
+        self.rocking_curve = rc
+
+        self.detector = MrtDetector(centre=_v3(d["centre"]), normal=_v3(d["normal"]),
+                                    u=_v3(d["u"]), v=_v3(d["v"]), nx=int(d["nx"]),
+                                    ny=int(d["ny"]), pitch=float(d["pitch"]))
+
+    def refs(self):
+        return (C.byref(self.source), C.byref(self.crystal), C.byref(self.mosaic),
+                C.byref(self.rocking_curve), C.byref(self.detector))
+
+
+def device_info():
+    info = MrtDeviceInfo()
+    _check(load().mrt_get_device_info(C.byref(info)))
+    return {"device": info.device, "compute_units": info.compute_units,
+            "clock_khz": info.clock_khz, "lds_bytes_per_block": info.lds_bytes_per_block,
+            "name": info.name.decode(), "arch": info.arch.decode()}
+
+
+def alloc_images(w, device="cuda", energy=True):
+    """Device images of a workload: counts (ny, nx) int32 holding uint32 bits
+    and energy (ny, nx) int64 holding uint64 bits."""
+    import torch
+    nx, ny = int(w["detector"]["nx"]), int(w["detector"]["ny"])
+    counts = torch.empty((ny, nx), dtype=torch.int32, device=device)
+    en = torch.empty((ny, nx), dtype=torch.int64, device=device) if energy else None
+    return counts, en
+
+
+def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_events=0,
+          accumulate=False, counts=None, energy=None, want_energy=True, record_buf=None,
+          grid_blocks=0, block_threads=0, stream=None, sync=True):
+    """Trace rays [first, first + n_rays) of workload `w` with ``mrt_trace``.
+
+    counts / energy: torch device tensors to fill (allocated when None).
+    records: None, "all" or "detected".  sync=True waits for the stream and
+    returns the counters (and the kernel time); sync=False enqueues only.
+    Returns a dict with ``counts``, ``energy``, ``records`` (uint8 device
+    tensor of n x 104 bytes, or None) and ``counters`` (dict, or None)."""
+    import torch
+    L = load()
+    n = int(w["n_rays"] if n_rays is None else n_rays)
+    seed = int(w["seed"] if seed is None else seed)
+    prec = PRECISION[precision or w.get("precision", "fp64")]
+    mode = RECORDS[records]
+    if counts is None:
+        counts, e2 = alloc_images(w, energy=want_energy)
+        if energy is None:
+            energy = e2
+    rec = record_buf
+    cap = 0
+    if mode != 0:
+        if rec is None:
+            rec = torch.empty((n, RECORD_BYTES), dtype=torch.uint8, device=counts.device)
+        cap = rec.shape[0]
+    S = Structs(w)
+    opt = MrtOptions(precision=prec, records_mode=mode, max_events=int(max_events),
+                     accumulate=1 if accumulate else 0, grid_blocks=int(grid_blocks),
+                     block_threads=int(block_threads))
+    cnt = MrtCounters()
+    if stream is None:
+        stream = torch.cuda.current_stream(counts.device)
+    st = L.mrt_trace(*S.refs(), int(first), n, seed, C.byref(opt),
+                     C.c_void_p(counts.data_ptr()),
+                     C.c_void_p(energy.data_ptr()) if energy is not None else None,
+                     C.c_void_p(rec.data_ptr()) if rec is not None else None, cap,
+                     C.byref(cnt) if sync else None, C.c_void_p(stream.cuda_stream))
+    _check(st)
+    out = {"counts": counts, "energy": energy, "records": rec, "counters": None}
+    if sync:
+        out["counters"] = {f: int(getattr(cnt, f)) for f in COUNTER_FIELDS}
+        out["counters"]["kernel_ms"] = float(cnt.kernel_ms)
+    return out
+
+
+def records_to_numpy(rec, count=None):
+    """Copy device records (uint8 n x 104) to a numpy structured array."""
+    a = rec.cpu().numpy()
+    if count is not None:
+        a = a[:count]
+    return np.ascontiguousarray(a).view(RECORD_DTYPE).reshape(-1)
+
+
+def image_to_numpy(counts=None, energy=None):
+    """Device images to numpy uint32 / uint64 arrays."""
+    c = counts.cpu().numpy().view(np.uint32) if counts is not None else None
+    e = energy.cpu().numpy().view(np.uint64) if energy is not None else None
+    return c, e

@@ -1,0 +1,136 @@
+"""Comparison of GPU results with the oracle's, ray by ray and pixel by pixel.
+
+The parity contract for the FP64 path:
+  * per ray, status, number of events, number of reflections, detection
+    flag and pixel are equal;
+  * energies, entry / end points and final directions agree to
+    |a - b| <= 1e-12 max(|a|, |b|, 1 mm);
+  * images are bit-exact except for pixels touched by counted ties: rays
+    whose oracle decision margin (distance of a compared quantity from its
+    threshold: free path vs exit distance, absorption and acceptance
+    uniforms, pixel edges, crystal edges) is below TIE, or whose energy
+    quantum rint(E * 1e6) sits within TIE_MEV of a rounding boundary.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+REL = 1e-12
+TIE = 1e-9
+TIE_MEV = 1e-6
+
+INT_FIELDS = ("ray_id", "status", "n_events", "n_refl", "detected", "pix_i", "pix_j")
+FLOAT_FIELDS = ("energy", "entry", "end", "dir")
+
+
+def close(a, b, rel=REL):
+    """Elementwise |a - b| <= rel * max(|a|, |b|, 1); NaN equals NaN."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    both_nan = np.isnan(a) & np.isnan(b)
+    scale = np.maximum(np.maximum(np.abs(a), np.abs(b)), 1.0)
+    ok = np.abs(a - b) <= rel * scale
+    return ok | both_nan
+
+
+def record_mismatch(gpu, orc, rel=REL):
+    """Boolean per ray: True where any field differs beyond the contract."""
+    bad = np.zeros(len(orc), bool)
+    for f in INT_FIELDS:
+        bad |= gpu[f] != orc[f]
+    for f in FLOAT_FIELDS:
+        ok = close(gpu[f], orc[f], rel)
+        if ok.ndim > 1:
+            ok = ok.all(axis=1)
+        bad |= ~ok
+    return bad
+
+
+def energy_tie(energy_kev):
+    q = np.asarray(energy_kev) * 1e6
+    return np.abs(q - np.floor(q) - 0.5) < TIE_MEV
+
+
+def image_from_records(rec, nx, ny):
+    """Counts and energy images built from detected records."""
+    det = rec[rec["detected"] == 1]
+    px = det["pix_j"].astype(np.int64) * nx + det["pix_i"].astype(np.int64)
+    counts = np.bincount(px, minlength=nx * ny).astype(np.uint32).reshape(ny, nx)
+    q = np.rint(det["energy"] * 1e6).astype(np.uint64)
+    energy = np.zeros(nx * ny, np.uint64)
+    np.add.at(energy, px, q)
+    return counts, energy.reshape(ny, nx)
+
+
+def compare(gpu_rec, orc_rec, margins, rel=REL, tie=TIE):
+    """Classify every ray.  Returns (n_ties, bad_indices, tie_mask)."""
+    assert len(gpu_rec) == len(orc_rec)
+    mism = record_mismatch(gpu_rec, orc_rec, rel)
+    tie_mask = (np.asarray(margins) < tie) | energy_tie(orc_rec["energy"])
+    bad = np.nonzero(mism & ~tie_mask)[0]
+    n_ties = int(np.count_nonzero(mism & tie_mask))
+    return n_ties, bad, mism & tie_mask
+
+
+def describe(gpu_rec, orc_rec, margins, idx, limit=5):
+    lines = []
+    for i in list(idx)[:limit]:
+        lines.append(f"ray {orc_rec['ray_id'][i]} margin {margins[i]:.3e}\n"
+                     f"  gpu {gpu_rec[i]}\n  orc {orc_rec[i]}")
+    return "\n".join(lines)
+
+
+def images_explained(gpu_counts, gpu_energy, orc_counts, orc_energy, gpu_rec, orc_rec,
+                     tie_mask, nx, ny):
+    """True when the two images differ only by the contributions of the tie
+    rays (each side's own records of those rays)."""
+    gc_t, ge_t = image_from_records(gpu_rec[tie_mask], nx, ny)
+    oc_t, oe_t = image_from_records(orc_rec[tie_mask], nx, ny)
+    ok_c = np.array_equal(gpu_counts.astype(np.int64) - gc_t.astype(np.int64),
+                          orc_counts.astype(np.int64) - oc_t.astype(np.int64))
+    ok_e = True
+    if gpu_energy is not None and orc_energy is not None:
+        ok_e = np.array_equal(gpu_energy.astype(np.int64) - ge_t.astype(np.int64),
+                              orc_energy.astype(np.int64) - oe_t.astype(np.int64))
+    return ok_c and ok_e
+
+
+def projected_profile(counts):
+    """Sum over rows: counts per column (the dispersive axis)."""
+    return np.asarray(counts, np.float64).sum(axis=0)
+
+
+def centroid(profile, centre_col, half=15):
+    lo = max(0, int(round(centre_col)) - half)
+    hi = min(len(profile), int(round(centre_col)) + half + 1)
+    cols = np.arange(lo, hi, dtype=np.float64)
+    w = profile[lo:hi]
+    return float((cols * w).sum() / w.sum())
+
+
+def fwhm(profile, centre_col, half=15):
+    """Full width at half maximum of the peak near centre_col, by linear
+    interpolation of the half-maximum crossings."""
+    lo = max(0, int(round(centre_col)) - half)
+    hi = min(len(profile), int(round(centre_col)) + half + 1)
+    seg = profile[lo:hi]
+    m = int(np.argmax(seg))
+    hm = seg[m] / 2.0
+    i = m
+    while i > 0 and seg[i] > hm:
+        i -= 1
+    left = i + (hm - seg[i]) / (seg[i + 1] - seg[i]) if seg[i + 1] != seg[i] else float(i)
+    j = m
+    while j < len(seg) - 1 and seg[j] > hm:
+        j += 1
+    right = j - 1 + (seg[j - 1] - hm) / (seg[j - 1] - seg[j]) if seg[j - 1] != seg[j] else float(j)
+    return float(right - left)
+
+
+def chi2_per_pixel(a, b, scale=1.0):
+    """(1 / N) sum over pixels with a + b > 0 of (a - s b)^2 / (a + s^2 b)."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    m = (a + b) > 0
+    d = a[m] - scale * b[m]
+    return float((d * d / (a[m] + scale * scale * b[m])).sum() / max(1, m.sum()))

@@ -1,0 +1,157 @@
+"""The C-ABI boundary without a GPU: the library loads, exports every function
+``include/*.h`` declares, and its host-side validation turns every invalid
+argument into a status code and a message before touching a device."""
+import ctypes as C
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_16955_amd import mosaicrt as mrt
+from paper_2503_16955_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(mrt_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = mrt.load()
+    names = declared_functions()
+    assert {"mrt_trace", "mrt_last_error", "mrt_version", "mrt_get_device_info"} <= names
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(mrt.EXPORTS) <= names
+
+
+def test_version_matches_header():
+    text = open(os.path.join(ROOT, "include", "mosaicrt.h")).read()
+    v = int(re.search(r"#define\s+MRT_VERSION\s+(\d+)", text).group(1))
+    assert mrt.load().mrt_version() == v
+
+
+def test_struct_sizes_match_header():
+    # sizes the header's layout implies (x86-64 / amdgcn, natural alignment)
+    assert C.sizeof(mrt.MrtSource) == 320
+    assert C.sizeof(mrt.MrtCrystal) == 224
+    assert C.sizeof(mrt.MrtMosaic) == 24
+    assert C.sizeof(mrt.MrtRockingCurve) == 72
+    assert C.sizeof(mrt.MrtDetector) == 112
+    assert C.sizeof(mrt.MrtOptions) == 32
+    assert C.sizeof(mrt.MrtCounters) == 88
+    assert mrt.RECORD_DTYPE.itemsize == 104
+
+
+def _call(w, n=1000, first=0, opts=None, counts=1, energy=0, records=None, cap=0,
+          counters=False):
+    """mrt_trace with fake (never dereferenced) device pointers: validation
+    runs first and returns before any device call."""
+    L = mrt.load()
+    S = mrt.Structs(w)
+    o = opts or mrt.MrtOptions()
+    cnt = mrt.MrtCounters()
+    return L.mrt_trace(*S.refs(), first, n, 0, C.byref(o),
+                       C.c_void_p(counts) if counts else None,
+                       C.c_void_p(energy) if energy else None,
+                       C.c_void_p(records) if records else None, cap,
+                       C.byref(cnt) if counters else None, None)
+
+
+def _mut(path, value, base="flat_hopg"):
+    w = W.get(base)
+    d = w
+    for k in path[:-1]:
+        d = d[k]
+    d[path[-1]] = value
+    return w
+
+
+INVALID = [
+    ("source axis not unit", ("source", "axis"), [1.0, 0.0, 0.1]),
+    ("source b1 not orthogonal", ("source", "b1"), [0.97294474, 0.0, -0.23103794]),
+    ("negative half angle", ("source", "half_angle"), -0.1),
+    ("zero e_min", ("source", "e_min"), 0.0),
+    ("e_max below e_min", ("source", "e_max"), 7.0),
+    ("crystal normal not unit", ("crystal", "normal"), [0.0, 0.0, 2.0]),
+    ("zero thickness", ("crystal", "thickness"), 0.0),
+    ("negative mu0", ("crystal", "mu0"), -1.0),
+    ("zero mfp", ("crystal", "mfp"), 0.0),
+    ("negative max_refl", ("crystal", "max_refl"), -1),
+    ("zero 2d", ("crystal", "two_d"), 0.0),
+    ("negative mosaic fwhm", ("mosaic", "fwhm"), -1e-3),
+    ("eta above 1", ("mosaic", "eta"), 1.5),
+    ("zero rocking-curve width", ("rocking_curve", "fwhm"), 0.0),
+    ("peak above 1", ("rocking_curve", "peak"), 1.5),
+    ("detector axes not orthogonal", ("detector", "u"), [0.0, 1.0, 0.0]),
+    ("zero pitch", ("detector", "pitch"), 0.0),
+    ("zero columns", ("detector", "nx"), 0),
+    ("image of 2^31 pixels", ("detector", "nx"), 1 << 16),
+]
+
+
+@pytest.mark.parametrize("label,path,value", INVALID, ids=[x[0] for x in INVALID])
+def test_invalid_arguments_rejected(label, path, value):
+    w = _mut(path, value)
+    if label == "image of 2^31 pixels":
+        w["detector"]["ny"] = 1 << 15
+    assert _call(w) == mrt.EINVAL
+    assert mrt.last_error() != ""
+
+
+def test_invalid_spectra_and_tables():
+    w = W.get("von_hamos_hapg")
+    w["source"]["lines"] = [(8.0, -0.001, 1.0)]
+    assert _call(w) == mrt.EINVAL
+    w = W.get("von_hamos_hapg")
+    w["source"]["lines"], w["source"]["background_w"] = [(8.0, 0.001, 0.0)], 0.0
+    assert _call(w) == mrt.EINVAL and "zero" in mrt.last_error()
+    w = W.get("flat_stress")
+    w["rocking_curve"]["table"] = [0.1]
+    assert _call(w) == mrt.EINVAL
+    w = W.get("flat_stress")
+    w["rocking_curve"]["table"] = [0.1, 1.5, 0.2]
+    assert _call(w) == mrt.EINVAL
+    w = W.get("flat_stress")
+    w["rocking_curve"]["x_max"] = w["rocking_curve"]["x_min"]
+    assert _call(w) == mrt.EINVAL
+    w = W.get("flat_stress")
+    w["source"]["bin_weights"] = [0.0] * 8
+    assert _call(w) == mrt.EINVAL
+    w = W.get("von_hamos_hapg")
+    w["crystal"]["width"] = 4.0 * w["crystal"]["radius"]
+    assert _call(w) == mrt.EINVAL
+
+
+def test_invalid_run_arguments():
+    w = W.get("flat_hopg")
+    assert _call(w, n=0) == mrt.EINVAL
+    assert _call(w, n=10, first=(1 << 64) - 5) == mrt.EINVAL
+    assert _call(w, counts=0) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(precision=7)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(records_mode=1)) == mrt.EINVAL   # no buffer
+    assert _call(w, opts=mrt.MrtOptions(records_mode=1), records=0x1000, cap=10,
+                 n=1000) == mrt.ECAPACITY
+    assert _call(w, opts=mrt.MrtOptions(block_threads=96)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(grid_blocks=-1)) == mrt.EINVAL
+
+
+def test_valid_call_without_gpu_fails_loudly():
+    """A valid call on a machine without a GPU reports EDEVICE; there is no
+    CPU fallback."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st = _call(W.get("flat_hopg"))
+    assert st == mrt.EDEVICE, (st, mrt.last_error())
+    with pytest.raises(Exception):
+        mrt.trace(W.get("flat_hopg"))

@@ -1,0 +1,354 @@
+"""Parity of the HIP FP64 path with the FP64 CPU oracle, through the C-ABI.
+
+Per-ray records (status, events, reflections, pixel exact; doubles within
+1e-12 relative) and images (bit-exact except counted ties) on the same
+seeded inputs, at sizes the oracle finishes in seconds, for every source
+spectrum, crystal geometry, mosaic distribution and rocking curve the
+library implements, plus the edge cases of the method (misses only, no
+Bragg angle, zero mosaic, zero attenuation, truncation, ray ids past 2^32,
+tiny and ragged launches).
+"""
+import copy
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_16955_amd import mosaicrt as mrt
+from paper_2503_16955_amd import workloads as W
+
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def run_both(w, n, first=0, seed=None, max_events=0, **kw):
+    print(f"[parity] {w['name']} n={n} first={first} seed={seed}", flush=True)
+    g = mrt.trace(w, n_rays=n, first=first, seed=seed, records="all", max_events=max_events,
+                  **kw)
+    gc, ge = mrt.image_to_numpy(g["counts"], g["energy"])
+    grec = mrt.records_to_numpy(g["records"])
+    o = oracle.trace(w, first=first, n=n, seed=seed, max_events=max_events, records=True,
+                     margins=True)
+    return g, gc, ge, grec, o
+
+
+def assert_parity(w, n, first=0, seed=None, max_events=0, max_ties=0, **kw):
+    g, gc, ge, grec, o = run_both(w, n, first, seed, max_events, **kw)
+    orec, mg = o["records"], o["margins"]
+    n_ties, bad, tie_mask = parity.compare(grec, orec, mg)
+    assert len(bad) == 0, (f"{len(bad)} rays differ beyond the contract:\n"
+                           + parity.describe(grec, orec, mg, bad))
+    assert n_ties <= max_ties, f"{n_ties} tie rays"
+    nx, ny = w["detector"]["nx"], w["detector"]["ny"]
+    assert parity.images_explained(gc, ge, o["counts"], o["energy_mev"], grec, orec, tie_mask,
+                                   nx, ny)
+    gcnt, ocnt = g["counters"], o["counters"]
+    if n_ties == 0:
+        for f in ("emitted", "missed", "absorbed", "exit_reflected", "exit_transmitted",
+                  "truncated", "detected", "events", "reflections"):
+            assert gcnt[f] == ocnt[f], (f, gcnt[f], ocnt[f])
+    return g, o
+
+
+# ---- the workloads at oracle-sized ray counts --------------------------------
+
+def test_flat_hopg_full_config():
+    """Flat HOPG(002), uniform 7.9-8.1 keV, vMF 0.4 deg, Gaussian 50 urad: all
+    1e5 rays of the configuration."""
+    w = W.get("flat_hopg")
+    assert_parity(w, w["n_rays"])
+
+
+def test_von_hamos_first_million():
+    """Von Hamos HAPG, two lines on a flat background, pseudo-Voigt mosaic and
+    rocking curve, up to 4 reflections: ray ids [0, 1e6)."""
+    assert_parity(W.get("von_hamos_hapg"), 1_000_000)
+
+
+def test_flat_stress_fp64():
+    """Thick HOPG, Lorentzian 0.8 deg, tabulated Darwin-Prins rocking curve in
+    LDS, 1024-bin spectrum CDF in LDS, up to 8 reflections, 4096^2 detector."""
+    w = W.get("flat_stress", precision="fp64")
+    assert_parity(w, 300_000)
+
+
+# ---- every distribution kind ----------------------------------------------
+
+def _flat_variant(mosaic=None, irc=None, **crystal):
+    w = W.get("flat_hopg")
+    w["name"] = "flat_variant"
+    if mosaic:
+        w["mosaic"] = mosaic
+    if irc:
+        w["rocking_curve"] = irc
+    w["crystal"].update(crystal)
+    return w
+
+
+MOSAICS = {
+    "vmf": dict(kind="gaussian_vmf", fwhm=0.4 * W.DEG, eta=0.0),
+    "lorentzian": dict(kind="lorentzian", fwhm=0.3 * W.DEG, eta=0.0),
+    "pseudo_voigt": dict(kind="pseudo_voigt", fwhm=0.3 * W.DEG, eta=0.3),
+    "wrapped_lorentzian": dict(kind="wrapped_lorentzian", fwhm=0.1 * W.DEG, eta=0.0),
+    "spherical_wrapped_lorentzian": dict(kind="spherical_wrapped_lorentzian", fwhm=0.3 * W.DEG,
+                                         eta=0.0),
+}
+
+
+@pytest.mark.parametrize("kind", sorted(MOSAICS))
+def test_mosaic_kinds(kind):
+    w = _flat_variant(mosaic=MOSAICS[kind], max_refl=3)
+    g, o = assert_parity(w, 100_000)
+    assert o["counters"]["reflections"] > 100
+
+
+IRCS = {
+    "gaussian": dict(kind="gaussian", peak=0.5, shift=0.0, fwhm=50e-6),
+    "gaussian_shifted": dict(kind="gaussian", peak=0.8, shift=30e-6, fwhm=80e-6),
+    "pseudo_voigt": dict(kind="pseudo_voigt", peak=0.5, shift=-10e-6, fwhm_g=100e-6,
+                         fwhm_l=20e-6),
+    "lorentzian": dict(kind="lorentzian", peak=0.4, shift=0.0, fwhm=60e-6),
+    "box": dict(kind="box", peak=0.3, shift=5e-6, fwhm=100e-6),
+}
+
+
+@pytest.mark.parametrize("kind", sorted(IRCS))
+def test_rocking_curve_kinds(kind):
+    w = _flat_variant(irc=IRCS[kind], max_refl=2)
+    g, o = assert_parity(w, 100_000)
+    assert o["counters"]["reflections"] > 100
+
+
+def test_rocking_curve_table_coarse():
+    """A 7-node table: linear interpolation between nodes, zero outside."""
+    tab = [0.0, 0.1, 0.45, 0.6, 0.3, 0.05, 0.0]
+    w = _flat_variant(irc=dict(kind="table", peak=0.6, shift=0.0, table=tab, x_min=-90e-6,
+                               x_max=120e-6), max_refl=2)
+    assert_parity(w, 100_000)
+
+
+def test_spectrum_kinds_on_cylinder():
+    """Uniform and table spectra on the von Hamos crystal (lines are covered by
+    the von Hamos workload)."""
+    w = W.get("von_hamos_hapg")
+    w["source"].update(spectrum="uniform")
+    w["name"] = "vh_uniform"
+    assert_parity(w, 200_000)
+    w = W.get("von_hamos_hapg")
+    w["source"].update(spectrum="table", e_min=7.95, e_max=8.1,
+                       bin_weights=list(W.exponential_spectrum(n=37, e_min=7.95, e_max=8.1)))
+    w["name"] = "vh_table"
+    assert_parity(w, 200_000)
+
+
+# ---- edge cases ----------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4097])
+def test_tiny_and_ragged_launches(n):
+    assert_parity(W.get("von_hamos_hapg"), n, first=12345)
+
+
+def test_ray_ids_past_2_pow_32():
+    """The high word of the ray id enters the Philox counter."""
+    assert_parity(W.get("flat_hopg"), 5000, first=(1 << 32) - 2500)
+    assert_parity(W.get("flat_hopg"), 5000, first=(7 << 40) + 3, seed=(1 << 63) + 99)
+
+
+def test_truncation_cap():
+    """A tiny event cap truncates most entering rays, identically."""
+    w = W.get("flat_hopg")
+    g, o = assert_parity(w, 20_000, max_events=5)
+    assert o["counters"]["truncated"] > 1000
+
+
+def test_zero_mosaic_is_specular():
+    w = _flat_variant(mosaic=dict(kind="gaussian_vmf", fwhm=0.0, eta=0.0),
+                      irc=dict(kind="gaussian", peak=0.9, shift=0.0, fwhm=2e-3))
+    g, o = assert_parity(w, 50_000)
+    rec = o["records"]
+    refl = rec[(rec["n_refl"] == 1)]
+    assert len(refl) > 100
+    # specular off the +z surface: the final direction's z-component is positive
+    assert np.all(refl["dir"][:, 2] > 0)
+
+
+def test_no_attenuation_and_no_reflectivity():
+    w = _flat_variant(mu0=0.0)
+    assert_parity(w, 30_000)
+    w = _flat_variant(irc=dict(kind="gaussian", peak=0.0, shift=0.0, fwhm=50e-6))
+    g, o = assert_parity(w, 30_000)
+    assert o["counters"]["reflections"] == 0
+
+
+def test_no_bragg_angle():
+    """Energies below hc / 2d can never reflect."""
+    w = W.get("flat_hopg")
+    w["source"].update(e_min=1.0, e_max=1.5)
+    g, o = assert_parity(w, 30_000)
+    assert o["counters"]["reflections"] == 0 and o["counters"]["absorbed"] > 0
+
+
+def test_all_miss():
+    w = W.get("flat_hopg")
+    w["source"]["axis"] = [-a for a in w["source"]["axis"]]
+    g, o = assert_parity(w, 10_000)
+    assert o["counters"]["missed"] == 10_000
+
+
+def test_max_reflections_zero():
+    g, o = assert_parity(_flat_variant(max_refl=0), 30_000)
+    assert o["counters"]["reflections"] == 0
+
+
+# ---- properties of the launch ---------------------------------------------------
+
+def test_launch_shape_invariance():
+    """Images and records do not depend on the grid or block size."""
+    w = W.get("von_hamos_hapg")
+    n = 300_000
+    ref = mrt.trace(w, n_rays=n, records="all")
+    rc, re = mrt.image_to_numpy(ref["counts"], ref["energy"])
+    rr = mrt.records_to_numpy(ref["records"])
+    for grid, block in [(1, 64), (3, 128), (97, 256), (2048, 64)]:
+        print(f"[shape] grid={grid} block={block}", flush=True)
+        g = mrt.trace(w, n_rays=n, records="all", grid_blocks=grid, block_threads=block)
+        gc, ge = mrt.image_to_numpy(g["counts"], g["energy"])
+        assert np.array_equal(gc, rc) and np.array_equal(ge, re)
+        assert mrt.records_to_numpy(g["records"]).tobytes() == rr.tobytes()
+
+
+def test_split_ranges_accumulate():
+    """[0, a) + [a, n) accumulated equals [0, n) bit for bit (exact resume)."""
+    w = W.get("von_hamos_hapg")
+    n, a = 500_000, 123_457
+    full = mrt.trace(w, n_rays=n)
+    part = mrt.trace(w, n_rays=a)
+    mrt.trace(w, n_rays=n - a, first=a, counts=part["counts"], energy=part["energy"],
+              accumulate=True)
+    fc, fe = mrt.image_to_numpy(full["counts"], full["energy"])
+    pc, pe = mrt.image_to_numpy(part["counts"], part["energy"])
+    assert np.array_equal(fc, pc) and np.array_equal(fe, pe)
+
+
+def test_records_detected_mode():
+    w = W.get("flat_hopg")
+    n = w["n_rays"]
+    allr = mrt.records_to_numpy(mrt.trace(w, records="all")["records"])
+    d = mrt.trace(w, records="detected")
+    k = d["counters"]["records"]
+    assert k == d["counters"]["detected"] == int(allr["detected"].sum())
+    det = mrt.records_to_numpy(d["records"], k)
+    det = det[np.argsort(det["ray_id"])]
+    assert det.tobytes() == allr[allr["detected"] == 1].tobytes()
+    assert n > k
+
+
+def test_records_detected_capacity_error():
+    w = W.get("flat_hopg")
+    import torch
+    buf = torch.empty((10, mrt.RECORD_BYTES), dtype=torch.uint8, device="cuda")
+    with pytest.raises(mrt.MosaicRTError) as e:
+        mrt.trace(w, records="detected", record_buf=buf)
+    assert e.value.status == mrt.ECAPACITY
+
+
+def test_async_call_on_side_stream():
+    """sync=False enqueues on the given stream; the result equals a
+    synchronous call."""
+    import torch
+    w = W.get("flat_hopg")
+    ref = mrt.trace(w)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = mrt.trace(w, stream=s, sync=False)
+    s.synchronize()
+    a, _ = mrt.image_to_numpy(ref["counts"])
+    b, _ = mrt.image_to_numpy(out["counts"])
+    assert np.array_equal(a, b)
+
+
+# ---- full-size launch (the benchmark's configuration) --------------------------
+
+def test_von_hamos_full_size_sampled():
+    """1e8 von Hamos rays, FP64: the records kernel is checked against the oracle
+    on 4096 sampled ray ids, the benchmark's no-records kernel must give the
+    image the records imply, and the counters must conserve photons."""
+    import torch
+    w = W.get("von_hamos_hapg")
+    n = w["n_rays"]
+    nx, ny = w["detector"]["nx"], w["detector"]["ny"]
+    print("[full] records launch", flush=True)
+    g = mrt.trace(w, records="all")
+    c = g["counters"]
+    assert c["emitted"] == n
+    assert (c["missed"] + c["absorbed"] + c["exit_reflected"] + c["exit_transmitted"]
+            + c["truncated"]) == n
+    rng = np.random.default_rng(7)
+    ids = np.unique(rng.integers(0, n, 4096, dtype=np.int64))
+    rec_dev = g["records"]
+    sample = rec_dev.index_select(0, torch.as_tensor(ids, device=rec_dev.device))
+    grec = mrt.records_to_numpy(sample)
+    orec, mg = oracle.trace_ids(w, ids)
+    n_ties, bad, _ = parity.compare(grec, orec, mg)
+    assert len(bad) == 0, parity.describe(grec, orec, mg, bad)
+    assert n_ties == 0
+    # image implied by the records, built on the device
+    as_i32 = rec_dev.view(torch.int32)            # 26 words per record
+    det = rec_dev[:, 103] == 1                    # byte 103: detected flag
+    pix_i = as_i32[:, 22][det].long()             # bytes 88-91
+    pix_j = as_i32[:, 23][det].long()             # bytes 92-95
+    img = torch.bincount(pix_j * nx + pix_i, minlength=nx * ny).view(ny, nx)
+    del as_i32, det, pix_i, pix_j
+    print("[full] no-records launch (benchmark kernel)", flush=True)
+    b = mrt.trace(w)
+    assert torch.equal(b["counts"].long(), img)
+    assert b["counters"]["detected"] == int(img.sum())
+    assert b["counters"]["events"] == c["events"]
+
+
+# ---- the FP32-mixed path against FP64 ------------------------------------------
+
+def test_fp32_mixed_matches_fp64_statistically():
+    """Same seed and ray ids: centroid shift, FWHM change and chi-square per
+    pixel of the FP32-mixed von Hamos image against the FP64 one, per line."""
+    w = W.get("von_hamos_hapg")
+    n = 20_000_000
+    d = mrt.trace(w, n_rays=n, precision="fp64")
+    m = mrt.trace(w, n_rays=n, precision="fp32_mixed")
+    dc, _ = mrt.image_to_numpy(d["counts"])
+    mc, _ = mrt.image_to_numpy(m["counts"])
+    for f in ("missed",):
+        assert d["counters"][f] == m["counters"][f]
+    pd, pm = parity.projected_profile(dc), parity.projected_profile(mc)
+    nx = w["detector"]["nx"]
+    for e_line in (8.028, 8.048):
+        col = _line_column(w, e_line)
+        c_d, c_m = parity.centroid(pd, col), parity.centroid(pm, col)
+        f_d, f_m = parity.fwhm(pd, col), parity.fwhm(pm, col)
+        print(f"[mixed] line {e_line}: centroid {c_d:.4f} vs {c_m:.4f}, "
+              f"fwhm {f_d:.4f} vs {f_m:.4f}", flush=True)
+        assert abs(c_d - c_m) <= 0.02
+        assert abs(f_m - f_d) <= 0.005 * f_d + 0.02
+        assert 0 < col < nx
+    chi2 = parity.chi2_per_pixel(mc, dc)
+    print(f"[mixed] chi2/px {chi2:.4f}", flush=True)
+    assert chi2 <= 1.05
+    assert abs(m["counters"]["detected"] - d["counters"]["detected"]) <= 5 * math.sqrt(
+        d["counters"]["detected"])
+
+
+def _line_column(w, e_kev):
+    """Zero-mosaic focus column of an energy on the von Hamos detector: the
+    on-axis focus sits at z = 2 R / tan(alpha_B)."""
+    two_d = w["crystal"]["two_d"]
+    a = math.asin(12.398419843320026 / (two_d * e_kev))
+    z = 2.0 * w["crystal"]["radius"] / math.tan(a)
+    det = w["detector"]
+    return (z - det["centre"][2]) / det["pitch"] + det["nx"] / 2.0
+
+
+if __name__ == "__main__":
+    sys.exit(pytest.main([__file__, "-v"]))
