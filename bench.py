@@ -33,12 +33,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_precision(mrt, w, precision, steps, warmup, n, counts, energy):
+def run_precision(mrt, w, precision, steps, warmup, n, counts, energy, refill=0):
     import torch
     first_base = 1 << 40          # warm-up rays come from a separate id range
     for s in range(warmup):
         mrt.trace(w, n_rays=n, first=first_base + s * n, precision=precision, counts=counts,
-                  energy=energy)
+                  energy=energy, refill_idle=refill)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -47,7 +47,7 @@ def run_precision(mrt, w, precision, steps, warmup, n, counts, energy):
     ev0.record(stream)
     for s in range(steps):
         out = mrt.trace(w, n_rays=n, first=s * n, precision=precision, counts=counts,
-                        energy=energy, accumulate=s > 0, stream=stream)
+                        energy=energy, accumulate=s > 0, stream=stream, refill_idle=refill)
         per_step.append(out["counters"])
         log(f"{precision} step {s}: kernel {out['counters']['kernel_ms']:.2f} ms")
     ev1.record(stream)
@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--refill", type=int, default=0, help="lanes idle before a wave refills (0 = default)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the transport shards by ray-id ranges with one "
@@ -112,7 +113,8 @@ def main():
     log(f"device {info['name']} {info['arch']} CUs {info['compute_units']}")
     counts, energy = mrt.alloc_images(w)
 
-    per64, gpu_ms64, wall64 = run_precision(mrt, w, "fp64", a.steps, a.warmup, n, counts, energy)
+    per64, gpu_ms64, wall64 = run_precision(mrt, w, "fp64", a.steps, a.warmup, n, counts, energy,
+                                            a.refill)
     rays = n * a.steps
     value = rays / (gpu_ms64 * 1e-3)
     events64 = sum(c["events"] for c in per64)
@@ -132,7 +134,8 @@ def main():
         "counters_last_step": {k: v for k, v in per64[-1].items() if k != "kernel_ms"},
     }
     if not a.no_mixed:
-        pm, gms, wl = run_precision(mrt, w, "fp32_mixed", a.steps, a.warmup, n, counts, energy)
+        pm, gms, wl = run_precision(mrt, w, "fp32_mixed", a.steps, a.warmup, n, counts, energy,
+                                    a.refill)
         res["fp32_mixed"] = {
             "value": round(rays / (gms * 1e-3), 1), "unit": "rays/s",
             "ms_per_step": round(gms / a.steps, 4),

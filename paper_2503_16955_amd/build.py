@@ -1,30 +1,39 @@
-"""Builds libmosaicrt.so (HIP for gfx950) in-tree."""
+"""Builds libmosaicrt.so (HIP for gfx950) in-tree.  The trace-kernel instance
+translation units compile in parallel."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmosaicrt.so")
-SOURCES = ["trace_kernels.hip", "runtime.cpp"]
+SOURCES = ["trace_f64_flat.hip", "trace_f64_cyl.hip", "trace_f32_flat.hip", "trace_f32_cyl.hip",
+           "launch.hip", "runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
-         # packed FP32 instructions stay off (hand-free scalar FP32 only)
+         # no packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose=False, extra_flags=()):
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
-        cmd = [HIPCC, *FLAGS, *extra_flags, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+def _compile(src, extra_flags, verbose):
+    obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *extra_flags, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+    return obj
+
+
+def build(verbose=False, extra_flags=(), jobs=None):
+    jobs = jobs or min(len(SOURCES), max(1, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, extra_flags, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -1,0 +1,38 @@
+// Kernel lookup across the instance translation units, and the fill kernel
+// that clears images and counters on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include "trace_params.h"
+
+namespace mrt {
+
+const void *trace_table_f64_flat(int mdf, int irc, bool rec);
+const void *trace_table_f64_cyl(int mdf, int irc, bool rec);
+const void *trace_table_f32_flat(int mdf, int irc, bool rec);
+const void *trace_table_f32_cyl(int mdf, int irc, bool rec);
+
+const void *trace_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records) {
+    const bool flat = geometry == MRT_GEOMETRY_FLAT;
+    if (precision == MRT_FP64)
+        return flat ? trace_table_f64_flat(mdf, irc, records) : trace_table_f64_cyl(mdf, irc, records);
+    return flat ? trace_table_f32_flat(mdf, irc, records) : trace_table_f32_cyl(mdf, irc, records);
+}
+
+namespace {
+__global__ void zero_kernel(uint32_t *p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+}  // namespace
+
+int launch_zero(void *ptr, size_t n_words, void *stream) {
+    if (n_words == 0) return 0;
+    size_t blocks = (n_words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t *)ptr, n_words);
+    return (int)hipGetLastError();
+}
+
+}  // namespace mrt

@@ -1,6 +1,7 @@
 // Host runtime of the C-ABI: validation, launch parameters, table staging,
 // counters and timing.  Every step of the transport itself runs in the
-// kernels of trace_kernels.hip.
+// trace kernels (trace_impl.h, instantiated in trace_f64_*.hip and
+// trace_f32_*.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -122,6 +123,13 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
         return fail(MRT_EINVAL, "rocking curve: unknown kind");
     }
     if (!std::isfinite(r->shift)) return fail(MRT_EINVAL, "rocking curve: bad shift");
+    {
+        const size_t lut = r->kind == MRT_IRC_TABLE ? (size_t)r->n_table : 0;
+        const size_t cdf = s->spectrum == MRT_SPECTRUM_TABLE ? (size_t)s->n_bins + 1 : 0;
+        if ((lut + cdf) * sizeof(double) > (size_t)mrt::kMaxTableBytes)
+            return fail(MRT_EINVAL, "rocking-curve table plus spectrum bins exceed %d bytes of LDS",
+                        mrt::kMaxTableBytes);
+    }
     // detector
     if (!finite3(d->centre) || !unit(d->normal) || !unit(d->u) || !unit(d->v) ||
         !ortho(d->normal, d->u) || !ortho(d->normal, d->v) || !ortho(d->u, d->v))
@@ -250,15 +258,17 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
         P.g_k = 4.0 * ln2 / (r->fwhm * r->fwhm);
         break;
     case MRT_IRC_PSEUDO_VOIGT: {
+        // r(x) / R(0) = A h^2 / (h^2 + x^2) + B exp(-g_k x^2), with
+        // A = eta L(0) / R(0), B = (1 - eta) G(0) / R(0) (Eqs. Gaussian, Lorentz)
         double w, eta;
         pvoigt(r->fwhm_g, r->fwhm_l, &w, &eta);
         P.g_k = 4.0 * ln2 / (w * w);
-        P.pv_eta = eta;
-        P.pv_gn = std::sqrt(4.0 * ln2 / (kPi * w * w));
-        P.pv_ln = w / (2.0 * kPi);
+        const double g0 = std::sqrt(4.0 * ln2 / (kPi * w * w));
+        const double l0 = 2.0 / (kPi * w);
+        const double r0 = eta * l0 + (1.0 - eta) * g0;
+        P.pv_a = eta * l0 / r0;
+        P.pv_b = (1.0 - eta) * g0 / r0;
         P.pv_h2 = (w / 2.0) * (w / 2.0);
-        const double r0 = eta * (P.pv_ln / P.pv_h2) + (1.0 - eta) * P.pv_gn;
-        P.pv_inv_r0 = 1.0 / r0;
         break;
     }
     case MRT_IRC_LORENTZIAN:
@@ -276,6 +286,7 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
         tables.insert(tables.end(), r->table, r->table + r->n_table);
         break;
     }
+    P.g_k_log2e = P.g_k / ln2;
     if (s->spectrum == MRT_SPECTRUM_TABLE) {
         P.n_bins = s->n_bins;
         double total = 0.0;
@@ -373,6 +384,8 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     if (opt.block_threads < 0 || opt.block_threads > 256 || opt.block_threads % 64 != 0)
         return fail(MRT_EINVAL, "options: block_threads must be a multiple of 64 up to 256");
     if (opt.grid_blocks < 0) return fail(MRT_EINVAL, "options: grid_blocks must be >= 0");
+    if (opt.refill_idle < 0 || opt.refill_idle > 64)
+        return fail(MRT_EINVAL, "options: refill_idle must lie in [0, 64]");
 
     int dev = 0, cus = 0;
     if ((st = current_device(&dev, &cus)) != MRT_OK) return st;
@@ -384,10 +397,8 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     P.first = first_ray_id;
     P.n = n_rays;
     P.seed = seed;
-    for (int r = 0; r < 10; ++r) {
-        P.key0[r] = (uint32_t)seed + (uint32_t)r * 0x9E3779B9u;
-        P.key1[r] = (uint32_t)(seed >> 32) + (uint32_t)r * 0xBB67AE85u;
-    }
+    P.key0 = (uint32_t)seed;
+    P.key1 = (uint32_t)(seed >> 32);
     P.max_events = opt.max_events ? opt.max_events : (1u << 20);
     P.records_mode = opt.records_mode;
     P.rec_cap = records_capacity;
@@ -431,16 +442,21 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
             return release(fail(MRT_EDEVICE, "zero kernel launch failed"));
     }
 
+    const bool rec = opt.records_mode != MRT_RECORDS_NONE;
+    const void *kernel = mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
+                                               rocking_curve->kind, rec);
+    if (!kernel) return release(fail(MRT_EINVAL, "no kernel for this combination of kinds"));
     const int block = opt.block_threads ? opt.block_threads : 256;
     const size_t lds = tables.size() * sizeof(double);
     int grid = opt.grid_blocks;
     if (grid == 0) {
         int per_cu = 0;
-        if (mrt::occupancy(opt.precision, opt.records_mode != MRT_RECORDS_NONE, block, lds, &per_cu) != 0 ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         grid = cus * per_cu;
     }
+    P.refill_idle = opt.refill_idle > 0 ? (uint32_t)opt.refill_idle : 16u;
     // chunk size: enough chunks for every wave to claim several
     const uint64_t waves = (uint64_t)grid * (uint64_t)(block / 64);
     uint64_t chunk = n_rays / (waves * 8);
@@ -453,8 +469,9 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
             hipEventRecord(ev0, stream) != hipSuccess)
             return release(hip_fail(hipGetLastError(), "hipEvent setup"));
     }
-    if (mrt::launch_trace(P, opt.precision, opt.records_mode != MRT_RECORDS_NONE, grid, block, lds,
-                          stream) != 0) {
+    void *args[] = {&P};
+    if (hipLaunchKernel(kernel, dim3((unsigned)grid), dim3((unsigned)block), args, lds, stream) !=
+        hipSuccess) {
         if (ev0) { (void)hipEventDestroy(ev0); (void)hipEventDestroy(ev1); }
         return release(fail(MRT_EDEVICE, "trace kernel launch failed: %s",
                             hipGetErrorString(hipGetLastError())));
@@ -483,6 +500,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
         h_counters->detected = host[mrt::kCDetected];
         h_counters->events = host[mrt::kCEvents];
         h_counters->reflections = host[mrt::kCReflections];
+        h_counters->refined = host[mrt::kCRefined];
         const unsigned long long nrec = host[mrt::kCRecords];
         h_counters->records = opt.records_mode == MRT_RECORDS_ALL ? n_rays
                               : std::min<unsigned long long>(nrec, records_capacity);

@@ -1,0 +1,708 @@
+// Per-ray mosaic-crystal transport kernel for gfx950 (MI355X), templated on
+// precision, crystal geometry, mosaic distribution and rocking curve, so that
+// each instance keeps only its own parameters live across the event loop.
+//
+// One lane traces one ray at a time.  Waves are persistent: each claims
+// chunks of ray ids from a global counter, lanes whose ray has ended are
+// refilled from the chunk (a ray that misses the crystal is retired inside
+// the refill loop), and per-ray state lives in registers.  Random numbers
+// come from Philox4x32-10 keyed by (seed, ray id, draw index), so a ray's
+// result does not depend on the lane, wave or launch shape that traced it.
+//
+// The physics per ray (HEART, arXiv 2503.16955):
+//   source (sec. 2.1) -> front-face entry (sec. 2.2) -> events at the
+//   majorant rate mu0 + R_max / h (Eq. AnyEvent): absorb with probability
+//   mu0 / mu_tot, otherwise draw a crystallite normal from the mosaic
+//   distribution (sec. 2.2.2), take Delta = asin|k.n| - alpha_B (Eq.
+//   BraggLaw) and reflect (reflection equation, sec. 2.2.4) with probability
+//   r(Delta - Delta_M) / R_max (sec. 2.2.1) -> detector binning (sec. 2.3).
+//
+// R = double: everything in FP64.  R = float (mixed): geometry, free paths,
+// tilts and detector in FP32; photon energy, Bragg angle, k.n (accumulated
+// in FP64 from the FP32 components), Delta and the rocking-curve argument in
+// FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "trace_params.h"
+
+namespace mrt {
+namespace tk {
+
+constexpr int kWave = 64;
+constexpr double kHC = 12.398419843320026;   // h c in keV Angstrom (SI 2019 exact)
+
+template <class R> struct V3 { R x, y, z; };
+
+template <class R> __device__ __forceinline__ R cvt(double x) { return (R)x; }
+template <class R> __device__ __forceinline__ V3<R> ld3(const double *a) {
+    return V3<R>{cvt<R>(a[0]), cvt<R>(a[1]), cvt<R>(a[2])};
+}
+template <class R> __device__ __forceinline__ R dot(V3<R> a, V3<R> b) {
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <class R> __device__ __forceinline__ V3<R> axpy(V3<R> p, R t, V3<R> k) {
+    return V3<R>{p.x + t * k.x, p.y + t * k.y, p.z + t * k.z};
+}
+template <class R> __device__ __forceinline__ V3<R> sub(V3<R> a, V3<R> b) {
+    return V3<R>{a.x - b.x, a.y - b.y, a.z - b.z};
+}
+template <class R> __device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b) {
+    return V3<R>{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class R> __device__ __forceinline__ R fminr(R a, R b) { return a < b ? a : b; }
+template <class R> __device__ __forceinline__ R uni(uint32_t w);
+template <> __device__ __forceinline__ double uni<double>(uint32_t w) { return dm::u01_f64(w); }
+template <> __device__ __forceinline__ float uni<float>(uint32_t w) { return dm::u01_f32(w); }
+
+// Per-lane ray state.
+template <class R, bool REC> struct Ray {
+    V3<R> p, k;      // crystal-local position, unit direction
+    R dist;          // distance to the crystal boundary along k from p
+    double E;        // photon energy, keV
+    double sa;       // sin(alpha_B) = hc / (2d E); >= 1: no Bragg angle
+    float saf, caf;  // sin and cos of alpha_B in FP32, for the acceptance filter
+    uint64_t id;
+    uint32_t nev, nrefl;
+};
+template <class R> struct Ray<R, true> {
+    V3<R> p, k;
+    R dist;
+    double E;
+    double sa;
+    float saf, caf;
+    uint64_t id;
+    uint32_t nev, nrefl;
+    V3<R> entry;
+};
+
+// Wave-uniform counters (scalar registers), flushed with one atomic each.
+struct WaveCounts {
+    uint64_t missed, absorbed, exit_refl, exit_trans, truncated, detected, events, reflections,
+        refined;
+};
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <class R, int GEOM, int MDF, int IRC, bool REC>
+struct Tracer {
+    using RayT = Ray<R, REC>;
+    static constexpr bool kF64 = sizeof(R) == 8;
+
+    // ---- crystal geometry (sec. 2.2) ------------------------------------
+    // Front-face entry; false on a miss.
+    static __device__ __forceinline__ bool entry(const TraceParams &P, V3<R> o, V3<R> k, R &t) {
+        if constexpr (GEOM == MRT_GEOMETRY_FLAT) {
+            const V3<R> N = ld3<R>(P.N);
+            const R zeta = dot(o, N), kn = dot(k, N);
+            if (!(kn < R(0))) return false;
+            t = -zeta / kn;
+            if (!(t > R(0))) return false;
+            const V3<R> h = axpy(o, t, k);
+            const R xi = dot(h, ld3<R>(P.e1)), eta = dot(h, ld3<R>(P.e2));
+            return __builtin_fabs(xi) <= cvt<R>(P.hl) && __builtin_fabs(eta) <= cvt<R>(P.hw);
+        } else {
+            const V3<R> ax = ld3<R>(P.ax);
+            const R ka = dot(k, ax);
+            const V3<R> kp = axpy(k, -ka, ax);
+            const R zo = dot(o, ax);
+            const V3<R> rho = axpy(o, -zo, ax);
+            const R a = dot(kp, kp), b = dot(rho, kp);
+            const R cc = dot(rho, rho) - cvt<R>(P.R2);
+            if (!(cc < R(0)) || !(a > R(0))) return false;
+            const R disc = b * b - a * cc;
+            const R sq = dm::sqrt(disc);
+            t = b >= R(0) ? -cc / (b + sq) : (-b + sq) / a;
+            const V3<R> h = axpy(o, t, k);
+            const R zh = dot(h, ax);
+            const V3<R> rh = axpy(h, -zh, ax);
+            return __builtin_fabs(zh) <= cvt<R>(P.hl) && dot(rh, ld3<R>(P.op)) <= R(0) &&
+                   dot(rh, ld3<R>(P.om)) <= R(0);
+        }
+    }
+
+    // Distance to the boundary from an inside point along k: the minimum
+    // positive crossing over the faces k moves toward.
+    static __device__ __forceinline__ R exit_distance(const TraceParams &P, V3<R> p, V3<R> k) {
+        R t = R(INFINITY);
+        if constexpr (GEOM == MRT_GEOMETRY_FLAT) {
+            const V3<R> N = ld3<R>(P.N), e1 = ld3<R>(P.e1), e2 = ld3<R>(P.e2);
+            const R zeta = dot(p, N), xi = dot(p, e1), eta = dot(p, e2);
+            const R kn = dot(k, N), k1 = dot(k, e1), k2 = dot(k, e2);
+            const R hl = cvt<R>(P.hl), hw = cvt<R>(P.hw), T = cvt<R>(P.T);
+            if (kn > R(0)) t = fminr(t, -zeta / kn);
+            if (kn < R(0)) t = fminr(t, (-T - zeta) / kn);
+            if (k1 > R(0)) t = fminr(t, (hl - xi) / k1);
+            if (k1 < R(0)) t = fminr(t, (-hl - xi) / k1);
+            if (k2 > R(0)) t = fminr(t, (hw - eta) / k2);
+            if (k2 < R(0)) t = fminr(t, (-hw - eta) / k2);
+        } else {
+            const V3<R> ax = ld3<R>(P.ax);
+            const R z = dot(p, ax), ka = dot(k, ax);
+            const V3<R> rho = axpy(p, -z, ax), kp = axpy(k, -ka, ax);
+            const R a = dot(kp, kp), b = dot(rho, kp), r2 = dot(rho, rho);
+            if (a > R(0)) {
+                const R co = r2 - cvt<R>(P.Ro2);
+                R disc = b * b - a * co;
+                if (disc < R(0)) disc = R(0);
+                const R sq = dm::sqrt(disc);
+                const R to = b >= R(0) ? -co / (b + sq) : (-b + sq) / a;
+                t = fminr(t, to);
+                if (b < R(0)) {
+                    const R ci = r2 - cvt<R>(P.R2);
+                    const R di = b * b - a * ci;
+                    if (di >= R(0)) t = fminr(t, ci / (-b + dm::sqrt(di)));
+                }
+            }
+            const R hl = cvt<R>(P.hl);
+            if (ka > R(0)) t = fminr(t, (hl - z) / ka);
+            if (ka < R(0)) t = fminr(t, (-hl - z) / ka);
+            const V3<R> op = ld3<R>(P.op), om = ld3<R>(P.om);
+            const R kop = dot(k, op), kom = dot(k, om);
+            if (kop > R(0)) t = fminr(t, -dot(rho, op) / kop);
+            if (kom > R(0)) t = fminr(t, -dot(rho, om) / kom);
+        }
+        return t > R(0) ? t : R(0);
+    }
+
+    // ---- mosaic tilt (sec. 2.2.2) ----------------------------------------
+    // Radial part: (cos theta, sin theta) of the crystallite normal from the
+    // uniform u2, by the inverse of the distribution's radial CDF.
+    static __device__ __forceinline__ void vmf(const TraceParams &P, R u, R &ct, R &st) {
+        // Eq. MF: v = 1 - cos(theta) = -s^2 log(u + (1 - u) e^{-2/s^2})
+        R v = -cvt<R>(P.vmf_s2) * dm::log_pos(u + (R(1) - u) * cvt<R>(P.vmf_floor));
+        v = v < R(2) ? v : R(2);
+        ct = R(1) - v;
+        st = dm::sqrt(v * (R(2) - v));
+    }
+    static __device__ __forceinline__ void lorentz(const TraceParams &P, R q, R &ct, R &st) {
+        // bivariate Cauchy in the tangent plane: tan(theta) = g sqrt(1 - q^2) / q
+        const R g = cvt<R>(P.lor_g);
+        const R om = (R(1) - q) * (R(1) + q);
+        const R rs = dm::rsqrt(g * g * om + q * q);
+        ct = q * rs;
+        st = g * dm::sqrt(om) * rs;
+    }
+    static __device__ __forceinline__ V3<R> mosaic_normal(const TraceParams &P, R u2, R u3, V3<R> N,
+                                                          V3<R> e1, V3<R> e2) {
+        R ct, st;
+        if constexpr (MDF == MRT_MOSAIC_GAUSSIAN_VMF) {
+            vmf(P, u2, ct, st);
+        } else if constexpr (MDF == MRT_MOSAIC_LORENTZIAN) {
+            lorentz(P, R(1) - u2, ct, st);
+        } else if constexpr (MDF == MRT_MOSAIC_PSEUDO_VOIGT) {
+            // Lorentzian with probability eta, else von Mises-Fisher; the two
+            // branches share the square root of sin(theta)
+            const R eta = cvt<R>(P.m_eta);
+            R arg, scale;
+            if (u2 < eta) {
+                const R q = (eta - u2) * cvt<R>(P.inv_eta);
+                const R g = cvt<R>(P.lor_g);
+                const R om = (R(1) - q) * (R(1) + q);
+                const R rs = dm::rsqrt(g * g * om + q * q);
+                ct = q * rs;
+                arg = om;
+                scale = g * rs;
+            } else {
+                const R u = (u2 - eta) * cvt<R>(P.inv_1meta);
+                R v = -cvt<R>(P.vmf_s2) * dm::log_pos(u + (R(1) - u) * cvt<R>(P.vmf_floor));
+                v = v < R(2) ? v : R(2);
+                ct = R(1) - v;
+                arg = v * (R(2) - v);
+                scale = R(1);
+            }
+            st = scale * dm::sqrt(arg);
+        } else if constexpr (MDF == MRT_MOSAIC_WRAPPED_LORENTZIAN) {
+            // Eq. WL: density in v proportional to 1 / (g^2 + 2 v)
+            R v;
+            if constexpr (kF64) v = P.wl_half_g2 * ::expm1(u2 * P.wl_z);
+            else v = (float)P.wl_half_g2 * ::expm1f(u2 * (float)P.wl_z);
+            v = v < R(2) ? v : R(2);
+            ct = R(1) - v;
+            st = dm::sqrt(v * (R(2) - v));
+        } else {
+            // Eq. SWL: density in v proportional to 1 / (cosh(G/2) - 1 + v)^2
+            R v = dm::div(cvt<R>(P.swl_k) * u2, cvt<R>(P.swl_d) - R(2) * u2);
+            v = v < R(2) ? v : R(2);
+            ct = R(1) - v;
+            st = dm::sqrt(v * (R(2) - v));
+        }
+        if (!(P.fwhm > 0.0)) {   // perfect alignment
+            ct = R(1);
+            st = R(0);
+        }
+        R sx, cx;
+        dm::sincos_turns(u3, &sx, &cx);
+        return V3<R>{ct * N.x + st * (cx * e1.x + sx * e2.x),
+                     ct * N.y + st * (cx * e1.y + sx * e2.y),
+                     ct * N.z + st * (cx * e1.z + sx * e2.z)};
+    }
+
+    // Local surface frame at p: N toward the source side, e1 along the length
+    // axis (flat) or the cylinder axis, e2 = N x e1.
+    static __device__ __forceinline__ void frame(const TraceParams &P, V3<R> p, V3<R> &N, V3<R> &e1,
+                                                 V3<R> &e2) {
+        if constexpr (GEOM == MRT_GEOMETRY_FLAT) {
+            N = ld3<R>(P.N);
+            e1 = ld3<R>(P.e1);
+            e2 = ld3<R>(P.e2);
+        } else {
+            const V3<R> ax = ld3<R>(P.ax);
+            const V3<R> rho = axpy(p, -dot(p, ax), ax);
+            const R inv = dm::rsqrt(dot(rho, rho));
+            N = V3<R>{-rho.x * inv, -rho.y * inv, -rho.z * inv};
+            e1 = ax;
+            e2 = cross(N, e1);
+        }
+    }
+
+    // ---- rocking curve (sec. 2.2.1): r(x) / R_max at x = Delta - Delta_M ---
+    static __device__ __forceinline__ R irc_ratio(const TraceParams &P, const double *lut, double x) {
+        if constexpr (IRC == MRT_IRC_GAUSSIAN) {
+            if constexpr (kF64) return ::exp(-P.g_k * x * x);
+            else return dm::exp_((float)(-P.g_k * x * x));
+        } else if constexpr (IRC == MRT_IRC_PSEUDO_VOIGT) {
+            // eta L(x)/R(0) + (1 - eta) G(x)/R(0) = A h^2/(h^2 + x^2) + B exp(-k x^2)
+            const double x2 = x * x;
+            if constexpr (kF64) {
+                return P.pv_a * dm::div(P.pv_h2, P.pv_h2 + x2) + P.pv_b * ::exp(-P.g_k * x2);
+            } else {
+                const float h2 = (float)P.pv_h2, xf = (float)x2;
+                return (float)P.pv_a * h2 * dm::rcp(h2 + xf) +
+                       (float)P.pv_b * dm::exp_(-(float)P.g_k * xf);
+            }
+        } else if constexpr (IRC == MRT_IRC_LORENTZIAN) {
+            if constexpr (kF64) return dm::div(P.lor_h2, P.lor_h2 + x * x);
+            else return (float)P.lor_h2 * dm::rcp((float)(P.lor_h2 + x * x));
+        } else if constexpr (IRC == MRT_IRC_BOX) {
+            return __builtin_fabs(x) <= P.box_half ? R(1) : R(0);
+        } else {
+            // table: linear interpolation on equally spaced nodes, 0 outside
+            if (!(x >= P.lut_x0 && x <= P.lut_x1)) return R(0);   // also rejects NaN
+            const int n = P.lut_n;
+            if (x == P.lut_x1) return cvt<R>(lut[n - 1] * P.lut_inv_max);
+            const double f = (x - P.lut_x0) * P.lut_scale;
+            const int j = (int)__builtin_floor(f);
+            if (j >= n - 1) return cvt<R>(lut[n - 1] * P.lut_inv_max);
+            const double t = f - (double)j;
+            return cvt<R>(((1.0 - t) * lut[j] + t * lut[j + 1]) * P.lut_inv_max);
+        }
+    }
+
+    // ---- acceptance filter ------------------------------------------------
+    // The decision u_acc < r(x) / R_max with x = Delta - Delta_M is first
+    // taken from an FP32 estimate of x whose error is below kFilterErr (the
+    // float forms of sin(Delta) = c cos(alpha_B) - sqrt(1 - c^2) sin(alpha_B)
+    // and of the arcsine series have a worst case of ~3.5e-7 rad, from c's
+    // rounding, v_sqrt_f32 and the truncated series), bounding r over
+    // [|x| - kFilterErr, |x| + kFilterErr] with a relative margin for the
+    // FP32 curve.  Returns 1 (accept), 0 (reject) or -1 when u_acc falls in
+    // that band, in which case the exact FP64 evaluation decides; the result
+    // is therefore always the exact one.
+    static constexpr float kFilterErr = 2e-6f;
+    static __device__ __forceinline__ float ratio_f32(const TraceParams &P, float a) {
+        const float a2 = a * a;
+        if constexpr (IRC == MRT_IRC_GAUSSIAN) {
+            return __builtin_amdgcn_exp2f(-(float)P.g_k_log2e * a2);
+        } else if constexpr (IRC == MRT_IRC_PSEUDO_VOIGT) {
+            const float h2 = (float)P.pv_h2;
+            return (float)P.pv_a * h2 * __builtin_amdgcn_rcpf(h2 + a2) +
+                   (float)P.pv_b * __builtin_amdgcn_exp2f(-(float)P.g_k_log2e * a2);
+        } else {
+            const float h2 = (float)P.lor_h2;
+            return h2 * __builtin_amdgcn_rcpf(h2 + a2);
+        }
+    }
+    static __device__ __forceinline__ int filter(const TraceParams &P, double akn, float saf,
+                                                 float caf, float u_acc) {
+        const float c = (float)akn;
+        const float cw = __builtin_amdgcn_sqrtf(__builtin_fmaf(-c, c, 1.0f));
+        if (!(cw >= 0.1f)) return -1;   // normal within ~6 deg of k: no bound
+        const float z = __builtin_fmaf(c, caf, -cw * saf);
+        const float shift = (float)P.shift;
+        float lo, hi, slo, shi;   // bounds of |x| and of x
+        if (__builtin_fabsf(z) <= 0.25f) {
+            const float w = z * z;
+            float p = 35.0f / 1152.0f;
+            p = __builtin_fmaf(p, w, 5.0f / 112.0f);
+            p = __builtin_fmaf(p, w, 3.0f / 40.0f);
+            p = __builtin_fmaf(p, w, 1.0f / 6.0f);
+            const float x = __builtin_fmaf(z * w, p, z) - shift;
+            slo = x - kFilterErr;
+            shi = x + kFilterErr;
+            const float ax = __builtin_fabsf(x);
+            lo = ax - kFilterErr;
+            hi = ax + kFilterErr;
+        } else {
+            // |Delta| > asin(1/4)
+            const float d = 0.25268025514207865f - kFilterErr;
+            slo = z > 0.0f ? d - shift : -INFINITY;
+            shi = z > 0.0f ? INFINITY : -d - shift;
+            lo = d - __builtin_fabsf(shift);
+            hi = INFINITY;
+        }
+        lo = lo > 0.0f ? lo : 0.0f;
+        if constexpr (IRC == MRT_IRC_TABLE) {
+            // zero outside [x_min, x_max]
+            const float x0 = (float)P.lut_x0, x1 = (float)P.lut_x1;
+            if (shi < x0 - __builtin_fabsf(x0) * 0x1p-20f - 1e-12f ||
+                slo > x1 + __builtin_fabsf(x1) * 0x1p-20f + 1e-12f)
+                return 0;
+            return -1;
+        } else if constexpr (IRC == MRT_IRC_BOX) {
+            const float half = (float)P.box_half;
+            if (hi < half * (1.0f - 0x1p-20f)) return 1;
+            if (lo > half * (1.0f + 0x1p-20f)) return 0;
+            return -1;
+        } else {
+            // r / R_max is even and decreasing in |x|
+            const float r_hi = ratio_f32(P, lo) * 1.0001f + 1e-30f;
+            const float r_lo = hi < INFINITY ? ratio_f32(P, hi) * 0.9999f : 0.0f;
+            if (u_acc < r_lo) return 1;
+            if (u_acc >= r_hi) return 0;
+            return -1;
+        }
+    }
+
+    // ---- one event (sec. 2.2.3, 2.2.4).  Returns the end status, or -1. ----
+    static __device__ __forceinline__ int step(const TraceParams &P, const double *lut, RayT &ry,
+                                               bool &reflected, bool &refined) {
+        if (ry.nev == P.max_events) return MRT_TRUNCATED;
+        const dm::Words w = dm::philox(P.key0, P.key1, ry.nev, (uint32_t)ry.id,
+                                       (uint32_t)(ry.id >> 32), 1u);
+        ++ry.nev;
+        const int exit_status = ry.nrefl ? MRT_EXIT_REFLECTED : MRT_EXIT_TRANSMITTED;
+        if ((int)ry.nrefl >= P.max_refl) {
+            // reflection budget spent: Beer-Lambert absorption only
+            const R l = -dm::log_pos(uni<R>(w.w0)) * cvt<R>(P.inv_mu0);
+            if (l < ry.dist) {
+                ry.p = axpy(ry.p, l, ry.k);
+                return MRT_ABSORBED;
+            }
+            ry.p = axpy(ry.p, ry.dist, ry.k);
+            return exit_status;
+        }
+        // free path to the next event at the majorant rate (Eq. AnyEvent)
+        const R l = -dm::log_pos(uni<R>(w.w0)) * cvt<R>(P.inv_mu_tot);
+        if (l >= ry.dist) {
+            ry.p = axpy(ry.p, ry.dist, ry.k);
+            return exit_status;
+        }
+        ry.p = axpy(ry.p, l, ry.k);
+        ry.dist -= l;
+        const R u1 = uni<R>(w.w1);
+        const R pa = cvt<R>(P.p_a);
+        if (u1 < pa) return MRT_ABSORBED;      // absorbed when u < mu0 / mu_tot
+        if (!(ry.sa < 1.0)) return -1;         // no Bragg angle: never reflects
+        const R u_acc = (u1 - pa) * cvt<R>(P.inv_1mpa);
+
+        V3<R> N, e1, e2;
+        frame(P, ry.p, N, e1, e2);
+        const V3<R> n = mosaic_normal(P, uni<R>(w.w2), uni<R>(w.w3), N, e1, e2);
+        // Bragg deviation in FP64, k.n accumulated in FP64 from the components
+        const double kn = (double)ry.k.x * (double)n.x + (double)ry.k.y * (double)n.y +
+                          (double)ry.k.z * (double)n.z;
+        double akn = __builtin_fabs(kn);
+        akn = akn < 1.0 ? akn : 1.0;
+        int dec = filter(P, akn, ry.saf, ry.caf, (float)u_acc);
+        if (dec < 0) {
+            // exact: Delta = asin|k.n| - alpha_B in FP64 (Eq. BraggLaw)
+            refined = true;
+            const double x = (::asin(akn) - ::asin(ry.sa)) - P.shift;
+            dec = u_acc < irc_ratio(P, lut, x) ? 1 : 0;
+        }
+        if (dec) {
+            // reflection equation of sec. 2.2.4
+            const R two_kn = R(2) * (R)kn;
+            const V3<R> ks{ry.k.x - two_kn * n.x, ry.k.y - two_kn * n.y, ry.k.z - two_kn * n.z};
+            const R nr = dm::rsqrt(dot(ks, ks));
+            ry.k = V3<R>{ks.x * nr, ks.y * nr, ks.z * nr};
+            ++ry.nrefl;
+            ry.dist = exit_distance(P, ry.p, ry.k);
+            reflected = true;
+        }
+        return -1;
+    }
+
+    // ---- source (sec. 2.1) -------------------------------------------------
+    // Direction uniform in solid angle inside the cone.
+    static __device__ __forceinline__ V3<R> direction(const TraceParams &P, const dm::Words &a) {
+        const R v = uni<R>(a.w0) * cvt<R>(P.vmax);
+        const R ct = R(1) - v;
+        const R st = dm::sqrt(v * (R(2) - v));
+        R sp, cp;
+        dm::sincos_turns(uni<R>(a.w1), &sp, &cp);
+        const V3<R> ax = ld3<R>(P.sa), b1 = ld3<R>(P.sb1), b2 = ld3<R>(P.sb2);
+        return V3<R>{ct * ax.x + st * (cp * b1.x + sp * b2.x),
+                     ct * ax.y + st * (cp * b1.y + sp * b2.y),
+                     ct * ax.z + st * (cp * b1.z + sp * b2.z)};
+    }
+    // Energy from the spectrum used as a PDF (FP64 in both precisions).
+    static __device__ __forceinline__ double energy(const TraceParams &P, const double *cdf,
+                                                    const dm::Words &a, uint64_t ray) {
+        const double s2 = dm::u01_f64(a.w2), s3 = dm::u01_f64(a.w3);
+        if (P.spectrum == MRT_SPECTRUM_UNIFORM) return P.e_min + s2 * P.e_span;
+        if (P.spectrum == MRT_SPECTRUM_LINES) {
+            int pick = P.n_lines;
+            for (int j = 0; j < P.n_lines; ++j)
+                if (s2 < P.line_cum[j]) { pick = j; break; }
+            if (pick >= P.n_lines) return P.e_min + s3 * P.e_span;
+            const dm::Words b = dm::philox(P.key0, P.key1, 1u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
+            double sg, cg;
+            dm::sincos_turns(dm::u01_f64(b.w0), &sg, &cg);
+            return P.line_e[pick] + P.line_sig[pick] * dm::sqrt(-2.0 * dm::log_pos(s3)) * cg;
+        }
+        // largest bin b with cdf[b] <= s2, uniform inside the bin
+        int lo = 0, hi = P.n_bins - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cdf[mid] <= s2) lo = mid;
+            else hi = mid - 1;
+        }
+        return P.e_min + ((double)lo + s3) * P.e_span / (double)P.n_bins;
+    }
+
+    // ---- records (sec. 3: saved ray data) ------------------------------------
+    static __device__ __forceinline__ void write_record(const TraceParams &P, const RayT &ry,
+                                                        int status, bool miss, V3<R> end,
+                                                        bool detected, int pi, int pj) {
+        if constexpr (REC) {
+            int64_t idx = -1;
+            if (P.records_mode == MRT_RECORDS_ALL) {
+                idx = (int64_t)(ry.id - P.first);
+            } else if (detected) {
+                const unsigned long long slot = atomicAdd(&P.dev_counters[kCRecords], 1ull);
+                if (slot < P.rec_cap) idx = (int64_t)slot;
+            }
+            if (idx < 0) return;
+            mrt_hit_record *r = &P.records[idx];
+            const double nan = __builtin_nan("");
+            r->ray_id = ry.id;
+            r->energy_kev = ry.E;
+            r->entry[0] = miss ? nan : (double)ry.entry.x + P.origin[0];
+            r->entry[1] = miss ? nan : (double)ry.entry.y + P.origin[1];
+            r->entry[2] = miss ? nan : (double)ry.entry.z + P.origin[2];
+            r->end[0] = miss ? nan : (double)end.x + P.origin[0];
+            r->end[1] = miss ? nan : (double)end.y + P.origin[1];
+            r->end[2] = miss ? nan : (double)end.z + P.origin[2];
+            r->dir[0] = ry.k.x;
+            r->dir[1] = ry.k.y;
+            r->dir[2] = ry.k.z;
+            r->pix_i = pi;
+            r->pix_j = pj;
+            r->n_events = ry.nev;
+            r->n_refl = (uint16_t)ry.nrefl;
+            r->status = (uint8_t)status;
+            r->detected = detected ? 1 : 0;
+        }
+    }
+
+    // ---- end of a ray: detector (sec. 2.3) and images -------------------------
+    // Returns true when the ray lands on a pixel.
+    static __device__ __forceinline__ bool finish(const TraceParams &P, const RayT &ry, int status) {
+        int pi = -1, pj = -1;
+        bool detected = false;
+        V3<R> end = ry.p;
+        if (status == MRT_EXIT_REFLECTED || status == MRT_EXIT_TRANSMITTED) {
+            const V3<R> dn = ld3<R>(P.dn);
+            const R kn = dot(ry.k, dn);
+            if (kn < R(0)) {
+                const V3<R> dP = ld3<R>(P.dP);
+                const R t = dot(sub(dP, ry.p), dn) / kn;
+                if (t > R(0)) {
+                    const V3<R> h = axpy(ry.p, t, ry.k);
+                    const V3<R> d = sub(h, dP);
+                    const R fu = dot(d, ld3<R>(P.du)) / cvt<R>(P.pitch) + cvt<R>(P.half_nx);
+                    const R fv = dot(d, ld3<R>(P.dv)) / cvt<R>(P.pitch) + cvt<R>(P.half_ny);
+                    const R fi = __builtin_floor(fu), fj = __builtin_floor(fv);
+                    if (fi >= R(0) && fj >= R(0) && fi < (R)P.nx && fj < (R)P.ny) {
+                        pi = (int)fi;
+                        pj = (int)fj;
+                        detected = true;
+                        end = h;
+                        const size_t px = (size_t)pj * (size_t)P.nx + (size_t)pi;
+                        atomicAdd(&P.counts[px], 1u);
+                        if (P.energy)
+                            atomicAdd(&P.energy[px], (unsigned long long)__builtin_rint(ry.E * 1e6));
+                    }
+                }
+            }
+        }
+        write_record(P, ry, status, false, end, detected, pi, pj);
+        return detected;
+    }
+
+    // Start a ray: source direction and front-face entry.  On a hit, the
+    // energy, Bragg angle and first exit distance follow and true is
+    // returned; a miss is retired here (record written) and false returned.
+    static __device__ __forceinline__ bool start(const TraceParams &P, const double *cdf,
+                                                 uint64_t ray, RayT &ry) {
+        const dm::Words a = dm::philox(P.key0, P.key1, 0u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
+        const V3<R> o = ld3<R>(P.so);
+        const V3<R> k = direction(P, a);
+        ry.id = ray;
+        ry.k = k;
+        ry.nev = 0;
+        ry.nrefl = 0;
+        R t;
+        const bool hit = entry(P, o, k, t);
+        if (!hit) {
+            if constexpr (REC) {
+                ry.E = energy(P, cdf, a, ray);
+                ry.p = o;
+                write_record(P, ry, MRT_MISS, true, o, false, -1, -1);
+            }
+            return false;
+        }
+        ry.p = axpy(o, t, k);
+        if constexpr (REC) ry.entry = ry.p;
+        ry.E = energy(P, cdf, a, ray);
+        const double s = kHC / (P.two_d * ry.E);   // Eq. BraggLaw: sin(alpha_B)
+        ry.sa = s < 1.0 ? s : 2.0;
+        ry.saf = (float)s;
+        ry.caf = s < 1.0 ? (float)dm::sqrt(fma(-s, s, 1.0)) : 0.0f;
+        ry.dist = exit_distance(P, ry.p, ry.k);
+        return true;
+    }
+};
+
+__device__ __forceinline__ void flush(const TraceParams &P, WaveCounts &c) {
+    if (__lane_id() == 0) {
+        unsigned long long *d = P.dev_counters;
+        if (c.missed) atomicAdd(&d[kCMissed], (unsigned long long)c.missed);
+        if (c.absorbed) atomicAdd(&d[kCAbsorbed], (unsigned long long)c.absorbed);
+        if (c.exit_refl) atomicAdd(&d[kCExitReflected], (unsigned long long)c.exit_refl);
+        if (c.exit_trans) atomicAdd(&d[kCExitTransmitted], (unsigned long long)c.exit_trans);
+        if (c.truncated) atomicAdd(&d[kCTruncated], (unsigned long long)c.truncated);
+        if (c.detected) atomicAdd(&d[kCDetected], (unsigned long long)c.detected);
+        if (c.events) atomicAdd(&d[kCEvents], (unsigned long long)c.events);
+        if (c.reflections) atomicAdd(&d[kCReflections], (unsigned long long)c.reflections);
+        if (c.refined) atomicAdd(&d[kCRefined], (unsigned long long)c.refined);
+    }
+    c = WaveCounts{};
+}
+
+// ---------------------------------------------------------------------------
+// Persistent trace kernel.
+// ---------------------------------------------------------------------------
+template <class R, int GEOM, int MDF, int IRC, bool REC>
+__global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
+    using T = Tracer<R, GEOM, MDF, IRC, REC>;
+    extern __shared__ double lds[];
+    // stage the rocking-curve table and the spectrum CDF in LDS
+    const int nl = IRC == MRT_IRC_TABLE ? P.lut_n : 0;
+    const int nc = P.spectrum == MRT_SPECTRUM_TABLE ? P.n_bins + 1 : 0;
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) lds[i] = P.lut[i];
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) lds[nl + i] = P.bin_cdf[i];
+    __syncthreads();
+    const double *lut = lds;
+    const double *cdf = lds + nl;
+
+    typename T::RayT ry;
+    bool active = false;
+    WaveCounts cnt{};
+    uint64_t next = 0, end = 0;   // wave-uniform chunk cursor (offsets into [0, n))
+    bool more = true;             // wave-uniform: unclaimed rays remain
+    const uint32_t refill_at = P.refill_idle < 1u ? 1u : (P.refill_idle > 64u ? 64u : P.refill_idle);
+
+    for (;;) {
+        // refill idle lanes from the wave's chunk, claiming chunks as needed;
+        // rays that miss the crystal are counted and retired here
+        while (more) {
+            const uint64_t idle = ballot(!active);
+            const uint32_t nidle = popc(idle);
+            if (nidle == 0 || (nidle < refill_at && idle != ~0ull)) break;
+            if (next == end) {
+                flush(P, cnt);
+                unsigned long long base = 0;
+                if (__lane_id() == 0) base = atomicAdd(P.chunk_counter, (unsigned long long)P.chunk);
+                base = uniform64(base);
+                if (base >= P.n) {
+                    more = false;
+                    break;
+                }
+                next = base;
+                end = base + P.chunk < P.n ? base + P.chunk : P.n;
+            }
+            const uint64_t avail = end - next;
+            const uint32_t take = avail < nidle ? (uint32_t)avail : nidle;
+            bool missed = false;
+            if (!active) {
+                const uint32_t r = lane_rank(idle);
+                if (r < take) {
+                    active = T::start(P, cdf, P.first + next + r, ry);
+                    missed = !active;
+                }
+            }
+            cnt.missed += popc(ballot(missed));
+            next += take;
+        }
+        const uint64_t act0 = ballot(active);
+        if (act0 == 0) {
+            if (!more) break;
+            continue;
+        }
+
+        // events: run until refill_at lanes are idle (drain once rays run out);
+        // refill_at is in [1, 64], so keep is at least 1
+        const uint32_t keep = more ? 65u - refill_at : 1u;
+        for (;;) {
+            bool reflected = false, refined = false;
+            int status = -1;
+            const bool was_active = active;
+            if (active) status = T::step(P, lut, ry, reflected, refined);
+            const bool ended = status >= 0;
+            bool det = false;
+            if (ended) {
+                det = T::finish(P, ry, status);
+                active = false;
+            }
+            // every step draws one event except a truncation, which ends the ray first
+            cnt.events += popc(ballot(was_active && status != MRT_TRUNCATED));
+            if (ballot(reflected)) cnt.reflections += popc(ballot(reflected));
+            cnt.refined += popc(ballot(refined));
+            const uint64_t endm = ballot(ended);
+            if (endm) {
+                cnt.absorbed += popc(ballot(ended && status == MRT_ABSORBED));
+                cnt.exit_refl += popc(ballot(ended && status == MRT_EXIT_REFLECTED));
+                cnt.exit_trans += popc(ballot(ended && status == MRT_EXIT_TRANSMITTED));
+                cnt.truncated += popc(ballot(ended && status == MRT_TRUNCATED));
+                cnt.detected += popc(ballot(det));
+            }
+            if (popc(ballot(active)) < keep) break;
+        }
+    }
+    flush(P, cnt);
+}
+
+}  // namespace tk
+
+// Kernel lookup of one translation unit: precision and geometry fixed,
+// mosaic kind x rocking-curve kind x records.
+#define MRT_TRACE_TABLE(FN, R, GEOM)                                                          \
+    const void *FN(int mdf, int irc, bool rec) {                                               \
+        using namespace tk;                                                                   \
+        static const void *const t[5][5][2] = {                                               \
+            MRT_ROW(R, GEOM, 0), MRT_ROW(R, GEOM, 1), MRT_ROW(R, GEOM, 2), MRT_ROW(R, GEOM, 3), \
+            MRT_ROW(R, GEOM, 4)};                                                             \
+        if (mdf < 0 || mdf > 4 || irc < 0 || irc > 4) return nullptr;                         \
+        return t[mdf][irc][rec ? 1 : 0];                                                      \
+    }
+#define MRT_PAIR(R, GEOM, M, I) \
+    {(const void *)trace_kernel<R, GEOM, M, I, false>, (const void *)trace_kernel<R, GEOM, M, I, true>}
+#define MRT_ROW(R, GEOM, M)                                                                   \
+    {MRT_PAIR(R, GEOM, M, 0), MRT_PAIR(R, GEOM, M, 1), MRT_PAIR(R, GEOM, M, 2),                \
+     MRT_PAIR(R, GEOM, M, 3), MRT_PAIR(R, GEOM, M, 4)}
+
+}  // namespace mrt

@@ -4,6 +4,7 @@
 // axis at z_c), which keeps coordinates small so that the FP32 path keeps
 // nanometre resolution inside the crystal.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 #include "mosaicrt.h"
@@ -11,6 +12,8 @@
 namespace mrt {
 
 constexpr int kMaxLines = 8;
+// Largest tables staged in LDS (rocking-curve values plus spectrum CDF).
+constexpr int kMaxTableBytes = 64 * 1024;
 
 struct TraceParams {
     // ---- source (sec. 2.1), local coordinates
@@ -44,11 +47,12 @@ struct TraceParams {
     double wl_half_g2, wl_z;      // g^2 / 2 and ln((g^2 + 4) / g^2)
     double swl_k, swl_d;          // 4 sinh^2(Gamma / 4) and cosh(Gamma / 2) + 1
 
-    // ---- rocking curve (sec. 2.2.1)
+    // ---- rocking curve (sec. 2.2.1), all as r(x) / R_max
     int32_t irc, lut_n;
     double shift;
     double g_k;                   // 4 ln 2 / Lambda^2
-    double pv_eta, pv_gn, pv_ln, pv_h2, pv_inv_r0;
+    double g_k_log2e;             // g_k / ln 2, for exp2 in the FP32 filter
+    double pv_a, pv_b, pv_h2;     // A h^2 / (h^2 + x^2) + B exp(-g_k x^2)
     double lor_h2, box_half;
     double lut_x0, lut_x1, lut_scale, lut_inv_max;
     const double *lut;            // device
@@ -60,11 +64,11 @@ struct TraceParams {
 
     // ---- run
     uint64_t first, n, seed;
-    uint32_t key0[10], key1[10];  // Philox round keys
+    uint32_t key0, key1;          // Philox key: seed low and high words
     uint32_t max_events;
     uint32_t chunk;               // ray ids a wave claims at a time
+    uint32_t refill_idle;         // refill a wave once this many lanes are idle
     int32_t records_mode;
-    int32_t pad2;
     uint64_t rec_cap;
     uint32_t *counts;
     unsigned long long *energy;
@@ -76,14 +80,12 @@ struct TraceParams {
 // Device counter slots.
 enum {
     kCMissed = 0, kCAbsorbed, kCExitReflected, kCExitTransmitted, kCTruncated, kCDetected,
-    kCEvents, kCReflections, kCRecords, kNumCounters
+    kCEvents, kCReflections, kCRecords, kCRefined, kNumCounters
 };
 
-// Launch the trace kernel of the requested precision on `stream`.
-int launch_trace(const TraceParams &p, int precision, bool records, int grid, int block,
-                 size_t lds_bytes, void *stream);
+// Kernel of a precision / geometry / mosaic / rocking-curve / records
+// combination (nullptr for an unknown kind).
+const void *trace_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records);
 int launch_zero(void *ptr_u32, size_t n_words, void *stream);
-// Resident blocks per compute unit for the given kernel variant.
-int occupancy(int precision, bool records, int block, size_t lds_bytes, int *blocks_per_cu);
 
 }  // namespace mrt

@@ -72,11 +72,11 @@ class MrtOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("records_mode", C.c_int32),
                 ("max_events", C.c_uint32), ("accumulate", C.c_int32),
                 ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("refill_idle", C.c_int32), ("reserved", C.c_int32)]
 
 
 COUNTER_FIELDS = ("emitted", "missed", "absorbed", "exit_reflected", "exit_transmitted",
-                  "truncated", "detected", "events", "reflections", "records")
+                  "truncated", "detected", "events", "reflections", "records", "refined")
 
 
 class MrtCounters(C.Structure):
@@ -224,7 +224,7 @@ def alloc_images(w, device="cuda", energy=True):
 
 def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_events=0,
           accumulate=False, counts=None, energy=None, want_energy=True, record_buf=None,
-          grid_blocks=0, block_threads=0, stream=None, sync=True):
+          grid_blocks=0, block_threads=0, refill_idle=0, stream=None, sync=True):
     """Trace rays [first, first + n_rays) of workload `w` with ``mrt_trace``.
 
     counts / energy: torch device tensors to fill (allocated when None).
@@ -251,7 +251,7 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
     S = Structs(w)
     opt = MrtOptions(precision=prec, records_mode=mode, max_events=int(max_events),
                      accumulate=1 if accumulate else 0, grid_blocks=int(grid_blocks),
-                     block_threads=int(block_threads))
+                     block_threads=int(block_threads), refill_idle=int(refill_idle))
     cnt = MrtCounters()
     if stream is None:
         stream = torch.cuda.current_stream(counts.device)

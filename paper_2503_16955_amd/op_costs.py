@@ -21,46 +21,83 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# VALU instructions per operation (gfx950, -O3, packed FP32 disabled).
+# VALU instructions per operation in steady state (gfx950, -O3, packed FP32
+# disabled), as counted by derive().
 OP_COSTS = {
-    "f64": {"log": 97, "exp": 41, "asin": 99, "sqrt": 21, "rcp": 11, "expm1": 52,
-            "sincos": 153},
-    "f32": {"log": 13, "exp": 2, "sqrt": 6, "rcp": 11, "expm1": 26, "sincos": 3},
-    "philox": 80,
+    "f64": {"log": 36, "exp": 22, "expm1": 31, "sqrt": 14, "rsqrt": 8, "rcp": 5, "div": 11,
+            "sincos": 40},
+    "f32": {"log": 2, "exp": 2, "expm1": 23, "sqrt": 1, "rsqrt": 1, "rcp": 1, "div": 11,
+            "sincos": 2},
+    "filter": {"gaussian": 37, "pseudo_voigt": 45, "table": 25, "lorentzian": 37, "box": 27},
+    "philox": 53,
 }
 
 PROBES = {
-    ("f64", "log"): ("log_f64", "copy_f64"), ("f64", "exp"): ("exp_f64", "copy_f64"),
-    ("f64", "asin"): ("asin_f64", "copy_f64"), ("f64", "sqrt"): ("sqrt_f64", "copy_f64"),
-    ("f64", "rcp"): ("rcp_f64", "copy_f64"), ("f64", "expm1"): ("expm1_f64", "copy_f64"),
-    ("f64", "sincos"): ("sincos_f64", "copy2_f64"),
-    ("f32", "log"): ("log_f32", "copy_f32"), ("f32", "exp"): ("exp_f32", "copy_f32"),
-    ("f32", "sqrt"): ("sqrt_f32", "copy_f32"), ("f32", "rcp"): ("rcp_f32", "copy_f32"),
-    ("f32", "expm1"): ("expm1_f32", "copy_f32"), ("f32", "sincos"): ("sincos_f32", "copy2_f32"),
-    ("philox",): ("philox", "copy4_u32"),
+    ("f64", "log"): ("log_f64", "glue_f64"), ("f64", "exp"): ("exp_f64", "glue_f64"),
+    ("f64", "expm1"): ("expm1_f64", "glue_f64"), ("f64", "sqrt"): ("sqrt_f64", "glue_f64"),
+    ("f64", "rsqrt"): ("rsqrt_f64", "glue_f64"), ("f64", "rcp"): ("rcp_f64", "glue_f64"),
+    ("f64", "div"): ("div_ieee_f64", "glue_f64"), ("f64", "sincos"): ("sincos_f64", "glue2_f64"),
+    ("f32", "log"): ("log_f32", "glue_f32"), ("f32", "exp"): ("exp_f32", "glue_f32"),
+    ("f32", "expm1"): ("expm1_f32", "glue_f32"), ("f32", "sqrt"): ("sqrt_f32", "glue_f32"),
+    ("f32", "rsqrt"): ("rsqrt_f32", "glue_f32"), ("f32", "rcp"): ("rcp_f32", "glue_f32"),
+    ("f32", "div"): ("div_ieee_f32", "glue_f32"), ("f32", "sincos"): ("sincos_f32", "glue2_f32"),
+    ("philox",): ("philox", "glue_u32"),
+    ("filter", "gaussian"): ("filter_gaussian", "glue_filter"),
+    ("filter", "pseudo_voigt"): ("filter_pseudo_voigt", "glue_filter"),
+    ("filter", "table"): ("filter_table", "glue_filter"),
+    ("filter", "lorentzian"): ("filter_lorentzian", "glue_filter"),
+    ("filter", "box"): ("filter_box", "glue_filter"),
 }
+
+
+def _loop_valu(lines):
+    """VALU instructions inside the loop of one probe kernel: from the target
+    of its backward branch to the branch."""
+    labels, ins = {}, []
+    for line in lines:
+        t = line.strip()
+        m = re.match(r"^[0-9a-f]+ <(L\d+)>:", t)
+        if m:
+            labels[m.group(1)] = len(ins)
+            continue
+        if t:
+            ins.append(t.split("//")[0].strip())
+    best = None
+    for i, x in enumerate(ins):
+        m = re.match(r"s_(?:cbranch_\w+|branch)\s+(L\d+)", x)
+        if m and labels.get(m.group(1), len(ins)) < i:
+            a = labels[m.group(1)]
+            if best is None or i - a > best[1] - best[0]:
+                best = (a, i)
+    if best is None:
+        return 0
+    return sum(1 for x in ins[best[0]:best[1] + 1] if x.startswith("v_"))
 
 
 def derive(hipcc="/opt/rocm/bin/hipcc", objdump="/opt/rocm/llvm/bin/llvm-objdump", tmp="/tmp"):
     """Recount OP_COSTS from the probe kernels' gfx950 code."""
     src = os.path.join(HERE, "csrc", "op_cost_probe.hip")
     obj = os.path.join(tmp, "mosaicrt_op_cost_probe.co")
-    subprocess.check_call([hipcc, "-O3", "--offload-arch=gfx950", "-Xclang", "-target-feature",
-                           "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
-                           "--no-gpu-bundle-output", "-c", src, "-o", obj],
+    subprocess.check_call([hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang",
+                           "-target-feature", "-Xclang", "-packed-fp32-ops", "-I",
+                           os.path.join(HERE, "csrc"), "-I", os.path.join(os.path.dirname(HERE), "include"),
+                           "--cuda-device-only", "--no-gpu-bundle-output", "-c", src, "-o", obj],
                           stderr=subprocess.DEVNULL)
-    dis = subprocess.check_output([objdump, "-d", "--no-show-raw-insn", obj], text=True)
-    counts, cur = {}, None
-    for line in dis.splitlines():
+    dis = subprocess.check_output([objdump, "-d", "--no-show-raw-insn", "--symbolize-operands",
+                                   obj], text=True).splitlines()
+    funcs, cur = {}, None
+    for line in dis:
         m = re.match(r"^[0-9a-f]+ <probe_(\w+)>:", line)
         if m:
             cur = m.group(1)
-            counts[cur] = 0
+            funcs[cur] = []
             continue
-        t = line.strip().split()
-        if cur and t and t[0].startswith("v_"):
-            counts[cur] += 1
-    out = {"f64": {}, "f32": {}}
+        if re.match(r"^[0-9a-f]+ <[^L]", line):
+            cur = None
+        if cur:
+            funcs[cur].append(line)
+    counts = {k: _loop_valu(v) for k, v in funcs.items()}
+    out = {"f64": {}, "f32": {}, "filter": {}}
     for key, (probe, base) in PROBES.items():
         c = counts[probe] - counts[base]
         if key == ("philox",):
@@ -73,50 +110,52 @@ def derive(hipcc="/opt/rocm/bin/hipcc", objdump="/opt/rocm/llvm/bin/llvm-objdump
 def mix(precision, geometry, mosaic, irc, spectrum, mosaic_eta=0.0):
     """Operation mix per unit, in VALU instructions, from OP_COSTS.
 
-    Units: 'ray' (every emitted ray: source draws and front-face entry test),
-    'entered' (Bragg angle and first exit distance), 'event' (one draw of the
-    event uniforms, free path, move, absorption test), 'tilt' (local frame,
-    crystallite normal, Bragg deviation in FP64, rocking-curve value,
-    acceptance test), 'reflection' (reflected direction and new exit distance)
-    and 'detected' (detector plane, pixel, two integer atomics)."""
+    Units: 'ray' (every emitted ray: cone direction and front-face entry
+    test), 'entered' (energy, Bragg angle, first exit distance), 'event' (one
+    draw of the event uniforms, free path, move, absorption test), 'tilt'
+    (local frame, crystallite normal, k.n in FP64, acceptance decision),
+    'reflection' (reflected direction and new exit distance) and 'detected'
+    (detector plane, pixel, two integer atomics).  Plain arithmetic, compares
+    and selects count one each."""
     D = OP_COSTS["f64"]
     R = OP_COSTS["f64"] if precision == "fp64" else OP_COSTS["f32"]
     ph = OP_COSTS["philox"]
+    U = 2 if precision == "fp64" else 3          # word -> uniform
     cyl = geometry == "cylinder"
-    # exit distance: flat = 6 face tests with one reciprocal each;
-    # cylinder = 2 quadratic roots (sqrt + rcp) + 2 end planes + 2 edge planes
-    exit_d = (6 * R["rcp"] + 30) if not cyl else (2 * (R["sqrt"] + R["rcp"]) + 4 * R["rcp"] + 45)
-    entry = (R["rcp"] + 20) if not cyl else (R["sqrt"] + R["rcp"] + 40)
-    source = 2 * ph + 8 + R["sqrt"] + R["sincos"] + 20 + entry
+    if cyl:
+        exit_d = 2 * R["sqrt"] + 6 * R["div"] + 45
+        entry = R["sqrt"] + R["div"] + 30
+        frame = R["rsqrt"] + 18
+    else:
+        exit_d = 6 * R["div"] + 30
+        entry = R["div"] + 20
+        frame = 0
+    ray = ph + 2 * U + R["sqrt"] + R["sincos"] + 18 + entry
     if spectrum == "lines":
-        source += D["log"] + D["sqrt"] + D["sincos"] + 12
+        energy = 8 + ph + D["sincos"] + D["log"] + D["sqrt"] + 6
     elif spectrum == "table":
-        source += 10 * 4 + 6
+        energy = 10 * 4 + 6
     else:
-        source += 2
-    entered = D["rcp"] + D["asin"] + 4 + exit_d + 6
-    event = ph + 8 + R["log"] + 10
-    frame = 0 if not cyl else (6 + R["sqrt"] + R["rcp"] + 3 + 6)
-    vmf = R["log"] + 4 + R["sqrt"] + 3
-    lor = 3 + 2 * R["sqrt"] + 2 * R["rcp"] + 3
+        energy = 2
+    entered = energy + D["div"] + D["sqrt"] + 5 + exit_d
+    event = ph + 4 * U + R["log"] + 8
+    vmf = R["log"] + R["sqrt"] + 8
+    lor = R["rsqrt"] + R["sqrt"] + 8
     if mosaic == "gaussian_vmf":
-        tilt_mdf = vmf
+        mdf = vmf
     elif mosaic == "lorentzian":
-        tilt_mdf = lor
+        mdf = lor
     elif mosaic == "pseudo_voigt":
-        tilt_mdf = 3 + mosaic_eta * lor + (1.0 - mosaic_eta) * vmf
+        mdf = 3 + mosaic_eta * (R["rsqrt"] + 7) + (1.0 - mosaic_eta) * (R["log"] + 7) + R["sqrt"] + 1
     elif mosaic == "wrapped_lorentzian":
-        tilt_mdf = R["expm1"] + 3 + R["sqrt"] + 3
+        mdf = R["expm1"] + R["sqrt"] + 7
     else:
-        tilt_mdf = R["rcp"] + 4 + R["sqrt"] + 3
-    irc_cost = {"gaussian": D["exp"] + 3, "pseudo_voigt": D["exp"] + D["rcp"] + 8,
-                "table": 20, "lorentzian": D["rcp"] + 3, "box": 3}[irc]
-    if precision != "fp64" and irc in ("gaussian", "pseudo_voigt"):
-        irc_cost = irc_cost - D["exp"] + R["exp"] + 2
-    tilt = frame + tilt_mdf + 1 + R["sincos"] + 12 + 6 + D["asin"] + 3 + irc_cost + 2
-    reflection = 9 + 3 + R["sqrt"] + 3 * R["rcp"] + exit_d
-    detected = 12 + R["rcp"] + 14 + 4
-    return {"ray": source, "entered": entered, "event": event, "tilt": tilt,
+        mdf = R["div"] + R["sqrt"] + 7
+    kn = 3 if precision == "fp64" else 9
+    tilt = 2 + frame + mdf + R["sincos"] + 12 + kn + 2 + OP_COSTS["filter"][irc] + 2
+    reflection = 7 + R["rsqrt"] + 3 + exit_d
+    detected = 3 * R["div"] + 36
+    return {"ray": ray, "entered": entered, "event": event, "tilt": tilt,
             "reflection": reflection, "detected": detected}
 
 

@@ -48,7 +48,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(mrt.MrtRockingCurve) == 72
     assert C.sizeof(mrt.MrtDetector) == 112
     assert C.sizeof(mrt.MrtOptions) == 32
-    assert C.sizeof(mrt.MrtCounters) == 88
+    assert C.sizeof(mrt.MrtCounters) == 96
     assert mrt.RECORD_DTYPE.itemsize == 104
 
 

@@ -212,12 +212,31 @@ def test_launch_shape_invariance():
     ref = mrt.trace(w, n_rays=n, records="all")
     rc, re = mrt.image_to_numpy(ref["counts"], ref["energy"])
     rr = mrt.records_to_numpy(ref["records"])
-    for grid, block in [(1, 64), (3, 128), (97, 256), (2048, 64)]:
-        print(f"[shape] grid={grid} block={block}", flush=True)
-        g = mrt.trace(w, n_rays=n, records="all", grid_blocks=grid, block_threads=block)
+    for grid, block, refill in [(1, 64, 0), (3, 128, 1), (97, 256, 64), (2048, 64, 7), (0, 0, 1),
+                                (0, 0, 64)]:
+        print(f"[shape] grid={grid} block={block} refill={refill}", flush=True)
+        g = mrt.trace(w, n_rays=n, records="all", grid_blocks=grid, block_threads=block,
+                      refill_idle=refill)
         gc, ge = mrt.image_to_numpy(g["counts"], g["energy"])
         assert np.array_equal(gc, rc) and np.array_equal(ge, re)
         assert mrt.records_to_numpy(g["records"]).tobytes() == rr.tobytes()
+
+
+@pytest.mark.parametrize("name,n", [("flat_hopg", 100_000), ("von_hamos_hapg", 1_000_000),
+                                    ("flat_stress", 300_000)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_records_kernel_matches_plain_kernel(name, n, precision):
+    """The instance that writes records and the one that does not (the
+    benchmark's) produce the same images and counters."""
+    w = W.get(name)
+    a = mrt.trace(w, n_rays=n, precision=precision, records="all")
+    b = mrt.trace(w, n_rays=n, precision=precision)
+    ac, ae = mrt.image_to_numpy(a["counts"], a["energy"])
+    bc, be = mrt.image_to_numpy(b["counts"], b["energy"])
+    assert np.array_equal(ac, bc) and np.array_equal(ae, be)
+    for f in mrt.COUNTER_FIELDS:
+        if f != "records":
+            assert a["counters"][f] == b["counters"][f], f
 
 
 def test_split_ranges_accumulate():
