@@ -16,6 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # no packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # keep loop-invariant constants out of registers: hoisting them out
+         # of the persistent ray loop costs ~100 VGPRs and halves occupancy,
+         # and the trace kernels are latency-bound at two waves per SIMD
+         "-mllvm", "-disable-machine-licm",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

@@ -49,12 +49,14 @@ __device__ __forceinline__ float u01_f32(uint32_t w) {
     return (float)(((w >> 9) << 1) | 1u) * 0x1p-24f;
 }
 
-// Polynomial step p z + c as the three-operand v_fma_f64.  The compiler
-// otherwise emits the two-address v_fmac_f64, which overwrites its addend and
-// so needs a copy of every loop-invariant coefficient at each use.
+// Polynomial step p z + c as the three-operand v_fma_f64 with the constant
+// coefficient c in scalar registers (built by the scalar unit next to its
+// use).  The compiler otherwise materialises 64-bit coefficients with two
+// VALU moves each and uses the two-address v_fmac_f64, which overwrites its
+// addend and so needs a further copy at every use.  c must be wave-uniform.
 __device__ __forceinline__ double poly_step(double p, double z, double c) {
     double r;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "v"(c));
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "s"(c));
     return r;
 }
 

@@ -1,17 +1,23 @@
-"""VALU instruction cost of the operations on the transport's per-event path,
-as the library's kernels compile them for gfx950, and the algorithmic
-operation count of a trace.
+"""Issue cost of the operations on the transport's per-event path, as the
+library's kernels compile them for gfx950, and the algorithmic work of a
+trace in VALU issue slots.
+
+gfx950 issues VALU instructions at different rates by class (measured with
+a throughput microbenchmark on MI355X: per CU and clock, 32-bit ALU and FP32
+arithmetic 128 lanes, FP64 arithmetic and 32-bit integer multiplies 64 lanes,
+v_mad_u64_u32 ~36 lanes, FP32 transcendentals 32, FP64 rcp/rsq ~21).  One
+issue slot is one lane of the 64-lane-per-clock class, so the peak is
+256 CUs x 64 x 2.4 GHz = 39.32 T slots/s and an instruction costs
+SLOT_WEIGHT of its class.
 
 ``OP_COSTS`` was counted by ``derive()``: each probe kernel in
-``csrc/op_cost_probe.hip`` applies one operation; its VALU instruction count
-in the gfx950 disassembly minus that of the matching copy kernel is the
-operation's cost.  Plain arithmetic (add, mul, fma, compare, select,
-convert) costs one instruction.  The algorithmic work of a trace is the
-method's operation mix per unit (per emitted ray, per entering ray, per event,
-per drawn crystallite tilt, per reflection, per detected ray), each operation
-priced by this table, times the unit counts the trace reports.  It does not
-depend on how the kernel is written: a faster kernel does the same
-algorithmic work in less time.
+``csrc/op_cost_probe.hip`` applies one operation inside a loop (constants
+placed as in the trace kernel); the slot-weighted VALU instructions of its
+loop body, minus those of the glue-only loop, are the operation's cost.
+The algorithmic work of a trace is the method's operation mix per unit
+(per emitted ray, per entering ray, per event, per drawn crystallite tilt,
+per reflection, per detected ray), each operation priced by this table,
+times the unit counts the trace reports.
 """
 from __future__ import annotations
 
@@ -21,16 +27,30 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# VALU instructions per operation in steady state (gfx950, -O3, packed FP32
-# disabled), as counted by derive().
-OP_COSTS = {
-    "f64": {"log": 36, "exp": 22, "expm1": 31, "sqrt": 14, "rsqrt": 8, "rcp": 5, "div": 11,
-            "sincos": 40},
-    "f32": {"log": 2, "exp": 2, "expm1": 23, "sqrt": 1, "rsqrt": 1, "rcp": 1, "div": 11,
-            "sincos": 2},
-    "filter": {"gaussian": 37, "pseudo_voigt": 45, "table": 25, "lorentzian": 37, "box": 27},
-    "philox": 53,
-}
+# Issue slots per VALU instruction class on gfx950 (see the module doc).
+SLOT_WEIGHT = {"alu32": 0.5, "alu64": 1.0, "mad64": 1.75, "trans32": 2.0, "trans64": 3.0}
+_TRANS32 = ("v_exp_f32", "v_log_f32", "v_sqrt_f32", "v_rsq_f32", "v_rcp_f32", "v_sin_f32",
+            "v_cos_f32")
+_TRANS64 = ("v_rcp_f64", "v_rsq_f64", "v_sqrt_f64")
+
+
+def slot_class(op):
+    """Class of a VALU mnemonic (without its encoding suffix)."""
+    op = re.sub(r"_e(32|64)$", "", op)
+    if op.startswith(_TRANS32):
+        return "trans32"
+    if op.startswith(_TRANS64):
+        return "trans64"
+    if op.startswith(("v_mad_u64_u32", "v_mad_i64_i32")):
+        return "mad64"
+    if ("f64" in op or "b64" in op or "u64" in op or "i64" in op
+            or op.startswith(("v_mul_hi_u32", "v_mul_lo_u32", "v_mul_hi_i32"))):
+        return "alu64"
+    return "alu32"
+
+
+# Issue slots per operation in the trace kernels' code, as counted by derive().
+OP_COSTS = {'f64': {'log': 36.5, 'exp': 30.0, 'expm1': 37.0, 'sqrt': 15.0, 'rsqrt': 10.0, 'rcp': 7.0, 'div': 13.0, 'sincos': 34.5}, 'f32': {'log': 2.5, 'exp': 2.5, 'expm1': 13.0, 'sqrt': 2.0, 'rsqrt': 2.0, 'rcp': 2.0, 'div': 7.0, 'sincos': 4.0}, 'filter': {'gaussian': 26.5, 'pseudo_voigt': 33.5, 'table': 17.5, 'lorentzian': 26.5, 'box': 18.0}, 'philox': 51.5}
 
 PROBES = {
     ("f64", "log"): ("log_f64", "glue_f64"), ("f64", "exp"): ("exp_f64", "glue_f64"),
@@ -51,8 +71,8 @@ PROBES = {
 
 
 def _loop_valu(lines):
-    """VALU instructions inside the loop of one probe kernel: from the target
-    of its backward branch to the branch."""
+    """Slot-weighted VALU instructions inside the loop of one probe kernel:
+    from the target of its backward branch to the branch."""
     labels, ins = {}, []
     for line in lines:
         t = line.strip()
@@ -70,19 +90,19 @@ def _loop_valu(lines):
             if best is None or i - a > best[1] - best[0]:
                 best = (a, i)
     if best is None:
-        return 0
-    return sum(1 for x in ins[best[0]:best[1] + 1] if x.startswith("v_"))
+        return 0.0
+    return sum(SLOT_WEIGHT[slot_class(x.split()[0])] for x in ins[best[0]:best[1] + 1]
+               if x.startswith("v_"))
 
 
 def derive(hipcc="/opt/rocm/bin/hipcc", objdump="/opt/rocm/llvm/bin/llvm-objdump", tmp="/tmp"):
     """Recount OP_COSTS from the probe kernels' gfx950 code."""
     src = os.path.join(HERE, "csrc", "op_cost_probe.hip")
     obj = os.path.join(tmp, "mosaicrt_op_cost_probe.co")
-    subprocess.check_call([hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang",
-                           "-target-feature", "-Xclang", "-packed-fp32-ops", "-I",
-                           os.path.join(HERE, "csrc"), "-I", os.path.join(os.path.dirname(HERE), "include"),
-                           "--cuda-device-only", "--no-gpu-bundle-output", "-c", src, "-o", obj],
-                          stderr=subprocess.DEVNULL)
+    from . import build as _build
+    flags = [f for f in _build.FLAGS if f != "-fPIC"]
+    subprocess.check_call([hipcc, *flags, "--cuda-device-only", "--no-gpu-bundle-output", "-c",
+                           src, "-o", obj], stderr=subprocess.DEVNULL)
     dis = subprocess.check_output([objdump, "-d", "--no-show-raw-insn", "--symbolize-operands",
                                    obj], text=True).splitlines()
     funcs, cur = {}, None
@@ -99,7 +119,7 @@ def derive(hipcc="/opt/rocm/bin/hipcc", objdump="/opt/rocm/llvm/bin/llvm-objdump
     counts = {k: _loop_valu(v) for k, v in funcs.items()}
     out = {"f64": {}, "f32": {}, "filter": {}}
     for key, (probe, base) in PROBES.items():
-        c = counts[probe] - counts[base]
+        c = round(counts[probe] - counts[base], 2)
         if key == ("philox",):
             out["philox"] = c
         else:
@@ -108,7 +128,7 @@ def derive(hipcc="/opt/rocm/bin/hipcc", objdump="/opt/rocm/llvm/bin/llvm-objdump
 
 
 def mix(precision, geometry, mosaic, irc, spectrum, mosaic_eta=0.0):
-    """Operation mix per unit, in VALU instructions, from OP_COSTS.
+    """Operation mix per unit, in issue slots, from OP_COSTS.
 
     Units: 'ray' (every emitted ray: cone direction and front-face entry
     test), 'entered' (energy, Bragg angle, first exit distance), 'event' (one
@@ -116,51 +136,55 @@ def mix(precision, geometry, mosaic, irc, spectrum, mosaic_eta=0.0):
     (local frame, crystallite normal, k.n in FP64, acceptance decision),
     'reflection' (reflected direction and new exit distance) and 'detected'
     (detector plane, pixel, two integer atomics).  Plain arithmetic, compares
-    and selects count one each."""
+    and selects count one instruction each, in the precision of the path
+    (FP64 1 slot, FP32 0.5), except the FP64 energy and k.n of both paths."""
     D = OP_COSTS["f64"]
     R = OP_COSTS["f64"] if precision == "fp64" else OP_COSTS["f32"]
+    a = SLOT_WEIGHT["alu64"] if precision == "fp64" else SLOT_WEIGHT["alu32"]
+    d = SLOT_WEIGHT["alu64"]
     ph = OP_COSTS["philox"]
-    U = 2 if precision == "fp64" else 3          # word -> uniform
+    U = 2 * d if precision == "fp64" else 3 * SLOT_WEIGHT["alu32"]   # word -> uniform
     cyl = geometry == "cylinder"
     if cyl:
-        exit_d = 2 * R["sqrt"] + 6 * R["div"] + 45
-        entry = R["sqrt"] + R["div"] + 30
-        frame = R["rsqrt"] + 18
+        exit_d = 2 * R["sqrt"] + 6 * R["div"] + 45 * a
+        entry = R["sqrt"] + R["div"] + 30 * a
+        frame = R["rsqrt"] + 18 * a
     else:
-        exit_d = 6 * R["div"] + 30
-        entry = R["div"] + 20
+        exit_d = 6 * R["div"] + 30 * a
+        entry = R["div"] + 20 * a
         frame = 0
-    ray = ph + 2 * U + R["sqrt"] + R["sincos"] + 18 + entry
+    ray = ph + 2 * U + R["sqrt"] + R["sincos"] + 18 * a + entry
     if spectrum == "lines":
-        energy = 8 + ph + D["sincos"] + D["log"] + D["sqrt"] + 6
+        energy = 8 * d + ph + D["sincos"] + D["log"] + D["sqrt"] + 6 * d
     elif spectrum == "table":
-        energy = 10 * 4 + 6
+        energy = 46 * d
     else:
-        energy = 2
-    entered = energy + D["div"] + D["sqrt"] + 5 + exit_d
-    event = ph + 4 * U + R["log"] + 8
-    vmf = R["log"] + R["sqrt"] + 8
-    lor = R["rsqrt"] + R["sqrt"] + 8
+        energy = 2 * d
+    entered = energy + D["div"] + D["sqrt"] + 5 * d + exit_d
+    event = ph + 4 * U + R["log"] + 8 * a
+    vmf = R["log"] + R["sqrt"] + 8 * a
+    lor = R["rsqrt"] + R["sqrt"] + 8 * a
     if mosaic == "gaussian_vmf":
         mdf = vmf
     elif mosaic == "lorentzian":
         mdf = lor
     elif mosaic == "pseudo_voigt":
-        mdf = 3 + mosaic_eta * (R["rsqrt"] + 7) + (1.0 - mosaic_eta) * (R["log"] + 7) + R["sqrt"] + 1
+        mdf = (3 * a + mosaic_eta * (R["rsqrt"] + 7 * a) + (1.0 - mosaic_eta) * (R["log"] + 7 * a)
+               + R["sqrt"] + a)
     elif mosaic == "wrapped_lorentzian":
-        mdf = R["expm1"] + R["sqrt"] + 7
+        mdf = R["expm1"] + R["sqrt"] + 7 * a
     else:
-        mdf = R["div"] + R["sqrt"] + 7
-    kn = 3 if precision == "fp64" else 9
-    tilt = 2 + frame + mdf + R["sincos"] + 12 + kn + 2 + OP_COSTS["filter"][irc] + 2
-    reflection = 7 + R["rsqrt"] + 3 + exit_d
-    detected = 3 * R["div"] + 36
+        mdf = R["div"] + R["sqrt"] + 7 * a
+    kn = 3 * d if precision == "fp64" else 9 * d
+    tilt = 2 * a + frame + mdf + R["sincos"] + 12 * a + kn + 2 * d + OP_COSTS["filter"][irc] + 2 * a
+    reflection = 7 * a + R["rsqrt"] + 3 * a + exit_d
+    detected = 3 * R["div"] + 36 * a
     return {"ray": ray, "entered": entered, "event": event, "tilt": tilt,
             "reflection": reflection, "detected": detected}
 
 
 def algorithmic_ops(workload, precision, counters):
-    """VALU lane-operations the method needs for a trace with these counters."""
+    """Issue slots the method needs for a trace with these counters."""
     m = workload["mosaic"]
     M = mix(precision, workload["crystal"]["geometry"], m["kind"],
             workload["rocking_curve"]["kind"], workload["source"]["spectrum"],
