@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rays/sec traced (FP32-mixed vs FP64) at matched image; serving p50/p99 latency"
 PEAK_CLOCK_HZ = 2.4e9            # MI355X peak engine clock
-LANES_PER_CU_PER_CLK = 64        # 4 SIMDs x 16 lanes: one VALU lane-op each per clock
+LANES_PER_CU_PER_CLK = 64        # issue slots per CU and clock: the FP64 FMA lane rate
 
 
 def log(msg):
@@ -57,14 +57,32 @@ def run_precision(mrt, w, precision, steps, warmup, n, counts, energy, refill=0)
     return per_step, gpu_ms, wall
 
 
-def roofline(op_costs, w, precision, per_step, cus):
+KIND = {"geometry": {"flat": 0, "cylinder": 1},
+        "mosaic": {"gaussian_vmf": 0, "lorentzian": 1, "pseudo_voigt": 2, "wrapped_lorentzian": 3,
+                   "spherical_wrapped_lorentzian": 4},
+        "irc": {"gaussian": 0, "pseudo_voigt": 1, "table": 2, "lorentzian": 3, "box": 4}}
+
+
+def kernel_name(w, precision, records=False):
+    """The trace-kernel instance a workload runs (as profilers name it)."""
+    r = "double" if precision == "fp64" else "float"
+    g = KIND["geometry"][w["crystal"]["geometry"]]
+    m = KIND["mosaic"][w["mosaic"]["kind"]]
+    i = KIND["irc"][w["rocking_curve"]["kind"]]
+    return (f"void mrt::tk::trace_kernel<{r}, {g}, {m}, {i}, {'true' if records else 'false'}>"
+            "(mrt::TraceParams)")
+
+
+def roofline(op_costs, profiling, w, precision, per_step, cus):
     ops = [op_costs.algorithmic_ops(w, precision, c) for c in per_step]
     ms = [c["kernel_ms"] for c in per_step]
     achieved = sum(o / (m * 1e-3) for o, m in zip(ops, ms)) / len(ops) / 1e12
     peak = cus * LANES_PER_CU_PER_CLK * PEAK_CLOCK_HZ / 1e12
+    name = kernel_name(w, precision)
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
-            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": f"trace_kernel<{'double' if precision == 'fp64' else 'float'}, no records>",
+            "unit": "TOP/s", "frac": round(achieved / peak, 4),
+            "traffic": profiling.traffic_per_launch(name),
+            "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; 32-bit ops cost 1/2)",
             "ops_per_launch": int(sum(ops) / len(ops)),
             "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
 
@@ -78,7 +96,39 @@ def cpu_baseline(w, n):
     dt = time.perf_counter() - t0
     return {"value": round(n / dt, 1), "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"ray ids [0, {n}) of the same workload, FP64, images on, {dt:.2f} s",
-            "events": r["counters"]["events"]}
+            "events": r["counters"]["events"]}, r
+
+
+def precision_report(mrt, precision, w, c64, c32, rays, oracle_result, n_oracle):
+    """FP32-mixed against FP64 at the same rays, both against the oracle."""
+    import numpy as np
+    import torch
+    lines = [e for e, _, _ in w["source"].get("lines", [])]
+    a64, _ = mrt.image_to_numpy(c64)
+    a32, _ = mrt.image_to_numpy(c32)
+    rep = {"rays": rays, "fp32_vs_fp64": precision.compare_images(w, a32, a64, lines)}
+    # per-ray pixel changes on a sample, from device records of both paths
+    n = min(n_oracle, 10_000_000)
+    r64 = mrt.trace(w, n_rays=n, precision="fp64", records="all")["records"]
+    r32 = mrt.trace(w, n_rays=n, precision="fp32_mixed", records="all")["records"]
+    i64, i32 = r64.view(torch.int32), r32.view(torch.int32)
+    d64, d32 = r64[:, 103] == 1, r32[:, 103] == 1
+    moved = (d64 != d32) | (d64 & ((i64[:, 22] != i32[:, 22]) | (i64[:, 23] != i32[:, 23])))
+    rep["sample_rays"] = n
+    rep["detected_rays_moved_fraction"] = float(moved.sum().item()) / max(1, int(d64.sum().item()))
+    del r64, r32, i64, i32
+    if oracle_result is not None:
+        g64 = mrt.trace(w, n_rays=n_oracle, precision="fp64")
+        g32 = mrt.trace(w, n_rays=n_oracle, precision="fp32_mixed")
+        o, _ = oracle_result["counts"], None
+        b64, e64 = mrt.image_to_numpy(g64["counts"], g64["energy"])
+        b32, _ = mrt.image_to_numpy(g32["counts"])
+        rep["oracle_rays"] = n_oracle
+        rep["fp64_vs_oracle_bit_exact"] = bool(np.array_equal(b64, o) and
+                                               np.array_equal(e64, oracle_result["energy_mev"]))
+        rep["fp64_vs_oracle_pixels_differing"] = int(np.count_nonzero(b64 != o))
+        rep["fp32_vs_oracle"] = precision.compare_images(w, b32, o, lines)
+    return rep
 
 
 def main():
@@ -101,17 +151,20 @@ def main():
 
     import torch
     from paper_2503_16955_amd import mosaicrt as mrt
-    from paper_2503_16955_amd import op_costs
+    from paper_2503_16955_amd import op_costs, profiling
     from paper_2503_16955_amd import workloads as W
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    from paper_2503_16955_amd import precision
+
     w = W.get(a.workload)
     n = a.rays or w["n_rays"]
     info = mrt.device_info()
     log(f"device {info['name']} {info['arch']} CUs {info['compute_units']}")
     counts, energy = mrt.alloc_images(w)
+    counts32, energy32 = mrt.alloc_images(w)
 
     per64, gpu_ms64, wall64 = run_precision(mrt, w, "fp64", a.steps, a.warmup, n, counts, energy,
                                             a.refill)
@@ -130,22 +183,26 @@ def main():
                    "parallelism": "1 GPU"},
         "events_per_s": round(events64 / (gpu_ms64 * 1e-3), 1),
         "wall_s": round(wall64, 3),
-        "roofline": roofline(op_costs, w, "fp64", per64, info["compute_units"]),
+        "roofline": roofline(op_costs, profiling, w, "fp64", per64, info["compute_units"]),
         "counters_last_step": {k: v for k, v in per64[-1].items() if k != "kernel_ms"},
     }
     if not a.no_mixed:
-        pm, gms, wl = run_precision(mrt, w, "fp32_mixed", a.steps, a.warmup, n, counts, energy,
-                                    a.refill)
+        pm, gms, wl = run_precision(mrt, w, "fp32_mixed", a.steps, a.warmup, n, counts32,
+                                    energy32, a.refill)
         res["fp32_mixed"] = {
             "value": round(rays / (gms * 1e-3), 1), "unit": "rays/s",
             "ms_per_step": round(gms / a.steps, 4),
             "events_per_s": round(sum(c["events"] for c in pm) / (gms * 1e-3), 1),
             "speedup_vs_fp64": round(gpu_ms64 / gms, 3),
-            "roofline": roofline(op_costs, w, "fp32_mixed", pm, info["compute_units"]),
+            "roofline": roofline(op_costs, profiling, w, "fp32_mixed", pm, info["compute_units"]),
         }
     res["serving"] = None
+    orc = None
     if not a.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, a.cpu_rays)
+        res["cpu_baseline"], orc = cpu_baseline(w, a.cpu_rays)
+    if not a.no_mixed and w["source"]["spectrum"] == "lines" and w["crystal"]["geometry"] == "cylinder":
+        res["precision"] = precision_report(mrt, precision, w, counts, counts32, n * a.steps, orc,
+                                            a.cpu_rays)
     print(json.dumps(res), flush=True)
 
 

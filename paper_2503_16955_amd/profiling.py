@@ -1,0 +1,172 @@
+"""Profile bookkeeping for the trace kernels.
+
+* ``python -m paper_2503_16955_amd.profiling copy [--mib M]`` runs one plain
+  device-to-device copy of M MiB: the reference that scales the HBM byte
+  counters (FETCH_SIZE, WRITE_SIZE) of the same box.
+* ``python -m paper_2503_16955_amd.profiling summarize ...`` turns rocprofv3
+  CSV outputs (kernel trace with stats, and one ``--pmc`` pass per counter
+  group) into a short markdown summary and ``hbm_traffic.json`` (HBM bytes
+  per launch of each trace kernel, scaled by the copy reference).
+* ``sources_sha256()`` fingerprints the kernel sources and build flags;
+  ``hbm_traffic.json`` records it, and a reader treats the traffic as
+  unknown once the kernels have changed since the counters were taken.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(HERE, "csrc", "*.h")) +
+                   glob.glob(os.path.join(HERE, "csrc", "*.hip")) +
+                   glob.glob(os.path.join(HERE, "csrc", "*.cpp")) +
+                   [os.path.join(ROOT, "include", "mosaicrt.h"), os.path.join(HERE, "build.py")])
+    for f in files:
+        if os.path.basename(f) == "op_cost_probe.hip":
+            continue
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(kernel_name):
+    """HBM bytes per launch of a kernel from hbm_traffic.json, or None when the
+    file is missing, lacks the kernel, or predates the current sources."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_sha256():
+        return None
+    k = t.get("kernels", {}).get(kernel_name)
+    return None if k is None else k["hbm_bytes_per_launch"]
+
+
+def copy_reference(mib):
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {n * 4} bytes", flush=True)
+
+
+def _rows(d):
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            out += list(csv.DictReader(fh))
+    return out
+
+
+def _per_kernel(rows):
+    """{(kernel, counter): [value per dispatch]}"""
+    agg = collections.defaultdict(list)
+    for r in rows:
+        agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return agg
+
+
+def _copy_kib(d, counter):
+    vals = [v for (k, c), vs in _per_kernel(_rows(d)).items() if c == counter and "copyBuffer" in k
+            for v in vs]
+    return max(vals) if vals else None
+
+
+def summarize(trace_dir, pmc_dirs, copy_fetch, copy_write, copy_mib, command, out_md, label):
+    lines = [f"# rocprofv3: {label}", "", "Commands (from /tmp on one MI355X, gfx950):", "", "```"]
+    lines += command.strip().splitlines()
+    lines += ["```", ""]
+    # kernel trace statistics
+    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if stats:
+        lines += ["Kernel trace (durations in microseconds):", "",
+                  "| kernel | calls | average us | min us | max us | % |", "|---|---|---|---|---|---|"]
+        with open(stats[0]) as fh:
+            for r in csv.DictReader(fh):
+                lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                             f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                             f"{float(r['Percentage']):.2f} |")
+        lines.append("")
+    # counters
+    agg = collections.defaultdict(list)
+    for d in pmc_dirs:
+        for k, v in _per_kernel(_rows(d)).items():
+            agg[k] += v
+    kernels = sorted({k for k, _ in agg if "trace_kernel" in k})
+    counters = sorted({c for _, c in agg})
+    if kernels:
+        lines += ["Counters per dispatch (mean over dispatches of each trace kernel):", "",
+                  "| counter | " + " | ".join(f"`{k[:60]}`" for k in kernels) + " |",
+                  "|---|" + "---|" * len(kernels)]
+        for c in counters:
+            vals = [agg.get((k, c)) for k in kernels]
+            lines.append(f"| {c} | " + " | ".join(f"{sum(v) / len(v):.4g}" if v else "-" for v in vals)
+                         + " |")
+        lines.append("")
+    cf, cw = _copy_kib(copy_fetch, "FETCH_SIZE"), _copy_kib(copy_write, "WRITE_SIZE")
+    traffic = {"sources_sha256": sources_sha256(), "kernels": {}}
+    if cf and cw:
+        ref_kib = copy_mib * 1024.0
+        sf, sw = ref_kib / cf, ref_kib / cw
+        lines += [f"Copy reference ({copy_mib} MiB read and written): FETCH_SIZE {cf:.0f} KiB, "
+                  f"WRITE_SIZE {cw:.0f} KiB per dispatch, so the scale factors are {sf:.3f} (fetch) "
+                  f"and {sw:.3f} (write).", ""]
+        for k in kernels:
+            f, w = agg.get((k, "FETCH_SIZE")), agg.get((k, "WRITE_SIZE"))
+            if f and w:
+                b = (sum(f) / len(f) * sf + sum(w) / len(w) * sw) * 1024.0
+                traffic["kernels"][k] = {"fetch_kib": sum(f) / len(f), "write_kib": sum(w) / len(w),
+                                         "fetch_scale": sf, "write_scale": sw,
+                                         "hbm_bytes_per_launch": b}
+                lines.append(f"HBM traffic of `{k[:90]}`: {b / 1e6:.2f} MB per launch.")
+        lines.append("")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    return traffic
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=256)
+    s = sub.add_parser("summarize")
+    s.add_argument("--trace", required=True)
+    s.add_argument("--pmc", nargs="*", default=[])
+    s.add_argument("--copy-fetch", required=True)
+    s.add_argument("--copy-write", required=True)
+    s.add_argument("--copy-mib", type=int, default=256)
+    s.add_argument("--command-file", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--label", required=True)
+    s.add_argument("--traffic-json", default=None)
+    a = ap.parse_args()
+    if a.cmd == "copy":
+        copy_reference(a.mib)
+        return
+    with open(a.command_file) as fh:
+        command = fh.read()
+    t = summarize(a.trace, a.pmc, a.copy_fetch, a.copy_write, a.copy_mib, command, a.out, a.label)
+    if a.traffic_json:
+        with open(a.traffic_json, "w") as fh:
+            json.dump(t, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -95,42 +95,7 @@ def images_explained(gpu_counts, gpu_energy, orc_counts, orc_energy, gpu_rec, or
     return ok_c and ok_e
 
 
-def projected_profile(counts):
-    """Sum over rows: counts per column (the dispersive axis)."""
-    return np.asarray(counts, np.float64).sum(axis=0)
-
-
-def centroid(profile, centre_col, half=15):
-    lo = max(0, int(round(centre_col)) - half)
-    hi = min(len(profile), int(round(centre_col)) + half + 1)
-    cols = np.arange(lo, hi, dtype=np.float64)
-    w = profile[lo:hi]
-    return float((cols * w).sum() / w.sum())
-
-
-def fwhm(profile, centre_col, half=15):
-    """Full width at half maximum of the peak near centre_col, by linear
-    interpolation of the half-maximum crossings."""
-    lo = max(0, int(round(centre_col)) - half)
-    hi = min(len(profile), int(round(centre_col)) + half + 1)
-    seg = profile[lo:hi]
-    m = int(np.argmax(seg))
-    hm = seg[m] / 2.0
-    i = m
-    while i > 0 and seg[i] > hm:
-        i -= 1
-    left = i + (hm - seg[i]) / (seg[i + 1] - seg[i]) if seg[i + 1] != seg[i] else float(i)
-    j = m
-    while j < len(seg) - 1 and seg[j] > hm:
-        j += 1
-    right = j - 1 + (seg[j - 1] - hm) / (seg[j - 1] - seg[j]) if seg[j - 1] != seg[j] else float(j)
-    return float(right - left)
-
-
-def chi2_per_pixel(a, b, scale=1.0):
-    """(1 / N) sum over pixels with a + b > 0 of (a - s b)^2 / (a + s^2 b)."""
-    a = np.asarray(a, np.float64).ravel()
-    b = np.asarray(b, np.float64).ravel()
-    m = (a + b) > 0
-    d = a[m] - scale * b[m]
-    return float((d * d / (a[m] + scale * scale * b[m])).sum() / max(1, m.sum()))
+# image-level precision metrics live in the package (they are reported by
+# the benchmark too)
+from paper_2503_16955_amd.precision import (centroid, chi2_per_pixel,  # noqa: E402,F401
+                                            dispersive_profile as projected_profile, fwhm)

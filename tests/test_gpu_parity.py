@@ -360,13 +360,8 @@ def test_fp32_mixed_matches_fp64_statistically():
 
 
 def _line_column(w, e_kev):
-    """Zero-mosaic focus column of an energy on the von Hamos detector: the
-    on-axis focus sits at z = 2 R / tan(alpha_B)."""
-    two_d = w["crystal"]["two_d"]
-    a = math.asin(12.398419843320026 / (two_d * e_kev))
-    z = 2.0 * w["crystal"]["radius"] / math.tan(a)
-    det = w["detector"]
-    return (z - det["centre"][2]) / det["pitch"] + det["nx"] / 2.0
+    from paper_2503_16955_amd.precision import von_hamos_line_column
+    return von_hamos_line_column(w, e_kev)
 
 
 if __name__ == "__main__":
