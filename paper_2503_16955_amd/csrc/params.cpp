@@ -1,0 +1,293 @@
+// Validation of the public structs and construction of the kernels'
+// parameter block, shared by mrt_trace and the request server.
+#include "params.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+namespace mrt {
+
+namespace {
+constexpr double kPi = 3.1415926535897932384626433832795;
+}  // namespace
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *r) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static bool unit(const double *v) { return std::fabs(std::sqrt(dot3(v, v)) - 1.0) <= 1e-12; }
+static bool ortho(const double *a, const double *b) { return std::fabs(dot3(a, b)) <= 1e-12; }
+static bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
+                    const mrt_rocking_curve *r, const mrt_detector *d, Failer fail) {
+    if (!s || !c || !m || !r || !d) return fail(MRT_EINVAL, "null struct pointer");
+    // source
+    if (!finite3(s->origin) || !unit(s->axis) || !unit(s->b1) || !ortho(s->axis, s->b1))
+        return fail(MRT_EINVAL, "source: axis and b1 must be orthonormal unit vectors");
+    if (!(s->half_angle >= 0.0 && s->half_angle < kPi))
+        return fail(MRT_EINVAL, "source: half_angle must lie in [0, pi)");
+    if (s->spectrum < 0 || s->spectrum > 2) return fail(MRT_EINVAL, "source: unknown spectrum kind");
+    if (!(s->e_min > 0.0) || !(s->e_max >= s->e_min))
+        return fail(MRT_EINVAL, "source: need 0 < e_min <= e_max");
+    if (s->spectrum == MRT_SPECTRUM_LINES) {
+        if (s->n_lines < 0 || s->n_lines > 8) return fail(MRT_EINVAL, "source: n_lines must be 0..8");
+        double tot = s->background_w;
+        if (!(s->background_w >= 0.0)) return fail(MRT_EINVAL, "source: negative background weight");
+        for (int j = 0; j < s->n_lines; ++j) {
+            if (!(s->line_sigma[j] >= 0.0) || !(s->line_w[j] >= 0.0) || !(s->line_e[j] > 0.0))
+                return fail(MRT_EINVAL, "source: line %d needs E > 0, sigma >= 0, weight >= 0", j);
+            tot += s->line_w[j];
+        }
+        if (!(tot > 0.0)) return fail(MRT_EINVAL, "source: all spectrum weights are zero");
+    }
+    if (s->spectrum == MRT_SPECTRUM_TABLE) {
+        if (s->n_bins < 1 || !s->bin_w) return fail(MRT_EINVAL, "source: table spectrum needs n_bins >= 1");
+        double tot = 0.0;
+        for (int b = 0; b < s->n_bins; ++b) {
+            if (!(s->bin_w[b] >= 0.0)) return fail(MRT_EINVAL, "source: negative bin weight");
+            tot += s->bin_w[b];
+        }
+        if (!(tot > 0.0)) return fail(MRT_EINVAL, "source: all bin weights are zero");
+    }
+    // crystal
+    if (c->geometry == MRT_GEOMETRY_FLAT) {
+        if (!finite3(c->centre) || !unit(c->normal) || !unit(c->e1) || !ortho(c->normal, c->e1))
+            return fail(MRT_EINVAL, "crystal: normal and e1 must be orthonormal unit vectors");
+    } else if (c->geometry == MRT_GEOMETRY_CYLINDER) {
+        if (!finite3(c->axis_pt) || !unit(c->axis_dir) || !unit(c->ref_dir) ||
+            !ortho(c->axis_dir, c->ref_dir))
+            return fail(MRT_EINVAL, "crystal: axis_dir and ref_dir must be orthonormal unit vectors");
+        if (!(c->radius > 0.0)) return fail(MRT_EINVAL, "crystal: radius must be > 0");
+        if (!(c->width / c->radius < kPi)) return fail(MRT_EINVAL, "crystal: width / radius must be < pi");
+        if (!std::isfinite(c->phi_c) || !std::isfinite(c->z_c)) return fail(MRT_EINVAL, "crystal: bad phi_c / z_c");
+    } else {
+        return fail(MRT_EINVAL, "crystal: unknown geometry");
+    }
+    if (!(c->length > 0.0) || !(c->width > 0.0) || !(c->thickness > 0.0))
+        return fail(MRT_EINVAL, "crystal: length, width and thickness must be > 0");
+    if (!(c->two_d > 0.0)) return fail(MRT_EINVAL, "crystal: two_d must be > 0");
+    if (!(c->mu0 >= 0.0) || !std::isfinite(c->mu0)) return fail(MRT_EINVAL, "crystal: mu0 must be >= 0");
+    if (!(c->mfp > 0.0) || !std::isfinite(c->mfp)) return fail(MRT_EINVAL, "crystal: mfp must be > 0");
+    if (c->max_refl < 0) return fail(MRT_EINVAL, "crystal: max_refl must be >= 0");
+    // mosaic
+    if (m->kind < 0 || m->kind > 4) return fail(MRT_EINVAL, "mosaic: unknown kind");
+    if (!(m->fwhm >= 0.0) || !std::isfinite(m->fwhm)) return fail(MRT_EINVAL, "mosaic: fwhm must be >= 0");
+    if (!(m->eta >= 0.0 && m->eta <= 1.0)) return fail(MRT_EINVAL, "mosaic: eta must lie in [0, 1]");
+    // rocking curve
+    switch (r->kind) {
+    case MRT_IRC_GAUSSIAN: case MRT_IRC_LORENTZIAN: case MRT_IRC_BOX:
+        if (!(r->fwhm > 0.0)) return fail(MRT_EINVAL, "rocking curve: fwhm must be > 0");
+        if (!(r->peak >= 0.0 && r->peak <= 1.0)) return fail(MRT_EINVAL, "rocking curve: peak must lie in [0, 1]");
+        break;
+    case MRT_IRC_PSEUDO_VOIGT:
+        if (!(r->fwhm_g >= 0.0) || !(r->fwhm_l >= 0.0) || !(r->fwhm_g + r->fwhm_l > 0.0))
+            return fail(MRT_EINVAL, "rocking curve: need fwhm_g, fwhm_l >= 0, not both 0");
+        if (!(r->peak >= 0.0 && r->peak <= 1.0)) return fail(MRT_EINVAL, "rocking curve: peak must lie in [0, 1]");
+        break;
+    case MRT_IRC_TABLE:
+        if (r->n_table < 2 || !r->table) return fail(MRT_EINVAL, "rocking curve: table needs n_table >= 2");
+        if (!(r->x_max > r->x_min)) return fail(MRT_EINVAL, "rocking curve: need x_max > x_min");
+        for (int i = 0; i < r->n_table; ++i)
+            if (!(r->table[i] >= 0.0 && r->table[i] <= 1.0))
+                return fail(MRT_EINVAL, "rocking curve: table values must lie in [0, 1]");
+        break;
+    default:
+        return fail(MRT_EINVAL, "rocking curve: unknown kind");
+    }
+    if (!std::isfinite(r->shift)) return fail(MRT_EINVAL, "rocking curve: bad shift");
+    {
+        const size_t lut = r->kind == MRT_IRC_TABLE ? (size_t)r->n_table : 0;
+        const size_t cdf = s->spectrum == MRT_SPECTRUM_TABLE ? (size_t)s->n_bins + 1 : 0;
+        if ((lut + cdf) * sizeof(double) > (size_t)kMaxTableBytes)
+            return fail(MRT_EINVAL, "rocking-curve table plus spectrum bins exceed %d bytes of LDS",
+                        kMaxTableBytes);
+    }
+    // detector
+    if (!finite3(d->centre) || !unit(d->normal) || !unit(d->u) || !unit(d->v) ||
+        !ortho(d->normal, d->u) || !ortho(d->normal, d->v) || !ortho(d->u, d->v))
+        return fail(MRT_EINVAL, "detector: normal, u, v must be orthonormal unit vectors");
+    if (d->nx < 1 || d->ny < 1 || (int64_t)d->nx * (int64_t)d->ny >= (int64_t(1) << 31))
+        return fail(MRT_EINVAL, "detector: need nx, ny >= 1 and nx * ny < 2^31");
+    if (!(d->pitch > 0.0)) return fail(MRT_EINVAL, "detector: pitch must be > 0");
+    return MRT_OK;
+}
+
+static void pvoigt(double g, double l, double *fwhm, double *eta) {
+    // total width and Lorentzian fraction of the pseudo-Voigt (sec. 2.2.1)
+    const double f5 = std::pow(g, 5) + 2.69269 * std::pow(g, 4) * l + 2.42843 * std::pow(g, 3) * l * l +
+                      4.47163 * g * g * std::pow(l, 3) + 0.07842 * g * std::pow(l, 4) + std::pow(l, 5);
+    const double f = std::pow(f5, 0.2);
+    const double q = l / f;
+    *fwhm = f;
+    *eta = 1.36603 * q - 0.47719 * q * q + 0.11116 * q * q * q;
+}
+
+// Fill the kernel parameters; `tables` receives the rocking-curve table
+// followed by the spectrum CDF (uploaded by the caller).
+void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
+                  const mrt_rocking_curve *r, const mrt_detector *d, TraceParams &P,
+                  std::vector<double> &tables) {
+    std::memset(&P, 0, sizeof P);
+    // local origin
+    double O[3];
+    if (c->geometry == MRT_GEOMETRY_FLAT) {
+        for (int i = 0; i < 3; ++i) O[i] = c->centre[i];
+    } else {
+        for (int i = 0; i < 3; ++i) O[i] = c->axis_pt[i] + c->z_c * c->axis_dir[i];
+    }
+    for (int i = 0; i < 3; ++i) P.origin[i] = O[i];
+
+    // source
+    for (int i = 0; i < 3; ++i) {
+        P.so[i] = s->origin[i] - O[i];
+        P.sa[i] = s->axis[i];
+        P.sb1[i] = s->b1[i];
+    }
+    cross3(s->axis, s->b1, P.sb2);
+    const double sh = std::sin(s->half_angle / 2.0);
+    P.vmax = 2.0 * sh * sh;
+    P.spectrum = s->spectrum;
+    P.e_min = s->e_min;
+    P.e_span = s->e_max - s->e_min;
+    if (s->spectrum == MRT_SPECTRUM_LINES) {
+        P.n_lines = s->n_lines;
+        double total = 0.0;
+        for (int j = 0; j < s->n_lines; ++j) total += s->line_w[j];
+        total += s->background_w;
+        double acc = 0.0;
+        for (int j = 0; j < s->n_lines; ++j) {
+            acc += s->line_w[j];
+            P.line_cum[j] = acc / total;
+            P.line_e[j] = s->line_e[j];
+            P.line_sig[j] = s->line_sigma[j];
+        }
+    }
+
+    // crystal
+    P.geometry = c->geometry;
+    P.max_refl = c->max_refl;
+    P.hl = c->length / 2.0;
+    P.hw = c->width / 2.0;
+    P.T = c->thickness;
+    if (c->geometry == MRT_GEOMETRY_FLAT) {
+        for (int i = 0; i < 3; ++i) { P.N[i] = c->normal[i]; P.e1[i] = c->e1[i]; }
+        cross3(c->normal, c->e1, P.e2);
+    } else {
+        double b2[3];
+        cross3(c->axis_dir, c->ref_dir, b2);
+        const double half = c->width / (2.0 * c->radius);
+        const double pp = c->phi_c + half, pm = c->phi_c - half;
+        for (int i = 0; i < 3; ++i) {
+            P.ax[i] = c->axis_dir[i];
+            P.op[i] = -std::sin(pp) * c->ref_dir[i] + std::cos(pp) * b2[i];
+            P.om[i] = std::sin(pm) * c->ref_dir[i] - std::cos(pm) * b2[i];
+        }
+        P.R = c->radius;
+        P.R2 = c->radius * c->radius;
+        const double ro = c->radius + c->thickness;
+        P.Ro2 = ro * ro;
+    }
+    double rmax = r->peak;
+    if (r->kind == MRT_IRC_TABLE) {
+        rmax = 0.0;
+        for (int i = 0; i < r->n_table; ++i) rmax = std::max(rmax, r->table[i]);
+    }
+    const double lambda_c = rmax / c->mfp;   // majorant crystallite-encounter rate
+    const double mu_tot = c->mu0 + lambda_c;
+    P.mu0 = c->mu0;
+    P.inv_mu0 = 1.0 / c->mu0;
+    P.inv_mu_tot = 1.0 / mu_tot;
+    P.p_a = mu_tot > 0.0 ? c->mu0 / mu_tot : 1.0;
+    P.inv_1mpa = 1.0 / (1.0 - P.p_a);
+    P.two_d = c->two_d;
+
+    // mosaic
+    P.mdf = m->kind;
+    P.fwhm = m->fwhm;
+    P.m_eta = m->eta;
+    P.inv_eta = m->eta > 0.0 ? 1.0 / m->eta : 0.0;
+    P.inv_1meta = m->eta < 1.0 ? 1.0 / (1.0 - m->eta) : 0.0;
+    if (m->fwhm > 0.0) {
+        const double sv = m->fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        P.vmf_s2 = sv * sv;
+        P.vmf_floor = std::exp(-2.0 / P.vmf_s2);
+        const double g = m->fwhm / 2.0;
+        P.lor_g = g;
+        P.wl_half_g2 = g * g / 2.0;
+        P.wl_z = std::log((g * g + 4.0) / (g * g));
+        const double a = m->fwhm / 2.0;
+        const double s2 = std::sinh(a / 2.0);
+        P.swl_k = 2.0 * s2 * s2 * 2.0;
+        P.swl_d = std::cosh(a) + 1.0;
+    }
+
+    // rocking curve
+    P.irc = r->kind;
+    P.shift = r->shift;
+    const double ln2 = std::log(2.0);
+    switch (r->kind) {
+    case MRT_IRC_GAUSSIAN:
+        P.g_k = 4.0 * ln2 / (r->fwhm * r->fwhm);
+        break;
+    case MRT_IRC_PSEUDO_VOIGT: {
+        // r(x) / R(0) = A h^2 / (h^2 + x^2) + B exp(-g_k x^2), with
+        // A = eta L(0) / R(0), B = (1 - eta) G(0) / R(0) (Eqs. Gaussian, Lorentz)
+        double w, eta;
+        pvoigt(r->fwhm_g, r->fwhm_l, &w, &eta);
+        P.g_k = 4.0 * ln2 / (w * w);
+        const double g0 = std::sqrt(4.0 * ln2 / (kPi * w * w));
+        const double l0 = 2.0 / (kPi * w);
+        const double r0 = eta * l0 + (1.0 - eta) * g0;
+        P.pv_a = eta * l0 / r0;
+        P.pv_b = (1.0 - eta) * g0 / r0;
+        P.pv_h2 = (w / 2.0) * (w / 2.0);
+        break;
+    }
+    case MRT_IRC_LORENTZIAN:
+        P.lor_h2 = (r->fwhm / 2.0) * (r->fwhm / 2.0);
+        break;
+    case MRT_IRC_BOX:
+        P.box_half = r->fwhm / 2.0;
+        break;
+    case MRT_IRC_TABLE:
+        P.lut_n = r->n_table;
+        P.lut_x0 = r->x_min;
+        P.lut_x1 = r->x_max;
+        P.lut_scale = (double)(r->n_table - 1) / (r->x_max - r->x_min);
+        P.lut_inv_max = rmax > 0.0 ? 1.0 / rmax : 0.0;
+        tables.insert(tables.end(), r->table, r->table + r->n_table);
+        break;
+    }
+    P.g_k_log2e = P.g_k / ln2;
+    if (s->spectrum == MRT_SPECTRUM_TABLE) {
+        P.n_bins = s->n_bins;
+        double total = 0.0;
+        for (int b = 0; b < s->n_bins; ++b) total += s->bin_w[b];
+        double acc = 0.0;
+        for (int b = 0; b <= s->n_bins; ++b) {
+            tables.push_back(b == s->n_bins ? 1.0 : acc / total);
+            if (b < s->n_bins) acc += s->bin_w[b];
+        }
+    }
+
+    // detector
+    for (int i = 0; i < 3; ++i) {
+        P.dP[i] = d->centre[i] - O[i];
+        P.dn[i] = d->normal[i];
+        P.du[i] = d->u[i];
+        P.dv[i] = d->v[i];
+    }
+    P.nx = d->nx;
+    P.ny = d->ny;
+    P.pitch = d->pitch;
+    P.half_nx = (double)d->nx / 2.0;
+    P.half_ny = (double)d->ny / 2.0;
+}
+
+}  // namespace mrt

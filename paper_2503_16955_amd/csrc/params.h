@@ -1,0 +1,30 @@
+// Validation of the public structs and the kernels' parameter block
+// (shared by the one-call path and the request server).
+#pragma once
+#include <vector>
+
+#include "mosaicrt.h"
+#include "trace_params.h"
+
+namespace mrt {
+
+// Error reporter: records a formatted message and returns the status.
+typedef mrt_status (*Failer)(mrt_status, const char *, ...);
+
+// The library's reporter: the message becomes this thread's mrt_last_error().
+mrt_status fail(mrt_status s, const char *fmt, ...);
+const char *last_error();
+void clear_error();
+
+// EINVAL with a message (through `fail`) for an invalid combination.
+mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
+                    const mrt_rocking_curve *r, const mrt_detector *d, Failer fail);
+
+// Fill the parameter block (geometry in crystal-local coordinates); `tables`
+// receives the rocking-curve table followed by the spectrum CDF.  The run
+// fields (ray range, seed, buffers, counters) are left to the caller.
+void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
+                  const mrt_rocking_curve *r, const mrt_detector *d, TraceParams &P,
+                  std::vector<double> &tables);
+
+}  // namespace mrt

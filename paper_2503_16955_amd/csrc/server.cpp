@@ -1,0 +1,390 @@
+// Request server (continuous batching): the host engine around the serving
+// kernel.  The scheduling policy (admission, fair-share rounds, completion)
+// lives in server_plan.h; this file owns the device memory, the background
+// engine thread and the C-ABI.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "mosaicrt.h"
+#include "params.h"
+#include "server_plan.h"
+#include "trace_params.h"
+
+namespace {
+
+using mrt::fail;
+
+// Host record of one request.
+struct Rec {
+    mrt::TraceParams P;            // parameter block (device pointers set at admission)
+    std::vector<double> tables;    // rocking-curve table, then spectrum CDF
+    int32_t nx = 0, ny = 0;
+    uint64_t n_rays = 0;
+    uint32_t *d_counts = nullptr;
+    unsigned long long *d_energy = nullptr;
+    double *d_tables = nullptr;
+    mrt_counters counters{};
+};
+
+}  // namespace
+
+struct mrt_server {
+    mrt_server_config cfg{};
+    int device = 0;
+    mrt::serve::Plan plan;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::map<uint64_t, Rec> recs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread engine;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    mrt::TraceParams *d_slots = nullptr;
+    unsigned long long *d_counters = nullptr;   // max_slots x kNumCounters
+    mrt::ServeChunk *d_chunks = nullptr;
+    mrt::ServeChunk *h_chunks = nullptr;        // pinned staging
+    size_t chunk_cap = 0;
+    unsigned int *d_cursor = nullptr;
+    const void *kernel = nullptr;
+    int grid = 0;
+    std::chrono::steady_clock::time_point t0;
+    mrt_server_stats stats{};
+
+    mrt_server(const mrt_server_config &c, uint64_t round_rays, uint32_t chunk)
+        : cfg(c), plan(c.hbm_budget_bytes, c.max_slots, round_rays, chunk),
+          t0(std::chrono::steady_clock::now()) {}
+
+    double now_ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+            .count();
+    }
+};
+
+namespace {
+
+uint64_t request_bytes(const Rec &r) {
+    return (uint64_t)r.nx * (uint64_t)r.ny * (sizeof(uint32_t) + sizeof(uint64_t)) +
+           r.tables.size() * sizeof(double);
+}
+
+void free_rec(mrt_server *S, Rec &r) {
+    if (r.d_counts) (void)hipFreeAsync(r.d_counts, S->stream);
+    if (r.d_energy) (void)hipFreeAsync(r.d_energy, S->stream);
+    if (r.d_tables) (void)hipFreeAsync(r.d_tables, S->stream);
+    r.d_counts = nullptr;
+    r.d_energy = nullptr;
+    r.d_tables = nullptr;
+}
+
+// Device set-up of an admitted request (engine thread, lock held).
+bool admit_one(mrt_server *S, uint64_t ticket) {
+    Rec &r = S->recs.at(ticket);
+    const int32_t slot = S->plan.find(ticket)->slot;
+    const size_t px = (size_t)r.nx * (size_t)r.ny;
+    hipError_t e = hipMallocAsync((void **)&r.d_counts, px * sizeof(uint32_t), S->stream);
+    if (e == hipSuccess)
+        e = hipMallocAsync((void **)&r.d_energy, px * sizeof(uint64_t), S->stream);
+    if (e == hipSuccess && !r.tables.empty())
+        e = hipMallocAsync((void **)&r.d_tables, r.tables.size() * sizeof(double), S->stream);
+    if (e != hipSuccess) {
+        free_rec(S, r);
+        return false;
+    }
+    mrt::TraceParams &P = r.P;
+    P.counts = r.d_counts;
+    P.energy = r.d_energy;
+    const int nl = P.irc == MRT_IRC_TABLE ? P.lut_n : 0;
+    P.lut = nl ? r.d_tables : nullptr;
+    P.bin_cdf = P.spectrum == MRT_SPECTRUM_TABLE ? r.d_tables + nl : nullptr;
+    P.dev_counters = S->d_counters + (size_t)slot * mrt::kNumCounters;
+    P.records_mode = MRT_RECORDS_NONE;
+    P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : 16u;
+    if (!r.tables.empty())
+        (void)hipMemcpyAsync(r.d_tables, r.tables.data(), r.tables.size() * sizeof(double),
+                             hipMemcpyHostToDevice, S->stream);
+    mrt::launch_zero(r.d_counts, px, S->stream);
+    mrt::launch_zero(r.d_energy, 2 * px, S->stream);
+    mrt::launch_zero(P.dev_counters, 2 * mrt::kNumCounters, S->stream);
+    e = hipMemcpyAsync(&S->d_slots[slot], &P, sizeof(P), hipMemcpyHostToDevice, S->stream);
+    if (e != hipSuccess) {
+        free_rec(S, r);
+        return false;
+    }
+    return true;
+}
+
+void read_counters(mrt_server *S, Rec &r, int32_t slot) {
+    unsigned long long h[mrt::kNumCounters];
+    if (hipMemcpy(h, S->d_counters + (size_t)slot * mrt::kNumCounters, sizeof h,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return;
+    mrt_counters &c = r.counters;
+    c.emitted = r.n_rays;
+    c.missed = h[mrt::kCMissed];
+    c.absorbed = h[mrt::kCAbsorbed];
+    c.exit_reflected = h[mrt::kCExitReflected];
+    c.exit_transmitted = h[mrt::kCExitTransmitted];
+    c.truncated = h[mrt::kCTruncated];
+    c.detected = h[mrt::kCDetected];
+    c.events = h[mrt::kCEvents];
+    c.reflections = h[mrt::kCReflections];
+    c.refined = h[mrt::kCRefined];
+    c.records = 0;
+    c.kernel_ms = 0.0;
+}
+
+void engine(mrt_server *S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        if (S->stop) break;
+        for (uint64_t t : S->plan.admit(S->now_ms()))
+            if (!admit_one(S, t)) S->plan.fail(t, MRT_ENOMEM, S->now_ms());
+        std::vector<mrt::serve::Item> items = S->plan.plan_round();
+        if (items.empty()) {
+            S->cv_done.notify_all();
+            S->cv_work.wait(lk);
+            continue;
+        }
+        const size_t n = items.size();
+        for (size_t i = 0; i < n; ++i)
+            S->h_chunks[i] = mrt::ServeChunk{items[i].first, items[i].count, items[i].slot};
+        lk.unlock();
+        hipError_t e = hipMemcpyAsync(S->d_chunks, S->h_chunks, n * sizeof(mrt::ServeChunk),
+                                      hipMemcpyHostToDevice, S->stream);
+        if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(S->d_cursor, 1, S->stream);
+        if (e == hipSuccess) e = hipEventRecord(S->ev0, S->stream);
+        uint32_t n_chunks = (uint32_t)n;
+        void *args[] = {&S->d_slots, &S->d_chunks, &n_chunks, &S->d_cursor};
+        if (e == hipSuccess)
+            e = hipLaunchKernel(S->kernel, dim3((unsigned)S->grid), dim3(256), args, 0, S->stream);
+        if (e == hipSuccess) e = hipEventRecord(S->ev1, S->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(S->ev1);
+        float ms = 0.0f;
+        if (e == hipSuccess) (void)hipEventElapsedTime(&ms, S->ev0, S->ev1);
+        lk.lock();
+        const double now = S->now_ms();
+        if (e != hipSuccess) {
+            // the device failed: every request of the round fails
+            for (const auto &it : items) {
+                const mrt::serve::Request *q = S->plan.find(it.ticket);
+                if (q && q->state == mrt::serve::kRunning) S->plan.fail(it.ticket, MRT_EDEVICE, now);
+            }
+        } else {
+            S->stats.rounds += 1;
+            S->stats.busy_ms += ms;
+            for (const auto &it : items) S->stats.rays_traced += it.count;
+            for (uint64_t t : S->plan.complete_round(items, now)) {
+                const mrt::serve::Request *q = S->plan.find(t);
+                if (q && q->state == mrt::serve::kDone) read_counters(S, S->recs.at(t), q->slot);
+            }
+        }
+        S->cv_done.notify_all();
+    }
+    S->cv_done.notify_all();
+}
+
+void fill_result(const mrt_server *S, uint64_t ticket, mrt_request_result *out) {
+    const mrt::serve::Request *q = S->plan.find(ticket);
+    const Rec &r = S->recs.at(ticket);
+    std::memset(out, 0, sizeof *out);
+    out->state = q->state;
+    out->status = q->status;
+    out->d_counts = r.d_counts;
+    out->d_energy_mev = (uint64_t *)r.d_energy;
+    out->nx = r.nx;
+    out->ny = r.ny;
+    out->rays_done = q->completed;
+    if (q->state == mrt::serve::kDone) out->counters = r.counters;
+    out->submit_ms = q->t_submit;
+    out->admit_ms = q->t_admit;
+    out->done_ms = q->t_done;
+}
+
+bool terminal(int32_t s) {
+    return s == mrt::serve::kDone || s == mrt::serve::kFailed || s == mrt::serve::kCanceled;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrt_status mrt_server_create(const mrt_server_config *config, mrt_server **out) {
+    if (!config || !out) return fail(MRT_EINVAL, "null argument");
+    const mrt_server_config &c = *config;
+    if (c.hbm_budget_bytes == 0) return fail(MRT_EINVAL, "hbm_budget_bytes must be > 0");
+    if (c.max_slots < 1 || c.max_slots > 1024) return fail(MRT_EINVAL, "max_slots must be 1..1024");
+    if (c.precision != MRT_FP64 && c.precision != MRT_FP32_MIXED)
+        return fail(MRT_EINVAL, "unknown precision");
+    if (c.chunk % 64 != 0) return fail(MRT_EINVAL, "chunk must be a multiple of 64");
+    if (c.refill_idle < 0 || c.refill_idle > 64) return fail(MRT_EINVAL, "refill_idle must be 0..64");
+    const uint64_t round_rays = c.round_rays ? c.round_rays : (1ull << 24);
+    const uint32_t chunk = c.chunk ? c.chunk : 4096u;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MRT_EDEVICE, "no device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(MRT_EDEVICE, "no device properties");
+    mrt_server *S = new mrt_server(c, round_rays, chunk);
+    S->cfg.round_rays = round_rays;
+    S->cfg.chunk = chunk;
+    S->device = dev;
+    S->kernel = mrt::serve_kernel_ptr(c.precision);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->kernel, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    S->grid = per_cu * prop.multiProcessorCount;
+    // chunks of one round: round_rays / chunk full chunks plus one partial per slot
+    S->chunk_cap = (size_t)(round_rays / chunk) + (size_t)c.max_slots * 2 + 16;
+    bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreate(&S->ev0) == hipSuccess && hipEventCreate(&S->ev1) == hipSuccess &&
+              hipMalloc((void **)&S->d_slots, sizeof(mrt::TraceParams) * (size_t)c.max_slots) == hipSuccess &&
+              hipMalloc((void **)&S->d_counters,
+                        sizeof(unsigned long long) * mrt::kNumCounters * (size_t)c.max_slots) == hipSuccess &&
+              hipMalloc((void **)&S->d_chunks, sizeof(mrt::ServeChunk) * S->chunk_cap) == hipSuccess &&
+              hipMalloc((void **)&S->d_cursor, 64) == hipSuccess &&
+              hipHostMalloc((void **)&S->h_chunks, sizeof(mrt::ServeChunk) * S->chunk_cap, 0) == hipSuccess;
+    if (!ok) {
+        mrt_server_destroy(S);
+        return fail(MRT_ENOMEM, "server set-up allocation failed");
+    }
+    S->engine = std::thread(engine, S);
+    *out = S;
+    return MRT_OK;
+}
+
+mrt_status mrt_server_submit(mrt_server *S, const mrt_request *q, uint64_t *ticket) {
+    if (!S || !q || !ticket) return fail(MRT_EINVAL, "null argument");
+    mrt_status st = mrt::validate(q->source, q->crystal, q->mosaic, q->rocking_curve, q->detector,
+                                  fail);
+    if (st != MRT_OK) return st;
+    if (q->n_rays == 0) return fail(MRT_EINVAL, "n_rays must be > 0");
+    Rec r;
+    mrt::build_params(q->source, q->crystal, q->mosaic, q->rocking_curve, q->detector, r.P,
+                      r.tables);
+    r.nx = q->detector->nx;
+    r.ny = q->detector->ny;
+    r.n_rays = q->n_rays;
+    r.P.first = 0;
+    r.P.n = q->n_rays;
+    r.P.seed = q->seed;
+    r.P.key0 = (uint32_t)q->seed;
+    r.P.key1 = (uint32_t)(q->seed >> 32);
+    r.P.max_events = q->max_events ? q->max_events : (1u << 20);
+    const uint64_t bytes = request_bytes(r);
+    std::lock_guard<std::mutex> lk(S->mu);
+    const uint64_t t = S->next_ticket++;
+    if (!S->plan.submit(t, q->n_rays, bytes, S->now_ms()))
+        return fail(MRT_ENOMEM, "request needs %llu bytes, budget is %llu",
+                     (unsigned long long)bytes, (unsigned long long)S->plan.budget());
+    S->recs.emplace(t, std::move(r));
+    S->stats.submitted += 1;
+    *ticket = t;
+    S->cv_work.notify_all();
+    return MRT_OK;
+}
+
+mrt_status mrt_server_poll(mrt_server *S, uint64_t ticket, mrt_request_result *result) {
+    if (!S || !result) return fail(MRT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (!S->plan.find(ticket)) return fail(MRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    fill_result(S, ticket, result);
+    return MRT_OK;
+}
+
+mrt_status mrt_server_wait(mrt_server *S, uint64_t ticket, double timeout_ms,
+                           mrt_request_result *result) {
+    if (!S || !result) return fail(MRT_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (!S->plan.find(ticket)) return fail(MRT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    auto done = [&] { const auto *q = S->plan.find(ticket); return !q || terminal(q->state) || S->stop; };
+    if (timeout_ms < 0) {
+        S->cv_done.wait(lk, done);
+    } else if (!S->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), done)) {
+        fill_result(S, ticket, result);
+        return fail(MRT_EAGAIN, "request %llu not finished", (unsigned long long)ticket);
+    }
+    if (!S->plan.find(ticket)) return fail(MRT_EINVAL, "ticket %llu released", (unsigned long long)ticket);
+    fill_result(S, ticket, result);
+    return MRT_OK;
+}
+
+mrt_status mrt_server_cancel(mrt_server *S, uint64_t ticket) {
+    if (!S) return fail(MRT_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (!S->plan.cancel(ticket, S->now_ms()))
+        return fail(MRT_EINVAL, "ticket %llu is unknown or finished", (unsigned long long)ticket);
+    S->cv_work.notify_all();
+    S->cv_done.notify_all();
+    return MRT_OK;
+}
+
+mrt_status mrt_server_release(mrt_server *S, uint64_t ticket) {
+    if (!S) return fail(MRT_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->recs.find(ticket);
+    if (it == S->recs.end() || S->plan.release(ticket) < 0)
+        return fail(MRT_EINVAL, "ticket %llu is unknown or not finished", (unsigned long long)ticket);
+    free_rec(S, it->second);
+    S->recs.erase(it);
+    S->cv_work.notify_all();   // memory freed: queued requests may fit now
+    return MRT_OK;
+}
+
+mrt_status mrt_server_get_stats(mrt_server *S, mrt_server_stats *out) {
+    if (!S || !out) return fail(MRT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    out->queued = S->plan.queued();
+    out->running = S->plan.running();
+    uint64_t d = 0, f = 0, c = 0;
+    for (const auto &kv : S->recs) {
+        const auto *q = S->plan.find(kv.first);
+        if (!q) continue;
+        d += q->state == mrt::serve::kDone;
+        f += q->state == mrt::serve::kFailed;
+        c += q->state == mrt::serve::kCanceled;
+    }
+    out->done = d;
+    out->failed = f;
+    out->canceled = c;
+    out->used_bytes = S->plan.used_bytes();
+    out->budget_bytes = S->plan.budget();
+    return MRT_OK;
+}
+
+void mrt_server_destroy(mrt_server *S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv_work.notify_all();
+        S->cv_done.notify_all();
+    }
+    if (S->engine.joinable()) S->engine.join();
+    if (S->stream) {
+        for (auto &kv : S->recs) free_rec(S, kv.second);
+        (void)hipStreamSynchronize(S->stream);
+    }
+    if (S->d_slots) (void)hipFree(S->d_slots);
+    if (S->d_counters) (void)hipFree(S->d_counters);
+    if (S->d_chunks) (void)hipFree(S->d_chunks);
+    if (S->d_cursor) (void)hipFree(S->d_cursor);
+    if (S->h_chunks) (void)hipHostFree(S->h_chunks);
+    if (S->ev0) (void)hipEventDestroy(S->ev0);
+    if (S->ev1) (void)hipEventDestroy(S->ev1);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+}
+
+}  // extern "C"

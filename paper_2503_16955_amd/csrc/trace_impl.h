@@ -95,15 +95,33 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// A kind template argument of kAny means: read the kind from the parameter
+// block at run time (one wave always traces rays of one parameter block, so
+// the branches stay wave-uniform).
+constexpr int kAny = -1;
+
 template <class R, int GEOM, int MDF, int IRC, bool REC>
 struct Tracer {
     using RayT = Ray<R, REC>;
     static constexpr bool kF64 = sizeof(R) == 8;
 
+    static __device__ __forceinline__ bool is_flat(const TraceParams &P) {
+        if constexpr (GEOM == kAny) return P.geometry == MRT_GEOMETRY_FLAT;
+        else return GEOM == MRT_GEOMETRY_FLAT;
+    }
+    static __device__ __forceinline__ bool mdf_is(const TraceParams &P, int k) {
+        if constexpr (MDF == kAny) return P.mdf == k;
+        else return MDF == k;
+    }
+    static __device__ __forceinline__ bool irc_is(const TraceParams &P, int k) {
+        if constexpr (IRC == kAny) return P.irc == k;
+        else return IRC == k;
+    }
+
     // ---- crystal geometry (sec. 2.2) ------------------------------------
     // Front-face entry; false on a miss.
     static __device__ __forceinline__ bool entry(const TraceParams &P, V3<R> o, V3<R> k, R &t) {
-        if constexpr (GEOM == MRT_GEOMETRY_FLAT) {
+        if (is_flat(P)) {
             const V3<R> N = ld3<R>(P.N);
             const R zeta = dot(o, N), kn = dot(k, N);
             if (!(kn < R(0))) return false;
@@ -136,7 +154,7 @@ struct Tracer {
     // positive crossing over the faces k moves toward.
     static __device__ __forceinline__ R exit_distance(const TraceParams &P, V3<R> p, V3<R> k) {
         R t = R(INFINITY);
-        if constexpr (GEOM == MRT_GEOMETRY_FLAT) {
+        if (is_flat(P)) {
             const V3<R> N = ld3<R>(P.N), e1 = ld3<R>(P.e1), e2 = ld3<R>(P.e2);
             const R zeta = dot(p, N), xi = dot(p, e1), eta = dot(p, e2);
             const R kn = dot(k, N), k1 = dot(k, e1), k2 = dot(k, e2);
@@ -197,11 +215,11 @@ struct Tracer {
     static __device__ __forceinline__ V3<R> mosaic_normal(const TraceParams &P, R u2, R u3, V3<R> N,
                                                           V3<R> e1, V3<R> e2) {
         R ct, st;
-        if constexpr (MDF == MRT_MOSAIC_GAUSSIAN_VMF) {
+        if (mdf_is(P, MRT_MOSAIC_GAUSSIAN_VMF)) {
             vmf(P, u2, ct, st);
-        } else if constexpr (MDF == MRT_MOSAIC_LORENTZIAN) {
+        } else if (mdf_is(P, MRT_MOSAIC_LORENTZIAN)) {
             lorentz(P, R(1) - u2, ct, st);
-        } else if constexpr (MDF == MRT_MOSAIC_PSEUDO_VOIGT) {
+        } else if (mdf_is(P, MRT_MOSAIC_PSEUDO_VOIGT)) {
             // Lorentzian with probability eta, else von Mises-Fisher; the two
             // branches share the square root of sin(theta)
             const R eta = cvt<R>(P.m_eta);
@@ -223,7 +241,7 @@ struct Tracer {
                 scale = R(1);
             }
             st = scale * dm::sqrt(arg);
-        } else if constexpr (MDF == MRT_MOSAIC_WRAPPED_LORENTZIAN) {
+        } else if (mdf_is(P, MRT_MOSAIC_WRAPPED_LORENTZIAN)) {
             // Eq. WL: density in v proportional to 1 / (g^2 + 2 v)
             R v;
             if constexpr (kF64) v = P.wl_half_g2 * ::expm1(u2 * P.wl_z);
@@ -253,7 +271,7 @@ struct Tracer {
     // axis (flat) or the cylinder axis, e2 = N x e1.
     static __device__ __forceinline__ void frame(const TraceParams &P, V3<R> p, V3<R> &N, V3<R> &e1,
                                                  V3<R> &e2) {
-        if constexpr (GEOM == MRT_GEOMETRY_FLAT) {
+        if (is_flat(P)) {
             N = ld3<R>(P.N);
             e1 = ld3<R>(P.e1);
             e2 = ld3<R>(P.e2);
@@ -269,10 +287,10 @@ struct Tracer {
 
     // ---- rocking curve (sec. 2.2.1): r(x) / R_max at x = Delta - Delta_M ---
     static __device__ __forceinline__ R irc_ratio(const TraceParams &P, const double *lut, double x) {
-        if constexpr (IRC == MRT_IRC_GAUSSIAN) {
+        if (irc_is(P, MRT_IRC_GAUSSIAN)) {
             if constexpr (kF64) return ::exp(-P.g_k * x * x);
             else return dm::exp_((float)(-P.g_k * x * x));
-        } else if constexpr (IRC == MRT_IRC_PSEUDO_VOIGT) {
+        } else if (irc_is(P, MRT_IRC_PSEUDO_VOIGT)) {
             // eta L(x)/R(0) + (1 - eta) G(x)/R(0) = A h^2/(h^2 + x^2) + B exp(-k x^2)
             const double x2 = x * x;
             if constexpr (kF64) {
@@ -282,10 +300,10 @@ struct Tracer {
                 return (float)P.pv_a * h2 * dm::rcp(h2 + xf) +
                        (float)P.pv_b * dm::exp_(-(float)P.g_k * xf);
             }
-        } else if constexpr (IRC == MRT_IRC_LORENTZIAN) {
+        } else if (irc_is(P, MRT_IRC_LORENTZIAN)) {
             if constexpr (kF64) return dm::div(P.lor_h2, P.lor_h2 + x * x);
             else return (float)P.lor_h2 * dm::rcp((float)(P.lor_h2 + x * x));
-        } else if constexpr (IRC == MRT_IRC_BOX) {
+        } else if (irc_is(P, MRT_IRC_BOX)) {
             return __builtin_fabs(x) <= P.box_half ? R(1) : R(0);
         } else {
             // table: linear interpolation on equally spaced nodes, 0 outside
@@ -313,9 +331,9 @@ struct Tracer {
     static constexpr float kFilterErr = 2e-6f;
     static __device__ __forceinline__ float ratio_f32(const TraceParams &P, float a) {
         const float a2 = a * a;
-        if constexpr (IRC == MRT_IRC_GAUSSIAN) {
+        if (irc_is(P, MRT_IRC_GAUSSIAN)) {
             return __builtin_amdgcn_exp2f(-(float)P.g_k_log2e * a2);
-        } else if constexpr (IRC == MRT_IRC_PSEUDO_VOIGT) {
+        } else if (irc_is(P, MRT_IRC_PSEUDO_VOIGT)) {
             const float h2 = (float)P.pv_h2;
             return (float)P.pv_a * h2 * __builtin_amdgcn_rcpf(h2 + a2) +
                    (float)P.pv_b * __builtin_amdgcn_exp2f(-(float)P.g_k_log2e * a2);
@@ -353,14 +371,14 @@ struct Tracer {
             hi = INFINITY;
         }
         lo = lo > 0.0f ? lo : 0.0f;
-        if constexpr (IRC == MRT_IRC_TABLE) {
+        if (irc_is(P, MRT_IRC_TABLE)) {
             // zero outside [x_min, x_max]
             const float x0 = (float)P.lut_x0, x1 = (float)P.lut_x1;
             if (shi < x0 - __builtin_fabsf(x0) * 0x1p-20f - 1e-12f ||
                 slo > x1 + __builtin_fabsf(x1) * 0x1p-20f + 1e-12f)
                 return 0;
             return -1;
-        } else if constexpr (IRC == MRT_IRC_BOX) {
+        } else if (irc_is(P, MRT_IRC_BOX)) {
             const float half = (float)P.box_half;
             if (hi < half * (1.0f - 0x1p-20f)) return 1;
             if (lo > half * (1.0f + 0x1p-20f)) return 0;
@@ -594,46 +612,35 @@ __device__ __forceinline__ void flush(const TraceParams &P, WaveCounts &c) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent trace kernel.
+// The persistent ray loop of one wave.  Lanes whose ray has ended are
+// refilled with new ray ids from the wave's current chunk [next, end), which
+// `claim(next, end)` renews (false when no rays are left); rays that miss the
+// crystal are counted and retired inside the refill.  Events run until
+// refill_at lanes are idle, then the wave refills; once the rays run out the
+// remaining lanes drain.  Counters are flushed to P.dev_counters whenever a
+// new chunk is claimed and at the end.
 // ---------------------------------------------------------------------------
-template <class R, int GEOM, int MDF, int IRC, bool REC>
-__global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
-    using T = Tracer<R, GEOM, MDF, IRC, REC>;
-    extern __shared__ double lds[];
-    // stage the rocking-curve table and the spectrum CDF in LDS
-    const int nl = IRC == MRT_IRC_TABLE ? P.lut_n : 0;
-    const int nc = P.spectrum == MRT_SPECTRUM_TABLE ? P.n_bins + 1 : 0;
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) lds[i] = P.lut[i];
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) lds[nl + i] = P.bin_cdf[i];
-    __syncthreads();
-    const double *lut = lds;
-    const double *cdf = lds + nl;
-
+template <class T, class Claim>
+__device__ __forceinline__ void trace_loop(const TraceParams &P, const double *lut,
+                                           const double *cdf, Claim &claim) {
     typename T::RayT ry;
     bool active = false;
     WaveCounts cnt{};
-    uint64_t next = 0, end = 0;   // wave-uniform chunk cursor (offsets into [0, n))
+    uint64_t next = 0, end = 0;   // wave-uniform cursor of ray ids
     bool more = true;             // wave-uniform: unclaimed rays remain
     const uint32_t refill_at = P.refill_idle < 1u ? 1u : (P.refill_idle > 64u ? 64u : P.refill_idle);
 
     for (;;) {
-        // refill idle lanes from the wave's chunk, claiming chunks as needed;
-        // rays that miss the crystal are counted and retired here
         while (more) {
             const uint64_t idle = ballot(!active);
             const uint32_t nidle = popc(idle);
             if (nidle == 0 || (nidle < refill_at && idle != ~0ull)) break;
             if (next == end) {
                 flush(P, cnt);
-                unsigned long long base = 0;
-                if (__lane_id() == 0) base = atomicAdd(P.chunk_counter, (unsigned long long)P.chunk);
-                base = uniform64(base);
-                if (base >= P.n) {
+                if (!claim(next, end)) {
                     more = false;
                     break;
                 }
-                next = base;
-                end = base + P.chunk < P.n ? base + P.chunk : P.n;
             }
             const uint64_t avail = end - next;
             const uint32_t take = avail < nidle ? (uint32_t)avail : nidle;
@@ -641,7 +648,7 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
             if (!active) {
                 const uint32_t r = lane_rank(idle);
                 if (r < take) {
-                    active = T::start(P, cdf, P.first + next + r, ry);
+                    active = T::start(P, cdf, next + r, ry);
                     missed = !active;
                 }
             }
@@ -654,7 +661,6 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
             continue;
         }
 
-        // events: run until refill_at lanes are idle (drain once rays run out);
         // refill_at is in [1, 64], so keep is at least 1
         const uint32_t keep = more ? 65u - refill_at : 1u;
         for (;;) {
@@ -684,6 +690,39 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
         }
     }
     flush(P, cnt);
+}
+
+// Chunks of one call's ray range, claimed from a global cursor.
+struct RangeClaim {
+    unsigned long long *cursor;
+    uint64_t first, n;
+    uint32_t chunk;
+    __device__ __forceinline__ bool operator()(uint64_t &next, uint64_t &end) {
+        unsigned long long base = 0;
+        if (__lane_id() == 0) base = atomicAdd(cursor, (unsigned long long)chunk);
+        base = uniform64(base);
+        if (base >= n) return false;
+        next = first + base;
+        end = first + (base + chunk < n ? base + chunk : n);
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Persistent trace kernel of one call (sec. 2; rays [P.first, P.first + P.n)).
+// ---------------------------------------------------------------------------
+template <class R, int GEOM, int MDF, int IRC, bool REC>
+__global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
+    using T = Tracer<R, GEOM, MDF, IRC, REC>;
+    extern __shared__ double lds[];
+    // stage the rocking-curve table and the spectrum CDF in LDS
+    const int nl = T::irc_is(P, MRT_IRC_TABLE) ? P.lut_n : 0;
+    const int nc = P.spectrum == MRT_SPECTRUM_TABLE ? P.n_bins + 1 : 0;
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) lds[i] = P.lut[i];
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) lds[nl + i] = P.bin_cdf[i];
+    __syncthreads();
+    RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
+    trace_loop<T>(P, lds, lds + nl, claim);
 }
 
 }  // namespace tk

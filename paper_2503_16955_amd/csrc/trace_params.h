@@ -83,9 +83,20 @@ enum {
     kCEvents, kCReflections, kCRecords, kCRefined, kNumCounters
 };
 
+// One piece of a serving round: rays [first, first + count) of the request
+// whose parameter block is slots[slot].
+struct ServeChunk {
+    uint64_t first;
+    uint32_t count;
+    int32_t slot;
+};
+
 // Kernel of a precision / geometry / mosaic / rocking-curve / records
 // combination (nullptr for an unknown kind).
 const void *trace_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records);
 int launch_zero(void *ptr_u32, size_t n_words, void *stream);
+// Serving kernel of a precision: (const TraceParams *slots, const ServeChunk
+// *chunks, uint32_t n_chunks, unsigned int *cursor).
+const void *serve_kernel_ptr(int precision);
 
 }  // namespace mrt

@@ -119,6 +119,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python paper_2503_16955_amd/build.py` (hipcc, gfx950)")
+    # torch first: its HIP runtime must be the one the library binds to.
+    # torch's HIP library asks for the runtime by a different file name than
+    # the library does, so loading the library first would put a second HIP
+    # runtime in the process, and torch's would then find no GPU.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P = C.POINTER
     L.mrt_trace.restype = C.c_int
@@ -281,3 +286,157 @@ def image_to_numpy(counts=None, energy=None):
     c = counts.cpu().numpy().view(np.uint32) if counts is not None else None
     e = energy.cpu().numpy().view(np.uint64) if energy is not None else None
     return c, e
+
+
+# ---- request server (continuous batching) -----------------------------------
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELED = range(5)
+REQ_STATE_NAMES = ["queued", "running", "done", "failed", "canceled"]
+
+
+class MrtServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int32),
+                ("precision", C.c_int32), ("round_rays", C.c_uint64), ("chunk", C.c_uint32),
+                ("refill_idle", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+
+class MrtRequest(C.Structure):
+    _fields_ = [("source", C.POINTER(MrtSource)), ("crystal", C.POINTER(MrtCrystal)),
+                ("mosaic", C.POINTER(MrtMosaic)), ("rocking_curve", C.POINTER(MrtRockingCurve)),
+                ("detector", C.POINTER(MrtDetector)), ("n_rays", C.c_uint64),
+                ("seed", C.c_uint64), ("max_events", C.c_uint32), ("reserved", C.c_int32)]
+
+
+class MrtRequestResult(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("d_counts", C.c_void_p),
+                ("d_energy_mev", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("rays_done", C.c_uint64), ("counters", MrtCounters), ("submit_ms", C.c_double),
+                ("admit_ms", C.c_double), ("done_ms", C.c_double)]
+
+
+class MrtServerStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "queued", "running", "done", "failed",
+                                          "canceled", "rounds", "rays_traced", "used_bytes",
+                                          "budget_bytes")] + [("busy_ms", C.c_double)]
+
+
+SERVER_EXPORTS = ("mrt_server_create", "mrt_server_submit", "mrt_server_poll", "mrt_server_wait",
+                  "mrt_server_cancel", "mrt_server_release", "mrt_server_get_stats",
+                  "mrt_server_destroy")
+EXPORTS = EXPORTS + SERVER_EXPORTS
+
+
+def _load_server(L):
+    P = C.POINTER
+    if getattr(L, "_server_ready", False):
+        return L
+    L.mrt_server_create.restype = C.c_int
+    L.mrt_server_create.argtypes = [P(MrtServerConfig), P(C.c_void_p)]
+    L.mrt_server_submit.restype = C.c_int
+    L.mrt_server_submit.argtypes = [C.c_void_p, P(MrtRequest), P(C.c_uint64)]
+    L.mrt_server_poll.restype = C.c_int
+    L.mrt_server_poll.argtypes = [C.c_void_p, C.c_uint64, P(MrtRequestResult)]
+    L.mrt_server_wait.restype = C.c_int
+    L.mrt_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_double, P(MrtRequestResult)]
+    L.mrt_server_cancel.restype = C.c_int
+    L.mrt_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
+    L.mrt_server_release.restype = C.c_int
+    L.mrt_server_release.argtypes = [C.c_void_p, C.c_uint64]
+    L.mrt_server_get_stats.restype = C.c_int
+    L.mrt_server_get_stats.argtypes = [C.c_void_p, P(MrtServerStats)]
+    L.mrt_server_destroy.restype = None
+    L.mrt_server_destroy.argtypes = [C.c_void_p]
+    L._server_ready = True
+    return L
+
+
+class _DeviceArray:
+    """Zero-copy view of device memory for torch.as_tensor (the memory stays
+    owned by the server)."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2}
+
+
+class Server:
+    """Continuous-batching request server (``mrt_server_*``).
+
+    submit() queues a workload (its five structs, a ray count and a seed);
+    the server's engine thread admits requests in arrival order by free slot
+    and device-memory budget and traces all running requests in shared
+    rounds.  wait()/poll() return a dict with the state, counters, timing
+    (server clock, ms) and, once admitted, torch views of the request's
+    device-resident images; release() frees them."""
+
+    def __init__(self, hbm_budget_bytes=1 << 30, max_slots=64, precision="fp32_mixed",
+                 round_rays=0, chunk=0, refill_idle=0):
+        self._L = _load_server(load())
+        cfg = MrtServerConfig(hbm_budget_bytes=int(hbm_budget_bytes), max_slots=int(max_slots),
+                              precision=PRECISION[precision], round_rays=int(round_rays),
+                              chunk=int(chunk), refill_idle=int(refill_idle))
+        h = C.c_void_p()
+        _check(self._L.mrt_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self.precision = precision
+
+    def submit(self, w, n_rays=None, seed=None, max_events=0):
+        S = Structs(w)
+        q = MrtRequest(C.pointer(S.source), C.pointer(S.crystal), C.pointer(S.mosaic),
+                       C.pointer(S.rocking_curve), C.pointer(S.detector),
+                       int(w["n_rays"] if n_rays is None else n_rays),
+                       int(w["seed"] if seed is None else seed), int(max_events), 0)
+        t = C.c_uint64()
+        _check(self._L.mrt_server_submit(self._h, C.byref(q), C.byref(t)))
+        return int(t.value)
+
+    def _result(self, r):
+        import torch
+        out = {"state": REQ_STATE_NAMES[r.state], "status": r.status, "rays_done": int(r.rays_done),
+               "submit_ms": r.submit_ms, "admit_ms": r.admit_ms, "done_ms": r.done_ms,
+               "counters": {f: int(getattr(r.counters, f)) for f in COUNTER_FIELDS},
+               "counts": None, "energy": None}
+        if r.d_counts:
+            out["counts"] = torch.as_tensor(_DeviceArray(r.d_counts, (r.ny, r.nx), "<i4"),
+                                            device="cuda")
+            out["energy"] = torch.as_tensor(_DeviceArray(r.d_energy_mev, (r.ny, r.nx), "<i8"),
+                                            device="cuda")
+        return out
+
+    def poll(self, ticket):
+        r = MrtRequestResult()
+        _check(self._L.mrt_server_poll(self._h, int(ticket), C.byref(r)))
+        return self._result(r)
+
+    def wait(self, ticket, timeout_ms=-1.0):
+        r = MrtRequestResult()
+        _check(self._L.mrt_server_wait(self._h, int(ticket), float(timeout_ms), C.byref(r)))
+        return self._result(r)
+
+    def cancel(self, ticket):
+        _check(self._L.mrt_server_cancel(self._h, int(ticket)))
+
+    def release(self, ticket):
+        _check(self._L.mrt_server_release(self._h, int(ticket)))
+
+    def stats(self):
+        s = MrtServerStats()
+        _check(self._L.mrt_server_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in MrtServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            self._L.mrt_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,62 @@
+// Host stand-in for the device side of HIP, used to run the trace kernels'
+// code on the CPU in tests: one wave is 64 coroutines (simt_emu.cpp) that
+// meet at every wave-level operation (ballot, readfirstlane), so the kernels'
+// SIMT control flow executes as written.  Device math builtins map to host
+// functions of equal or better accuracy.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <cmath>
+
+#define __device__
+#define __host__
+#define __global__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__
+
+struct simt_dim3 {
+    unsigned x, y, z;
+};
+extern thread_local simt_dim3 threadIdx, blockIdx, blockDim, gridDim;
+
+// wave primitives (simt_emu.cpp)
+uint64_t simt_ballot(bool p);
+uint32_t simt_readfirstlane(uint32_t v);
+int simt_lane();
+inline void __syncthreads() {}
+
+inline uint64_t __ballot(int p) { return simt_ballot(p != 0); }
+inline int __lane_id() { return simt_lane(); }
+inline unsigned long long __popcll(unsigned long long x) { return (unsigned long long)__builtin_popcountll(x); }
+inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return simt_readfirstlane(v); }
+inline uint32_t __builtin_amdgcn_mbcnt_lo(uint32_t m, uint32_t a) {
+    const int l = simt_lane();
+    const uint32_t below = l >= 32 ? 0xffffffffu : ((1u << l) - 1u);
+    return a + (uint32_t)__builtin_popcount(m & below);
+}
+inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t a) {
+    const int l = simt_lane();
+    const uint32_t below = l <= 32 ? 0u : ((1u << (l - 32)) - 1u);
+    return a + (uint32_t)__builtin_popcount(m & below);
+}
+
+inline unsigned int atomicAdd(unsigned int *p, unsigned int v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v) {
+    return __atomic_fetch_add(p, v, __ATOMIC_RELAXED);
+}
+
+inline long long __double_as_longlong(double x) { long long r; memcpy(&r, &x, 8); return r; }
+inline double __longlong_as_double(long long x) { double r; memcpy(&r, &x, 8); return r; }
+
+inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
+inline double __builtin_amdgcn_rsq(double x) { return 1.0 / std::sqrt(x); }
+inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
+inline float __builtin_amdgcn_rsqf(float x) { return 1.0f / std::sqrt(x); }
+inline float __builtin_amdgcn_sqrtf(float x) { return std::sqrt(x); }
+inline float __builtin_amdgcn_exp2f(float x) { return std::exp2(x); }
+inline float __builtin_amdgcn_logf(float x) { return std::log2(x); }
+inline float __builtin_amdgcn_sinf(float x) { return (float)std::sin(6.283185307179586 * (double)x); }
+inline float __builtin_amdgcn_cosf(float x) { return (float)std::cos(6.283185307179586 * (double)x); }

@@ -1,0 +1,232 @@
+// CPU execution of the trace kernels' device code for tests.  A wave is 64
+// coroutines (ucontext) stepped in lane order; each wave-level operation
+// (ballot, readfirstlane) is a meeting point where every lane must arrive
+// before any continues, which is exactly the lockstep the kernels assume at
+// those points (they only occur in wave-uniform control flow).  A lane that
+// reaches a different meeting point from its wave, or ends early, is an error.
+// Waves of a grid run one after another (a valid interleaving for the
+// kernels, which only communicate through atomics).
+#include <hip/hip_runtime.h>
+#include <ucontext.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
+#include <vector>
+
+#include "mosaicrt.h"
+#include "params.h"
+#include "trace_impl.h"
+#include "trace_params.h"
+
+thread_local simt_dim3 threadIdx, blockIdx, blockDim, gridDim;
+
+namespace {
+
+constexpr int kLanes = 64;
+constexpr size_t kStack = 512 * 1024;
+
+enum Op { kNone = 0, kBallot = 1, kFirst = 2 };
+
+struct Wave {
+    ucontext_t sched;
+    ucontext_t ctx[kLanes];
+    std::vector<char> stacks;
+    int lane = 0;
+    bool finished[kLanes];
+    int op[kLanes];
+    uint64_t arg[kLanes];
+    uint64_t result = 0;
+    long long meetings = 0;
+    int error = 0;
+    std::function<void()> body;
+};
+
+thread_local Wave *g_wave = nullptr;
+
+void lane_entry() {
+    Wave *W = g_wave;
+    W->body();
+    W->finished[W->lane] = true;
+    swapcontext(&W->ctx[W->lane], &W->sched);
+}
+
+uint64_t meet(int op, uint64_t v) {
+    Wave *W = g_wave;
+    W->op[W->lane] = op;
+    W->arg[W->lane] = v;
+    swapcontext(&W->ctx[W->lane], &W->sched);
+    return W->result;
+}
+
+// Run `body` as one wave; returns 0, or -1 on a divergent meeting point.
+int run_wave(const std::function<void()> &body, long long max_meetings) {
+    Wave W;
+    W.stacks.resize(kStack * kLanes);
+    W.body = body;
+    g_wave = &W;
+    for (int l = 0; l < kLanes; ++l) {
+        W.finished[l] = false;
+        getcontext(&W.ctx[l]);
+        W.ctx[l].uc_stack.ss_sp = W.stacks.data() + kStack * l;
+        W.ctx[l].uc_stack.ss_size = kStack;
+        W.ctx[l].uc_link = nullptr;
+        makecontext(&W.ctx[l], lane_entry, 0);
+    }
+    for (;;) {
+        for (int l = 0; l < kLanes; ++l) {
+            W.lane = l;
+            W.op[l] = kNone;
+            threadIdx.x = (unsigned)l;
+            swapcontext(&W.sched, &W.ctx[l]);
+        }
+        int n_done = 0;
+        for (int l = 0; l < kLanes; ++l) n_done += W.finished[l];
+        if (n_done == kLanes) break;
+        if (n_done) { W.error = -1; break; }               // some lanes ended, others wait
+        const int op = W.op[0];
+        for (int l = 1; l < kLanes; ++l)
+            if (W.op[l] != op) W.error = -1;               // lanes at different meeting points
+        if (W.error) break;
+        if (op == kBallot) {
+            uint64_t m = 0;
+            for (int l = 0; l < kLanes; ++l) m |= (W.arg[l] ? 1ull : 0ull) << l;
+            W.result = m;
+        } else {
+            W.result = W.arg[0];
+        }
+        if (++W.meetings > max_meetings) { W.error = -2; break; }
+    }
+    g_wave = nullptr;
+    return W.error;
+}
+
+}  // namespace
+
+uint64_t simt_ballot(bool p) { return meet(kBallot, p ? 1 : 0); }
+uint32_t simt_readfirstlane(uint32_t v) { return (uint32_t)meet(kFirst, v); }
+int simt_lane() { return g_wave ? g_wave->lane : 0; }
+
+namespace mrt {
+// error reporting used by params.cpp
+static thread_local char g_err[512];
+mrt_status fail(mrt_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+const char *last_error() { return g_err; }
+void clear_error() { g_err[0] = 0; }
+}  // namespace mrt
+
+namespace {
+using namespace mrt;
+using namespace mrt::tk;
+
+template <class R>
+void serve_body(const TraceParams *slots, const ServeChunk *chunks, uint32_t n, unsigned int *cursor) {
+    // the serving kernel's body, as in serve.hip
+    using T = Tracer<R, kAny, kAny, kAny, false>;
+    for (;;) {
+        unsigned int c = 0;
+        if (__lane_id() == 0) c = atomicAdd(cursor, 1u);
+        c = uniform(c);
+        if (c >= n) return;
+        const ServeChunk ch = chunks[c];
+        const TraceParams &P = slots[ch.slot];
+        struct OneChunk {
+            uint64_t first, end;
+            bool used;
+            bool operator()(uint64_t &next, uint64_t &e) {
+                if (used) return false;
+                used = true;
+                next = first;
+                e = end;
+                return true;
+            }
+        } claim{ch.first, ch.first + ch.count, false};
+        trace_loop<T>(P, P.lut, P.bin_cdf, claim);
+    }
+}
+
+template <class R, bool REC>
+void trace_body(const TraceParams &P) {
+    using T = Tracer<R, kAny, kAny, kAny, REC>;
+    RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
+    trace_loop<T>(P, P.lut, P.bin_cdf, claim);
+}
+}  // namespace
+
+extern "C" {
+
+// Fill a parameter block from the public structs (host pointers for the
+// tables: the emulated kernels read them in place).
+int emu_build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
+                     const mrt_rocking_curve *r, const mrt_detector *d, TraceParams *P,
+                     double *tables_out, int tables_cap, int *n_tables) {
+    if (mrt::validate(s, c, m, r, d, mrt::fail) != MRT_OK) return -1;
+    std::vector<double> t;
+    mrt::build_params(s, c, m, r, d, *P, t);
+    *n_tables = (int)t.size();
+    if ((int)t.size() > tables_cap) return -2;
+    for (size_t i = 0; i < t.size(); ++i) tables_out[i] = t[i];
+    P->lut = P->irc == MRT_IRC_TABLE ? tables_out : nullptr;
+    P->bin_cdf = P->spectrum == MRT_SPECTRUM_TABLE ? tables_out + (P->irc == MRT_IRC_TABLE ? P->lut_n : 0)
+                                                   : nullptr;
+    return 0;
+}
+int emu_params_size() { return (int)sizeof(TraceParams); }
+
+// The run fields of a parameter block (as the one-call path and the server
+// set them).
+void emu_set_run(TraceParams *P, uint64_t first, uint64_t n, uint64_t seed, uint32_t max_events,
+                 uint32_t *counts, unsigned long long *energy, unsigned long long *counters,
+                 uint32_t chunk, uint32_t refill_idle) {
+    P->first = first;
+    P->n = n;
+    P->seed = seed;
+    P->key0 = (uint32_t)seed;
+    P->key1 = (uint32_t)(seed >> 32);
+    P->max_events = max_events ? max_events : (1u << 20);
+    P->records_mode = MRT_RECORDS_NONE;
+    P->records = nullptr;
+    P->counts = counts;
+    P->energy = energy;
+    P->dev_counters = counters;
+    P->chunk_counter = counters + kNumCounters;
+    P->chunk = chunk;
+    P->refill_idle = refill_idle;
+}
+
+// Run the serving kernel body with n_waves waves; 0 on success.
+int emu_serve(const TraceParams *slots, const ServeChunk *chunks, uint32_t n, int n_waves,
+              int precision, long long max_meetings) {
+    unsigned int cursor = 0;
+    for (int w = 0; w < n_waves; ++w) {
+        int e = run_wave([&] {
+            if (precision == MRT_FP64) serve_body<double>(slots, chunks, n, &cursor);
+            else serve_body<float>(slots, chunks, n, &cursor);
+        }, max_meetings);
+        if (e) return e;
+    }
+    return 0;
+}
+
+// Run the one-call trace loop (ray range P.first .. P.first + P.n) with
+// n_waves waves; P's buffers and counters are host memory.
+int emu_trace(TraceParams *P, int n_waves, int precision, long long max_meetings) {
+    for (int w = 0; w < n_waves; ++w) {
+        int e = run_wave([&] {
+            const bool rec = P->records_mode != MRT_RECORDS_NONE;
+            if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P); else trace_body<double, false>(*P); }
+            else { if (rec) trace_body<float, true>(*P); else trace_body<float, false>(*P); }
+        }, max_meetings);
+        if (e) return e;
+    }
+    return 0;
+}
+
+}  // extern "C"

@@ -155,3 +155,29 @@ def test_valid_call_without_gpu_fails_loudly():
     assert st == mrt.EDEVICE, (st, mrt.last_error())
     with pytest.raises(Exception):
         mrt.trace(W.get("flat_hopg"))
+
+
+def test_server_config_validation_and_no_gpu():
+    """Server configuration errors are EINVAL before any device call; a valid
+    configuration without a GPU is EDEVICE."""
+    import torch
+    L = mrt._load_server(mrt.load())
+    h = C.c_void_p()
+    bad = [dict(hbm_budget_bytes=0), dict(max_slots=0), dict(max_slots=5000), dict(precision=9),
+           dict(chunk=100), dict(refill_idle=65)]
+    for b in bad:
+        cfg = dict(hbm_budget_bytes=1 << 30, max_slots=8, precision=1, round_rays=0, chunk=0,
+                   refill_idle=0)
+        cfg.update(b)
+        assert L.mrt_server_create(C.byref(mrt.MrtServerConfig(**cfg)), C.byref(h)) == mrt.EINVAL, b
+    assert L.mrt_server_create(None, C.byref(h)) == mrt.EINVAL
+    if not torch.cuda.is_available():
+        cfg = mrt.MrtServerConfig(hbm_budget_bytes=1 << 30, max_slots=8, precision=1)
+        assert L.mrt_server_create(C.byref(cfg), C.byref(h)) == mrt.EDEVICE
+
+
+def test_server_struct_sizes():
+    assert C.sizeof(mrt.MrtServerConfig) == 40
+    assert C.sizeof(mrt.MrtRequest) == 64
+    assert C.sizeof(mrt.MrtRequestResult) == 160
+    assert C.sizeof(mrt.MrtServerStats) == 88

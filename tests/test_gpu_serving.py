@@ -1,0 +1,125 @@
+"""The request server on the GPU: every request traced in a mix of
+concurrently running requests (shared rounds of one persistent launch)
+gives exactly the images and counters of the same request traced alone;
+admission respects the memory budget in arrival order; cancellation and
+release return memory."""
+import copy
+import math
+import time
+
+import numpy as np
+import pytest
+
+from paper_2503_16955_amd import mosaicrt as mrt
+from paper_2503_16955_amd import workloads as W
+from serving_mix import mix as _mix
+
+pytestmark = pytest.mark.gpu
+
+WAIT_MS = 60_000.0    # a request of these tests finishes in well under a second
+
+
+def _alone(w, n, seed, precision):
+    r = mrt.trace(w, n_rays=n, seed=seed, precision=precision)
+    c, e = mrt.image_to_numpy(r["counts"], r["energy"])
+    return c, e, r["counters"]
+
+
+def _check_equal(res, w, n, seed, precision):
+    assert res["state"] == "done", res["state"]
+    c = res["counts"].cpu().numpy().view(np.uint32)
+    e = res["energy"].cpu().numpy().view(np.uint64)
+    ac, ae, acnt = _alone(w, n, seed, precision)
+    assert np.array_equal(c, ac) and np.array_equal(e, ae)
+    for f in ("emitted", "missed", "absorbed", "exit_reflected", "exit_transmitted", "truncated",
+              "detected", "events", "reflections", "refined"):
+        assert res["counters"][f] == acnt[f], f
+
+
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
+def test_mix_equals_alone(precision):
+    reqs = _mix()
+    with mrt.Server(hbm_budget_bytes=1 << 30, max_slots=16, precision=precision,
+                    round_rays=1 << 19, chunk=2048) as srv:
+        tickets = [srv.submit(w, n_rays=n, seed=s) for w, n, s in reqs]
+        results = []
+        for t, (w, n, _) in zip(tickets, reqs):
+            results.append(srv.wait(t, timeout_ms=WAIT_MS))
+            print(f"[serve] {precision} ticket {t} {w['name']} n={n} done", flush=True)
+        st = srv.stats()
+        assert st["rounds"] > 3            # the requests shared several rounds
+        assert st["rays_traced"] == sum(n for _, n, _ in reqs)
+        for (w, n, s), r in zip(reqs, results):
+            print(f"[serve] {precision} {w['name']} n={n} rounds={st['rounds']}", flush=True)
+            _check_equal(r, w, n, s, precision)
+        for t in tickets:
+            srv.release(t)
+        assert srv.stats()["used_bytes"] == 0
+
+
+def test_budget_admission_in_arrival_order():
+    w = W.get("von_hamos_hapg")
+    per = 2048 * 512 * 12
+    with mrt.Server(hbm_budget_bytes=2 * per + 1000, max_slots=8, precision="fp32_mixed",
+                    round_rays=1 << 20) as srv:
+        tickets = [srv.submit(w, n_rays=1_000_000 + i, seed=10 + i) for i in range(6)]
+        done = []
+        # release each request as soon as it is done, so the next ones fit
+        pending = list(tickets)
+        while pending:
+            t = pending.pop(0)
+            r = srv.wait(t, timeout_ms=WAIT_MS)
+            done.append(r)
+            _check_equal(r, w, 1_000_000 + tickets.index(t), 10 + tickets.index(t), "fp32_mixed")
+            srv.release(t)
+        admits = [r["admit_ms"] for r in done]
+        assert admits == sorted(admits)
+        # at most two requests' images fit: the third waited for a release
+        assert done[2]["admit_ms"] >= min(done[0]["done_ms"], done[1]["done_ms"])
+
+
+def test_oversized_request_is_rejected():
+    w = W.get("flat_stress")                # 4096^2 images: 192 MiB
+    with mrt.Server(hbm_budget_bytes=64 << 20, max_slots=4) as srv:
+        with pytest.raises(mrt.MosaicRTError) as e:
+            srv.submit(w, n_rays=1000)
+        assert e.value.status == mrt.ENOMEM
+
+
+def test_cancel_and_release():
+    w = W.get("von_hamos_hapg")
+    with mrt.Server(hbm_budget_bytes=1 << 30, max_slots=4, precision="fp32_mixed",
+                    round_rays=1 << 20) as srv:
+        big = srv.submit(w, n_rays=2_000_000_000)
+        small = srv.submit(w, n_rays=100_000, seed=7)
+        time.sleep(0.05)
+        srv.cancel(big)
+        r = srv.wait(big, timeout_ms=WAIT_MS)
+        assert r["state"] == "canceled" and 0 < r["rays_done"] < 2_000_000_000
+        _check_equal(srv.wait(small, timeout_ms=WAIT_MS), w, 100_000, 7, "fp32_mixed")
+        srv.release(big)
+        srv.release(small)
+        assert srv.stats()["used_bytes"] == 0
+        with pytest.raises(mrt.MosaicRTError):
+            srv.release(big)
+
+
+def test_poisson_arrivals_latency_recorded():
+    reqs = W.serving_requests(n=24, seed=4)
+    rng = np.random.default_rng(5)
+    with mrt.Server(hbm_budget_bytes=1 << 30, max_slots=16, precision="fp32_mixed") as srv:
+        tickets = []
+        for w in reqs:
+            w = copy.deepcopy(w)
+            w["n_rays"] = min(w["n_rays"], 2_000_000)
+            time.sleep(rng.exponential(0.002))
+            tickets.append((srv.submit(w), w))
+        lat = []
+        for t, w in tickets:
+            r = srv.wait(t, timeout_ms=WAIT_MS)
+            assert r["state"] == "done"
+            lat.append(r["done_ms"] - r["submit_ms"])
+            srv.release(t)
+        assert all(x > 0 for x in lat)
+        print(f"[serve] p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms",
+              flush=True)

@@ -1,0 +1,246 @@
+"""The request server's host engine (server.cpp, through its C-ABI) on the CPU
+against a fake HIP runtime (helpers/fakehip): device memory is host memory
+with a byte budget, stream work runs at once, and the serving "kernel"
+(helpers/server_harness.cpp) adds a hash of (seed, ray id) for every ray of
+every chunk of a round to the request's images and counters.  The expected
+images of a request therefore follow from its seed and ray count alone, which
+checks that rounds cover every ray of every request exactly once and that
+results land in the request's own buffers.  A gate holds the fake kernel, so
+requests can be observed while a round is in flight."""
+import ctypes as C
+import os
+import subprocess
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2503_16955_amd import mosaicrt as mrt
+from paper_2503_16955_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2503_16955_amd", "csrc")
+DEVICE_BYTES = 1 << 40
+M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    out = tmp_path_factory.mktemp("engine") / "libserver_harness.so"
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-pthread", "-shared", "-fPIC",
+                           "-I", os.path.join(HERE, "helpers", "fakehip"),
+                           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                           os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "params.cpp"),
+                           os.path.join(HERE, "helpers", "server_harness.cpp"), "-o", str(out)])
+    L = mrt._load_server(C.CDLL(str(out)))
+    L.harness_init.argtypes = [C.c_long, C.c_int]
+    L.harness_free_bytes.restype = C.c_long
+    L.harness_gate.argtypes = [C.c_int]
+    L.harness_launches.restype = C.c_long
+    L.harness_last_error.restype = C.c_char_p
+    return L
+
+
+def _mix64(x):
+    x = x ^ (x >> np.uint64(30))
+    x = x * np.uint64(0xBF58476D1CE4E5B9)
+    x = x ^ (x >> np.uint64(27))
+    x = x * np.uint64(0x94D049BB133111EB)
+    return x ^ (x >> np.uint64(31))
+
+
+def expected(n, seed, px):
+    """Images and counters the fake kernel produces for rays 0..n-1."""
+    with np.errstate(over="ignore"):
+        ids = np.arange(n, dtype=np.uint64)
+        h = _mix64(np.uint64(seed) * np.uint64(0x9E3779B97F4A7C15) + ids)
+    pix = (h % np.uint64(px)).astype(np.int64)
+    counts = np.bincount(pix, minlength=px).astype(np.uint32)
+    energy = np.zeros(px, np.uint64)
+    np.add.at(energy, pix, ids)
+    missed = int(((h >> np.uint64(60)) & np.uint64(1)).sum())
+    events = int((np.uint64(1) + ((h >> np.uint64(50)) & np.uint64(3))).sum())
+    return counts, energy, dict(missed=missed, events=events, detected=n, emitted=n)
+
+
+class Srv:
+    def __init__(self, L, budget=1 << 30, slots=4, round_rays=8192, chunk=1024,
+                 precision="fp32_mixed"):
+        self.L = L
+        cfg = mrt.MrtServerConfig(hbm_budget_bytes=budget, max_slots=slots,
+                                  precision=mrt.PRECISION[precision], round_rays=round_rays,
+                                  chunk=chunk, refill_idle=0)
+        h = C.c_void_p()
+        assert L.mrt_server_create(C.byref(cfg), C.byref(h)) == 0
+        self.h = h
+        self.keep = []
+
+    def submit(self, w, n, seed):
+        S = mrt.Structs(w)
+        self.keep.append(S)
+        q = mrt.MrtRequest(C.pointer(S.source), C.pointer(S.crystal), C.pointer(S.mosaic),
+                           C.pointer(S.rocking_curve), C.pointer(S.detector), n, seed, 0, 0)
+        t = C.c_uint64()
+        st = self.L.mrt_server_submit(self.h, C.byref(q), C.byref(t))
+        return st, t.value
+
+    def wait(self, t, timeout_ms=10_000.0):
+        r = mrt.MrtRequestResult()
+        st = self.L.mrt_server_wait(self.h, t, timeout_ms, C.byref(r))
+        return st, r
+
+    def stats(self):
+        s = mrt.MrtServerStats()
+        assert self.L.mrt_server_get_stats(self.h, C.byref(s)) == 0
+        return s
+
+    def destroy(self):
+        if self.h:
+            self.L.mrt_server_destroy(self.h)
+            self.h = None
+
+
+def _images(r):
+    px = r.nx * r.ny
+    c = np.ctypeslib.as_array((C.c_uint32 * px).from_address(r.d_counts)).copy()
+    e = np.ctypeslib.as_array((C.c_uint64 * px).from_address(r.d_energy_mev)).copy()
+    return c, e
+
+
+def test_every_ray_of_every_request_exactly_once(lib):
+    lib.harness_init(DEVICE_BYTES, 0)
+    w = W.get("flat_hopg")
+    px = w["detector"]["nx"] * w["detector"]["ny"]
+    reqs = [(1, 11), (1000, 12), (5000, 13), (20_000, 14), (33_333, 15), (64, 16), (65, 17)]
+    s = Srv(lib)
+    try:
+        tickets = []
+        for n, seed in reqs:
+            st, t = s.submit(w, n, seed)
+            assert st == 0
+            tickets.append(t)
+        for t, (n, seed) in zip(tickets, reqs):
+            st, r = s.wait(t)
+            assert st == 0 and r.state == mrt.REQ_DONE, (st, r.state)
+            assert r.rays_done == n
+            c, e = _images(r)
+            ec, ee, cnt = expected(n, seed, px)
+            assert np.array_equal(c, ec) and np.array_equal(e, ee)
+            for k, v in cnt.items():
+                assert getattr(r.counters, k) == v, k
+            assert r.submit_ms <= r.admit_ms <= r.done_ms
+        st = s.stats()
+        assert st.rounds > 1 and st.rays_traced == sum(n for n, _ in reqs)
+        assert st.done == len(reqs)
+        for t in tickets:
+            assert lib.mrt_server_release(s.h, t) == 0
+        assert s.stats().used_bytes == 0
+    finally:
+        s.destroy()
+    assert lib.harness_free_bytes() == DEVICE_BYTES      # everything returned
+
+
+def test_failed_launch_fails_its_round_only(lib):
+    lib.harness_init(DEVICE_BYTES, 1)
+    w = W.get("flat_hopg")
+    s = Srv(lib)
+    try:
+        st, t1 = s.submit(w, 3000, 1)
+        st1, r1 = s.wait(t1)
+        assert st1 == 0 and r1.state == mrt.REQ_FAILED and r1.status == mrt.EDEVICE
+        st, t2 = s.submit(w, 3000, 2)
+        st2, r2 = s.wait(t2)
+        assert st2 == 0 and r2.state == mrt.REQ_DONE and r2.rays_done == 3000
+        assert lib.mrt_server_release(s.h, t1) == 0 and lib.mrt_server_release(s.h, t2) == 0
+    finally:
+        s.destroy()
+    assert lib.harness_free_bytes() == DEVICE_BYTES
+
+
+def test_device_allocation_failure_fails_the_request(lib):
+    w = W.get("flat_hopg")
+    px = w["detector"]["nx"] * w["detector"]["ny"]
+    lib.harness_init(DEVICE_BYTES, 0)
+    s = Srv(lib)
+    fixed = DEVICE_BYTES - lib.harness_free_bytes()      # the server's own buffers
+    s.destroy()
+    # room for the server's buffers and half of one request's images
+    lib.harness_init(fixed + px * 6, 0)
+    s = Srv(lib)
+    try:
+        st, t = s.submit(w, 1000, 3)
+        assert st == 0
+        st, r = s.wait(t)
+        assert st == 0 and r.state == mrt.REQ_FAILED and r.status == mrt.ENOMEM
+        assert s.stats().used_bytes == 0
+        assert lib.mrt_server_release(s.h, t) == 0
+    finally:
+        s.destroy()
+    assert lib.harness_free_bytes() == fixed + px * 6
+
+
+def test_wait_timeout_then_cancel_while_running(lib):
+    lib.harness_init(DEVICE_BYTES, 0)
+    lib.harness_gate(0)
+    w = W.get("flat_hopg")
+    s = Srv(lib, round_rays=4096, chunk=1024)
+    try:
+        st, t = s.submit(w, 1_000_000, 4)
+        assert st == 0
+        st, r = s.wait(t, timeout_ms=50.0)
+        assert st == mrt.EAGAIN and r.state == mrt.REQ_RUNNING
+        assert lib.mrt_server_cancel(s.h, t) == 0
+        lib.harness_gate(1)
+        st, r = s.wait(t)
+        assert st == 0 and r.state == mrt.REQ_CANCELED
+        assert 0 < r.rays_done < 1_000_000 and r.rays_done % 1024 == 0
+        assert lib.mrt_server_cancel(s.h, t) != 0           # already finished
+        assert lib.mrt_server_release(s.h, t) == 0
+        assert lib.mrt_server_release(s.h, t) != 0          # already released
+    finally:
+        lib.harness_gate(1)
+        s.destroy()
+    assert lib.harness_free_bytes() == DEVICE_BYTES
+
+
+def test_cancel_queued_request_and_unknown_tickets(lib):
+    lib.harness_init(DEVICE_BYTES, 0)
+    lib.harness_gate(0)
+    w = W.get("flat_hopg")
+    s = Srv(lib, slots=1)
+    try:
+        _, t1 = s.submit(w, 100_000, 5)
+        _, t2 = s.submit(w, 1000, 6)          # queued behind t1 (one slot)
+        time.sleep(0.05)
+        assert lib.mrt_server_cancel(s.h, t2) == 0
+        st, r2 = s.wait(t2)
+        assert st == 0 and r2.state == mrt.REQ_CANCELED and r2.rays_done == 0
+        lib.harness_gate(1)
+        st, r1 = s.wait(t1)
+        assert st == 0 and r1.state == mrt.REQ_DONE
+        r = mrt.MrtRequestResult()
+        assert lib.mrt_server_poll(s.h, 999_999, C.byref(r)) == mrt.EINVAL
+        assert lib.mrt_server_release(s.h, 999_999) == mrt.EINVAL
+    finally:
+        lib.harness_gate(1)
+        s.destroy()
+
+
+def test_destroy_with_work_in_flight_returns(lib):
+    lib.harness_init(DEVICE_BYTES, 0)
+    lib.harness_gate(0)
+    w = W.get("flat_hopg")
+    s = Srv(lib)
+    for i in range(6):
+        assert s.submit(w, 50_000, 100 + i)[0] == 0
+    deadline = time.time() + 5
+    while lib.harness_launches() == 0 and time.time() < deadline:
+        time.sleep(0.001)
+    assert lib.harness_launches() > 0
+    opener = threading.Timer(0.1, lambda: lib.harness_gate(1))
+    opener.start()
+    s.destroy()              # waits for the round in flight, frees everything
+    opener.join()
+    assert lib.harness_free_bytes() == DEVICE_BYTES

@@ -1,0 +1,129 @@
+"""The kernels' device code run on the CPU: the serving kernel's body and the
+one-call trace loop (runtime kinds) execute under a SIMT emulator
+(helpers/simt_emu.cpp: 64 coroutines per wave that meet at every ballot and
+readfirstlane), so their wave-level control flow (lane refill, chunk claims,
+drain, counter flushes) runs as written, without a GPU.
+
+Checks: every emulated wave terminates with its lanes in lockstep at each
+wave operation; the serving kernel, fed a round list that interleaves chunks
+of the whole request mix, gives each request exactly the images and counters
+of the same request traced alone; the counters balance (every emitted ray
+ends in exactly one way).
+
+What the emulation cannot show is how the compiler maps this control flow to
+the hardware's exec masks; that is checked on the GPU."""
+import ctypes as C
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2503_16955_amd import mosaicrt as mrt
+from serving_mix import mix
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2503_16955_amd", "csrc")
+N_COUNTERS = 10            # device counter words per request (kNumCounters)
+SCALE = 0.002              # ray counts of the mix scaled down for the emulator
+WAVES = 4
+MAX_MEETINGS = 10 ** 9
+
+# The one inline-asm statement of the device math (a v_fma_f64 with a scalar
+# operand) becomes the equivalent fused multiply-add on the host.
+ASM_FMA = 'asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "s"(c));'
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    d = tmp_path_factory.mktemp("simt")
+    for f in ("trace_impl.h", "trace_params.h", "device_math.h", "params.h", "params.cpp"):
+        shutil.copy(os.path.join(CSRC, f), d / f)
+    dm = (d / "device_math.h").read_text()
+    assert dm.count(ASM_FMA) == 1, "device_math.h: the inline asm this test replaces has changed"
+    (d / "device_math.h").write_text(dm.replace(ASM_FMA, "r = __builtin_fma(p, z, c);"))
+    lib = d / "libsimt_emu.so"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
+                           "-I", os.path.join(HERE, "helpers", "fakedev"), "-I", str(d),
+                           "-I", os.path.join(ROOT, "include"),
+                           os.path.join(HERE, "helpers", "simt_emu.cpp"), str(d / "params.cpp"),
+                           "-o", str(lib)])
+    L = C.CDLL(str(lib))
+    L.emu_build_params.argtypes = [C.c_void_p] * 7 + [C.c_int, C.c_void_p]
+    L.emu_set_run.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32]
+    L.emu_trace.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_longlong]
+    L.emu_serve.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int, C.c_int, C.c_longlong]
+    return L
+
+
+class Job:
+    """One request: its parameter block, tables, images and counters in host
+    memory (the emulated kernels use them in place)."""
+
+    def __init__(self, L, w, n, seed):
+        self.S = mrt.Structs(w)
+        self.P = (C.c_char * L.emu_params_size())()
+        self.tab = np.zeros(1 << 16, np.float64)
+        nt = C.c_int()
+        r = L.emu_build_params(*[C.cast(x, C.c_void_p) for x in self.S.refs()], C.byref(self.P),
+                               self.tab.ctypes.data, len(self.tab), C.byref(nt))
+        assert r == 0, r
+        px = w["detector"]["nx"] * w["detector"]["ny"]
+        self.counts = np.zeros(px, np.uint32)
+        self.energy = np.zeros(px, np.uint64)
+        self.cnt = np.zeros(N_COUNTERS + 8, np.uint64)
+        L.emu_set_run(self.P, 0, n, seed, 0, self.counts.ctypes.data, self.energy.ctypes.data,
+                      self.cnt.ctypes.data, 64, 16)
+        self.n = n
+
+    def counters(self):
+        names = ("missed", "absorbed", "exit_reflected", "exit_transmitted", "truncated",
+                 "detected", "events", "reflections", "records", "refined")
+        return dict(zip(names, (int(x) for x in self.cnt[:N_COUNTERS])))
+
+
+def _jobs():
+    out = []
+    for w, n, s in mix():
+        out.append((w, n if n < 5000 else max(1, int(n * SCALE)), s))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
+def test_served_mix_equals_requests_alone(emu, precision):
+    prec = mrt.PRECISION[precision]
+    jobs = _jobs()
+    alone = []
+    for w, n, s in jobs:
+        j = Job(emu, w, n, s)
+        assert emu.emu_trace(j.P, WAVES, prec, MAX_MEETINGS) == 0, w["name"]
+        c = j.counters()
+        ended = (c["missed"] + c["absorbed"] + c["exit_reflected"] + c["exit_transmitted"]
+                 + c["truncated"])
+        assert ended == n, (w["name"], c)
+        assert c["detected"] <= c["exit_reflected"] + c["exit_transmitted"]
+        alone.append(j)
+
+    served = [Job(emu, w, n, s) for w, n, s in jobs]
+    ps = len(served[0].P)
+    slots = (C.c_char * (ps * len(served)))()
+    for i, j in enumerate(served):
+        C.memmove(C.addressof(slots) + i * ps, j.P, ps)
+    # a round list interleaving 256-ray chunks of every request
+    items, pos = [], [0] * len(served)
+    while any(p < j.n for p, j in zip(pos, served)):
+        for i, j in enumerate(served):
+            if pos[i] < j.n:
+                c = min(256, j.n - pos[i])
+                items.append((pos[i], c, i))
+                pos[i] += c
+    ch = np.array(items, dtype=[("first", "<u8"), ("count", "<u4"), ("slot", "<i4")])
+    assert emu.emu_serve(slots, ch.ctypes.data, len(ch), 3 * WAVES, prec, MAX_MEETINGS) == 0
+
+    for a, b, (w, n, s) in zip(alone, served, jobs):
+        assert np.array_equal(a.counts, b.counts), (w["name"], n)
+        assert np.array_equal(a.energy, b.energy), (w["name"], n)
+        assert a.counters() == b.counters(), (w["name"], n)
