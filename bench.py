@@ -9,11 +9,17 @@ pseudo-Voigt rocking curve 50/8 urad, two lines at 8.048 / 8.028 keV on a flat
 (step s traces ray ids [s N, (s + 1) N), so K steps are one K N-ray
 simulation).  The same steps are then run in FP32-mixed precision.
 
+Then the request server serves 256 spectrometer-design requests (varied
+crystal radius, mosaic, thickness, energy window; ray counts log-uniform in
+1e5-1e8) in each precision: once all queued at once (saturated rays/s), once
+with Poisson arrivals at 0.7 times that rate (p50/p99 latency from submission
+to completion, rays/s).
+
 Printed: one JSON line with rays/s (FP64 is `value`), events/s, the ALU
 roofline of the trace kernel (algorithmic VALU lane-operations per launch over
 the kernel's HIP-event duration on its stream, against 256 CUs x 64 lanes x
-2.4 GHz), and the FP64 CPU oracle timed on a bounded sample of the same
-workload on the host's cores.
+2.4 GHz), the serving figures, and the FP64 CPU oracle timed on a bounded
+sample of the same workload on the host's cores.
 """
 import argparse
 import json
@@ -131,6 +137,79 @@ def precision_report(mrt, precision, w, c64, c32, rays, oracle_result, n_oracle)
     return rep
 
 
+def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None):
+    """Serve the requests: submitted all at once (gaps_s None) or with the
+    given inter-arrival gaps; a consumer thread takes each finished request
+    from the completion queue and releases it at once.  Returns per-request
+    latencies (ms, server clock), rays, the span from first submission to last
+    completion (s) and the server's stats."""
+    import threading
+    n = len(reqs)
+    done = []
+    srv = mrt.Server(hbm_budget_bytes=budget, max_slots=max_slots, precision=precision)
+
+    def consume():
+        for _ in range(n):
+            t, r = srv.wait_any(views=False)
+            if r["state"] != "done":
+                raise RuntimeError(f"request {t} ended {r['state']} (status {r['status']})")
+            done.append(r)
+            srv.release(t)
+
+    th = threading.Thread(target=consume)
+    th.start()
+    try:
+        for i, w in enumerate(reqs):
+            if gaps_s is not None and i:
+                time.sleep(gaps_s[i])
+            srv.submit(w)
+        th.join()
+        st = srv.stats()
+    finally:
+        srv.close()
+    if len(done) != n:
+        raise RuntimeError("serving: not every request finished")
+    lat = [r["done_ms"] - r["submit_ms"] for r in done]
+    span = (max(r["done_ms"] for r in done) - min(r["submit_ms"] for r in done)) * 1e-3
+    return lat, span, st
+
+
+def serving(mrt, W, n_requests, budget, max_slots, load, seed=4):
+    """The serving workload (design requests of varied geometry and ray
+    count): for each precision, the saturated throughput (all requests queued
+    at once), then Poisson arrivals at `load` times that throughput with
+    p50/p99 latency."""
+    import numpy as np
+    reqs = W.serving_requests(n=n_requests, seed=seed)
+    rays = sum(w["n_rays"] for w in reqs)
+    out = {"requests": n_requests, "total_rays": rays, "hbm_budget_bytes": budget,
+           "max_slots": max_slots, "load": load,
+           "mix": "von Hamos R 60-120 mm, mosaic FWHM 0.05-0.8 deg (Gaussian / Lorentzian / "
+                  "pseudo-Voigt), 20-100 um, 0.1-0.4 keV windows at 7.5-8.5 keV, "
+                  "rays log-uniform 1e5-1e8"}
+    for prec in ("fp32_mixed", "fp64"):
+        for w in reqs:
+            w["precision"] = prec
+        lat0, span0, st0 = serving_run(mrt, reqs, prec, budget, max_slots)
+        sat = rays / span0
+        rate = load * sat / (rays / n_requests)           # requests per second
+        gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n_requests)
+        lat, span, st = serving_run(mrt, reqs, prec, budget, max_slots, gaps)
+        out[prec] = {
+            "saturated_rays_per_s": round(sat, 1),
+            "saturated_gpu_busy": round(st0["busy_ms"] * 1e-3 / span0, 3),
+            "arrival_rate_per_s": round(rate, 2),
+            "rays_per_s": round(rays / span, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "max_ms": round(float(np.max(lat)), 2),
+            "rounds": int(st["rounds"]),
+        }
+        log(f"serving {prec}: saturated {sat:.3e} rays/s, Poisson {rate:.1f}/s: "
+            f"p50 {out[prec]['p50_ms']} ms p99 {out[prec]['p99_ms']} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +221,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--refill", type=int, default=0, help="lanes idle before a wave refills (0 = default)")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-budget-mib", type=int, default=4096)
+    ap.add_argument("--serving-load", type=float, default=0.7)
+    ap.add_argument("--no-serving", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the transport shards by ray-id ranges with one "
@@ -196,7 +279,8 @@ def main():
             "speedup_vs_fp64": round(gpu_ms64 / gms, 3),
             "roofline": roofline(op_costs, profiling, w, "fp32_mixed", pm, info["compute_units"]),
         }
-    res["serving"] = None
+    res["serving"] = None if a.no_serving else serving(
+        mrt, W, a.serving_requests, a.serving_budget_mib << 20, 64, a.serving_load)
     orc = None
     if not a.no_cpu_baseline:
         res["cpu_baseline"], orc = cpu_baseline(w, a.cpu_rays)

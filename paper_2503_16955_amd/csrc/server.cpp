@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -45,6 +46,7 @@ struct mrt_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::map<uint64_t, Rec> recs;
+    std::deque<uint64_t> finished;              // completion queue for wait_any
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread engine;
@@ -150,7 +152,11 @@ void engine(mrt_server *S) {
     for (;;) {
         if (S->stop) break;
         for (uint64_t t : S->plan.admit(S->now_ms()))
-            if (!admit_one(S, t)) S->plan.fail(t, MRT_ENOMEM, S->now_ms());
+            if (!admit_one(S, t)) {
+                S->plan.fail(t, MRT_ENOMEM, S->now_ms());
+                S->finished.push_back(t);
+                S->cv_done.notify_all();
+            }
         std::vector<mrt::serve::Item> items = S->plan.plan_round();
         if (items.empty()) {
             S->cv_done.notify_all();
@@ -179,7 +185,10 @@ void engine(mrt_server *S) {
             // the device failed: every request of the round fails
             for (const auto &it : items) {
                 const mrt::serve::Request *q = S->plan.find(it.ticket);
-                if (q && q->state == mrt::serve::kRunning) S->plan.fail(it.ticket, MRT_EDEVICE, now);
+                if (q && q->state == mrt::serve::kRunning) {
+                    S->plan.fail(it.ticket, MRT_EDEVICE, now);
+                    S->finished.push_back(it.ticket);
+                }
             }
         } else {
             S->stats.rounds += 1;
@@ -188,6 +197,7 @@ void engine(mrt_server *S) {
             for (uint64_t t : S->plan.complete_round(items, now)) {
                 const mrt::serve::Request *q = S->plan.find(t);
                 if (q && q->state == mrt::serve::kDone) read_counters(S, S->recs.at(t), q->slot);
+                S->finished.push_back(t);
             }
         }
         S->cv_done.notify_all();
@@ -319,11 +329,39 @@ mrt_status mrt_server_wait(mrt_server *S, uint64_t ticket, double timeout_ms,
     return MRT_OK;
 }
 
+mrt_status mrt_server_wait_any(mrt_server *S, double timeout_ms, uint64_t *ticket,
+                               mrt_request_result *result) {
+    if (!S || !ticket || !result) return fail(MRT_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    const auto deadline = std::chrono::steady_clock::now() +
+                          std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                              std::chrono::duration<double, std::milli>(timeout_ms < 0 ? 0.0 : timeout_ms));
+    for (;;) {
+        // tickets released before they were reported are skipped
+        while (!S->finished.empty() && !S->plan.find(S->finished.front())) S->finished.pop_front();
+        if (!S->finished.empty()) break;
+        if (S->stop) return fail(MRT_EINVAL, "server stopped");
+        if (timeout_ms < 0) {
+            S->cv_done.wait(lk);
+        } else if (S->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+            while (!S->finished.empty() && !S->plan.find(S->finished.front())) S->finished.pop_front();
+            if (S->finished.empty()) return fail(MRT_EAGAIN, "no request finished within the timeout");
+            break;
+        }
+    }
+    const uint64_t t = S->finished.front();
+    S->finished.pop_front();
+    *ticket = t;
+    fill_result(S, t, result);
+    return MRT_OK;
+}
+
 mrt_status mrt_server_cancel(mrt_server *S, uint64_t ticket) {
     if (!S) return fail(MRT_EINVAL, "null server");
     std::lock_guard<std::mutex> lk(S->mu);
     if (!S->plan.cancel(ticket, S->now_ms()))
         return fail(MRT_EINVAL, "ticket %llu is unknown or finished", (unsigned long long)ticket);
+    if (S->plan.find(ticket)->state == mrt::serve::kCanceled) S->finished.push_back(ticket);
     S->cv_work.notify_all();
     S->cv_done.notify_all();
     return MRT_OK;

@@ -321,7 +321,7 @@ class MrtServerStats(C.Structure):
 
 
 SERVER_EXPORTS = ("mrt_server_create", "mrt_server_submit", "mrt_server_poll", "mrt_server_wait",
-                  "mrt_server_cancel", "mrt_server_release", "mrt_server_get_stats",
+                  "mrt_server_wait_any", "mrt_server_cancel", "mrt_server_release", "mrt_server_get_stats",
                   "mrt_server_destroy")
 EXPORTS = EXPORTS + SERVER_EXPORTS
 
@@ -338,6 +338,8 @@ def _load_server(L):
     L.mrt_server_poll.argtypes = [C.c_void_p, C.c_uint64, P(MrtRequestResult)]
     L.mrt_server_wait.restype = C.c_int
     L.mrt_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_double, P(MrtRequestResult)]
+    L.mrt_server_wait_any.restype = C.c_int
+    L.mrt_server_wait_any.argtypes = [C.c_void_p, C.c_double, P(C.c_uint64), P(MrtRequestResult)]
     L.mrt_server_cancel.restype = C.c_int
     L.mrt_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
     L.mrt_server_release.restype = C.c_int
@@ -390,13 +392,13 @@ class Server:
         _check(self._L.mrt_server_submit(self._h, C.byref(q), C.byref(t)))
         return int(t.value)
 
-    def _result(self, r):
+    def _result(self, r, views=True):
         import torch
         out = {"state": REQ_STATE_NAMES[r.state], "status": r.status, "rays_done": int(r.rays_done),
                "submit_ms": r.submit_ms, "admit_ms": r.admit_ms, "done_ms": r.done_ms,
                "counters": {f: int(getattr(r.counters, f)) for f in COUNTER_FIELDS},
                "counts": None, "energy": None}
-        if r.d_counts:
+        if r.d_counts and views:
             out["counts"] = torch.as_tensor(_DeviceArray(r.d_counts, (r.ny, r.nx), "<i4"),
                                             device="cuda")
             out["energy"] = torch.as_tensor(_DeviceArray(r.d_energy_mev, (r.ny, r.nx), "<i8"),
@@ -412,6 +414,16 @@ class Server:
         r = MrtRequestResult()
         _check(self._L.mrt_server_wait(self._h, int(ticket), float(timeout_ms), C.byref(r)))
         return self._result(r)
+
+    def wait_any(self, timeout_ms=-1.0, views=True):
+        """(ticket, result) of the next finished request, in completion order;
+        each finished request is returned once.  views=False leaves out the
+        torch image views (a cheaper call for a consumer that only needs the
+        state and timing)."""
+        r = MrtRequestResult()
+        t = C.c_uint64()
+        _check(self._L.mrt_server_wait_any(self._h, float(timeout_ms), C.byref(t), C.byref(r)))
+        return int(t.value), (self._result(r) if views else self._result(r, views=False))
 
     def cancel(self, ticket):
         _check(self._L.mrt_server_cancel(self._h, int(ticket)))

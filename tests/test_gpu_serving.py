@@ -105,21 +105,26 @@ def test_cancel_and_release():
 
 
 def test_poisson_arrivals_latency_recorded():
+    """Requests arrive while others run; a consumer takes each from the
+    completion queue as it finishes and releases it."""
     reqs = W.serving_requests(n=24, seed=4)
     rng = np.random.default_rng(5)
     with mrt.Server(hbm_budget_bytes=1 << 30, max_slots=16, precision="fp32_mixed") as srv:
-        tickets = []
+        tickets = set()
         for w in reqs:
             w = copy.deepcopy(w)
             w["n_rays"] = min(w["n_rays"], 2_000_000)
             time.sleep(rng.exponential(0.002))
-            tickets.append((srv.submit(w), w))
-        lat = []
-        for t, w in tickets:
-            r = srv.wait(t, timeout_ms=WAIT_MS)
-            assert r["state"] == "done"
+            tickets.add(srv.submit(w))
+        lat, order = [], []
+        for _ in reqs:
+            t, r = srv.wait_any(timeout_ms=WAIT_MS, views=False)
+            assert r["state"] == "done" and t in tickets
             lat.append(r["done_ms"] - r["submit_ms"])
+            order.append(r["done_ms"])
             srv.release(t)
+        assert order == sorted(order)
         assert all(x > 0 for x in lat)
+        assert srv.stats()["used_bytes"] == 0
         print(f"[serve] p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms",
               flush=True)

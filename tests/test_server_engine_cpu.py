@@ -244,3 +244,73 @@ def test_destroy_with_work_in_flight_returns(lib):
     s.destroy()              # waits for the round in flight, frees everything
     opener.join()
     assert lib.harness_free_bytes() == DEVICE_BYTES
+
+
+def _wait_any(s, timeout_ms):
+    r = mrt.MrtRequestResult()
+    t = C.c_uint64()
+    st = s.L.mrt_server_wait_any(s.h, timeout_ms, C.byref(t), C.byref(r))
+    return st, t.value, r
+
+
+def test_wait_any_reports_each_finished_request_once_in_completion_order(lib):
+    lib.harness_init(DEVICE_BYTES, 0)
+    w = W.get("flat_hopg")
+    s = Srv(lib, slots=8, round_rays=8192, chunk=1024)
+    try:
+        st, _, _ = _wait_any(s, 20.0)
+        assert st == mrt.EAGAIN                               # nothing finished yet
+        lib.harness_gate(0)
+        sizes = [200_000, 1000, 30_000, 1, 5000]
+        tickets = [s.submit(w, n, 40 + i)[1] for i, n in enumerate(sizes)]
+        lib.harness_gate(1)
+        seen = []
+        for _ in sizes:
+            st, t, r = _wait_any(s, 10_000.0)
+            assert st == 0 and r.state == mrt.REQ_DONE
+            seen.append((r.done_ms, t))
+        assert sorted(t for _, t in seen) == sorted(tickets)  # each exactly once
+        assert [d for d, _ in seen] == sorted(d for d, _ in seen)
+        assert seen[-1][1] == tickets[0]                      # the largest finishes last
+        st, _, _ = _wait_any(s, 20.0)
+        assert st == mrt.EAGAIN
+        # a request released before it is reported is skipped
+        _, ta = s.submit(w, 100, 90)
+        _, tb = s.submit(w, 100, 91)
+        assert s.wait(ta)[0] == 0 and s.wait(tb)[0] == 0
+        assert lib.mrt_server_release(s.h, ta) == 0
+        st, t, r = _wait_any(s, 10_000.0)
+        assert st == 0 and t == tb
+        for t in tickets + [tb]:
+            assert lib.mrt_server_release(s.h, t) == 0
+    finally:
+        lib.harness_gate(1)
+        s.destroy()
+    assert lib.harness_free_bytes() == DEVICE_BYTES
+
+
+def test_wait_any_reports_failures_and_cancellations(lib):
+    w = W.get("flat_hopg")
+    px = w["detector"]["nx"] * w["detector"]["ny"]
+    lib.harness_init(DEVICE_BYTES, 0)
+    s = Srv(lib)
+    fixed = DEVICE_BYTES - lib.harness_free_bytes()
+    s.destroy()
+    lib.harness_init(fixed + px * 12 + 64, 0)               # one request's images fit
+    lib.harness_gate(0)
+    s = Srv(lib, slots=1)
+    try:
+        _, t1 = s.submit(w, 1_000_000, 1)                   # runs (gate closed)
+        _, t2 = s.submit(w, 1000, 2)                        # queued: one slot
+        assert lib.mrt_server_cancel(s.h, t2) == 0
+        st, t, r = _wait_any(s, 10_000.0)
+        assert st == 0 and t == t2 and r.state == mrt.REQ_CANCELED
+        assert lib.mrt_server_cancel(s.h, t1) == 0
+        lib.harness_gate(1)
+        st, t, r = _wait_any(s, 10_000.0)
+        assert st == 0 and t == t1 and r.state == mrt.REQ_CANCELED
+        for t in (t1, t2):
+            assert lib.mrt_server_release(s.h, t) == 0
+    finally:
+        lib.harness_gate(1)
+        s.destroy()
