@@ -174,6 +174,26 @@ def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None):
     return lat, span, st
 
 
+def sequential_run(mrt, reqs, precision):
+    """The same requests traced one mrt_trace call after another on one
+    stream (each with the kernel specialised for its kinds), as the reference
+    point for the server.  Returns (seconds, events)."""
+    import torch
+    counts, energy = mrt.alloc_images(reqs[0])
+    stream = torch.cuda.current_stream()
+    mrt.trace(reqs[0], n_rays=1 << 16, precision=precision, counts=counts, energy=energy)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    events = 0
+    for w in reqs:
+        out = mrt.trace(w, precision=precision, counts=counts, energy=energy, stream=stream)
+        events += out["counters"]["events"]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) * 1e-3, events
+
+
 def serving(mrt, W, n_requests, budget, max_slots, load, seed=4):
     """The serving workload (design requests of varied geometry and ray
     count): for each precision, the saturated throughput (all requests queued
@@ -190,12 +210,15 @@ def serving(mrt, W, n_requests, budget, max_slots, load, seed=4):
     for prec in ("fp32_mixed", "fp64"):
         for w in reqs:
             w["precision"] = prec
+        seq_s, seq_events = sequential_run(mrt, reqs, prec)
         lat0, span0, st0 = serving_run(mrt, reqs, prec, budget, max_slots)
         sat = rays / span0
         rate = load * sat / (rays / n_requests)           # requests per second
         gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n_requests)
         lat, span, st = serving_run(mrt, reqs, prec, budget, max_slots, gaps)
         out[prec] = {
+            "one_call_per_request_rays_per_s": round(rays / seq_s, 1),
+            "events_per_ray": round(seq_events / rays, 3),
             "saturated_rays_per_s": round(sat, 1),
             "saturated_gpu_busy": round(st0["busy_ms"] * 1e-3 / span0, 3),
             "arrival_rate_per_s": round(rate, 2),

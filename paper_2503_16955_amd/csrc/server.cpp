@@ -4,6 +4,7 @@
 // engine thread and the C-ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
@@ -54,10 +55,9 @@ struct mrt_server {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     mrt::TraceParams *d_slots = nullptr;
     unsigned long long *d_counters = nullptr;   // max_slots x kNumCounters
-    mrt::ServeChunk *d_chunks = nullptr;
-    mrt::ServeChunk *h_chunks = nullptr;        // pinned staging
-    size_t chunk_cap = 0;
-    unsigned int *d_cursor = nullptr;
+    mrt::ServeItem *d_items = nullptr;          // max_slots items of a round
+    mrt::ServeItem *h_items = nullptr;          // pinned staging
+    unsigned long long *d_cursors = nullptr;    // one chunk cursor per item
     const void *kernel = nullptr;
     int grid = 0;
     std::chrono::steady_clock::time_point t0;
@@ -163,16 +163,31 @@ void engine(mrt_server *S) {
             S->cv_work.wait(lk);
             continue;
         }
-        const size_t n = items.size();
-        for (size_t i = 0; i < n; ++i)
-            S->h_chunks[i] = mrt::ServeChunk{items[i].first, items[i].count, items[i].slot};
+        // one item per request: the round's pieces of a request are contiguous
+        uint32_t n = 0;
+        uint64_t total = 0;
+        for (const auto &it : items) {
+            mrt::ServeItem *last = n ? &S->h_items[n - 1] : nullptr;
+            if (last && last->slot == it.slot && last->first + last->count == it.first) {
+                last->count += it.count;
+            } else {
+                S->h_items[n++] = mrt::ServeItem{it.first, it.count, total, it.slot, 0u};
+            }
+            total += it.count;
+        }
+        // chunks of about a quarter of a wave's share of the round, in whole
+        // waves of rays, as the one-call path sizes them
+        const uint64_t waves = (uint64_t)S->grid * 4u;
+        uint64_t chunk = (total / (waves * 4u) + 63u) / 64u * 64u;
+        chunk = std::max<uint64_t>(64u, std::min<uint64_t>(2048u, chunk));
+        for (uint32_t i = 0; i < n; ++i) S->h_items[i].chunk = (uint32_t)chunk;
         lk.unlock();
-        hipError_t e = hipMemcpyAsync(S->d_chunks, S->h_chunks, n * sizeof(mrt::ServeChunk),
+        hipError_t e = hipMemcpyAsync(S->d_items, S->h_items, n * sizeof(mrt::ServeItem),
                                       hipMemcpyHostToDevice, S->stream);
-        if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(S->d_cursor, 1, S->stream);
+        if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(S->d_cursors, 2u * n, S->stream);
         if (e == hipSuccess) e = hipEventRecord(S->ev0, S->stream);
-        uint32_t n_chunks = (uint32_t)n;
-        void *args[] = {&S->d_slots, &S->d_chunks, &n_chunks, &S->d_cursor};
+        uint32_t n_items = n;
+        void *args[] = {&S->d_slots, &S->d_items, &n_items, &total, &S->d_cursors};
         if (e == hipSuccess)
             e = hipLaunchKernel(S->kernel, dim3((unsigned)S->grid), dim3(256), args, 0, S->stream);
         if (e == hipSuccess) e = hipEventRecord(S->ev1, S->stream);
@@ -254,16 +269,14 @@ mrt_status mrt_server_create(const mrt_server_config *config, mrt_server **out) 
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->kernel, 256, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     S->grid = per_cu * prop.multiProcessorCount;
-    // chunks of one round: round_rays / chunk full chunks plus one partial per slot
-    S->chunk_cap = (size_t)(round_rays / chunk) + (size_t)c.max_slots * 2 + 16;
     bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreate(&S->ev0) == hipSuccess && hipEventCreate(&S->ev1) == hipSuccess &&
               hipMalloc((void **)&S->d_slots, sizeof(mrt::TraceParams) * (size_t)c.max_slots) == hipSuccess &&
               hipMalloc((void **)&S->d_counters,
                         sizeof(unsigned long long) * mrt::kNumCounters * (size_t)c.max_slots) == hipSuccess &&
-              hipMalloc((void **)&S->d_chunks, sizeof(mrt::ServeChunk) * S->chunk_cap) == hipSuccess &&
-              hipMalloc((void **)&S->d_cursor, 64) == hipSuccess &&
-              hipHostMalloc((void **)&S->h_chunks, sizeof(mrt::ServeChunk) * S->chunk_cap, 0) == hipSuccess;
+              hipMalloc((void **)&S->d_items, sizeof(mrt::ServeItem) * (size_t)c.max_slots) == hipSuccess &&
+              hipMalloc((void **)&S->d_cursors, sizeof(unsigned long long) * (size_t)c.max_slots) == hipSuccess &&
+              hipHostMalloc((void **)&S->h_items, sizeof(mrt::ServeItem) * (size_t)c.max_slots, 0) == hipSuccess;
     if (!ok) {
         mrt_server_destroy(S);
         return fail(MRT_ENOMEM, "server set-up allocation failed");
@@ -416,9 +429,9 @@ void mrt_server_destroy(mrt_server *S) {
     }
     if (S->d_slots) (void)hipFree(S->d_slots);
     if (S->d_counters) (void)hipFree(S->d_counters);
-    if (S->d_chunks) (void)hipFree(S->d_chunks);
-    if (S->d_cursor) (void)hipFree(S->d_cursor);
-    if (S->h_chunks) (void)hipHostFree(S->h_chunks);
+    if (S->d_items) (void)hipFree(S->d_items);
+    if (S->d_cursors) (void)hipFree(S->d_cursors);
+    if (S->h_items) (void)hipHostFree(S->h_items);
     if (S->ev0) (void)hipEventDestroy(S->ev0);
     if (S->ev1) (void)hipEventDestroy(S->ev1);
     if (S->stream) (void)hipStreamDestroy(S->stream);

@@ -709,6 +709,42 @@ struct RangeClaim {
 };
 
 // ---------------------------------------------------------------------------
+// Serving: the waves of one launch trace a round's items (one per request,
+// each with its own chunk cursor).  Wave `wave` of `n_waves` starts at the
+// item that holds ray position wave * total / n_waves of the round, so each
+// item starts with a share of the waves proportional to its rays; the wave
+// claims chunks of that item exactly as the one-call kernel claims chunks of
+// its range (no drain between chunks), and when the item is exhausted it
+// moves on to the following items in turn, helping wherever rays are left,
+// until it has visited every item.  The wave index must be wave-uniform.
+// The loop head holds no lane-conditional code before trace_loop's first
+// wave operation, so the compiler cannot split the wave across the
+// back-edge (the counter flush that ends trace_loop is lane-0-only).
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slots,
+                                            const ServeItem *__restrict__ items, uint32_t n_items,
+                                            uint64_t total, unsigned long long *__restrict__ cursors,
+                                            uint32_t wave, uint32_t n_waves) {
+    if (n_items == 0 || n_waves == 0) return;
+    // first item: the last one whose start is at or before the position
+    const uint64_t pos = (uint64_t)wave * total / n_waves;
+    uint32_t lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (items[mid].start <= pos) lo = mid;
+        else hi = mid - 1;
+    }
+    for (uint32_t k = 0; k < n_items; ++k) {
+        const uint32_t i = lo + k < n_items ? lo + k : lo + k - n_items;
+        const ServeItem it = items[i];
+        const TraceParams &P = slots[it.slot];
+        RangeClaim claim{&cursors[i], it.first, it.count, it.chunk};
+        trace_loop<T>(P, P.lut, P.bin_cdf, claim);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Persistent trace kernel of one call (sec. 2; rays [P.first, P.first + P.n)).
 // ---------------------------------------------------------------------------
 template <class R, int GEOM, int MDF, int IRC, bool REC>

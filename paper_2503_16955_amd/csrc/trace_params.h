@@ -83,20 +83,26 @@ enum {
     kCEvents, kCReflections, kCRecords, kCRefined, kNumCounters
 };
 
-// One piece of a serving round: rays [first, first + count) of the request
-// whose parameter block is slots[slot].
-struct ServeChunk {
+// One request's share of a serving round: rays [first, first + count) of the
+// request whose parameter block is slots[slot], handed to waves `chunk` rays
+// at a time.  `start` is the sum of the counts of the items before it (waves
+// pick their first item by it, so each item starts with a share of the waves
+// proportional to its rays).
+struct ServeItem {
     uint64_t first;
-    uint32_t count;
+    uint64_t count;
+    uint64_t start;
     int32_t slot;
+    uint32_t chunk;
 };
 
 // Kernel of a precision / geometry / mosaic / rocking-curve / records
 // combination (nullptr for an unknown kind).
 const void *trace_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records);
 int launch_zero(void *ptr_u32, size_t n_words, void *stream);
-// Serving kernel of a precision: (const TraceParams *slots, const ServeChunk
-// *chunks, uint32_t n_chunks, unsigned int *cursor).
+// Serving kernel of a precision: (const TraceParams *slots, const ServeItem
+// *items, uint32_t n_items, uint64_t total, unsigned long long *cursors), one
+// zeroed cursor per item.
 const void *serve_kernel_ptr(int precision);
 
 }  // namespace mrt

@@ -1,6 +1,6 @@
 // The request server's host engine (paper_2503_16955_amd/csrc/server.cpp) on
 // the CPU, against the fake HIP layer in fakehip/: the serving "kernel" walks
-// the round's chunk list like the device kernel does and, for every ray id,
+// the round's items (one ray range per request) and, for every ray id,
 // adds a deterministic hash of (seed, ray id) to the request's images and
 // counters, so a test can recompute each request's expected result.
 #include <hip/hip_runtime.h>
@@ -36,13 +36,17 @@ void serve(void **args) {
     g_launches.fetch_add(1);
     while (!g_gate.load()) std::this_thread::sleep_for(std::chrono::milliseconds(1));
     const mrt::TraceParams *slots = *(const mrt::TraceParams **)args[0];
-    const mrt::ServeChunk *chunks = *(const mrt::ServeChunk **)args[1];
+    const mrt::ServeItem *items = *(const mrt::ServeItem **)args[1];
     const uint32_t n = *(const uint32_t *)args[2];
+    const uint64_t total = *(const uint64_t *)args[3];
+    uint64_t start = 0;
     for (uint32_t c = 0; c < n; ++c) {
-        const mrt::ServeChunk &ch = chunks[c];
-        const mrt::TraceParams &P = slots[ch.slot];
+        const mrt::ServeItem &it = items[c];
+        if (it.start != start || it.chunk < 64 || it.chunk % 64) abort();   // malformed round
+        start += it.count;
+        const mrt::TraceParams &P = slots[it.slot];
         const uint64_t px = (uint64_t)P.nx * (uint64_t)P.ny;
-        for (uint64_t id = ch.first; id < ch.first + ch.count; ++id) {
+        for (uint64_t id = it.first; id < it.first + it.count; ++id) {
             const uint64_t h = mix64(P.seed * 0x9E3779B97F4A7C15ull + id);
             P.counts[h % px] += 1u;
             P.energy[h % px] += id;
@@ -51,6 +55,7 @@ void serve(void **args) {
             P.dev_counters[mrt::kCDetected] += 1;
         }
     }
+    if (start != total) abort();
 }
 }  // namespace
 

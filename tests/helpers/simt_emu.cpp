@@ -127,29 +127,10 @@ using namespace mrt;
 using namespace mrt::tk;
 
 template <class R>
-void serve_body(const TraceParams *slots, const ServeChunk *chunks, uint32_t n, unsigned int *cursor) {
-    // the serving kernel's body, as in serve.hip
-    using T = Tracer<R, kAny, kAny, kAny, false>;
-    for (;;) {
-        unsigned int c = 0;
-        if (__lane_id() == 0) c = atomicAdd(cursor, 1u);
-        c = uniform(c);
-        if (c >= n) return;
-        const ServeChunk ch = chunks[c];
-        const TraceParams &P = slots[ch.slot];
-        struct OneChunk {
-            uint64_t first, end;
-            bool used;
-            bool operator()(uint64_t &next, uint64_t &e) {
-                if (used) return false;
-                used = true;
-                next = first;
-                e = end;
-                return true;
-            }
-        } claim{ch.first, ch.first + ch.count, false};
-        trace_loop<T>(P, P.lut, P.bin_cdf, claim);
-    }
+void serve_body(const TraceParams *slots, const ServeItem *items, uint32_t n, uint64_t total,
+                unsigned long long *cursors, uint32_t wave, uint32_t n_waves) {
+    // the serving kernel's body, with the wave index it would compute
+    serve_waves<Tracer<R, kAny, kAny, kAny, false>>(slots, items, n, total, cursors, wave, n_waves);
 }
 
 template <class R, bool REC>
@@ -201,14 +182,19 @@ void emu_set_run(TraceParams *P, uint64_t first, uint64_t n, uint64_t seed, uint
     P->refill_idle = refill_idle;
 }
 
-// Run the serving kernel body with n_waves waves; 0 on success.
-int emu_serve(const TraceParams *slots, const ServeChunk *chunks, uint32_t n, int n_waves,
+// Run the serving kernel body with n_waves waves (one after another) over a
+// round's items; 0 on success.
+int emu_serve(const TraceParams *slots, const ServeItem *items, uint32_t n, int n_waves,
               int precision, long long max_meetings) {
-    unsigned int cursor = 0;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; ++i) total += items[i].count;
+    std::vector<unsigned long long> cursors(n ? n : 1, 0ull);
     for (int w = 0; w < n_waves; ++w) {
         int e = run_wave([&] {
-            if (precision == MRT_FP64) serve_body<double>(slots, chunks, n, &cursor);
-            else serve_body<float>(slots, chunks, n, &cursor);
+            if (precision == MRT_FP64)
+                serve_body<double>(slots, items, n, total, cursors.data(), (uint32_t)w, (uint32_t)n_waves);
+            else
+                serve_body<float>(slots, items, n, total, cursors.data(), (uint32_t)w, (uint32_t)n_waves);
         }, max_meetings);
         if (e) return e;
     }

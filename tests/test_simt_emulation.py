@@ -5,9 +5,9 @@ readfirstlane), so their wave-level control flow (lane refill, chunk claims,
 drain, counter flushes) runs as written, without a GPU.
 
 Checks: every emulated wave terminates with its lanes in lockstep at each
-wave operation; the serving kernel, fed a round list that interleaves chunks
-of the whole request mix, gives each request exactly the images and counters
-of the same request traced alone; the counters balance (every emitted ray
+wave operation; the serving loop, fed a round of items that interleaves ray
+ranges of the whole request mix, gives each request exactly the images and
+counters of the same request traced alone; the counters balance (every emitted ray
 ends in exactly one way).
 
 What the emulation cannot show is how the compiler maps this control flow to
@@ -112,16 +112,22 @@ def test_served_mix_equals_requests_alone(emu, precision):
     slots = (C.c_char * (ps * len(served)))()
     for i, j in enumerate(served):
         C.memmove(C.addressof(slots) + i * ps, j.P, ps)
-    # a round list interleaving 256-ray chunks of every request
-    items, pos = [], [0] * len(served)
-    while any(p < j.n for p, j in zip(pos, served)):
-        for i, j in enumerate(served):
-            if pos[i] < j.n:
-                c = min(256, j.n - pos[i])
-                items.append((pos[i], c, i))
-                pos[i] += c
-    ch = np.array(items, dtype=[("first", "<u8"), ("count", "<u4"), ("slot", "<i4")])
-    assert emu.emu_serve(slots, ch.ctypes.data, len(ch), 3 * WAVES, prec, MAX_MEETINGS) == 0
+    # a round of items: each request split into two ray ranges, the halves
+    # of all requests interleaved (the kernel takes any items; the server
+    # sends one per request)
+    items = []
+    for i, j in enumerate(served):
+        items.append((0, j.n // 2, i))
+    for i, j in enumerate(served):
+        items.append((j.n // 2, j.n - j.n // 2, i))
+    items = [x for x in items if x[1] > 0]
+    it = np.zeros(len(items), dtype=[("first", "<u8"), ("count", "<u8"), ("start", "<u8"),
+                                     ("slot", "<i4"), ("chunk", "<u4")])
+    start = 0
+    for k, (f, c, i) in enumerate(items):
+        it[k] = (f, c, start, i, 64 * (1 + k % 4))
+        start += c
+    assert emu.emu_serve(slots, it.ctypes.data, len(it), 3 * WAVES, prec, MAX_MEETINGS) == 0
 
     for a, b, (w, n, s) in zip(alone, served, jobs):
         assert np.array_equal(a.counts, b.counts), (w["name"], n)
