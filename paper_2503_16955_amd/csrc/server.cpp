@@ -38,6 +38,18 @@ struct Rec {
     mrt_counters counters{};
 };
 
+// Rounds in flight at once.  While one round's last waves finish, the next
+// round's waves already fill the freed compute units (the rounds run on two
+// streams), and the host prepares rounds while the device works.
+constexpr int kDepth = 2;
+static_assert(kDepth == 2, "the engine alternates between two round buffers");
+
+// A launched round: its pieces (for completion) and its buffer.
+struct Round {
+    std::vector<mrt::serve::Item> items;
+    int buf = 0;
+};
+
 }  // namespace
 
 struct mrt_server {
@@ -51,13 +63,18 @@ struct mrt_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread engine;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t setup = nullptr;                // admission uploads and frees
+    hipEvent_t ev_ref = nullptr;                // time origin of the busy figure
+    double busy_end = 0.0;                      // end of the last completed round (ms)
     mrt::TraceParams *d_slots = nullptr;
     unsigned long long *d_counters = nullptr;   // max_slots x kNumCounters
-    mrt::ServeItem *d_items = nullptr;          // max_slots items of a round
-    mrt::ServeItem *h_items = nullptr;          // pinned staging
-    unsigned long long *d_cursors = nullptr;    // one chunk cursor per item
+    // per round buffer (kDepth rounds in flight, each on its own stream)
+    hipStream_t streams[kDepth] = {};
+    hipEvent_t ev0[kDepth] = {}, ev1[kDepth] = {};
+    mrt::ServeItem *d_items[kDepth] = {};       // max_slots items of a round
+    mrt::ServeItem *h_items[kDepth] = {};       // pinned staging
+    unsigned long long *d_cursors[kDepth] = {}; // one chunk cursor per item
+    std::deque<Round> inflight;
     const void *kernel = nullptr;
     int grid = 0;
     std::chrono::steady_clock::time_point t0;
@@ -81,24 +98,26 @@ uint64_t request_bytes(const Rec &r) {
 }
 
 void free_rec(mrt_server *S, Rec &r) {
-    if (r.d_counts) (void)hipFreeAsync(r.d_counts, S->stream);
-    if (r.d_energy) (void)hipFreeAsync(r.d_energy, S->stream);
-    if (r.d_tables) (void)hipFreeAsync(r.d_tables, S->stream);
+    if (r.d_counts) (void)hipFreeAsync(r.d_counts, S->setup);
+    if (r.d_energy) (void)hipFreeAsync(r.d_energy, S->setup);
+    if (r.d_tables) (void)hipFreeAsync(r.d_tables, S->setup);
     r.d_counts = nullptr;
     r.d_energy = nullptr;
     r.d_tables = nullptr;
 }
 
-// Device set-up of an admitted request (engine thread, lock held).
+// Device set-up of an admitted request (engine thread, lock held), enqueued
+// on the set-up stream; the caller synchronises that stream before any round
+// that may use the request is launched.
 bool admit_one(mrt_server *S, uint64_t ticket) {
     Rec &r = S->recs.at(ticket);
     const int32_t slot = S->plan.find(ticket)->slot;
     const size_t px = (size_t)r.nx * (size_t)r.ny;
-    hipError_t e = hipMallocAsync((void **)&r.d_counts, px * sizeof(uint32_t), S->stream);
+    hipError_t e = hipMallocAsync((void **)&r.d_counts, px * sizeof(uint32_t), S->setup);
     if (e == hipSuccess)
-        e = hipMallocAsync((void **)&r.d_energy, px * sizeof(uint64_t), S->stream);
+        e = hipMallocAsync((void **)&r.d_energy, px * sizeof(uint64_t), S->setup);
     if (e == hipSuccess && !r.tables.empty())
-        e = hipMallocAsync((void **)&r.d_tables, r.tables.size() * sizeof(double), S->stream);
+        e = hipMallocAsync((void **)&r.d_tables, r.tables.size() * sizeof(double), S->setup);
     if (e != hipSuccess) {
         free_rec(S, r);
         return false;
@@ -114,11 +133,11 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : 16u;
     if (!r.tables.empty())
         (void)hipMemcpyAsync(r.d_tables, r.tables.data(), r.tables.size() * sizeof(double),
-                             hipMemcpyHostToDevice, S->stream);
-    mrt::launch_zero(r.d_counts, px, S->stream);
-    mrt::launch_zero(r.d_energy, 2 * px, S->stream);
-    mrt::launch_zero(P.dev_counters, 2 * mrt::kNumCounters, S->stream);
-    e = hipMemcpyAsync(&S->d_slots[slot], &P, sizeof(P), hipMemcpyHostToDevice, S->stream);
+                             hipMemcpyHostToDevice, S->setup);
+    mrt::launch_zero(r.d_counts, px, S->setup);
+    mrt::launch_zero(r.d_energy, 2 * px, S->setup);
+    mrt::launch_zero(P.dev_counters, 2 * mrt::kNumCounters, S->setup);
+    e = hipMemcpyAsync(&S->d_slots[slot], &P, sizeof(P), hipMemcpyHostToDevice, S->setup);
     if (e != hipSuccess) {
         free_rec(S, r);
         return false;
@@ -146,77 +165,148 @@ void read_counters(mrt_server *S, Rec &r, int32_t slot) {
     c.kernel_ms = 0.0;
 }
 
+// Admit queued requests while slots and memory allow; their set-up is
+// complete on the device when this returns.
+void admit_all(mrt_server *S) {
+    std::vector<uint64_t> ok;
+    for (uint64_t t : S->plan.admit(S->now_ms())) {
+        if (admit_one(S, t)) {
+            ok.push_back(t);
+        } else {
+            S->plan.fail(t, MRT_ENOMEM, S->now_ms());
+            S->finished.push_back(t);
+            S->cv_done.notify_all();
+        }
+    }
+    if (!ok.empty() && hipStreamSynchronize(S->setup) != hipSuccess) {
+        for (uint64_t t : ok) {
+            S->plan.fail(t, MRT_EDEVICE, S->now_ms());
+            S->finished.push_back(t);
+        }
+        S->cv_done.notify_all();
+    }
+}
+
+// Every running request of the given pieces fails (device error).
+void fail_items(mrt_server *S, const std::vector<mrt::serve::Item> &items) {
+    const double now = S->now_ms();
+    for (const auto &it : items) {
+        const mrt::serve::Request *q = S->plan.find(it.ticket);
+        if (q && q->state == mrt::serve::kRunning) {
+            S->plan.fail(it.ticket, MRT_EDEVICE, now);
+            S->finished.push_back(it.ticket);
+        }
+    }
+}
+
+// Stage a round in buffer b (lock held): one item per request (the round's
+// pieces of a request are contiguous), chunks of about a quarter of a wave's
+// share of the round in whole waves of rays, as the one-call path sizes them.
+void stage_round(mrt_server *S, const std::vector<mrt::serve::Item> &items, int b, uint32_t *n_out,
+                 uint64_t *total_out) {
+    mrt::ServeItem *h = S->h_items[b];
+    uint32_t n = 0;
+    uint64_t total = 0;
+    for (const auto &it : items) {
+        mrt::ServeItem *last = n ? &h[n - 1] : nullptr;
+        if (last && last->slot == it.slot && last->first + last->count == it.first) {
+            last->count += it.count;
+        } else {
+            h[n++] = mrt::ServeItem{it.first, it.count, total, it.slot, 0u};
+        }
+        total += it.count;
+    }
+    const uint64_t waves = (uint64_t)S->grid * 4u;
+    uint64_t chunk = (total / (waves * 4u) + 63u) / 64u * 64u;
+    chunk = std::max<uint64_t>(64u, std::min<uint64_t>(2048u, chunk));
+    for (uint32_t i = 0; i < n; ++i) h[i].chunk = (uint32_t)chunk;
+    *n_out = n;
+    *total_out = total;
+}
+
+// Enqueue a staged round on its stream (lock not held).
+hipError_t launch_round(mrt_server *S, int b, uint32_t n, uint64_t total) {
+    hipStream_t st = S->streams[b];
+    hipError_t e = hipMemcpyAsync(S->d_items[b], S->h_items[b], n * sizeof(mrt::ServeItem),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(S->d_cursors[b], 2u * n, st);
+    if (e == hipSuccess) e = hipEventRecord(S->ev0[b], st);
+    void *args[] = {&S->d_slots, &S->d_items[b], &n, &total, &S->d_cursors[b]};
+    if (e == hipSuccess) e = hipLaunchKernel(S->kernel, dim3((unsigned)S->grid), dim3(256), args, 0, st);
+    if (e == hipSuccess) e = hipEventRecord(S->ev1[b], st);
+    return e;
+}
+
+// Wait for the oldest round in flight and account for it (lock held on
+// entry and exit, released while waiting).  A device error fails the
+// requests of every round in flight, after waiting for all of them.
+void finish_oldest(mrt_server *S, std::unique_lock<std::mutex> &lk) {
+    Round rd = std::move(S->inflight.front());
+    S->inflight.pop_front();
+    lk.unlock();
+    hipError_t e = hipEventSynchronize(S->ev1[rd.buf]);
+    float t0 = 0.0f, t1 = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t0, S->ev_ref, S->ev0[rd.buf]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t1, S->ev_ref, S->ev1[rd.buf]);
+    lk.lock();
+    if (e != hipSuccess) {
+        fail_items(S, rd.items);
+        while (!S->inflight.empty()) {
+            Round o = std::move(S->inflight.front());
+            S->inflight.pop_front();
+            lk.unlock();
+            (void)hipEventSynchronize(S->ev1[o.buf]);
+            lk.lock();
+            fail_items(S, o.items);
+        }
+        S->cv_done.notify_all();
+        return;
+    }
+    // busy time: the union of the rounds' kernel intervals
+    S->stats.busy_ms += std::max(0.0, (double)t1 - std::max((double)t0, S->busy_end));
+    S->busy_end = std::max(S->busy_end, (double)t1);
+    S->stats.rounds += 1;
+    for (const auto &it : rd.items) S->stats.rays_traced += it.count;
+    for (uint64_t t : S->plan.complete_round(rd.items, S->now_ms())) {
+        const mrt::serve::Request *q = S->plan.find(t);
+        if (q && q->state == mrt::serve::kDone) read_counters(S, S->recs.at(t), q->slot);
+        S->finished.push_back(t);
+    }
+    S->cv_done.notify_all();
+}
+
 void engine(mrt_server *S) {
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         if (S->stop) break;
-        for (uint64_t t : S->plan.admit(S->now_ms()))
-            if (!admit_one(S, t)) {
-                S->plan.fail(t, MRT_ENOMEM, S->now_ms());
-                S->finished.push_back(t);
+        admit_all(S);
+        // keep kDepth rounds in flight
+        while ((int)S->inflight.size() < kDepth && !S->stop) {
+            std::vector<mrt::serve::Item> items = S->plan.plan_round();
+            if (items.empty()) break;
+            const int b = S->inflight.empty() ? 0 : 1 - S->inflight.back().buf;
+            uint32_t n = 0;
+            uint64_t total = 0;
+            stage_round(S, items, b, &n, &total);
+            lk.unlock();
+            const hipError_t e = launch_round(S, b, n, total);
+            lk.lock();
+            if (e != hipSuccess) {
+                fail_items(S, items);
                 S->cv_done.notify_all();
+                continue;
             }
-        std::vector<mrt::serve::Item> items = S->plan.plan_round();
-        if (items.empty()) {
+            S->inflight.push_back(Round{std::move(items), b});
+        }
+        if (S->inflight.empty()) {
             S->cv_done.notify_all();
-            S->cv_work.wait(lk);
+            if (!S->stop) S->cv_work.wait(lk);
             continue;
         }
-        // one item per request: the round's pieces of a request are contiguous
-        uint32_t n = 0;
-        uint64_t total = 0;
-        for (const auto &it : items) {
-            mrt::ServeItem *last = n ? &S->h_items[n - 1] : nullptr;
-            if (last && last->slot == it.slot && last->first + last->count == it.first) {
-                last->count += it.count;
-            } else {
-                S->h_items[n++] = mrt::ServeItem{it.first, it.count, total, it.slot, 0u};
-            }
-            total += it.count;
-        }
-        // chunks of about a quarter of a wave's share of the round, in whole
-        // waves of rays, as the one-call path sizes them
-        const uint64_t waves = (uint64_t)S->grid * 4u;
-        uint64_t chunk = (total / (waves * 4u) + 63u) / 64u * 64u;
-        chunk = std::max<uint64_t>(64u, std::min<uint64_t>(2048u, chunk));
-        for (uint32_t i = 0; i < n; ++i) S->h_items[i].chunk = (uint32_t)chunk;
-        lk.unlock();
-        hipError_t e = hipMemcpyAsync(S->d_items, S->h_items, n * sizeof(mrt::ServeItem),
-                                      hipMemcpyHostToDevice, S->stream);
-        if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(S->d_cursors, 2u * n, S->stream);
-        if (e == hipSuccess) e = hipEventRecord(S->ev0, S->stream);
-        uint32_t n_items = n;
-        void *args[] = {&S->d_slots, &S->d_items, &n_items, &total, &S->d_cursors};
-        if (e == hipSuccess)
-            e = hipLaunchKernel(S->kernel, dim3((unsigned)S->grid), dim3(256), args, 0, S->stream);
-        if (e == hipSuccess) e = hipEventRecord(S->ev1, S->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(S->ev1);
-        float ms = 0.0f;
-        if (e == hipSuccess) (void)hipEventElapsedTime(&ms, S->ev0, S->ev1);
-        lk.lock();
-        const double now = S->now_ms();
-        if (e != hipSuccess) {
-            // the device failed: every request of the round fails
-            for (const auto &it : items) {
-                const mrt::serve::Request *q = S->plan.find(it.ticket);
-                if (q && q->state == mrt::serve::kRunning) {
-                    S->plan.fail(it.ticket, MRT_EDEVICE, now);
-                    S->finished.push_back(it.ticket);
-                }
-            }
-        } else {
-            S->stats.rounds += 1;
-            S->stats.busy_ms += ms;
-            for (const auto &it : items) S->stats.rays_traced += it.count;
-            for (uint64_t t : S->plan.complete_round(items, now)) {
-                const mrt::serve::Request *q = S->plan.find(t);
-                if (q && q->state == mrt::serve::kDone) read_counters(S, S->recs.at(t), q->slot);
-                S->finished.push_back(t);
-            }
-        }
-        S->cv_done.notify_all();
+        finish_oldest(S, lk);
     }
+    while (!S->inflight.empty()) finish_oldest(S, lk);
     S->cv_done.notify_all();
 }
 
@@ -269,14 +359,21 @@ mrt_status mrt_server_create(const mrt_server_config *config, mrt_server **out) 
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->kernel, 256, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     S->grid = per_cu * prop.multiProcessorCount;
-    bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreate(&S->ev0) == hipSuccess && hipEventCreate(&S->ev1) == hipSuccess &&
-              hipMalloc((void **)&S->d_slots, sizeof(mrt::TraceParams) * (size_t)c.max_slots) == hipSuccess &&
-              hipMalloc((void **)&S->d_counters,
-                        sizeof(unsigned long long) * mrt::kNumCounters * (size_t)c.max_slots) == hipSuccess &&
-              hipMalloc((void **)&S->d_items, sizeof(mrt::ServeItem) * (size_t)c.max_slots) == hipSuccess &&
-              hipMalloc((void **)&S->d_cursors, sizeof(unsigned long long) * (size_t)c.max_slots) == hipSuccess &&
-              hipHostMalloc((void **)&S->h_items, sizeof(mrt::ServeItem) * (size_t)c.max_slots, 0) == hipSuccess;
+    const size_t ms = (size_t)c.max_slots;
+    bool ok = hipStreamCreateWithFlags(&S->setup, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreate(&S->ev_ref) == hipSuccess &&
+              hipMalloc((void **)&S->d_slots, sizeof(mrt::TraceParams) * ms) == hipSuccess &&
+              hipMalloc((void **)&S->d_counters, sizeof(unsigned long long) * mrt::kNumCounters * ms) ==
+                  hipSuccess;
+    for (int b = 0; ok && b < kDepth; ++b)
+        ok = hipStreamCreateWithFlags(&S->streams[b], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreate(&S->ev0[b]) == hipSuccess && hipEventCreate(&S->ev1[b]) == hipSuccess &&
+             hipMalloc((void **)&S->d_items[b], sizeof(mrt::ServeItem) * ms) == hipSuccess &&
+             hipMalloc((void **)&S->d_cursors[b], sizeof(unsigned long long) * ms) == hipSuccess &&
+             hipHostMalloc((void **)&S->h_items[b], sizeof(mrt::ServeItem) * ms, 0) == hipSuccess;
+    // the time origin of the busy figure
+    ok = ok && hipEventRecord(S->ev_ref, S->setup) == hipSuccess &&
+         hipStreamSynchronize(S->setup) == hipSuccess;
     if (!ok) {
         mrt_server_destroy(S);
         return fail(MRT_ENOMEM, "server set-up allocation failed");
@@ -422,19 +519,23 @@ void mrt_server_destroy(mrt_server *S) {
         S->cv_work.notify_all();
         S->cv_done.notify_all();
     }
-    if (S->engine.joinable()) S->engine.join();
-    if (S->stream) {
+    if (S->engine.joinable()) S->engine.join();   // the engine waits for its rounds in flight
+    if (S->setup) {
         for (auto &kv : S->recs) free_rec(S, kv.second);
-        (void)hipStreamSynchronize(S->stream);
+        (void)hipStreamSynchronize(S->setup);
     }
     if (S->d_slots) (void)hipFree(S->d_slots);
     if (S->d_counters) (void)hipFree(S->d_counters);
-    if (S->d_items) (void)hipFree(S->d_items);
-    if (S->d_cursors) (void)hipFree(S->d_cursors);
-    if (S->h_items) (void)hipHostFree(S->h_items);
-    if (S->ev0) (void)hipEventDestroy(S->ev0);
-    if (S->ev1) (void)hipEventDestroy(S->ev1);
-    if (S->stream) (void)hipStreamDestroy(S->stream);
+    for (int b = 0; b < kDepth; ++b) {
+        if (S->d_items[b]) (void)hipFree(S->d_items[b]);
+        if (S->d_cursors[b]) (void)hipFree(S->d_cursors[b]);
+        if (S->h_items[b]) (void)hipHostFree(S->h_items[b]);
+        if (S->ev0[b]) (void)hipEventDestroy(S->ev0[b]);
+        if (S->ev1[b]) (void)hipEventDestroy(S->ev1[b]);
+        if (S->streams[b]) (void)hipStreamDestroy(S->streams[b]);
+    }
+    if (S->ev_ref) (void)hipEventDestroy(S->ev_ref);
+    if (S->setup) (void)hipStreamDestroy(S->setup);
     delete S;
 }
 

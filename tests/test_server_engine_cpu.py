@@ -314,3 +314,32 @@ def test_wait_any_reports_failures_and_cancellations(lib):
     finally:
         lib.harness_gate(1)
         s.destroy()
+
+
+def test_two_rounds_in_flight_and_no_more(lib):
+    """The engine launches the next round before the current one has
+    finished (the two run at once), but never a third."""
+    lib.harness_init(DEVICE_BYTES, 0)
+    lib.harness_gate(0)
+    w = W.get("flat_hopg")
+    px = w["detector"]["nx"] * w["detector"]["ny"]
+    s = Srv(lib, round_rays=4096, chunk=1024)
+    try:
+        _, t = s.submit(w, 40_000, 21)          # ten rounds of work
+        deadline = time.time() + 5
+        while lib.harness_launches() < 2 and time.time() < deadline:
+            time.sleep(0.001)
+        assert lib.harness_launches() == 2      # both rounds executing, held by the gate
+        time.sleep(0.05)
+        assert lib.harness_launches() == 2      # no third round before one finishes
+        lib.harness_gate(1)
+        st, r = s.wait(t)
+        assert st == 0 and r.state == mrt.REQ_DONE
+        c, e = _images(r)
+        ec, ee, cnt = expected(40_000, 21, px)
+        assert np.array_equal(c, ec) and np.array_equal(e, ee)
+        assert s.stats().rounds == 10
+        assert lib.mrt_server_release(s.h, t) == 0
+    finally:
+        lib.harness_gate(1)
+        s.destroy()
