@@ -1,0 +1,33 @@
+#!/bin/bash
+# rocprofv3 runs behind profiles/: the kernel trace of the benchmark's trace
+# kernels, the kernel trace of a serving run, HBM byte counters of the trace
+# kernels and of a plain 256 MiB copy (the scale reference), and SQ
+# instruction counters.  Each pass is a run of its own (counters are not
+# multiplexed).  Usage: profile_kernels.sh OUT_DIR   (run from anywhere)
+set -u
+R=$(cd "$(dirname "$0")/.." && pwd)
+OUT=$(mkdir -p "$1" && cd "$1" && pwd)
+export TMPDIR=/tmp PYTHONPATH=$R
+cd /tmp
+B="python3 $R/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-serving"
+B1="python3 $R/bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-serving"
+S="python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-mixed --serving-requests 64"
+C="python3 -m paper_2503_16955_amd.profiling copy --mib 256"
+step() {   # name, time limit (s), command...
+    local name=$1 lim=$2; shift 2
+    echo "== $name $(date +%T)"
+    timeout -k 10 "$lim" "$@" > "$OUT/prof_$name.log" 2>&1
+    local rc=$?
+    echo "$name rc=$rc"
+    # rocprofv3 may end with SIGSEGV (139) after a complete run
+    if [ $rc -ne 0 ] && [ $rc -ne 139 ]; then exit $rc; fi
+}
+step trace 240 rocprofv3 --kernel-trace --stats --output-format csv -d "$OUT/prof_trace" -o trace -- $B
+step serve 240 rocprofv3 --kernel-trace --stats --output-format csv -d "$OUT/prof_serve" -o serve -- $S
+step fetch 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d "$OUT/prof_fetch" -o fetch -- $B1
+step write 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d "$OUT/prof_write" -o write -- $B1
+step cfetch 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d "$OUT/prof_cfetch" -o cfetch -- $C
+step cwrite 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d "$OUT/prof_cwrite" -o cwrite -- $C
+step sq1 120 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_SMEM SQ_INSTS_LDS SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES --output-format csv -d "$OUT/prof_sq1" -o sq1 -- $B1
+step sq2 120 rocprofv3 --pmc SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_CVT SQ_INSTS_VALU_TRANS_F32 --output-format csv -d "$OUT/prof_sq2" -o sq2 -- $B1
+echo "done $(date +%T)"
