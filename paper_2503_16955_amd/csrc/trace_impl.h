@@ -747,9 +747,8 @@ __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slot
 // ---------------------------------------------------------------------------
 // Persistent trace kernel of one call (sec. 2; rays [P.first, P.first + P.n)).
 // ---------------------------------------------------------------------------
-template <class R, int GEOM, int MDF, int IRC, bool REC>
-__global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
-    using T = Tracer<R, GEOM, MDF, IRC, REC>;
+template <class T>
+__device__ __forceinline__ void trace_body(const TraceParams &P) {
     extern __shared__ double lds[];
     // stage the rocking-curve table and the spectrum CDF in LDS
     const int nl = T::irc_is(P, MRT_IRC_TABLE) ? P.lut_n : 0;
@@ -759,6 +758,24 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
     __syncthreads();
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
     trace_loop<T>(P, lds, lds + nl, claim);
+}
+
+// The parameter block is the kernel's by-value argument.  FP64 kernels
+// without a rocking-curve table read it through the kernel-argument segment
+// pointer, so each field is a scalar load where it is used; read as a
+// by-value argument, the whole block is loaded into scalar registers at
+// entry, and the pressure spills them into vector-register lanes (FP64 von
+// Hamos kernel: 111 -> 87 VGPRs, 4 -> 5 waves per SIMD, 2-8% faster over the
+// mosaic kinds).  The other kernels keep the by-value form, measured faster
+// for them: with a table the in-loop scalar loads share the LDS reads' wait
+// counter (up to 20% slower), and the FP32-mixed kernels lost up to 40%.
+template <class R, int GEOM, int MDF, int IRC, bool REC>
+__global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
+    using T = Tracer<R, GEOM, MDF, IRC, REC>;
+    if constexpr (sizeof(R) == 8 && IRC != MRT_IRC_TABLE)
+        trace_body<T>(*(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr());
+    else
+        trace_body<T>(P);
 }
 
 }  // namespace tk

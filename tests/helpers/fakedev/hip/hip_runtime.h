@@ -48,6 +48,10 @@ inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v)
     return __atomic_fetch_add(p, v, __ATOMIC_RELAXED);
 }
 
+// The kernels read their by-value parameter block through this pointer; the
+// emulator runs the loops below the kernels and never calls it.
+inline const void *__builtin_amdgcn_kernarg_segment_ptr() { return nullptr; }
+
 inline long long __double_as_longlong(double x) { long long r; memcpy(&r, &x, 8); return r; }
 inline double __longlong_as_double(long long x) { double r; memcpy(&r, &x, 8); return r; }
 
