@@ -328,19 +328,83 @@ def test_von_hamos_full_size_sampled():
     assert b["counters"]["events"] == c["events"]
 
 
+def _conserved(c, n):
+    assert c["emitted"] == n
+    assert (c["missed"] + c["absorbed"] + c["exit_reflected"] + c["exit_transmitted"]
+            + c["truncated"]) == n
+    assert c["detected"] <= c["exit_reflected"] + c["exit_transmitted"]
+
+
+def test_stress_full_size():
+    """The stress workload at its full 2e9 rays (one call each, as mrt_trace
+    launches it): in both precisions photons are conserved, no ray hits the
+    event cap, the counts image sums to the detected count and the energy image
+    to detected energies inside the spectrum's window; the FP32-mixed image
+    equals the sum of its two halves traced separately (bit for bit at full
+    size); FP64 per-ray records match the oracle on ray ranges sampled across
+    the whole id range; and the FP32-mixed image agrees with the FP64 one
+    (chi-square per pixel)."""
+    import torch
+    w = W.get("flat_stress")
+    n = w["n_rays"]
+    e_lo, e_hi = w["source"]["e_min"], w["source"]["e_max"]
+    out = {}
+    for prec in ("fp32_mixed", "fp64"):
+        print(f"[stress] {prec} {n} rays", flush=True)
+        r = mrt.trace(w, n_rays=n, precision=prec)
+        c = r["counters"]
+        _conserved(c, n)
+        assert c["truncated"] == 0
+        counts = r["counts"].view(torch.int32).long()
+        assert int(counts.sum()) == c["detected"]
+        esum = int(r["energy"].view(torch.int64).sum())
+        assert c["detected"] * e_lo * 1e6 - c["detected"] <= esum <= c["detected"] * e_hi * 1e6 + c["detected"]
+        out[prec] = (counts, c)
+    # the FP32-mixed image is the sum of its halves (order-independent atomics)
+    print("[stress] fp32_mixed halves", flush=True)
+    h = n // 2
+    a = mrt.trace(w, n_rays=h, first=0, precision="fp32_mixed")
+    b = mrt.trace(w, n_rays=n - h, first=h, precision="fp32_mixed", counts=a["counts"],
+                  energy=a["energy"], accumulate=True)
+    assert torch.equal(b["counts"].view(torch.int32).long(), out["fp32_mixed"][0])
+    # FP64 records against the oracle on ranges spread over [0, 2e9)
+    print("[stress] sampled ranges", flush=True)
+    rng = np.random.default_rng(11)
+    starts = np.sort(rng.integers(0, n - 64, 48, dtype=np.int64))
+    grecs, ids = [], []
+    for s0 in starts:
+        g = mrt.trace(w, n_rays=64, first=int(s0), precision="fp64", records="all")
+        grecs.append(mrt.records_to_numpy(g["records"]))
+        ids.append(np.arange(s0, s0 + 64, dtype=np.int64))
+    grec = np.concatenate(grecs)
+    orec, mg = oracle.trace_ids(w, np.concatenate(ids))
+    n_ties, bad, _ = parity.compare(grec, orec, mg)
+    assert len(bad) == 0, parity.describe(grec, orec, mg, bad)
+    assert n_ties == 0
+    # FP32-mixed vs FP64 at full size
+    c32 = out["fp32_mixed"][0].cpu().numpy()
+    c64 = out["fp64"][0].cpu().numpy()
+    chi2 = parity.chi2_per_pixel(c32, c64)
+    print(f"[stress] chi2/px fp32_mixed vs fp64: {chi2:.4f}", flush=True)
+    assert chi2 <= 1.05
+
+
 # ---- the FP32-mixed path against FP64 ------------------------------------------
 
 def test_fp32_mixed_matches_fp64_statistically():
-    """Same seed and ray ids: centroid shift, FWHM change and chi-square per
-    pixel of the FP32-mixed von Hamos image against the FP64 one, per line."""
+    """Same seed and ray ids, at the precision configuration's full 1e9 rays:
+    centroid shift, FWHM change and chi-square per pixel of the FP32-mixed
+    von Hamos image against the FP64 one, per line."""
     w = W.get("von_hamos_hapg")
-    n = 20_000_000
+    n = 1_000_000_000
     d = mrt.trace(w, n_rays=n, precision="fp64")
     m = mrt.trace(w, n_rays=n, precision="fp32_mixed")
     dc, _ = mrt.image_to_numpy(d["counts"])
     mc, _ = mrt.image_to_numpy(m["counts"])
-    for f in ("missed",):
-        assert d["counters"][f] == m["counters"][f]
+    # the FP32-mixed entry test is FP32: rays within float rounding (~3e-6 mm)
+    # of the crystal edges may enter in one precision and miss in the other,
+    # about 2.6e-7 of the rays for this 100 x 30 mm crystal
+    assert abs(d["counters"]["missed"] - m["counters"]["missed"]) <= 2e-6 * n
     pd, pm = parity.projected_profile(dc), parity.projected_profile(mc)
     nx = w["detector"]["nx"]
     for e_line in (8.028, 8.048):
