@@ -105,7 +105,7 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
         const size_t lut = r->kind == MRT_IRC_TABLE ? (size_t)r->n_table : 0;
         const size_t cdf = s->spectrum == MRT_SPECTRUM_TABLE ? (size_t)s->n_bins + 1 : 0;
         if ((lut + cdf) * sizeof(double) > (size_t)kMaxTableBytes)
-            return fail(MRT_EINVAL, "rocking-curve table plus spectrum bins exceed %d bytes of LDS",
+            return fail(MRT_EINVAL, "rocking-curve table plus spectrum bins exceed %d bytes",
                         kMaxTableBytes);
     }
     // detector
@@ -288,6 +288,15 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
     P.pitch = d->pitch;
     P.half_nx = (double)d->nx / 2.0;
     P.half_ny = (double)d->ny / 2.0;
+
+    // FP32 copies for the FP32-mixed kernels (round to nearest)
+#define MRT_F32_S(n) P.f32.n = (float)P.n;
+#define MRT_F32_V(n) \
+    for (int i = 0; i < 3; ++i) P.f32.n[i] = (float)P.n[i];
+    MRT_F32_SCALARS(MRT_F32_S)
+    MRT_F32_VECTORS(MRT_F32_V)
+#undef MRT_F32_S
+#undef MRT_F32_V
 }
 
 }  // namespace mrt

@@ -180,7 +180,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
                                                rocking_curve->kind, rec);
     if (!kernel) return release(fail(MRT_EINVAL, "no kernel for this combination of kinds"));
     const int block = opt.block_threads ? opt.block_threads : 256;
-    const size_t lds = tables.size() * sizeof(double);
+    const size_t lds = 0;   // the kernels read their tables from device memory
     int grid = opt.grid_blocks;
     if (grid == 0) {
         int per_cu = 0;

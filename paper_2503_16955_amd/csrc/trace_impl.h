@@ -52,6 +52,15 @@ template <class R> __device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b) {
     return V3<R>{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 template <class R> __device__ __forceinline__ R fminr(R a, R b) { return a < b ? a : b; }
+// A parameter in the path's precision: the FP64 value, or its FP32 copy.
+template <class R> __device__ __forceinline__ R par(double d, float f) {
+    if constexpr (sizeof(R) == 8) return d;
+    else return f;
+}
+template <class R> __device__ __forceinline__ V3<R> par3(const double *d, const float *f) {
+    if constexpr (sizeof(R) == 8) return V3<R>{d[0], d[1], d[2]};
+    else return V3<R>{f[0], f[1], f[2]};
+}
 template <class R> __device__ __forceinline__ R uni(uint32_t w);
 template <> __device__ __forceinline__ double uni<double>(uint32_t w) { return dm::u01_f64(w); }
 template <> __device__ __forceinline__ float uni<float>(uint32_t w) { return dm::u01_f32(w); }
@@ -122,22 +131,22 @@ struct Tracer {
     // Front-face entry; false on a miss.
     static __device__ __forceinline__ bool entry(const TraceParams &P, V3<R> o, V3<R> k, R &t) {
         if (is_flat(P)) {
-            const V3<R> N = ld3<R>(P.N);
+            const V3<R> N = par3<R>(P.N, P.f32.N);
             const R zeta = dot(o, N), kn = dot(k, N);
             if (!(kn < R(0))) return false;
             t = -zeta / kn;
             if (!(t > R(0))) return false;
             const V3<R> h = axpy(o, t, k);
-            const R xi = dot(h, ld3<R>(P.e1)), eta = dot(h, ld3<R>(P.e2));
-            return __builtin_fabs(xi) <= cvt<R>(P.hl) && __builtin_fabs(eta) <= cvt<R>(P.hw);
+            const R xi = dot(h, par3<R>(P.e1, P.f32.e1)), eta = dot(h, par3<R>(P.e2, P.f32.e2));
+            return __builtin_fabs(xi) <= par<R>(P.hl, P.f32.hl) && __builtin_fabs(eta) <= par<R>(P.hw, P.f32.hw);
         } else {
-            const V3<R> ax = ld3<R>(P.ax);
+            const V3<R> ax = par3<R>(P.ax, P.f32.ax);
             const R ka = dot(k, ax);
             const V3<R> kp = axpy(k, -ka, ax);
             const R zo = dot(o, ax);
             const V3<R> rho = axpy(o, -zo, ax);
             const R a = dot(kp, kp), b = dot(rho, kp);
-            const R cc = dot(rho, rho) - cvt<R>(P.R2);
+            const R cc = dot(rho, rho) - par<R>(P.R2, P.f32.R2);
             if (!(cc < R(0)) || !(a > R(0))) return false;
             const R disc = b * b - a * cc;
             const R sq = dm::sqrt(disc);
@@ -145,8 +154,8 @@ struct Tracer {
             const V3<R> h = axpy(o, t, k);
             const R zh = dot(h, ax);
             const V3<R> rh = axpy(h, -zh, ax);
-            return __builtin_fabs(zh) <= cvt<R>(P.hl) && dot(rh, ld3<R>(P.op)) <= R(0) &&
-                   dot(rh, ld3<R>(P.om)) <= R(0);
+            return __builtin_fabs(zh) <= par<R>(P.hl, P.f32.hl) && dot(rh, par3<R>(P.op, P.f32.op)) <= R(0) &&
+                   dot(rh, par3<R>(P.om, P.f32.om)) <= R(0);
         }
     }
 
@@ -155,10 +164,10 @@ struct Tracer {
     static __device__ __forceinline__ R exit_distance(const TraceParams &P, V3<R> p, V3<R> k) {
         R t = R(INFINITY);
         if (is_flat(P)) {
-            const V3<R> N = ld3<R>(P.N), e1 = ld3<R>(P.e1), e2 = ld3<R>(P.e2);
+            const V3<R> N = par3<R>(P.N, P.f32.N), e1 = par3<R>(P.e1, P.f32.e1), e2 = par3<R>(P.e2, P.f32.e2);
             const R zeta = dot(p, N), xi = dot(p, e1), eta = dot(p, e2);
             const R kn = dot(k, N), k1 = dot(k, e1), k2 = dot(k, e2);
-            const R hl = cvt<R>(P.hl), hw = cvt<R>(P.hw), T = cvt<R>(P.T);
+            const R hl = par<R>(P.hl, P.f32.hl), hw = par<R>(P.hw, P.f32.hw), T = par<R>(P.T, P.f32.T);
             if (kn > R(0)) t = fminr(t, -zeta / kn);
             if (kn < R(0)) t = fminr(t, (-T - zeta) / kn);
             if (k1 > R(0)) t = fminr(t, (hl - xi) / k1);
@@ -166,27 +175,27 @@ struct Tracer {
             if (k2 > R(0)) t = fminr(t, (hw - eta) / k2);
             if (k2 < R(0)) t = fminr(t, (-hw - eta) / k2);
         } else {
-            const V3<R> ax = ld3<R>(P.ax);
+            const V3<R> ax = par3<R>(P.ax, P.f32.ax);
             const R z = dot(p, ax), ka = dot(k, ax);
             const V3<R> rho = axpy(p, -z, ax), kp = axpy(k, -ka, ax);
             const R a = dot(kp, kp), b = dot(rho, kp), r2 = dot(rho, rho);
             if (a > R(0)) {
-                const R co = r2 - cvt<R>(P.Ro2);
+                const R co = r2 - par<R>(P.Ro2, P.f32.Ro2);
                 R disc = b * b - a * co;
                 if (disc < R(0)) disc = R(0);
                 const R sq = dm::sqrt(disc);
                 const R to = b >= R(0) ? -co / (b + sq) : (-b + sq) / a;
                 t = fminr(t, to);
                 if (b < R(0)) {
-                    const R ci = r2 - cvt<R>(P.R2);
+                    const R ci = r2 - par<R>(P.R2, P.f32.R2);
                     const R di = b * b - a * ci;
                     if (di >= R(0)) t = fminr(t, ci / (-b + dm::sqrt(di)));
                 }
             }
-            const R hl = cvt<R>(P.hl);
+            const R hl = par<R>(P.hl, P.f32.hl);
             if (ka > R(0)) t = fminr(t, (hl - z) / ka);
             if (ka < R(0)) t = fminr(t, (-hl - z) / ka);
-            const V3<R> op = ld3<R>(P.op), om = ld3<R>(P.om);
+            const V3<R> op = par3<R>(P.op, P.f32.op), om = par3<R>(P.om, P.f32.om);
             const R kop = dot(k, op), kom = dot(k, om);
             if (kop > R(0)) t = fminr(t, -dot(rho, op) / kop);
             if (kom > R(0)) t = fminr(t, -dot(rho, om) / kom);
@@ -199,14 +208,14 @@ struct Tracer {
     // uniform u2, by the inverse of the distribution's radial CDF.
     static __device__ __forceinline__ void vmf(const TraceParams &P, R u, R &ct, R &st) {
         // Eq. MF: v = 1 - cos(theta) = -s^2 log(u + (1 - u) e^{-2/s^2})
-        R v = -cvt<R>(P.vmf_s2) * dm::log_pos(u + (R(1) - u) * cvt<R>(P.vmf_floor));
+        R v = -par<R>(P.vmf_s2, P.f32.vmf_s2) * dm::log_pos(u + (R(1) - u) * par<R>(P.vmf_floor, P.f32.vmf_floor));
         v = v < R(2) ? v : R(2);
         ct = R(1) - v;
         st = dm::sqrt(v * (R(2) - v));
     }
     static __device__ __forceinline__ void lorentz(const TraceParams &P, R q, R &ct, R &st) {
         // bivariate Cauchy in the tangent plane: tan(theta) = g sqrt(1 - q^2) / q
-        const R g = cvt<R>(P.lor_g);
+        const R g = par<R>(P.lor_g, P.f32.lor_g);
         const R om = (R(1) - q) * (R(1) + q);
         const R rs = dm::rsqrt(g * g * om + q * q);
         ct = q * rs;
@@ -222,19 +231,19 @@ struct Tracer {
         } else if (mdf_is(P, MRT_MOSAIC_PSEUDO_VOIGT)) {
             // Lorentzian with probability eta, else von Mises-Fisher; the two
             // branches share the square root of sin(theta)
-            const R eta = cvt<R>(P.m_eta);
+            const R eta = par<R>(P.m_eta, P.f32.m_eta);
             R arg, scale;
             if (u2 < eta) {
-                const R q = (eta - u2) * cvt<R>(P.inv_eta);
-                const R g = cvt<R>(P.lor_g);
+                const R q = (eta - u2) * par<R>(P.inv_eta, P.f32.inv_eta);
+                const R g = par<R>(P.lor_g, P.f32.lor_g);
                 const R om = (R(1) - q) * (R(1) + q);
                 const R rs = dm::rsqrt(g * g * om + q * q);
                 ct = q * rs;
                 arg = om;
                 scale = g * rs;
             } else {
-                const R u = (u2 - eta) * cvt<R>(P.inv_1meta);
-                R v = -cvt<R>(P.vmf_s2) * dm::log_pos(u + (R(1) - u) * cvt<R>(P.vmf_floor));
+                const R u = (u2 - eta) * par<R>(P.inv_1meta, P.f32.inv_1meta);
+                R v = -par<R>(P.vmf_s2, P.f32.vmf_s2) * dm::log_pos(u + (R(1) - u) * par<R>(P.vmf_floor, P.f32.vmf_floor));
                 v = v < R(2) ? v : R(2);
                 ct = R(1) - v;
                 arg = v * (R(2) - v);
@@ -245,13 +254,13 @@ struct Tracer {
             // Eq. WL: density in v proportional to 1 / (g^2 + 2 v)
             R v;
             if constexpr (kF64) v = P.wl_half_g2 * ::expm1(u2 * P.wl_z);
-            else v = (float)P.wl_half_g2 * ::expm1f(u2 * (float)P.wl_z);
+            else v = P.f32.wl_half_g2 * ::expm1f(u2 * P.f32.wl_z);
             v = v < R(2) ? v : R(2);
             ct = R(1) - v;
             st = dm::sqrt(v * (R(2) - v));
         } else {
             // Eq. SWL: density in v proportional to 1 / (cosh(G/2) - 1 + v)^2
-            R v = dm::div(cvt<R>(P.swl_k) * u2, cvt<R>(P.swl_d) - R(2) * u2);
+            R v = dm::div(par<R>(P.swl_k, P.f32.swl_k) * u2, par<R>(P.swl_d, P.f32.swl_d) - R(2) * u2);
             v = v < R(2) ? v : R(2);
             ct = R(1) - v;
             st = dm::sqrt(v * (R(2) - v));
@@ -272,11 +281,11 @@ struct Tracer {
     static __device__ __forceinline__ void frame(const TraceParams &P, V3<R> p, V3<R> &N, V3<R> &e1,
                                                  V3<R> &e2) {
         if (is_flat(P)) {
-            N = ld3<R>(P.N);
-            e1 = ld3<R>(P.e1);
-            e2 = ld3<R>(P.e2);
+            N = par3<R>(P.N, P.f32.N);
+            e1 = par3<R>(P.e1, P.f32.e1);
+            e2 = par3<R>(P.e2, P.f32.e2);
         } else {
-            const V3<R> ax = ld3<R>(P.ax);
+            const V3<R> ax = par3<R>(P.ax, P.f32.ax);
             const V3<R> rho = axpy(p, -dot(p, ax), ax);
             const R inv = dm::rsqrt(dot(rho, rho));
             N = V3<R>{-rho.x * inv, -rho.y * inv, -rho.z * inv};
@@ -296,13 +305,13 @@ struct Tracer {
             if constexpr (kF64) {
                 return P.pv_a * dm::div(P.pv_h2, P.pv_h2 + x2) + P.pv_b * ::exp(-P.g_k * x2);
             } else {
-                const float h2 = (float)P.pv_h2, xf = (float)x2;
-                return (float)P.pv_a * h2 * dm::rcp(h2 + xf) +
-                       (float)P.pv_b * dm::exp_(-(float)P.g_k * xf);
+                const float h2 = P.f32.pv_h2, xf = (float)x2;
+                return P.f32.pv_a * h2 * dm::rcp(h2 + xf) +
+                       P.f32.pv_b * dm::exp_(-P.f32.g_k * xf);
             }
         } else if (irc_is(P, MRT_IRC_LORENTZIAN)) {
             if constexpr (kF64) return dm::div(P.lor_h2, P.lor_h2 + x * x);
-            else return (float)P.lor_h2 * dm::rcp((float)(P.lor_h2 + x * x));
+            else return P.f32.lor_h2 * dm::rcp((float)(P.lor_h2 + x * x));
         } else if (irc_is(P, MRT_IRC_BOX)) {
             return __builtin_fabs(x) <= P.box_half ? R(1) : R(0);
         } else {
@@ -332,13 +341,13 @@ struct Tracer {
     static __device__ __forceinline__ float ratio_f32(const TraceParams &P, float a) {
         const float a2 = a * a;
         if (irc_is(P, MRT_IRC_GAUSSIAN)) {
-            return __builtin_amdgcn_exp2f(-(float)P.g_k_log2e * a2);
+            return __builtin_amdgcn_exp2f(-P.f32.g_k_log2e * a2);
         } else if (irc_is(P, MRT_IRC_PSEUDO_VOIGT)) {
-            const float h2 = (float)P.pv_h2;
-            return (float)P.pv_a * h2 * __builtin_amdgcn_rcpf(h2 + a2) +
-                   (float)P.pv_b * __builtin_amdgcn_exp2f(-(float)P.g_k_log2e * a2);
+            const float h2 = P.f32.pv_h2;
+            return P.f32.pv_a * h2 * __builtin_amdgcn_rcpf(h2 + a2) +
+                   P.f32.pv_b * __builtin_amdgcn_exp2f(-P.f32.g_k_log2e * a2);
         } else {
-            const float h2 = (float)P.lor_h2;
+            const float h2 = P.f32.lor_h2;
             return h2 * __builtin_amdgcn_rcpf(h2 + a2);
         }
     }
@@ -348,7 +357,7 @@ struct Tracer {
         const float cw = __builtin_amdgcn_sqrtf(__builtin_fmaf(-c, c, 1.0f));
         if (!(cw >= 0.1f)) return -1;   // normal within ~6 deg of k: no bound
         const float z = __builtin_fmaf(c, caf, -cw * saf);
-        const float shift = (float)P.shift;
+        const float shift = P.f32.shift;
         float lo, hi, slo, shi;   // bounds of |x| and of x
         if (__builtin_fabsf(z) <= 0.25f) {
             const float w = z * z;
@@ -373,13 +382,13 @@ struct Tracer {
         lo = lo > 0.0f ? lo : 0.0f;
         if (irc_is(P, MRT_IRC_TABLE)) {
             // zero outside [x_min, x_max]
-            const float x0 = (float)P.lut_x0, x1 = (float)P.lut_x1;
+            const float x0 = P.f32.lut_x0, x1 = P.f32.lut_x1;
             if (shi < x0 - __builtin_fabsf(x0) * 0x1p-20f - 1e-12f ||
                 slo > x1 + __builtin_fabsf(x1) * 0x1p-20f + 1e-12f)
                 return 0;
             return -1;
         } else if (irc_is(P, MRT_IRC_BOX)) {
-            const float half = (float)P.box_half;
+            const float half = P.f32.box_half;
             if (hi < half * (1.0f - 0x1p-20f)) return 1;
             if (lo > half * (1.0f + 0x1p-20f)) return 0;
             return -1;
@@ -403,7 +412,7 @@ struct Tracer {
         const int exit_status = ry.nrefl ? MRT_EXIT_REFLECTED : MRT_EXIT_TRANSMITTED;
         if ((int)ry.nrefl >= P.max_refl) {
             // reflection budget spent: Beer-Lambert absorption only
-            const R l = -dm::log_pos(uni<R>(w.w0)) * cvt<R>(P.inv_mu0);
+            const R l = -dm::log_pos(uni<R>(w.w0)) * par<R>(P.inv_mu0, P.f32.inv_mu0);
             if (l < ry.dist) {
                 ry.p = axpy(ry.p, l, ry.k);
                 return MRT_ABSORBED;
@@ -412,7 +421,7 @@ struct Tracer {
             return exit_status;
         }
         // free path to the next event at the majorant rate (Eq. AnyEvent)
-        const R l = -dm::log_pos(uni<R>(w.w0)) * cvt<R>(P.inv_mu_tot);
+        const R l = -dm::log_pos(uni<R>(w.w0)) * par<R>(P.inv_mu_tot, P.f32.inv_mu_tot);
         if (l >= ry.dist) {
             ry.p = axpy(ry.p, ry.dist, ry.k);
             return exit_status;
@@ -420,10 +429,10 @@ struct Tracer {
         ry.p = axpy(ry.p, l, ry.k);
         ry.dist -= l;
         const R u1 = uni<R>(w.w1);
-        const R pa = cvt<R>(P.p_a);
+        const R pa = par<R>(P.p_a, P.f32.p_a);
         if (u1 < pa) return MRT_ABSORBED;      // absorbed when u < mu0 / mu_tot
         if (!(ry.sa < 1.0)) return -1;         // no Bragg angle: never reflects
-        const R u_acc = (u1 - pa) * cvt<R>(P.inv_1mpa);
+        const R u_acc = (u1 - pa) * par<R>(P.inv_1mpa, P.f32.inv_1mpa);
 
         V3<R> N, e1, e2;
         frame(P, ry.p, N, e1, e2);
@@ -456,12 +465,12 @@ struct Tracer {
     // ---- source (sec. 2.1) -------------------------------------------------
     // Direction uniform in solid angle inside the cone.
     static __device__ __forceinline__ V3<R> direction(const TraceParams &P, const dm::Words &a) {
-        const R v = uni<R>(a.w0) * cvt<R>(P.vmax);
+        const R v = uni<R>(a.w0) * par<R>(P.vmax, P.f32.vmax);
         const R ct = R(1) - v;
         const R st = dm::sqrt(v * (R(2) - v));
         R sp, cp;
         dm::sincos_turns(uni<R>(a.w1), &sp, &cp);
-        const V3<R> ax = ld3<R>(P.sa), b1 = ld3<R>(P.sb1), b2 = ld3<R>(P.sb2);
+        const V3<R> ax = par3<R>(P.sa, P.f32.sa), b1 = par3<R>(P.sb1, P.f32.sb1), b2 = par3<R>(P.sb2, P.f32.sb2);
         return V3<R>{ct * ax.x + st * (cp * b1.x + sp * b2.x),
                      ct * ax.y + st * (cp * b1.y + sp * b2.y),
                      ct * ax.z + st * (cp * b1.z + sp * b2.z)};
@@ -533,16 +542,16 @@ struct Tracer {
         bool detected = false;
         V3<R> end = ry.p;
         if (status == MRT_EXIT_REFLECTED || status == MRT_EXIT_TRANSMITTED) {
-            const V3<R> dn = ld3<R>(P.dn);
+            const V3<R> dn = par3<R>(P.dn, P.f32.dn);
             const R kn = dot(ry.k, dn);
             if (kn < R(0)) {
-                const V3<R> dP = ld3<R>(P.dP);
+                const V3<R> dP = par3<R>(P.dP, P.f32.dP);
                 const R t = dot(sub(dP, ry.p), dn) / kn;
                 if (t > R(0)) {
                     const V3<R> h = axpy(ry.p, t, ry.k);
                     const V3<R> d = sub(h, dP);
-                    const R fu = dot(d, ld3<R>(P.du)) / cvt<R>(P.pitch) + cvt<R>(P.half_nx);
-                    const R fv = dot(d, ld3<R>(P.dv)) / cvt<R>(P.pitch) + cvt<R>(P.half_ny);
+                    const R fu = dot(d, par3<R>(P.du, P.f32.du)) / par<R>(P.pitch, P.f32.pitch) + par<R>(P.half_nx, P.f32.half_nx);
+                    const R fv = dot(d, par3<R>(P.dv, P.f32.dv)) / par<R>(P.pitch, P.f32.pitch) + par<R>(P.half_ny, P.f32.half_ny);
                     const R fi = __builtin_floor(fu), fj = __builtin_floor(fv);
                     if (fi >= R(0) && fj >= R(0) && fi < (R)P.nx && fj < (R)P.ny) {
                         pi = (int)fi;
@@ -567,7 +576,7 @@ struct Tracer {
     static __device__ __forceinline__ bool start(const TraceParams &P, const double *cdf,
                                                  uint64_t ray, RayT &ry) {
         const dm::Words a = dm::philox(P.key0, P.key1, 0u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
-        const V3<R> o = ld3<R>(P.so);
+        const V3<R> o = par3<R>(P.so, P.f32.so);
         const V3<R> k = direction(P, a);
         ry.id = ray;
         ry.k = k;
@@ -617,8 +626,10 @@ __device__ __forceinline__ void flush(const TraceParams &P, WaveCounts &c) {
 // `claim(next, end)` renews (false when no rays are left); rays that miss the
 // crystal are counted and retired inside the refill.  Events run until
 // refill_at lanes are idle, then the wave refills; once the rays run out the
-// remaining lanes drain.  Counters are flushed to P.dev_counters whenever a
-// new chunk is claimed and at the end.
+// remaining lanes drain.  The wave's counters (64-bit, in scalar registers)
+// are added to P.dev_counters once, at the end: flushing them at every chunk
+// claim put nine atomics on the same nine addresses per chunk, which
+// throttled workloads whose chunks go fast (most rays missing).
 // ---------------------------------------------------------------------------
 template <class T, class Claim>
 __device__ __forceinline__ void trace_loop(const TraceParams &P, const double *lut,
@@ -636,7 +647,6 @@ __device__ __forceinline__ void trace_loop(const TraceParams &P, const double *l
             const uint32_t nidle = popc(idle);
             if (nidle == 0 || (nidle < refill_at && idle != ~0ull)) break;
             if (next == end) {
-                flush(P, cnt);
                 if (!claim(next, end)) {
                     more = false;
                     break;
@@ -746,36 +756,24 @@ __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slot
 
 // ---------------------------------------------------------------------------
 // Persistent trace kernel of one call (sec. 2; rays [P.first, P.first + P.n)).
+//
+// The parameter block is the kernel's by-value argument, read through the
+// kernel-argument segment pointer so that each field is a scalar load where
+// it is used.  Read as a by-value argument, the whole block is loaded into
+// scalar registers at entry and the pressure spills them into vector
+// register lanes (FP64 von Hamos kernel: 111 -> 87 VGPRs).  The rocking-curve
+// table and the spectrum CDF are read from device memory, where they stay
+// cache-resident (at most 32 + 8 KB): staging them in LDS capped occupancy
+// at 4 waves per SIMD (40 KB per workgroup), and LDS reads share the wait
+// counter of the scalar parameter loads; the stress workload ran 10-11%
+// faster without it in both precisions.
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ void trace_body(const TraceParams &P) {
-    extern __shared__ double lds[];
-    // stage the rocking-curve table and the spectrum CDF in LDS
-    const int nl = T::irc_is(P, MRT_IRC_TABLE) ? P.lut_n : 0;
-    const int nc = P.spectrum == MRT_SPECTRUM_TABLE ? P.n_bins + 1 : 0;
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) lds[i] = P.lut[i];
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) lds[nl + i] = P.bin_cdf[i];
-    __syncthreads();
-    RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
-    trace_loop<T>(P, lds, lds + nl, claim);
-}
-
-// The parameter block is the kernel's by-value argument.  FP64 kernels
-// without a rocking-curve table read it through the kernel-argument segment
-// pointer, so each field is a scalar load where it is used; read as a
-// by-value argument, the whole block is loaded into scalar registers at
-// entry, and the pressure spills them into vector-register lanes (FP64 von
-// Hamos kernel: 111 -> 87 VGPRs, 4 -> 5 waves per SIMD, 2-8% faster over the
-// mosaic kinds).  The other kernels keep the by-value form, measured faster
-// for them: with a table the in-loop scalar loads share the LDS reads' wait
-// counter (up to 20% slower), and the FP32-mixed kernels lost up to 40%.
 template <class R, int GEOM, int MDF, int IRC, bool REC>
 __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
     using T = Tracer<R, GEOM, MDF, IRC, REC>;
-    if constexpr (sizeof(R) == 8 && IRC != MRT_IRC_TABLE)
-        trace_body<T>(*(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr());
-    else
-        trace_body<T>(P);
+    const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
+    RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
+    trace_loop<T>(Q, Q.lut, Q.bin_cdf, claim);
 }
 
 }  // namespace tk

@@ -12,8 +12,30 @@
 namespace mrt {
 
 constexpr int kMaxLines = 8;
-// Largest tables staged in LDS (rocking-curve values plus spectrum CDF).
+// Largest tables (rocking-curve values plus spectrum CDF), kept small enough
+// to stay cache-resident while the kernels read them.
 constexpr int kMaxTableBytes = 64 * 1024;
+
+// Parameters the FP32-mixed kernels use in FP32 arithmetic.  The host keeps an
+// FP32 copy of each (rounded to nearest, as a device conversion would round
+// it), so those kernels read them ready for use instead of converting them
+// from FP64 inside the ray loop or holding converted copies in registers.
+#define MRT_F32_SCALARS(X)                                                                    \
+    X(vmax) X(hl) X(hw) X(T) X(R2) X(Ro2) X(inv_mu0) X(inv_mu_tot) X(p_a) X(inv_1mpa)          \
+    X(m_eta) X(inv_eta) X(inv_1meta) X(vmf_s2) X(vmf_floor) X(lor_g) X(wl_half_g2) X(wl_z)     \
+    X(swl_k) X(swl_d) X(shift) X(g_k) X(g_k_log2e) X(pv_a) X(pv_b) X(pv_h2) X(lor_h2)          \
+    X(box_half) X(lut_x0) X(lut_x1) X(pitch) X(half_nx) X(half_ny)
+#define MRT_F32_VECTORS(X) \
+    X(so) X(sa) X(sb1) X(sb2) X(N) X(e1) X(e2) X(ax) X(op) X(om) X(dP) X(dn) X(du) X(dv)
+
+struct TraceParamsF32 {
+#define MRT_F32_S(n) float n;
+#define MRT_F32_V(n) float n[3];
+    MRT_F32_SCALARS(MRT_F32_S)
+    MRT_F32_VECTORS(MRT_F32_V)
+#undef MRT_F32_S
+#undef MRT_F32_V
+};
 
 struct TraceParams {
     // ---- source (sec. 2.1), local coordinates
@@ -75,6 +97,8 @@ struct TraceParams {
     mrt_hit_record *records;
     unsigned long long *dev_counters;   // kNumCounters entries
     unsigned long long *chunk_counter;  // next unclaimed ray offset
+
+    TraceParamsF32 f32;           // FP32 copies (see above)
 };
 
 // Device counter slots.

@@ -69,8 +69,8 @@ def test_von_hamos_first_million():
 
 
 def test_flat_stress_fp64():
-    """Thick HOPG, Lorentzian 0.8 deg, tabulated Darwin-Prins rocking curve in
-    LDS, 1024-bin spectrum CDF in LDS, up to 8 reflections, 4096^2 detector."""
+    """Thick HOPG, Lorentzian 0.8 deg, tabulated Darwin-Prins rocking curve,
+    1024-bin spectrum CDF, up to 8 reflections, 4096^2 detector."""
     w = W.get("flat_stress", precision="fp64")
     assert_parity(w, 300_000)
 
