@@ -100,9 +100,17 @@ def cpu_baseline(w, n):
     t0 = time.perf_counter()
     r = oracle.trace(w, first=0, n=n, threads=threads)
     dt = time.perf_counter() - t0
+    # and on one core, over a tenth of the sample
+    n1 = max(1, n // 10)
+    t1 = time.perf_counter()
+    oracle.trace(w, first=0, n=n1, threads=1)
+    dt1 = time.perf_counter() - t1
+    log(f"oracle: {n1} rays on 1 thread")
     return {"value": round(n / dt, 1), "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"ray ids [0, {n}) of the same workload, FP64, images on, {dt:.2f} s",
-            "events": r["counters"]["events"]}, r
+            "events": r["counters"]["events"],
+            "one_core": {"value": round(n1 / dt1, 1), "unit": "rays/s",
+                         "sample": f"ray ids [0, {n1}), {dt1:.2f} s"}}, r
 
 
 def precision_report(mrt, precision, w, c64, c32, rays, oracle_result, n_oracle):
@@ -137,7 +145,7 @@ def precision_report(mrt, precision, w, c64, c32, rays, oracle_result, n_oracle)
     return rep
 
 
-def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None):
+def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None, round_rays=0):
     """Serve the requests: submitted all at once (gaps_s None) or with the
     given inter-arrival gaps; a consumer thread takes each finished request
     from the completion queue and releases it at once.  Returns per-request
@@ -146,7 +154,8 @@ def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None):
     import threading
     n = len(reqs)
     done = []
-    srv = mrt.Server(hbm_budget_bytes=budget, max_slots=max_slots, precision=precision)
+    srv = mrt.Server(hbm_budget_bytes=budget, max_slots=max_slots, precision=precision,
+                     round_rays=round_rays)
 
     def consume():
         for _ in range(n):
@@ -194,7 +203,7 @@ def sequential_run(mrt, reqs, precision):
     return ev0.elapsed_time(ev1) * 1e-3, events
 
 
-def serving(mrt, W, n_requests, budget, max_slots, load, seed=4):
+def serving(mrt, W, n_requests, budget, max_slots, load, seed=4, round_rays=0):
     """The serving workload (design requests of varied geometry and ray
     count): for each precision, the saturated throughput (all requests queued
     at once), then Poisson arrivals at `load` times that throughput with
@@ -211,11 +220,11 @@ def serving(mrt, W, n_requests, budget, max_slots, load, seed=4):
         for w in reqs:
             w["precision"] = prec
         seq_s, seq_events = sequential_run(mrt, reqs, prec)
-        lat0, span0, st0 = serving_run(mrt, reqs, prec, budget, max_slots)
+        lat0, span0, st0 = serving_run(mrt, reqs, prec, budget, max_slots, round_rays=round_rays)
         sat = rays / span0
         rate = load * sat / (rays / n_requests)           # requests per second
         gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n_requests)
-        lat, span, st = serving_run(mrt, reqs, prec, budget, max_slots, gaps)
+        lat, span, st = serving_run(mrt, reqs, prec, budget, max_slots, gaps, round_rays)
         out[prec] = {
             "one_call_per_request_rays_per_s": round(rays / seq_s, 1),
             "events_per_ray": round(seq_events / rays, 3),
@@ -247,6 +256,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-budget-mib", type=int, default=4096)
     ap.add_argument("--serving-load", type=float, default=0.7)
+    ap.add_argument("--serving-round-rays", type=int, default=0, help="rays per round (0 = the server's default)")
     ap.add_argument("--no-serving", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -303,7 +313,8 @@ def main():
             "roofline": roofline(op_costs, profiling, w, "fp32_mixed", pm, info["compute_units"]),
         }
     res["serving"] = None if a.no_serving else serving(
-        mrt, W, a.serving_requests, a.serving_budget_mib << 20, 64, a.serving_load)
+        mrt, W, a.serving_requests, a.serving_budget_mib << 20, 64, a.serving_load,
+        round_rays=a.serving_round_rays)
     orc = None
     if not a.no_cpu_baseline:
         res["cpu_baseline"], orc = cpu_baseline(w, a.cpu_rays)

@@ -64,16 +64,24 @@ struct mrt_server {
     bool stop = false;
     std::thread engine;
     hipStream_t setup = nullptr;                // admission uploads and frees
+    hipEvent_t ev_setup = nullptr;              // end of the latest admission uploads
+    bool setup_recorded = false;
     hipEvent_t ev_ref = nullptr;                // time origin of the busy figure
+    // pinned staging per slot: parameter block and tables of the request in
+    // the slot (rewritten only when the slot is reassigned, by which time the
+    // previous request's rounds, which waited for its uploads, are done)
+    mrt::TraceParams *h_params = nullptr;
+    double *h_tables = nullptr;                 // max_slots x kMaxTableBytes
     double busy_end = 0.0;                      // end of the last completed round (ms)
     mrt::TraceParams *d_slots = nullptr;
     unsigned long long *d_counters = nullptr;   // max_slots x kNumCounters
     // per round buffer (kDepth rounds in flight, each on its own stream)
     hipStream_t streams[kDepth] = {};
     hipEvent_t ev0[kDepth] = {}, ev1[kDepth] = {};
-    mrt::ServeItem *d_items[kDepth] = {};       // max_slots items of a round
+    // items of a round followed by their zeroed chunk cursors, one copy
+    mrt::ServeItem *d_items[kDepth] = {};
     mrt::ServeItem *h_items[kDepth] = {};       // pinned staging
-    unsigned long long *d_cursors[kDepth] = {}; // one chunk cursor per item
+    unsigned long long *h_counters[kDepth] = {}; // pinned snapshot of all slots' counters
     std::deque<Round> inflight;
     const void *kernel = nullptr;
     int grid = 0;
@@ -107,8 +115,8 @@ void free_rec(mrt_server *S, Rec &r) {
 }
 
 // Device set-up of an admitted request (engine thread, lock held), enqueued
-// on the set-up stream; the caller synchronises that stream before any round
-// that may use the request is launched.
+// on the set-up stream from pinned staging; the caller records the set-up
+// event that every later round waits for.
 bool admit_one(mrt_server *S, uint64_t ticket) {
     Rec &r = S->recs.at(ticket);
     const int32_t slot = S->plan.find(ticket)->slot;
@@ -131,13 +139,19 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     P.dev_counters = S->d_counters + (size_t)slot * mrt::kNumCounters;
     P.records_mode = MRT_RECORDS_NONE;
     P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : 16u;
-    if (!r.tables.empty())
-        (void)hipMemcpyAsync(r.d_tables, r.tables.data(), r.tables.size() * sizeof(double),
-                             hipMemcpyHostToDevice, S->setup);
-    mrt::launch_zero(r.d_counts, px, S->setup);
-    mrt::launch_zero(r.d_energy, 2 * px, S->setup);
-    mrt::launch_zero(P.dev_counters, 2 * mrt::kNumCounters, S->setup);
-    e = hipMemcpyAsync(&S->d_slots[slot], &P, sizeof(P), hipMemcpyHostToDevice, S->setup);
+    double *ht = S->h_tables + (size_t)slot * (mrt::kMaxTableBytes / sizeof(double));
+    if (!r.tables.empty()) {
+        std::memcpy(ht, r.tables.data(), r.tables.size() * sizeof(double));
+        e = hipMemcpyAsync(r.d_tables, ht, r.tables.size() * sizeof(double),
+                           hipMemcpyHostToDevice, S->setup);
+    }
+    if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(r.d_counts, px, S->setup);
+    if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(r.d_energy, 2 * px, S->setup);
+    if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(P.dev_counters, 2 * mrt::kNumCounters, S->setup);
+    S->h_params[slot] = P;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&S->d_slots[slot], &S->h_params[slot], sizeof(P), hipMemcpyHostToDevice,
+                           S->setup);
     if (e != hipSuccess) {
         free_rec(S, r);
         return false;
@@ -145,11 +159,10 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     return true;
 }
 
-void read_counters(mrt_server *S, Rec &r, int32_t slot) {
-    unsigned long long h[mrt::kNumCounters];
-    if (hipMemcpy(h, S->d_counters + (size_t)slot * mrt::kNumCounters, sizeof h,
-                  hipMemcpyDeviceToHost) != hipSuccess)
-        return;
+// A finished request's counters, from the snapshot taken after the round
+// that finished it (which also waited for the round before it).
+void read_counters(mrt_server *S, Rec &r, int32_t slot, int buf) {
+    const unsigned long long *h = S->h_counters[buf] + (size_t)slot * mrt::kNumCounters;
     mrt_counters &c = r.counters;
     c.emitted = r.n_rays;
     c.missed = h[mrt::kCMissed];
@@ -165,8 +178,8 @@ void read_counters(mrt_server *S, Rec &r, int32_t slot) {
     c.kernel_ms = 0.0;
 }
 
-// Admit queued requests while slots and memory allow; their set-up is
-// complete on the device when this returns.
+// Admit queued requests while slots and memory allow; their uploads are
+// enqueued, and every round launched afterwards waits for them.
 void admit_all(mrt_server *S) {
     std::vector<uint64_t> ok;
     for (uint64_t t : S->plan.admit(S->now_ms())) {
@@ -178,12 +191,16 @@ void admit_all(mrt_server *S) {
             S->cv_done.notify_all();
         }
     }
-    if (!ok.empty() && hipStreamSynchronize(S->setup) != hipSuccess) {
-        for (uint64_t t : ok) {
-            S->plan.fail(t, MRT_EDEVICE, S->now_ms());
-            S->finished.push_back(t);
+    if (!ok.empty()) {
+        if (hipEventRecord(S->ev_setup, S->setup) == hipSuccess) {
+            S->setup_recorded = true;
+        } else {
+            for (uint64_t t : ok) {
+                S->plan.fail(t, MRT_EDEVICE, S->now_ms());
+                S->finished.push_back(t);
+            }
+            S->cv_done.notify_all();
         }
-        S->cv_done.notify_all();
     }
 }
 
@@ -220,19 +237,32 @@ void stage_round(mrt_server *S, const std::vector<mrt::serve::Item> &items, int 
     uint64_t chunk = (total / (waves * 4u) + 63u) / 64u * 64u;
     chunk = std::max<uint64_t>(64u, std::min<uint64_t>(2048u, chunk));
     for (uint32_t i = 0; i < n; ++i) h[i].chunk = (uint32_t)chunk;
+    // the chunk cursors follow the items, zeroed by the same copy
+    std::memset(h + n, 0, n * sizeof(unsigned long long));
     *n_out = n;
     *total_out = total;
 }
 
-// Enqueue a staged round on its stream (lock not held).
-hipError_t launch_round(mrt_server *S, int b, uint32_t n, uint64_t total) {
+// Enqueue a staged round on its stream (lock not held): wait for the latest
+// admission uploads, copy the items and zeroed cursors, launch, then snapshot
+// every slot's counters once the round before it (other) has ended too.
+hipError_t launch_round(mrt_server *S, int b, uint32_t n, uint64_t total, bool wait_setup,
+                        hipEvent_t other) {
     hipStream_t st = S->streams[b];
-    hipError_t e = hipMemcpyAsync(S->d_items[b], S->h_items[b], n * sizeof(mrt::ServeItem),
-                                  hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = (hipError_t)mrt::launch_zero(S->d_cursors[b], 2u * n, st);
+    hipError_t e = wait_setup ? hipStreamWaitEvent(st, S->ev_setup, 0) : hipSuccess;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_items[b], S->h_items[b],
+                           n * (sizeof(mrt::ServeItem) + sizeof(unsigned long long)),
+                           hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(S->ev0[b], st);
-    void *args[] = {&S->d_slots, &S->d_items[b], &n, &total, &S->d_cursors[b]};
+    unsigned long long *cursors = (unsigned long long *)(S->d_items[b] + n);
+    void *args[] = {&S->d_slots, &S->d_items[b], &n, &total, &cursors};
     if (e == hipSuccess) e = hipLaunchKernel(S->kernel, dim3((unsigned)S->grid), dim3(256), args, 0, st);
+    if (e == hipSuccess && other) e = hipStreamWaitEvent(st, other, 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->h_counters[b], S->d_counters,
+                           sizeof(unsigned long long) * mrt::kNumCounters * (size_t)S->cfg.max_slots,
+                           hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipEventRecord(S->ev1[b], st);
     return e;
 }
@@ -269,7 +299,7 @@ void finish_oldest(mrt_server *S, std::unique_lock<std::mutex> &lk) {
     for (const auto &it : rd.items) S->stats.rays_traced += it.count;
     for (uint64_t t : S->plan.complete_round(rd.items, S->now_ms())) {
         const mrt::serve::Request *q = S->plan.find(t);
-        if (q && q->state == mrt::serve::kDone) read_counters(S, S->recs.at(t), q->slot);
+        if (q && q->state == mrt::serve::kDone) read_counters(S, S->recs.at(t), q->slot, rd.buf);
         S->finished.push_back(t);
     }
     S->cv_done.notify_all();
@@ -286,11 +316,13 @@ void engine(mrt_server *S) {
             std::vector<mrt::serve::Item> items = S->plan.plan_round();
             if (items.empty()) break;
             const int b = S->inflight.empty() ? 0 : 1 - S->inflight.back().buf;
+            hipEvent_t other = S->inflight.empty() ? nullptr : S->ev1[S->inflight.back().buf];
+            const bool wait_setup = S->setup_recorded;
             uint32_t n = 0;
             uint64_t total = 0;
             stage_round(S, items, b, &n, &total);
             lk.unlock();
-            const hipError_t e = launch_round(S, b, n, total);
+            const hipError_t e = launch_round(S, b, n, total, wait_setup, other);
             lk.lock();
             if (e != hipSuccess) {
                 fail_items(S, items);
@@ -361,16 +393,21 @@ mrt_status mrt_server_create(const mrt_server_config *config, mrt_server **out) 
     S->grid = per_cu * prop.multiProcessorCount;
     const size_t ms = (size_t)c.max_slots;
     bool ok = hipStreamCreateWithFlags(&S->setup, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreate(&S->ev_ref) == hipSuccess &&
+              hipEventCreate(&S->ev_ref) == hipSuccess && hipEventCreate(&S->ev_setup) == hipSuccess &&
+              hipHostMalloc((void **)&S->h_params, sizeof(mrt::TraceParams) * ms, 0) == hipSuccess &&
+              hipHostMalloc((void **)&S->h_tables, (size_t)mrt::kMaxTableBytes * ms, 0) == hipSuccess &&
               hipMalloc((void **)&S->d_slots, sizeof(mrt::TraceParams) * ms) == hipSuccess &&
               hipMalloc((void **)&S->d_counters, sizeof(unsigned long long) * mrt::kNumCounters * ms) ==
                   hipSuccess;
     for (int b = 0; ok && b < kDepth; ++b)
         ok = hipStreamCreateWithFlags(&S->streams[b], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreate(&S->ev0[b]) == hipSuccess && hipEventCreate(&S->ev1[b]) == hipSuccess &&
-             hipMalloc((void **)&S->d_items[b], sizeof(mrt::ServeItem) * ms) == hipSuccess &&
-             hipMalloc((void **)&S->d_cursors[b], sizeof(unsigned long long) * ms) == hipSuccess &&
-             hipHostMalloc((void **)&S->h_items[b], sizeof(mrt::ServeItem) * ms, 0) == hipSuccess;
+             hipMalloc((void **)&S->d_items[b], (sizeof(mrt::ServeItem) + sizeof(unsigned long long)) * ms) ==
+                 hipSuccess &&
+             hipHostMalloc((void **)&S->h_items[b], (sizeof(mrt::ServeItem) + sizeof(unsigned long long)) * ms,
+                           0) == hipSuccess &&
+             hipHostMalloc((void **)&S->h_counters[b], sizeof(unsigned long long) * mrt::kNumCounters * ms,
+                           0) == hipSuccess;
     // the time origin of the busy figure
     ok = ok && hipEventRecord(S->ev_ref, S->setup) == hipSuccess &&
          hipStreamSynchronize(S->setup) == hipSuccess;
@@ -528,13 +565,16 @@ void mrt_server_destroy(mrt_server *S) {
     if (S->d_counters) (void)hipFree(S->d_counters);
     for (int b = 0; b < kDepth; ++b) {
         if (S->d_items[b]) (void)hipFree(S->d_items[b]);
-        if (S->d_cursors[b]) (void)hipFree(S->d_cursors[b]);
         if (S->h_items[b]) (void)hipHostFree(S->h_items[b]);
+        if (S->h_counters[b]) (void)hipHostFree(S->h_counters[b]);
         if (S->ev0[b]) (void)hipEventDestroy(S->ev0[b]);
         if (S->ev1[b]) (void)hipEventDestroy(S->ev1[b]);
         if (S->streams[b]) (void)hipStreamDestroy(S->streams[b]);
     }
     if (S->ev_ref) (void)hipEventDestroy(S->ev_ref);
+    if (S->ev_setup) (void)hipEventDestroy(S->ev_setup);
+    if (S->h_params) (void)hipHostFree(S->h_params);
+    if (S->h_tables) (void)hipHostFree(S->h_tables);
     if (S->setup) (void)hipStreamDestroy(S->setup);
     delete S;
 }

@@ -166,6 +166,20 @@ inline hipError_t hipEventSynchronize(hipEvent_t e) {
     e->cv.wait(lk, [&] { return e->reached >= want; });
     return hipSuccess;
 }
+// The stream waits, at this point of its queue, for the event's latest
+// recording as of this call.
+inline hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
+    uint64_t want;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        want = e->recorded;
+    }
+    s->push([e, want] {
+        std::unique_lock<std::mutex> lk(e->mu);
+        e->cv.wait(lk, [&] { return e->reached >= want; });
+    });
+    return hipSuccess;
+}
 inline hipError_t hipStreamSynchronize(hipStream_t s) {
     ihipEvent_t e;
     hipEventRecord(&e, s);
