@@ -137,7 +137,7 @@ template <class R, bool REC>
 void trace_body(const TraceParams &P) {
     using T = Tracer<R, kAny, kAny, kAny, REC>;
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
-    trace_loop<T>(P, P.lut, P.bin_cdf, claim);
+    trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim);
 }
 }  // namespace
 
