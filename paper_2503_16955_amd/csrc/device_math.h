@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "math_tables.h"
+
 namespace mrt {
 namespace dm {
 
@@ -106,73 +108,59 @@ __device__ __forceinline__ double rsqrt(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// Natural logarithm of a positive normal double.  x = 2^e m with m in
-// [sqrt(1/2), sqrt(2)); with f = m - 1 and s = f / (2 + f),
-//   log(1 + f) = 2 atanh(s) = f - s f + 2 s (s^2/3 + s^4/5 + ...)
-// (the atanh series of the logarithm, Abramowitz and Stegun 4.1.27), |s| <=
-// 0.1716, truncated after s^23; ln 2 is split so that e ln2_hi is exact.
+// Natural logarithm of a positive normal double, by the table method: x =
+// 2^e m with m in [1, 2); inv is the table's float near 1 / m (128 intervals)
+// and r = m inv - 1, |r| <= 2^-8, from one FMA; then
+//   log x = e ln 2 + (-log inv) + log1p(r),
+// log1p by its series to r^8, the high parts e ln2_hi (exact: ln2_hi has 32
+// significant bits) and -log(inv)_hi summed first.  Within 2^-7 of 1 the
+// table is bypassed (r = x - 1, exact) so that small logarithms keep their
+// relative accuracy.  About 1 ulp.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double log_pos(double x) {
     const uint64_t b = (uint64_t)__double_as_longlong(x);
-    int e = (int)(b >> 52) - 1023;
-    double m = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
-    if (m > 1.4142135623730951) {
-        m *= 0.5;
-        e += 1;
-    }
-    const double f = m - 1.0;
-    const double s = div(f, 2.0 + f);
-    const double z = s * s;
-    double p = 2.0 / 23.0;
-    p = poly_step(p, z, 2.0 / 21.0);
-    p = poly_step(p, z, 2.0 / 19.0);
-    p = poly_step(p, z, 2.0 / 17.0);
-    p = poly_step(p, z, 2.0 / 15.0);
-    p = poly_step(p, z, 2.0 / 13.0);
-    p = poly_step(p, z, 2.0 / 11.0);
-    p = poly_step(p, z, 2.0 / 9.0);
-    p = poly_step(p, z, 2.0 / 7.0);
-    p = poly_step(p, z, 2.0 / 5.0);
-    p = poly_step(p, z, 2.0 / 3.0);
-    const double l1p = fma(-s, f, f) + s * z * p;
-    const double de = (double)e;
-    return fma(de, 0.6931467056274414, fma(de, 4.7493250390316726e-07, l1p));
+    const int e = (int)(b >> 52) - 1023;
+    const double m = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    const LogEntry t = kLogTable[(b >> 45) & 127];
+    const bool near1 = __builtin_fabs(x - 1.0) <= 0x1p-7;
+    const double r = near1 ? x - 1.0 : fma(m, (double)t.inv, -1.0);
+    double p = -1.0 / 8.0;
+    p = poly_step(p, r, 1.0 / 7.0);
+    p = poly_step(p, r, -1.0 / 6.0);
+    p = poly_step(p, r, 1.0 / 5.0);
+    p = poly_step(p, r, -1.0 / 4.0);
+    p = poly_step(p, r, 1.0 / 3.0);
+    p = poly_step(p, r, -1.0 / 2.0);
+    const double l1p = fma(r * r, p, r);
+    const double de = near1 ? 0.0 : (double)e;
+    const double hi = near1 ? 0.0 : fma(de, 0x1.62e42feep-1, t.nlog_hi);
+    const double lo = near1 ? 0.0 : fma(de, 0x1.a39ef35793c76p-33, (double)t.nlog_lo);
+    return hi + (lo + l1p);
 }
 
 // ---------------------------------------------------------------------------
-// sin(2 pi u) and cos(2 pi u) for an angle given in turns (|u| < 2^30).  The
-// reduction to the nearest quarter turn is exact in turns; the remainder
-// (|a| <= pi/4 after scaling by 2 pi) goes through the Taylor series of sin
-// to a^17 and of cos to a^18, and the quadrant permutes and negates.
+// sin and cos of 2 pi u (u in turns, u in [0, 1)).  u = q / 256 + r exactly
+// (|r| <= 1/512); with a = 2 pi r, |a| <= 0.0123, sin a and cos a by their
+// series to a^7 and a^6, then the angle-addition formulas with the table's
+// sin and cos of 2 pi q / 256 (exact at the quadrant points).  About 1 ulp.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sincos_turns(double u, double *sn, double *cs) {
-    const double q = __builtin_rint(4.0 * u);
-    const double r = fma(-0.25, q, u);
-    const double a = r * 6.283185307179586;
+    const double q = __builtin_rint(256.0 * u);
+    const double r = fma(-0x1p-8, q, u);
+    const double a = fma(r, 0x1.921fb54442d18p+2, r * 0x1.1a62633145c07p-52);
     const double z = a * a;
-    double P = 1.0 / 355687428096000.0;
-    P = poly_step(P, z, -1.0 / 1307674368000.0);
-    P = poly_step(P, z, 1.0 / 6227020800.0);
-    P = poly_step(P, z, -1.0 / 39916800.0);
-    P = poly_step(P, z, 1.0 / 362880.0);
-    P = poly_step(P, z, -1.0 / 5040.0);
-    P = poly_step(P, z, 1.0 / 120.0);
-    P = poly_step(P, z, -1.0 / 6.0);
-    const double s = fma(a * z, P, a);
-    double Q = -1.0 / 6402373705728000.0;
-    Q = poly_step(Q, z, 1.0 / 20922789888000.0);
-    Q = poly_step(Q, z, -1.0 / 87178291200.0);
-    Q = poly_step(Q, z, 1.0 / 479001600.0);
-    Q = poly_step(Q, z, -1.0 / 3628800.0);
-    Q = poly_step(Q, z, 1.0 / 40320.0);
-    Q = poly_step(Q, z, -1.0 / 720.0);
-    Q = poly_step(Q, z, 1.0 / 24.0);
-    const double c = fma(z * z, Q, fma(-0.5, z, 1.0));
-    const int qi = (int)q & 3;
-    const double ss = (qi & 1) ? c : s;
-    const double cc = (qi & 1) ? s : c;
-    *sn = (qi & 2) ? -ss : ss;
-    *cs = (qi == 1 || qi == 2) ? -cc : cc;
+    double ps = -1.0 / 5040.0;
+    ps = poly_step(ps, z, 1.0 / 120.0);
+    ps = poly_step(ps, z, -1.0 / 6.0);
+    const double sa = fma(a * z, ps, a);
+    double pc = -1.0 / 720.0;
+    pc = poly_step(pc, z, 1.0 / 24.0);
+    pc = poly_step(pc, z, -0.5);
+    const double cm = z * pc;   // cos a - 1
+    const SinCosEntry t = kSinCosTable[(int)q & 255];
+    // the table value is added last, to the small corrections
+    *sn = t.s + fma(t.s, cm, t.c * sa);
+    *cs = t.c + fma(t.c, cm, -(t.s * sa));
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,27 @@
+"""The FP64 device math routines (table log, sin/cos of turns, in
+device_math.h) compiled for the host and compared with long-double
+references: a few ulps at most, far inside the 1e-12 per-ray parity
+contract."""
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2503_16955_amd", "csrc")
+ASM_FMA = 'asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "s"(c));'
+
+
+def test_fp64_log_and_sincos_within_two_ulps(tmp_path):
+    shutil.copy(os.path.join(CSRC, "math_tables.h"), tmp_path / "math_tables.h")
+    dm = open(os.path.join(CSRC, "device_math.h")).read()
+    assert dm.count(ASM_FMA) == 1
+    (tmp_path / "device_math.h").write_text(dm.replace(ASM_FMA, "r = __builtin_fma(p, z, c);"))
+    exe = tmp_path / "math_accuracy"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", os.path.join(HERE, "helpers", "fakedev"),
+                           "-I", str(tmp_path), "-I", os.path.join(ROOT, "include"),
+                           os.path.join(HERE, "helpers", "math_accuracy.cpp"), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split()
+    err = dict(zip(out[0::2], map(float, out[1::2])))
+    assert err["log"] <= 2.0, err
+    assert err["sin"] <= 2.5 and err["cos"] <= 2.5, err

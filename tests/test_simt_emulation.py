@@ -39,7 +39,8 @@ ASM_FMA = 'asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "s"(c));'
 @pytest.fixture(scope="module")
 def emu(tmp_path_factory):
     d = tmp_path_factory.mktemp("simt")
-    for f in ("trace_impl.h", "trace_params.h", "device_math.h", "params.h", "params.cpp"):
+    for f in ("trace_impl.h", "trace_params.h", "device_math.h", "math_tables.h", "params.h",
+              "params.cpp"):
         shutil.copy(os.path.join(CSRC, f), d / f)
     dm = (d / "device_math.h").read_text()
     assert dm.count(ASM_FMA) == 1, "device_math.h: the inline asm this test replaces has changed"
