@@ -189,7 +189,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
             per_cu = 1;
         grid = cus * per_cu;
     }
-    P.refill_idle = opt.refill_idle > 0 ? (uint32_t)opt.refill_idle : 16u;
+    P.refill_idle = opt.refill_idle > 0 ? (uint32_t)opt.refill_idle : 8u;
     // chunk size: enough chunks for every wave to claim several
     const uint64_t waves = (uint64_t)grid * (uint64_t)(block / 64);
     uint64_t chunk = n_rays / (waves * 8);

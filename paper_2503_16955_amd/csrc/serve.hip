@@ -14,9 +14,11 @@ __global__ void __launch_bounds__(256)
     serve_kernel(const TraceParams *__restrict__ slots, const ServeItem *__restrict__ items,
                  uint32_t n_items, uint64_t total, unsigned long long *__restrict__ cursors) {
     const uint32_t waves_per_block = blockDim.x >> 6;
-    const uint32_t wave = blockIdx.x * waves_per_block + uniform(threadIdx.x >> 6);
-    serve_waves<Tracer<R, kAny, kAny, kAny, false>>(slots, items, n_items, total, cursors, wave,
-                                                    gridDim.x * waves_per_block);
+    const uint32_t w = uniform(threadIdx.x >> 6);
+    __shared__ RayQueue<R, false> queues[4];   // one ray queue per wave
+    serve_waves<Tracer<R, kAny, kAny, kAny, false>>(slots, items, n_items, total, cursors,
+                                                    blockIdx.x * waves_per_block + w,
+                                                    gridDim.x * waves_per_block, queues[w]);
 }
 
 }  // namespace tk

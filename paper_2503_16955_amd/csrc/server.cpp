@@ -138,7 +138,7 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     P.bin_cdf = P.spectrum == MRT_SPECTRUM_TABLE ? r.d_tables + nl : nullptr;
     P.dev_counters = S->d_counters + (size_t)slot * mrt::kNumCounters;
     P.records_mode = MRT_RECORDS_NONE;
-    P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : 16u;
+    P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : 8u;
     double *ht = S->h_tables + (size_t)slot * (mrt::kMaxTableBytes / sizeof(double));
     if (!r.tables.empty()) {
         std::memcpy(ht, r.tables.data(), r.tables.size() * sizeof(double));

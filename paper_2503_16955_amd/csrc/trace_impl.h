@@ -103,6 +103,64 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
+// Orders one wave's LDS writes before its later reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wave queue of rays that have entered the crystal, in LDS (one array
+// per field, so the lanes of a wave touch consecutive addresses).  A wave
+// starts a batch of candidate rays on all its lanes at once and queues those
+// that enter; lanes whose ray has ended take queued rays.  The queue is only
+// refilled when empty, so its entries are [head, head + queued) with no
+// wrap-around.  While a batch is started, the queue's (then free) slots also
+// hold the running rays (slot = lane), so that the candidates can use the
+// same registers.
+constexpr uint32_t kQueue = 64;
+template <class R, bool REC> struct QueueEntry {};   // entry points: record kernels only
+template <class R> struct QueueEntry<R, true> {
+    R ex[kQueue], ey[kQueue], ez[kQueue];
+};
+template <class R, bool REC> struct RayQueue : QueueEntry<R, REC> {
+    R px[kQueue], py[kQueue], pz[kQueue], kx[kQueue], ky[kQueue], kz[kQueue], dist[kQueue];
+    double E[kQueue], sa[kQueue];
+    uint64_t id[kQueue];
+    float saf[kQueue], caf[kQueue];
+    uint32_t nev[kQueue], nrefl[kQueue];
+
+    // f(array, field) for every field of a ray
+    template <class F> __device__ __forceinline__ void fields(Ray<R, REC> &r, F f) {
+        f(px, r.p.x); f(py, r.p.y); f(pz, r.p.z);
+        f(kx, r.k.x); f(ky, r.k.y); f(kz, r.k.z);
+        f(dist, r.dist); f(E, r.E); f(sa, r.sa); f(id, r.id); f(saf, r.saf); f(caf, r.caf);
+        f(nev, r.nev); f(nrefl, r.nrefl);
+        if constexpr (REC) {
+            f(this->ex, r.entry.x); f(this->ey, r.entry.y); f(this->ez, r.entry.z);
+        }
+    }
+    __device__ __forceinline__ void put(uint32_t i, Ray<R, REC> &r) {
+        fields(r, [&](auto *a, auto &v) { a[i] = v; });
+    }
+    __device__ __forceinline__ void take(uint32_t i, Ray<R, REC> &r) {
+        fields(r, [&](auto *a, auto &v) { v = a[i]; });
+    }
+    // After a batch: lanes with `parked` set take back their ray from slot
+    // `lane` while lanes with `queue` set store their candidate `r` at slot
+    // `rank`, field by field, all lanes' reads of a field before any write
+    // of it.  Only one field of the parked ray is held beside the
+    // candidate at a time.
+    __device__ __forceinline__ void unpark(uint32_t lane, bool parked, bool queue, uint32_t rank,
+                                           Ray<R, REC> &r) {
+        fields(r, [&](auto *a, auto &v) {
+            const auto t = a[lane];
+            wave_sync();
+            if (queue) a[rank] = v;
+            v = parked ? t : v;
+        });
+    }
+};
 
 // A kind template argument of kAny means: read the kind from the parameter
 // block at run time (one wave always traces rays of one parameter block, so
@@ -621,20 +679,24 @@ __device__ __forceinline__ void flush(const TraceParams &P, WaveCounts &c) {
 }
 
 // ---------------------------------------------------------------------------
-// The persistent ray loop of one wave.  Lanes whose ray has ended are
-// refilled with new ray ids from the wave's current chunk [next, end), which
-// `claim(next, end)` renews (false when no rays are left); rays that miss the
-// crystal are counted and retired inside the refill (where the FP32-mixed
-// kernels also do the detector and record work of the rays that ended).  Events run until
-// refill_at lanes are idle, then the wave refills; once the rays run out the
-// remaining lanes drain.  The wave's counters (64-bit, in scalar registers)
-// are added to P.dev_counters once, at the end: flushing them at every chunk
-// claim put nine atomics on the same nine addresses per chunk, which
-// throttled workloads whose chunks go fast (most rays missing).
+// The persistent ray loop of one wave.  Lanes whose ray has ended take rays
+// from the wave's queue `q` (RayQueue).  When the queue is empty, all 64
+// lanes start the next 64 ray ids of the wave's current chunk [next, end) at
+// once, which `claim(next, end)` renews (false when no rays are left); rays
+// that miss the crystal are counted and retired there, and those that enter
+// are queued.  So starting a ray costs one lane of a full-width batch, and
+// the lanes that take queued rays are never left idle by misses.  Events run
+// until refill_at lanes are idle, then the wave refills; once the rays run
+// out the remaining lanes drain.  With the FP32-mixed kernels the detector
+// and record work of the rays that ended also runs at the refill.  The
+// wave's counters (64-bit, in scalar registers) are added to P.dev_counters
+// once, at the end: flushing them at every chunk claim put nine atomics on
+// the same nine addresses per chunk, which throttled workloads whose chunks
+// go fast (most rays missing).
 // ---------------------------------------------------------------------------
-template <class T, bool kDefer, class Claim>
+template <class T, bool kDefer, class Claim, class Q>
 __device__ __forceinline__ void trace_loop(const TraceParams &P, const double *lut,
-                                           const double *cdf, Claim &claim) {
+                                           const double *cdf, Claim &claim, Q &q) {
     typename T::RayT ry;
     bool active = false;
     bool pending = false;         // the lane's ray has ended and awaits finish()
@@ -642,7 +704,9 @@ __device__ __forceinline__ void trace_loop(const TraceParams &P, const double *l
     WaveCounts cnt{};
     uint64_t next = 0, end = 0;   // wave-uniform cursor of ray ids
     bool more = true;             // wave-uniform: unclaimed rays remain
+    uint32_t head = 0, queued = 0;   // wave-uniform: the queue holds [head, head + queued)
     const uint32_t refill_at = P.refill_idle < 1u ? 1u : (P.refill_idle > 64u ? 64u : P.refill_idle);
+    const uint32_t lane = __lane_id();
 
     // kDefer: the detector and record work of an ended ray waits for the
     // next refill, where it runs for all the rays that ended since, rather
@@ -656,37 +720,54 @@ __device__ __forceinline__ void trace_loop(const TraceParams &P, const double *l
             }
             cnt.detected += popc(ballot(det));
         }
-        while (more) {
+        for (;;) {
             const uint64_t idle = ballot(!active);
             const uint32_t nidle = popc(idle);
             if (nidle == 0 || (nidle < refill_at && idle != ~0ull)) break;
-            if (next == end) {
-                if (!claim(next, end)) {
+            if (queued == 0) {
+                if (!more) break;
+                if (next == end && !claim(next, end)) {
                     more = false;
                     break;
                 }
+                const uint64_t avail = end - next;
+                const uint32_t width = avail < kQueue ? (uint32_t)avail : kQueue;
+                // the running rays wait in the empty queue while every lane
+                // starts a candidate in the same registers
+                if (active) q.put(lane, ry);
+                bool hit = false, missed = false;
+                if (lane < width) {
+                    hit = T::start(P, cdf, next + lane, ry);
+                    missed = !hit;
+                }
+                const uint64_t hits = ballot(hit);
+                q.unpark(lane, active, hit, lane_rank(hits), ry);
+                cnt.missed += popc(ballot(missed));
+                head = 0;
+                queued = popc(hits);
+                next += width;
+                wave_sync();
+                continue;
             }
-            const uint64_t avail = end - next;
-            const uint32_t take = avail < nidle ? (uint32_t)avail : nidle;
-            bool missed = false;
             if (!active) {
                 const uint32_t r = lane_rank(idle);
-                if (r < take) {
-                    active = T::start(P, cdf, next + r, ry);
-                    missed = !active;
+                if (r < queued) {
+                    q.take(head + r, ry);
+                    active = true;
                 }
             }
-            cnt.missed += popc(ballot(missed));
-            next += take;
+            const uint32_t take = queued < nidle ? queued : nidle;
+            head += take;
+            queued -= take;
         }
         const uint64_t act0 = ballot(active);
         if (act0 == 0) {
-            if (!more) break;
+            if (!more && queued == 0) break;
             continue;
         }
 
         // refill_at is in [1, 64], so keep is at least 1
-        const uint32_t keep = more ? 65u - refill_at : 1u;
+        const uint32_t keep = more || queued ? 65u - refill_at : 1u;
         for (;;) {
             bool reflected = false, refined = false;
             int status = -1;
@@ -750,11 +831,11 @@ struct RangeClaim {
 // wave operation, so the compiler cannot split the wave across the
 // back-edge (the counter flush that ends trace_loop is lane-0-only).
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, class Q>
 __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slots,
                                             const ServeItem *__restrict__ items, uint32_t n_items,
                                             uint64_t total, unsigned long long *__restrict__ cursors,
-                                            uint32_t wave, uint32_t n_waves) {
+                                            uint32_t wave, uint32_t n_waves, Q &q) {
     if (n_items == 0 || n_waves == 0) return;
     // first item: the last one whose start is at or before the position
     const uint64_t pos = (uint64_t)wave * total / n_waves;
@@ -769,7 +850,7 @@ __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slot
         const ServeItem it = items[i];
         const TraceParams &P = slots[it.slot];
         RangeClaim claim{&cursors[i], it.first, it.count, it.chunk};
-        trace_loop<T, false>(P, P.lut, P.bin_cdf, claim);
+        trace_loop<T, false>(P, P.lut, P.bin_cdf, claim, q);
     }
 }
 
@@ -792,10 +873,13 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
     using T = Tracer<R, GEOM, MDF, IRC, REC>;
     const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
     RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
+    // one ray queue per wave (at most 4 waves per workgroup)
+    __shared__ RayQueue<R, REC> queues[4];
+    RayQueue<R, REC> &q = queues[uniform(threadIdx.x >> 6)];
     // The FP32-mixed kernels defer the ended rays' detector and record work to
     // the refill (2-16% faster).  The FP64 kernels finish at once: deferring
     // raised their scalar-register spills from 2 to ~40-60 and cost 2-9%.
-    trace_loop<T, !T::kF64>(Q, Q.lut, Q.bin_cdf, claim);
+    trace_loop<T, !T::kF64>(Q, Q.lut, Q.bin_cdf, claim, q);
 }
 
 }  // namespace tk

@@ -28,6 +28,9 @@ uint64_t simt_ballot(bool p);
 uint32_t simt_readfirstlane(uint32_t v);
 int simt_lane();
 inline void __syncthreads() {}
+// wave-level memory ordering: a meeting point of the wave's lanes
+inline void __builtin_amdgcn_wave_barrier() { (void)simt_readfirstlane(0); }
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
 
 inline uint64_t __ballot(int p) { return simt_ballot(p != 0); }
 inline int __lane_id() { return simt_lane(); }

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <functional>
 #include <vector>
 
@@ -126,19 +127,28 @@ namespace {
 using namespace mrt;
 using namespace mrt::tk;
 
+// `queue` is the wave's LDS ray queue: memory shared by the wave's lanes.
 template <class R>
 void serve_body(const TraceParams *slots, const ServeItem *items, uint32_t n, uint64_t total,
-                unsigned long long *cursors, uint32_t wave, uint32_t n_waves) {
+                unsigned long long *cursors, uint32_t wave, uint32_t n_waves, void *queue) {
     // the serving kernel's body, with the wave index it would compute
-    serve_waves<Tracer<R, kAny, kAny, kAny, false>>(slots, items, n, total, cursors, wave, n_waves);
+    serve_waves<Tracer<R, kAny, kAny, kAny, false>>(slots, items, n, total, cursors, wave, n_waves,
+                                                    *(RayQueue<R, false> *)queue);
 }
 
 template <class R, bool REC>
-void trace_body(const TraceParams &P) {
+void trace_body(const TraceParams &P, void *queue) {
     using T = Tracer<R, kAny, kAny, kAny, REC>;
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
-    trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim);
+    trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(RayQueue<R, REC> *)queue);
 }
+
+// Room for any RayQueue, filled with a byte pattern so that a read of an
+// entry no lane has written shows up as garbage.
+struct QueueMem {
+    alignas(64) unsigned char b[sizeof(RayQueue<double, true>)];
+    QueueMem() { memset(b, 0xA5, sizeof b); }
+};
 }  // namespace
 
 extern "C" {
@@ -190,11 +200,12 @@ int emu_serve(const TraceParams *slots, const ServeItem *items, uint32_t n, int 
     for (uint32_t i = 0; i < n; ++i) total += items[i].count;
     std::vector<unsigned long long> cursors(n ? n : 1, 0ull);
     for (int w = 0; w < n_waves; ++w) {
+        QueueMem q;
         int e = run_wave([&] {
             if (precision == MRT_FP64)
-                serve_body<double>(slots, items, n, total, cursors.data(), (uint32_t)w, (uint32_t)n_waves);
+                serve_body<double>(slots, items, n, total, cursors.data(), (uint32_t)w, (uint32_t)n_waves, q.b);
             else
-                serve_body<float>(slots, items, n, total, cursors.data(), (uint32_t)w, (uint32_t)n_waves);
+                serve_body<float>(slots, items, n, total, cursors.data(), (uint32_t)w, (uint32_t)n_waves, q.b);
         }, max_meetings);
         if (e) return e;
     }
@@ -205,10 +216,11 @@ int emu_serve(const TraceParams *slots, const ServeItem *items, uint32_t n, int 
 // n_waves waves; P's buffers and counters are host memory.
 int emu_trace(TraceParams *P, int n_waves, int precision, long long max_meetings) {
     for (int w = 0; w < n_waves; ++w) {
+        QueueMem q;
         int e = run_wave([&] {
             const bool rec = P->records_mode != MRT_RECORDS_NONE;
-            if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P); else trace_body<double, false>(*P); }
-            else { if (rec) trace_body<float, true>(*P); else trace_body<float, false>(*P); }
+            if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P, q.b); else trace_body<double, false>(*P, q.b); }
+            else { if (rec) trace_body<float, true>(*P, q.b); else trace_body<float, false>(*P, q.b); }
         }, max_meetings);
         if (e) return e;
     }

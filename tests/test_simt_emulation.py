@@ -134,3 +134,28 @@ def test_served_mix_equals_requests_alone(emu, precision):
         assert np.array_equal(a.counts, b.counts), (w["name"], n)
         assert np.array_equal(a.energy, b.energy), (w["name"], n)
         assert a.counters() == b.counters(), (w["name"], n)
+
+
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
+def test_schedule_does_not_change_results(emu, precision):
+    """The wave's schedule (idle lanes that trigger a refill, chunk size,
+    number of waves) decides which lanes and which batches of candidate rays
+    carry each ray, never its result: images and counters are identical for
+    refill thresholds 1..64 and chunks that are not multiples of the 64-ray
+    batch (ragged batches at every chunk end)."""
+    prec = mrt.PRECISION[precision]
+    for w, n, s in _jobs()[:6]:
+        ref = None
+        for chunk, refill, waves in ((64, 16, WAVES), (100, 1, 3), (37, 4, 5), (2048, 64, 2),
+                                     (130, 63, WAVES)):
+            j = Job(emu, w, n, s)
+            emu.emu_set_run(j.P, 0, n, s, 0, j.counts.ctypes.data, j.energy.ctypes.data,
+                            j.cnt.ctypes.data, chunk, refill)
+            assert emu.emu_trace(j.P, waves, prec, MAX_MEETINGS) == 0, (w["name"], chunk, refill)
+            got = (j.counts.copy(), j.energy.copy(), j.counters())
+            if ref is None:
+                ref = got
+                continue
+            assert np.array_equal(ref[0], got[0]), (w["name"], chunk, refill)
+            assert np.array_equal(ref[1], got[1]), (w["name"], chunk, refill)
+            assert ref[2] == got[2], (w["name"], chunk, refill)
