@@ -876,10 +876,11 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
     // one ray queue per wave (at most 4 waves per workgroup)
     __shared__ RayQueue<R, REC> queues[4];
     RayQueue<R, REC> &q = queues[uniform(threadIdx.x >> 6)];
-    // The FP32-mixed kernels defer the ended rays' detector and record work to
-    // the refill (2-16% faster).  The FP64 kernels finish at once: deferring
-    // raised their scalar-register spills from 2 to ~40-60 and cost 2-9%.
-    trace_loop<T, !T::kF64>(Q, Q.lut, Q.bin_cdf, claim, q);
+    // The kernels defer the ended rays' detector and record work to the
+    // refill, except the FP64 cylinder (von Hamos) kernels, which were 4%
+    // slower with it (FP32-mixed: 2-16% faster; FP64 flat: 8-10% faster).
+    constexpr bool kDefer = !T::kF64 || GEOM == MRT_GEOMETRY_FLAT;
+    trace_loop<T, kDefer>(Q, Q.lut, Q.bin_cdf, claim, q);
 }
 
 }  // namespace tk
