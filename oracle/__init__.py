@@ -23,6 +23,7 @@ _GEOM = {"flat": 0, "cylinder": 1}
 _MDF = {"gaussian_vmf": 0, "lorentzian": 1, "pseudo_voigt": 2, "wrapped_lorentzian": 3,
         "spherical_wrapped_lorentzian": 4}
 _IRC = {"gaussian": 0, "pseudo_voigt": 1, "table": 2, "lorentzian": 3, "box": 4}
+_MODEL = {"stepping": 0, "mwg": 1}
 
 D3 = C.c_double * 3
 D8 = C.c_double * 8
@@ -56,6 +57,19 @@ class Irc(C.Structure):
                 ("shift", C.c_double), ("fwhm", C.c_double), ("fwhm_g", C.c_double),
                 ("fwhm_l", C.c_double), ("x_min", C.c_double), ("x_max", C.c_double),
                 ("table", C.POINTER(C.c_double))]
+
+
+class Model(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("burn_in", C.c_int32), ("psi_nodes", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+def model_of(w):
+    """The event model of a workload: w["event_model"] = {"kind": "mwg",
+    "burn_in": B, "psi_nodes": M}, or absent (null-collision stepping)."""
+    e = w.get("event_model") or {"kind": "stepping"}
+    return Model(kind=_MODEL[e["kind"]], burn_in=int(e.get("burn_in", 500)),
+                 psi_nodes=int(e.get("psi_nodes", 256)))
 
 
 class Detector(C.Structure):
@@ -104,6 +118,29 @@ def lib():
                                 C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
                                 C.c_void_p, C.c_void_p, C.c_void_p, P(Counters), C.c_void_p,
                                 C.c_int]
+        L.orc_trace_model.restype = C.c_int
+        L.orc_trace_model.argtypes = [P(Source), P(Crystal), P(Mosaic), P(Irc), P(Detector),
+                                      P(Model), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, P(Counters),
+                                      C.c_void_p, C.c_int]
+        L.orc_trace_ids_model.restype = C.c_int
+        L.orc_trace_ids_model.argtypes = [P(Source), P(Crystal), P(Mosaic), P(Irc),
+                                          P(Detector), P(Model), C.c_void_p, C.c_uint64,
+                                          C.c_uint64, C.c_uint32, C.c_void_p, C.c_void_p,
+                                          C.c_int]
+        L.orc_mdf_density.restype = C.c_double
+        L.orc_mdf_density.argtypes = [P(Mosaic), C.c_double]
+        L.orc_psi_integral.restype = C.c_double
+        L.orc_psi_integral.argtypes = [P(Mosaic), C.c_double, C.c_double, C.c_int]
+        L.orc_irc_integral.restype = C.c_double
+        L.orc_irc_integral.argtypes = [P(Irc)]
+        L.orc_irc_width.restype = C.c_double
+        L.orc_irc_width.argtypes = [P(Irc)]
+        L.orc_mwg_sample.argtypes = [P(Mosaic), P(Irc), C.c_double, C.c_double, C.c_uint64,
+                                     C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_double,
+                                     P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.orc_crystallite.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_double,
+                                      C.c_double, P(C.c_double)]
         L.orc_trace_ids.restype = C.c_int
         L.orc_trace_ids.argtypes = [P(Source), P(Crystal), P(Mosaic), P(Irc), P(Detector),
                                     C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint32,
@@ -183,8 +220,10 @@ def trace(w, first=0, n=None, seed=None, max_events=0, images=True, records=Fals
     mg = np.zeros(n, np.float64) if margins else None
     cnt = Counters()
     ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
-    rc = lib().orc_trace(*S.args(), first, n, seed, max_events, ptr(counts), ptr(energy),
-                         ptr(recs), C.byref(cnt), ptr(mg), threads)
+    model = model_of(w)
+    rc = lib().orc_trace_model(*S.args(), C.byref(model), first, n, seed, max_events,
+                               ptr(counts), ptr(energy), ptr(recs), C.byref(cnt), ptr(mg),
+                               threads)
     if rc != 0:
         raise ValueError(f"oracle rejected the workload (code {rc})")
     out["counters"] = {f: getattr(cnt, f) for f, _ in Counters._fields_}
@@ -204,9 +243,10 @@ def trace_ids(w, ids, seed=None, max_events=0, threads=0):
     S = Structs(w)
     recs = np.zeros(len(ids), RECORD_DTYPE)
     mg = np.zeros(len(ids), np.float64)
-    rc = lib().orc_trace_ids(*S.args(), ids.ctypes.data_as(C.c_void_p), len(ids), seed,
-                             max_events, recs.ctypes.data_as(C.c_void_p),
-                             mg.ctypes.data_as(C.c_void_p), threads)
+    model = model_of(w)
+    rc = lib().orc_trace_ids_model(*S.args(), C.byref(model), ids.ctypes.data_as(C.c_void_p),
+                                   len(ids), seed, max_events, recs.ctypes.data_as(C.c_void_p),
+                                   mg.ctypes.data_as(C.c_void_p), threads)
     if rc != 0:
         raise ValueError(f"oracle rejected the workload (code {rc})")
     return recs, mg
@@ -282,3 +322,63 @@ def source_sample(w, ray_ids, seed=None):
 def exit_distance(w, p, k):
     S = Structs(w)
     return lib().orc_exit_distance(C.byref(S.cr), _d3(p), _d3(k))
+
+
+# ---- the paper's event model: pieces for unit pins -------------------------
+
+def _mosaic(mosaic):
+    return Mosaic(kind=_MDF[mosaic["kind"]], fwhm=mosaic["fwhm"], eta=mosaic.get("eta", 0.0))
+
+
+def _irc(rocking_curve):
+    r = rocking_curve
+    tab = np.ascontiguousarray(r.get("table", [0.0]), dtype=np.float64)
+    irc = Irc(kind=_IRC[r["kind"]], peak=r.get("peak", 0.0), shift=r.get("shift", 0.0),
+              fwhm=r.get("fwhm", 0.0), fwhm_g=r.get("fwhm_g", 0.0), fwhm_l=r.get("fwhm_l", 0.0),
+              x_min=r.get("x_min", 0.0), x_max=r.get("x_max", 0.0))
+    irc.n_table = len(tab) if r["kind"] == "table" else 0
+    irc.table = tab.ctypes.data_as(C.POINTER(C.c_double))
+    return irc, tab
+
+
+def mdf_density(mosaic, v):
+    """Mosaic density per steradian at v = 1 - cos(theta)."""
+    m = _mosaic(mosaic)
+    vs = np.atleast_1d(np.asarray(v, np.float64))
+    return np.array([lib().orc_mdf_density(C.byref(m), float(x)) for x in vs])
+
+
+def psi_integral(mosaic, alpha, beta, nodes=256):
+    m = _mosaic(mosaic)
+    return lib().orc_psi_integral(C.byref(m), float(alpha), float(beta), int(nodes))
+
+
+def irc_integral(rocking_curve):
+    irc, _tab = _irc(rocking_curve)
+    return lib().orc_irc_integral(C.byref(irc))
+
+
+def irc_width(rocking_curve):
+    irc, _tab = _irc(rocking_curve)
+    return lib().orc_irc_width(C.byref(irc))
+
+
+def mwg_sample(mosaic, rocking_curve, w_psi, w_delta, seed, rays, event, burn_in, alpha, ab):
+    """(psi, Delta) drawn by the sampler for each ray id in `rays`."""
+    m = _mosaic(mosaic)
+    irc, _tab = _irc(rocking_curve)
+    rays = np.atleast_1d(np.asarray(rays, np.uint64))
+    out = np.zeros((len(rays), 2))
+    ps, de = C.c_double(), C.c_double()
+    for i, r in enumerate(rays):
+        lib().orc_mwg_sample(C.byref(m), C.byref(irc), float(w_psi), float(w_delta), int(seed),
+                             int(r), int(event), int(burn_in), float(alpha), float(ab),
+                             C.byref(ps), C.byref(de), None)
+        out[i] = ps.value, de.value
+    return out
+
+
+def crystallite(N, k, alpha, b, psi):
+    n = D3()
+    lib().orc_crystallite(_d3(N), _d3(k), float(alpha), float(b), float(psi), n)
+    return np.array(list(n))

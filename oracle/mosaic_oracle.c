@@ -6,10 +6,13 @@
  * the benchmark.  It shares nothing with the GPU library but the written
  * model it follows; each function names the part of the paper it restates.
  *
- * The paper draws a free path from exp(-(mu0 + gamma0 sigma) l) (sec. 2.2.3,
- * Eq. AnyEvent), absorbs with probability mu0 / mu_eff, and otherwise samples
- * the reflecting crystallite from the integrand of Eq. ReflXsection.  Here
- * the same law is realised by null-collision (Woodcock) stepping: candidate
+ * Two event models.  The paper's own (sec. 2.2.3, 2.2.4; mwg_events): a free
+ * path from exp(-(mu0 + gamma0 sigma) l) (Eq. AnyEvent) with gamma0 sigma from
+ * Eq. SimpleReflXsection, absorption with probability mu0 / mu_eff, and
+ * otherwise a reflecting crystallite sampled from the integrand of Eq.
+ * ReflXsection by Metropolis-within-Gibbs.  The default realises the same
+ * law without the approximation of Eq. SimpleReflXsection and without a
+ * Markov chain, by null-collision (Woodcock) stepping: candidate
  * crystallite encounters arrive at a majorant rate lambda_c = R_max / h, each
  * draws a crystallite normal from the mosaic distribution on the unit sphere
  * (sec. 2.2.2) and reflects with probability r(Delta - Delta_M) / R_max,
@@ -462,6 +465,207 @@ static void local_frame(const orc_crystal *c, const double p[3],
     cross(N, e1, e2);
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* The paper's own event model (sec. 2.2.3, 2.2.4): free paths at the rate  */
+/* mu0 + gamma0 sigma(alpha) of Eq. AnyEvent with gamma0 sigma from Eq.     */
+/* SimpleReflXsection, absorption with probability mu0 / mu_eff, otherwise  */
+/* a reflection off a crystallite whose (psi, Delta) is drawn by a          */
+/* Metropolis-within-Gibbs sampler from the integrand of Eq. ReflXsection.  */
+/* The reflection strength is the one the stepping model uses: Q R(Delta) = */
+/* r(Delta - Delta_M) / h, the per-encounter reflection probability over    */
+/* the mean path between encounters, with the polarisation factor folded    */
+/* into r's peak, so the two models agree up to the approximation of Eq.    */
+/* SimpleReflXsection (an IRC much narrower than the mosaic).              */
+/* ------------------------------------------------------------------------ */
+
+/* Sphere densities of the mosaic distributions (sec. 2.2.2) per steradian,
+   normalised over the sphere, as functions of v = 1 - cos(theta). */
+static double vmf_density(double gamma, double v) {
+    /* Eq. MF: proportional to exp(cos(theta) / s^2) */
+    double s = gamma / (2.0 * sqrt(2.0 * log(2.0)));
+    double kappa = 1.0 / (s * s);
+    return kappa * exp(-kappa * v) / (ORC_TWO_PI * -expm1(-2.0 * kappa));
+}
+
+static double cauchy_density(double gamma, double v) {
+    /* the bivariate Cauchy tilt of lorentz_tilt: planar density
+       g / (2 pi (g^2 + T^2)^(3/2)) at T = tan(theta), times the gnomonic
+       area ratio 1 / cos^3(theta); zero on the far hemisphere */
+    double c = 1.0 - v;
+    if (!(c > 0.0)) return 0.0;
+    double g = gamma / 2.0;
+    double q = v * (2.0 - v) + g * g * c * c;   /* sin^2 + g^2 cos^2 */
+    return g / (ORC_TWO_PI * q * sqrt(q));
+}
+
+double orc_mdf_density(const orc_mosaic *m, double v) {
+    double gamma = m->fwhm;
+    switch (m->kind) {
+    case ORC_MDF_VMF:
+        return vmf_density(gamma, v);
+    case ORC_MDF_LORENTZ:
+        return cauchy_density(gamma, v);
+    case ORC_MDF_PVOIGT:
+        return m->eta * cauchy_density(gamma, v) + (1.0 - m->eta) * vmf_density(gamma, v);
+    case ORC_MDF_WRAPPED_LORENTZ: {
+        /* Eq. WL: proportional to 1 / (g^2 + 2 v), v in [0, 2] */
+        double g = gamma / 2.0;
+        double Z = log((g * g + 4.0) / (g * g));
+        return 1.0 / (ORC_PI * Z * (g * g + 2.0 * v));
+    }
+    case ORC_MDF_SPHERICAL_WRAPPED_LORENTZ: {
+        /* Eq. SWL: proportional to 1 / (cosh(Gamma/2) - 1 + v)^2, with
+           cosh(Gamma/2) - 1 = 2 sinh^2(Gamma/4) free of cancellation */
+        double sh = sinh(gamma / 4.0);
+        double A = 2.0 * sh * sh;
+        return A * (A + 2.0) / (2.0 * ORC_TWO_PI * (A + v) * (A + v));
+    }
+    }
+    return 0.0;
+}
+
+/* v = 1 - cos(theta(alpha, psi, beta)) of Eq. ThetaPsi, written without
+   cancellation: 2 sin^2((alpha - beta)/2) + 2 cos(alpha) cos(beta) sin^2(psi/2). */
+static double theta_v(double alpha, double beta, double psi) {
+    double a = sin((alpha - beta) / 2.0), b = sin(psi / 2.0);
+    return 2.0 * a * a + 2.0 * cos(alpha) * cos(beta) * b * b;
+}
+
+/* The psi integral of Eq. SimpleReflXsection, int W(theta(alpha, psi, beta))
+   dpsi over [-pi, pi], by the trapezoid rule on the nodes
+   psi_j = pi (j / M)^3, j = 0..M, dense near psi = 0 where the integrand
+   peaks; the integrand is even in psi. */
+double orc_psi_integral(const orc_mosaic *m, double alpha, double beta, int M) {
+    double a = sin((alpha - beta) / 2.0);
+    double v0 = 2.0 * a * a, cc = 2.0 * cos(alpha) * cos(beta);
+    double prev_psi = 0.0, prev_f = orc_mdf_density(m, v0), sum = 0.0;
+    for (int j = 1; j <= M; ++j) {
+        double t = (double)j / (double)M;
+        double psi = ORC_PI * t * t * t;
+        double b = sin(psi / 2.0);
+        double f = orc_mdf_density(m, v0 + cc * b * b);
+        sum += (psi - prev_psi) * (prev_f + f) / 2.0;
+        prev_psi = psi;
+        prev_f = f;
+    }
+    return 2.0 * sum;
+}
+
+/* int r(x) dx over the whole curve (closed forms; the table by the
+   trapezoid rule, exact for its linear interpolation). */
+double orc_irc_integral(const orc_irc *irc) {
+    switch (irc->kind) {
+    case ORC_IRC_GAUSS:
+        return irc->peak * irc->fwhm * sqrt(ORC_PI / (4.0 * log(2.0)));
+    case ORC_IRC_PVOIGT: {
+        double w, eta;
+        orc_pvoigt_params(irc->fwhm_g, irc->fwhm_l, &w, &eta);
+        return irc->peak / (eta * lorentz_unit(0.0, w) + (1.0 - eta) * gauss_unit(0.0, w));
+    }
+    case ORC_IRC_TABLE: {
+        int n = irc->n_table;
+        double sum = 0.0;
+        for (int j = 0; j + 1 < n; ++j) sum += (irc->table[j] + irc->table[j + 1]) / 2.0;
+        return sum * (irc->x_max - irc->x_min) / (double)(n - 1);
+    }
+    case ORC_IRC_LORENTZ:
+        return irc->peak * ORC_PI * irc->fwhm / 2.0;
+    case ORC_IRC_BOX:
+        return irc->peak * irc->fwhm;
+    }
+    return 0.0;
+}
+
+/* Step width of the sampler's Delta proposals: the IRC's full width at half
+   maximum (for the table, the span of its nodes at or above half its
+   maximum). */
+double orc_irc_width(const orc_irc *irc) {
+    switch (irc->kind) {
+    case ORC_IRC_PVOIGT: {
+        double w, eta;
+        orc_pvoigt_params(irc->fwhm_g, irc->fwhm_l, &w, &eta);
+        return w;
+    }
+    case ORC_IRC_TABLE: {
+        double mx = irc_max(irc);
+        int cnt = 0;
+        for (int j = 0; j < irc->n_table; ++j) cnt += irc->table[j] >= mx / 2.0;
+        return (double)cnt * (irc->x_max - irc->x_min) / (double)(irc->n_table - 1);
+    }
+    default:
+        return irc->fwhm;
+    }
+}
+
+/* Integrand of Eq. ReflXsection in (psi, Delta) up to a constant: the
+   target of the sampler.  ab = alpha_B; b = alpha_B + Delta is the angle of
+   incidence on the crystallite. */
+static double mwg_target(const orc_mosaic *m, const orc_irc *irc, double alpha, double ab,
+                         double psi, double delta) {
+    double r = orc_irc_value(irc, delta - irc->shift);
+    if (!(r > 0.0)) return 0.0;
+    double b = ab + delta;
+    return r * cos(b) * orc_mdf_density(m, theta_v(alpha, b, psi));
+}
+
+/* Metropolis-within-Gibbs draw of (psi, Delta) (sec. 2.2.4): from
+   (0, Delta_M), `burn_in` sweeps, each a psi move and then a Delta move,
+   both symmetric uniform random walks (half-widths w_psi and w_delta); a
+   move is taken when u f(current) < f(proposed), or from a point of zero
+   density; Delta outside [-alpha_B, pi/2 - alpha_B] is rejected; psi wraps
+   on [-pi, pi).  Sweep s of event e uses the Philox words of counter
+   (s, ray, 2^31 + e). */
+void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
+                    uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
+                    double alpha, double ab, double *psi_out, double *delta_out,
+                    double *margin) {
+    double lo = -ab, hi = ORC_PI / 2.0 - ab;
+    double psi = 0.0, delta = irc->shift;
+    if (delta < lo) delta = lo;
+    if (delta > hi) delta = hi;
+    double f = mwg_target(m, irc, alpha, ab, psi, delta);
+    for (int s = 0; s < burn_in; ++s) {
+        double u[4];
+        ray_words(seed, ray, 0x80000000u | event, (uint32_t)s, u);
+        double pn = psi + w_psi * (2.0 * u[0] - 1.0);
+        if (pn >= ORC_PI) pn -= ORC_TWO_PI;
+        else if (pn < -ORC_PI) pn += ORC_TWO_PI;
+        double fn = mwg_target(m, irc, alpha, ab, pn, delta);
+        if (margin && f > 0.0 && fn > 0.0) note(margin, (fn - u[1] * f) / fmax(fn, u[1] * f));
+        if (u[1] * f < fn || f == 0.0) {
+            psi = pn;
+            f = fn;
+        }
+        double dn = delta + w_delta * (2.0 * u[2] - 1.0);
+        if (dn >= lo && dn <= hi) {
+            fn = mwg_target(m, irc, alpha, ab, psi, dn);
+            if (margin && f > 0.0 && fn > 0.0) note(margin, (fn - u[3] * f) / fmax(fn, u[3] * f));
+            if (u[3] * f < fn || f == 0.0) {
+                delta = dn;
+                f = fn;
+            }
+        }
+    }
+    *psi_out = psi;
+    *delta_out = delta;
+}
+
+/* Crystallite normal for glancing angle alpha on the planes of normal N
+   (sin(alpha) = -k.N), angle of incidence b on the crystallite and
+   rotation psi about the ray (sec. 2.2.2): N rotated by alpha - b about
+   N x k, then by psi about k (Rodrigues' formula both times). */
+void orc_crystallite(const double N[3], const double k[3], double alpha, double b,
+                     double psi, double n[3]) {
+    double th = alpha - b, ca = cos(alpha), sa = sin(alpha);
+    double n0[3], kx[3];
+    for (int i = 0; i < 3; ++i)   /* (k + sin(alpha) N) / cos(alpha) is the unit (N x k) x N */
+        n0[i] = ca > 0.0 ? cos(th) * N[i] + sin(th) * (k[i] + sa * N[i]) / ca : N[i];
+    cross(k, n0, kx);
+    double kn0 = dot(k, n0), cp = cos(psi), sp = sin(psi);
+    for (int i = 0; i < 3; ++i) n[i] = cp * n0[i] + sp * kx[i] + (1.0 - cp) * kn0 * k[i];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Detector (sec. 2.3): a rectangle of nx x ny square pixels.                */
 /* ------------------------------------------------------------------------ */
@@ -499,12 +703,24 @@ typedef struct trace_ctx {
     uint64_t seed;
     uint32_t max_events;
     double r_max, mu_tot, p_a;
+    /* the paper's event model */
+    int mwg;                 /* 1: event model of sec. 2.2.3-2.2.4 */
+    int burn_in, psi_nodes;
+    double q;                /* int r dx / h */
+    double w_delta;          /* sampler step in Delta */
 } trace_ctx;
 
 static void ctx_init(trace_ctx *X, const orc_source *s, const orc_crystal *c,
                      const orc_mosaic *m, const orc_irc *irc, const orc_detector *d,
-                     uint64_t seed, uint32_t max_events) {
+                     const orc_model *model, uint64_t seed, uint32_t max_events) {
     memset(X, 0, sizeof(*X));
+    if (model && model->kind == ORC_MODEL_MWG) {
+        X->mwg = 1;
+        X->burn_in = model->burn_in;
+        X->psi_nodes = model->psi_nodes;
+        X->q = orc_irc_integral(irc) / c->mfp;
+        X->w_delta = orc_irc_width(irc);
+    }
     X->s = s; X->c = c; X->m = m; X->irc = irc; X->d = d;
     X->seed = seed;
     X->max_events = max_events ? max_events : (1u << 20);
@@ -515,6 +731,71 @@ static void ctx_init(trace_ctx *X, const orc_source *s, const orc_crystal *c,
     double lambda_c = X->r_max / c->mfp;
     X->mu_tot = c->mu0 + lambda_c;
     X->p_a = X->mu_tot > 0.0 ? c->mu0 / X->mu_tot : 1.0;
+}
+
+
+/* Events of one ray in the paper's model (sec. 2.2.3, 2.2.4).  Event i draws
+   (u0, u1, u2) = the Philox words of counter (i, ray, 1): the free path
+   -ln(u0) / mu_eff with mu_eff = mu0 + gamma0 sigma_H(alpha) +
+   gamma0 sigma_anti-H(-alpha) at the event's start point (sin(alpha) =
+   -k.N there; the normal is held along the path, the paper's assumption),
+   exit when the path reaches the boundary, absorption when
+   u1 <= mu0 / mu_eff, otherwise a reflection off the H planes (normal N)
+   when u2 sigma < sigma_H, else off the anti-H planes (normal -N). */
+static void mwg_events(const trace_ctx *X, uint64_t ray, double alpha_b, double p[3],
+                       double k[3], uint32_t *n_ev, uint32_t *n_rf, int *status, double *m) {
+    const orc_crystal *c = X->c;
+    uint32_t n_events = 0, n_refl = 0;
+    double beta = alpha_b + X->irc->shift, cos_beta = cos(beta);
+    double cb = cos_beta > 0.05 ? cos_beta : 0.05;
+    double w_psi = X->m->fwhm / cb;
+    for (;;) {
+        if (n_events == X->max_events) { *status = ORC_TRUNCATED; break; }
+        double u[4];
+        ray_words(X->seed, ray, 1, n_events, u);
+        uint32_t event = n_events++;
+        double dist = exit_distance(c, &X->E, p, k);
+        double N[3], e1[3], e2[3];
+        local_frame(c, p, N, e1, e2);
+        double sn = -dot(k, N);
+        if (sn > 1.0) sn = 1.0;
+        if (sn < -1.0) sn = -1.0;
+        double alpha = asin(sn);
+        double sig_h = 0.0, sig_a = 0.0;
+        if (alpha_b >= 0.0 && (int)n_refl < c->max_refl) {
+            sig_h = X->q * cos_beta * orc_psi_integral(X->m, alpha, beta, X->psi_nodes);
+            sig_a = X->q * cos_beta * orc_psi_integral(X->m, -alpha, beta, X->psi_nodes);
+        }
+        double mu = c->mu0 + sig_h + sig_a;
+        double l = -log(u[0]) / mu;
+        note(m, (l - dist) / fmax(l, dist));
+        if (l >= dist) {
+            axpy(p, dist, k, p);
+            *status = n_refl ? ORC_EXIT_REFLECTED : ORC_EXIT_TRANSMITTED;
+            break;
+        }
+        axpy(p, l, k, p);
+        double pa = c->mu0 / mu;
+        note(m, u[1] - pa);
+        if (u[1] <= pa) { *status = ORC_ABSORBED; break; }
+        double sig = sig_h + sig_a;
+        note(m, (sig_h - u[2] * sig) / sig);
+        int anti = !(u[2] * sig < sig_h);
+        double Ns[3];
+        for (int i = 0; i < 3; ++i) Ns[i] = anti ? -N[i] : N[i];
+        double as = anti ? -alpha : alpha;
+        double psi, delta, n[3], ks[3];
+        orc_mwg_sample(X->m, X->irc, w_psi, X->w_delta, X->seed, ray, event, X->burn_in, as,
+                       alpha_b, &psi, &delta, m);
+        orc_crystallite(Ns, k, as, alpha_b + delta, psi, n);
+        /* reflection equation of sec. 2.2.4 */
+        axpy(k, -2.0 * dot(k, n), n, ks);
+        double nr = sqrt(dot(ks, ks));
+        for (int i = 0; i < 3; ++i) k[i] = ks[i] / nr;
+        ++n_refl;
+    }
+    *n_ev = n_events;
+    *n_rf = n_refl;
 }
 
 static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double *margin) {
@@ -545,6 +826,10 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
     uint32_t n_events = 0, n_refl = 0;
     int status = ORC_TRUNCATED;
 
+    if (X->mwg) {
+        mwg_events(X, ray, alpha_b, p, k, &n_events, &n_refl, &status, &m);
+        goto finish;
+    }
     for (;;) {
         if (n_events == X->max_events) { status = ORC_TRUNCATED; break; }
         double u[4];
@@ -599,6 +884,7 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
         }
     }
 
+finish:
     rec->status = (uint8_t)status;
     rec->n_events = n_events;
     rec->n_refl = (uint16_t)n_refl;
@@ -664,8 +950,16 @@ static void *run_job(void *arg) {
 }
 
 static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
-                    const orc_irc *irc, const orc_detector *d) {
+                    const orc_irc *irc, const orc_detector *d, const orc_model *model,
+                    uint32_t max_events) {
     if (!s || !c || !m || !irc || !d) return -1;
+    if (model && model->kind == ORC_MODEL_MWG) {
+        if (!(m->fwhm > 0.0)) return -9;               /* W must be a density */
+        if (model->burn_in < 0 || model->psi_nodes < 1) return -10;
+        if (max_events > 0x7fffffffu) return -11;      /* sampler counter word */
+    } else if (model && model->kind != ORC_MODEL_STEPPING) {
+        return -12;
+    }
     if (c->mfp <= 0.0 || c->mu0 < 0.0 || c->thickness <= 0.0 || c->two_d <= 0.0) return -2;
     if (c->geometry == ORC_GEOM_CYLINDER && !(c->width / (2.0 * c->radius) < ORC_PI / 2.0)) return -3;
     if (m->fwhm < 0.0 || m->eta < 0.0 || m->eta > 1.0) return -4;
@@ -718,29 +1012,47 @@ static int run_threads(const trace_ctx *X, uint64_t first, uint64_t n, const uin
     return 0;
 }
 
+int orc_trace_model(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
+                    const orc_irc *irc, const orc_detector *d, const orc_model *model,
+                    uint64_t first, uint64_t n, uint64_t seed, uint32_t max_events,
+                    uint32_t *counts, uint64_t *energy_mev,
+                    orc_record *records, orc_counters *counters, double *margins,
+                    int n_threads) {
+    int e = validate(s, c, m, irc, d, model, max_events);
+    if (e) return e;
+    trace_ctx X;
+    ctx_init(&X, s, c, m, irc, d, model, seed, max_events);
+    return run_threads(&X, first, n, NULL, counts, energy_mev, records, counters, margins,
+                       n_threads);
+}
+
 int orc_trace(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
               const orc_irc *irc, const orc_detector *d,
               uint64_t first, uint64_t n, uint64_t seed, uint32_t max_events,
               uint32_t *counts, uint64_t *energy_mev,
               orc_record *records, orc_counters *counters, double *margins,
               int n_threads) {
-    int e = validate(s, c, m, irc, d);
+    return orc_trace_model(s, c, m, irc, d, NULL, first, n, seed, max_events, counts,
+                           energy_mev, records, counters, margins, n_threads);
+}
+
+int orc_trace_ids_model(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
+                        const orc_irc *irc, const orc_detector *d, const orc_model *model,
+                        const uint64_t *ids, uint64_t n, uint64_t seed, uint32_t max_events,
+                        orc_record *records, double *margins, int n_threads) {
+    int e = validate(s, c, m, irc, d, model, max_events);
     if (e) return e;
     trace_ctx X;
-    ctx_init(&X, s, c, m, irc, d, seed, max_events);
-    return run_threads(&X, first, n, NULL, counts, energy_mev, records, counters, margins,
-                       n_threads);
+    ctx_init(&X, s, c, m, irc, d, model, seed, max_events);
+    return run_threads(&X, 0, n, ids, NULL, NULL, records, NULL, margins, n_threads);
 }
 
 int orc_trace_ids(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
                   const orc_irc *irc, const orc_detector *d,
                   const uint64_t *ids, uint64_t n, uint64_t seed, uint32_t max_events,
                   orc_record *records, double *margins, int n_threads) {
-    int e = validate(s, c, m, irc, d);
-    if (e) return e;
-    trace_ctx X;
-    ctx_init(&X, s, c, m, irc, d, seed, max_events);
-    return run_threads(&X, 0, n, ids, NULL, NULL, records, NULL, margins, n_threads);
+    return orc_trace_ids_model(s, c, m, irc, d, NULL, ids, n, seed, max_events, records,
+                               margins, n_threads);
 }
 
 int orc_version(void) { return 1; }

@@ -36,6 +36,7 @@ enum { ORC_MDF_VMF = 0, ORC_MDF_LORENTZ = 1, ORC_MDF_PVOIGT = 2,
        ORC_MDF_WRAPPED_LORENTZ = 3, ORC_MDF_SPHERICAL_WRAPPED_LORENTZ = 4 };
 enum { ORC_IRC_GAUSS = 0, ORC_IRC_PVOIGT = 1, ORC_IRC_TABLE = 2,
        ORC_IRC_LORENTZ = 3, ORC_IRC_BOX = 4 };
+enum { ORC_MODEL_STEPPING = 0, ORC_MODEL_MWG = 1 };
 enum { ORC_MISS = 0, ORC_ABSORBED = 1, ORC_EXIT_REFLECTED = 2,
        ORC_EXIT_TRANSMITTED = 3, ORC_TRUNCATED = 4 };
 
@@ -95,6 +96,18 @@ typedef struct orc_detector {
 } orc_detector;
 
 /* One record per ray (104 bytes). */
+/* Event model.  STEPPING: null-collision stepping with per-encounter
+   acceptance.  MWG: the paper's model (sec. 2.2.3-2.2.4): free paths at
+   mu0 + gamma0 sigma(alpha), sigma by the psi quadrature of Eq.
+   SimpleReflXsection on psi_nodes intervals, reflections with (psi, Delta)
+   from burn_in Metropolis-within-Gibbs sweeps. */
+typedef struct orc_model {
+    int32_t kind;            /* ORC_MODEL_* */
+    int32_t burn_in;
+    int32_t psi_nodes;
+    int32_t pad_;
+} orc_model;
+
 typedef struct orc_record {
     uint64_t ray_id;
     double energy;
@@ -139,11 +152,38 @@ void orc_source_sample(const orc_source *s, uint64_t seed, uint64_t ray_id,
 /* Exit distance of a point inside the crystal moving along k. */
 double orc_exit_distance(const orc_crystal *c, const double p[3], const double k[3]);
 
+/* Pieces of the paper's event model, for unit pins.  orc_mdf_density: the
+   mosaic density per steradian at v = 1 - cos(theta).  orc_psi_integral: the
+   psi integral of Eq. SimpleReflXsection on M intervals.  orc_irc_integral:
+   int r(x) dx.  orc_irc_width: the sampler's Delta step.  orc_mwg_sample:
+   one sampler draw (margin may be NULL).  orc_crystallite: the normal at
+   (alpha, b = alpha_B + Delta, psi) about planes of normal N. */
+double orc_mdf_density(const orc_mosaic *m, double v);
+double orc_psi_integral(const orc_mosaic *m, double alpha, double beta, int M);
+double orc_irc_integral(const orc_irc *irc);
+double orc_irc_width(const orc_irc *irc);
+void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
+                    uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
+                    double alpha, double ab, double *psi_out, double *delta_out,
+                    double *margin);
+void orc_crystallite(const double N[3], const double k[3], double alpha, double b,
+                     double psi, double n[3]);
+
 /* Trace rays [first, first + n).  counts / energy_mev / records / counters /
    margins may each be NULL.  Images are accumulated into (not cleared).
    records and margins are indexed by ray_id - first.  margins[i] is the
    smallest decision margin met by ray i (a diagnostic for tie analysis).
    n_threads <= 0 uses every online core.  Returns 0 or a negative error. */
+int orc_trace_model(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
+                    const orc_irc *irc, const orc_detector *d, const orc_model *model,
+                    uint64_t first, uint64_t n, uint64_t seed, uint32_t max_events,
+                    uint32_t *counts, uint64_t *energy_mev,
+                    orc_record *records, orc_counters *counters, double *margins,
+                    int n_threads);
+int orc_trace_ids_model(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
+                        const orc_irc *irc, const orc_detector *d, const orc_model *model,
+                        const uint64_t *ids, uint64_t n, uint64_t seed, uint32_t max_events,
+                        orc_record *records, double *margins, int n_threads);
 int orc_trace(const orc_source *s, const orc_crystal *c, const orc_mosaic *m,
               const orc_irc *irc, const orc_detector *d,
               uint64_t first, uint64_t n, uint64_t seed, uint32_t max_events,

@@ -35,8 +35,8 @@ def dens_wl(v, gamma):           # Eq. WL
     return 1.0 / (math.pi * math.log(1 + (4 / gamma) ** 2)) / ((gamma / 2) ** 2 + 2 * v)
 
 
-def dens_swl(v, gamma):          # Eq. SWL
-    return math.sinh(gamma / 2) ** 2 / (4 * math.pi) / (math.cosh(gamma / 2) - 1 + v) ** 2
+def dens_swl(v, gamma):          # Eq. SWL; cosh(G/2) - 1 = 2 sinh^2(G/4) avoids cancellation
+    return math.sinh(gamma / 2) ** 2 / (4 * math.pi) / (2 * math.sinh(gamma / 4) ** 2 + v) ** 2
 
 
 def dens_lorentz(v, gamma):
