@@ -130,6 +130,84 @@ static void pvoigt(double g, double l, double *fwhm, double *eta) {
 
 // Fill the kernel parameters; `tables` receives the rocking-curve table
 // followed by the spectrum CDF (uploaded by the caller).
+// int r(x) dx of a rocking curve: closed forms, and the trapezoid rule for
+// the table (exact for its linear interpolation).
+static double irc_integral(const mrt_rocking_curve *r) {
+    switch (r->kind) {
+    case MRT_IRC_GAUSSIAN:
+        return r->peak * r->fwhm * std::sqrt(kPi / (4.0 * std::log(2.0)));
+    case MRT_IRC_PSEUDO_VOIGT: {
+        // r = peak R(x) / R(0) with R of unit area (Eqs. Gaussian, Lorentz)
+        double w, eta;
+        pvoigt(r->fwhm_g, r->fwhm_l, &w, &eta);
+        const double g0 = std::sqrt(4.0 * std::log(2.0) / (kPi * w * w)), l0 = 2.0 / (kPi * w);
+        return r->peak / (eta * l0 + (1.0 - eta) * g0);
+    }
+    case MRT_IRC_LORENTZIAN:
+        return r->peak * kPi * r->fwhm / 2.0;
+    case MRT_IRC_BOX:
+        return r->peak * r->fwhm;
+    default: {
+        double sum = 0.0;
+        for (int j = 0; j + 1 < r->n_table; ++j) sum += (r->table[j] + r->table[j + 1]) / 2.0;
+        return sum * (r->x_max - r->x_min) / (double)(r->n_table - 1);
+    }
+    }
+}
+
+// Step of the sampler's Delta proposals: the curve's full width at half
+// maximum (for the table, the span of its nodes at or above half its maximum).
+static double irc_width(const mrt_rocking_curve *r) {
+    switch (r->kind) {
+    case MRT_IRC_PSEUDO_VOIGT: {
+        double w, eta;
+        pvoigt(r->fwhm_g, r->fwhm_l, &w, &eta);
+        return w;
+    }
+    case MRT_IRC_TABLE: {
+        double mx = 0.0;
+        for (int j = 0; j < r->n_table; ++j) mx = std::max(mx, r->table[j]);
+        int cnt = 0;
+        for (int j = 0; j < r->n_table; ++j) cnt += r->table[j] >= mx / 2.0;
+        return (double)cnt * (r->x_max - r->x_min) / (double)(r->n_table - 1);
+    }
+    default:
+        return r->fwhm;
+    }
+}
+
+void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_curve *r,
+                      int burn_in, int psi_nodes, int batch, TraceParams &P,
+                      std::vector<double> &psi) {
+    P.burn_in = burn_in;
+    P.psi_nodes = psi_nodes;
+    P.mwg_batch = batch;
+    P.q = irc_integral(r) / c->mfp;
+    P.w_delta = irc_width(r);
+    // sphere densities of the mosaic distributions per steradian (sec. 2.2.2)
+    const double gamma = m->fwhm;
+    const double sv = gamma / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    P.vmf_kappa = 1.0 / (sv * sv);
+    P.vmf_norm = P.vmf_kappa / (2.0 * kPi * -std::expm1(-2.0 * P.vmf_kappa));
+    const double g = gamma / 2.0;
+    P.cau_g2 = g * g;
+    P.cau_norm = g / (2.0 * kPi);
+    P.wl_g2 = g * g;
+    P.wl_norm = 1.0 / (kPi * std::log((g * g + 4.0) / (g * g)));
+    const double sh = std::sinh(gamma / 4.0);
+    P.swl_a = 2.0 * sh * sh;
+    P.swl_norm = P.swl_a * (P.swl_a + 2.0) / (4.0 * kPi);
+    // nodes psi_j = pi (j / M)^3, dense near psi = 0
+    double prev = 0.0;
+    for (int j = 0; j <= psi_nodes; ++j) {
+        const double t = (double)j / (double)psi_nodes;
+        const double pj = kPi * t * t * t;
+        psi.push_back(std::sin(pj / 2.0));
+        psi.push_back(pj - prev);
+        prev = pj;
+    }
+}
+
 void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
                   const mrt_rocking_curve *r, const mrt_detector *d, TraceParams &P,
                   std::vector<double> &tables) {

@@ -119,6 +119,17 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     if (opt.grid_blocks < 0) return fail(MRT_EINVAL, "options: grid_blocks must be >= 0");
     if (opt.refill_idle < 0 || opt.refill_idle > 64)
         return fail(MRT_EINVAL, "options: refill_idle must lie in [0, 64]");
+    const bool mwg = opt.event_model == MRT_MODEL_MWG;
+    if (opt.event_model != MRT_MODEL_STEPPING && !mwg) return fail(MRT_EINVAL, "options: unknown event model");
+    if (mwg) {
+        if (opt.precision != MRT_FP64) return fail(MRT_EINVAL, "options: the MWG event model runs in FP64");
+        if (!(mosaic->fwhm > 0.0)) return fail(MRT_EINVAL, "the MWG event model needs a mosaic fwhm > 0");
+        if (opt.mwg_burn_in < MRT_MWG_NO_BURN_IN) return fail(MRT_EINVAL, "options: mwg_burn_in must be >= -1");
+        if (opt.psi_nodes < 0 || opt.psi_nodes > mrt::kMaxPsiNodes)
+            return fail(MRT_EINVAL, "options: psi_nodes must lie in [0, %d]", mrt::kMaxPsiNodes);
+        if (opt.mwg_batch < 0 || opt.mwg_batch > 64) return fail(MRT_EINVAL, "options: mwg_batch must lie in [0, 64]");
+        if (opt.max_events > 0x7fffffffu) return fail(MRT_EINVAL, "options: the MWG event model needs max_events < 2^31");
+    }
 
     int dev = 0, cus = 0;
     if ((st = current_device(&dev, &cus)) != MRT_OK) return st;
@@ -127,6 +138,12 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     mrt::TraceParams P;
     std::vector<double> tables;
     mrt::build_params(source, crystal, mosaic, rocking_curve, detector, P, tables);
+    const size_t psi_at = tables.size();   // the psi table follows the other tables
+    if (mwg) {
+        const int burn = opt.mwg_burn_in == 0 ? 500 : (opt.mwg_burn_in < 0 ? 0 : opt.mwg_burn_in);
+        mrt::build_mwg_params(crystal, mosaic, rocking_curve, burn, opt.psi_nodes ? opt.psi_nodes : 256,
+                              opt.mwg_batch ? opt.mwg_batch : 32, P, tables);
+    }
     P.first = first_ray_id;
     P.n = n_rays;
     P.seed = seed;
@@ -152,6 +169,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     P.bin_cdf = source->spectrum == MRT_SPECTRUM_TABLE
                     ? dtab + (rocking_curve->kind == MRT_IRC_TABLE ? rocking_curve->n_table : 0)
                     : nullptr;
+    P.psi_tab = mwg ? dtab + psi_at : nullptr;
 
     auto release = [&](mrt_status s) {
         (void)hipFreeAsync(scratch, stream);
@@ -176,8 +194,9 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     }
 
     const bool rec = opt.records_mode != MRT_RECORDS_NONE;
-    const void *kernel = mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
-                                               rocking_curve->kind, rec);
+    const void *kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec)
+                             : mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
+                                                     rocking_curve->kind, rec);
     if (!kernel) return release(fail(MRT_EINVAL, "no kernel for this combination of kinds"));
     const int block = opt.block_threads ? opt.block_threads : 256;
     const size_t lds = 0;   // the kernels read their tables from device memory

@@ -1,0 +1,338 @@
+// The paper's own event model (sec. 2.2.3, 2.2.4), FP64: free paths at
+// mu0 + gamma0 sigma_H(alpha) + gamma0 sigma_anti-H(-alpha) (Eq. AnyEvent)
+// with gamma0 sigma from the psi quadrature of Eq. SimpleReflXsection,
+// absorption with probability mu0 / mu_eff, and reflections off a crystallite
+// whose (psi, Delta) is drawn by a Metropolis-within-Gibbs sampler from the
+// integrand of Eq. ReflXsection and oriented by the two rotations of sec.
+// 2.2.2.  The reflection strength is the stepping model's:
+// Q R(Delta) = r(Delta - Delta_M) / h, with the polarisation factor folded
+// into r's peak.  Source, entry, exit distances, local frame, rocking curve
+// and detector are the stepping kernels' (Tracer).
+//
+// The sampler's burn-in (hundreds of sweeps) costs far more than an event,
+// so a lane whose event is a reflection parks, and the parked lanes of a
+// wave run the sampler together once mwg_batch of them wait or no lane can
+// take another event.
+#include "trace_impl.h"
+
+namespace mrt {
+namespace tk {
+
+template <int GEOM, bool REC>
+struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
+    using B = Tracer<double, GEOM, kAny, kAny, REC>;
+    using RayT = typename B::RayT;
+
+    // ---- mosaic densities per steradian at v = 1 - cos(theta) ----------
+    template <int K> static __device__ __forceinline__ double density(const TraceParams &P, double v) {
+        if constexpr (K == MRT_MOSAIC_GAUSSIAN_VMF) {
+            return P.vmf_norm * ::exp(-P.vmf_kappa * v);
+        } else if constexpr (K == MRT_MOSAIC_LORENTZIAN) {
+            const double c = 1.0 - v;
+            if (!(c > 0.0)) return 0.0;
+            const double q = v * (2.0 - v) + P.cau_g2 * c * c;
+            return P.cau_norm / (q * ::sqrt(q));
+        } else if constexpr (K == MRT_MOSAIC_PSEUDO_VOIGT) {
+            return P.m_eta * density<MRT_MOSAIC_LORENTZIAN>(P, v) +
+                   (1.0 - P.m_eta) * density<MRT_MOSAIC_GAUSSIAN_VMF>(P, v);
+        } else if constexpr (K == MRT_MOSAIC_WRAPPED_LORENTZIAN) {
+            return P.wl_norm / (P.wl_g2 + 2.0 * v);
+        } else {
+            const double d = P.swl_a + v;
+            return P.swl_norm / (d * d);
+        }
+    }
+    static __device__ __forceinline__ double density_any(const TraceParams &P, double v) {
+        switch (P.mdf) {
+        case MRT_MOSAIC_GAUSSIAN_VMF: return density<MRT_MOSAIC_GAUSSIAN_VMF>(P, v);
+        case MRT_MOSAIC_LORENTZIAN: return density<MRT_MOSAIC_LORENTZIAN>(P, v);
+        case MRT_MOSAIC_PSEUDO_VOIGT: return density<MRT_MOSAIC_PSEUDO_VOIGT>(P, v);
+        case MRT_MOSAIC_WRAPPED_LORENTZIAN: return density<MRT_MOSAIC_WRAPPED_LORENTZIAN>(P, v);
+        default: return density<MRT_MOSAIC_SPHERICAL_WRAPPED_LORENTZIAN>(P, v);
+        }
+    }
+
+    // ---- psi integrals of Eq. SimpleReflXsection for alpha and -alpha ----
+    // Trapezoid rule over psi_j = pi (j / M)^3 on [0, pi], doubled (the
+    // integrand is even); v = 2 sin^2((a - beta)/2) + 2 cos(a) cos(beta)
+    // sin^2(psi/2) by Eq. ThetaPsi.  The table holds (sin(psi_j / 2),
+    // psi_j - psi_{j-1}) per node; its index is wave-uniform (scalar loads).
+    template <int K>
+    static __device__ __forceinline__ void psi_pair(const TraceParams &P, double alpha, double beta,
+                                                    double &ih, double &ia) {
+        const double sh = ::sin((alpha - beta) / 2.0), sa = ::sin((-alpha - beta) / 2.0);
+        const double v0h = 2.0 * sh * sh, v0a = 2.0 * sa * sa;
+        const double cc = 2.0 * ::cos(alpha) * ::cos(beta);
+        double fh = density<K>(P, v0h), fa = density<K>(P, v0a), sum_h = 0.0, sum_a = 0.0;
+        const double *tab = P.psi_tab;
+        for (int j = 1; j <= P.psi_nodes; ++j) {
+            const double b = tab[2 * j], dpsi = tab[2 * j + 1];
+            const double bb = cc * b * b;
+            const double gh = density<K>(P, v0h + bb), ga = density<K>(P, v0a + bb);
+            sum_h += dpsi * (fh + gh) / 2.0;
+            sum_a += dpsi * (fa + ga) / 2.0;
+            fh = gh;
+            fa = ga;
+        }
+        ih = 2.0 * sum_h;
+        ia = 2.0 * sum_a;
+    }
+    static __device__ __forceinline__ void psi_integrals(const TraceParams &P, double alpha,
+                                                         double beta, double &ih, double &ia) {
+        switch (P.mdf) {
+        case MRT_MOSAIC_GAUSSIAN_VMF: psi_pair<MRT_MOSAIC_GAUSSIAN_VMF>(P, alpha, beta, ih, ia); break;
+        case MRT_MOSAIC_LORENTZIAN: psi_pair<MRT_MOSAIC_LORENTZIAN>(P, alpha, beta, ih, ia); break;
+        case MRT_MOSAIC_PSEUDO_VOIGT: psi_pair<MRT_MOSAIC_PSEUDO_VOIGT>(P, alpha, beta, ih, ia); break;
+        case MRT_MOSAIC_WRAPPED_LORENTZIAN:
+            psi_pair<MRT_MOSAIC_WRAPPED_LORENTZIAN>(P, alpha, beta, ih, ia);
+            break;
+        default: psi_pair<MRT_MOSAIC_SPHERICAL_WRAPPED_LORENTZIAN>(P, alpha, beta, ih, ia); break;
+        }
+    }
+
+    // ---- one event: free path, then exit, absorption or a pending
+    // reflection.  Returns the end status, or -1 (`pend` set when the event
+    // is a reflection off the planes of normal Ns at glancing angle alpha_s).
+    static __device__ __forceinline__ int event(const TraceParams &P, RayT &ry, bool &pend,
+                                                V3<double> &Ns, double &alpha_s) {
+        if (ry.nev == P.max_events) return MRT_TRUNCATED;
+        const dm::Words w = dm::philox(P.key0, P.key1, ry.nev, (uint32_t)ry.id,
+                                       (uint32_t)(ry.id >> 32), 1u);
+        ++ry.nev;
+        const int exit_status = ry.nrefl ? MRT_EXIT_REFLECTED : MRT_EXIT_TRANSMITTED;
+        const double dist = B::exit_distance(P, ry.p, ry.k);
+        V3<double> N, e1, e2;
+        B::frame(P, ry.p, N, e1, e2);
+        double sn = -dot(ry.k, N);
+        sn = sn > 1.0 ? 1.0 : (sn < -1.0 ? -1.0 : sn);
+        const double alpha = ::asin(sn);
+        double sig_h = 0.0, sig_a = 0.0;
+        if (ry.sa < 1.0 && (int)ry.nrefl < P.max_refl) {
+            const double beta = ::asin(ry.sa) + P.shift;
+            double ih, ia;
+            psi_integrals(P, alpha, beta, ih, ia);
+            const double qc = P.q * ::cos(beta);
+            sig_h = qc * ih;
+            sig_a = qc * ia;
+        }
+        const double mu = P.mu0 + sig_h + sig_a;
+        const double l = -dm::log_pos(dm::u01_f64(w.w0)) / mu;
+        if (l >= dist) {
+            ry.p = axpy(ry.p, dist, ry.k);
+            return exit_status;
+        }
+        ry.p = axpy(ry.p, l, ry.k);
+        if (dm::u01_f64(w.w1) <= P.mu0 / mu) return MRT_ABSORBED;
+        // H planes (normal N) or anti-H planes (normal -N), by their share
+        const bool anti = !(dm::u01_f64(w.w2) * (sig_h + sig_a) < sig_h);
+        Ns = anti ? V3<double>{-N.x, -N.y, -N.z} : N;
+        alpha_s = anti ? -alpha : alpha;
+        pend = true;
+        return -1;
+    }
+
+    // ---- the sampler's target: the integrand of Eq. ReflXsection --------
+    static __device__ __forceinline__ double target(const TraceParams &P, const double *lut,
+                                                    double alpha, double ab, double psi,
+                                                    double delta) {
+        const double r = B::irc_ratio(P, lut, delta - P.shift);
+        if (!(r > 0.0)) return 0.0;
+        const double b = ab + delta;
+        const double sb = ::sin((alpha - b) / 2.0), sp = ::sin(psi / 2.0);
+        const double v = 2.0 * sb * sb + 2.0 * ::cos(alpha) * ::cos(b) * sp * sp;
+        return r * ::cos(b) * density_any(P, v);
+    }
+
+    // ---- Metropolis-within-Gibbs draw and the reflection -----------------
+    // From (0, Delta_M): burn_in sweeps of a psi move and a Delta move,
+    // symmetric uniform random walks, a move taken when u f(current) <
+    // f(proposed) or from a point of zero density, Delta outside
+    // [-alpha_B, pi/2 - alpha_B] rejected, psi wrapped on [-pi, pi).  Sweep s
+    // of event e draws the Philox words of counter (s, ray, 2^31 + e).  Then
+    // N is rotated by alpha - (alpha_B + Delta) about N x k and by psi about
+    // k, and k is reflected (sec. 2.2.4).
+    static __device__ __forceinline__ void reflect(const TraceParams &P, const double *lut, RayT &ry,
+                                                   V3<double> Ns, double alpha) {
+        const double ab = ::asin(ry.sa);
+        const double lo = -ab, hi = kPiHalf - ab;
+        double psi = 0.0, delta = P.shift;
+        delta = delta < lo ? lo : (delta > hi ? hi : delta);
+        double cb = ::cos(ab + P.shift);
+        cb = cb > 0.05 ? cb : 0.05;
+        const double w_psi = P.fwhm / cb;
+        const uint32_t event = ry.nev - 1u;
+        double f = target(P, lut, alpha, ab, psi, delta);
+        for (int s = 0; s < P.burn_in; ++s) {
+            const dm::Words w = dm::philox(P.key0, P.key1, (uint32_t)s, (uint32_t)ry.id,
+                                           (uint32_t)(ry.id >> 32), 0x80000000u | event);
+            double pn = psi + w_psi * (2.0 * dm::u01_f64(w.w0) - 1.0);
+            pn = pn >= kPi ? pn - 2.0 * kPi : (pn < -kPi ? pn + 2.0 * kPi : pn);
+            double fn = target(P, lut, alpha, ab, pn, delta);
+            if (dm::u01_f64(w.w1) * f < fn || f == 0.0) {
+                psi = pn;
+                f = fn;
+            }
+            const double dn = delta + P.w_delta * (2.0 * dm::u01_f64(w.w2) - 1.0);
+            if (dn >= lo && dn <= hi) {
+                fn = target(P, lut, alpha, ab, psi, dn);
+                if (dm::u01_f64(w.w3) * f < fn || f == 0.0) {
+                    delta = dn;
+                    f = fn;
+                }
+            }
+        }
+        // crystallite normal
+        const double th = alpha - (ab + delta), ca = ::cos(alpha), sa = ::sin(alpha);
+        const V3<double> k = ry.k;
+        V3<double> n0 = Ns;
+        if (ca > 0.0) {
+            const double ct = ::cos(th), st = ::sin(th);
+            n0 = V3<double>{ct * Ns.x + st * (k.x + sa * Ns.x) / ca, ct * Ns.y + st * (k.y + sa * Ns.y) / ca,
+                            ct * Ns.z + st * (k.z + sa * Ns.z) / ca};
+        }
+        const V3<double> kx = cross(k, n0);
+        const double kn0 = dot(k, n0), cp = ::cos(psi), sp = ::sin(psi);
+        const V3<double> n{cp * n0.x + sp * kx.x + (1.0 - cp) * kn0 * k.x,
+                           cp * n0.y + sp * kx.y + (1.0 - cp) * kn0 * k.y,
+                           cp * n0.z + sp * kx.z + (1.0 - cp) * kn0 * k.z};
+        const double two_kn = 2.0 * dot(k, n);
+        const V3<double> ks{k.x - two_kn * n.x, k.y - two_kn * n.y, k.z - two_kn * n.z};
+        const double nr = ::sqrt(dot(ks, ks));
+        ry.k = V3<double>{ks.x / nr, ks.y / nr, ks.z / nr};
+        ++ry.nrefl;
+    }
+
+    static constexpr double kPi = 3.14159265358979323846;
+    static constexpr double kPiHalf = 1.57079632679489661923;
+};
+
+// ---------------------------------------------------------------------------
+// The persistent loop of one wave for the paper's model.  Ray starts, the
+// queue refill and the detector work are those of trace_loop (same queue,
+// same claims, same counters); the event step differs, and lanes whose event
+// is a reflection park until the wave runs the sampler for all of them.
+// ---------------------------------------------------------------------------
+template <class T, class Claim, class Q>
+__device__ __forceinline__ void mwg_loop(const TraceParams &P, const double *lut, const double *cdf,
+                                         Claim &claim, Q &q) {
+    typename T::RayT ry;
+    bool active = false;
+    bool pend = false;            // the lane waits for the sampler
+    V3<double> Ns{0.0, 0.0, 0.0};
+    double alpha_s = 0.0;
+    WaveCounts cnt{};
+    uint64_t next = 0, end = 0;
+    bool more = true;
+    uint32_t head = 0, queued = 0;
+    const uint32_t refill_at = P.refill_idle < 1u ? 1u : (P.refill_idle > 64u ? 64u : P.refill_idle);
+    const uint32_t batch = P.mwg_batch < 1 ? 1u : (P.mwg_batch > 64 ? 64u : (uint32_t)P.mwg_batch);
+    const uint32_t lane = __lane_id();
+
+    for (;;) {
+        for (;;) {
+            const uint64_t idle = ballot(!active);
+            const uint32_t nidle = popc(idle);
+            if (nidle == 0 || (nidle < refill_at && idle != ~0ull)) break;
+            if (queued == 0) {
+                if (!more) break;
+                if (next == end && !claim(next, end)) {
+                    more = false;
+                    break;
+                }
+                const uint64_t avail = end - next;
+                const uint32_t width = avail < kQueue ? (uint32_t)avail : kQueue;
+                if (active) q.put(lane, ry);
+                bool hit = false, missed = false;
+                if (lane < width) {
+                    hit = T::start(P, cdf, next + lane, ry);
+                    missed = !hit;
+                }
+                const uint64_t hits = ballot(hit);
+                q.unpark(lane, active, hit, lane_rank(hits), ry);
+                cnt.missed += popc(ballot(missed));
+                head = 0;
+                queued = popc(hits);
+                next += width;
+                wave_sync();
+                continue;
+            }
+            if (!active) {
+                const uint32_t r = lane_rank(idle);
+                if (r < queued) {
+                    q.take(head + r, ry);
+                    active = true;
+                }
+            }
+            const uint32_t take = queued < nidle ? queued : nidle;
+            head += take;
+            queued -= take;
+        }
+        const uint64_t act0 = ballot(active);
+        if (act0 == 0) {
+            if (!more && queued == 0) break;
+            continue;
+        }
+
+        const uint32_t keep = more || queued ? 65u - refill_at : 1u;
+        for (;;) {
+            int status = -1;
+            const bool stepping = active && !pend;
+            if (stepping) status = T::event(P, ry, pend, Ns, alpha_s);
+            const bool ended = status >= 0;
+            bool det = false;
+            if (ended) {
+                det = T::finish(P, ry, status);
+                active = false;
+            }
+            cnt.events += popc(ballot(stepping && status != MRT_TRUNCATED));
+            const uint64_t endm = ballot(ended);
+            if (endm) {
+                cnt.absorbed += popc(ballot(ended && status == MRT_ABSORBED));
+                cnt.exit_refl += popc(ballot(ended && status == MRT_EXIT_REFLECTED));
+                cnt.exit_trans += popc(ballot(ended && status == MRT_EXIT_TRANSMITTED));
+                cnt.truncated += popc(ballot(ended && status == MRT_TRUNCATED));
+                cnt.detected += popc(ballot(det));
+            }
+            // The parked lanes run the sampler together once `batch` of them
+            // wait.  While rays can still be taken in, at most `keep` wait
+            // (then no lane steps and the wave would not break to refill);
+            // while draining, they also run when no lane can step.
+            const uint32_t npend = popc(ballot(pend));
+            const bool refilling = more || queued;
+            const uint32_t due = refilling && keep < batch ? keep : batch;
+            if (npend && (npend >= due || (!refilling && popc(ballot(active && !pend)) == 0))) {
+                if (pend) {
+                    T::reflect(P, lut, ry, Ns, alpha_s);
+                    pend = false;
+                }
+                cnt.reflections += npend;
+            }
+            if (popc(ballot(active)) < keep) break;
+        }
+    }
+    flush(P, cnt);
+}
+
+template <int GEOM, bool REC>
+__global__ void __launch_bounds__(256) mwg_kernel(const TraceParams P) {
+    using T = MwgTracer<GEOM, REC>;
+    const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
+    RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
+    __shared__ RayQueue<double, REC> queues[4];   // one per wave
+    RayQueue<double, REC> &q = queues[uniform(threadIdx.x >> 6)];
+    mwg_loop<T>(Q, Q.lut, Q.bin_cdf, claim, q);
+}
+
+}  // namespace tk
+
+const void *mwg_kernel_ptr(int geometry, bool records) {
+    if (geometry == MRT_GEOMETRY_FLAT)
+        return records ? (const void *)tk::mwg_kernel<MRT_GEOMETRY_FLAT, true>
+                       : (const void *)tk::mwg_kernel<MRT_GEOMETRY_FLAT, false>;
+    if (geometry == MRT_GEOMETRY_CYLINDER)
+        return records ? (const void *)tk::mwg_kernel<MRT_GEOMETRY_CYLINDER, true>
+                       : (const void *)tk::mwg_kernel<MRT_GEOMETRY_CYLINDER, false>;
+    return nullptr;
+}
+
+}  // namespace mrt

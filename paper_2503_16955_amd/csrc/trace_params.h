@@ -79,6 +79,17 @@ struct TraceParams {
     double lut_x0, lut_x1, lut_scale, lut_inv_max;
     const double *lut;            // device
 
+    // ---- the paper's event model (sec. 2.2.3, 2.2.4; FP64 kernels only)
+    int32_t burn_in, psi_nodes;   // sampler sweeps; psi quadrature intervals
+    int32_t mwg_batch, pad2;      // parked lanes that start the sampler
+    double q;                     // int r dx / mfp (Q R = r / mfp)
+    double w_delta;               // sampler step in Delta
+    double vmf_kappa, vmf_norm;   // density kappa e^{-kappa v} / (2 pi (1 - e^{-2 kappa}))
+    double cau_g2, cau_norm;      // (Gamma/2)^2 and (Gamma/2) / (2 pi)
+    double wl_g2, wl_norm;        // (Gamma/2)^2 and 1 / (pi ln((g^2 + 4) / g^2))
+    double swl_a, swl_norm;       // 2 sinh^2(Gamma/4) and A (A + 2) / (4 pi)
+    const double *psi_tab;        // (sin(psi_j / 2), psi_j - psi_{j-1}), j = 0..M (device)
+
     // ---- detector (sec. 2.3), local coordinates
     double dP[3], dn[3], du[3], dv[3];
     int32_t nx, ny;
@@ -128,5 +139,9 @@ int launch_zero(void *ptr_u32, size_t n_words, void *stream);
 // *items, uint32_t n_items, uint64_t total, unsigned long long *cursors), one
 // zeroed cursor per item.
 const void *serve_kernel_ptr(int precision);
+// Kernel of the paper's event model (FP64) for a geometry (nullptr for an
+// unknown one): (TraceParams), like the trace kernels.
+const void *mwg_kernel_ptr(int geometry, bool records);
+constexpr int kMaxPsiNodes = 2048;
 
 }  // namespace mrt

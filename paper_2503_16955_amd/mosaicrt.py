@@ -72,7 +72,25 @@ class MrtOptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("records_mode", C.c_int32),
                 ("max_events", C.c_uint32), ("accumulate", C.c_int32),
                 ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
-                ("refill_idle", C.c_int32), ("reserved", C.c_int32)]
+                ("refill_idle", C.c_int32), ("event_model", C.c_int32),
+                ("mwg_burn_in", C.c_int32), ("psi_nodes", C.c_int32), ("mwg_batch", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+MODEL = {"stepping": 0, "mwg": 1}
+MWG_NO_BURN_IN = -1
+
+
+def model_options(w):
+    """Event-model fields of mrt_options for workload `w`: w["event_model"] =
+    {"kind": "mwg", "burn_in": B, "psi_nodes": M} selects the paper's model
+    (B sweeps, 0 meaning none; the library defaults are 500 and 256)."""
+    e = w.get("event_model") or {"kind": "stepping"}
+    if e["kind"] == "stepping":
+        return {"event_model": 0}
+    b = int(e.get("burn_in", 500))
+    return {"event_model": MODEL[e["kind"]], "mwg_burn_in": MWG_NO_BURN_IN if b == 0 else b,
+            "psi_nodes": int(e.get("psi_nodes", 256))}
 
 
 COUNTER_FIELDS = ("emitted", "missed", "absorbed", "exit_reflected", "exit_transmitted",
@@ -229,11 +247,12 @@ def alloc_images(w, device="cuda", energy=True):
 
 def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_events=0,
           accumulate=False, counts=None, energy=None, want_energy=True, record_buf=None,
-          grid_blocks=0, block_threads=0, refill_idle=0, stream=None, sync=True):
+          grid_blocks=0, block_threads=0, refill_idle=0, mwg_batch=0, stream=None, sync=True):
     """Trace rays [first, first + n_rays) of workload `w` with ``mrt_trace``.
 
     counts / energy: torch device tensors to fill (allocated when None).
-    records: None, "all" or "detected".  sync=True waits for the stream and
+    records: None, "all" or "detected".  The event model comes from
+    w["event_model"] (see model_options).  sync=True waits for the stream and
     returns the counters (and the kernel time); sync=False enqueues only.
     Returns a dict with ``counts``, ``energy``, ``records`` (uint8 device
     tensor of n x 104 bytes, or None) and ``counters`` (dict, or None)."""
@@ -256,7 +275,8 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
     S = Structs(w)
     opt = MrtOptions(precision=prec, records_mode=mode, max_events=int(max_events),
                      accumulate=1 if accumulate else 0, grid_blocks=int(grid_blocks),
-                     block_threads=int(block_threads), refill_idle=int(refill_idle))
+                     block_threads=int(block_threads), refill_idle=int(refill_idle),
+                     mwg_batch=int(mwg_batch), **model_options(w))
     cnt = MrtCounters()
     if stream is None:
         stream = torch.cuda.current_stream(counts.device)

@@ -19,6 +19,7 @@
 #include "mosaicrt.h"
 #include "params.h"
 #include "trace_impl.h"
+#include "trace_mwg.h"   // the paper's event model (trace_mwg.hip)
 #include "trace_params.h"
 
 thread_local simt_dim3 threadIdx, blockIdx, blockDim, gridDim;
@@ -143,6 +144,12 @@ void trace_body(const TraceParams &P, void *queue) {
     trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(RayQueue<R, REC> *)queue);
 }
 
+template <bool REC>
+void mwg_body(const TraceParams &P, void *queue) {
+    RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
+    mwg_loop<MwgTracer<kAny, REC>>(P, P.lut, P.bin_cdf, claim, *(RayQueue<double, REC> *)queue);
+}
+
 // Room for any RayQueue, filled with a byte pattern so that a read of an
 // entry no lane has written shows up as garbage.
 struct QueueMem {
@@ -171,6 +178,32 @@ int emu_build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic
 }
 int emu_params_size() { return (int)sizeof(TraceParams); }
 
+// The paper's event model: its parameters, with the psi table appended at
+// tables_out[n_used...] (host memory the emulated kernel reads in place).
+int emu_build_mwg(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_curve *r,
+                  int burn_in, int psi_nodes, int batch, TraceParams *P, double *tables_out,
+                  int tables_cap, int n_used) {
+    std::vector<double> t;
+    mrt::build_mwg_params(c, m, r, burn_in, psi_nodes, batch, *P, t);
+    if (n_used + (int)t.size() > tables_cap) return -2;
+    for (size_t i = 0; i < t.size(); ++i) tables_out[n_used + i] = t[i];
+    P->psi_tab = tables_out + n_used;
+    return 0;
+}
+
+// Run the paper's event model's loop (FP64) with n_waves waves.
+int emu_trace_mwg(TraceParams *P, int n_waves, long long max_meetings) {
+    for (int w = 0; w < n_waves; ++w) {
+        QueueMem q;
+        int e = run_wave([&] {
+            if (P->records_mode != MRT_RECORDS_NONE) mwg_body<true>(*P, q.b);
+            else mwg_body<false>(*P, q.b);
+        }, max_meetings);
+        if (e) return e;
+    }
+    return 0;
+}
+
 // The run fields of a parameter block (as the one-call path and the server
 // set them).
 void emu_set_run(TraceParams *P, uint64_t first, uint64_t n, uint64_t seed, uint32_t max_events,
@@ -190,6 +223,13 @@ void emu_set_run(TraceParams *P, uint64_t first, uint64_t n, uint64_t seed, uint
     P->chunk_counter = counters + kNumCounters;
     P->chunk = chunk;
     P->refill_idle = refill_idle;
+}
+
+// Records of every ray (ALL mode) into host memory.
+void emu_set_records(TraceParams *P, mrt_hit_record *records, uint64_t cap) {
+    P->records_mode = MRT_RECORDS_ALL;
+    P->records = records;
+    P->rec_cap = cap;
 }
 
 // Run the serving kernel body with n_waves waves (one after another) over a

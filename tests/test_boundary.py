@@ -47,7 +47,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(mrt.MrtMosaic) == 24
     assert C.sizeof(mrt.MrtRockingCurve) == 72
     assert C.sizeof(mrt.MrtDetector) == 112
-    assert C.sizeof(mrt.MrtOptions) == 32
+    assert C.sizeof(mrt.MrtOptions) == 48
     assert C.sizeof(mrt.MrtCounters) == 96
     assert mrt.RECORD_DTYPE.itemsize == 104
 
@@ -143,6 +143,24 @@ def test_invalid_run_arguments():
                  n=1000) == mrt.ECAPACITY
     assert _call(w, opts=mrt.MrtOptions(block_threads=96)) == mrt.EINVAL
     assert _call(w, opts=mrt.MrtOptions(grid_blocks=-1)) == mrt.EINVAL
+
+
+def test_invalid_event_model_options():
+    # the paper's event model: FP64 only, a mosaic density (fwhm > 0), burn-in
+    # >= -1, at most 2048 psi intervals, batch within a wave, and event
+    # indices that fit the sampler's counter word
+    w = W.get("flat_hopg")
+    M = dict(event_model=mrt.MODEL["mwg"])
+    assert _call(w, opts=mrt.MrtOptions(event_model=5)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(precision=1, **M)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(mwg_burn_in=-2, **M)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(psi_nodes=2049, **M)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(psi_nodes=-1, **M)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(mwg_batch=65, **M)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(max_events=1 << 31, **M)) == mrt.EINVAL
+    w["mosaic"]["fwhm"] = 0.0
+    assert _call(w, opts=mrt.MrtOptions(**M)) == mrt.EINVAL
+    assert "fwhm" in mrt.last_error()
 
 
 def test_valid_call_without_gpu_fails_loudly():

@@ -42,6 +42,7 @@ def emu(tmp_path_factory):
     for f in ("trace_impl.h", "trace_params.h", "device_math.h", "math_tables.h", "params.h",
               "params.cpp"):
         shutil.copy(os.path.join(CSRC, f), d / f)
+    shutil.copy(os.path.join(CSRC, "trace_mwg.hip"), d / "trace_mwg.h")
     dm = (d / "device_math.h").read_text()
     assert dm.count(ASM_FMA) == 1, "device_math.h: the inline asm this test replaces has changed"
     (d / "device_math.h").write_text(dm.replace(ASM_FMA, "r = __builtin_fma(p, z, c);"))
@@ -57,6 +58,10 @@ def emu(tmp_path_factory):
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32]
     L.emu_trace.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_longlong]
     L.emu_serve.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int, C.c_int, C.c_longlong]
+    L.emu_build_mwg.argtypes = [C.c_void_p] * 3 + [C.c_int] * 3 + [C.c_void_p, C.c_void_p, C.c_int,
+                                                                   C.c_int]
+    L.emu_trace_mwg.argtypes = [C.c_void_p, C.c_int, C.c_longlong]
+    L.emu_set_records.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64]
     return L
 
 
@@ -72,6 +77,7 @@ class Job:
         r = L.emu_build_params(*[C.cast(x, C.c_void_p) for x in self.S.refs()], C.byref(self.P),
                                self.tab.ctypes.data, len(self.tab), C.byref(nt))
         assert r == 0, r
+        self.n_tables = nt.value
         px = w["detector"]["nx"] * w["detector"]["ny"]
         self.counts = np.zeros(px, np.uint32)
         self.energy = np.zeros(px, np.uint64)
@@ -159,3 +165,36 @@ def test_schedule_does_not_change_results(emu, precision):
             assert np.array_equal(ref[0], got[0]), (w["name"], chunk, refill)
             assert np.array_equal(ref[1], got[1]), (w["name"], chunk, refill)
             assert ref[2] == got[2], (w["name"], chunk, refill)
+
+
+@pytest.mark.parametrize("name,n,burn", [("flat_hopg", 4000, 300), ("von_hamos_hapg", 6000, 200),
+                                          ("flat_stress", 1500, 100)])
+def test_mwg_loop_matches_the_oracle_ray_for_ray(emu, name, n, burn):
+    """The paper's event model: the device loop (event step with the psi
+    quadrature, parked lanes and batched sampler, queue refill) run under the
+    emulator gives every ray the oracle's status, event and reflection
+    counts and pixel, and its end point and direction within 1e-12."""
+    import oracle
+    from paper_2503_16955_amd import workloads as W
+    w = W.get(name)
+    w["event_model"] = {"kind": "mwg", "burn_in": burn, "psi_nodes": 256}
+    seed = w["seed"]
+    j = Job(emu, w, n, seed)
+    refs = [C.cast(x, C.c_void_p) for x in j.S.refs()]
+    assert emu.emu_build_mwg(refs[1], refs[2], refs[3], burn, 256, 16, C.byref(j.P),
+                             j.tab.ctypes.data, len(j.tab), j.n_tables) == 0
+    rec = np.zeros(n, mrt.RECORD_DTYPE)
+    emu.emu_set_records(j.P, rec.ctypes.data, n)
+    assert emu.emu_trace_mwg(j.P, WAVES, MAX_MEETINGS) == 0
+    o = oracle.trace(w, n=n, seed=seed, records=True)
+    orec = o["records"]
+    for f in ("ray_id", "status", "n_events", "n_refl", "detected", "pix_i", "pix_j"):
+        assert np.array_equal(rec[f], orec[f]), f
+    for f in ("energy", "end", "dir"):
+        a, b = rec[f], orec[f]
+        ok = np.isnan(a) & np.isnan(b) | (np.abs(a - b) <= 1e-12 * np.maximum(np.maximum(np.abs(a), np.abs(b)), 1.0))
+        assert ok.all(), f
+    assert np.array_equal(j.counts, o["counts"].ravel())
+    c = j.counters()
+    assert c["reflections"] == int(orec["n_refl"].sum()) > 0
+    assert c["events"] == int(orec["n_events"].sum())
