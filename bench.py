@@ -15,6 +15,11 @@ crystal radius, mosaic, thickness, energy window; ray counts log-uniform in
 with Poisson arrivals at 0.7 times that rate (p50/p99 latency from submission
 to completion, rays/s).
 
+The same workload is also traced in the paper's own event model (free paths
+at mu0 + gamma0 sigma(alpha) with sigma from the psi quadrature of Eq.
+SimpleReflXsection, reflecting crystallites from Metropolis-within-Gibbs with
+500 sweeps), FP64, with its own roofline and oracle rate ("mwg_model").
+
 Printed: one JSON line with rays/s (FP64 is `value`), events/s, the ALU
 roofline of the trace kernel (algorithmic VALU lane-operations per launch over
 the kernel's HIP-event duration on its stream, against 256 CUs x 64 lanes x
@@ -91,6 +96,57 @@ def roofline(op_costs, profiling, w, precision, per_step, cus):
             "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; 32-bit ops cost 1/2)",
             "ops_per_launch": int(sum(ops) / len(ops)),
             "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
+
+
+def mwg_kernel_name(w, records=False):
+    g = KIND["geometry"][w["crystal"]["geometry"]]
+    return f"void mrt::tk::mwg_kernel<{g}, {'true' if records else 'false'}>(mrt::TraceParams)"
+
+
+def roofline_mwg(op_costs, profiling, w, per_step, cus, psi_nodes, burn_in):
+    ops = [op_costs.algorithmic_ops_mwg(w, c, psi_nodes, burn_in) for c in per_step]
+    ms = [c["kernel_ms"] for c in per_step]
+    achieved = sum(o / (m * 1e-3) for o, m in zip(ops, ms)) / len(ops) / 1e12
+    peak = cus * LANES_PER_CU_PER_CLK * PEAK_CLOCK_HZ / 1e12
+    name = mwg_kernel_name(w)
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4),
+            "traffic": profiling.traffic_per_launch(name),
+            "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; 32-bit ops cost 1/2)",
+            "ops_per_launch": int(sum(ops) / len(ops)),
+            "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
+
+
+def mwg_model(mrt, op_costs, profiling, w, n, steps, warmup, burn_in, psi_nodes, cus, cpu_rays,
+              stepping_value):
+    """The paper's event model on the same workload and ray ids (FP64)."""
+    import copy
+    wm = copy.deepcopy(w)
+    wm["event_model"] = {"kind": "mwg", "burn_in": burn_in, "psi_nodes": psi_nodes}
+    counts, energy = mrt.alloc_images(wm)
+    per, gms, wall = run_precision(mrt, wm, "fp64", steps, warmup, n, counts, energy)
+    rays = n * steps
+    refl = sum(c["reflections"] for c in per)
+    out = {"value": round(rays / (gms * 1e-3), 1), "unit": "rays/s", "steps": steps,
+           "ms_per_step": round(gms / steps, 4), "burn_in": burn_in, "psi_nodes": psi_nodes,
+           "events_per_s": round(sum(c["events"] for c in per) / (gms * 1e-3), 1),
+           "reflections_per_s": round(refl / (gms * 1e-3), 1),
+           "sweeps_per_s": round(refl * burn_in / (gms * 1e-3), 1),
+           "vs_stepping": round(rays / (gms * 1e-3) / stepping_value, 4),
+           "roofline": roofline_mwg(op_costs, profiling, wm, per, cus, psi_nodes, burn_in),
+           "counters_last_step": {k: v for k, v in per[-1].items() if k != "kernel_ms"}}
+    if cpu_rays:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        log(f"oracle, paper's model: {cpu_rays} rays on {threads} threads")
+        t0 = time.perf_counter()
+        oracle.trace(wm, first=0, n=cpu_rays, threads=threads, images=True)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(cpu_rays / dt, 1), "unit": "rays/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"ray ids [0, {cpu_rays}) of the same workload in the "
+                                         f"paper's model, FP64, images on, {dt:.2f} s"}
+    return out
 
 
 def cpu_baseline(w, n):
@@ -258,6 +314,11 @@ def main():
     ap.add_argument("--serving-load", type=float, default=0.7)
     ap.add_argument("--serving-round-rays", type=int, default=0, help="rays per round (0 = the server's default)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--mwg-steps", type=int, default=3, help="steps of the paper's event model")
+    ap.add_argument("--mwg-burn-in", type=int, default=500)
+    ap.add_argument("--mwg-psi-nodes", type=int, default=256)
+    ap.add_argument("--mwg-cpu-rays", type=int, default=10_000_000)
+    ap.add_argument("--no-mwg", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the transport shards by ray-id ranges with one "
@@ -312,6 +373,12 @@ def main():
             "speedup_vs_fp64": round(gpu_ms64 / gms, 3),
             "roofline": roofline(op_costs, profiling, w, "fp32_mixed", pm, info["compute_units"]),
         }
+    if not a.no_mwg:
+        res["mwg_model"] = mwg_model(mrt, op_costs, profiling, w, n, a.mwg_steps, 1, a.mwg_burn_in,
+                                     a.mwg_psi_nodes, info["compute_units"],
+                                     0 if a.no_cpu_baseline else a.mwg_cpu_rays, value)
+        log(f"paper's model: {res['mwg_model']['value']:.3e} rays/s, "
+            f"{res['mwg_model']['ms_per_step']} ms per step")
     res["serving"] = None if a.no_serving else serving(
         mrt, W, a.serving_requests, a.serving_budget_mib << 20, 64, a.serving_load,
         round_rays=a.serving_round_rays)

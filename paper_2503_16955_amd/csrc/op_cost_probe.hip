@@ -31,6 +31,9 @@ PROBE(sqrt_f64, double, dm::sqrt(x) * 0.5)
 PROBE(rsqrt_f64, double, dm::rsqrt(x) * 0.5)
 PROBE(rcp_f64, double, dm::rcp(x) * 0.5)
 PROBE(div_ieee_f64, double, (1.0 / x) * 0.5)
+PROBE(sin_f64, double, ::sin(x) * 0.5)
+PROBE(cos_f64, double, ::cos(x) * 0.5)
+PROBE(asin_f64, double, ::asin(x) * 0.5)
 PROBE(glue_f32, float, x * 0.5f)
 PROBE(log_f32, float, dm::log_pos(x) * 0.5f)
 PROBE(exp_f32, float, dm::exp_(x) * 0.5f)

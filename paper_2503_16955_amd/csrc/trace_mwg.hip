@@ -23,6 +23,22 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
     using B = Tracer<double, GEOM, kAny, kAny, REC>;
     using RayT = typename B::RayT;
 
+    // sin and cos of an angle within a turn, by the table-driven sin/cos of
+    // turns (22 issue slots for both; the radian library forms cost ~128 each)
+    static __device__ __forceinline__ double sin_(double x) {
+        double s, c;
+        dm::sincos_turns(x * kInv2Pi, &s, &c);
+        return s;
+    }
+    static __device__ __forceinline__ double cos_(double x) {
+        double s, c;
+        dm::sincos_turns(x * kInv2Pi, &s, &c);
+        return c;
+    }
+    static __device__ __forceinline__ void sincos_(double x, double *s, double *c) {
+        dm::sincos_turns(x * kInv2Pi, s, c);
+    }
+
     // ---- mosaic densities per steradian at v = 1 - cos(theta) ----------
     template <int K> static __device__ __forceinline__ double density(const TraceParams &P, double v) {
         if constexpr (K == MRT_MOSAIC_GAUSSIAN_VMF) {
@@ -60,9 +76,9 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
     template <int K>
     static __device__ __forceinline__ void psi_pair(const TraceParams &P, double alpha, double beta,
                                                     double &ih, double &ia) {
-        const double sh = ::sin((alpha - beta) / 2.0), sa = ::sin((-alpha - beta) / 2.0);
+        const double sh = sin_((alpha - beta) / 2.0), sa = sin_((-alpha - beta) / 2.0);
         const double v0h = 2.0 * sh * sh, v0a = 2.0 * sa * sa;
-        const double cc = 2.0 * ::cos(alpha) * ::cos(beta);
+        const double cc = 2.0 * cos_(alpha) * cos_(beta);
         double fh = density<K>(P, v0h), fa = density<K>(P, v0a), sum_h = 0.0, sum_a = 0.0;
         const double *tab = P.psi_tab;
         for (int j = 1; j <= P.psi_nodes; ++j) {
@@ -111,7 +127,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
             const double beta = ::asin(ry.sa) + P.shift;
             double ih, ia;
             psi_integrals(P, alpha, beta, ih, ia);
-            const double qc = P.q * ::cos(beta);
+            const double qc = P.q * cos_(beta);
             sig_h = qc * ih;
             sig_a = qc * ia;
         }
@@ -132,15 +148,27 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
     }
 
     // ---- the sampler's target: the integrand of Eq. ReflXsection --------
-    static __device__ __forceinline__ double target(const TraceParams &P, const double *lut,
-                                                    double alpha, double ab, double psi,
-                                                    double delta) {
-        const double r = B::irc_ratio(P, lut, delta - P.shift);
-        if (!(r > 0.0)) return 0.0;
+    // f(psi, Delta) = r(Delta - Delta_M) cos(b) W(v), b = alpha_B + Delta,
+    // v = 2 sin^2((alpha - b)/2) + 2 cos(alpha) cos(b) sin^2(psi/2).  The
+    // sampler keeps the factors of the current point: a psi move changes
+    // only sin(psi/2), a Delta move only r, cos(b) and sin((alpha - b)/2), so
+    // each factor is evaluated once per move, as the full formula would.
+    struct Point {
+        double r, cb, sab, sp;   // r(Delta - Delta_M), cos(b), sin((alpha - b)/2), sin(psi/2)
+    };
+    static __device__ __forceinline__ double value(const TraceParams &P, const Point &x,
+                                                   double ca) {
+        if (!(x.r > 0.0)) return 0.0;
+        const double v = 2.0 * x.sab * x.sab + 2.0 * ca * x.cb * x.sp * x.sp;
+        return x.r * x.cb * density_any(P, v);
+    }
+    static __device__ __forceinline__ void at_delta(const TraceParams &P, const double *lut,
+                                                    double alpha, double ab, double delta,
+                                                    Point &x) {
         const double b = ab + delta;
-        const double sb = ::sin((alpha - b) / 2.0), sp = ::sin(psi / 2.0);
-        const double v = 2.0 * sb * sb + 2.0 * ::cos(alpha) * ::cos(b) * sp * sp;
-        return r * ::cos(b) * density_any(P, v);
+        x.r = B::irc_ratio(P, lut, delta - P.shift);
+        x.cb = cos_(b);
+        x.sab = sin_((alpha - b) / 2.0);
     }
 
     // ---- Metropolis-within-Gibbs draw and the reflection -----------------
@@ -157,41 +185,55 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
         const double lo = -ab, hi = kPiHalf - ab;
         double psi = 0.0, delta = P.shift;
         delta = delta < lo ? lo : (delta > hi ? hi : delta);
-        double cb = ::cos(ab + P.shift);
-        cb = cb > 0.05 ? cb : 0.05;
-        const double w_psi = P.fwhm / cb;
+        double cbm = cos_(ab + P.shift);
+        cbm = cbm > 0.05 ? cbm : 0.05;
+        const double w_psi = P.fwhm / cbm;
+        double sa, ca;
+        sincos_(alpha, &sa, &ca);
         const uint32_t event = ry.nev - 1u;
-        double f = target(P, lut, alpha, ab, psi, delta);
+        Point x;
+        at_delta(P, lut, alpha, ab, delta, x);
+        x.sp = 0.0;   // sin(0 / 2)
+        double f = value(P, x, ca);
         for (int s = 0; s < P.burn_in; ++s) {
             const dm::Words w = dm::philox(P.key0, P.key1, (uint32_t)s, (uint32_t)ry.id,
                                            (uint32_t)(ry.id >> 32), 0x80000000u | event);
             double pn = psi + w_psi * (2.0 * dm::u01_f64(w.w0) - 1.0);
             pn = pn >= kPi ? pn - 2.0 * kPi : (pn < -kPi ? pn + 2.0 * kPi : pn);
-            double fn = target(P, lut, alpha, ab, pn, delta);
+            Point y = x;
+            y.sp = sin_(pn / 2.0);
+            double fn = value(P, y, ca);
             if (dm::u01_f64(w.w1) * f < fn || f == 0.0) {
                 psi = pn;
+                x = y;
                 f = fn;
             }
             const double dn = delta + P.w_delta * (2.0 * dm::u01_f64(w.w2) - 1.0);
             if (dn >= lo && dn <= hi) {
-                fn = target(P, lut, alpha, ab, psi, dn);
+                y = x;
+                at_delta(P, lut, alpha, ab, dn, y);
+                fn = value(P, y, ca);
                 if (dm::u01_f64(w.w3) * f < fn || f == 0.0) {
                     delta = dn;
+                    x = y;
                     f = fn;
                 }
             }
         }
         // crystallite normal
-        const double th = alpha - (ab + delta), ca = ::cos(alpha), sa = ::sin(alpha);
+        const double th = alpha - (ab + delta);
         const V3<double> k = ry.k;
         V3<double> n0 = Ns;
         if (ca > 0.0) {
-            const double ct = ::cos(th), st = ::sin(th);
+            double st, ct;
+            sincos_(th, &st, &ct);
             n0 = V3<double>{ct * Ns.x + st * (k.x + sa * Ns.x) / ca, ct * Ns.y + st * (k.y + sa * Ns.y) / ca,
                             ct * Ns.z + st * (k.z + sa * Ns.z) / ca};
         }
         const V3<double> kx = cross(k, n0);
-        const double kn0 = dot(k, n0), cp = ::cos(psi), sp = ::sin(psi);
+        double sp, cp;
+        sincos_(psi, &sp, &cp);
+        const double kn0 = dot(k, n0);
         const V3<double> n{cp * n0.x + sp * kx.x + (1.0 - cp) * kn0 * k.x,
                            cp * n0.y + sp * kx.y + (1.0 - cp) * kn0 * k.y,
                            cp * n0.z + sp * kx.z + (1.0 - cp) * kn0 * k.z};
@@ -203,6 +245,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
     }
 
     static constexpr double kPi = 3.14159265358979323846;
+    static constexpr double kInv2Pi = 0.15915494309189533577;
     static constexpr double kPiHalf = 1.57079632679489661923;
 };
 

@@ -50,13 +50,15 @@ def slot_class(op):
 
 
 # Issue slots per operation in the trace kernels' code, as counted by derive().
-OP_COSTS = {'f64': {'log': 28.5, 'exp': 30.0, 'expm1': 37.0, 'sqrt': 15.0, 'rsqrt': 10.0, 'rcp': 7.0, 'div': 13.0, 'sincos': 22.0}, 'f32': {'log': 2.5, 'exp': 2.5, 'expm1': 13.0, 'sqrt': 2.0, 'rsqrt': 2.0, 'rcp': 2.0, 'div': 7.0, 'sincos': 4.0}, 'filter': {'gaussian': 26.5, 'pseudo_voigt': 33.5, 'table': 17.5, 'lorentzian': 26.5, 'box': 18.0}, 'philox': 51.5}
+OP_COSTS = {'f64': {'log': 28.5, 'exp': 30.0, 'expm1': 37.0, 'sqrt': 15.0, 'rsqrt': 10.0, 'rcp': 7.0, 'div': 13.0, 'sincos': 22.0, 'sin': 127.5, 'cos': 127.5, 'asin': 86.5}, 'f32': {'log': 2.5, 'exp': 2.5, 'expm1': 13.0, 'sqrt': 2.0, 'rsqrt': 2.0, 'rcp': 2.0, 'div': 7.0, 'sincos': 4.0}, 'filter': {'gaussian': 26.5, 'pseudo_voigt': 33.5, 'table': 17.5, 'lorentzian': 26.5, 'box': 18.0}, 'philox': 51.5}
 
 PROBES = {
     ("f64", "log"): ("log_f64", "glue_f64"), ("f64", "exp"): ("exp_f64", "glue_f64"),
     ("f64", "expm1"): ("expm1_f64", "glue_f64"), ("f64", "sqrt"): ("sqrt_f64", "glue_f64"),
     ("f64", "rsqrt"): ("rsqrt_f64", "glue_f64"), ("f64", "rcp"): ("rcp_f64", "glue_f64"),
     ("f64", "div"): ("div_ieee_f64", "glue_f64"), ("f64", "sincos"): ("sincos_f64", "glue2_f64"),
+    ("f64", "sin"): ("sin_f64", "glue_f64"), ("f64", "cos"): ("cos_f64", "glue_f64"),
+    ("f64", "asin"): ("asin_f64", "glue_f64"),
     ("f32", "log"): ("log_f32", "glue_f32"), ("f32", "exp"): ("exp_f32", "glue_f32"),
     ("f32", "expm1"): ("expm1_f32", "glue_f32"), ("f32", "sqrt"): ("sqrt_f32", "glue_f32"),
     ("f32", "rsqrt"): ("rsqrt_f32", "glue_f32"), ("f32", "rcp"): ("rcp_f32", "glue_f32"),
@@ -200,3 +202,67 @@ def algorithmic_ops(workload, precision, counters):
 
 if __name__ == "__main__":
     print(derive())
+
+
+# ---- the paper's event model (FP64) ------------------------------------------
+
+def _density_cost(mosaic):
+    """Issue slots of one mosaic density value per steradian."""
+    D, a = OP_COSTS["f64"], SLOT_WEIGHT["alu64"]
+    vmf = D["exp"] + 2 * a
+    cau = D["sqrt"] + D["div"] + 7 * a
+    return {"gaussian_vmf": vmf, "lorentzian": cau, "pseudo_voigt": vmf + cau + 3 * a,
+            "wrapped_lorentzian": D["div"] + 2 * a,
+            "spherical_wrapped_lorentzian": D["div"] + 3 * a}[mosaic]
+
+
+def _irc_cost(irc):
+    D, a = OP_COSTS["f64"], SLOT_WEIGHT["alu64"]
+    return {"gaussian": D["exp"] + 3 * a, "pseudo_voigt": D["div"] + D["exp"] + 8 * a,
+            "lorentzian": D["div"] + 3 * a, "box": 2 * a, "table": 15 * a}[irc]
+
+
+def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in):
+    """Operation mix per unit of the paper's event model, in issue slots.
+
+    Units: 'ray' and 'entered' as in mix() (FP64); 'event' (one free path:
+    Philox, exit distance, frame, glancing angle, the psi quadrature of Eq.
+    SimpleReflXsection on psi_nodes intervals for the H and anti-H planes,
+    free path, absorption and plane choice); 'reflection' (burn_in sweeps of
+    the sampler, each one Philox, a psi move and a Delta move re-evaluating
+    only the factors they change, then the crystallite's orientation and the
+    reflection); 'detected' as in mix().  Sines and cosines are priced as
+    the table-driven sin/cos of turns."""
+    D, a = OP_COSTS["f64"], SLOT_WEIGHT["alu64"]
+    base = mix("fp64", geometry, "gaussian_vmf", "gaussian", spectrum)
+    cyl = geometry == "cylinder"
+    exit_d = (2 * D["sqrt"] + 6 * D["div"] + 45 * a) if cyl else (6 * D["div"] + 30 * a)
+    frame = (D["rsqrt"] + 18 * a) if cyl else 0.0
+    W = _density_cost(mosaic)
+    sc = D["sincos"]
+    quad = (2 * D["asin"] + 4 * sc + 10 * a + 2 * W
+            + psi_nodes * (2 * W + 8 * a) + sc + 3 * a)
+    event = (OP_COSTS["philox"] + 3 * 2 * a + exit_d + frame + 5 * a + quad
+             + D["log"] + 2 * D["div"] + 14 * a)
+    R = _irc_cost(irc)
+    sweep = (OP_COSTS["philox"] + 4 * 2 * a + 9 * a + sc + (W + 8 * a) + 3 * a
+             + 7 * a + R + 2 * sc + 4 * a + (W + 8 * a) + 3 * a)
+    orient = 2 * sc + 3 * D["div"] + 15 * a + 9 * a + 5 * a + 15 * a + 11 * a + D["sqrt"] + 3 * D["div"]
+    reflection = (D["asin"] + sc + D["div"] + sc + R + 2 * sc + 3 * a + W + burn_in * sweep
+                  + orient)
+    return {"ray": base["ray"], "entered": base["entered"], "event": event,
+            "reflection": reflection, "detected": base["detected"], "sweep": sweep,
+            "quadrature": quad}
+
+
+def algorithmic_ops_mwg(workload, counters, psi_nodes, burn_in):
+    """Issue slots the paper's model needs for a trace with these counters
+    (every event priced with the quadrature; events past a ray's reflection
+    cap skip it, which over-prices them slightly)."""
+    m = workload["mosaic"]
+    M = mix_mwg(workload["crystal"]["geometry"], m["kind"], workload["rocking_curve"]["kind"],
+                workload["source"]["spectrum"], psi_nodes, burn_in)
+    c = counters
+    entered = c["emitted"] - c["missed"]
+    return (c["emitted"] * M["ray"] + entered * M["entered"] + c["events"] * M["event"]
+            + c["reflections"] * M["reflection"] + c["detected"] * M["detected"])

@@ -108,7 +108,7 @@ def summarize(trace_dir, pmc_dirs, copy_fetch, copy_write, copy_mib, command, ou
     for d in pmc_dirs:
         for k, v in _per_kernel(_rows(d)).items():
             agg[k] += v
-    kernels = sorted({k for k, _ in agg if "trace_kernel" in k})
+    kernels = sorted({k for k, _ in agg if "trace_kernel" in k or "mwg_kernel" in k})
     counters = sorted({c for _, c in agg})
     if kernels:
         lines += ["Counters per dispatch (mean over dispatches of each trace kernel):", "",
