@@ -74,7 +74,9 @@ def model_of(w):
 
 class Detector(C.Structure):
     _fields_ = [("centre", D3), ("normal", D3), ("u", D3), ("v", D3),
-                ("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_double)]
+                ("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_double),
+                ("n_qe", C.c_int32), ("pad_", C.c_int32), ("qe_kev", C.POINTER(C.c_double)),
+                ("qe", C.POINTER(C.c_double))]
 
 
 class Counters(C.Structure):
@@ -196,6 +198,11 @@ class Structs:
 
         self.det = Detector(centre=_d3(d["centre"]), normal=_d3(d["normal"]), u=_d3(d["u"]),
                             v=_d3(d["v"]), nx=d["nx"], ny=d["ny"], pitch=d["pitch"])
+        qe = np.ascontiguousarray(d.get("qe") or [(0.0, 1.0)], dtype=np.float64).reshape(-1, 2)
+        self._qe_e, self._qe_v = np.ascontiguousarray(qe[:, 0]), np.ascontiguousarray(qe[:, 1])
+        self.det.n_qe = len(qe) if d.get("qe") else 0
+        self.det.qe_kev = self._qe_e.ctypes.data_as(C.POINTER(C.c_double))
+        self.det.qe = self._qe_v.ctypes.data_as(C.POINTER(C.c_double))
 
     def args(self):
         return (C.byref(self.src), C.byref(self.cr), C.byref(self.mo), C.byref(self.irc),
@@ -382,3 +389,14 @@ def crystallite(N, k, alpha, b, psi):
     n = D3()
     lib().orc_crystallite(_d3(N), _d3(k), float(alpha), float(b), float(psi), n)
     return np.array(list(n))
+
+
+def calibration_map(counts, energy_mev):
+    """Mean photon energy per pixel in keV, NaN where no photon landed
+    (sec. 3, the calibration map): (energy / counts) * 1e-6."""
+    c = np.asarray(counts).astype(np.float64)
+    e = np.asarray(energy_mev).astype(np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        m = (e / c) * 1e-6
+    m[np.asarray(counts) == 0] = np.nan
+    return m

@@ -903,6 +903,26 @@ finish:
     *margin = m;
 }
 
+/* Energy a detected photon adds to the energy image (sec. 3): E, or E times
+   the detector's quantum efficiency, the user's table interpolated linearly
+   at E with the end values held outside it. */
+static double detected_energy(const orc_detector *D, double E) {
+    int n = D->n_qe;
+    if (n <= 0) return E;
+    double q;
+    if (n == 1 || !(E > D->qe_kev[0])) {
+        q = D->qe[0];
+    } else if (!(E < D->qe_kev[n - 1])) {
+        q = D->qe[n - 1];
+    } else {
+        int j = 0;   /* the last node at or below E */
+        while (D->qe_kev[j + 1] <= E) ++j;
+        double slope = (D->qe[j + 1] - D->qe[j]) / (D->qe_kev[j + 1] - D->qe_kev[j]);
+        q = D->qe[j] + slope * (E - D->qe_kev[j]);
+    }
+    return E * q;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Threaded driver: contiguous ray-id blocks, integer image accumulation.    */
 /* ------------------------------------------------------------------------ */
@@ -940,7 +960,7 @@ static void *run_job(void *arg) {
             size_t px = (size_t)r.pix_j * (size_t)D->nx + (size_t)r.pix_i;
             if (J->counts) __atomic_fetch_add(&J->counts[px], 1u, __ATOMIC_RELAXED);
             if (J->energy)
-                __atomic_fetch_add(&J->energy[px], (uint64_t)nearbyint(r.energy * 1e6),
+                __atomic_fetch_add(&J->energy[px], (uint64_t)nearbyint(detected_energy(D, r.energy) * 1e6),
                                    __ATOMIC_RELAXED);
         }
         if (J->records) J->records[i] = r;
@@ -967,6 +987,9 @@ static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic 
     if (s->spectrum == ORC_SPEC_TABLE && (s->n_bins < 1 || !s->bin_w)) return -6;
     if (s->spectrum == ORC_SPEC_LINES && (s->n_lines < 0 || s->n_lines > 8)) return -7;
     if (d->nx <= 0 || d->ny <= 0 || d->pitch <= 0.0) return -8;
+    if (d->n_qe < 0 || (d->n_qe > 0 && (!d->qe_kev || !d->qe))) return -13;
+    for (int i = 1; i < d->n_qe; ++i)
+        if (!(d->qe_kev[i] > d->qe_kev[i - 1])) return -13;
     return 0;
 }
 

@@ -89,10 +89,14 @@ typedef struct orc_irc {
     const double *table;     /* n_table values (host) */
 } orc_irc;
 
+/* n_qe > 0: quantum efficiency table (energies strictly increasing, keV);
+   a detected photon adds rint(E QE(E) 1e6) to the energy image. */
 typedef struct orc_detector {
     double centre[3], normal[3], u[3], v[3];
     int32_t nx, ny;
     double pitch;
+    int32_t n_qe, pad_;
+    const double *qe_kev, *qe;
 } orc_detector;
 
 /* One record per ray (104 bytes). */

@@ -104,8 +104,9 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
     {
         const size_t lut = r->kind == MRT_IRC_TABLE ? (size_t)r->n_table : 0;
         const size_t cdf = s->spectrum == MRT_SPECTRUM_TABLE ? (size_t)s->n_bins + 1 : 0;
-        if ((lut + cdf) * sizeof(double) > (size_t)kMaxTableBytes)
-            return fail(MRT_EINVAL, "rocking-curve table plus spectrum bins exceed %d bytes",
+        const size_t qe = d->n_qe > 0 ? 2 * (size_t)d->n_qe : 0;
+        if ((lut + cdf + qe) * sizeof(double) > (size_t)kMaxTableBytes)
+            return fail(MRT_EINVAL, "rocking-curve table, spectrum bins and QE table exceed %d bytes",
                         kMaxTableBytes);
     }
     // detector
@@ -115,6 +116,17 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
     if (d->nx < 1 || d->ny < 1 || (int64_t)d->nx * (int64_t)d->ny >= (int64_t(1) << 31))
         return fail(MRT_EINVAL, "detector: need nx, ny >= 1 and nx * ny < 2^31");
     if (!(d->pitch > 0.0)) return fail(MRT_EINVAL, "detector: pitch must be > 0");
+    if (d->n_qe < 0 || d->n_qe > kMaxQeNodes)
+        return fail(MRT_EINVAL, "detector: n_qe must lie in [0, %d]", kMaxQeNodes);
+    if (d->n_qe > 0) {
+        if (!d->qe_kev || !d->qe) return fail(MRT_EINVAL, "detector: QE table pointers are NULL");
+        for (int i = 0; i < d->n_qe; ++i) {
+            if (!std::isfinite(d->qe_kev[i]) || !(d->qe[i] >= 0.0 && d->qe[i] <= 1.0))
+                return fail(MRT_EINVAL, "detector: QE values must lie in [0, 1] at finite energies");
+            if (i && !(d->qe_kev[i] > d->qe_kev[i - 1]))
+                return fail(MRT_EINVAL, "detector: QE energies must increase strictly");
+        }
+    }
     return MRT_OK;
 }
 
@@ -366,6 +378,12 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
     P.pitch = d->pitch;
     P.half_nx = (double)d->nx / 2.0;
     P.half_ny = (double)d->ny / 2.0;
+    P.qe_n = d->n_qe;
+    P.qe_at = (int32_t)tables.size();
+    if (d->n_qe > 0) {
+        tables.insert(tables.end(), d->qe_kev, d->qe_kev + d->n_qe);
+        tables.insert(tables.end(), d->qe, d->qe + d->n_qe);
+    }
 
     // FP32 copies for the FP32-mixed kernels (round to nearest)
 #define MRT_F32_S(n) P.f32.n = (float)P.n;

@@ -92,6 +92,16 @@ mrt_status mrt_get_device_info(mrt_device_info *info) {
     return MRT_OK;
 }
 
+mrt_status mrt_calibration_map(const uint32_t *d_counts, const uint64_t *d_energy_mev,
+                               uint64_t n_pixels, double *d_map_kev, void *hip_stream) {
+    mrt::clear_error();
+    if (!d_counts || !d_energy_mev || !d_map_kev)
+        return fail(MRT_EINVAL, "calibration map: NULL image or map pointer");
+    if (mrt::launch_calibration_map(d_counts, d_energy_mev, (size_t)n_pixels, d_map_kev, hip_stream) != 0)
+        return fail(MRT_EDEVICE, "calibration map launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return MRT_OK;
+}
+
 mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
                      const mrt_mosaic *mosaic, const mrt_rocking_curve *rocking_curve,
                      const mrt_detector *detector, uint64_t first_ray_id, uint64_t n_rays,
@@ -170,6 +180,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
                     ? dtab + (rocking_curve->kind == MRT_IRC_TABLE ? rocking_curve->n_table : 0)
                     : nullptr;
     P.psi_tab = mwg ? dtab + psi_at : nullptr;
+    P.qe = P.qe_n > 0 ? dtab + P.qe_at : nullptr;
 
     auto release = [&](mrt_status s) {
         (void)hipFreeAsync(scratch, stream);

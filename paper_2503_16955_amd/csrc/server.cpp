@@ -136,6 +136,7 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     const int nl = P.irc == MRT_IRC_TABLE ? P.lut_n : 0;
     P.lut = nl ? r.d_tables : nullptr;
     P.bin_cdf = P.spectrum == MRT_SPECTRUM_TABLE ? r.d_tables + nl : nullptr;
+    P.qe = P.qe_n > 0 ? r.d_tables + P.qe_at : nullptr;
     P.dev_counters = S->d_counters + (size_t)slot * mrt::kNumCounters;
     P.records_mode = MRT_RECORDS_NONE;
     P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : 8u;

@@ -593,6 +593,25 @@ struct Tracer {
         }
     }
 
+    // ---- detector quantum efficiency (sec. 3): the table interpolated
+    // linearly at E, end values held outside, evaluated as
+    // q_j + (q_{j+1} - q_j) / (e_{j+1} - e_j) * (E - e_j) with separately
+    // rounded operations (no fused multiply-add), j the last node <= E.
+    static __device__ __forceinline__ double qe_weight(const TraceParams &P, double E) {
+        const int n = P.qe_n;
+        const double *e = P.qe, *q = P.qe + n;
+        if (n == 1 || !(E > e[0])) return q[0];
+        if (!(E < e[n - 1])) return q[n - 1];
+        int lo = 0, hi = n - 1;   // e[lo] <= E < e[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (e[mid] <= E) lo = mid;
+            else hi = mid;
+        }
+        const double slope = __ddiv_rn(__dsub_rn(q[lo + 1], q[lo]), __dsub_rn(e[lo + 1], e[lo]));
+        return __dadd_rn(q[lo], __dmul_rn(slope, __dsub_rn(E, e[lo])));
+    }
+
     // ---- end of a ray: detector (sec. 2.3) and images -------------------------
     // Returns true when the ray lands on a pixel.
     static __device__ __forceinline__ bool finish(const TraceParams &P, const RayT &ry, int status) {
@@ -618,8 +637,10 @@ struct Tracer {
                         end = h;
                         const size_t px = (size_t)pj * (size_t)P.nx + (size_t)pi;
                         atomicAdd(&P.counts[px], 1u);
-                        if (P.energy)
-                            atomicAdd(&P.energy[px], (unsigned long long)__builtin_rint(ry.E * 1e6));
+                        if (P.energy) {
+                            const double ew = P.qe_n > 0 ? __dmul_rn(ry.E, qe_weight(P, ry.E)) : ry.E;
+                            atomicAdd(&P.energy[px], (unsigned long long)__builtin_rint(ew * 1e6));
+                        }
                     }
                 }
             }

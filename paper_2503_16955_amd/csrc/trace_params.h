@@ -94,6 +94,8 @@ struct TraceParams {
     double dP[3], dn[3], du[3], dv[3];
     int32_t nx, ny;
     double pitch, half_nx, half_ny;
+    int32_t qe_n, qe_at;          // quantum-efficiency nodes; their index in the tables
+    const double *qe;             // qe_n energies (keV), then qe_n values (device)
 
     // ---- run
     uint64_t first, n, seed;
@@ -135,6 +137,9 @@ struct ServeItem {
 // combination (nullptr for an unknown kind).
 const void *trace_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records);
 int launch_zero(void *ptr_u32, size_t n_words, void *stream);
+int launch_calibration_map(const uint32_t *counts, const uint64_t *energy, size_t n, double *map,
+                           void *stream);
+constexpr int kMaxQeNodes = 1024;
 // Serving kernel of a precision: (const TraceParams *slots, const ServeItem
 // *items, uint32_t n_items, uint64_t total, unsigned long long *cursors), one
 // zeroed cursor per item.

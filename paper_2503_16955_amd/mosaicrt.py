@@ -65,7 +65,9 @@ class MrtRockingCurve(C.Structure):
 
 class MrtDetector(C.Structure):
     _fields_ = [("centre", _D3), ("normal", _D3), ("u", _D3), ("v", _D3),
-                ("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_double)]
+                ("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_double),
+                ("n_qe", C.c_int32), ("pad_", C.c_int32), ("qe_kev", C.POINTER(C.c_double)),
+                ("qe", C.POINTER(C.c_double))]
 
 
 class MrtOptions(C.Structure):
@@ -116,7 +118,8 @@ RECORD_BYTES = 104
 assert RECORD_DTYPE.itemsize == RECORD_BYTES
 
 # Every symbol the header declares.
-EXPORTS = ("mrt_trace", "mrt_get_device_info", "mrt_last_error", "mrt_version")
+EXPORTS = ("mrt_trace", "mrt_get_device_info", "mrt_last_error", "mrt_version",
+           "mrt_calibration_map")
 
 
 class MosaicRTError(RuntimeError):
@@ -155,6 +158,8 @@ def load():
     L.mrt_last_error.argtypes = []
     L.mrt_version.restype = C.c_int
     L.mrt_version.argtypes = []
+    L.mrt_calibration_map.restype = C.c_int
+    L.mrt_calibration_map.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]
     _lib = L
     return L
 
@@ -221,6 +226,13 @@ class Structs:
         self.detector = MrtDetector(centre=_v3(d["centre"]), normal=_v3(d["normal"]),
                                     u=_v3(d["u"]), v=_v3(d["v"]), nx=int(d["nx"]),
                                     ny=int(d["ny"]), pitch=float(d["pitch"]))
+        # quantum efficiency: d["qe"] = [(E_keV, QE), ...] with E increasing
+        qe = np.ascontiguousarray(d.get("qe") or [(0.0, 1.0)], dtype=np.float64).reshape(-1, 2)
+        self._qe_e = np.ascontiguousarray(qe[:, 0])
+        self._qe_v = np.ascontiguousarray(qe[:, 1])
+        self.detector.n_qe = len(qe) if d.get("qe") else 0
+        self.detector.qe_kev = self._qe_e.ctypes.data_as(C.POINTER(C.c_double))
+        self.detector.qe = self._qe_v.ctypes.data_as(C.POINTER(C.c_double))
 
     def refs(self):
         return (C.byref(self.source), C.byref(self.crystal), C.byref(self.mosaic),
@@ -291,6 +303,28 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
         out["counters"] = {f: int(getattr(cnt, f)) for f in COUNTER_FIELDS}
         out["counters"]["kernel_ms"] = float(cnt.kernel_ms)
     return out
+
+
+def calibration_map(counts, energy, stream=None):
+    """Mean photon energy per pixel (keV; NaN where no photon landed) of
+    device images, by ``mrt_calibration_map``: a float64 device tensor."""
+    import torch
+    L = load()
+    m = torch.empty(counts.shape, dtype=torch.float64, device=counts.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(counts.device)
+    _check(L.mrt_calibration_map(C.c_void_p(counts.data_ptr()), C.c_void_p(energy.data_ptr()),
+                                 counts.numel(), C.c_void_p(m.data_ptr()),
+                                 C.c_void_p(stream.cuda_stream)))
+    return m
+
+
+def calibrate(w, e_min, e_max, n_rays=None, **kw):
+    """Trace the calibration run of `w` (workloads.calibration_workload) and
+    return (counts, energy, map)."""
+    from .workloads import calibration_workload
+    out = trace(calibration_workload(w, e_min, e_max), n_rays=n_rays, **kw)
+    return out["counts"], out["energy"], calibration_map(out["counts"], out["energy"])
 
 
 def records_to_numpy(rec, count=None):

@@ -189,3 +189,15 @@ _PLACEMENT_TABLE_RAD = [0.25244, 0.24901, 0.24566, 0.24241, 0.23924, 0.23615, 0.
 
 def placement_angle(energy_kev: float) -> float:
     return float(np.interp(energy_kev, _PLACEMENT_TABLE_KEV, _PLACEMENT_TABLE_RAD))
+
+
+def calibration_workload(w, e_min, e_max):
+    """The paper's calibration run (sec. 3): the same spectrometer with photon
+    energies uniform over [e_min, e_max] keV and no detector efficiency."""
+    c = copy.deepcopy(w)
+    c["source"] = dict(c["source"], spectrum="uniform", e_min=float(e_min), e_max=float(e_max))
+    c["source"].pop("lines", None)
+    c["detector"] = dict(c["detector"])
+    c["detector"].pop("qe", None)
+    c["name"] = w["name"] + "_calibration"
+    return c

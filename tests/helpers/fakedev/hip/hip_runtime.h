@@ -60,6 +60,10 @@ inline long long __double_as_longlong(double x) { long long r; memcpy(&r, &x, 8)
 inline double __longlong_as_double(long long x) { double r; memcpy(&r, &x, 8); return r; }
 
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
+inline double __dadd_rn(double a, double b) { return a + b; }
+inline double __dsub_rn(double a, double b) { return a - b; }
+inline double __dmul_rn(double a, double b) { return a * b; }
+inline double __ddiv_rn(double a, double b) { return a / b; }
 inline double __builtin_amdgcn_rsq(double x) { return 1.0 / std::sqrt(x); }
 inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
 inline float __builtin_amdgcn_rsqf(float x) { return 1.0f / std::sqrt(x); }

@@ -174,6 +174,7 @@ int emu_build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic
     P->lut = P->irc == MRT_IRC_TABLE ? tables_out : nullptr;
     P->bin_cdf = P->spectrum == MRT_SPECTRUM_TABLE ? tables_out + (P->irc == MRT_IRC_TABLE ? P->lut_n : 0)
                                                    : nullptr;
+    P->qe = P->qe_n > 0 ? tables_out + P->qe_at : nullptr;
     return 0;
 }
 int emu_params_size() { return (int)sizeof(TraceParams); }

@@ -46,7 +46,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(mrt.MrtCrystal) == 224
     assert C.sizeof(mrt.MrtMosaic) == 24
     assert C.sizeof(mrt.MrtRockingCurve) == 72
-    assert C.sizeof(mrt.MrtDetector) == 112
+    assert C.sizeof(mrt.MrtDetector) == 136
     assert C.sizeof(mrt.MrtOptions) == 48
     assert C.sizeof(mrt.MrtCounters) == 96
     assert mrt.RECORD_DTYPE.itemsize == 104
@@ -143,6 +143,23 @@ def test_invalid_run_arguments():
                  n=1000) == mrt.ECAPACITY
     assert _call(w, opts=mrt.MrtOptions(block_threads=96)) == mrt.EINVAL
     assert _call(w, opts=mrt.MrtOptions(grid_blocks=-1)) == mrt.EINVAL
+
+
+def test_invalid_qe_tables_and_calibration_arguments():
+    # QE: energies strictly increasing, values in [0, 1], at most 1024 nodes;
+    # the calibration map needs its three device pointers
+    for table in ([(8.0, 0.5), (8.0, 0.6)], [(8.1, 0.5), (8.0, 0.6)], [(8.0, 1.5)],
+                  [(8.0, -0.1)], [(float("nan"), 0.5)], [(7.0 + i * 1e-3, 0.5) for i in range(1025)]):
+        w = W.get("flat_hopg")
+        w["detector"]["qe"] = table
+        assert _call(w) == mrt.EINVAL, table
+    w = W.get("flat_hopg")
+    w["detector"]["qe"] = [(7.0, 0.5), (9.0, 0.6)]
+    assert _call(w) != mrt.EINVAL      # valid: fails later, at the device
+    L = mrt.load()
+    assert L.mrt_calibration_map(None, C.c_void_p(8), 10, C.c_void_p(8), None) == mrt.EINVAL
+    assert L.mrt_calibration_map(C.c_void_p(8), None, 10, C.c_void_p(8), None) == mrt.EINVAL
+    assert L.mrt_calibration_map(C.c_void_p(8), C.c_void_p(8), 10, None, None) == mrt.EINVAL
 
 
 def test_invalid_event_model_options():
