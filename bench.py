@@ -317,7 +317,7 @@ def main():
     ap.add_argument("--mwg-steps", type=int, default=3, help="steps of the paper's event model")
     ap.add_argument("--mwg-burn-in", type=int, default=500)
     ap.add_argument("--mwg-psi-nodes", type=int, default=256)
-    ap.add_argument("--mwg-cpu-rays", type=int, default=10_000_000)
+    ap.add_argument("--mwg-cpu-rays", type=int, default=20_000_000)
     ap.add_argument("--no-mwg", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

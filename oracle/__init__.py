@@ -56,7 +56,9 @@ class Irc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_table", C.c_int32), ("peak", C.c_double),
                 ("shift", C.c_double), ("fwhm", C.c_double), ("fwhm_g", C.c_double),
                 ("fwhm_l", C.c_double), ("x_min", C.c_double), ("x_max", C.c_double),
-                ("table", C.POINTER(C.c_double))]
+                ("table", C.POINTER(C.c_double)), ("n_dep", C.c_int32), ("pad_", C.c_int32),
+                ("dep_kev", C.POINTER(C.c_double)), ("dep_shift", C.POINTER(C.c_double)),
+                ("dep_scale", C.POINTER(C.c_double))]
 
 
 class Model(C.Structure):
@@ -195,6 +197,12 @@ class Structs:
         self._table = np.ascontiguousarray(r.get("table", [0.0]), dtype=np.float64)
         self.irc.n_table = len(self._table) if r["kind"] == "table" else 0
         self.irc.table = self._table.ctypes.data_as(C.POINTER(C.c_double))
+        dep = np.ascontiguousarray(r.get("energy_dependence") or [(0.0, 0.0, 1.0)],
+                                   dtype=np.float64).reshape(-1, 3)
+        self._dep = [np.ascontiguousarray(dep[:, i]) for i in range(3)]
+        self.irc.n_dep = len(dep) if r.get("energy_dependence") else 0
+        P_ = C.POINTER(C.c_double)
+        self.irc.dep_kev, self.irc.dep_shift, self.irc.dep_scale = (a.ctypes.data_as(P_) for a in self._dep)
 
         self.det = Detector(centre=_d3(d["centre"]), normal=_d3(d["normal"]), u=_d3(d["u"]),
                             v=_d3(d["v"]), nx=d["nx"], ny=d["ny"], pitch=d["pitch"])

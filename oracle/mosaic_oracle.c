@@ -124,6 +124,17 @@ double orc_bragg_angle(double energy_kev, double two_d) {
     return asin(s);
 }
 
+/* Linear interpolation of a table of the photon energy (nodes x strictly
+   increasing), the end values held outside it. */
+static double interp_clamped(const double *x, const double *y, int n, double E) {
+    if (n == 1 || !(E > x[0])) return y[0];
+    if (!(E < x[n - 1])) return y[n - 1];
+    int j = 0;   /* the last node at or below E */
+    while (x[j + 1] <= E) ++j;
+    double slope = (y[j + 1] - y[j]) / (x[j + 1] - x[j]);
+    return y[j] + slope * (E - x[j]);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Intrinsic rocking curve (sec. 2.2.1).                                     */
 /* ------------------------------------------------------------------------ */
@@ -872,7 +883,16 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
         double akn = fabs(kn);
         if (akn > 1.0) akn = 1.0;
         double delta = asin(akn) - alpha_b;
-        double ratio = orc_irc_value(X->irc, delta - X->irc->shift) / X->r_max;
+        double arg = delta - X->irc->shift;
+        if (X->irc->n_dep > 0) {
+            /* the curve of this energy (sec. 2.2.1): shifted to Delta_M(E),
+               its width scaled by s(E) */
+            const orc_irc *q = X->irc;
+            double sh = interp_clamped(q->dep_kev, q->dep_shift, q->n_dep, E);
+            double sc = interp_clamped(q->dep_kev, q->dep_scale, q->n_dep, E);
+            arg = (delta - sh) / sc;
+        }
+        double ratio = orc_irc_value(X->irc, arg) / X->r_max;
         note(&m, u_acc - ratio);
         if (u_acc < ratio) {
             /* reflection equation of sec. 2.2.4 */
@@ -907,20 +927,8 @@ finish:
    the detector's quantum efficiency, the user's table interpolated linearly
    at E with the end values held outside it. */
 static double detected_energy(const orc_detector *D, double E) {
-    int n = D->n_qe;
-    if (n <= 0) return E;
-    double q;
-    if (n == 1 || !(E > D->qe_kev[0])) {
-        q = D->qe[0];
-    } else if (!(E < D->qe_kev[n - 1])) {
-        q = D->qe[n - 1];
-    } else {
-        int j = 0;   /* the last node at or below E */
-        while (D->qe_kev[j + 1] <= E) ++j;
-        double slope = (D->qe[j + 1] - D->qe[j]) / (D->qe_kev[j + 1] - D->qe_kev[j]);
-        q = D->qe[j] + slope * (E - D->qe_kev[j]);
-    }
-    return E * q;
+    if (D->n_qe <= 0) return E;
+    return E * interp_clamped(D->qe_kev, D->qe, D->n_qe, E);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -984,6 +992,11 @@ static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic 
     if (c->geometry == ORC_GEOM_CYLINDER && !(c->width / (2.0 * c->radius) < ORC_PI / 2.0)) return -3;
     if (m->fwhm < 0.0 || m->eta < 0.0 || m->eta > 1.0) return -4;
     if (irc->kind == ORC_IRC_TABLE && (irc->n_table < 2 || !irc->table)) return -5;
+    if (irc->n_dep < 0 || (irc->n_dep > 0 && (!irc->dep_kev || !irc->dep_shift || !irc->dep_scale)))
+        return -14;
+    for (int i = 0; i < irc->n_dep; ++i)
+        if (!(irc->dep_scale[i] > 0.0) || (i && !(irc->dep_kev[i] > irc->dep_kev[i - 1]))) return -14;
+    if (irc->n_dep > 0 && model && model->kind == ORC_MODEL_MWG) return -15;
     if (s->spectrum == ORC_SPEC_TABLE && (s->n_bins < 1 || !s->bin_w)) return -6;
     if (s->spectrum == ORC_SPEC_LINES && (s->n_lines < 0 || s->n_lines > 8)) return -7;
     if (d->nx <= 0 || d->ny <= 0 || d->pitch <= 0.0) return -8;

@@ -87,6 +87,11 @@ typedef struct orc_irc {
     double fwhm_g, fwhm_l;   /* pseudo-Voigt components */
     double x_min, x_max;     /* table range */
     const double *table;     /* n_table values (host) */
+    /* n_dep > 0: the curve of a photon of energy E is r((Delta -
+       Delta_M(E)) / s(E)), Delta_M and s interpolated linearly (end values
+       held) from (dep_kev, dep_shift) and (dep_kev, dep_scale) */
+    int32_t n_dep, pad_;
+    const double *dep_kev, *dep_shift, *dep_scale;
 } orc_irc;
 
 /* n_qe > 0: quantum efficiency table (energies strictly increasing, keV);

@@ -91,7 +91,7 @@ extern "C" __global__ void probe_glue_u32(const unsigned *__restrict__ a, unsign
         for (int j = 0; j < n; ++j)                                                            \
             x = x * 0.5 + (double)tk::Tracer<double, MRT_GEOMETRY_CYLINDER,                    \
                                              MRT_MOSAIC_PSEUDO_VOIGT, IRC, false>::filter(     \
-                              P, x, sa, ca, u);                                                \
+                              P, x, sa, ca, u, P.f32.shift, 1.0f);                            \
         o[i] = x;                                                                              \
     }
 FILTER_PROBE(filter_gaussian, MRT_IRC_GAUSSIAN)

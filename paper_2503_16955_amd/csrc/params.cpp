@@ -101,11 +101,25 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
         return fail(MRT_EINVAL, "rocking curve: unknown kind");
     }
     if (!std::isfinite(r->shift)) return fail(MRT_EINVAL, "rocking curve: bad shift");
+    if (r->n_dep < 0 || r->n_dep > kMaxQeNodes)
+        return fail(MRT_EINVAL, "rocking curve: n_dep must lie in [0, %d]", kMaxQeNodes);
+    if (r->n_dep > 0) {
+        if (!r->dep_kev || !r->dep_shift || !r->dep_scale)
+            return fail(MRT_EINVAL, "rocking curve: energy-dependence table pointers are NULL");
+        for (int i = 0; i < r->n_dep; ++i) {
+            if (!std::isfinite(r->dep_kev[i]) || !std::isfinite(r->dep_shift[i]) ||
+                !(r->dep_scale[i] > 0.0 && std::isfinite(r->dep_scale[i])))
+                return fail(MRT_EINVAL, "rocking curve: energy dependence needs finite shifts and scales > 0");
+            if (i && !(r->dep_kev[i] > r->dep_kev[i - 1]))
+                return fail(MRT_EINVAL, "rocking curve: energy-dependence energies must increase strictly");
+        }
+    }
     {
         const size_t lut = r->kind == MRT_IRC_TABLE ? (size_t)r->n_table : 0;
         const size_t cdf = s->spectrum == MRT_SPECTRUM_TABLE ? (size_t)s->n_bins + 1 : 0;
         const size_t qe = d->n_qe > 0 ? 2 * (size_t)d->n_qe : 0;
-        if ((lut + cdf + qe) * sizeof(double) > (size_t)kMaxTableBytes)
+        const size_t dep = r->n_dep > 0 ? 3 * (size_t)r->n_dep : 0;
+        if ((lut + cdf + qe + dep) * sizeof(double) > (size_t)kMaxTableBytes)
             return fail(MRT_EINVAL, "rocking-curve table, spectrum bins and QE table exceed %d bytes",
                         kMaxTableBytes);
     }
@@ -378,6 +392,13 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
     P.pitch = d->pitch;
     P.half_nx = (double)d->nx / 2.0;
     P.half_ny = (double)d->ny / 2.0;
+    P.dep_n = r->n_dep;
+    P.dep_at = (int32_t)tables.size();
+    if (r->n_dep > 0) {
+        tables.insert(tables.end(), r->dep_kev, r->dep_kev + r->n_dep);
+        tables.insert(tables.end(), r->dep_shift, r->dep_shift + r->n_dep);
+        tables.insert(tables.end(), r->dep_scale, r->dep_scale + r->n_dep);
+    }
     P.qe_n = d->n_qe;
     P.qe_at = (int32_t)tables.size();
     if (d->n_qe > 0) {

@@ -133,6 +133,8 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     if (opt.event_model != MRT_MODEL_STEPPING && !mwg) return fail(MRT_EINVAL, "options: unknown event model");
     if (mwg) {
         if (opt.precision != MRT_FP64) return fail(MRT_EINVAL, "options: the MWG event model runs in FP64");
+        if (rocking_curve->n_dep > 0)
+            return fail(MRT_EINVAL, "the MWG event model takes no energy-dependent rocking curve");
         if (!(mosaic->fwhm > 0.0)) return fail(MRT_EINVAL, "the MWG event model needs a mosaic fwhm > 0");
         if (opt.mwg_burn_in < MRT_MWG_NO_BURN_IN) return fail(MRT_EINVAL, "options: mwg_burn_in must be >= -1");
         if (opt.psi_nodes < 0 || opt.psi_nodes > mrt::kMaxPsiNodes)
@@ -181,6 +183,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
                     : nullptr;
     P.psi_tab = mwg ? dtab + psi_at : nullptr;
     P.qe = P.qe_n > 0 ? dtab + P.qe_at : nullptr;
+    P.dep = P.dep_n > 0 ? dtab + P.dep_at : nullptr;
 
     auto release = [&](mrt_status s) {
         (void)hipFreeAsync(scratch, stream);
@@ -206,6 +209,8 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
 
     const bool rec = opt.records_mode != MRT_RECORDS_NONE;
     const void *kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec)
+                         : rocking_curve->n_dep > 0
+                             ? mrt::edep_kernel_ptr(opt.precision, rec)
                              : mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
                                                      rocking_curve->kind, rec);
     if (!kernel) return release(fail(MRT_EINVAL, "no kernel for this combination of kinds"));

@@ -167,7 +167,9 @@ template <class R, bool REC> struct RayQueue : QueueEntry<R, REC> {
 // the branches stay wave-uniform).
 constexpr int kAny = -1;
 
-template <class R, int GEOM, int MDF, int IRC, bool REC>
+// EDEP: the rocking curve's shift and width depend on the photon energy
+// (tables interpolated per event; run-time kinds only).
+template <class R, int GEOM, int MDF, int IRC, bool REC, bool EDEP = false>
 struct Tracer {
     using RayT = Ray<R, REC>;
     static constexpr bool kF64 = sizeof(R) == 8;
@@ -409,13 +411,16 @@ struct Tracer {
             return h2 * __builtin_amdgcn_rcpf(h2 + a2);
         }
     }
+    // With EDEP the curve is read at x / s: the bounds of x are scaled by
+    // 1/s (inv_s, rounded to float) and widened by 2^-20 relative, which
+    // covers the float roundings of inv_s and of the products.
     static __device__ __forceinline__ int filter(const TraceParams &P, double akn, float saf,
-                                                 float caf, float u_acc) {
+                                                 float caf, float u_acc, float shift,
+                                                 float inv_s) {
         const float c = (float)akn;
         const float cw = __builtin_amdgcn_sqrtf(__builtin_fmaf(-c, c, 1.0f));
         if (!(cw >= 0.1f)) return -1;   // normal within ~6 deg of k: no bound
         const float z = __builtin_fmaf(c, caf, -cw * saf);
-        const float shift = P.f32.shift;
         float lo, hi, slo, shi;   // bounds of |x| and of x
         if (__builtin_fabsf(z) <= 0.25f) {
             const float w = z * z;
@@ -438,6 +443,15 @@ struct Tracer {
             hi = INFINITY;
         }
         lo = lo > 0.0f ? lo : 0.0f;
+        if constexpr (EDEP) {
+            const float up = 1.0f + 0x1p-20f, dn = 1.0f - 0x1p-20f;
+            lo *= inv_s * dn;
+            hi *= inv_s * up;   // INFINITY stays
+            slo *= inv_s;
+            shi *= inv_s;
+            slo -= __builtin_fabsf(slo) * 0x1p-20f;
+            shi += __builtin_fabsf(shi) * 0x1p-20f;
+        }
         if (irc_is(P, MRT_IRC_TABLE)) {
             // zero outside [x_min, x_max]
             const float x0 = P.f32.lut_x0, x1 = P.f32.lut_x1;
@@ -500,12 +514,26 @@ struct Tracer {
                           (double)ry.k.z * (double)n.z;
         double akn = __builtin_fabs(kn);
         akn = akn < 1.0 ? akn : 1.0;
-        int dec = filter(P, akn, ry.saf, ry.caf, (float)u_acc);
-        if (dec < 0) {
-            // exact: Delta = asin|k.n| - alpha_B in FP64 (Eq. BraggLaw)
-            refined = true;
-            const double x = (::asin(akn) - ::asin(ry.sa)) - P.shift;
-            dec = u_acc < irc_ratio(P, lut, x) ? 1 : 0;
+        int dec;
+        if constexpr (EDEP) {
+            // Delta_M(E) and the width scale s(E) (sec. 2.2.1): r read at
+            // (Delta - Delta_M(E)) / s(E)
+            const double shift = interp(P.dep, P.dep + P.dep_n, P.dep_n, ry.E);
+            const double scale = interp(P.dep, P.dep + 2 * P.dep_n, P.dep_n, ry.E);
+            dec = filter(P, akn, ry.saf, ry.caf, (float)u_acc, (float)shift, (float)(1.0 / scale));
+            if (dec < 0) {
+                refined = true;
+                const double x = ((::asin(akn) - ::asin(ry.sa)) - shift) / scale;
+                dec = u_acc < irc_ratio(P, lut, x) ? 1 : 0;
+            }
+        } else {
+            dec = filter(P, akn, ry.saf, ry.caf, (float)u_acc, P.f32.shift, 1.0f);
+            if (dec < 0) {
+                // exact: Delta = asin|k.n| - alpha_B in FP64 (Eq. BraggLaw)
+                refined = true;
+                const double x = (::asin(akn) - ::asin(ry.sa)) - P.shift;
+                dec = u_acc < irc_ratio(P, lut, x) ? 1 : 0;
+            }
         }
         if (dec) {
             // reflection equation of sec. 2.2.4
@@ -593,13 +621,12 @@ struct Tracer {
         }
     }
 
-    // ---- detector quantum efficiency (sec. 3): the table interpolated
-    // linearly at E, end values held outside, evaluated as
+    // ---- tables of the photon energy: nodes e (increasing), values q,
+    // interpolated linearly at E with the end values held outside, as
     // q_j + (q_{j+1} - q_j) / (e_{j+1} - e_j) * (E - e_j) with separately
     // rounded operations (no fused multiply-add), j the last node <= E.
-    static __device__ __forceinline__ double qe_weight(const TraceParams &P, double E) {
-        const int n = P.qe_n;
-        const double *e = P.qe, *q = P.qe + n;
+    static __device__ __forceinline__ double interp(const double *e, const double *q, int n,
+                                                    double E) {
         if (n == 1 || !(E > e[0])) return q[0];
         if (!(E < e[n - 1])) return q[n - 1];
         int lo = 0, hi = n - 1;   // e[lo] <= E < e[hi]
@@ -610,6 +637,10 @@ struct Tracer {
         }
         const double slope = __ddiv_rn(__dsub_rn(q[lo + 1], q[lo]), __dsub_rn(e[lo + 1], e[lo]));
         return __dadd_rn(q[lo], __dmul_rn(slope, __dsub_rn(E, e[lo])));
+    }
+    // detector quantum efficiency (sec. 3)
+    static __device__ __forceinline__ double qe_weight(const TraceParams &P, double E) {
+        return interp(P.qe, P.qe + P.qe_n, P.qe_n, E);
     }
 
     // ---- end of a ray: detector (sec. 2.3) and images -------------------------
@@ -902,6 +933,18 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
     // slower with it (FP32-mixed: 2-16% faster; FP64 flat: 8-10% faster).
     constexpr bool kDefer = !T::kF64 || GEOM == MRT_GEOMETRY_FLAT;
     trace_loop<T, kDefer>(Q, Q.lut, Q.bin_cdf, claim, q);
+}
+
+// The same loop for rocking curves whose shift and width depend on the
+// photon energy, with every kind read at run time.
+template <class R, bool REC>
+__global__ void __launch_bounds__(256) trace_kernel_edep(const TraceParams P) {
+    using T = Tracer<R, kAny, kAny, kAny, REC, true>;
+    const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
+    RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
+    __shared__ RayQueue<R, REC> queues[4];
+    RayQueue<R, REC> &q = queues[uniform(threadIdx.x >> 6)];
+    trace_loop<T, !T::kF64>(Q, Q.lut, Q.bin_cdf, claim, q);
 }
 
 }  // namespace tk

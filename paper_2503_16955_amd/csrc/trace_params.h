@@ -78,6 +78,8 @@ struct TraceParams {
     double lor_h2, box_half;
     double lut_x0, lut_x1, lut_scale, lut_inv_max;
     const double *lut;            // device
+    int32_t dep_n, dep_at;        // energy-dependence nodes; their index in the tables
+    const double *dep;            // dep_n energies, shifts, width scales (device)
 
     // ---- the paper's event model (sec. 2.2.3, 2.2.4; FP64 kernels only)
     int32_t burn_in, psi_nodes;   // sampler sweeps; psi quadrature intervals
@@ -147,6 +149,9 @@ const void *serve_kernel_ptr(int precision);
 // Kernel of the paper's event model (FP64) for a geometry (nullptr for an
 // unknown one): (TraceParams), like the trace kernels.
 const void *mwg_kernel_ptr(int geometry, bool records);
+// Kernel for rocking curves whose shift and width depend on the photon
+// energy (every kind read at run time).
+const void *edep_kernel_ptr(int precision, bool records);
 constexpr int kMaxPsiNodes = 2048;
 
 }  // namespace mrt

@@ -60,7 +60,9 @@ class MrtRockingCurve(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_table", C.c_int32), ("peak", C.c_double),
                 ("shift", C.c_double), ("fwhm", C.c_double), ("fwhm_g", C.c_double),
                 ("fwhm_l", C.c_double), ("x_min", C.c_double), ("x_max", C.c_double),
-                ("table", C.POINTER(C.c_double))]
+                ("table", C.POINTER(C.c_double)), ("n_dep", C.c_int32), ("pad_", C.c_int32),
+                ("dep_kev", C.POINTER(C.c_double)), ("dep_shift", C.POINTER(C.c_double)),
+                ("dep_scale", C.POINTER(C.c_double))]
 
 
 class MrtDetector(C.Structure):
@@ -221,6 +223,13 @@ class Structs:
         self._table = np.ascontiguousarray(r.get("table", [0.0]), dtype=np.float64)
         rc.n_table = len(self._table) if r["kind"] == "table" else 0
         rc.table = self._table.ctypes.data_as(C.POINTER(C.c_double))
+        # energy dependence: r["energy_dependence"] = [(E_keV, shift_rad, width_scale), ...]
+        dep = np.ascontiguousarray(r.get("energy_dependence") or [(0.0, 0.0, 1.0)],
+                                   dtype=np.float64).reshape(-1, 3)
+        self._dep = [np.ascontiguousarray(dep[:, i]) for i in range(3)]
+        rc.n_dep = len(dep) if r.get("energy_dependence") else 0
+        P = C.POINTER(C.c_double)
+        rc.dep_kev, rc.dep_shift, rc.dep_scale = (a.ctypes.data_as(P) for a in self._dep)
         self.rocking_curve = rc
 
         self.detector = MrtDetector(centre=_v3(d["centre"]), normal=_v3(d["normal"]),

@@ -137,9 +137,9 @@ void serve_body(const TraceParams *slots, const ServeItem *items, uint32_t n, ui
                                                     *(RayQueue<R, false> *)queue);
 }
 
-template <class R, bool REC>
+template <class R, bool REC, bool EDEP = false>
 void trace_body(const TraceParams &P, void *queue) {
-    using T = Tracer<R, kAny, kAny, kAny, REC>;
+    using T = Tracer<R, kAny, kAny, kAny, REC, EDEP>;
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
     trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(RayQueue<R, REC> *)queue);
 }
@@ -175,6 +175,7 @@ int emu_build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic
     P->bin_cdf = P->spectrum == MRT_SPECTRUM_TABLE ? tables_out + (P->irc == MRT_IRC_TABLE ? P->lut_n : 0)
                                                    : nullptr;
     P->qe = P->qe_n > 0 ? tables_out + P->qe_at : nullptr;
+    P->dep = P->dep_n > 0 ? tables_out + P->dep_at : nullptr;
     return 0;
 }
 int emu_params_size() { return (int)sizeof(TraceParams); }
@@ -260,7 +261,10 @@ int emu_trace(TraceParams *P, int n_waves, int precision, long long max_meetings
         QueueMem q;
         int e = run_wave([&] {
             const bool rec = P->records_mode != MRT_RECORDS_NONE;
-            if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P, q.b); else trace_body<double, false>(*P, q.b); }
+            if (P->dep_n > 0) {   // the energy-dependent rocking curve's kernel
+                if (precision == MRT_FP64) { if (rec) trace_body<double, true, true>(*P, q.b); else trace_body<double, false, true>(*P, q.b); }
+                else { if (rec) trace_body<float, true, true>(*P, q.b); else trace_body<float, false, true>(*P, q.b); }
+            } else if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P, q.b); else trace_body<double, false>(*P, q.b); }
             else { if (rec) trace_body<float, true>(*P, q.b); else trace_body<float, false>(*P, q.b); }
         }, max_meetings);
         if (e) return e;

@@ -45,7 +45,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(mrt.MrtSource) == 320
     assert C.sizeof(mrt.MrtCrystal) == 224
     assert C.sizeof(mrt.MrtMosaic) == 24
-    assert C.sizeof(mrt.MrtRockingCurve) == 72
+    assert C.sizeof(mrt.MrtRockingCurve) == 104
     assert C.sizeof(mrt.MrtDetector) == 136
     assert C.sizeof(mrt.MrtOptions) == 48
     assert C.sizeof(mrt.MrtCounters) == 96
@@ -160,6 +160,19 @@ def test_invalid_qe_tables_and_calibration_arguments():
     assert L.mrt_calibration_map(None, C.c_void_p(8), 10, C.c_void_p(8), None) == mrt.EINVAL
     assert L.mrt_calibration_map(C.c_void_p(8), None, 10, C.c_void_p(8), None) == mrt.EINVAL
     assert L.mrt_calibration_map(C.c_void_p(8), C.c_void_p(8), 10, None, None) == mrt.EINVAL
+
+
+def test_invalid_energy_dependence_tables():
+    for table in ([(8.0, 0.0, 1.0), (8.0, 0.0, 1.0)], [(8.1, 0.0, 1.0), (8.0, 0.0, 1.0)],
+                  [(8.0, 0.0, 0.0)], [(8.0, float("inf"), 1.0)],
+                  [(7.0 + i * 1e-3, 0.0, 1.0) for i in range(1025)]):
+        w = W.get("flat_hopg")
+        w["rocking_curve"]["energy_dependence"] = table
+        assert _call(w) == mrt.EINVAL, table
+    w = W.get("flat_hopg")
+    w["rocking_curve"]["energy_dependence"] = [(8.0, 1e-5, 1.2)]
+    assert _call(w) != mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(event_model=mrt.MODEL["mwg"])) == mrt.EINVAL
 
 
 def test_invalid_event_model_options():
