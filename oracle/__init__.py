@@ -63,15 +63,16 @@ class Irc(C.Structure):
 
 class Model(C.Structure):
     _fields_ = [("kind", C.c_int32), ("burn_in", C.c_int32), ("psi_nodes", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("irc_off", C.c_int32)]
 
 
 def model_of(w):
     """The event model of a workload: w["event_model"] = {"kind": "mwg",
-    "burn_in": B, "psi_nodes": M}, or absent (null-collision stepping)."""
+    "burn_in": B, "psi_nodes": M, "irc_off": False}, or absent (null-collision
+    stepping)."""
     e = w.get("event_model") or {"kind": "stepping"}
     return Model(kind=_MODEL[e["kind"]], burn_in=int(e.get("burn_in", 500)),
-                 psi_nodes=int(e.get("psi_nodes", 256)))
+                 psi_nodes=int(e.get("psi_nodes", 256)), irc_off=1 if e.get("irc_off") else 0)
 
 
 class Detector(C.Structure):

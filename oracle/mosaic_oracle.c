@@ -621,16 +621,17 @@ static double mwg_target(const orc_mosaic *m, const orc_irc *irc, double alpha, 
 }
 
 /* Metropolis-within-Gibbs draw of (psi, Delta) (sec. 2.2.4): from
-   (0, Delta_M), `burn_in` sweeps, each a psi move and then a Delta move,
+   (0, Delta_M), `burn_in` sweeps, each a psi move and then (moves_delta;
+   with the IRC disabled, sec. 2.2.1, Delta stays at Delta_M) a Delta move,
    both symmetric uniform random walks (half-widths w_psi and w_delta); a
    move is taken when u f(current) < f(proposed), or from a point of zero
    density; Delta outside [-alpha_B, pi/2 - alpha_B] is rejected; psi wraps
    on [-pi, pi).  Sweep s of event e uses the Philox words of counter
    (s, ray, 2^31 + e). */
-void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
-                    uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
-                    double alpha, double ab, double *psi_out, double *delta_out,
-                    double *margin) {
+static void mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
+                       uint64_t seed, uint64_t ray, uint32_t event, int burn_in, int moves_delta,
+                       double alpha, double ab, double *psi_out, double *delta_out,
+                       double *margin) {
     double lo = -ab, hi = ORC_PI / 2.0 - ab;
     double psi = 0.0, delta = irc->shift;
     if (delta < lo) delta = lo;
@@ -648,6 +649,7 @@ void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, doubl
             psi = pn;
             f = fn;
         }
+        if (!moves_delta) continue;
         double dn = delta + w_delta * (2.0 * u[2] - 1.0);
         if (dn >= lo && dn <= hi) {
             fn = mwg_target(m, irc, alpha, ab, psi, dn);
@@ -660,6 +662,22 @@ void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, doubl
     }
     *psi_out = psi;
     *delta_out = delta;
+}
+
+void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
+                    uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
+                    double alpha, double ab, double *psi_out, double *delta_out,
+                    double *margin) {
+    mwg_sample(m, irc, w_psi, w_delta, seed, ray, event, burn_in, 1, alpha, ab, psi_out,
+               delta_out, margin);
+}
+
+void orc_mwg_sample_psi(const orc_mosaic *m, const orc_irc *irc, double w_psi,
+                        uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
+                        double alpha, double ab, double *psi_out, double *delta_out,
+                        double *margin) {
+    mwg_sample(m, irc, w_psi, 0.0, seed, ray, event, burn_in, 0, alpha, ab, psi_out, delta_out,
+               margin);
 }
 
 /* Crystallite normal for glancing angle alpha on the planes of normal N
@@ -716,7 +734,7 @@ typedef struct trace_ctx {
     double r_max, mu_tot, p_a;
     /* the paper's event model */
     int mwg;                 /* 1: event model of sec. 2.2.3-2.2.4 */
-    int burn_in, psi_nodes;
+    int burn_in, psi_nodes, irc_off;
     double q;                /* int r dx / h */
     double w_delta;          /* sampler step in Delta */
 } trace_ctx;
@@ -729,6 +747,7 @@ static void ctx_init(trace_ctx *X, const orc_source *s, const orc_crystal *c,
         X->mwg = 1;
         X->burn_in = model->burn_in;
         X->psi_nodes = model->psi_nodes;
+        X->irc_off = model->irc_off;
         X->q = orc_irc_integral(irc) / c->mfp;
         X->w_delta = orc_irc_width(irc);
     }
@@ -796,8 +815,8 @@ static void mwg_events(const trace_ctx *X, uint64_t ray, double alpha_b, double 
         for (int i = 0; i < 3; ++i) Ns[i] = anti ? -N[i] : N[i];
         double as = anti ? -alpha : alpha;
         double psi, delta, n[3], ks[3];
-        orc_mwg_sample(X->m, X->irc, w_psi, X->w_delta, X->seed, ray, event, X->burn_in, as,
-                       alpha_b, &psi, &delta, m);
+        mwg_sample(X->m, X->irc, w_psi, X->w_delta, X->seed, ray, event, X->burn_in, !X->irc_off,
+                   as, alpha_b, &psi, &delta, m);
         orc_crystallite(Ns, k, as, alpha_b + delta, psi, n);
         /* reflection equation of sec. 2.2.4 */
         axpy(k, -2.0 * dot(k, n), n, ks);

@@ -114,7 +114,7 @@ typedef struct orc_model {
     int32_t kind;            /* ORC_MODEL_* */
     int32_t burn_in;
     int32_t psi_nodes;
-    int32_t pad_;
+    int32_t irc_off;         /* 1: the IRC disabled, every reflection at Delta_M */
 } orc_model;
 
 typedef struct orc_record {
@@ -175,6 +175,12 @@ void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, doubl
                     uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
                     double alpha, double ab, double *psi_out, double *delta_out,
                     double *margin);
+/* The same with Delta held at Delta_M (the IRC disabled, sec. 2.2.1): the
+   sweeps make psi moves only. */
+void orc_mwg_sample_psi(const orc_mosaic *m, const orc_irc *irc, double w_psi,
+                        uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
+                        double alpha, double ab, double *psi_out, double *delta_out,
+                        double *margin);
 void orc_crystallite(const double N[3], const double k[3], double alpha, double b,
                      double psi, double n[3]);
 

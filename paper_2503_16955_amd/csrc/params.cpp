@@ -203,9 +203,10 @@ static double irc_width(const mrt_rocking_curve *r) {
 }
 
 void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_curve *r,
-                      int burn_in, int psi_nodes, int batch, TraceParams &P,
+                      int burn_in, int psi_nodes, int batch, bool irc_off, TraceParams &P,
                       std::vector<double> &psi) {
     P.burn_in = burn_in;
+    P.irc_off = irc_off ? 1 : 0;
     P.psi_nodes = psi_nodes;
     P.mwg_batch = batch;
     P.q = irc_integral(r) / c->mfp;

@@ -31,7 +31,7 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
 // sweeps, quadrature intervals, batch, reflection strength, density
 // constants) and append the psi table (2 (psi_nodes + 1) values) to `psi`.
 void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_curve *r,
-                      int burn_in, int psi_nodes, int batch, TraceParams &P,
+                      int burn_in, int psi_nodes, int batch, bool irc_off, TraceParams &P,
                       std::vector<double> &psi);
 
 }  // namespace mrt

@@ -131,6 +131,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
         return fail(MRT_EINVAL, "options: refill_idle must lie in [0, 64]");
     const bool mwg = opt.event_model == MRT_MODEL_MWG;
     if (opt.event_model != MRT_MODEL_STEPPING && !mwg) return fail(MRT_EINVAL, "options: unknown event model");
+    if (!mwg && opt.mwg_irc_off != 0) return fail(MRT_EINVAL, "options: mwg_irc_off needs the MWG event model");
     if (mwg) {
         if (opt.precision != MRT_FP64) return fail(MRT_EINVAL, "options: the MWG event model runs in FP64");
         if (rocking_curve->n_dep > 0)
@@ -141,6 +142,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
             return fail(MRT_EINVAL, "options: psi_nodes must lie in [0, %d]", mrt::kMaxPsiNodes);
         if (opt.mwg_batch < 0 || opt.mwg_batch > 64) return fail(MRT_EINVAL, "options: mwg_batch must lie in [0, 64]");
         if (opt.max_events > 0x7fffffffu) return fail(MRT_EINVAL, "options: the MWG event model needs max_events < 2^31");
+        if (opt.mwg_irc_off != 0 && opt.mwg_irc_off != 1) return fail(MRT_EINVAL, "options: mwg_irc_off must be 0 or 1");
     }
 
     int dev = 0, cus = 0;
@@ -154,7 +156,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     if (mwg) {
         const int burn = opt.mwg_burn_in == 0 ? 500 : (opt.mwg_burn_in < 0 ? 0 : opt.mwg_burn_in);
         mrt::build_mwg_params(crystal, mosaic, rocking_curve, burn, opt.psi_nodes ? opt.psi_nodes : 256,
-                              opt.mwg_batch ? opt.mwg_batch : 32, P, tables);
+                              opt.mwg_batch ? opt.mwg_batch : 32, opt.mwg_irc_off != 0, P, tables);
     }
     P.first = first_ray_id;
     P.n = n_rays;

@@ -172,7 +172,8 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
     }
 
     // ---- Metropolis-within-Gibbs draw and the reflection -----------------
-    // From (0, Delta_M): burn_in sweeps of a psi move and a Delta move,
+    // From (0, Delta_M): burn_in sweeps of a psi move and (unless the IRC is
+    // disabled, which holds Delta at Delta_M) a Delta move,
     // symmetric uniform random walks, a move taken when u f(current) <
     // f(proposed) or from a point of zero density, Delta outside
     // [-alpha_B, pi/2 - alpha_B] rejected, psi wrapped on [-pi, pi).  Sweep s
@@ -209,7 +210,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC> {
                 f = fn;
             }
             const double dn = delta + P.w_delta * (2.0 * dm::u01_f64(w.w2) - 1.0);
-            if (dn >= lo && dn <= hi) {
+            if (!P.irc_off && dn >= lo && dn <= hi) {   // the IRC disabled: Delta stays
                 y = x;
                 at_delta(P, lut, alpha, ab, dn, y);
                 fn = value(P, y, ca);

@@ -83,7 +83,7 @@ struct TraceParams {
 
     // ---- the paper's event model (sec. 2.2.3, 2.2.4; FP64 kernels only)
     int32_t burn_in, psi_nodes;   // sampler sweeps; psi quadrature intervals
-    int32_t mwg_batch, pad2;      // parked lanes that start the sampler
+    int32_t mwg_batch, irc_off;   // parked lanes that start the sampler; IRC disabled
     double q;                     // int r dx / mfp (Q R = r / mfp)
     double w_delta;               // sampler step in Delta
     double vmf_kappa, vmf_norm;   // density kappa e^{-kappa v} / (2 pi (1 - e^{-2 kappa}))

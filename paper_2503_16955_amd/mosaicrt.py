@@ -78,7 +78,7 @@ class MrtOptions(C.Structure):
                 ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
                 ("refill_idle", C.c_int32), ("event_model", C.c_int32),
                 ("mwg_burn_in", C.c_int32), ("psi_nodes", C.c_int32), ("mwg_batch", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("mwg_irc_off", C.c_int32)]
 
 
 MODEL = {"stepping": 0, "mwg": 1}
@@ -94,7 +94,7 @@ def model_options(w):
         return {"event_model": 0}
     b = int(e.get("burn_in", 500))
     return {"event_model": MODEL[e["kind"]], "mwg_burn_in": MWG_NO_BURN_IN if b == 0 else b,
-            "psi_nodes": int(e.get("psi_nodes", 256))}
+            "psi_nodes": int(e.get("psi_nodes", 256)), "mwg_irc_off": 1 if e.get("irc_off") else 0}
 
 
 COUNTER_FIELDS = ("emitted", "missed", "absorbed", "exit_reflected", "exit_transmitted",

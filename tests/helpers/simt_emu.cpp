@@ -186,7 +186,7 @@ int emu_build_mwg(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_c
                   int burn_in, int psi_nodes, int batch, TraceParams *P, double *tables_out,
                   int tables_cap, int n_used) {
     std::vector<double> t;
-    mrt::build_mwg_params(c, m, r, burn_in, psi_nodes, batch, *P, t);
+    mrt::build_mwg_params(c, m, r, burn_in, psi_nodes, batch, false, *P, t);
     if (n_used + (int)t.size() > tables_cap) return -2;
     for (size_t i = 0; i < t.size(); ++i) tables_out[n_used + i] = t[i];
     P->psi_tab = tables_out + n_used;

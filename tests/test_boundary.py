@@ -188,6 +188,8 @@ def test_invalid_event_model_options():
     assert _call(w, opts=mrt.MrtOptions(psi_nodes=-1, **M)) == mrt.EINVAL
     assert _call(w, opts=mrt.MrtOptions(mwg_batch=65, **M)) == mrt.EINVAL
     assert _call(w, opts=mrt.MrtOptions(max_events=1 << 31, **M)) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(mwg_irc_off=1)) == mrt.EINVAL      # needs the MWG model
+    assert _call(w, opts=mrt.MrtOptions(mwg_irc_off=2, **M)) == mrt.EINVAL
     w["mosaic"]["fwhm"] = 0.0
     assert _call(w, opts=mrt.MrtOptions(**M)) == mrt.EINVAL
     assert "fwhm" in mrt.last_error()

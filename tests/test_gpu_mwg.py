@@ -172,3 +172,12 @@ def test_mwg_von_hamos_full_size_sampled():
     assert torch.equal(b["counts"].long(), img)
     assert b["counters"]["events"] == c["events"]
     assert b["counters"]["reflections"] == c["reflections"]
+
+
+def test_mwg_irc_disabled():
+    # sec. 2.2.1: the IRC disabled, every reflection at Delta_M (psi moves only)
+    w = mwg(W.get("von_hamos_hapg"), burn_in=300)
+    w["event_model"]["irc_off"] = True
+    w["rocking_curve"]["shift"] = 8e-6
+    g, o = assert_parity(w, 200_000)
+    assert o["counters"]["reflections"] > 1000

@@ -316,3 +316,28 @@ def test_model_rejects_what_it_cannot_trace():
         oracle.trace(_mwg(w), n=10)
     with pytest.raises(ValueError):
         oracle.trace(_mwg(W.get("flat_hopg"), burn_in=-1), n=10)
+
+
+def test_irc_disabled_reflects_at_delta_m_exactly():
+    # sec. 2.2.1: with the IRC disabled every reflecting crystallite sits at
+    # Delta = Delta_M exactly (|k.n| = sin(alpha_B + Delta_M)); the rate and
+    # the psi law are unchanged
+    energy = 8.0
+    ab = math.asin(HC / (6.708 * energy))
+    w = pencil(ab + 0.1 * DEG, energy, n=100000)
+    w["mosaic"] = dict(kind="gaussian_vmf", fwhm=0.4 * DEG, eta=0.0)
+    w["rocking_curve"] = dict(G_IRC, shift=12e-6)
+    on = oracle.trace(_mwg(w, burn_in=200), records=True, images=False)
+    off = oracle.trace(_mwg(w, burn_in=200, irc_off=True), records=True, images=False)
+    # the same events: the free paths and plane choices do not involve Delta
+    assert on["counters"]["reflections"] == off["counters"]["reflections"] > 300
+    rec = off["records"]
+    refl = rec["n_refl"] == 1
+    k0 = np.array(w["source"]["axis"])
+    n = rec["dir"][refl] - k0
+    n /= np.linalg.norm(n, axis=1)[:, None]
+    assert np.abs(np.arcsin(np.abs(n @ k0)) - (ab + 12e-6)).max() < 1e-10
+    rec_on = on["records"][on["records"]["n_refl"] == 1]
+    n_on = rec_on["dir"] - k0
+    n_on /= np.linalg.norm(n_on, axis=1)[:, None]
+    assert np.std(np.arcsin(np.abs(n_on @ k0)) - ab) > 5e-6
