@@ -24,6 +24,7 @@ _MDF = {"gaussian_vmf": 0, "lorentzian": 1, "pseudo_voigt": 2, "wrapped_lorentzi
         "spherical_wrapped_lorentzian": 4}
 _IRC = {"gaussian": 0, "pseudo_voigt": 1, "table": 2, "lorentzian": 3, "box": 4}
 _MODEL = {"stepping": 0, "mwg": 1}
+_SPOT = {"point": 0, "gaussian": 1, "disk": 2}
 
 D3 = C.c_double * 3
 D8 = C.c_double * 8
@@ -34,8 +35,11 @@ class Source(C.Structure):
                 ("spectrum", C.c_int32), ("n_lines", C.c_int32),
                 ("e_min", C.c_double), ("e_max", C.c_double),
                 ("line_e", D8), ("line_sigma", D8), ("line_w", D8),
-                ("background_w", C.c_double), ("n_bins", C.c_int32), ("pad_", C.c_int32),
-                ("bin_w", C.POINTER(C.c_double))]
+                ("background_w", C.c_double), ("n_bins", C.c_int32), ("spot_kind", C.c_int32),
+                ("bin_w", C.POINTER(C.c_double)),
+                ("spot_u", D3), ("spot_v", D3), ("spot_sigma", C.c_double * 2),
+                ("user_o", C.c_void_p), ("user_k", C.c_void_p), ("user_e", C.c_void_p),
+                ("user_first", C.c_uint64)]
 
 
 class Crystal(C.Structure):
@@ -177,6 +181,13 @@ class Structs:
         self._bins = np.ascontiguousarray(s.get("bin_weights", [1.0]), dtype=np.float64)
         self.src.n_bins = len(self._bins) if s["spectrum"] == "table" else 0
         self.src.bin_w = self._bins.ctypes.data_as(C.POINTER(C.c_double))
+        spot = s.get("spot")
+        if spot:
+            self.src.spot_kind = _SPOT[spot["kind"]]
+            self.src.spot_u, self.src.spot_v = _d3(spot["u"]), _d3(spot["v"])
+            sig = list(spot["sigma"]) if np.ndim(spot["sigma"]) else [spot["sigma"]]
+            self.src.spot_sigma = (C.c_double * 2)(*(float(x) for x in (sig + [0.0])[:2]))
+        self._rays = []
 
         self.cr = Crystal()
         self.cr.geometry = _GEOM[c["geometry"]]
@@ -213,14 +224,33 @@ class Structs:
         self.det.qe_kev = self._qe_e.ctypes.data_as(C.POINTER(C.c_double))
         self.det.qe = self._qe_v.ctypes.data_as(C.POINTER(C.c_double))
 
+    def set_rays(self, rays, first, n_rows):
+        """Point the source at user ray arrays (host numpy float64): rows
+        for ray ids first .. first + n_rows - 1."""
+        for key, field, shape in (("origins", "user_o", (n_rows, 3)),
+                                  ("directions", "user_k", (n_rows, 3)),
+                                  ("energies", "user_e", (n_rows,))):
+            a = (rays or {}).get(key)
+            if a is None:
+                continue
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            if a.shape != shape:
+                raise ValueError(f"rays[{key!r}] must have shape {shape}")
+            self._rays.append(a)
+            setattr(self.src, field, a.ctypes.data)
+        self.src.user_first = first
+
     def args(self):
         return (C.byref(self.src), C.byref(self.cr), C.byref(self.mo), C.byref(self.irc),
                 C.byref(self.det))
 
 
 def trace(w, first=0, n=None, seed=None, max_events=0, images=True, records=False,
-          margins=False, threads=0):
+          margins=False, threads=0, rays=None):
     """Trace rays [first, first + n) of workload `w` on the CPU.
+
+    rays: optional user ray arrays (numpy, row i for ray first + i):
+    ``origins`` (n, 3), ``directions`` (n, 3), ``energies`` (n,).
 
     Returns a dict with ``counts`` (ny, nx) uint32, ``energy_mev`` (ny, nx)
     uint64, ``counters`` (dict), and on request ``records`` (structured array)
@@ -228,6 +258,7 @@ def trace(w, first=0, n=None, seed=None, max_events=0, images=True, records=Fals
     n = int(w["n_rays"] if n is None else n)
     seed = int(w["seed"] if seed is None else seed)
     S = Structs(w)
+    S.set_rays(rays, first, n)
     nx, ny = w["detector"]["nx"], w["detector"]["ny"]
     out = {}
     counts = np.zeros((ny, nx), np.uint32) if images else None
@@ -252,11 +283,16 @@ def trace(w, first=0, n=None, seed=None, max_events=0, images=True, records=Fals
     return out
 
 
-def trace_ids(w, ids, seed=None, max_events=0, threads=0):
-    """Records and decision margins for an arbitrary list of ray ids."""
+def trace_ids(w, ids, seed=None, max_events=0, threads=0, rays=None, first=0, n_rows=None):
+    """Records and decision margins for an arbitrary list of ray ids (user
+    ray arrays, if any, hold the n_rows rays from id `first` on)."""
     ids = np.ascontiguousarray(ids, dtype=np.uint64)
     seed = int(w["seed"] if seed is None else seed)
     S = Structs(w)
+    if rays:
+        if n_rows is None or np.any(ids < first) or np.any(ids >= first + n_rows):
+            raise ValueError("ray ids outside the user arrays")
+        S.set_rays(rays, first, n_rows)
     recs = np.zeros(len(ids), RECORD_DTYPE)
     mg = np.zeros(len(ids), np.float64)
     model = model_of(w)

@@ -274,14 +274,48 @@ void orc_mdf_sample(const orc_mosaic *m, double u2, double u3,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Photon source (sec. 2.1): a point source, directions uniform in solid    */
-/* angle inside a cone, energies drawn from the spectrum used as a PDF.     */
+/* Photon source (sec. 2.1): origins at the source point or spread over    */
+/* the source spot (sec. 4.2), directions uniform in solid angle inside a   */
+/* cone, energies drawn from the spectrum used as a PDF; any of the three   */
+/* may instead come from the user's arrays.                                  */
 /* ------------------------------------------------------------------------ */
+static void sample_point_source(const orc_source *s, const double *w, double o[3], double k[3],
+                                double *energy);
+
 void orc_source_sample(const orc_source *s, uint64_t seed, uint64_t ray_id,
                        double o[3], double k[3], double *energy) {
     double w[8];
     ray_words(seed, ray_id, 0, 0, w);
     ray_words(seed, ray_id, 0, 1, w + 4);
+    uint64_t row = ray_id - s->user_first;
+    sample_point_source(s, w, o, k, energy);
+
+    /* spot: an offset (x, y) in the plane of spot_u, spot_v from the two
+       uniforms w[5], w[6] -- a 2-D normal by the Box-Muller transform, or a
+       point uniform over the disk (radius R sqrt(u) for a uniform area) */
+    if (s->spot_kind != ORC_SPOT_POINT) {
+        double phi = ORC_TWO_PI * w[6];
+        double x, y;
+        if (s->spot_kind == ORC_SPOT_GAUSSIAN) {
+            double r = sqrt(-2.0 * log(w[5]));
+            x = s->spot_sigma[0] * r * cos(phi);
+            y = s->spot_sigma[1] * r * sin(phi);
+        } else {
+            double r = s->spot_sigma[0] * sqrt(w[5]);
+            x = r * cos(phi);
+            y = r * sin(phi);
+        }
+        for (int i = 0; i < 3; ++i) o[i] += x * s->spot_u[i] + y * s->spot_v[i];
+    }
+    if (s->user_o)
+        for (int i = 0; i < 3; ++i) o[i] = s->user_o[3 * row + i];
+    if (s->user_k)
+        for (int i = 0; i < 3; ++i) k[i] = s->user_k[3 * row + i];
+    if (s->user_e) *energy = s->user_e[row];
+}
+
+static void sample_point_source(const orc_source *s, const double *w, double o[3], double k[3],
+                                double *energy) {
 
     /* direction: 1 - cos(theta) uniform on [0, 1 - cos(theta_max)] */
     double sh = sin(s->half_angle / 2.0);
@@ -1017,6 +1051,9 @@ static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic 
         if (!(irc->dep_scale[i] > 0.0) || (i && !(irc->dep_kev[i] > irc->dep_kev[i - 1]))) return -14;
     if (irc->n_dep > 0 && model && model->kind == ORC_MODEL_MWG) return -15;
     if (s->spectrum == ORC_SPEC_TABLE && (s->n_bins < 1 || !s->bin_w)) return -6;
+    if (s->spot_kind < ORC_SPOT_POINT || s->spot_kind > ORC_SPOT_DISK) return -16;
+    if (s->spot_kind != ORC_SPOT_POINT &&
+        (!(s->spot_sigma[0] >= 0.0) || !(s->spot_sigma[1] >= 0.0))) return -16;
     if (s->spectrum == ORC_SPEC_LINES && (s->n_lines < 0 || s->n_lines > 8)) return -7;
     if (d->nx <= 0 || d->ny <= 0 || d->pitch <= 0.0) return -8;
     if (d->n_qe < 0 || (d->n_qe > 0 && (!d->qe_kev || !d->qe))) return -13;

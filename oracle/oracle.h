@@ -37,6 +37,7 @@ enum { ORC_MDF_VMF = 0, ORC_MDF_LORENTZ = 1, ORC_MDF_PVOIGT = 2,
 enum { ORC_IRC_GAUSS = 0, ORC_IRC_PVOIGT = 1, ORC_IRC_TABLE = 2,
        ORC_IRC_LORENTZ = 3, ORC_IRC_BOX = 4 };
 enum { ORC_MODEL_STEPPING = 0, ORC_MODEL_MWG = 1 };
+enum { ORC_SPOT_POINT = 0, ORC_SPOT_GAUSSIAN = 1, ORC_SPOT_DISK = 2 };
 enum { ORC_MISS = 0, ORC_ABSORBED = 1, ORC_EXIT_REFLECTED = 2,
        ORC_EXIT_TRANSMITTED = 3, ORC_TRUNCATED = 4 };
 
@@ -51,8 +52,16 @@ typedef struct orc_source {
     double line_e[8], line_sigma[8], line_w[8];
     double background_w;
     int32_t n_bins;          /* table spectrum */
-    int32_t pad_;
+    int32_t spot_kind;       /* ORC_SPOT_*: the source spot (sec. 4.2) */
     const double *bin_w;     /* n_bins weights (host) */
+    /* spot plane (orthonormal) and size: Gaussian standard deviations
+       along u and v, or the disk radius in spot_sigma[0] */
+    double spot_u[3], spot_v[3], spot_sigma[2];
+    /* user ray arrays (sec. 2.1), host, row ray_id - user_first, or NULL:
+       origins (x, y, z), unit directions, energies; each replaces the
+       sampled field (user origins also replace the spot) */
+    const double *user_o, *user_k, *user_e;
+    uint64_t user_first;
 } orc_source;
 
 typedef struct orc_crystal {

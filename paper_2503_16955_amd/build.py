@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmosaicrt.so")
 SOURCES = ["trace_f64_flat.hip", "trace_f64_cyl.hip", "trace_f32_flat.hip", "trace_f32_cyl.hip",
-           "trace_mwg.hip", "trace_edep.hip", "serve.hip", "launch.hip", "params.cpp", "runtime.cpp", "server.cpp"]
+           "trace_mwg.hip", "trace_ext.hip", "serve.hip", "launch.hip", "params.cpp", "runtime.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

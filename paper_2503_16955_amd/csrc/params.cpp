@@ -55,6 +55,16 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
         }
         if (!(tot > 0.0)) return fail(MRT_EINVAL, "source: all bin weights are zero");
     }
+    if (s->spot_kind < MRT_SPOT_POINT || s->spot_kind > MRT_SPOT_DISK)
+        return fail(MRT_EINVAL, "source: unknown spot kind");
+    if (s->spot_kind != MRT_SPOT_POINT) {
+        if (!unit(s->spot_u) || !unit(s->spot_v) || !ortho(s->spot_u, s->spot_v))
+            return fail(MRT_EINVAL, "source: spot_u and spot_v must be orthonormal unit vectors");
+        const int ns = s->spot_kind == MRT_SPOT_GAUSSIAN ? 2 : 1;
+        for (int i = 0; i < ns; ++i)
+            if (!(s->spot_sigma[i] >= 0.0) || !std::isfinite(s->spot_sigma[i]))
+                return fail(MRT_EINVAL, "source: spot_sigma must be finite and >= 0");
+    }
     // crystal
     if (c->geometry == MRT_GEOMETRY_FLAT) {
         if (!finite3(c->centre) || !unit(c->normal) || !unit(c->e1) || !ortho(c->normal, c->e1))
@@ -235,6 +245,10 @@ void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocki
     }
 }
 
+bool uses_ext(const mrt_source *s, const mrt_rocking_curve *r) {
+    return r->n_dep > 0 || s->spot_kind != MRT_SPOT_POINT || s->origins || s->directions || s->energies;
+}
+
 void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
                   const mrt_rocking_curve *r, const mrt_detector *d, TraceParams &P,
                   std::vector<double> &tables) {
@@ -255,6 +269,15 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
         P.sb1[i] = s->b1[i];
     }
     cross3(s->axis, s->b1, P.sb2);
+    P.spot_kind = s->spot_kind;
+    if (s->spot_kind != MRT_SPOT_POINT) {
+        for (int i = 0; i < 3; ++i) { P.spot_u[i] = s->spot_u[i]; P.spot_v[i] = s->spot_v[i]; }
+        P.spot_sigma[0] = s->spot_sigma[0];
+        P.spot_sigma[1] = s->spot_kind == MRT_SPOT_GAUSSIAN ? s->spot_sigma[1] : 0.0;
+    }
+    P.user_o = s->origins;
+    P.user_k = s->directions;
+    P.user_e = s->energies;
     const double sh = std::sin(s->half_angle / 2.0);
     P.vmax = 2.0 * sh * sh;
     P.spectrum = s->spectrum;

@@ -27,6 +27,10 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
                   const mrt_rocking_curve *r, const mrt_detector *d, TraceParams &P,
                   std::vector<double> &tables);
 
+// True when the run needs the extended-input kernels: an energy-dependent
+// rocking curve, a source spot or user ray arrays.
+bool uses_ext(const mrt_source *s, const mrt_rocking_curve *r);
+
 // The paper's event model: fill its part of the parameter block (sampler
 // sweeps, quadrature intervals, batch, reflection strength, density
 // constants) and append the psi table (2 (psi_nodes + 1) values) to `psi`.

@@ -211,8 +211,8 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
 
     const bool rec = opt.records_mode != MRT_RECORDS_NONE;
     const void *kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec)
-                         : rocking_curve->n_dep > 0
-                             ? mrt::edep_kernel_ptr(opt.precision, rec)
+                         : mrt::uses_ext(source, rocking_curve)
+                             ? mrt::ext_kernel_ptr(opt.precision, rec)
                              : mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
                                                      rocking_curve->kind, rec);
     if (!kernel) return release(fail(MRT_EINVAL, "no kernel for this combination of kinds"));

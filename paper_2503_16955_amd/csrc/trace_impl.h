@@ -167,9 +167,10 @@ template <class R, bool REC> struct RayQueue : QueueEntry<R, REC> {
 // the branches stay wave-uniform).
 constexpr int kAny = -1;
 
-// EDEP: the rocking curve's shift and width depend on the photon energy
-// (tables interpolated per event; run-time kinds only).
-template <class R, int GEOM, int MDF, int IRC, bool REC, bool EDEP = false>
+// EXT: the extended inputs (run-time kinds only): a rocking curve whose shift
+// and width depend on the photon energy (tables interpolated per event), a
+// finite source spot, and user-supplied origins, directions or energies.
+template <class R, int GEOM, int MDF, int IRC, bool REC, bool EXT = false>
 struct Tracer {
     using RayT = Ray<R, REC>;
     static constexpr bool kF64 = sizeof(R) == 8;
@@ -411,7 +412,7 @@ struct Tracer {
             return h2 * __builtin_amdgcn_rcpf(h2 + a2);
         }
     }
-    // With EDEP the curve is read at x / s: the bounds of x are scaled by
+    // With EXT the curve is read at x / s: the bounds of x are scaled by
     // 1/s (inv_s, rounded to float) and widened by 2^-20 relative, which
     // covers the float roundings of inv_s and of the products.
     static __device__ __forceinline__ int filter(const TraceParams &P, double akn, float saf,
@@ -443,7 +444,8 @@ struct Tracer {
             hi = INFINITY;
         }
         lo = lo > 0.0f ? lo : 0.0f;
-        if constexpr (EDEP) {
+        // (inv_s == 1 scales nothing and needs no margin)
+        if (EXT && inv_s != 1.0f) {
             const float up = 1.0f + 0x1p-20f, dn = 1.0f - 0x1p-20f;
             lo *= inv_s * dn;
             hi *= inv_s * up;   // INFINITY stays
@@ -515,7 +517,9 @@ struct Tracer {
         double akn = __builtin_fabs(kn);
         akn = akn < 1.0 ? akn : 1.0;
         int dec;
-        if constexpr (EDEP) {
+        bool dep = false;   // the curve depends on the energy (wave-uniform)
+        if constexpr (EXT) dep = P.dep_n > 0;
+        if (dep) {
             // Delta_M(E) and the width scale s(E) (sec. 2.2.1): r read at
             // (Delta - Delta_M(E)) / s(E)
             const double shift = interp(P.dep, P.dep + P.dep_n, P.dep_n, ry.E);
@@ -680,14 +684,60 @@ struct Tracer {
         return detected;
     }
 
+    // The photon energy: the user's array (EXT), else drawn from the spectrum.
+    static __device__ __forceinline__ double ray_energy(const TraceParams &P, const double *cdf,
+                                                        const dm::Words &a, uint64_t ray) {
+        if constexpr (EXT) {
+            if (P.user_e) return P.user_e[ray - P.first];
+        }
+        return energy(P, cdf, a, ray);
+    }
+    // Offset (x, y) of a ray's origin in the spot plane from uniforms u, v:
+    // Gaussian, sigma_x sqrt(-2 ln u) (cos, sin)(2 pi v) (Box-Muller), or
+    // uniform over the disk of radius sigma_x, sigma_x sqrt(u) (cos, sin)(2 pi v).
+    static __device__ __forceinline__ void spot_offset(const TraceParams &P, double u, double v,
+                                                       double &x, double &y) {
+        double s, c;
+        dm::sincos_turns(v, &s, &c);
+        if (P.spot_kind == MRT_SPOT_GAUSSIAN) {
+            const double r = dm::sqrt(-2.0 * dm::log_pos(u));
+            x = P.spot_sigma[0] * r * c;
+            y = P.spot_sigma[1] * r * s;
+        } else {
+            const double r = P.spot_sigma[0] * dm::sqrt(u);
+            x = r * c;
+            y = r * s;
+        }
+    }
+
     // Start a ray: source direction and front-face entry.  On a hit, the
     // energy, Bragg angle and first exit distance follow and true is
     // returned; a miss is retired here (record written) and false returned.
     static __device__ __forceinline__ bool start(const TraceParams &P, const double *cdf,
                                                  uint64_t ray, RayT &ry) {
         const dm::Words a = dm::philox(P.key0, P.key1, 0u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
-        const V3<R> o = par3<R>(P.so, P.f32.so);
-        const V3<R> k = direction(P, a);
+        V3<R> o, k;
+        if constexpr (EXT) {
+            const size_t i = (size_t)(ray - P.first);
+            double od[3] = {P.so[0], P.so[1], P.so[2]};
+            if (P.user_o) {
+                // user origins, global coordinates
+                for (int c = 0; c < 3; ++c) od[c] = P.user_o[3 * i + c] - P.origin[c];
+            } else if (P.spot_kind != MRT_SPOT_POINT) {
+                // finite source spot (sec. 4.2): words 1, 2 of the source's second draw
+                const dm::Words b = dm::philox(P.key0, P.key1, 1u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
+                double x, y;
+                spot_offset(P, dm::u01_f64(b.w1), dm::u01_f64(b.w2), x, y);
+                for (int c = 0; c < 3; ++c) od[c] += x * P.spot_u[c] + y * P.spot_v[c];
+            }
+            o = V3<R>{cvt<R>(od[0]), cvt<R>(od[1]), cvt<R>(od[2])};
+            k = P.user_k ? V3<R>{cvt<R>(P.user_k[3 * i]), cvt<R>(P.user_k[3 * i + 1]),
+                                 cvt<R>(P.user_k[3 * i + 2])}
+                         : direction(P, a);
+        } else {
+            o = par3<R>(P.so, P.f32.so);
+            k = direction(P, a);
+        }
         ry.id = ray;
         ry.k = k;
         ry.nev = 0;
@@ -696,7 +746,7 @@ struct Tracer {
         const bool hit = entry(P, o, k, t);
         if (!hit) {
             if constexpr (REC) {
-                ry.E = energy(P, cdf, a, ray);
+                ry.E = ray_energy(P, cdf, a, ray);
                 ry.p = o;
                 write_record(P, ry, MRT_MISS, true, o, false, -1, -1);
             }
@@ -704,7 +754,7 @@ struct Tracer {
         }
         ry.p = axpy(o, t, k);
         if constexpr (REC) ry.entry = ry.p;
-        ry.E = energy(P, cdf, a, ray);
+        ry.E = ray_energy(P, cdf, a, ray);
         const double s = kHC / (P.two_d * ry.E);   // Eq. BraggLaw: sin(alpha_B)
         ry.sa = s < 1.0 ? s : 2.0;
         ry.saf = (float)s;
@@ -935,10 +985,10 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
     trace_loop<T, kDefer>(Q, Q.lut, Q.bin_cdf, claim, q);
 }
 
-// The same loop for rocking curves whose shift and width depend on the
-// photon energy, with every kind read at run time.
+// The same loop with the extended inputs (energy-dependent rocking curve,
+// source spot, user ray arrays), with every kind read at run time.
 template <class R, bool REC>
-__global__ void __launch_bounds__(256) trace_kernel_edep(const TraceParams P) {
+__global__ void __launch_bounds__(256) trace_kernel_ext(const TraceParams P) {
     using T = Tracer<R, kAny, kAny, kAny, REC, true>;
     const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
     RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};

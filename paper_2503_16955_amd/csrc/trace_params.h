@@ -48,6 +48,9 @@ struct TraceParams {
     double line_cum[kMaxLines];   // running weight sums / total, lines in order
     int32_t n_bins, pad0;
     const double *bin_cdf;        // n_bins + 1 normalised prefix sums (device)
+    int32_t spot_kind, pad_s;     // finite source spot (MRT_SPOT_*)
+    double spot_u[3], spot_v[3], spot_sigma[2];
+    const double *user_o, *user_k, *user_e;   // user ray arrays (device) or NULL
 
     // ---- crystal (sec. 2.2)
     int32_t geometry, max_refl;
@@ -149,9 +152,9 @@ const void *serve_kernel_ptr(int precision);
 // Kernel of the paper's event model (FP64) for a geometry (nullptr for an
 // unknown one): (TraceParams), like the trace kernels.
 const void *mwg_kernel_ptr(int geometry, bool records);
-// Kernel for rocking curves whose shift and width depend on the photon
-// energy (every kind read at run time).
-const void *edep_kernel_ptr(int precision, bool records);
+// Kernel for the extended inputs: an energy-dependent rocking curve, a
+// finite source spot, user ray arrays (every kind read at run time).
+const void *ext_kernel_ptr(int precision, bool records);
 constexpr int kMaxPsiNodes = 2048;
 
 }  // namespace mrt

@@ -22,6 +22,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, EAGAIN, ECANCELED = range(7)
 STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ECAPACITY", "EAGAIN", "ECANCELED"]
 SPECTRUM = {"uniform": 0, "lines": 1, "table": 2}
 GEOMETRY = {"flat": 0, "cylinder": 1}
+SPOT = {"point": 0, "gaussian": 1, "disk": 2}
 MOSAIC = {"gaussian_vmf": 0, "lorentzian": 1, "pseudo_voigt": 2, "wrapped_lorentzian": 3,
           "spherical_wrapped_lorentzian": 4}
 ROCKING = {"gaussian": 0, "pseudo_voigt": 1, "table": 2, "lorentzian": 3, "box": 4}
@@ -38,8 +39,10 @@ class MrtSource(C.Structure):
                 ("spectrum", C.c_int32), ("n_lines", C.c_int32),
                 ("e_min", C.c_double), ("e_max", C.c_double),
                 ("line_e", _D8), ("line_sigma", _D8), ("line_w", _D8),
-                ("background_w", C.c_double), ("n_bins", C.c_int32), ("reserved", C.c_int32),
-                ("bin_w", C.POINTER(C.c_double))]
+                ("background_w", C.c_double), ("n_bins", C.c_int32), ("spot_kind", C.c_int32),
+                ("bin_w", C.POINTER(C.c_double)),
+                ("spot_u", _D3), ("spot_v", _D3), ("spot_sigma", C.c_double * 2),
+                ("origins", C.c_void_p), ("directions", C.c_void_p), ("energies", C.c_void_p)]
 
 
 class MrtCrystal(C.Structure):
@@ -199,6 +202,12 @@ class Structs:
         self._bins = np.ascontiguousarray(s.get("bin_weights", [1.0]), dtype=np.float64)
         src.n_bins = len(self._bins) if s["spectrum"] == "table" else 0
         src.bin_w = self._bins.ctypes.data_as(C.POINTER(C.c_double))
+        spot = s.get("spot")
+        if spot:
+            src.spot_kind = SPOT[spot["kind"]]
+            src.spot_u, src.spot_v = _v3(spot["u"]), _v3(spot["v"])
+            sig = list(spot["sigma"]) if np.ndim(spot["sigma"]) else [spot["sigma"]]
+            src.spot_sigma = (C.c_double * 2)(*(float(x) for x in (sig + [0.0])[:2]))
         self.source = src
 
         cr = MrtCrystal()
@@ -266,13 +275,38 @@ def alloc_images(w, device="cuda", energy=True):
     return counts, en
 
 
+def _user_rays(rays, n, device):
+    """Device pointers of the user ray arrays (float64, contiguous, rows for
+    the n rays of the call): origins (n, 3), directions (n, 3), energies (n,)."""
+    import torch
+    ptrs = {}
+    for key, shape in (("origins", (n, 3)), ("directions", (n, 3)), ("energies", (n,))):
+        t = (rays or {}).get(key)
+        if t is None:
+            ptrs[key] = None
+            continue
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.device == device
+                and t.is_contiguous() and tuple(t.shape) == shape):
+            raise ValueError(f"rays[{key!r}] must be a contiguous float64 tensor of shape {shape} "
+                             f"on {device}")
+        ptrs[key] = t.data_ptr()
+    unknown = set(rays or {}) - set(ptrs)
+    if unknown:
+        raise ValueError(f"unknown ray arrays {sorted(unknown)}")
+    return ptrs
+
+
 def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_events=0,
           accumulate=False, counts=None, energy=None, want_energy=True, record_buf=None,
-          grid_blocks=0, block_threads=0, refill_idle=0, mwg_batch=0, stream=None, sync=True):
+          grid_blocks=0, block_threads=0, refill_idle=0, mwg_batch=0, rays=None, stream=None,
+          sync=True):
     """Trace rays [first, first + n_rays) of workload `w` with ``mrt_trace``.
 
     counts / energy: torch device tensors to fill (allocated when None).
-    records: None, "all" or "detected".  The event model comes from
+    rays: optional dict of user ray arrays, torch float64 device tensors
+    ``origins`` (n, 3; global mm), ``directions`` (n, 3; unit) and
+    ``energies`` (n,; keV), row i for ray first + i; each one given replaces
+    the sampled field.  records: None, "all" or "detected".  The event model comes from
     w["event_model"] (see model_options).  sync=True waits for the stream and
     returns the counters (and the kernel time); sync=False enqueues only.
     Returns a dict with ``counts``, ``energy``, ``records`` (uint8 device
@@ -294,6 +328,8 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
             rec = torch.empty((n, RECORD_BYTES), dtype=torch.uint8, device=counts.device)
         cap = rec.shape[0]
     S = Structs(w)
+    for key, ptr in _user_rays(rays, n, counts.device).items():
+        setattr(S.source, key, ptr)
     opt = MrtOptions(precision=prec, records_mode=mode, max_events=int(max_events),
                      accumulate=1 if accumulate else 0, grid_blocks=int(grid_blocks),
                      block_threads=int(block_threads), refill_idle=int(refill_idle),

@@ -201,3 +201,17 @@ def calibration_workload(w, e_min, e_max):
     c["detector"].pop("qe", None)
     c["name"] = w["name"] + "_calibration"
     return c
+
+
+def with_spot(w, kind="gaussian", fwhm=0.010):
+    """`w` with a finite source spot in the plane normal to the source axis
+    (sec. 4.2: a nominal 10 um Gaussian XFEL spot on the target).  Gaussian:
+    `fwhm` (mm) in both directions; disk: diameter `fwhm`."""
+    c = copy.deepcopy(w)
+    s = c["source"]
+    b2 = np.cross(s["axis"], s["b1"])
+    sigma = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0))) if kind == "gaussian" else fwhm / 2.0
+    s["spot"] = dict(kind=kind, u=list(s["b1"]), v=[float(x) for x in b2],
+                     sigma=[sigma, sigma] if kind == "gaussian" else [sigma, 0.0])
+    c["name"] = w["name"] + "_" + kind + "_spot"
+    return c

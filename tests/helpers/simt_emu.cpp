@@ -137,9 +137,9 @@ void serve_body(const TraceParams *slots, const ServeItem *items, uint32_t n, ui
                                                     *(RayQueue<R, false> *)queue);
 }
 
-template <class R, bool REC, bool EDEP = false>
+template <class R, bool REC, bool EXT = false>
 void trace_body(const TraceParams &P, void *queue) {
-    using T = Tracer<R, kAny, kAny, kAny, REC, EDEP>;
+    using T = Tracer<R, kAny, kAny, kAny, REC, EXT>;
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
     trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(RayQueue<R, REC> *)queue);
 }
@@ -261,7 +261,9 @@ int emu_trace(TraceParams *P, int n_waves, int precision, long long max_meetings
         QueueMem q;
         int e = run_wave([&] {
             const bool rec = P->records_mode != MRT_RECORDS_NONE;
-            if (P->dep_n > 0) {   // the energy-dependent rocking curve's kernel
+            // the extended-input kernel: energy-dependent rocking curve,
+            // source spot, user ray arrays
+            if (P->dep_n > 0 || P->spot_kind != MRT_SPOT_POINT || P->user_o || P->user_k || P->user_e) {
                 if (precision == MRT_FP64) { if (rec) trace_body<double, true, true>(*P, q.b); else trace_body<double, false, true>(*P, q.b); }
                 else { if (rec) trace_body<float, true, true>(*P, q.b); else trace_body<float, false, true>(*P, q.b); }
             } else if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P, q.b); else trace_body<double, false>(*P, q.b); }

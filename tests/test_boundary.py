@@ -42,7 +42,7 @@ def test_version_matches_header():
 
 def test_struct_sizes_match_header():
     # sizes the header's layout implies (x86-64 / amdgcn, natural alignment)
-    assert C.sizeof(mrt.MrtSource) == 320
+    assert C.sizeof(mrt.MrtSource) == 408
     assert C.sizeof(mrt.MrtCrystal) == 224
     assert C.sizeof(mrt.MrtMosaic) == 24
     assert C.sizeof(mrt.MrtRockingCurve) == 104
@@ -50,6 +50,41 @@ def test_struct_sizes_match_header():
     assert C.sizeof(mrt.MrtOptions) == 48
     assert C.sizeof(mrt.MrtCounters) == 96
     assert mrt.RECORD_DTYPE.itemsize == 104
+
+
+LAYOUT_STRUCTS = [("mrt_source", "MrtSource"), ("mrt_crystal", "MrtCrystal"),
+                  ("mrt_mosaic", "MrtMosaic"), ("mrt_rocking_curve", "MrtRockingCurve"),
+                  ("mrt_detector", "MrtDetector"), ("mrt_options", "MrtOptions"),
+                  ("mrt_counters", "MrtCounters"), ("mrt_server_config", "MrtServerConfig"),
+                  ("mrt_request", "MrtRequest"), ("mrt_request_result", "MrtRequestResult")]
+
+
+def test_binding_layout_matches_the_compiled_header(tmp_path):
+    """Every field offset and struct size of the Python binding equals what
+    a C compiler makes of include/mosaicrt.h."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mosaicrt.h"',
+             'int main(void) {']
+    want = []
+    for cname, pyname in LAYOUT_STRUCTS:
+        cls = getattr(mrt, pyname)
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        want.append(C.sizeof(cls))
+        for f in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f[0]}));')
+            want.append(getattr(cls, f[0]).offset)
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == want
 
 
 def _call(w, n=1000, first=0, opts=None, counts=1, energy=0, records=None, cap=0,
@@ -130,6 +165,52 @@ def test_invalid_spectra_and_tables():
     w = W.get("von_hamos_hapg")
     w["crystal"]["width"] = 4.0 * w["crystal"]["radius"]
     assert _call(w) == mrt.EINVAL
+
+
+SPOT = dict(kind="gaussian", u=[1.0, 0.0, 0.0], v=[0.0, 1.0, 0.0], sigma=[0.01, 0.02])
+
+
+@pytest.mark.parametrize("change", [
+    dict(kind="gaussian", sigma=[-0.01, 0.01]), dict(kind="gaussian", sigma=[0.01, float("nan")]),
+    dict(kind="disk", sigma=[float("inf"), 0.0]), dict(u=[1.0, 0.0, 0.1]),
+    dict(v=[0.6, 0.8, 0.0]),
+])
+def test_invalid_source_spots(change):
+    w = W.get("flat_hopg")
+    w["source"]["spot"] = dict(SPOT, **change)
+    assert _call(w) == mrt.EINVAL and "spot" in mrt.last_error()
+
+
+def test_unknown_spot_kind_and_valid_spots():
+    import torch
+    w = W.get("flat_hopg")
+    w["source"]["spot"] = SPOT
+    S = mrt.Structs(w)
+    S.source.spot_kind = 3
+    L = mrt.load()
+    o, cnt = mrt.MrtOptions(), mrt.MrtCounters()
+    assert L.mrt_trace(*S.refs(), 0, 10, 0, C.byref(o), C.c_void_p(1), None, None, 0, None,
+                       None) == mrt.EINVAL
+    if torch.cuda.is_available():
+        return
+    # a disk ignores spot_sigma[1]; a valid spot gets past validation
+    for spot in (SPOT, dict(SPOT, kind="disk", sigma=[0.01, -5.0])):
+        w["source"]["spot"] = spot
+        assert _call(w) == mrt.EDEVICE, mrt.last_error()
+
+
+def test_user_ray_arrays_are_checked_by_the_binding():
+    import torch
+    w = W.get("flat_hopg")
+    bad = [dict(energies=torch.ones(10, dtype=torch.float64)),                # host tensor
+           dict(origins=torch.zeros((10, 3), dtype=torch.float32)),
+           dict(directions=torch.zeros((3, 10), dtype=torch.float64).t()),
+           dict(speeds=torch.zeros(10, dtype=torch.float64))]
+    for rays in bad:
+        with pytest.raises(ValueError):
+            mrt._user_rays(rays, 10, torch.device("cuda", 0))
+    assert mrt._user_rays(None, 10, torch.device("cpu")) == dict(origins=None, directions=None,
+                                                                 energies=None)
 
 
 def test_invalid_run_arguments():

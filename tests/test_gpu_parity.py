@@ -24,14 +24,20 @@ import parity
 pytestmark = pytest.mark.gpu
 
 
-def run_both(w, n, first=0, seed=None, max_events=0, **kw):
-    print(f"[parity] {w['name']} n={n} first={first} seed={seed}", flush=True)
+def run_both(w, n, first=0, seed=None, max_events=0, rays=None, **kw):
+    """rays: optional user ray arrays (numpy), copied to the device for the
+    HIP path and read in place by the oracle."""
+    import torch
+    print(f"[parity] {w['name']} n={n} first={first} seed={seed} rays={sorted(rays or {})}",
+          flush=True)
+    dev = {k: torch.as_tensor(np.ascontiguousarray(v, np.float64), device="cuda")
+           for k, v in (rays or {}).items()}
     g = mrt.trace(w, n_rays=n, first=first, seed=seed, records="all", max_events=max_events,
-                  **kw)
+                  rays=dev or None, **kw)
     gc, ge = mrt.image_to_numpy(g["counts"], g["energy"])
     grec = mrt.records_to_numpy(g["records"])
     o = oracle.trace(w, first=first, n=n, seed=seed, max_events=max_events, records=True,
-                     margins=True)
+                     margins=True, rays=rays)
     return g, gc, ge, grec, o
 
 
