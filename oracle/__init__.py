@@ -42,13 +42,19 @@ class Source(C.Structure):
                 ("user_first", C.c_uint64)]
 
 
+class Planes(C.Structure):
+    _fields_ = [("hbar_ratio", C.c_double), ("n_extra", C.c_int32), ("pad_", C.c_int32),
+                ("two_d", D3), ("strength", D3), ("width_scale", D3), ("shift", D3)]
+
+
 class Crystal(C.Structure):
     _fields_ = [("geometry", C.c_int32), ("max_refl", C.c_int32),
                 ("centre", D3), ("normal", D3), ("e1", D3),
                 ("axis_pt", D3), ("axis_dir", D3), ("ref_dir", D3),
                 ("radius", C.c_double), ("phi_c", C.c_double), ("z_c", C.c_double),
                 ("length", C.c_double), ("width", C.c_double), ("thickness", C.c_double),
-                ("two_d", C.c_double), ("mu0", C.c_double), ("mfp", C.c_double)]
+                ("two_d", C.c_double), ("mu0", C.c_double), ("mfp", C.c_double),
+                ("planes", C.POINTER(Planes))]
 
 
 class Mosaic(C.Structure):
@@ -199,6 +205,14 @@ class Structs:
                     "mu0", "mfp"):
             if key in c:
                 setattr(self.cr, key, float(c[key]))
+        if c.get("planes") is not None:
+            pl = c["planes"]
+            extra = list(pl.get("extra", []))
+            self._planes = Planes(hbar_ratio=float(pl.get("hbar_ratio", 1.0)), n_extra=len(extra))
+            for j, (p_d, p_a, p_sc, p_sh) in enumerate(extra[:3]):
+                self._planes.two_d[j], self._planes.strength[j] = p_d, p_a
+                self._planes.width_scale[j], self._planes.shift[j] = p_sc, p_sh
+            self.cr.planes = C.pointer(self._planes)
 
         self.mo = Mosaic(kind=_MDF[m["kind"]], fwhm=m["fwhm"], eta=m.get("eta", 0.0))
 

@@ -766,6 +766,7 @@ typedef struct trace_ctx {
     uint64_t seed;
     uint32_t max_events;
     double r_max, mu_tot, p_a;
+    double plane_tot;        /* sum of the plane sets' peaks, both sides */
     /* the paper's event model */
     int mwg;                 /* 1: event model of sec. 2.2.3-2.2.4 */
     int burn_in, psi_nodes, irc_off;
@@ -793,6 +794,15 @@ static void ctx_init(trace_ctx *X, const orc_source *s, const orc_crystal *c,
        candidate reflection accepted with probability r / R_max */
     X->r_max = irc_max(irc);
     double lambda_c = X->r_max / c->mfp;
+    /* with further planes each set and side is a candidate at its own
+       peak: the majorant is the sum of the peaks */
+    X->plane_tot = 1.0;
+    if (c->planes) {
+        double sum = 1.0;
+        for (int j = 0; j < c->planes->n_extra; ++j) sum += c->planes->strength[j];
+        X->plane_tot = sum * fmax(1.0, c->planes->hbar_ratio);
+        lambda_c = X->r_max * X->plane_tot / c->mfp;
+    }
     X->mu_tot = c->mu0 + lambda_c;
     X->p_a = X->mu_tot > 0.0 ? c->mu0 / X->mu_tot : 1.0;
 }
@@ -946,8 +956,34 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
             arg = (delta - sh) / sc;
         }
         double ratio = orc_irc_value(X->irc, arg) / X->r_max;
-        note(&m, u_acc - ratio);
-        if (u_acc < ratio) {
+        int reflect;
+        if (c->planes) {
+            /* several plane sets and the two sides (sec. 2.2.3): the
+               candidate reflects with the summed probability of every set
+               j, sum_j a_j r_j(Delta_j), times hbar_ratio when the ray
+               travels along n (it meets the antiparallel planes), over the
+               majorant sum of the peaks.  The reflected direction is the
+               same whichever set reflects, so none is chosen. */
+            const orc_planes *pl = c->planes;
+            double a = asin(akn);
+            double sum = 0.0;
+            for (int j = 0; j <= pl->n_extra; ++j) {
+                double ab = j ? orc_bragg_angle(E, pl->two_d[j - 1]) : alpha_b;
+                if (ab < 0.0) continue;
+                double sh = j ? pl->shift[j - 1] : X->irc->shift;
+                double sc = j ? pl->width_scale[j - 1] : 1.0;
+                double st = j ? pl->strength[j - 1] : 1.0;
+                sum += st * (orc_irc_value(X->irc, ((a - ab) - sh) / sc) / X->r_max);
+            }
+            double side = kn < 0.0 ? 1.0 : pl->hbar_ratio;
+            double lhs = u_acc * X->plane_tot, rhs = side * sum;
+            note(&m, (lhs - rhs) / X->plane_tot);
+            reflect = lhs < rhs;
+        } else {
+            note(&m, u_acc - ratio);
+            reflect = u_acc < ratio;
+        }
+        if (reflect) {
             /* reflection equation of sec. 2.2.4 */
             double ks[3];
             axpy(k, -2.0 * kn, n, ks);
@@ -1050,6 +1086,15 @@ static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic 
     for (int i = 0; i < irc->n_dep; ++i)
         if (!(irc->dep_scale[i] > 0.0) || (i && !(irc->dep_kev[i] > irc->dep_kev[i - 1]))) return -14;
     if (irc->n_dep > 0 && model && model->kind == ORC_MODEL_MWG) return -15;
+    if (c->planes) {
+        const orc_planes *pl = c->planes;
+        if (!(pl->hbar_ratio >= 0.0) || pl->n_extra < 0 || pl->n_extra > 3) return -17;
+        for (int j = 0; j < pl->n_extra; ++j)
+            if (!(pl->two_d[j] > 0.0 && pl->two_d[j] <= c->two_d) || !(pl->strength[j] > 0.0) ||
+                !(pl->width_scale[j] > 0.0))
+                return -17;
+        if ((model && model->kind == ORC_MODEL_MWG) || irc->n_dep > 0) return -17;
+    }
     if (s->spectrum == ORC_SPEC_TABLE && (s->n_bins < 1 || !s->bin_w)) return -6;
     if (s->spot_kind < ORC_SPOT_POINT || s->spot_kind > ORC_SPOT_DISK) return -16;
     if (s->spot_kind != ORC_SPOT_POINT &&

@@ -64,6 +64,17 @@ typedef struct orc_source {
     uint64_t user_first;
 } orc_source;
 
+/* Reflecting planes beyond the main set (sec. 2.2.3, closing paragraphs):
+   the antiparallel planes' strength relative to H, and up to three further
+   plane sets (higher orders) with their own spacing, peak strength
+   relative to the main curve, width scale and shift of the curve. */
+typedef struct orc_planes {
+    double hbar_ratio;
+    int32_t n_extra;
+    int32_t pad_;
+    double two_d[3], strength[3], width_scale[3], shift[3];
+} orc_planes;
+
 typedef struct orc_crystal {
     int32_t geometry;        /* ORC_GEOM_* */
     int32_t max_refl;
@@ -78,6 +89,7 @@ typedef struct orc_crystal {
     double two_d;            /* Angstrom */
     double mu0;              /* linear attenuation, 1/mm */
     double mfp;              /* mean path between crystallite encounters, mm */
+    const orc_planes *planes;  /* NULL: the main set alone, H and H-bar alike */
 } orc_crystal;
 
 typedef struct orc_mosaic {

@@ -85,6 +85,19 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
     if (!(c->mu0 >= 0.0) || !std::isfinite(c->mu0)) return fail(MRT_EINVAL, "crystal: mu0 must be >= 0");
     if (!(c->mfp > 0.0) || !std::isfinite(c->mfp)) return fail(MRT_EINVAL, "crystal: mfp must be > 0");
     if (c->max_refl < 0) return fail(MRT_EINVAL, "crystal: max_refl must be >= 0");
+    if (const mrt_planes *pl = c->planes) {
+        if (!(pl->hbar_ratio >= 0.0) || !std::isfinite(pl->hbar_ratio))
+            return fail(MRT_EINVAL, "planes: hbar_ratio must be finite and >= 0");
+        if (pl->n_extra < 0 || pl->n_extra > 3) return fail(MRT_EINVAL, "planes: n_extra must be 0..3");
+        for (int j = 0; j < pl->n_extra; ++j) {
+            if (!(pl->two_d[j] > 0.0) || !(pl->two_d[j] <= c->two_d))
+                return fail(MRT_EINVAL, "planes: two_d[%d] must lie in (0, crystal two_d]", j);
+            if (!(pl->strength[j] > 0.0) || !std::isfinite(pl->strength[j]) ||
+                !(pl->width_scale[j] > 0.0) || !std::isfinite(pl->width_scale[j]) ||
+                !std::isfinite(pl->shift[j]))
+                return fail(MRT_EINVAL, "planes: set %d needs finite strength > 0, width_scale > 0, shift", j);
+        }
+    }
     // mosaic
     if (m->kind < 0 || m->kind > 4) return fail(MRT_EINVAL, "mosaic: unknown kind");
     if (!(m->fwhm >= 0.0) || !std::isfinite(m->fwhm)) return fail(MRT_EINVAL, "mosaic: fwhm must be >= 0");
@@ -123,6 +136,8 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
             if (i && !(r->dep_kev[i] > r->dep_kev[i - 1]))
                 return fail(MRT_EINVAL, "rocking curve: energy-dependence energies must increase strictly");
         }
+        if (c->planes)
+            return fail(MRT_EINVAL, "an energy-dependent rocking curve takes no further reflecting planes");
     }
     {
         const size_t lut = r->kind == MRT_IRC_TABLE ? (size_t)r->n_table : 0;
@@ -245,8 +260,8 @@ void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocki
     }
 }
 
-bool uses_ext(const mrt_source *s, const mrt_rocking_curve *r) {
-    return r->n_dep > 0 || s->spot_kind != MRT_SPOT_POINT || s->origins || s->directions || s->energies;
+bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve *r) {
+    return r->n_dep > 0 || c->planes || s->spot_kind != MRT_SPOT_POINT || s->origins || s->directions || s->energies;
 }
 
 void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
@@ -326,7 +341,29 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
         rmax = 0.0;
         for (int i = 0; i < r->n_table; ++i) rmax = std::max(rmax, r->table[i]);
     }
-    const double lambda_c = rmax / c->mfp;   // majorant crystallite-encounter rate
+    // reflecting planes: set 0 is the main set (the curve as given)
+    P.n_planes = 1;
+    P.plane_2d[0] = c->two_d;
+    P.plane_a[0] = 1.0;
+    P.plane_scale[0] = 1.0;
+    P.plane_shift[0] = r->shift;
+    P.hbar = 1.0;
+    if (const mrt_planes *pl = c->planes) {
+        P.has_planes = 1;
+        P.hbar = pl->hbar_ratio;
+        for (int j = 0; j < pl->n_extra; ++j) {
+            P.plane_2d[1 + j] = pl->two_d[j];
+            P.plane_a[1 + j] = pl->strength[j];
+            P.plane_scale[1 + j] = pl->width_scale[j];
+            P.plane_shift[1 + j] = pl->shift[j];
+        }
+        P.n_planes = 1 + pl->n_extra;
+    }
+    double sum_a = 0.0;
+    for (int j = 0; j < P.n_planes; ++j) sum_a += P.plane_a[j];
+    P.plane_tot = sum_a * std::max(1.0, P.hbar);
+    // majorant crystallite-encounter rate: every set and side at its peak
+    const double lambda_c = rmax * P.plane_tot / c->mfp;
     const double mu_tot = c->mu0 + lambda_c;
     P.mu0 = c->mu0;
     P.inv_mu0 = 1.0 / c->mu0;

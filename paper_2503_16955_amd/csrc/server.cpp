@@ -427,9 +427,9 @@ mrt_status mrt_server_submit(mrt_server *S, const mrt_request *q, uint64_t *tick
                                   fail);
     if (st != MRT_OK) return st;
     if (q->n_rays == 0) return fail(MRT_EINVAL, "n_rays must be > 0");
-    if (mrt::uses_ext(q->source, q->rocking_curve))
-        return fail(MRT_EINVAL, "energy-dependent rocking curves, source spots and user ray arrays "
-                                "are traced by mrt_trace, not served");
+    if (mrt::uses_ext(q->source, q->crystal, q->rocking_curve))
+        return fail(MRT_EINVAL, "energy-dependent rocking curves, source spots, user ray arrays and "
+                                "further reflecting planes are traced by mrt_trace, not served");
     Rec r;
     mrt::build_params(q->source, q->crystal, q->mosaic, q->rocking_curve, q->detector, r.P,
                       r.tables);

@@ -517,9 +517,29 @@ struct Tracer {
         double akn = __builtin_fabs(kn);
         akn = akn < 1.0 ? akn : 1.0;
         int dec;
-        bool dep = false;   // the curve depends on the energy (wave-uniform)
-        if constexpr (EXT) dep = P.dep_n > 0;
-        if (dep) {
+        bool dep = false;      // the curve depends on the energy (wave-uniform)
+        bool planes = false;   // further plane sets or an H-bar ratio (wave-uniform)
+        if constexpr (EXT) {
+            dep = P.dep_n > 0;
+            planes = P.has_planes != 0;
+        }
+        if (planes) {
+            // every plane set j and side (sec. 2.2.3): reflect when
+            // u sum_j a_j max(1, hbar) < h(k.n) sum_j a_j r_j(Delta_j) / R_max,
+            // h = 1 against the normal (H), hbar along it (H-bar); always in FP64
+            refined = true;
+            const double a = ::asin(akn);
+            double sum = 0.0;
+            for (int j = 0; j < P.n_planes; ++j) {
+                const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
+                if (sj < 1.0) {
+                    const double x = ((a - ::asin(sj)) - P.plane_shift[j]) / P.plane_scale[j];
+                    sum += P.plane_a[j] * irc_ratio(P, lut, x);
+                }
+            }
+            const double h = kn < 0.0 ? 1.0 : P.hbar;
+            dec = (double)u_acc * P.plane_tot < h * sum ? 1 : 0;
+        } else if (dep) {
             // Delta_M(E) and the width scale s(E) (sec. 2.2.1): r read at
             // (Delta - Delta_M(E)) / s(E)
             const double shift = interp(P.dep, P.dep + P.dep_n, P.dep_n, ry.E);

@@ -61,6 +61,10 @@ struct TraceParams {
     double R, R2, Ro2;            // front radius, R^2, (R + T)^2
     double mu0, inv_mu0, inv_mu_tot, p_a, inv_1mpa;
     double two_d;                 // lattice spacing 2d (Angstrom)
+    // reflecting planes (extended-input kernels): set 0 is the main set
+    int32_t has_planes, n_planes;
+    double plane_2d[4], plane_a[4], plane_scale[4], plane_shift[4];
+    double hbar, plane_tot;       // H-bar / H ratio; sum_j a_j max(1, hbar)
     double origin[3];             // local origin in global coordinates
 
     // ---- mosaic (sec. 2.2.2)

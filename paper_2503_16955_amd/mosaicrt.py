@@ -45,13 +45,30 @@ class MrtSource(C.Structure):
                 ("origins", C.c_void_p), ("directions", C.c_void_p), ("energies", C.c_void_p)]
 
 
+class MrtPlanes(C.Structure):
+    _fields_ = [("hbar_ratio", C.c_double), ("n_extra", C.c_int32), ("reserved", C.c_int32),
+                ("two_d", _D3), ("strength", _D3), ("width_scale", _D3), ("shift", _D3)]
+
+
+def planes_struct(pl):
+    """MrtPlanes from a workload's crystal["planes"]: {"hbar_ratio": b,
+    "extra": [(two_d, strength, width_scale, shift), ...]}."""
+    out = MrtPlanes(hbar_ratio=float(pl.get("hbar_ratio", 1.0)))
+    extra = list(pl.get("extra", []))
+    out.n_extra = len(extra)
+    for j, (d, a, sc, sh) in enumerate(extra[:3]):
+        out.two_d[j], out.strength[j], out.width_scale[j], out.shift[j] = d, a, sc, sh
+    return out
+
+
 class MrtCrystal(C.Structure):
     _fields_ = [("geometry", C.c_int32), ("max_refl", C.c_int32),
                 ("centre", _D3), ("normal", _D3), ("e1", _D3),
                 ("axis_pt", _D3), ("axis_dir", _D3), ("ref_dir", _D3),
                 ("radius", C.c_double), ("phi_c", C.c_double), ("z_c", C.c_double),
                 ("length", C.c_double), ("width", C.c_double), ("thickness", C.c_double),
-                ("two_d", C.c_double), ("mu0", C.c_double), ("mfp", C.c_double)]
+                ("two_d", C.c_double), ("mu0", C.c_double), ("mfp", C.c_double),
+                ("planes", C.POINTER(MrtPlanes))]
 
 
 class MrtMosaic(C.Structure):
@@ -220,6 +237,9 @@ class Structs:
                     "mfp"):
             if key in c:
                 setattr(cr, key, float(c[key]))
+        if c.get("planes") is not None:
+            self._planes = planes_struct(c["planes"])
+            cr.planes = C.pointer(self._planes)
         self.crystal = cr
 
         self.mosaic = MrtMosaic(kind=MOSAIC[m["kind"]], fwhm=float(m["fwhm"]),

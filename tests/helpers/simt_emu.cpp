@@ -263,7 +263,8 @@ int emu_trace(TraceParams *P, int n_waves, int precision, long long max_meetings
             const bool rec = P->records_mode != MRT_RECORDS_NONE;
             // the extended-input kernel: energy-dependent rocking curve,
             // source spot, user ray arrays
-            if (P->dep_n > 0 || P->spot_kind != MRT_SPOT_POINT || P->user_o || P->user_k || P->user_e) {
+            if (P->dep_n > 0 || P->spot_kind != MRT_SPOT_POINT || P->user_o || P->user_k || P->user_e ||
+                P->has_planes) {
                 if (precision == MRT_FP64) { if (rec) trace_body<double, true, true>(*P, q.b); else trace_body<double, false, true>(*P, q.b); }
                 else { if (rec) trace_body<float, true, true>(*P, q.b); else trace_body<float, false, true>(*P, q.b); }
             } else if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P, q.b); else trace_body<double, false>(*P, q.b); }

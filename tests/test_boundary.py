@@ -43,7 +43,8 @@ def test_version_matches_header():
 def test_struct_sizes_match_header():
     # sizes the header's layout implies (x86-64 / amdgcn, natural alignment)
     assert C.sizeof(mrt.MrtSource) == 408
-    assert C.sizeof(mrt.MrtCrystal) == 224
+    assert C.sizeof(mrt.MrtCrystal) == 232
+    assert C.sizeof(mrt.MrtPlanes) == 112
     assert C.sizeof(mrt.MrtMosaic) == 24
     assert C.sizeof(mrt.MrtRockingCurve) == 104
     assert C.sizeof(mrt.MrtDetector) == 136
@@ -52,7 +53,7 @@ def test_struct_sizes_match_header():
     assert mrt.RECORD_DTYPE.itemsize == 104
 
 
-LAYOUT_STRUCTS = [("mrt_source", "MrtSource"), ("mrt_crystal", "MrtCrystal"),
+LAYOUT_STRUCTS = [("mrt_source", "MrtSource"), ("mrt_crystal", "MrtCrystal"), ("mrt_planes", "MrtPlanes"),
                   ("mrt_mosaic", "MrtMosaic"), ("mrt_rocking_curve", "MrtRockingCurve"),
                   ("mrt_detector", "MrtDetector"), ("mrt_options", "MrtOptions"),
                   ("mrt_counters", "MrtCounters"), ("mrt_server_config", "MrtServerConfig"),
@@ -196,6 +197,36 @@ def test_unknown_spot_kind_and_valid_spots():
     # a disk ignores spot_sigma[1]; a valid spot gets past validation
     for spot in (SPOT, dict(SPOT, kind="disk", sigma=[0.01, -5.0])):
         w["source"]["spot"] = spot
+        assert _call(w) == mrt.EDEVICE, mrt.last_error()
+
+
+@pytest.mark.parametrize("planes", [
+    dict(hbar_ratio=-0.5), dict(hbar_ratio=float("inf")), dict(extra=[(7.0, 1.0, 1.0, 0.0)]),
+    dict(extra=[(3.354, 0.0, 1.0, 0.0)]), dict(extra=[(3.354, 1.0, -1.0, 0.0)]),
+    dict(extra=[(3.354, 1.0, 1.0, float("nan"))]), dict(extra=[(0.0, 1.0, 1.0, 0.0)]),
+])
+def test_invalid_planes(planes):
+    w = W.get("flat_hopg")
+    w["crystal"]["planes"] = planes
+    assert _call(w) == mrt.EINVAL and "planes" in mrt.last_error()
+
+
+def test_planes_exclusions_and_count():
+    import torch
+    w = W.get("flat_hopg")
+    w["crystal"]["planes"] = dict(extra=[(3.354, 1.0, 1.0, 0.0)])
+    S = mrt.Structs(w)
+    S._planes.n_extra = 4
+    L = mrt.load()
+    o = mrt.MrtOptions()
+    assert L.mrt_trace(*S.refs(), 0, 10, 0, C.byref(o), C.c_void_p(1), None, None, 0, None,
+                       None) == mrt.EINVAL
+    assert _call(w, opts=mrt.MrtOptions(event_model=mrt.MODEL["mwg"])) == mrt.EINVAL
+    assert "planes" in mrt.last_error()
+    w["rocking_curve"]["energy_dependence"] = [(8.0, 0.0, 1.0)]
+    assert _call(w) == mrt.EINVAL and "planes" in mrt.last_error()
+    if not torch.cuda.is_available():
+        w["rocking_curve"].pop("energy_dependence")
         assert _call(w) == mrt.EDEVICE, mrt.last_error()
 
 

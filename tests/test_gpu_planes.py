@@ -1,0 +1,129 @@
+"""Further reflecting planes on the GPU (sec. 2.2.3, closing paragraphs),
+through the C-ABI: the antiparallel planes' own strength and higher orders,
+in per-ray parity with the oracle (FP64) on both geometries and the
+tabulated curve, sampled at the full 1e8-ray von Hamos size; the
+second-order identity (photons of 2E on 2d/2 trace like photons of E on 2d)
+on the device; an empty plane list takes the plain kernel's decisions;
+FP32-mixed agrees with FP64 statistically; the paper's event model and the
+request server refuse planes."""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_16955_amd import mosaicrt as mrt
+from paper_2503_16955_amd import workloads as W
+
+import parity
+from test_gpu_parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _planes(w, hbar=1.0, extra=()):
+    w = copy.deepcopy(w)
+    w["crystal"]["planes"] = {"hbar_ratio": hbar, "extra": list(extra)}
+    return w
+
+
+def _von_hamos_orders(hbar=0.5):
+    # a line at twice the Cu K-alpha-like energy, reflected by (004)
+    w = W.get("von_hamos_hapg")
+    w["source"]["lines"] = list(w["source"]["lines"]) + [(2 * 8.048, 0.004, 0.4)]
+    td = w["crystal"]["two_d"]
+    return _planes(w, hbar, [(td / 2, 0.6, 1.5, 5e-6)])
+
+
+def test_planes_flat_parity():
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    td = w["crystal"]["two_d"]
+    g, o = assert_parity(_planes(w, 0.3, [(td / 2, 0.5, 1.0, 0.0), (td / 3, 0.2, 0.7, -3e-6)]),
+                         100_000)
+    assert o["counters"]["reflections"] > 500
+
+
+def test_planes_von_hamos_parity():
+    g, o = assert_parity(_von_hamos_orders(), 300_000)
+    assert o["counters"]["reflections"] > 1000
+
+
+def test_planes_tabulated_curve_parity():
+    w = W.get("flat_stress", precision="fp64")
+    td = w["crystal"]["two_d"]
+    g, o = assert_parity(_planes(w, 1.7, [(td / 2, 0.4, 2.0, 0.0)]), 60_000)
+    assert o["counters"]["reflections"] > 500
+
+
+@pytest.mark.parametrize("n", [1, 65, 4097])
+def test_planes_ragged_launches(n):
+    assert_parity(_von_hamos_orders(0.0), n, first=(1 << 32) - 7)
+
+
+def test_second_order_at_twice_the_energy_on_the_device():
+    import torch
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    w = _planes(w, extra=[(w["crystal"]["two_d"] / 2, 1.0, 1.0, w["rocking_curve"]["shift"])])
+    n = 400_000
+    e = torch.as_tensor(np.random.default_rng(3).uniform(7.9, 8.1, n), device="cuda")
+    a = mrt.trace(w, n_rays=n, records="all", rays={"energies": e})
+    b = mrt.trace(w, n_rays=n, records="all", rays={"energies": 2 * e})
+    ra, rb = mrt.records_to_numpy(a["records"]), mrt.records_to_numpy(b["records"])
+    assert np.array_equal(rb["energy"], 2 * ra["energy"])
+    ra["energy"] = rb["energy"]
+    assert ra.tobytes() == rb.tobytes()
+    assert a["counters"]["reflections"] == b["counters"]["reflections"] > 1000
+
+
+def test_empty_plane_list_takes_the_plain_decisions():
+    w = W.get("von_hamos_hapg")
+    n = 2_000_000
+    a = mrt.trace(_planes(w), n_rays=n)
+    b = mrt.trace(w, n_rays=n)
+    for f in ("absorbed", "exit_reflected", "exit_transmitted", "detected", "events", "reflections"):
+        assert a["counters"][f] == b["counters"][f], f
+    ca, ea = mrt.image_to_numpy(a["counts"], a["energy"])
+    cb, eb = mrt.image_to_numpy(b["counts"], b["energy"])
+    assert np.array_equal(ca, cb) and np.array_equal(ea, eb)
+
+
+def test_planes_fp32_mixed_agree_with_fp64():
+    w = _von_hamos_orders()
+    n = 20_000_000
+    a = mrt.trace(w, n_rays=n, precision="fp32_mixed")["counters"]
+    b = mrt.trace(w, n_rays=n, precision="fp64")["counters"]
+    for f in ("reflections", "detected", "exit_reflected"):
+        assert abs(a[f] - b[f]) < 5 * np.sqrt(a[f] + b[f]) + 1e-3 * b[f], (f, a[f], b[f])
+
+
+def test_planes_refused_by_the_papers_model_and_the_server():
+    w = _von_hamos_orders()
+    m = copy.deepcopy(w)
+    m["event_model"] = {"kind": "mwg"}
+    with pytest.raises(mrt.MosaicRTError):
+        mrt.trace(m, n_rays=1000)
+    with mrt.Server(hbm_budget_bytes=1 << 28, max_slots=2) as srv:
+        with pytest.raises(mrt.MosaicRTError):
+            srv.submit(w, n_rays=1000)
+
+
+def test_planes_full_size_sampled():
+    """1e8 von Hamos rays with H-bar at 0.5 and a second order: 4096 sampled
+    ray ids against the oracle, photons conserved."""
+    import torch
+    w = _von_hamos_orders()
+    n = w["n_rays"]
+    print("[planes-full] records launch", flush=True)
+    g = mrt.trace(w, records="all")
+    ids = np.unique(np.random.default_rng(14).integers(0, n, 4096, dtype=np.int64))
+    rec_dev = g["records"]
+    grec = mrt.records_to_numpy(rec_dev.index_select(0, torch.as_tensor(ids, device=rec_dev.device)))
+    orec, mg = oracle.trace_ids(w, ids)
+    n_ties, bad, _ = parity.compare(grec, orec, mg)
+    assert len(bad) == 0, parity.describe(grec, orec, mg, bad)
+    assert n_ties == 0
+    c = g["counters"]
+    assert (c["missed"] + c["absorbed"] + c["exit_reflected"] + c["exit_transmitted"]
+            + c["truncated"]) == n

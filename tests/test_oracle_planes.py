@@ -1,0 +1,127 @@
+"""Pins of the oracle's further reflecting planes (sec. 2.2.3, closing
+paragraphs): the antiparallel planes' own strength and higher orders.
+
+Exact identities of the written model: an empty plane list changes nothing;
+a duplicate of the main set at strength 1 is the main set at twice the peak;
+the second order (spacing 2d/2) met by photons of energy 2E gives the records
+the first order gives at E (hc / ((2d/2) 2E) = hc / (2d E) in floating point);
+with the antiparallel planes switched off (ratio 0) no ray reflects twice on
+a flat crystal, and every first reflection is the one of the centrosymmetric
+run (the same random numbers decide it).  A width scale of 2 on the second
+order equals the first order's Gaussian curve of twice the FWHM up to
+rounding (compared ray by ray with the decision margins)."""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_16955_amd import workloads as W
+
+import parity
+
+
+def _rec(w, n, rays=None):
+    return oracle.trace(w, n=n, records=True, margins=True, rays=rays)
+
+
+def _planes(w, hbar=1.0, extra=()):
+    w = copy.deepcopy(w)
+    w["crystal"]["planes"] = {"hbar_ratio": hbar, "extra": list(extra)}
+    return w
+
+
+def test_empty_plane_list_changes_nothing():
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    a = _rec(w, 40000)["records"]
+    b = _rec(_planes(w), 40000)["records"]
+    assert a.tobytes() == b.tobytes()
+
+
+def test_duplicate_main_set_is_twice_the_peak():
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    assert w["rocking_curve"]["kind"] == "gaussian" and w["rocking_curve"]["peak"] == 0.5
+    rc = w["rocking_curve"]
+    dup = _planes(w, extra=[(w["crystal"]["two_d"], 1.0, 1.0, rc["shift"])])
+    twice = copy.deepcopy(w)
+    twice["rocking_curve"]["peak"] = 1.0
+    a, b = _rec(dup, 40000)["records"], _rec(twice, 40000)["records"]
+    assert a.tobytes() == b.tobytes()
+    assert b["n_refl"].sum() > _rec(w, 40000)["records"]["n_refl"].sum()
+
+
+def test_second_order_at_twice_the_energy_is_the_first_order():
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    rc = w["rocking_curve"]
+    w = _planes(w, extra=[(w["crystal"]["two_d"] / 2, 1.0, 1.0, rc["shift"])])
+    n = 40000
+    _, _, e = oracle.source_sample(w, np.arange(n))
+    a = _rec(w, n, rays={"energies": e})["records"]
+    b = _rec(w, n, rays={"energies": 2 * e})["records"]
+    assert np.array_equal(b["energy"], 2 * a["energy"])
+    a2 = a.copy()
+    a2["energy"] = b["energy"]
+    assert a2.tobytes() == b.tobytes()
+    assert a["n_refl"].sum() > 100
+    # without the second order the doubled energies do not reflect
+    plain = copy.deepcopy(w)
+    plain["crystal"].pop("planes")
+    assert _rec(plain, n, rays={"energies": 2 * e})["records"]["n_refl"].sum() == 0
+
+
+def test_second_order_width_scale_and_shift():
+    # second order with width scale 2 and its own shift, at 2E, against the
+    # first order at E whose curve has twice the FWHM and that shift; both
+    # runs carry a second set of strength 1 so that their majorants agree
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    td, rc = w["crystal"]["two_d"], w["rocking_curve"]
+    a_w = _planes(w, extra=[(td / 2, 1.0, 2.0, 12e-6)])
+    b_w = copy.deepcopy(w)
+    b_w["rocking_curve"] = dict(rc, fwhm=2 * rc["fwhm"], shift=12e-6)
+    b_w = _planes(b_w, extra=[(td / 2, 1.0, 1.0, 0.0)])
+    n = 40000
+    _, _, e = oracle.source_sample(w, np.arange(n))
+    A = _rec(a_w, n, rays={"energies": 2 * e})
+    B = _rec(b_w, n, rays={"energies": e})
+    ra, rb = A["records"].copy(), B["records"]
+    ra["energy"] = ra["energy"] / 2
+    n_ties, bad, _ = parity.compare(ra, rb, np.minimum(A["margins"], B["margins"]))
+    assert len(bad) == 0 and n_ties <= 2
+    assert rb["n_refl"].sum() > 100
+
+
+def test_no_antiparallel_planes_means_one_reflection():
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 8
+    w["crystal"]["thickness"] = 0.2
+    n = 100000
+    on = _rec(_planes(w, hbar=1.0), n)["records"]
+    off = _rec(_planes(w, hbar=0.0), n)["records"]
+    assert (on["n_refl"] >= 2).sum() > 50
+    assert off["n_refl"].max() == 1
+    assert np.array_equal(off["n_refl"] == 1, on["n_refl"] >= 1)
+
+
+@pytest.mark.parametrize("bad", [dict(hbar=-0.1), dict(extra=[(7.0, 1.0, 1.0, 0.0)]),
+                                 dict(extra=[(3.0, 0.0, 1.0, 0.0)]),
+                                 dict(extra=[(3.0, 1.0, 0.0, 0.0)]),
+                                 dict(extra=[(3.0, 1.0, 1.0, 0.0)] * 4)])
+def test_invalid_planes_rejected(bad):
+    w = _planes(W.get("flat_hopg"), **bad)
+    with pytest.raises(ValueError):
+        oracle.trace(w, n=10)
+
+
+def test_planes_rejected_with_the_papers_model_and_energy_dependence():
+    w = _planes(W.get("flat_hopg"))
+    w["event_model"] = {"kind": "mwg"}
+    with pytest.raises(ValueError):
+        oracle.trace(w, n=10)
+    w = _planes(W.get("flat_hopg"))
+    w["rocking_curve"]["energy_dependence"] = [(8.0, 0.0, 1.0)]
+    with pytest.raises(ValueError):
+        oracle.trace(w, n=10)

@@ -301,3 +301,35 @@ def test_source_spot_and_user_ray_loops(emu, case):
     _assert_records_match(rec, o["records"])
     assert np.array_equal(j.counts, o["counts"].ravel())
     assert int(rec["n_refl"].sum()) > 20
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_reflecting_planes_loop(emu, precision):
+    """The extended-input kernel with an antiparallel-plane ratio and a second
+    order, under the emulator: in FP64 every ray matches the oracle; in
+    FP32-mixed (every plane decision in FP64) the counters agree with FP64
+    within counting statistics."""
+    import oracle
+    from paper_2503_16955_amd import workloads as W
+    w = W.get("von_hamos_hapg")
+    td = w["crystal"]["two_d"]
+    w["crystal"]["planes"] = {"hbar_ratio": 0.4, "extra": [(td / 2, 0.6, 1.5, 5e-6)]}
+    # a line at twice the Cu K-alpha-like energy, which the second order
+    # reflects onto the same detector region
+    w["source"]["lines"] = list(w["source"]["lines"]) + [(2 * 8.048, 0.004, 0.4)]
+    n, seed = 5000, 4
+    j = Job(emu, w, n, seed)
+    if precision == "fp64":
+        rec = np.zeros(n, mrt.RECORD_DTYPE)
+        emu.emu_set_records(j.P, rec.ctypes.data, n)
+        assert emu.emu_trace(j.P, WAVES, mrt.PRECISION["fp64"], MAX_MEETINGS) == 0
+        o = oracle.trace(w, n=n, seed=seed, records=True)
+        _assert_records_match(rec, o["records"])
+        assert np.array_equal(j.counts, o["counts"].ravel())
+        assert int(rec["n_refl"].sum()) > 20
+    else:
+        assert emu.emu_trace(j.P, WAVES, mrt.PRECISION["fp32_mixed"], MAX_MEETINGS) == 0
+        o = oracle.trace(w, n=n, seed=seed)["counters"]
+        c = j.counters()
+        for f in ("reflections", "absorbed"):
+            assert abs(c[f] - o[f]) < 5 * np.sqrt(c[f] + o[f]) + 5, (f, c[f], o[f])
