@@ -39,7 +39,7 @@ class Source(C.Structure):
                 ("bin_w", C.POINTER(C.c_double)),
                 ("spot_u", D3), ("spot_v", D3), ("spot_sigma", C.c_double * 2),
                 ("user_o", C.c_void_p), ("user_k", C.c_void_p), ("user_e", C.c_void_p),
-                ("user_first", C.c_uint64)]
+                ("user_first", C.c_uint64), ("user_p", C.c_void_p)]
 
 
 class Planes(C.Structure):
@@ -117,6 +117,8 @@ def lib():
         P = C.POINTER
         L.orc_philox4x32.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
         L.orc_philox4x64.argtypes = [P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+        L.orc_polarisation_reflect.restype = C.c_double
+        L.orc_polarisation_reflect.argtypes = [P(C.c_double), P(C.c_double), P(C.c_double)]
         L.orc_bragg_angle.restype = C.c_double
         L.orc_bragg_angle.argtypes = [C.c_double, C.c_double]
         L.orc_pvoigt_params.argtypes = [C.c_double, C.c_double, P(C.c_double), P(C.c_double)]
@@ -243,7 +245,8 @@ class Structs:
         for ray ids first .. first + n_rows - 1."""
         for key, field, shape in (("origins", "user_o", (n_rows, 3)),
                                   ("directions", "user_k", (n_rows, 3)),
-                                  ("energies", "user_e", (n_rows,))):
+                                  ("energies", "user_e", (n_rows,)),
+                                  ("polarisations", "user_p", (n_rows, 3))):
             a = (rays or {}).get(key)
             if a is None:
                 continue
@@ -334,6 +337,13 @@ def philox4x64(ctr, key):
     o = (C.c_uint64 * 4)()
     lib().orc_philox4x64(c, k, o)
     return list(o)
+
+
+def polarisation_reflect(p, ks):
+    """(G, new polarisation) for polarisation p and reflected direction ks."""
+    out = D3()
+    g = lib().orc_polarisation_reflect(_d3(p), _d3(ks), out)
+    return g, np.array(list(out))
 
 
 def bragg_angle(energy_kev, two_d):

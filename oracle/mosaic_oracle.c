@@ -882,6 +882,11 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
 
     orc_source_sample(X->s, X->seed, ray, o, k, &E);
     rec->energy = E;
+    /* polarisation, when the user supplies it (sec. 2.1) */
+    int polarised = X->s->user_p != NULL;
+    double pol[3] = {0.0, 0.0, 0.0};
+    if (polarised)
+        for (int i = 0; i < 3; ++i) pol[i] = X->s->user_p[3 * (ray - X->s->user_first) + i];
     if (!crystal_entry(c, &X->E, o, k, &t_in, &m)) {
         rec->status = ORC_MISS;
         for (int i = 0; i < 3; ++i) {
@@ -956,6 +961,17 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
             arg = (delta - sh) / sc;
         }
         double ratio = orc_irc_value(X->irc, arg) / X->r_max;
+        /* the reflected direction (reflection equation of sec. 2.2.4) and,
+           with polarisations, the factor G = 1 - (p.k_s)^2 of sec. 2.2.3 */
+        double ks[3];
+        axpy(k, -2.0 * kn, n, ks);
+        double nr = sqrt(dot(ks, ks));
+        for (int i = 0; i < 3; ++i) ks[i] /= nr;
+        double pks = 0.0, G = 1.0;
+        if (polarised) {
+            pks = dot(pol, ks);
+            G = 1.0 - pks * pks;
+        }
         int reflect;
         if (c->planes) {
             /* several plane sets and the two sides (sec. 2.2.3): the
@@ -976,19 +992,21 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
                 sum += st * (orc_irc_value(X->irc, ((a - ab) - sh) / sc) / X->r_max);
             }
             double side = kn < 0.0 ? 1.0 : pl->hbar_ratio;
-            double lhs = u_acc * X->plane_tot, rhs = side * sum;
+            double lhs = u_acc * X->plane_tot, rhs = G * (side * sum);
             note(&m, (lhs - rhs) / X->plane_tot);
             reflect = lhs < rhs;
         } else {
-            note(&m, u_acc - ratio);
-            reflect = u_acc < ratio;
+            note(&m, u_acc - G * ratio);
+            reflect = u_acc < G * ratio;
         }
         if (reflect) {
-            /* reflection equation of sec. 2.2.4 */
-            double ks[3];
-            axpy(k, -2.0 * kn, n, ks);
-            double nr = sqrt(dot(ks, ks));
-            for (int i = 0; i < 3; ++i) k[i] = ks[i] / nr;
+            for (int i = 0; i < 3; ++i) k[i] = ks[i];
+            if (polarised) {
+                /* the polarisation after the reflection (sec. 2.2.4): its
+                   component along k_s removed, renormalised */
+                double g = sqrt(1.0 - pks * pks);
+                for (int i = 0; i < 3; ++i) pol[i] = (pol[i] - pks * ks[i]) / g;
+            }
             ++n_refl;
         }
     }
@@ -1010,6 +1028,16 @@ finish:
         }
     }
     *margin = m;
+}
+
+/* The polarisation factor and the polarisation after a reflection
+   (sec. 2.2.3, 2.2.4) for a polarisation p and a reflected direction k_s,
+   both unit: returns G = 1 - (p.k_s)^2 and writes the new polarisation. */
+double orc_polarisation_reflect(const double p[3], const double ks[3], double out[3]) {
+    double pks = dot(p, ks);
+    double g = sqrt(1.0 - pks * pks);
+    for (int i = 0; i < 3; ++i) out[i] = (p[i] - pks * ks[i]) / g;
+    return 1.0 - pks * pks;
 }
 
 /* Energy a detected photon adds to the energy image (sec. 3): E, or E times
@@ -1095,6 +1123,7 @@ static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic 
                 return -17;
         if ((model && model->kind == ORC_MODEL_MWG) || irc->n_dep > 0) return -17;
     }
+    if (s->user_p && model && model->kind == ORC_MODEL_MWG) return -18;
     if (s->spectrum == ORC_SPEC_TABLE && (s->n_bins < 1 || !s->bin_w)) return -6;
     if (s->spot_kind < ORC_SPOT_POINT || s->spot_kind > ORC_SPOT_DISK) return -16;
     if (s->spot_kind != ORC_SPOT_POINT &&

@@ -62,6 +62,9 @@ typedef struct orc_source {
        sampled field (user origins also replace the spot) */
     const double *user_o, *user_k, *user_e;
     uint64_t user_first;
+    /* user polarisations (sec. 2.1), host, same rows, or NULL: when given,
+       polarisation is tracked through the reflections */
+    const double *user_p;
 } orc_source;
 
 /* Reflecting planes beyond the main set (sec. 2.2.3, closing paragraphs):
@@ -233,6 +236,10 @@ int orc_trace_ids(const orc_source *s, const orc_crystal *c, const orc_mosaic *m
                   const orc_irc *irc, const orc_detector *d,
                   const uint64_t *ids, uint64_t n, uint64_t seed, uint32_t max_events,
                   orc_record *records, double *margins, int n_threads);
+
+/* The polarisation factor G = 1 - (p.k_s)^2 and the polarisation after a
+   reflection into k_s (sec. 2.2.3, 2.2.4). */
+double orc_polarisation_reflect(const double p[3], const double ks[3], double out[3]);
 
 int orc_version(void);
 

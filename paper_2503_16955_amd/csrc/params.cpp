@@ -261,7 +261,8 @@ void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocki
 }
 
 bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve *r) {
-    return r->n_dep > 0 || c->planes || s->spot_kind != MRT_SPOT_POINT || s->origins || s->directions || s->energies;
+    return r->n_dep > 0 || c->planes || s->spot_kind != MRT_SPOT_POINT || s->origins || s->directions ||
+           s->energies || s->polarisations;
 }
 
 void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
@@ -293,6 +294,7 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
     P.user_o = s->origins;
     P.user_k = s->directions;
     P.user_e = s->energies;
+    P.user_p = s->polarisations;
     const double sh = std::sin(s->half_angle / 2.0);
     P.vmax = 2.0 * sh * sh;
     P.spectrum = s->spectrum;

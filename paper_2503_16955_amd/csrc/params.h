@@ -28,7 +28,8 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
                   std::vector<double> &tables);
 
 // True when the run needs the extended-input kernels: an energy-dependent
-// rocking curve, a source spot, user ray arrays or further reflecting planes.
+// rocking curve, a source spot, user ray arrays (polarisations included) or
+// further reflecting planes.
 bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve *r);
 
 // The paper's event model: fill its part of the parameter block (sampler

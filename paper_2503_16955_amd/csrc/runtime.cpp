@@ -138,6 +138,8 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
             return fail(MRT_EINVAL, "the MWG event model takes no energy-dependent rocking curve");
         if (crystal->planes)
             return fail(MRT_EINVAL, "the MWG event model takes no further reflecting planes");
+        if (source->polarisations)
+            return fail(MRT_EINVAL, "the MWG event model takes no polarisations");
         if (!(mosaic->fwhm > 0.0)) return fail(MRT_EINVAL, "the MWG event model needs a mosaic fwhm > 0");
         if (opt.mwg_burn_in < MRT_MWG_NO_BURN_IN) return fail(MRT_EINVAL, "options: mwg_burn_in must be >= -1");
         if (opt.psi_nodes < 0 || opt.psi_nodes > mrt::kMaxPsiNodes)

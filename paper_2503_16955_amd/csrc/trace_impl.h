@@ -66,7 +66,15 @@ template <> __device__ __forceinline__ double uni<double>(uint32_t w) { return d
 template <> __device__ __forceinline__ float uni<float>(uint32_t w) { return dm::u01_f32(w); }
 
 // Per-lane ray state.
-template <class R, bool REC> struct Ray {
+template <class R, bool REC> struct RayEntry {};
+template <class R> struct RayEntry<R, true> {
+    V3<R> entry;     // front-face entry point (records)
+};
+template <class R, bool POL> struct RayPol {};
+template <class R> struct RayPol<R, true> {
+    V3<R> pol;       // unit polarisation vector (sec. 2.1, 2.2.4)
+};
+template <class R, bool REC, bool POL = false> struct Ray : RayEntry<R, REC>, RayPol<R, POL> {
     V3<R> p, k;      // crystal-local position, unit direction
     R dist;          // distance to the crystal boundary along k from p
     double E;        // photon energy, keV
@@ -74,16 +82,6 @@ template <class R, bool REC> struct Ray {
     float saf, caf;  // sin and cos of alpha_B in FP32, for the acceptance filter
     uint64_t id;
     uint32_t nev, nrefl;
-};
-template <class R> struct Ray<R, true> {
-    V3<R> p, k;
-    R dist;
-    double E;
-    double sa;
-    float saf, caf;
-    uint64_t id;
-    uint32_t nev, nrefl;
-    V3<R> entry;
 };
 
 // Wave-uniform counters (scalar registers), flushed with one atomic each.
@@ -123,7 +121,13 @@ template <class R, bool REC> struct QueueEntry {};   // entry points: record ker
 template <class R> struct QueueEntry<R, true> {
     R ex[kQueue], ey[kQueue], ez[kQueue];
 };
-template <class R, bool REC> struct RayQueue : QueueEntry<R, REC> {
+template <class R, bool POL> struct QueuePol {};     // polarisations: extended kernels only
+template <class R> struct QueuePol<R, true> {
+    R qx[kQueue], qy[kQueue], qz[kQueue];
+};
+template <class R, bool REC, bool POL = false>
+struct RayQueue : QueueEntry<R, REC>, QueuePol<R, POL> {
+    using RayT = Ray<R, REC, POL>;
     R px[kQueue], py[kQueue], pz[kQueue], kx[kQueue], ky[kQueue], kz[kQueue], dist[kQueue];
     double E[kQueue], sa[kQueue];
     uint64_t id[kQueue];
@@ -131,7 +135,7 @@ template <class R, bool REC> struct RayQueue : QueueEntry<R, REC> {
     uint32_t nev[kQueue], nrefl[kQueue];
 
     // f(array, field) for every field of a ray
-    template <class F> __device__ __forceinline__ void fields(Ray<R, REC> &r, F f) {
+    template <class F> __device__ __forceinline__ void fields(RayT &r, F f) {
         f(px, r.p.x); f(py, r.p.y); f(pz, r.p.z);
         f(kx, r.k.x); f(ky, r.k.y); f(kz, r.k.z);
         f(dist, r.dist); f(E, r.E); f(sa, r.sa); f(id, r.id); f(saf, r.saf); f(caf, r.caf);
@@ -139,11 +143,14 @@ template <class R, bool REC> struct RayQueue : QueueEntry<R, REC> {
         if constexpr (REC) {
             f(this->ex, r.entry.x); f(this->ey, r.entry.y); f(this->ez, r.entry.z);
         }
+        if constexpr (POL) {
+            f(this->qx, r.pol.x); f(this->qy, r.pol.y); f(this->qz, r.pol.z);
+        }
     }
-    __device__ __forceinline__ void put(uint32_t i, Ray<R, REC> &r) {
+    __device__ __forceinline__ void put(uint32_t i, RayT &r) {
         fields(r, [&](auto *a, auto &v) { a[i] = v; });
     }
-    __device__ __forceinline__ void take(uint32_t i, Ray<R, REC> &r) {
+    __device__ __forceinline__ void take(uint32_t i, RayT &r) {
         fields(r, [&](auto *a, auto &v) { v = a[i]; });
     }
     // After a batch: lanes with `parked` set take back their ray from slot
@@ -152,7 +159,7 @@ template <class R, bool REC> struct RayQueue : QueueEntry<R, REC> {
     // of it.  Only one field of the parked ray is held beside the
     // candidate at a time.
     __device__ __forceinline__ void unpark(uint32_t lane, bool parked, bool queue, uint32_t rank,
-                                           Ray<R, REC> &r) {
+                                           RayT &r) {
         fields(r, [&](auto *a, auto &v) {
             const auto t = a[lane];
             wave_sync();
@@ -169,10 +176,13 @@ constexpr int kAny = -1;
 
 // EXT: the extended inputs (run-time kinds only): a rocking curve whose shift
 // and width depend on the photon energy (tables interpolated per event), a
-// finite source spot, and user-supplied origins, directions or energies.
-template <class R, int GEOM, int MDF, int IRC, bool REC, bool EXT = false>
+// finite source spot, user-supplied origins, directions or energies, and
+// further reflecting planes.  POL: rays carry a polarisation vector, used
+// when the user supplies initial polarisations.
+template <class R, int GEOM, int MDF, int IRC, bool REC, bool EXT = false, bool POL = EXT>
 struct Tracer {
-    using RayT = Ray<R, REC>;
+    using RayT = Ray<R, REC, POL>;
+    using Queue = RayQueue<R, REC, POL>;
     static constexpr bool kF64 = sizeof(R) == 8;
 
     static __device__ __forceinline__ bool is_flat(const TraceParams &P) {
@@ -476,6 +486,14 @@ struct Tracer {
         }
     }
 
+    // Reflection equation of sec. 2.2.4: k - 2 (k.n) n, renormalised.
+    static __device__ __forceinline__ V3<R> reflect_dir(const V3<R> &k, double kn, const V3<R> &n) {
+        const R two_kn = R(2) * (R)kn;
+        const V3<R> ks{k.x - two_kn * n.x, k.y - two_kn * n.y, k.z - two_kn * n.z};
+        const R nr = dm::rsqrt(dot(ks, ks));
+        return V3<R>{ks.x * nr, ks.y * nr, ks.z * nr};
+    }
+
     // ---- one event (sec. 2.2.3, 2.2.4).  Returns the end status, or -1. ----
     static __device__ __forceinline__ int step(const TraceParams &P, const double *lut, RayT &ry,
                                                bool &reflected, bool &refined) {
@@ -519,26 +537,56 @@ struct Tracer {
         int dec;
         bool dep = false;      // the curve depends on the energy (wave-uniform)
         bool planes = false;   // further plane sets or an H-bar ratio (wave-uniform)
+        bool polar = false;    // rays carry polarisations (wave-uniform)
         if constexpr (EXT) {
             dep = P.dep_n > 0;
             planes = P.has_planes != 0;
         }
-        if (planes) {
-            // every plane set j and side (sec. 2.2.3): reflect when
-            // u sum_j a_j max(1, hbar) < h(k.n) sum_j a_j r_j(Delta_j) / R_max,
-            // h = 1 against the normal (H), hbar along it (H-bar); always in FP64
+        // with polarisations the reflected direction is needed before the
+        // decision (G depends on it)
+        V3<R> ksn{};
+        if constexpr (POL) {
+            polar = P.user_p != nullptr;
+            ksn = reflect_dir(ry.k, kn, n);
+        }
+        double pk = 0.0;   // p.k_s
+        if (planes || polar) {
+            // always in FP64; the reflection probability carries the
+            // polarisation factor G = 1 - (p.k_s)^2 (sec. 2.2.3) when
+            // polarisations are tracked
             refined = true;
-            const double a = ::asin(akn);
-            double sum = 0.0;
-            for (int j = 0; j < P.n_planes; ++j) {
-                const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
-                if (sj < 1.0) {
-                    const double x = ((a - ::asin(sj)) - P.plane_shift[j]) / P.plane_scale[j];
-                    sum += P.plane_a[j] * irc_ratio(P, lut, x);
+            double G = 1.0;
+            if constexpr (POL) {
+                if (polar) {
+                    pk = (double)ry.pol.x * (double)ksn.x + (double)ry.pol.y * (double)ksn.y +
+                         (double)ry.pol.z * (double)ksn.z;
+                    G = 1.0 - pk * pk;
                 }
             }
-            const double h = kn < 0.0 ? 1.0 : P.hbar;
-            dec = (double)u_acc * P.plane_tot < h * sum ? 1 : 0;
+            if (planes) {
+                // every plane set j and side (sec. 2.2.3): reflect when
+                // u sum_j a_j max(1, hbar) < G h(k.n) sum_j a_j r_j(Delta_j) / R_max,
+                // h = 1 against the normal (H), hbar along it (H-bar)
+                const double a = ::asin(akn);
+                double sum = 0.0;
+                for (int j = 0; j < P.n_planes; ++j) {
+                    const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
+                    if (sj < 1.0) {
+                        const double x = ((a - ::asin(sj)) - P.plane_shift[j]) / P.plane_scale[j];
+                        sum += P.plane_a[j] * irc_ratio(P, lut, x);
+                    }
+                }
+                const double h = kn < 0.0 ? 1.0 : P.hbar;
+                dec = (double)u_acc * P.plane_tot < G * (h * sum) ? 1 : 0;
+            } else {
+                double shift = P.shift, scale = 1.0;
+                if (dep) {
+                    shift = interp(P.dep, P.dep + P.dep_n, P.dep_n, ry.E);
+                    scale = interp(P.dep, P.dep + 2 * P.dep_n, P.dep_n, ry.E);
+                }
+                const double x = ((::asin(akn) - ::asin(ry.sa)) - shift) / scale;
+                dec = u_acc < G * irc_ratio(P, lut, x) ? 1 : 0;
+            }
         } else if (dep) {
             // Delta_M(E) and the width scale s(E) (sec. 2.2.1): r read at
             // (Delta - Delta_M(E)) / s(E)
@@ -560,11 +608,18 @@ struct Tracer {
             }
         }
         if (dec) {
-            // reflection equation of sec. 2.2.4
-            const R two_kn = R(2) * (R)kn;
-            const V3<R> ks{ry.k.x - two_kn * n.x, ry.k.y - two_kn * n.y, ry.k.z - two_kn * n.z};
-            const R nr = dm::rsqrt(dot(ks, ks));
-            ry.k = V3<R>{ks.x * nr, ks.y * nr, ks.z * nr};
+            if constexpr (POL) {
+                ry.k = ksn;
+                if (polar) {
+                    // polarisation after the reflection (sec. 2.2.4): the
+                    // old one with its component along k_s removed, unit
+                    const R f = (R)pk, g = dm::rsqrt((R)(1.0 - pk * pk));
+                    ry.pol = V3<R>{(ry.pol.x - f * ksn.x) * g, (ry.pol.y - f * ksn.y) * g,
+                                   (ry.pol.z - f * ksn.z) * g};
+                }
+            } else {
+                ry.k = reflect_dir(ry.k, kn, n);
+            }
             ++ry.nrefl;
             ry.dist = exit_distance(P, ry.p, ry.k);
             reflected = true;
@@ -762,6 +817,15 @@ struct Tracer {
         ry.k = k;
         ry.nev = 0;
         ry.nrefl = 0;
+        if constexpr (POL) {
+            if (P.user_p) {
+                const size_t i = (size_t)(ray - P.first);
+                ry.pol = V3<R>{cvt<R>(P.user_p[3 * i]), cvt<R>(P.user_p[3 * i + 1]),
+                               cvt<R>(P.user_p[3 * i + 2])};
+            } else {
+                ry.pol = V3<R>{R(0), R(0), R(0)};
+            }
+        }
         R t;
         const bool hit = entry(P, o, k, t);
         if (!hit) {
@@ -1012,8 +1076,8 @@ __global__ void __launch_bounds__(256) trace_kernel_ext(const TraceParams P) {
     using T = Tracer<R, kAny, kAny, kAny, REC, true>;
     const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
     RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
-    __shared__ RayQueue<R, REC> queues[4];
-    RayQueue<R, REC> &q = queues[uniform(threadIdx.x >> 6)];
+    __shared__ typename T::Queue queues[4];
+    typename T::Queue &q = queues[uniform(threadIdx.x >> 6)];
     trace_loop<T, !T::kF64>(Q, Q.lut, Q.bin_cdf, claim, q);
 }
 

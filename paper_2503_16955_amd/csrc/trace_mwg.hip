@@ -19,11 +19,11 @@ namespace mrt {
 namespace tk {
 
 template <int GEOM, bool REC>
-struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true> {
+struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
     // the base's start() with the extended inputs (source spot, user ray
     // arrays); its event code, which the energy-dependent curve would
-    // change, is not used here
-    using B = Tracer<double, GEOM, kAny, kAny, REC, true>;
+    // change, is not used here, and rays carry no polarisation
+    using B = Tracer<double, GEOM, kAny, kAny, REC, true, false>;
     using RayT = typename B::RayT;
 
     // sin and cos of an angle within a turn, by the table-driven sin/cos of

@@ -51,6 +51,7 @@ struct TraceParams {
     int32_t spot_kind, pad_s;     // finite source spot (MRT_SPOT_*)
     double spot_u[3], spot_v[3], spot_sigma[2];
     const double *user_o, *user_k, *user_e;   // user ray arrays (device) or NULL
+    const double *user_p;         // user polarisations (device) or NULL
 
     // ---- crystal (sec. 2.2)
     int32_t geometry, max_refl;

@@ -42,7 +42,8 @@ class MrtSource(C.Structure):
                 ("background_w", C.c_double), ("n_bins", C.c_int32), ("spot_kind", C.c_int32),
                 ("bin_w", C.POINTER(C.c_double)),
                 ("spot_u", _D3), ("spot_v", _D3), ("spot_sigma", C.c_double * 2),
-                ("origins", C.c_void_p), ("directions", C.c_void_p), ("energies", C.c_void_p)]
+                ("origins", C.c_void_p), ("directions", C.c_void_p), ("energies", C.c_void_p),
+                ("polarisations", C.c_void_p)]
 
 
 class MrtPlanes(C.Structure):
@@ -300,7 +301,8 @@ def _user_rays(rays, n, device):
     the n rays of the call): origins (n, 3), directions (n, 3), energies (n,)."""
     import torch
     ptrs = {}
-    for key, shape in (("origins", (n, 3)), ("directions", (n, 3)), ("energies", (n,))):
+    for key, shape in (("origins", (n, 3)), ("directions", (n, 3)), ("energies", (n,)),
+                       ("polarisations", (n, 3))):
         t = (rays or {}).get(key)
         if t is None:
             ptrs[key] = None
@@ -326,7 +328,8 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
     rays: optional dict of user ray arrays, torch float64 device tensors
     ``origins`` (n, 3; global mm), ``directions`` (n, 3; unit) and
     ``energies`` (n,; keV), row i for ray first + i; each one given replaces
-    the sampled field.  records: None, "all" or "detected".  The event model comes from
+    the sampled field; ``polarisations`` (n, 3; unit, normal to the
+    direction) turns on polarisation tracking.  records: None, "all" or "detected".  The event model comes from
     w["event_model"] (see model_options).  sync=True waits for the stream and
     returns the counters (and the kernel time); sync=False enqueues only.
     Returns a dict with ``counts``, ``energy``, ``records`` (uint8 device

@@ -141,7 +141,7 @@ template <class R, bool REC, bool EXT = false>
 void trace_body(const TraceParams &P, void *queue) {
     using T = Tracer<R, kAny, kAny, kAny, REC, EXT>;
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
-    trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(RayQueue<R, REC> *)queue);
+    trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(typename T::Queue *)queue);
 }
 
 template <bool REC>
@@ -153,7 +153,7 @@ void mwg_body(const TraceParams &P, void *queue) {
 // Room for any RayQueue, filled with a byte pattern so that a read of an
 // entry no lane has written shows up as garbage.
 struct QueueMem {
-    alignas(64) unsigned char b[sizeof(RayQueue<double, true>)];
+    alignas(64) unsigned char b[sizeof(RayQueue<double, true, true>)];
     QueueMem() { memset(b, 0xA5, sizeof b); }
 };
 }  // namespace
@@ -264,7 +264,7 @@ int emu_trace(TraceParams *P, int n_waves, int precision, long long max_meetings
             // the extended-input kernel: energy-dependent rocking curve,
             // source spot, user ray arrays
             if (P->dep_n > 0 || P->spot_kind != MRT_SPOT_POINT || P->user_o || P->user_k || P->user_e ||
-                P->has_planes) {
+                P->user_p || P->has_planes) {
                 if (precision == MRT_FP64) { if (rec) trace_body<double, true, true>(*P, q.b); else trace_body<double, false, true>(*P, q.b); }
                 else { if (rec) trace_body<float, true, true>(*P, q.b); else trace_body<float, false, true>(*P, q.b); }
             } else if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P, q.b); else trace_body<double, false>(*P, q.b); }

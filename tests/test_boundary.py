@@ -42,7 +42,7 @@ def test_version_matches_header():
 
 def test_struct_sizes_match_header():
     # sizes the header's layout implies (x86-64 / amdgcn, natural alignment)
-    assert C.sizeof(mrt.MrtSource) == 408
+    assert C.sizeof(mrt.MrtSource) == 416
     assert C.sizeof(mrt.MrtCrystal) == 232
     assert C.sizeof(mrt.MrtPlanes) == 112
     assert C.sizeof(mrt.MrtMosaic) == 24
@@ -241,7 +241,7 @@ def test_user_ray_arrays_are_checked_by_the_binding():
         with pytest.raises(ValueError):
             mrt._user_rays(rays, 10, torch.device("cuda", 0))
     assert mrt._user_rays(None, 10, torch.device("cpu")) == dict(origins=None, directions=None,
-                                                                 energies=None)
+                                                                 energies=None, polarisations=None)
 
 
 def test_invalid_run_arguments():
