@@ -27,6 +27,7 @@ the kernel's HIP-event duration on its stream, against 256 CUs x 64 lanes x
 sample of the same workload on the host's cores.
 """
 import argparse
+import copy
 import json
 import os
 import sys
@@ -44,12 +45,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_precision(mrt, w, precision, steps, warmup, n, counts, energy, refill=0):
+def run_precision(mrt, w, precision, steps, warmup, n, counts, energy, refill=0, rays=None):
     import torch
     first_base = 1 << 40          # warm-up rays come from a separate id range
     for s in range(warmup):
         mrt.trace(w, n_rays=n, first=first_base + s * n, precision=precision, counts=counts,
-                  energy=energy, refill_idle=refill)
+                  energy=energy, refill_idle=refill, rays=rays)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -58,7 +59,8 @@ def run_precision(mrt, w, precision, steps, warmup, n, counts, energy, refill=0)
     ev0.record(stream)
     for s in range(steps):
         out = mrt.trace(w, n_rays=n, first=s * n, precision=precision, counts=counts,
-                        energy=energy, accumulate=s > 0, stream=stream, refill_idle=refill)
+                        energy=energy, accumulate=s > 0, stream=stream, refill_idle=refill,
+                        rays=rays)
         per_step.append(out["counters"])
         log(f"{precision} step {s}: kernel {out['counters']['kernel_ms']:.2f} ms")
     ev1.record(stream)
@@ -146,6 +148,43 @@ def mwg_model(mrt, op_costs, profiling, w, n, steps, warmup, burn_in, psi_nodes,
                                "cores": threads, "kind": "oracle",
                                "sample": f"ray ids [0, {cpu_rays}) of the same workload in the "
                                          f"paper's model, FP64, images on, {dt:.2f} s"}
+    return out
+
+
+def extended_inputs(mrt, W, op_costs, w, n, steps, warmup, counts, energy, cus, plain):
+    """The extended-input kernels on the benchmark workload: the paper's
+    10 um Gaussian XFEL spot (sec. 4.2); the spot with every ray polarised
+    along the source's b1 (normal to the cone axis; a 2.4 GB device array);
+    the spot with the antiparallel planes at 0.8 and the (004) order at 0.3.
+    `plain` maps precision to the tuned kernel's rays/s."""
+    import torch
+    spot = W.with_spot(w)
+    b1 = torch.as_tensor(w["source"]["b1"], dtype=torch.float64, device="cuda")
+    pol = {"polarisations": b1.expand(n, 3).contiguous()}
+    planes = copy.deepcopy(spot)
+    planes["crystal"]["planes"] = {"hbar_ratio": 0.8,
+                                   "extra": [(w["crystal"]["two_d"] / 2, 0.3, 1.0, 0.0)]}
+    peak = cus * LANES_PER_CU_PER_CLK * PEAK_CLOCK_HZ / 1e12
+    out = {"note": "trace_kernel_ext (every kind read at run time) on the benchmark workload"}
+    for label, wl, rays, priced in (("xfel_spot", spot, None, dict(spot=True)),
+                                    ("xfel_spot_polarised", spot, pol, dict(spot=True, pol=True)),
+                                    ("xfel_spot_planes", planes, None, None)):
+        entry = {}
+        for prec in ("fp64", "fp32_mixed"):
+            ps, gms, _ = run_precision(mrt, wl, prec, steps, warmup, n, counts, energy, rays=rays)
+            v = n * steps / (gms * 1e-3)
+            e = {"value": round(v, 1), "unit": "rays/s", "ms_per_step": round(gms / steps, 4),
+                 "vs_tuned_kernel": round(v / plain[prec], 3) if plain.get(prec) else None,
+                 "refined_per_event": round(sum(c["refined"] for c in ps) / max(1, sum(c["events"] for c in ps)), 5)}
+            if priced is not None:
+                ops = [op_costs.algorithmic_ops_ext(wl, prec, c, **priced) for c in ps]
+                ach = sum(o / (c["kernel_ms"] * 1e-3) for o, c in zip(ops, ps)) / len(ps) / 1e12
+                e["roofline"] = {"bound": "alu", "achieved": round(ach, 4), "peak": round(peak, 4),
+                                 "unit": "TOP/s", "frac": round(ach / peak, 4)}
+            entry[prec] = e
+        out[label] = entry
+        log(f"extended {label}: fp64 {entry['fp64']['value']:.3e} rays/s")
+    del pol
     return out
 
 
@@ -319,6 +358,11 @@ def main():
     ap.add_argument("--mwg-psi-nodes", type=int, default=256)
     ap.add_argument("--mwg-cpu-rays", type=int, default=20_000_000)
     ap.add_argument("--no-mwg", action="store_true")
+    ap.add_argument("--no-extended", action="store_true",
+                    help="skip the extended-input kernels (spot, polarisation, planes)")
+    ap.add_argument("--shard-of", type=int, default=8,
+                    help="also time one GPU's share of the launch split over this many GPUs "
+                         "(0 = skip)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the transport shards by ray-id ranges with one "
@@ -373,6 +417,25 @@ def main():
             "speedup_vs_fp64": round(gpu_ms64 / gms, 3),
             "roofline": roofline(op_costs, profiling, w, "fp32_mixed", pm, info["compute_units"]),
         }
+    if not a.no_extended and not a.no_mixed:
+        res["extended"] = extended_inputs(
+            mrt, W, op_costs, w, n, a.steps, a.warmup, counts, energy, info["compute_units"],
+            {"fp64": value, "fp32_mixed": res["fp32_mixed"]["value"]})
+    if a.shard_of > 1:
+        # one GPU's ray-id range when the launch is split over shard_of GPUs:
+        # the shard kernel at its real shape (the integer image reduce that
+        # would follow is not run on one GPU)
+        ns = -(-n // a.shard_of)
+        sh = {"gpus_modelled": a.shard_of, "rays_per_step": ns,
+              "note": "ray ids [0, n/G) of the same workload on this GPU; no image reduce"}
+        for prec, (c_, e_) in (("fp64", (counts, energy)), ("fp32_mixed", (counts32, energy32))):
+            if prec == "fp32_mixed" and a.no_mixed:
+                continue
+            ps, gms, _ = run_precision(mrt, w, prec, a.steps, a.warmup, ns, c_, e_, a.refill)
+            sh[prec] = {"value": round(ns * a.steps / (gms * 1e-3), 1), "unit": "rays/s",
+                        "ms_per_step": round(gms / a.steps, 4)}
+        res["shard"] = sh
+        log(f"shard 1/{a.shard_of}: fp64 {sh['fp64']['value']:.3e} rays/s")
     if not a.no_mwg:
         res["mwg_model"] = mwg_model(mrt, op_costs, profiling, w, n, a.mwg_steps, 1, a.mwg_burn_in,
                                      a.mwg_psi_nodes, info["compute_units"],

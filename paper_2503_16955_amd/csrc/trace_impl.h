@@ -549,43 +549,55 @@ struct Tracer {
             polar = P.user_p != nullptr;
             ksn = reflect_dir(ry.k, kn, n);
         }
-        double pk = 0.0;   // p.k_s
-        if (planes || polar) {
-            // always in FP64; the reflection probability carries the
-            // polarisation factor G = 1 - (p.k_s)^2 (sec. 2.2.3) when
-            // polarisations are tracked
+        // the polarisation factor G = 1 - (p.k_s)^2 (sec. 2.2.3) multiplies
+        // the reflection probability when polarisations are tracked
+        double pk = 0.0, G = 1.0;
+        if constexpr (POL) {
+            if (polar) {
+                pk = (double)ry.pol.x * (double)ksn.x + (double)ry.pol.y * (double)ksn.y +
+                     (double)ry.pol.z * (double)ksn.z;
+                G = 1.0 - pk * pk;
+            }
+        }
+        if (planes) {
+            // every plane set j and side (sec. 2.2.3), always in FP64: reflect when
+            // u sum_j a_j max(1, hbar) < G h(k.n) sum_j a_j r_j(Delta_j) / R_max,
+            // h = 1 against the normal (H), hbar along it (H-bar)
             refined = true;
-            double G = 1.0;
-            if constexpr (POL) {
-                if (polar) {
-                    pk = (double)ry.pol.x * (double)ksn.x + (double)ry.pol.y * (double)ksn.y +
-                         (double)ry.pol.z * (double)ksn.z;
-                    G = 1.0 - pk * pk;
+            const double a = ::asin(akn);
+            double sum = 0.0;
+            for (int j = 0; j < P.n_planes; ++j) {
+                const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
+                if (sj < 1.0) {
+                    const double x = ((a - ::asin(sj)) - P.plane_shift[j]) / P.plane_scale[j];
+                    sum += P.plane_a[j] * irc_ratio(P, lut, x);
                 }
             }
-            if (planes) {
-                // every plane set j and side (sec. 2.2.3): reflect when
-                // u sum_j a_j max(1, hbar) < G h(k.n) sum_j a_j r_j(Delta_j) / R_max,
-                // h = 1 against the normal (H), hbar along it (H-bar)
-                const double a = ::asin(akn);
-                double sum = 0.0;
-                for (int j = 0; j < P.n_planes; ++j) {
-                    const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
-                    if (sj < 1.0) {
-                        const double x = ((a - ::asin(sj)) - P.plane_shift[j]) / P.plane_scale[j];
-                        sum += P.plane_a[j] * irc_ratio(P, lut, x);
-                    }
-                }
-                const double h = kn < 0.0 ? 1.0 : P.hbar;
-                dec = (double)u_acc * P.plane_tot < G * (h * sum) ? 1 : 0;
+            const double h = kn < 0.0 ? 1.0 : P.hbar;
+            dec = (double)u_acc * P.plane_tot < G * (h * sum) ? 1 : 0;
+        } else if (polar) {
+            // u < G r / R_max is u / G < r / R_max: the FP32 filter decides on
+            // u / G (its 1e-4 relative margins cover the rounding of u / G to
+            // float), G <= 0 never reflects, and a box curve's certain accept
+            // (r = R_max there) becomes u < G
+            double shift = P.shift, scale = 1.0;
+            float shf = P.f32.shift, inv_sf = 1.0f;
+            if (dep) {
+                shift = interp(P.dep, P.dep + P.dep_n, P.dep_n, ry.E);
+                scale = interp(P.dep, P.dep + 2 * P.dep_n, P.dep_n, ry.E);
+                shf = (float)shift;
+                inv_sf = (float)(1.0 / scale);
+            }
+            if (!(G > 0.0)) {
+                dec = 0;
             } else {
-                double shift = P.shift, scale = 1.0;
-                if (dep) {
-                    shift = interp(P.dep, P.dep + P.dep_n, P.dep_n, ry.E);
-                    scale = interp(P.dep, P.dep + 2 * P.dep_n, P.dep_n, ry.E);
+                dec = filter(P, akn, ry.saf, ry.caf, (float)((double)u_acc / G), shf, inv_sf);
+                if (dec == 1 && irc_is(P, MRT_IRC_BOX)) dec = (double)u_acc < G ? 1 : 0;
+                if (dec < 0) {
+                    refined = true;
+                    const double x = ((::asin(akn) - ::asin(ry.sa)) - shift) / scale;
+                    dec = u_acc < G * irc_ratio(P, lut, x) ? 1 : 0;
                 }
-                const double x = ((::asin(akn) - ::asin(ry.sa)) - shift) / scale;
-                dec = u_acc < G * irc_ratio(P, lut, x) ? 1 : 0;
             }
         } else if (dep) {
             // Delta_M(E) and the width scale s(E) (sec. 2.2.1): r read at

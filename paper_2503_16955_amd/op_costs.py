@@ -266,3 +266,30 @@ def algorithmic_ops_mwg(workload, counters, psi_nodes, burn_in):
     entered = c["emitted"] - c["missed"]
     return (c["emitted"] * M["ray"] + entered * M["entered"] + c["events"] * M["event"]
             + c["reflections"] * M["reflection"] + c["detected"] * M["detected"])
+
+
+# ---- the extended source and polarisation (stepping model) -------------------
+
+def algorithmic_ops_ext(workload, precision, counters, spot=False, pol=False):
+    """Issue slots of a stepping-model trace with a source spot and/or
+    polarisations: the plain mix plus, per emitted ray with a spot, the
+    second source draw, the Box-Muller offset (FP64 log, sqrt, sin/cos) and
+    the move in the spot plane; with polarisations, per tilt the reflected
+    direction (needed before the decision), G = 1 - (p.k_s)^2 and u / G, and
+    per reflection the projection and renormalisation of p."""
+    base = algorithmic_ops(workload, precision, counters)
+    D = OP_COSTS["f64"]
+    R = OP_COSTS["f64"] if precision == "fp64" else OP_COSTS["f32"]
+    a = SLOT_WEIGHT["alu64"] if precision == "fp64" else SLOT_WEIGHT["alu32"]
+    d = SLOT_WEIGHT["alu64"]
+    c = counters
+    extra = 0.0
+    if spot:
+        extra += c["emitted"] * (OP_COSTS["philox"] + 4 * d + D["log"] + D["sqrt"] + D["sincos"]
+                                 + 12 * d)
+    if pol:
+        ended = c["absorbed"] + c["exit_reflected"] + c["exit_transmitted"]
+        tilts = max(0, c["events"] - ended)
+        extra += tilts * (10 * a + R["rsqrt"] + 6 * d + D["div"])
+        extra += c["reflections"] * (6 * a + R["rsqrt"])
+    return base + extra

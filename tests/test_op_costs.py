@@ -29,3 +29,22 @@ def test_mix_is_positive_and_monotone():
     a = op_costs.algorithmic_ops(w, "fp64", c)
     c2 = dict(c, events=200)
     assert op_costs.algorithmic_ops(w, "fp64", c2) > a > 0
+
+
+def test_extended_pricing_adds_the_spot_and_polarisation_work():
+    from paper_2503_16955_amd import workloads as W
+    w = W.get("von_hamos_hapg")
+    c = dict(emitted=1000, missed=400, absorbed=50, exit_reflected=20, exit_transmitted=530,
+             truncated=0, detected=15, events=12000, reflections=30, refined=2)
+    for prec in ("fp64", "fp32_mixed"):
+        base = op_costs.algorithmic_ops(w, prec, c)
+        assert op_costs.algorithmic_ops_ext(w, prec, c) == base
+        s = op_costs.algorithmic_ops_ext(w, prec, c, spot=True)
+        p = op_costs.algorithmic_ops_ext(w, prec, c, pol=True)
+        both = op_costs.algorithmic_ops_ext(w, prec, c, spot=True, pol=True)
+        assert base < s and base < p
+        assert both == pytest.approx(s + p - base)
+        # the spot is per emitted ray, polarisation per tilt and reflection
+        c2 = dict(c, events=2 * c["events"])
+        assert op_costs.algorithmic_ops_ext(w, prec, c2, spot=True) - op_costs.algorithmic_ops(w, prec, c2) \
+            == pytest.approx(s - base)

@@ -342,7 +342,8 @@ def _random_polarisations(k, seed):
     return a / np.linalg.norm(a, axis=1)[:, None]
 
 
-@pytest.mark.parametrize("case", ["von_hamos", "flat_planes", "fp32_mixed"])
+@pytest.mark.parametrize("case", ["von_hamos", "flat_planes", "box", "energy_dependent", "table",
+                                  "fp32_mixed"])
 def test_polarisation_loop(emu, case):
     """The extended-input kernel with user polarisations (and, on the flat
     crystal, further planes), under the emulator: in FP64 every ray matches
@@ -353,6 +354,12 @@ def test_polarisation_loop(emu, case):
     if case == "flat_planes":
         w["crystal"]["max_refl"] = 4
         w["crystal"]["planes"] = {"hbar_ratio": 0.7, "extra": [(w["crystal"]["two_d"] / 2, 0.5, 1.0, 0.0)]}
+    elif case == "box":
+        w["rocking_curve"] = dict(kind="box", peak=0.5, shift=0.0, fwhm=80e-6)
+    elif case == "energy_dependent":
+        w["rocking_curve"]["energy_dependence"] = [(7.9, -20e-6, 0.7), (8.05, 5e-6, 1.6)]
+    elif case == "table":
+        w = W.get("flat_stress", precision="fp64")
     n, seed = 5000, 6
     _, k, _ = oracle.source_sample(w, np.arange(n), seed=seed)
     rays = {"polarisations": _random_polarisations(k, 1)}
