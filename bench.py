@@ -168,7 +168,7 @@ def extended_inputs(mrt, W, op_costs, w, n, steps, warmup, counts, energy, cus, 
     out = {"note": "trace_kernel_ext (every kind read at run time) on the benchmark workload"}
     for label, wl, rays, priced in (("xfel_spot", spot, None, dict(spot=True)),
                                     ("xfel_spot_polarised", spot, pol, dict(spot=True, pol=True)),
-                                    ("xfel_spot_planes", planes, None, None)):
+                                    ("xfel_spot_planes", planes, None, dict(spot=True, planes=1))):
         entry = {}
         for prec in ("fp64", "fp32_mixed"):
             ps, gms, _ = run_precision(mrt, wl, prec, steps, warmup, n, counts, energy, rays=rays)

@@ -362,7 +362,11 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
         P.n_planes = 1 + pl->n_extra;
     }
     double sum_a = 0.0;
-    for (int j = 0; j < P.n_planes; ++j) sum_a += P.plane_a[j];
+    for (int j = 0; j < P.n_planes; ++j) {
+        sum_a += P.plane_a[j];
+        P.plane_inv_scale[j] = 1.0 / P.plane_scale[j];
+        P.plane_ratio[j] = c->two_d / P.plane_2d[j];
+    }
     P.plane_tot = sum_a * std::max(1.0, P.hbar);
     // majorant crystallite-encounter rate: every set and side at its peak
     const double lambda_c = rmax * P.plane_tot / c->mfp;

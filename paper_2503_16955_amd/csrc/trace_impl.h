@@ -422,17 +422,17 @@ struct Tracer {
             return h2 * __builtin_amdgcn_rcpf(h2 + a2);
         }
     }
-    // With EXT the curve is read at x / s: the bounds of x are scaled by
-    // 1/s (inv_s, rounded to float) and widened by 2^-20 relative, which
-    // covers the float roundings of inv_s and of the products.
-    static __device__ __forceinline__ int filter(const TraceParams &P, double akn, float saf,
-                                                 float caf, float u_acc, float shift,
-                                                 float inv_s) {
+    // Bounds of x (lo, hi of |x|; slo, shi of x) from the FP32 estimate;
+    // false when there is none.  With EXT the curve is read at x / s: the
+    // bounds are scaled by 1/s (inv_s, rounded to float) and widened by 2^-20
+    // relative, which covers the float roundings of inv_s and of the products.
+    static __device__ __forceinline__ bool x_bounds(double akn, float saf, float caf, float shift,
+                                                    float inv_s, float &lo, float &hi, float &slo,
+                                                    float &shi) {
         const float c = (float)akn;
         const float cw = __builtin_amdgcn_sqrtf(__builtin_fmaf(-c, c, 1.0f));
-        if (!(cw >= 0.1f)) return -1;   // normal within ~6 deg of k: no bound
+        if (!(cw >= 0.1f)) return false;   // normal within ~6 deg of k: no bound
         const float z = __builtin_fmaf(c, caf, -cw * saf);
-        float lo, hi, slo, shi;   // bounds of |x| and of x
         if (__builtin_fabsf(z) <= 0.25f) {
             const float w = z * z;
             float p = 35.0f / 1152.0f;
@@ -464,13 +464,23 @@ struct Tracer {
             slo -= __builtin_fabsf(slo) * 0x1p-20f;
             shi += __builtin_fabsf(shi) * 0x1p-20f;
         }
+        return true;
+    }
+    static __device__ __forceinline__ bool outside_table(const TraceParams &P, float slo, float shi) {
+        // the table curve is zero outside [x_min, x_max]
+        const float x0 = P.f32.lut_x0, x1 = P.f32.lut_x1;
+        return shi < x0 - __builtin_fabsf(x0) * 0x1p-20f - 1e-12f ||
+               slo > x1 + __builtin_fabsf(x1) * 0x1p-20f + 1e-12f;
+    }
+    // The acceptance decision u_acc < r(x) / R_max from the bounds: 1
+    // (accept), 0 (reject) or -1 (the exact FP64 evaluation decides).
+    static __device__ __forceinline__ int filter(const TraceParams &P, double akn, float saf,
+                                                 float caf, float u_acc, float shift,
+                                                 float inv_s) {
+        float lo, hi, slo, shi;
+        if (!x_bounds(akn, saf, caf, shift, inv_s, lo, hi, slo, shi)) return -1;
         if (irc_is(P, MRT_IRC_TABLE)) {
-            // zero outside [x_min, x_max]
-            const float x0 = P.f32.lut_x0, x1 = P.f32.lut_x1;
-            if (shi < x0 - __builtin_fabsf(x0) * 0x1p-20f - 1e-12f ||
-                slo > x1 + __builtin_fabsf(x1) * 0x1p-20f + 1e-12f)
-                return 0;
-            return -1;
+            return outside_table(P, slo, shi) ? 0 : -1;
         } else if (irc_is(P, MRT_IRC_BOX)) {
             const float half = P.f32.box_half;
             if (hi < half * (1.0f - 0x1p-20f)) return 1;
@@ -483,6 +493,26 @@ struct Tracer {
             if (u_acc < r_lo) return 1;
             if (u_acc >= r_hi) return 0;
             return -1;
+        }
+    }
+    // Bounds [r_lo, r_hi] of r(x) / R_max, which lies in [0, 1] ([0, 1]
+    // when there is no bound), for sums of curves.
+    static __device__ __forceinline__ void ratio_bounds(const TraceParams &P, double akn,
+                                                        float saf, float caf, float shift,
+                                                        float inv_s, float &r_lo, float &r_hi) {
+        r_lo = 0.0f;
+        r_hi = 1.0f;
+        float lo, hi, slo, shi;
+        if (!x_bounds(akn, saf, caf, shift, inv_s, lo, hi, slo, shi)) return;
+        if (irc_is(P, MRT_IRC_TABLE)) {
+            if (outside_table(P, slo, shi)) r_hi = 0.0f;
+        } else if (irc_is(P, MRT_IRC_BOX)) {
+            const float half = P.f32.box_half;
+            if (hi < half * (1.0f - 0x1p-20f)) r_lo = 1.0f;
+            else if (lo > half * (1.0f + 0x1p-20f)) r_hi = 0.0f;
+        } else {
+            r_hi = ratio_f32(P, lo) * 1.0001f + 1e-30f;
+            r_lo = hi < INFINITY ? ratio_f32(P, hi) * 0.9999f : 0.0f;
         }
     }
 
@@ -560,21 +590,57 @@ struct Tracer {
             }
         }
         if (planes) {
-            // every plane set j and side (sec. 2.2.3), always in FP64: reflect when
+            // every plane set j and side (sec. 2.2.3): reflect when
             // u sum_j a_j max(1, hbar) < G h(k.n) sum_j a_j r_j(Delta_j) / R_max,
-            // h = 1 against the normal (H), hbar along it (H-bar)
-            refined = true;
-            const double a = ::asin(akn);
-            double sum = 0.0;
-            for (int j = 0; j < P.n_planes; ++j) {
-                const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
-                if (sj < 1.0) {
-                    const double x = ((a - ::asin(sj)) - P.plane_shift[j]) / P.plane_scale[j];
-                    sum += P.plane_a[j] * irc_ratio(P, lut, x);
+            // h = 1 against the normal (H), hbar along it (H-bar).  The FP32
+            // bounds of each r_j / R_max bound the sum; the exact FP64 sum
+            // decides only when u falls between them.
+            const double h = kn < 0.0 ? 1.0 : P.hbar;
+            const double hg = G * h;
+            const double lhs = (double)u_acc * P.plane_tot;
+            if (!(hg > 0.0)) {
+                dec = 0;
+            } else {
+                float s_lo = 0.0f, s_hi = 0.0f;
+                for (int j = 0; j < P.n_planes; ++j) {
+                    // sin(alpha_B,j) = sin(alpha_B) 2d / 2d_j; within 1e-9 of 1
+                    // the set is taken as unbounded, so the bounds never
+                    // disagree with the exact sum about which sets reflect
+                    float rl = 0.0f, rh = 0.0f;
+                    if (j == 0) {
+                        ratio_bounds(P, akn, ry.saf, ry.caf, P.f32.shift, 1.0f, rl, rh);
+                    } else {
+                        const double sj = ry.sa * P.plane_ratio[j];
+                        if (sj < 1.0 - 1e-9) {
+                            const float sf = (float)sj;
+                            ratio_bounds(P, akn, sf, __builtin_amdgcn_sqrtf(__builtin_fmaf(-sf, sf, 1.0f)),
+                                         (float)P.plane_shift[j], (float)P.plane_inv_scale[j], rl, rh);
+                        } else if (sj <= 1.0 + 1e-9) {
+                            rh = 1.0f;
+                        }
+                    }
+                    const float aj = (float)P.plane_a[j];
+                    s_lo += aj * rl;
+                    s_hi += aj * rh;
+                }
+                if (lhs >= hg * ((double)s_hi * (1.0 + 0x1p-20))) {
+                    dec = 0;
+                } else if (lhs < hg * ((double)s_lo * (1.0 - 0x1p-20))) {
+                    dec = 1;
+                } else {
+                    refined = true;
+                    const double a = ::asin(akn);
+                    double sum = 0.0;
+                    for (int j = 0; j < P.n_planes; ++j) {
+                        const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
+                        if (sj < 1.0) {
+                            const double x = ((a - ::asin(sj)) - P.plane_shift[j]) / P.plane_scale[j];
+                            sum += P.plane_a[j] * irc_ratio(P, lut, x);
+                        }
+                    }
+                    dec = lhs < G * (h * sum) ? 1 : 0;
                 }
             }
-            const double h = kn < 0.0 ? 1.0 : P.hbar;
-            dec = (double)u_acc * P.plane_tot < G * (h * sum) ? 1 : 0;
         } else if (polar) {
             // u < G r / R_max is u / G < r / R_max: the FP32 filter decides on
             // u / G (its 1e-4 relative margins cover the rounding of u / G to

@@ -64,7 +64,8 @@ struct TraceParams {
     double two_d;                 // lattice spacing 2d (Angstrom)
     // reflecting planes (extended-input kernels): set 0 is the main set
     int32_t has_planes, n_planes;
-    double plane_2d[4], plane_a[4], plane_scale[4], plane_shift[4];
+    double plane_2d[4], plane_a[4], plane_scale[4], plane_shift[4], plane_inv_scale[4];
+    double plane_ratio[4];        // 2d / 2d_j
     double hbar, plane_tot;       // H-bar / H ratio; sum_j a_j max(1, hbar)
     double origin[3];             // local origin in global coordinates
 

@@ -270,13 +270,17 @@ def algorithmic_ops_mwg(workload, counters, psi_nodes, burn_in):
 
 # ---- the extended source and polarisation (stepping model) -------------------
 
-def algorithmic_ops_ext(workload, precision, counters, spot=False, pol=False):
-    """Issue slots of a stepping-model trace with a source spot and/or
-    polarisations: the plain mix plus, per emitted ray with a spot, the
-    second source draw, the Box-Muller offset (FP64 log, sqrt, sin/cos) and
-    the move in the spot plane; with polarisations, per tilt the reflected
-    direction (needed before the decision), G = 1 - (p.k_s)^2 and u / G, and
-    per reflection the projection and renormalisation of p."""
+def algorithmic_ops_ext(workload, precision, counters, spot=False, pol=False, planes=0):
+    """Issue slots of a stepping-model trace with a source spot,
+    polarisations and/or `planes` further plane sets: the plain mix plus,
+    per emitted ray with a spot, the second source draw, the Box-Muller
+    offset (FP64 log, sqrt, sin/cos) and the move in the spot plane; with
+    polarisations, per tilt the reflected direction (needed before the
+    decision), G = 1 - (p.k_s)^2 and u / G, and per reflection the
+    projection and renormalisation of p; with further sets, per tilt and set
+    its sin(alpha_B) (one FP64 product), cos(alpha_B) (FP32 sqrt) and the
+    FP32 bounds of its curve, and the weighted sums and the FP64 comparison.
+    The counters already hold the events of the summed majorant."""
     base = algorithmic_ops(workload, precision, counters)
     D = OP_COSTS["f64"]
     R = OP_COSTS["f64"] if precision == "fp64" else OP_COSTS["f32"]
@@ -292,4 +296,12 @@ def algorithmic_ops_ext(workload, precision, counters, spot=False, pol=False):
         tilts = max(0, c["events"] - ended)
         extra += tilts * (10 * a + R["rsqrt"] + 6 * d + D["div"])
         extra += c["reflections"] * (6 * a + R["rsqrt"])
+    if planes:
+        ended = c["absorbed"] + c["exit_reflected"] + c["exit_transmitted"]
+        tilts = max(0, c["events"] - ended)
+        F = OP_COSTS["f32"]
+        f = SLOT_WEIGHT["alu32"]
+        irc = workload["rocking_curve"]["kind"]
+        per_set = d + 2 * d + F["sqrt"] + 2 * f + OP_COSTS["filter"][irc] + 4 * f
+        extra += tilts * (planes * per_set + 4 * f + 6 * d)
     return base + extra

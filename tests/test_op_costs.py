@@ -48,3 +48,15 @@ def test_extended_pricing_adds_the_spot_and_polarisation_work():
         c2 = dict(c, events=2 * c["events"])
         assert op_costs.algorithmic_ops_ext(w, prec, c2, spot=True) - op_costs.algorithmic_ops(w, prec, c2) \
             == pytest.approx(s - base)
+
+
+def test_extended_pricing_adds_the_plane_bounds():
+    from paper_2503_16955_amd import workloads as W
+    w = W.get("von_hamos_hapg")
+    c = dict(emitted=1000, missed=400, absorbed=50, exit_reflected=20, exit_transmitted=530,
+             truncated=0, detected=15, events=12000, reflections=30, refined=2)
+    one = op_costs.algorithmic_ops_ext(w, "fp64", c, planes=1)
+    two = op_costs.algorithmic_ops_ext(w, "fp64", c, planes=2)
+    base = op_costs.algorithmic_ops(w, "fp64", c)
+    assert base < one < two
+    assert (two - one) < (one - base)   # the sums and the comparison are paid once
