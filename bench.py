@@ -137,6 +137,23 @@ def mwg_model(mrt, op_costs, profiling, w, n, steps, warmup, burn_in, psi_nodes,
            "vs_stepping": round(rays / (gms * 1e-3) / stepping_value, 4),
            "roofline": roofline_mwg(op_costs, profiling, wm, per, cus, psi_nodes, burn_in),
            "counters_last_step": {k: v for k, v in per[-1].items() if k != "kernel_ms"}}
+    # with every ray polarised along the source's b1 (Eqs.
+    # SimpleReflXsectionPol, ReflXsectionPol), on the same rays
+    import torch
+    b1 = torch.as_tensor(w["source"]["b1"], dtype=torch.float64, device="cuda")
+    pol = {"polarisations": b1.expand(n, 3).contiguous()}
+    pp, pms, _ = run_precision(mrt, wm, "fp64", steps, warmup, n, counts, energy, rays=pol)
+    del pol
+    ops = [op_costs.algorithmic_ops_mwg(wm, c, psi_nodes, burn_in, pol=True) for c in pp]
+    ach = sum(o / (c["kernel_ms"] * 1e-3) for o, c in zip(ops, pp)) / len(pp) / 1e12
+    peak = cus * LANES_PER_CU_PER_CLK * PEAK_CLOCK_HZ / 1e12
+    out["polarised"] = {"value": round(rays / (pms * 1e-3), 1), "unit": "rays/s",
+                        "ms_per_step": round(pms / steps, 4),
+                        "vs_unpolarised": round(gms / pms, 4),
+                        "roofline": {"bound": "alu", "achieved": round(ach, 4),
+                                     "peak": round(peak, 4), "unit": "TOP/s",
+                                     "frac": round(ach / peak, 4)}}
+    log(f"paper's model, polarised: {out['polarised']['value']:.3e} rays/s")
     if cpu_rays:
         import oracle
         threads = min(16, len(os.sched_getaffinity(0)))

@@ -117,6 +117,13 @@ def lib():
         P = C.POINTER
         L.orc_philox4x32.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
         L.orc_philox4x64.argtypes = [P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+        L.orc_polarisation_angle.restype = C.c_double
+        L.orc_polarisation_angle.argtypes = [P(C.c_double), P(C.c_double), P(C.c_double), C.c_double]
+        L.orc_psi_integral_pol.restype = C.c_double
+        L.orc_psi_integral_pol.argtypes = [P(Mosaic), C.c_double, C.c_double, C.c_double, C.c_int]
+        L.orc_mwg_sample_pol.argtypes = [P(Mosaic), P(Irc), C.c_double, C.c_double, C.c_uint64,
+                                         C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_double,
+                                         C.c_double, P(C.c_double), P(C.c_double), P(C.c_double)]
         L.orc_polarisation_reflect.restype = C.c_double
         L.orc_polarisation_reflect.argtypes = [P(C.c_double), P(C.c_double), P(C.c_double)]
         L.orc_bragg_angle.restype = C.c_double
@@ -337,6 +344,34 @@ def philox4x64(ctr, key):
     o = (C.c_uint64 * 4)()
     lib().orc_philox4x64(c, k, o)
     return list(o)
+
+
+def polarisation_angle(p, N, k, alpha):
+    """The angle phi of polarisation p about k for planes of normal N."""
+    return lib().orc_polarisation_angle(_d3(p), _d3(N), _d3(k), float(alpha))
+
+
+def psi_integral_pol(mosaic, alpha, beta, phi, nodes=256):
+    """The psi integral of W G (Eq. SimpleReflXsectionPol)."""
+    return lib().orc_psi_integral_pol(C.byref(_mosaic(mosaic)), float(alpha), float(beta),
+                                      float(phi), int(nodes))
+
+
+def mwg_sample_pol(mosaic, rocking_curve, w_psi, w_delta, seed, rays, event, burn_in, alpha, ab,
+                   phi):
+    """(psi, Delta) drawn by the polarised sampler (polarisation angle phi)
+    for each ray id in `rays`."""
+    m = _mosaic(mosaic)
+    irc, _tab = _irc(rocking_curve)
+    rays = np.atleast_1d(np.asarray(rays, np.uint64))
+    out = np.zeros((len(rays), 2))
+    ps, de = C.c_double(), C.c_double()
+    for i, r in enumerate(rays):
+        lib().orc_mwg_sample_pol(C.byref(m), C.byref(irc), float(w_psi), float(w_delta), int(seed),
+                                 int(r), int(event), int(burn_in), float(alpha), float(ab),
+                                 float(phi), C.byref(ps), C.byref(de), None)
+        out[i] = ps.value, de.value
+    return out
 
 
 def polarisation_reflect(p, ks):

@@ -597,6 +597,47 @@ double orc_psi_integral(const orc_mosaic *m, double alpha, double beta, int M) {
     return 2.0 * sum;
 }
 
+/* The polarisation angle phi of a ray about its direction (sec. 2.2.3):
+   cos(phi) = p.(N x k) / cos(alpha) as the paper defines it, and
+   sin(phi) = p.u with u the unit component of N normal to k,
+   (N + sin(alpha) k) / cos(alpha), so that G(Delta, phi - psi) below equals
+   1 - (p.k_s)^2 for the crystallite at azimuth psi (the paper's first form
+   of G; pinned). */
+double orc_polarisation_angle(const double p[3], const double N[3], const double k[3],
+                              double alpha) {
+    double ca = cos(alpha), sa = sin(alpha), nk[3], u[3];
+    cross(N, k, nk);
+    for (int i = 0; i < 3; ++i) u[i] = (N[i] + sa * k[i]) / ca;
+    return atan2(dot(p, u), dot(p, nk) / ca);
+}
+
+/* G(Delta, phi - psi) = 1 - sin^2(2 b) sin^2(phi - psi), b = alpha_B + Delta:
+   the polarisation factor of a crystallite at azimuth psi (Eq. G_pol). */
+static double g_pol(double b, double phi, double psi) {
+    double s2 = sin(2.0 * b), sp = sin(phi - psi);
+    return 1.0 - s2 * s2 * sp * sp;
+}
+
+/* The psi integral of Eq. SimpleReflXsectionPol, int W(theta(alpha, psi,
+   beta)) G(beta, phi - psi) dpsi over [-pi, pi], by the trapezoid rule on
+   the nodes -psi_M .. -psi_1, 0, psi_1 .. psi_M (psi_j = pi (j / M)^3). */
+double orc_psi_integral_pol(const orc_mosaic *m, double alpha, double beta, double phi, int M) {
+    double sum = 0.0;
+    for (int side = -1; side <= 1; side += 2) {
+        double prev_psi = 0.0;
+        double prev_f = orc_mdf_density(m, theta_v(alpha, beta, 0.0)) * g_pol(beta, phi, 0.0);
+        for (int j = 1; j <= M; ++j) {
+            double t = (double)j / (double)M;
+            double psi = side * ORC_PI * t * t * t;
+            double f = orc_mdf_density(m, theta_v(alpha, beta, psi)) * g_pol(beta, phi, psi);
+            sum += fabs(psi - prev_psi) * (prev_f + f) / 2.0;
+            prev_psi = psi;
+            prev_f = f;
+        }
+    }
+    return sum;
+}
+
 /* int r(x) dx over the whole curve (closed forms; the table by the
    trapezoid rule, exact for its linear interpolation). */
 double orc_irc_integral(const orc_irc *irc) {
@@ -647,11 +688,13 @@ double orc_irc_width(const orc_irc *irc) {
    target of the sampler.  ab = alpha_B; b = alpha_B + Delta is the angle of
    incidence on the crystallite. */
 static double mwg_target(const orc_mosaic *m, const orc_irc *irc, double alpha, double ab,
-                         double psi, double delta) {
+                         double psi, double delta, const double *phi) {
     double r = orc_irc_value(irc, delta - irc->shift);
     if (!(r > 0.0)) return 0.0;
     double b = ab + delta;
-    return r * cos(b) * orc_mdf_density(m, theta_v(alpha, b, psi));
+    double f = r * cos(b) * orc_mdf_density(m, theta_v(alpha, b, psi));
+    /* polarised: the integrand of Eq. ReflXsectionPol */
+    return phi ? f * g_pol(b, *phi, psi) : f;
 }
 
 /* Metropolis-within-Gibbs draw of (psi, Delta) (sec. 2.2.4): from
@@ -664,20 +707,20 @@ static double mwg_target(const orc_mosaic *m, const orc_irc *irc, double alpha, 
    (s, ray, 2^31 + e). */
 static void mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
                        uint64_t seed, uint64_t ray, uint32_t event, int burn_in, int moves_delta,
-                       double alpha, double ab, double *psi_out, double *delta_out,
-                       double *margin) {
+                       double alpha, double ab, const double *phi, double *psi_out,
+                       double *delta_out, double *margin) {
     double lo = -ab, hi = ORC_PI / 2.0 - ab;
     double psi = 0.0, delta = irc->shift;
     if (delta < lo) delta = lo;
     if (delta > hi) delta = hi;
-    double f = mwg_target(m, irc, alpha, ab, psi, delta);
+    double f = mwg_target(m, irc, alpha, ab, psi, delta, phi);
     for (int s = 0; s < burn_in; ++s) {
         double u[4];
         ray_words(seed, ray, 0x80000000u | event, (uint32_t)s, u);
         double pn = psi + w_psi * (2.0 * u[0] - 1.0);
         if (pn >= ORC_PI) pn -= ORC_TWO_PI;
         else if (pn < -ORC_PI) pn += ORC_TWO_PI;
-        double fn = mwg_target(m, irc, alpha, ab, pn, delta);
+        double fn = mwg_target(m, irc, alpha, ab, pn, delta, phi);
         if (margin && f > 0.0 && fn > 0.0) note(margin, (fn - u[1] * f) / fmax(fn, u[1] * f));
         if (u[1] * f < fn || f == 0.0) {
             psi = pn;
@@ -686,7 +729,7 @@ static void mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, do
         if (!moves_delta) continue;
         double dn = delta + w_delta * (2.0 * u[2] - 1.0);
         if (dn >= lo && dn <= hi) {
-            fn = mwg_target(m, irc, alpha, ab, psi, dn);
+            fn = mwg_target(m, irc, alpha, ab, psi, dn, phi);
             if (margin && f > 0.0 && fn > 0.0) note(margin, (fn - u[3] * f) / fmax(fn, u[3] * f));
             if (u[3] * f < fn || f == 0.0) {
                 delta = dn;
@@ -702,7 +745,15 @@ void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, doubl
                     uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
                     double alpha, double ab, double *psi_out, double *delta_out,
                     double *margin) {
-    mwg_sample(m, irc, w_psi, w_delta, seed, ray, event, burn_in, 1, alpha, ab, psi_out,
+    mwg_sample(m, irc, w_psi, w_delta, seed, ray, event, burn_in, 1, alpha, ab, NULL, psi_out,
+               delta_out, margin);
+}
+
+void orc_mwg_sample_pol(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
+                        uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
+                        double alpha, double ab, double phi, double *psi_out, double *delta_out,
+                        double *margin) {
+    mwg_sample(m, irc, w_psi, w_delta, seed, ray, event, burn_in, 1, alpha, ab, &phi, psi_out,
                delta_out, margin);
 }
 
@@ -710,8 +761,8 @@ void orc_mwg_sample_psi(const orc_mosaic *m, const orc_irc *irc, double w_psi,
                         uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
                         double alpha, double ab, double *psi_out, double *delta_out,
                         double *margin) {
-    mwg_sample(m, irc, w_psi, 0.0, seed, ray, event, burn_in, 0, alpha, ab, psi_out, delta_out,
-               margin);
+    mwg_sample(m, irc, w_psi, 0.0, seed, ray, event, burn_in, 0, alpha, ab, NULL, psi_out,
+               delta_out, margin);
 }
 
 /* Crystallite normal for glancing angle alpha on the planes of normal N
@@ -817,7 +868,8 @@ static void ctx_init(trace_ctx *X, const orc_source *s, const orc_crystal *c,
    u1 <= mu0 / mu_eff, otherwise a reflection off the H planes (normal N)
    when u2 sigma < sigma_H, else off the anti-H planes (normal -N). */
 static void mwg_events(const trace_ctx *X, uint64_t ray, double alpha_b, double p[3],
-                       double k[3], uint32_t *n_ev, uint32_t *n_rf, int *status, double *m) {
+                       double k[3], double *pol, uint32_t *n_ev, uint32_t *n_rf, int *status,
+                       double *m) {
     const orc_crystal *c = X->c;
     uint32_t n_events = 0, n_refl = 0;
     double beta = alpha_b + X->irc->shift, cos_beta = cos(beta);
@@ -836,9 +888,18 @@ static void mwg_events(const trace_ctx *X, uint64_t ray, double alpha_b, double 
         if (sn < -1.0) sn = -1.0;
         double alpha = asin(sn);
         double sig_h = 0.0, sig_a = 0.0;
+        /* with polarisation, the angle of p about k seen from either side */
+        double minus_N[3] = {-N[0], -N[1], -N[2]};
+        double phi_h = pol ? orc_polarisation_angle(pol, N, k, alpha) : 0.0;
+        double phi_a = pol ? orc_polarisation_angle(pol, minus_N, k, -alpha) : 0.0;
         if (alpha_b >= 0.0 && (int)n_refl < c->max_refl) {
-            sig_h = X->q * cos_beta * orc_psi_integral(X->m, alpha, beta, X->psi_nodes);
-            sig_a = X->q * cos_beta * orc_psi_integral(X->m, -alpha, beta, X->psi_nodes);
+            if (pol) {
+                sig_h = X->q * cos_beta * orc_psi_integral_pol(X->m, alpha, beta, phi_h, X->psi_nodes);
+                sig_a = X->q * cos_beta * orc_psi_integral_pol(X->m, -alpha, beta, phi_a, X->psi_nodes);
+            } else {
+                sig_h = X->q * cos_beta * orc_psi_integral(X->m, alpha, beta, X->psi_nodes);
+                sig_a = X->q * cos_beta * orc_psi_integral(X->m, -alpha, beta, X->psi_nodes);
+            }
         }
         double mu = c->mu0 + sig_h + sig_a;
         double l = -log(u[0]) / mu;
@@ -859,13 +920,19 @@ static void mwg_events(const trace_ctx *X, uint64_t ray, double alpha_b, double 
         for (int i = 0; i < 3; ++i) Ns[i] = anti ? -N[i] : N[i];
         double as = anti ? -alpha : alpha;
         double psi, delta, n[3], ks[3];
+        double phi_s = anti ? phi_a : phi_h;
         mwg_sample(X->m, X->irc, w_psi, X->w_delta, X->seed, ray, event, X->burn_in, !X->irc_off,
-                   as, alpha_b, &psi, &delta, m);
+                   as, alpha_b, pol ? &phi_s : NULL, &psi, &delta, m);
         orc_crystallite(Ns, k, as, alpha_b + delta, psi, n);
         /* reflection equation of sec. 2.2.4 */
         axpy(k, -2.0 * dot(k, n), n, ks);
         double nr = sqrt(dot(ks, ks));
         for (int i = 0; i < 3; ++i) k[i] = ks[i] / nr;
+        if (pol) {
+            /* the polarisation after the reflection (sec. 2.2.4) */
+            double pks = dot(pol, k), g = sqrt(1.0 - pks * pks);
+            for (int i = 0; i < 3; ++i) pol[i] = (pol[i] - pks * k[i]) / g;
+        }
         ++n_refl;
     }
     *n_ev = n_events;
@@ -906,7 +973,7 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
     int status = ORC_TRUNCATED;
 
     if (X->mwg) {
-        mwg_events(X, ray, alpha_b, p, k, &n_events, &n_refl, &status, &m);
+        mwg_events(X, ray, alpha_b, p, k, polarised ? pol : NULL, &n_events, &n_refl, &status, &m);
         goto finish;
     }
     for (;;) {
@@ -1123,7 +1190,7 @@ static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic 
                 return -17;
         if ((model && model->kind == ORC_MODEL_MWG) || irc->n_dep > 0) return -17;
     }
-    if (s->user_p && model && model->kind == ORC_MODEL_MWG) return -18;
+
     if (s->spectrum == ORC_SPEC_TABLE && (s->n_bins < 1 || !s->bin_w)) return -6;
     if (s->spot_kind < ORC_SPOT_POINT || s->spot_kind > ORC_SPOT_DISK) return -16;
     if (s->spot_kind != ORC_SPOT_POINT &&

@@ -241,6 +241,18 @@ int orc_trace_ids(const orc_source *s, const orc_crystal *c, const orc_mosaic *m
    reflection into k_s (sec. 2.2.3, 2.2.4). */
 double orc_polarisation_reflect(const double p[3], const double ks[3], double out[3]);
 
+/* The paper's model with polarisation (sec. 2.2.3): the angle phi of p
+   about k for planes of normal N at glancing angle alpha, the psi integral
+   of Eq. SimpleReflXsectionPol, and the sampler with target the integrand
+   of Eq. ReflXsectionPol. */
+double orc_polarisation_angle(const double p[3], const double N[3], const double k[3],
+                              double alpha);
+double orc_psi_integral_pol(const orc_mosaic *m, double alpha, double beta, double phi, int M);
+void orc_mwg_sample_pol(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
+                        uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
+                        double alpha, double ab, double phi, double *psi_out, double *delta_out,
+                        double *margin);
+
 int orc_version(void);
 
 #ifdef __cplusplus

@@ -258,6 +258,11 @@ void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocki
         psi.push_back(pj - prev);
         prev = pj;
     }
+    // then cos(2 psi_j), j = 0..M, for the polarised cross-section
+    for (int j = 0; j <= psi_nodes; ++j) {
+        const double t = (double)j / (double)psi_nodes;
+        psi.push_back(std::cos(2.0 * kPi * t * t * t));
+    }
 }
 
 bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve *r) {

@@ -34,7 +34,8 @@ bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve
 
 // The paper's event model: fill its part of the parameter block (sampler
 // sweeps, quadrature intervals, batch, reflection strength, density
-// constants) and append the psi table (2 (psi_nodes + 1) values) to `psi`.
+// constants) and append the psi table to `psi`: (sin(psi_j / 2),
+// psi_j - psi_{j-1}) for j = 0..M, then cos(2 psi_j) for j = 0..M.
 void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_curve *r,
                       int burn_in, int psi_nodes, int batch, bool irc_off, TraceParams &P,
                       std::vector<double> &psi);

@@ -138,8 +138,6 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
             return fail(MRT_EINVAL, "the MWG event model takes no energy-dependent rocking curve");
         if (crystal->planes)
             return fail(MRT_EINVAL, "the MWG event model takes no further reflecting planes");
-        if (source->polarisations)
-            return fail(MRT_EINVAL, "the MWG event model takes no polarisations");
         if (!(mosaic->fwhm > 0.0)) return fail(MRT_EINVAL, "the MWG event model needs a mosaic fwhm > 0");
         if (opt.mwg_burn_in < MRT_MWG_NO_BURN_IN) return fail(MRT_EINVAL, "options: mwg_burn_in must be >= -1");
         if (opt.psi_nodes < 0 || opt.psi_nodes > mrt::kMaxPsiNodes)
@@ -188,6 +186,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
                     ? dtab + (rocking_curve->kind == MRT_IRC_TABLE ? rocking_curve->n_table : 0)
                     : nullptr;
     P.psi_tab = mwg ? dtab + psi_at : nullptr;
+    P.psi_cos2 = mwg ? P.psi_tab + 2 * (P.psi_nodes + 1) : nullptr;
     P.qe = P.qe_n > 0 ? dtab + P.qe_at : nullptr;
     P.dep = P.dep_n > 0 ? dtab + P.dep_at : nullptr;
 
@@ -214,7 +213,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     }
 
     const bool rec = opt.records_mode != MRT_RECORDS_NONE;
-    const void *kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec)
+    const void *kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec, source->polarisations != nullptr)
                          : mrt::uses_ext(source, crystal, rocking_curve)
                              ? mrt::ext_kernel_ptr(opt.precision, rec)
                              : mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,

@@ -18,12 +18,14 @@
 namespace mrt {
 namespace tk {
 
-template <int GEOM, bool REC>
-struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
+template <int GEOM, bool REC, bool POL = false>
+struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
     // the base's start() with the extended inputs (source spot, user ray
     // arrays); its event code, which the energy-dependent curve would
-    // change, is not used here, and rays carry no polarisation
-    using B = Tracer<double, GEOM, kAny, kAny, REC, true, false>;
+    // change, is not used here.  POL: rays carry polarisations (the user's),
+    // and the cross-section and the sampler's target carry the polarisation
+    // factor (Eqs. SimpleReflXsectionPol, ReflXsectionPol).
+    using B = Tracer<double, GEOM, kAny, kAny, REC, true, POL>;
     using RayT = typename B::RayT;
 
     // sin and cos of an angle within a turn, by the table-driven sin/cos of
@@ -76,13 +78,19 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
     // integrand is even); v = 2 sin^2((a - beta)/2) + 2 cos(a) cos(beta)
     // sin^2(psi/2) by Eq. ThetaPsi.  The table holds (sin(psi_j / 2),
     // psi_j - psi_{j-1}) per node; its index is wave-uniform (scalar loads).
-    template <int K>
+    // With polarisation (C2) the same rule also sums W cos(2 psi) on [0, pi]
+    // (i2h, i2a; the table cos(2 psi_j) follows the node table): W is even,
+    // so int W G over [-pi, pi] with G = 1 - S cos^2(phi' - psi) is
+    // (1 - S/2) int W - S cos(2 phi') int_0^pi W cos(2 psi).
+    template <int K, bool C2>
     static __device__ __forceinline__ void psi_pair(const TraceParams &P, double alpha, double beta,
-                                                    double &ih, double &ia) {
+                                                    double &ih, double &ia, double &i2h,
+                                                    double &i2a) {
         const double sh = sin_((alpha - beta) / 2.0), sa = sin_((-alpha - beta) / 2.0);
         const double v0h = 2.0 * sh * sh, v0a = 2.0 * sa * sa;
         const double cc = 2.0 * cos_(alpha) * cos_(beta);
         double fh = density<K>(P, v0h), fa = density<K>(P, v0a), sum_h = 0.0, sum_a = 0.0;
+        double c2p = 1.0, s2h = 0.0, s2a = 0.0;   // cos(2 psi_0) = 1
         const double *tab = P.psi_tab;
         for (int j = 1; j <= P.psi_nodes; ++j) {
             const double b = tab[2 * j], dpsi = tab[2 * j + 1];
@@ -90,22 +98,59 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
             const double gh = density<K>(P, v0h + bb), ga = density<K>(P, v0a + bb);
             sum_h += dpsi * (fh + gh) / 2.0;
             sum_a += dpsi * (fa + ga) / 2.0;
+            if constexpr (C2) {
+                const double c2 = P.psi_cos2[j];
+                s2h += dpsi * (fh * c2p + gh * c2) / 2.0;
+                s2a += dpsi * (fa * c2p + ga * c2) / 2.0;
+                c2p = c2;
+            }
             fh = gh;
             fa = ga;
         }
         ih = 2.0 * sum_h;
         ia = 2.0 * sum_a;
+        i2h = s2h;
+        i2a = s2a;
     }
+    template <bool C2>
     static __device__ __forceinline__ void psi_integrals(const TraceParams &P, double alpha,
-                                                         double beta, double &ih, double &ia) {
+                                                         double beta, double &ih, double &ia,
+                                                         double &i2h, double &i2a) {
         switch (P.mdf) {
-        case MRT_MOSAIC_GAUSSIAN_VMF: psi_pair<MRT_MOSAIC_GAUSSIAN_VMF>(P, alpha, beta, ih, ia); break;
-        case MRT_MOSAIC_LORENTZIAN: psi_pair<MRT_MOSAIC_LORENTZIAN>(P, alpha, beta, ih, ia); break;
-        case MRT_MOSAIC_PSEUDO_VOIGT: psi_pair<MRT_MOSAIC_PSEUDO_VOIGT>(P, alpha, beta, ih, ia); break;
-        case MRT_MOSAIC_WRAPPED_LORENTZIAN:
-            psi_pair<MRT_MOSAIC_WRAPPED_LORENTZIAN>(P, alpha, beta, ih, ia);
+        case MRT_MOSAIC_GAUSSIAN_VMF:
+            psi_pair<MRT_MOSAIC_GAUSSIAN_VMF, C2>(P, alpha, beta, ih, ia, i2h, i2a);
             break;
-        default: psi_pair<MRT_MOSAIC_SPHERICAL_WRAPPED_LORENTZIAN>(P, alpha, beta, ih, ia); break;
+        case MRT_MOSAIC_LORENTZIAN:
+            psi_pair<MRT_MOSAIC_LORENTZIAN, C2>(P, alpha, beta, ih, ia, i2h, i2a);
+            break;
+        case MRT_MOSAIC_PSEUDO_VOIGT:
+            psi_pair<MRT_MOSAIC_PSEUDO_VOIGT, C2>(P, alpha, beta, ih, ia, i2h, i2a);
+            break;
+        case MRT_MOSAIC_WRAPPED_LORENTZIAN:
+            psi_pair<MRT_MOSAIC_WRAPPED_LORENTZIAN, C2>(P, alpha, beta, ih, ia, i2h, i2a);
+            break;
+        default:
+            psi_pair<MRT_MOSAIC_SPHERICAL_WRAPPED_LORENTZIAN, C2>(P, alpha, beta, ih, ia, i2h, i2a);
+            break;
+        }
+    }
+    // The polarisation's direction about k in the frame of planes of normal
+    // N at glancing angle alpha: (c, s) = (p.u, p.(k x u)) normalised, u =
+    // (N + sin(alpha) k) / cos(alpha) the unit component of N normal to k (so
+    // only p's component normal to k counts, as in the paper's angle phi);
+    // the crystallite at azimuth psi has G = 1 - sin^2(2 b) (c cos(psi) +
+    // s sin(psi))^2.
+    static __device__ __forceinline__ void pol_frame(const V3<double> &p, const V3<double> &N,
+                                                     const V3<double> &k, double sa, double ca,
+                                                     double &c, double &s) {
+        const V3<double> u{(N.x + sa * k.x) / ca, (N.y + sa * k.y) / ca, (N.z + sa * k.z) / ca};
+        c = dot(p, u);
+        s = dot(p, cross(k, u));
+        const double r2 = c * c + s * s;
+        if (r2 > 0.0) {
+            const double inv = 1.0 / ::sqrt(r2);
+            c *= inv;
+            s *= inv;
         }
     }
 
@@ -128,8 +173,26 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
         double sig_h = 0.0, sig_a = 0.0;
         if (ry.sa < 1.0 && (int)ry.nrefl < P.max_refl) {
             const double beta = ::asin(ry.sa) + P.shift;
-            double ih, ia;
-            psi_integrals(P, alpha, beta, ih, ia);
+            double ih, ia, i2h, i2a;
+            bool polar = false;
+            if constexpr (POL) polar = P.user_p != nullptr;
+            if (polar) {
+                // Eq. SimpleReflXsectionPol; cos(2 phi') is the same seen
+                // from the H and anti-H planes
+                psi_integrals<true>(P, alpha, beta, ih, ia, i2h, i2a);
+                double c = 0.0, s = 0.0;
+                const double ca = ::sqrt(fma(-sn, sn, 1.0));
+                if constexpr (POL) {
+                    if (ca > 0.0) pol_frame(ry.pol, N, ry.k, sn, ca, c, s);
+                }
+                double s2, c2;
+                sincos_(2.0 * beta, &s2, &c2);
+                const double S = s2 * s2, cos2 = c * c - s * s;
+                ih = (1.0 - S / 2.0) * ih - S * cos2 * i2h;
+                ia = (1.0 - S / 2.0) * ia - S * cos2 * i2a;
+            } else {
+                psi_integrals<false>(P, alpha, beta, ih, ia, i2h, i2a);
+            }
             const double qc = P.q * cos_(beta);
             sig_h = qc * ih;
             sig_a = qc * ia;
@@ -156,21 +219,36 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
     // sampler keeps the factors of the current point: a psi move changes
     // only sin(psi/2), a Delta move only r, cos(b) and sin((alpha - b)/2), so
     // each factor is evaluated once per move, as the full formula would.
+    // With polarisation the target is the integrand of Eq. ReflXsectionPol:
+    // f G, G = 1 - sin^2(2 b) (c cos(psi) + s sin(psi))^2 (pol_frame); the
+    // point then also keeps sin^2(2 b) and cos(psi/2).
     struct Point {
         double r, cb, sab, sp;   // r(Delta - Delta_M), cos(b), sin((alpha - b)/2), sin(psi/2)
+        double s2b, cp;          // polarised: sin^2(2 b), cos(psi/2)
     };
     static __device__ __forceinline__ double value(const TraceParams &P, const Point &x,
-                                                   double ca) {
+                                                   double ca, bool polar, double pc, double ps) {
         if (!(x.r > 0.0)) return 0.0;
         const double v = 2.0 * x.sab * x.sab + 2.0 * ca * x.cb * x.sp * x.sp;
-        return x.r * x.cb * density_any(P, v);
+        const double f = x.r * x.cb * density_any(P, v);
+        if (!polar) return f;
+        // cos(psi) = 1 - 2 sin^2(psi/2), sin(psi) = 2 sin(psi/2) cos(psi/2)
+        const double proj = pc * (1.0 - 2.0 * x.sp * x.sp) + ps * (2.0 * x.sp * x.cp);
+        return f * (1.0 - x.s2b * proj * proj);
     }
     static __device__ __forceinline__ void at_delta(const TraceParams &P, const double *lut,
                                                     double alpha, double ab, double delta,
-                                                    Point &x) {
+                                                    bool polar, Point &x) {
         const double b = ab + delta;
         x.r = B::irc_ratio(P, lut, delta - P.shift);
-        x.cb = cos_(b);
+        if (polar) {
+            double sb;
+            sincos_(b, &sb, &x.cb);
+            const double s2 = 2.0 * sb * x.cb;
+            x.s2b = s2 * s2;
+        } else {
+            x.cb = cos_(b);
+        }
         x.sab = sin_((alpha - b) / 2.0);
     }
 
@@ -195,18 +273,26 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
         double sa, ca;
         sincos_(alpha, &sa, &ca);
         const uint32_t event = ry.nev - 1u;
+        bool polar = false;
+        double pc = 0.0, ps = 0.0;
+        if constexpr (POL) {
+            polar = P.user_p != nullptr;
+            if (polar && ca > 0.0) pol_frame(ry.pol, Ns, ry.k, sa, ca, pc, ps);
+        }
         Point x;
-        at_delta(P, lut, alpha, ab, delta, x);
+        at_delta(P, lut, alpha, ab, delta, polar, x);
         x.sp = 0.0;   // sin(0 / 2)
-        double f = value(P, x, ca);
+        x.cp = 1.0;
+        double f = value(P, x, ca, polar, pc, ps);
         for (int s = 0; s < P.burn_in; ++s) {
             const dm::Words w = dm::philox(P.key0, P.key1, (uint32_t)s, (uint32_t)ry.id,
                                            (uint32_t)(ry.id >> 32), 0x80000000u | event);
             double pn = psi + w_psi * (2.0 * dm::u01_f64(w.w0) - 1.0);
             pn = pn >= kPi ? pn - 2.0 * kPi : (pn < -kPi ? pn + 2.0 * kPi : pn);
             Point y = x;
-            y.sp = sin_(pn / 2.0);
-            double fn = value(P, y, ca);
+            if (polar) sincos_(pn / 2.0, &y.sp, &y.cp);
+            else y.sp = sin_(pn / 2.0);
+            double fn = value(P, y, ca, polar, pc, ps);
             if (dm::u01_f64(w.w1) * f < fn || f == 0.0) {
                 psi = pn;
                 x = y;
@@ -215,8 +301,8 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
             const double dn = delta + P.w_delta * (2.0 * dm::u01_f64(w.w2) - 1.0);
             if (!P.irc_off && dn >= lo && dn <= hi) {   // the IRC disabled: Delta stays
                 y = x;
-                at_delta(P, lut, alpha, ab, dn, y);
-                fn = value(P, y, ca);
+                at_delta(P, lut, alpha, ab, dn, polar, y);
+                fn = value(P, y, ca, polar, pc, ps);
                 if (dm::u01_f64(w.w3) * f < fn || f == 0.0) {
                     delta = dn;
                     x = y;
@@ -245,6 +331,14 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, false> {
         const V3<double> ks{k.x - two_kn * n.x, k.y - two_kn * n.y, k.z - two_kn * n.z};
         const double nr = ::sqrt(dot(ks, ks));
         ry.k = V3<double>{ks.x / nr, ks.y / nr, ks.z / nr};
+        if constexpr (POL) {
+            if (polar) {
+                // the polarisation after the reflection (sec. 2.2.4)
+                const double pks = dot(ry.pol, ry.k), g = ::sqrt(1.0 - pks * pks);
+                ry.pol = V3<double>{(ry.pol.x - pks * ry.k.x) / g, (ry.pol.y - pks * ry.k.y) / g,
+                                    (ry.pol.z - pks * ry.k.z) / g};
+            }
+        }
         ++ry.nrefl;
     }
 
@@ -360,25 +454,29 @@ __device__ __forceinline__ void mwg_loop(const TraceParams &P, const double *lut
     flush(P, cnt);
 }
 
-template <int GEOM, bool REC>
+template <int GEOM, bool REC, bool POL>
 __global__ void __launch_bounds__(256) mwg_kernel(const TraceParams P) {
-    using T = MwgTracer<GEOM, REC>;
+    using T = MwgTracer<GEOM, REC, POL>;
     const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
     RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
-    __shared__ RayQueue<double, REC> queues[4];   // one per wave
-    RayQueue<double, REC> &q = queues[uniform(threadIdx.x >> 6)];
+    __shared__ typename T::Queue queues[4];   // one per wave
+    typename T::Queue &q = queues[uniform(threadIdx.x >> 6)];
     mwg_loop<T>(Q, Q.lut, Q.bin_cdf, claim, q);
+}
+
+template <int GEOM, bool POL> const void *mwg_kernel_of(bool records) {
+    return records ? (const void *)mwg_kernel<GEOM, true, POL> : (const void *)mwg_kernel<GEOM, false, POL>;
 }
 
 }  // namespace tk
 
-const void *mwg_kernel_ptr(int geometry, bool records) {
+const void *mwg_kernel_ptr(int geometry, bool records, bool polarised) {
     if (geometry == MRT_GEOMETRY_FLAT)
-        return records ? (const void *)tk::mwg_kernel<MRT_GEOMETRY_FLAT, true>
-                       : (const void *)tk::mwg_kernel<MRT_GEOMETRY_FLAT, false>;
+        return polarised ? tk::mwg_kernel_of<MRT_GEOMETRY_FLAT, true>(records)
+                         : tk::mwg_kernel_of<MRT_GEOMETRY_FLAT, false>(records);
     if (geometry == MRT_GEOMETRY_CYLINDER)
-        return records ? (const void *)tk::mwg_kernel<MRT_GEOMETRY_CYLINDER, true>
-                       : (const void *)tk::mwg_kernel<MRT_GEOMETRY_CYLINDER, false>;
+        return polarised ? tk::mwg_kernel_of<MRT_GEOMETRY_CYLINDER, true>(records)
+                         : tk::mwg_kernel_of<MRT_GEOMETRY_CYLINDER, false>(records);
     return nullptr;
 }
 

@@ -100,6 +100,7 @@ struct TraceParams {
     double wl_g2, wl_norm;        // (Gamma/2)^2 and 1 / (pi ln((g^2 + 4) / g^2))
     double swl_a, swl_norm;       // 2 sinh^2(Gamma/4) and A (A + 2) / (4 pi)
     const double *psi_tab;        // (sin(psi_j / 2), psi_j - psi_{j-1}), j = 0..M (device)
+    const double *psi_cos2;       // cos(2 psi_j), j = 0..M (device; after psi_tab)
 
     // ---- detector (sec. 2.3), local coordinates
     double dP[3], dn[3], du[3], dv[3];
@@ -157,7 +158,7 @@ constexpr int kMaxQeNodes = 1024;
 const void *serve_kernel_ptr(int precision);
 // Kernel of the paper's event model (FP64) for a geometry (nullptr for an
 // unknown one): (TraceParams), like the trace kernels.
-const void *mwg_kernel_ptr(int geometry, bool records);
+const void *mwg_kernel_ptr(int geometry, bool records, bool polarised);
 // Kernel for the extended inputs: an energy-dependent rocking curve, a
 // finite source spot, user ray arrays (every kind read at run time).
 const void *ext_kernel_ptr(int precision, bool records);

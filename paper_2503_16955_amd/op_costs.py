@@ -222,7 +222,7 @@ def _irc_cost(irc):
             "lorentzian": D["div"] + 3 * a, "box": 2 * a, "table": 15 * a}[irc]
 
 
-def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in):
+def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False):
     """Operation mix per unit of the paper's event model, in issue slots.
 
     Units: 'ray' and 'entered' as in mix() (FP64); 'event' (one free path:
@@ -250,18 +250,31 @@ def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in):
     orient = 2 * sc + 3 * D["div"] + 15 * a + 9 * a + 5 * a + 15 * a + 11 * a + D["sqrt"] + 3 * D["div"]
     reflection = (D["asin"] + sc + D["div"] + sc + R + 2 * sc + 3 * a + W + burn_in * sweep
                   + orient)
+    if pol:
+        # Eq. SimpleReflXsectionPol: the sum of W cos(2 psi) beside the plain
+        # one on every node (a table load, a product and an FMA per side), the
+        # polarisation's frame (u, k x u, two dots, their normalisation) and
+        # sin^2(2 beta) per event; Eq. ReflXsectionPol: the frame once per
+        # reflection and, per sweep, G in both target evaluations and
+        # sin^2(2 b) in the Delta move; the polarisation's update after the
+        # reflection
+        frame_p = 6 * D["div"] + 30 * a + D["sqrt"] + D["div"] + 4 * a
+        event += psi_nodes * 4 * a + frame_p + sc + 8 * a
+        sweep_extra = 2 * 6 * a + 3 * a
+        sweep += sweep_extra
+        reflection += frame_p + burn_in * sweep_extra + 14 * a + D["sqrt"] + 3 * D["div"]
     return {"ray": base["ray"], "entered": base["entered"], "event": event,
             "reflection": reflection, "detected": base["detected"], "sweep": sweep,
             "quadrature": quad}
 
 
-def algorithmic_ops_mwg(workload, counters, psi_nodes, burn_in):
+def algorithmic_ops_mwg(workload, counters, psi_nodes, burn_in, pol=False):
     """Issue slots the paper's model needs for a trace with these counters
     (every event priced with the quadrature; events past a ray's reflection
-    cap skip it, which over-prices them slightly)."""
+    cap skip it, which over-prices them slightly); `pol`: with polarisation."""
     m = workload["mosaic"]
     M = mix_mwg(workload["crystal"]["geometry"], m["kind"], workload["rocking_curve"]["kind"],
-                workload["source"]["spectrum"], psi_nodes, burn_in)
+                workload["source"]["spectrum"], psi_nodes, burn_in, pol)
     c = counters
     entered = c["emitted"] - c["missed"]
     return (c["emitted"] * M["ray"] + entered * M["entered"] + c["events"] * M["event"]

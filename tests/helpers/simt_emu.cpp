@@ -144,10 +144,11 @@ void trace_body(const TraceParams &P, void *queue) {
     trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(typename T::Queue *)queue);
 }
 
-template <bool REC>
+template <bool REC, bool POL>
 void mwg_body(const TraceParams &P, void *queue) {
+    using T = MwgTracer<kAny, REC, POL>;
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
-    mwg_loop<MwgTracer<kAny, REC>>(P, P.lut, P.bin_cdf, claim, *(RayQueue<double, REC> *)queue);
+    mwg_loop<T>(P, P.lut, P.bin_cdf, claim, *(typename T::Queue *)queue);
 }
 
 // Room for any RayQueue, filled with a byte pattern so that a read of an
@@ -190,6 +191,7 @@ int emu_build_mwg(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_c
     if (n_used + (int)t.size() > tables_cap) return -2;
     for (size_t i = 0; i < t.size(); ++i) tables_out[n_used + i] = t[i];
     P->psi_tab = tables_out + n_used;
+    P->psi_cos2 = P->psi_tab + 2 * (psi_nodes + 1);
     return 0;
 }
 
@@ -198,8 +200,9 @@ int emu_trace_mwg(TraceParams *P, int n_waves, long long max_meetings) {
     for (int w = 0; w < n_waves; ++w) {
         QueueMem q;
         int e = run_wave([&] {
-            if (P->records_mode != MRT_RECORDS_NONE) mwg_body<true>(*P, q.b);
-            else mwg_body<false>(*P, q.b);
+            const bool rec = P->records_mode != MRT_RECORDS_NONE;
+            if (P->user_p) { if (rec) mwg_body<true, true>(*P, q.b); else mwg_body<false, true>(*P, q.b); }
+            else { if (rec) mwg_body<true, false>(*P, q.b); else mwg_body<false, false>(*P, q.b); }
         }, max_meetings);
         if (e) return e;
     }

@@ -4,7 +4,9 @@ von Hamos, the flat crystal with further planes, and the tabulated curve;
 ragged launches past 2^32; sampled at the full 1e8-ray von Hamos size; with
 no mosaic spread sigma polarisations give the unpolarised kernel's records
 bit for bit; FP32-mixed agrees with FP64 statistically; the paper's event
-model and the request server refuse polarisations."""
+model with polarisation (Eqs. SimpleReflXsectionPol, ReflXsectionPol) in
+parity on both geometries and two more mosaics, and sampled at 1e8 rays;
+the request server refuses the extended inputs."""
 import copy
 
 import numpy as np
@@ -98,15 +100,64 @@ def test_polarisation_fp32_mixed_agrees_with_fp64():
         assert abs(a[f] - b[f]) < 5 * np.sqrt(a[f] + b[f]) + 1e-3 * b[f], (f, a[f], b[f])
 
 
-def test_polarisation_refused_by_the_papers_model_and_the_server():
+def test_polarisation_refused_by_the_server():
     import torch
-    w = W.get("von_hamos_hapg")
-    p = torch.zeros((1000, 3), dtype=torch.float64, device="cuda")
-    p[:, 0] = 1.0
-    m = copy.deepcopy(w)
-    m["event_model"] = {"kind": "mwg"}
-    with pytest.raises(mrt.MosaicRTError):
-        mrt.trace(m, n_rays=1000, rays={"polarisations": p})
+    with mrt.Server(hbm_budget_bytes=1 << 28, max_slots=2) as srv:
+        w = W.get("von_hamos_hapg")
+        w["source"]["spot"] = dict(kind="disk", u=[1.0, 0.0, 0.0], v=[0.0, 0.97294474, 0.23103794],
+                                   sigma=[0.01, 0.0])
+        with pytest.raises(mrt.MosaicRTError):
+            srv.submit(w, n_rays=1000)
+
+
+def _mwg(w, burn_in=200):
+    w = copy.deepcopy(w)
+    w["event_model"] = {"kind": "mwg", "burn_in": burn_in, "psi_nodes": 256}
+    return w
+
+
+@pytest.mark.parametrize("name,n", [("von_hamos_hapg", 200_000), ("flat_hopg", 100_000)])
+def test_polarisation_in_the_papers_model_parity(name, n):
+    w = _mwg(W.get(name))
+    g, o = assert_parity(w, n, rays={"polarisations": _random_pol(w, n, 5)})
+    assert o["counters"]["reflections"] > 500
+
+
+@pytest.mark.parametrize("mosaic", [dict(kind="wrapped_lorentzian", fwhm=0.2 * W.DEG, eta=0.0),
+                                    dict(kind="lorentzian", fwhm=0.3 * W.DEG, eta=0.0)],
+                         ids=["wrapped_lorentzian", "lorentzian"])
+def test_polarisation_in_the_papers_model_mosaics(mosaic):
+    w = W.get("flat_hopg")
+    w["mosaic"] = mosaic
+    w["crystal"]["max_refl"] = 4
+    w = _mwg(w, burn_in=100)
+    n = 50_000
+    g, o = assert_parity(w, n, first=9, rays={"polarisations": _random_pol(w, n, 6, 9)})
+    assert o["counters"]["reflections"] > 200
+
+
+def test_polarisation_in_the_papers_model_full_size_sampled():
+    """1e8 von Hamos rays in the paper's model with device-generated random
+    polarisations: 1024 sampled rays against the oracle."""
+    import torch
+    w = _mwg(W.get("von_hamos_hapg"), burn_in=500)
+    n = w["n_rays"]
+    gen = torch.Generator(device="cuda").manual_seed(32)
+    p = torch.randn((n, 3), generator=gen, device="cuda", dtype=torch.float64)
+    p = (p / torch.linalg.norm(p, dim=1, keepdim=True)).contiguous()
+    print("[pol-mwg-full] records launch", flush=True)
+    g = mrt.trace(w, records="all", rays={"polarisations": p})
+    ids = np.unique(np.random.default_rng(16).integers(0, n, 1024, dtype=np.int64))
+    sel = torch.as_tensor(ids, device="cuda")
+    grec = mrt.records_to_numpy(g["records"].index_select(0, sel))
+    ph = p.index_select(0, sel).cpu().numpy()
+    parts = [oracle.trace_ids(w, [int(i)], rays={"polarisations": ph[j:j + 1]}, first=int(i), n_rows=1)
+             for j, i in enumerate(ids)]
+    orec = np.concatenate([q[0] for q in parts])
+    mg = np.concatenate([q[1] for q in parts])
+    n_ties, bad, _ = parity.compare(grec, orec, mg)
+    assert len(bad) == 0, parity.describe(grec, orec, mg, bad)
+    assert n_ties == 0
 
 
 def test_polarisation_full_size_sampled():

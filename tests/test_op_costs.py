@@ -60,3 +60,11 @@ def test_extended_pricing_adds_the_plane_bounds():
     base = op_costs.algorithmic_ops(w, "fp64", c)
     assert base < one < two
     assert (two - one) < (one - base)   # the sums and the comparison are paid once
+
+
+def test_polarised_model_pricing_adds_work_per_event_and_sweep():
+    a = op_costs.mix_mwg("cylinder", "pseudo_voigt", "pseudo_voigt", "lines", 256, 500)
+    b = op_costs.mix_mwg("cylinder", "pseudo_voigt", "pseudo_voigt", "lines", 256, 500, pol=True)
+    assert b["event"] > a["event"] and b["sweep"] > a["sweep"]
+    assert b["reflection"] - a["reflection"] > 500 * (b["sweep"] - a["sweep"])
+    assert b["ray"] == a["ray"] and b["detected"] == a["detected"]

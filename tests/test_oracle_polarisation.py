@@ -121,11 +121,3 @@ def test_random_polarisations_match_the_unpolarised_factor():
     assert abs(pol - unp) < 4 * math.sqrt(pol + unp), (pol, unp)
     plain = oracle.trace(w, n=n)["counters"]["reflections"]
     assert plain - pol > 4 * math.sqrt(pol + plain)
-
-
-def test_polarisations_rejected_by_the_papers_model():
-    w = W.get("flat_hopg")
-    w["event_model"] = {"kind": "mwg"}
-    p = np.tile([1.0, 0.0, 0.0], (10, 1))
-    with pytest.raises(ValueError):
-        oracle.trace(w, n=10, rays={"polarisations": p})

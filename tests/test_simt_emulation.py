@@ -263,7 +263,8 @@ def _user_rays(w, n, seed):
 
 
 @pytest.mark.parametrize("case", ["gaussian_spot", "disk_spot", "user_rays", "user_energies",
-                                  "mwg_spot", "mwg_user_rays"])
+                                  "mwg_spot", "mwg_user_rays", "mwg_polarised",
+                                  "mwg_polarised_oblique"])
 def test_source_spot_and_user_ray_loops(emu, case):
     """The extended-input kernels (FP64) run under the emulator with a source
     spot or user ray arrays: every ray matches the oracle's record; the
@@ -281,6 +282,13 @@ def test_source_spot_and_user_ray_loops(emu, case):
         w["source"]["spot"] = dict(kind="disk", u=[0.0, 1.0, 0.0], v=[0.0, 0.0, 1.0], sigma=[0.04])
     elif case == "user_energies":
         rays = {"energies": _user_rays(w, n, seed)["energies"]}
+    elif case == "mwg_polarised":
+        _, k, _ = oracle.source_sample(w, np.arange(n), seed=seed)
+        rays = {"polarisations": _random_polarisations(k, 2)}
+    elif case == "mwg_polarised_oblique":
+        # unit vectors with a component along k: only the normal part counts
+        a = np.random.default_rng(3).normal(size=(n, 3))
+        rays = {"polarisations": a / np.linalg.norm(a, axis=1)[:, None]}
     else:
         rays = _user_rays(w, n, seed)
     mwg = case.startswith("mwg")
