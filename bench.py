@@ -20,6 +20,11 @@ at mu0 + gamma0 sigma(alpha) with sigma from the psi quadrature of Eq.
 SimpleReflXsection, reflecting crystallites from Metropolis-within-Gibbs with
 500 sweeps), FP64, with its own roofline and oracle rate ("mwg_model").
 
+Each timed region enqueues its K traces back to back on one stream (the
+host does not wait between them); the same rays are then traced again with
+counters, whose unit counts and per-kernel HIP-event durations give the
+rooflines.
+
 Printed: one JSON line with rays/s (FP64 is `value`), events/s, the ALU
 roofline of the trace kernel (algorithmic VALU lane-operations per launch over
 the kernel's HIP-event duration on its stream, against 256 CUs x 64 lanes x
@@ -46,6 +51,10 @@ def log(msg):
 
 
 def run_precision(mrt, w, precision, steps, warmup, n, counts, energy, refill=0, rays=None):
+    """Warm up, then time `steps` traces of n rays enqueued back to back on
+    one stream (no host wait between them), then trace the same rays again
+    with counters (unit counts and each kernel's own duration, for the
+    roofline).  Returns (per-step counters, timed GPU ms, timed wall s)."""
     import torch
     first_base = 1 << 40          # warm-up rays come from a separate id range
     for s in range(warmup):
@@ -54,19 +63,22 @@ def run_precision(mrt, w, precision, steps, warmup, n, counts, energy, refill=0,
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    per_step = []
     t0 = time.perf_counter()
     ev0.record(stream)
+    for s in range(steps):
+        mrt.trace(w, n_rays=n, first=s * n, precision=precision, counts=counts, energy=energy,
+                  accumulate=s > 0, stream=stream, refill_idle=refill, rays=rays, sync=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    per_step = []
     for s in range(steps):
         out = mrt.trace(w, n_rays=n, first=s * n, precision=precision, counts=counts,
                         energy=energy, accumulate=s > 0, stream=stream, refill_idle=refill,
                         rays=rays)
         per_step.append(out["counters"])
         log(f"{precision} step {s}: kernel {out['counters']['kernel_ms']:.2f} ms")
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
     return per_step, gpu_ms, wall
 
 
@@ -100,9 +112,10 @@ def roofline(op_costs, profiling, w, precision, per_step, cus):
             "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
 
 
-def mwg_kernel_name(w, records=False):
+def mwg_kernel_name(w, records=False, polarised=False):
     g = KIND["geometry"][w["crystal"]["geometry"]]
-    return f"void mrt::tk::mwg_kernel<{g}, {'true' if records else 'false'}>(mrt::TraceParams)"
+    b = lambda x: "true" if x else "false"
+    return f"void mrt::tk::mwg_kernel<{g}, {b(records)}, {b(polarised)}>(mrt::TraceParams)"
 
 
 def roofline_mwg(op_costs, profiling, w, per_step, cus, psi_nodes, burn_in):
@@ -152,7 +165,10 @@ def mwg_model(mrt, op_costs, profiling, w, n, steps, warmup, burn_in, psi_nodes,
                         "vs_unpolarised": round(gms / pms, 4),
                         "roofline": {"bound": "alu", "achieved": round(ach, 4),
                                      "peak": round(peak, 4), "unit": "TOP/s",
-                                     "frac": round(ach / peak, 4)}}
+                                     "frac": round(ach / peak, 4),
+                                     "traffic": profiling.traffic_per_launch(
+                                         mwg_kernel_name(wm, polarised=True)),
+                                     "kernel": mwg_kernel_name(wm, polarised=True)}}
     log(f"paper's model, polarised: {out['polarised']['value']:.3e} rays/s")
     if cpu_rays:
         import oracle
