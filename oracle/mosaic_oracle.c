@@ -687,9 +687,10 @@ double orc_irc_width(const orc_irc *irc) {
 /* Integrand of Eq. ReflXsection in (psi, Delta) up to a constant: the
    target of the sampler.  ab = alpha_B; b = alpha_B + Delta is the angle of
    incidence on the crystallite. */
-static double mwg_target(const orc_mosaic *m, const orc_irc *irc, double alpha, double ab,
-                         double psi, double delta, const double *phi) {
-    double r = orc_irc_value(irc, delta - irc->shift);
+static double mwg_target(const orc_mosaic *m, const orc_irc *irc, double shift, double scale,
+                         double alpha, double ab, double psi, double delta, const double *phi) {
+    /* a further plane set reads the curve at (Delta - its shift) / its scale */
+    double r = orc_irc_value(irc, scale == 1.0 ? delta - shift : (delta - shift) / scale);
     if (!(r > 0.0)) return 0.0;
     double b = ab + delta;
     double f = r * cos(b) * orc_mdf_density(m, theta_v(alpha, b, psi));
@@ -705,22 +706,22 @@ static double mwg_target(const orc_mosaic *m, const orc_irc *irc, double alpha, 
    density; Delta outside [-alpha_B, pi/2 - alpha_B] is rejected; psi wraps
    on [-pi, pi).  Sweep s of event e uses the Philox words of counter
    (s, ray, 2^31 + e). */
-static void mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
-                       uint64_t seed, uint64_t ray, uint32_t event, int burn_in, int moves_delta,
-                       double alpha, double ab, const double *phi, double *psi_out,
-                       double *delta_out, double *margin) {
+static void mwg_sample(const orc_mosaic *m, const orc_irc *irc, double shift, double scale,
+                       double w_psi, double w_delta, uint64_t seed, uint64_t ray, uint32_t event,
+                       int burn_in, int moves_delta, double alpha, double ab, const double *phi,
+                       double *psi_out, double *delta_out, double *margin) {
     double lo = -ab, hi = ORC_PI / 2.0 - ab;
-    double psi = 0.0, delta = irc->shift;
+    double psi = 0.0, delta = shift;
     if (delta < lo) delta = lo;
     if (delta > hi) delta = hi;
-    double f = mwg_target(m, irc, alpha, ab, psi, delta, phi);
+    double f = mwg_target(m, irc, shift, scale, alpha, ab, psi, delta, phi);
     for (int s = 0; s < burn_in; ++s) {
         double u[4];
         ray_words(seed, ray, 0x80000000u | event, (uint32_t)s, u);
         double pn = psi + w_psi * (2.0 * u[0] - 1.0);
         if (pn >= ORC_PI) pn -= ORC_TWO_PI;
         else if (pn < -ORC_PI) pn += ORC_TWO_PI;
-        double fn = mwg_target(m, irc, alpha, ab, pn, delta, phi);
+        double fn = mwg_target(m, irc, shift, scale, alpha, ab, pn, delta, phi);
         if (margin && f > 0.0 && fn > 0.0) note(margin, (fn - u[1] * f) / fmax(fn, u[1] * f));
         if (u[1] * f < fn || f == 0.0) {
             psi = pn;
@@ -729,7 +730,7 @@ static void mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, do
         if (!moves_delta) continue;
         double dn = delta + w_delta * (2.0 * u[2] - 1.0);
         if (dn >= lo && dn <= hi) {
-            fn = mwg_target(m, irc, alpha, ab, psi, dn, phi);
+            fn = mwg_target(m, irc, shift, scale, alpha, ab, psi, dn, phi);
             if (margin && f > 0.0 && fn > 0.0) note(margin, (fn - u[3] * f) / fmax(fn, u[3] * f));
             if (u[3] * f < fn || f == 0.0) {
                 delta = dn;
@@ -745,24 +746,24 @@ void orc_mwg_sample(const orc_mosaic *m, const orc_irc *irc, double w_psi, doubl
                     uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
                     double alpha, double ab, double *psi_out, double *delta_out,
                     double *margin) {
-    mwg_sample(m, irc, w_psi, w_delta, seed, ray, event, burn_in, 1, alpha, ab, NULL, psi_out,
-               delta_out, margin);
+    mwg_sample(m, irc, irc->shift, 1.0, w_psi, w_delta, seed, ray, event, burn_in, 1, alpha, ab,
+               NULL, psi_out, delta_out, margin);
 }
 
 void orc_mwg_sample_pol(const orc_mosaic *m, const orc_irc *irc, double w_psi, double w_delta,
                         uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
                         double alpha, double ab, double phi, double *psi_out, double *delta_out,
                         double *margin) {
-    mwg_sample(m, irc, w_psi, w_delta, seed, ray, event, burn_in, 1, alpha, ab, &phi, psi_out,
-               delta_out, margin);
+    mwg_sample(m, irc, irc->shift, 1.0, w_psi, w_delta, seed, ray, event, burn_in, 1, alpha, ab,
+               &phi, psi_out, delta_out, margin);
 }
 
 void orc_mwg_sample_psi(const orc_mosaic *m, const orc_irc *irc, double w_psi,
                         uint64_t seed, uint64_t ray, uint32_t event, int burn_in,
                         double alpha, double ab, double *psi_out, double *delta_out,
                         double *margin) {
-    mwg_sample(m, irc, w_psi, 0.0, seed, ray, event, burn_in, 0, alpha, ab, NULL, psi_out,
-               delta_out, margin);
+    mwg_sample(m, irc, irc->shift, 1.0, w_psi, 0.0, seed, ray, event, burn_in, 0, alpha, ab,
+               NULL, psi_out, delta_out, margin);
 }
 
 /* Crystallite normal for glancing angle alpha on the planes of normal N
@@ -867,6 +868,105 @@ static void ctx_init(trace_ctx *X, const orc_source *s, const orc_crystal *c,
    exit when the path reaches the boundary, absorption when
    u1 <= mu0 / mu_eff, otherwise a reflection off the H planes (normal N)
    when u2 sigma < sigma_H, else off the anti-H planes (normal -N). */
+/* The psi integral of W (or of W G with a polarisation at angle phi). */
+static double psi_int(const trace_ctx *X, double alpha, double beta, const double *phi) {
+    return phi ? orc_psi_integral_pol(X->m, alpha, beta, *phi, X->psi_nodes)
+               : orc_psi_integral(X->m, alpha, beta, X->psi_nodes);
+}
+
+/* With further plane sets (sec. 2.2.3, closing paragraphs) the attenuation
+   sums the H and anti-H terms of every set j, each with its own Bragg angle
+   alpha_B,j, shift Delta_M,j and curve r((x - Delta_M,j) / s_j) of peak
+   strength a_j (so its integral is a_j s_j int r), the anti-H terms times
+   hbar_ratio; the reflecting set and side are then drawn by their shares,
+   in the order H_0, anti-H_0, H_1, ..., and the crystallite is sampled for
+   that set. */
+static void mwg_events_planes(const trace_ctx *X, uint64_t ray, double E, double p[3],
+                              double k[3], double *pol, uint32_t *n_ev, uint32_t *n_rf,
+                              int *status, double *m) {
+    const orc_crystal *c = X->c;
+    const orc_planes *pl = c->planes;
+    int nset = 1 + pl->n_extra;
+    double ab[4], shift[4], scale[4], strength[4];
+    for (int j = 0; j < nset; ++j) {
+        ab[j] = orc_bragg_angle(E, j ? pl->two_d[j - 1] : c->two_d);
+        shift[j] = j ? pl->shift[j - 1] : X->irc->shift;
+        scale[j] = j ? pl->width_scale[j - 1] : 1.0;
+        strength[j] = j ? pl->strength[j - 1] : 1.0;
+    }
+    uint32_t n_events = 0, n_refl = 0;
+    for (;;) {
+        if (n_events == X->max_events) { *status = ORC_TRUNCATED; break; }
+        double u[4];
+        ray_words(X->seed, ray, 1, n_events, u);
+        uint32_t event = n_events++;
+        double dist = exit_distance(c, &X->E, p, k);
+        double N[3], e1[3], e2[3];
+        local_frame(c, p, N, e1, e2);
+        double sn = -dot(k, N);
+        if (sn > 1.0) sn = 1.0;
+        if (sn < -1.0) sn = -1.0;
+        double alpha = asin(sn);
+        double minus_N[3] = {-N[0], -N[1], -N[2]};
+        double phi_h = pol ? orc_polarisation_angle(pol, N, k, alpha) : 0.0;
+        double phi_a = pol ? orc_polarisation_angle(pol, minus_N, k, -alpha) : 0.0;
+        double sh[4], sa[4], sum = 0.0;
+        for (int j = 0; j < nset; ++j) {
+            sh[j] = sa[j] = 0.0;
+            if (ab[j] >= 0.0 && (int)n_refl < c->max_refl) {
+                double beta = ab[j] + shift[j];
+                double qc = X->q * (strength[j] * scale[j]) * cos(beta);
+                sh[j] = qc * psi_int(X, alpha, beta, pol ? &phi_h : NULL);
+                sa[j] = pl->hbar_ratio * qc * psi_int(X, -alpha, beta, pol ? &phi_a : NULL);
+            }
+            sum += sh[j];
+            sum += sa[j];
+        }
+        double mu = c->mu0 + sum;
+        double l = -log(u[0]) / mu;
+        note(m, (l - dist) / fmax(l, dist));
+        if (l >= dist) {
+            axpy(p, dist, k, p);
+            *status = n_refl ? ORC_EXIT_REFLECTED : ORC_EXIT_TRANSMITTED;
+            break;
+        }
+        axpy(p, l, k, p);
+        double pa = c->mu0 / mu;
+        note(m, u[1] - pa);
+        if (u[1] <= pa) { *status = ORC_ABSORBED; break; }
+        double target = u[2] * sum, acc = 0.0;
+        int js = nset - 1, anti = 1;
+        for (int j = 0; j < nset; ++j) {
+            acc += sh[j];
+            note(m, (acc - target) / sum);
+            if (target < acc) { js = j; anti = 0; break; }
+            acc += sa[j];
+            note(m, (acc - target) / sum);
+            if (target < acc) { js = j; anti = 1; break; }
+        }
+        double Ns[3];
+        for (int i = 0; i < 3; ++i) Ns[i] = anti ? -N[i] : N[i];
+        double as = anti ? -alpha : alpha;
+        double cb = cos(ab[js] + shift[js]);
+        double w_psi = X->m->fwhm / (cb > 0.05 ? cb : 0.05);
+        double psi, delta, n[3], ks[3];
+        double phi_s = anti ? phi_a : phi_h;
+        mwg_sample(X->m, X->irc, shift[js], scale[js], w_psi, X->w_delta * scale[js], X->seed, ray,
+                   event, X->burn_in, !X->irc_off, as, ab[js], pol ? &phi_s : NULL, &psi, &delta, m);
+        orc_crystallite(Ns, k, as, ab[js] + delta, psi, n);
+        axpy(k, -2.0 * dot(k, n), n, ks);
+        double nr = sqrt(dot(ks, ks));
+        for (int i = 0; i < 3; ++i) k[i] = ks[i] / nr;
+        if (pol) {
+            double pks = dot(pol, k), g = sqrt(1.0 - pks * pks);
+            for (int i = 0; i < 3; ++i) pol[i] = (pol[i] - pks * k[i]) / g;
+        }
+        ++n_refl;
+    }
+    *n_ev = n_events;
+    *n_rf = n_refl;
+}
+
 static void mwg_events(const trace_ctx *X, uint64_t ray, double alpha_b, double p[3],
                        double k[3], double *pol, uint32_t *n_ev, uint32_t *n_rf, int *status,
                        double *m) {
@@ -921,8 +1021,8 @@ static void mwg_events(const trace_ctx *X, uint64_t ray, double alpha_b, double 
         double as = anti ? -alpha : alpha;
         double psi, delta, n[3], ks[3];
         double phi_s = anti ? phi_a : phi_h;
-        mwg_sample(X->m, X->irc, w_psi, X->w_delta, X->seed, ray, event, X->burn_in, !X->irc_off,
-                   as, alpha_b, pol ? &phi_s : NULL, &psi, &delta, m);
+        mwg_sample(X->m, X->irc, X->irc->shift, 1.0, w_psi, X->w_delta, X->seed, ray, event,
+                   X->burn_in, !X->irc_off, as, alpha_b, pol ? &phi_s : NULL, &psi, &delta, m);
         orc_crystallite(Ns, k, as, alpha_b + delta, psi, n);
         /* reflection equation of sec. 2.2.4 */
         axpy(k, -2.0 * dot(k, n), n, ks);
@@ -973,7 +1073,10 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
     int status = ORC_TRUNCATED;
 
     if (X->mwg) {
-        mwg_events(X, ray, alpha_b, p, k, polarised ? pol : NULL, &n_events, &n_refl, &status, &m);
+        if (c->planes)
+            mwg_events_planes(X, ray, E, p, k, polarised ? pol : NULL, &n_events, &n_refl, &status, &m);
+        else
+            mwg_events(X, ray, alpha_b, p, k, polarised ? pol : NULL, &n_events, &n_refl, &status, &m);
         goto finish;
     }
     for (;;) {
@@ -1188,7 +1291,7 @@ static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic 
             if (!(pl->two_d[j] > 0.0 && pl->two_d[j] <= c->two_d) || !(pl->strength[j] > 0.0) ||
                 !(pl->width_scale[j] > 0.0))
                 return -17;
-        if ((model && model->kind == ORC_MODEL_MWG) || irc->n_dep > 0) return -17;
+        if (irc->n_dep > 0) return -17;
     }
 
     if (s->spectrum == ORC_SPEC_TABLE && (s->n_bins < 1 || !s->bin_w)) return -6;

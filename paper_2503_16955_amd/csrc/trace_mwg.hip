@@ -18,13 +18,16 @@
 namespace mrt {
 namespace tk {
 
-template <int GEOM, bool REC, bool POL = false>
+template <int GEOM, bool REC, bool POL = false, bool PLANES = false>
 struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
     // the base's start() with the extended inputs (source spot, user ray
     // arrays); its event code, which the energy-dependent curve would
     // change, is not used here.  POL: rays carry polarisations (the user's),
     // and the cross-section and the sampler's target carry the polarisation
-    // factor (Eqs. SimpleReflXsectionPol, ReflXsectionPol).
+    // factor (Eqs. SimpleReflXsectionPol, ReflXsectionPol).  PLANES: the
+    // antiparallel planes' strength and further plane sets (sec. 2.2.3,
+    // closing paragraphs): the attenuation sums every set and side, and the
+    // reflecting set and side are drawn by their shares.
     using B = Tracer<double, GEOM, kAny, kAny, REC, true, POL>;
     using RayT = typename B::RayT;
 
@@ -158,7 +161,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
     // reflection.  Returns the end status, or -1 (`pend` set when the event
     // is a reflection off the planes of normal Ns at glancing angle alpha_s).
     static __device__ __forceinline__ int event(const TraceParams &P, RayT &ry, bool &pend,
-                                                V3<double> &Ns, double &alpha_s) {
+                                                V3<double> &Ns, double &alpha_s, int &pset) {
         if (ry.nev == P.max_events) return MRT_TRUNCATED;
         const dm::Words w = dm::philox(P.key0, P.key1, ry.nev, (uint32_t)ry.id,
                                        (uint32_t)(ry.id >> 32), 1u);
@@ -170,6 +173,8 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
         double sn = -dot(ry.k, N);
         sn = sn > 1.0 ? 1.0 : (sn < -1.0 ? -1.0 : sn);
         const double alpha = ::asin(sn);
+        if constexpr (PLANES) return event_planes(P, ry, pend, Ns, alpha_s, pset, w, exit_status,
+                                                  dist, N, sn, alpha);
         double sig_h = 0.0, sig_a = 0.0;
         if (ry.sa < 1.0 && (int)ry.nrefl < P.max_refl) {
             const double beta = ::asin(ry.sa) + P.shift;
@@ -213,6 +218,96 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
         return -1;
     }
 
+    // One event with plane sets: the H and anti-H terms of every set j (its
+    // Bragg angle, shift, and curve of strength a_j and width scale s_j, so
+    // q_j = a_j s_j q), the anti-H terms times hbar; the reflecting set and
+    // side drawn by u2 against the running sum in the order H_0, anti-H_0,
+    // H_1, ... (at most four sets; the loops unroll over them).
+    static __device__ __forceinline__ double sigma_pair(const TraceParams &P, const RayT &ry,
+                                                        const V3<double> &N, double sn,
+                                                        double alpha, double beta, double &ia) {
+        double ih, i2h, i2a;
+        bool polar = false;
+        if constexpr (POL) polar = P.user_p != nullptr;
+        if (polar) {
+            psi_integrals<true>(P, alpha, beta, ih, ia, i2h, i2a);
+            double c = 0.0, s = 0.0;
+            const double ca = ::sqrt(fma(-sn, sn, 1.0));
+            if constexpr (POL) {
+                if (ca > 0.0) pol_frame(ry.pol, N, ry.k, sn, ca, c, s);
+            }
+            double s2, c2;
+            sincos_(2.0 * beta, &s2, &c2);
+            const double S = s2 * s2, cos2 = c * c - s * s;
+            ih = (1.0 - S / 2.0) * ih - S * cos2 * i2h;
+            ia = (1.0 - S / 2.0) * ia - S * cos2 * i2a;
+        } else {
+            psi_integrals<false>(P, alpha, beta, ih, ia, i2h, i2a);
+        }
+        return ih;
+    }
+    static __device__ __forceinline__ int event_planes(const TraceParams &P, RayT &ry, bool &pend,
+                                                       V3<double> &Ns, double &alpha_s, int &pset,
+                                                       const dm::Words &w, int exit_status,
+                                                       double dist, const V3<double> &N, double sn,
+                                                       double alpha) {
+        double sh[kSets], sa[kSets], sum = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSets; ++j) {
+            sh[j] = 0.0;
+            sa[j] = 0.0;
+            if (j < P.n_planes) {
+                const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
+                if (sj < 1.0 && (int)ry.nrefl < P.max_refl) {
+                    const double beta = ::asin(sj) + P.plane_shift[j];
+                    double ia;
+                    const double ih = sigma_pair(P, ry, N, sn, alpha, beta, ia);
+                    const double qc = P.q * (P.plane_a[j] * P.plane_scale[j]) * cos_(beta);
+                    sh[j] = qc * ih;
+                    sa[j] = P.hbar * qc * ia;
+                }
+                sum += sh[j];
+                sum += sa[j];
+            }
+        }
+        const double mu = P.mu0 + sum;
+        const double l = -dm::log_pos(dm::u01_f64(w.w0)) / mu;
+        if (l >= dist) {
+            ry.p = axpy(ry.p, dist, ry.k);
+            return exit_status;
+        }
+        ry.p = axpy(ry.p, l, ry.k);
+        if (dm::u01_f64(w.w1) <= P.mu0 / mu) return MRT_ABSORBED;
+        const double target = dm::u01_f64(w.w2) * sum;
+        double acc = 0.0;
+        int js = P.n_planes - 1;
+        bool anti = true, chosen = false;
+#pragma unroll
+        for (int j = 0; j < kSets; ++j) {
+            if (j < P.n_planes && !chosen) {
+                acc += sh[j];
+                if (target < acc) {
+                    js = j;
+                    anti = false;
+                    chosen = true;
+                } else {
+                    acc += sa[j];
+                    if (target < acc) {
+                        js = j;
+                        anti = true;
+                        chosen = true;
+                    }
+                }
+            }
+        }
+        Ns = anti ? V3<double>{-N.x, -N.y, -N.z} : N;
+        alpha_s = anti ? -alpha : alpha;
+        pset = js;
+        pend = true;
+        return -1;
+    }
+    static constexpr int kSets = 4;
+
     // ---- the sampler's target: the integrand of Eq. ReflXsection --------
     // f(psi, Delta) = r(Delta - Delta_M) cos(b) W(v), b = alpha_B + Delta,
     // v = 2 sin^2((alpha - b)/2) + 2 cos(alpha) cos(b) sin^2(psi/2).  The
@@ -238,9 +333,11 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
     }
     static __device__ __forceinline__ void at_delta(const TraceParams &P, const double *lut,
                                                     double alpha, double ab, double delta,
-                                                    bool polar, Point &x) {
+                                                    double shift, double scale, bool polar,
+                                                    Point &x) {
         const double b = ab + delta;
-        x.r = B::irc_ratio(P, lut, delta - P.shift);
+        // a further plane set reads the curve at (Delta - its shift) / its scale
+        x.r = B::irc_ratio(P, lut, scale == 1.0 ? delta - shift : (delta - shift) / scale);
         if (polar) {
             double sb;
             sincos_(b, &sb, &x.cb);
@@ -262,12 +359,21 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
     // N is rotated by alpha - (alpha_B + Delta) about N x k and by psi about
     // k, and k is reflected (sec. 2.2.4).
     static __device__ __forceinline__ void reflect(const TraceParams &P, const double *lut, RayT &ry,
-                                                   V3<double> Ns, double alpha) {
-        const double ab = ::asin(ry.sa);
+                                                   V3<double> Ns, double alpha, int pset) {
+        // the reflecting set: its Bragg angle, shift and width scale
+        double ab, shift = P.shift, scale = 1.0;
+        if constexpr (PLANES) {
+            ab = ::asin(pset ? kHC / (P.plane_2d[pset] * ry.E) : ry.sa);
+            shift = P.plane_shift[pset];
+            scale = P.plane_scale[pset];
+        } else {
+            ab = ::asin(ry.sa);
+        }
+        const double w_delta = PLANES ? P.w_delta * scale : P.w_delta;
         const double lo = -ab, hi = kPiHalf - ab;
-        double psi = 0.0, delta = P.shift;
+        double psi = 0.0, delta = shift;
         delta = delta < lo ? lo : (delta > hi ? hi : delta);
-        double cbm = cos_(ab + P.shift);
+        double cbm = cos_(ab + shift);
         cbm = cbm > 0.05 ? cbm : 0.05;
         const double w_psi = P.fwhm / cbm;
         double sa, ca;
@@ -280,7 +386,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             if (polar && ca > 0.0) pol_frame(ry.pol, Ns, ry.k, sa, ca, pc, ps);
         }
         Point x;
-        at_delta(P, lut, alpha, ab, delta, polar, x);
+        at_delta(P, lut, alpha, ab, delta, shift, scale, polar, x);
         x.sp = 0.0;   // sin(0 / 2)
         x.cp = 1.0;
         double f = value(P, x, ca, polar, pc, ps);
@@ -298,10 +404,10 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
                 x = y;
                 f = fn;
             }
-            const double dn = delta + P.w_delta * (2.0 * dm::u01_f64(w.w2) - 1.0);
+            const double dn = delta + w_delta * (2.0 * dm::u01_f64(w.w2) - 1.0);
             if (!P.irc_off && dn >= lo && dn <= hi) {   // the IRC disabled: Delta stays
                 y = x;
-                at_delta(P, lut, alpha, ab, dn, polar, y);
+                at_delta(P, lut, alpha, ab, dn, shift, scale, polar, y);
                 fn = value(P, y, ca, polar, pc, ps);
                 if (dm::u01_f64(w.w3) * f < fn || f == 0.0) {
                     delta = dn;
@@ -361,6 +467,7 @@ __device__ __forceinline__ void mwg_loop(const TraceParams &P, const double *lut
     bool pend = false;            // the lane waits for the sampler
     V3<double> Ns{0.0, 0.0, 0.0};
     double alpha_s = 0.0;
+    int pset = 0;                 // the reflecting plane set (PLANES)
     WaveCounts cnt{};
     uint64_t next = 0, end = 0;
     bool more = true;
@@ -418,7 +525,7 @@ __device__ __forceinline__ void mwg_loop(const TraceParams &P, const double *lut
         for (;;) {
             int status = -1;
             const bool stepping = active && !pend;
-            if (stepping) status = T::event(P, ry, pend, Ns, alpha_s);
+            if (stepping) status = T::event(P, ry, pend, Ns, alpha_s, pset);
             const bool ended = status >= 0;
             bool det = false;
             if (ended) {
@@ -443,7 +550,7 @@ __device__ __forceinline__ void mwg_loop(const TraceParams &P, const double *lut
             const uint32_t due = refilling && keep < batch ? keep : batch;
             if (npend && (npend >= due || (!refilling && popc(ballot(active && !pend)) == 0))) {
                 if (pend) {
-                    T::reflect(P, lut, ry, Ns, alpha_s);
+                    T::reflect(P, lut, ry, Ns, alpha_s, pset);
                     pend = false;
                 }
                 cnt.reflections += npend;
@@ -454,9 +561,9 @@ __device__ __forceinline__ void mwg_loop(const TraceParams &P, const double *lut
     flush(P, cnt);
 }
 
-template <int GEOM, bool REC, bool POL>
+template <int GEOM, bool REC, bool POL, bool PLANES = false>
 __global__ void __launch_bounds__(256) mwg_kernel(const TraceParams P) {
-    using T = MwgTracer<GEOM, REC, POL>;
+    using T = MwgTracer<GEOM, REC, POL, PLANES>;
     const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
     RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
     __shared__ typename T::Queue queues[4];   // one per wave
@@ -464,19 +571,23 @@ __global__ void __launch_bounds__(256) mwg_kernel(const TraceParams P) {
     mwg_loop<T>(Q, Q.lut, Q.bin_cdf, claim, q);
 }
 
-template <int GEOM, bool POL> const void *mwg_kernel_of(bool records) {
-    return records ? (const void *)mwg_kernel<GEOM, true, POL> : (const void *)mwg_kernel<GEOM, false, POL>;
+template <int GEOM, bool POL, bool PLANES> const void *mwg_kernel_of(bool records) {
+    return records ? (const void *)mwg_kernel<GEOM, true, POL, PLANES>
+                   : (const void *)mwg_kernel<GEOM, false, POL, PLANES>;
+}
+template <int GEOM> const void *mwg_kernel_geom(bool records, bool polarised, bool planes) {
+    if (planes)
+        return polarised ? mwg_kernel_of<GEOM, true, true>(records) : mwg_kernel_of<GEOM, false, true>(records);
+    return polarised ? mwg_kernel_of<GEOM, true, false>(records) : mwg_kernel_of<GEOM, false, false>(records);
 }
 
 }  // namespace tk
 
-const void *mwg_kernel_ptr(int geometry, bool records, bool polarised) {
+const void *mwg_kernel_ptr(int geometry, bool records, bool polarised, bool planes) {
     if (geometry == MRT_GEOMETRY_FLAT)
-        return polarised ? tk::mwg_kernel_of<MRT_GEOMETRY_FLAT, true>(records)
-                         : tk::mwg_kernel_of<MRT_GEOMETRY_FLAT, false>(records);
+        return tk::mwg_kernel_geom<MRT_GEOMETRY_FLAT>(records, polarised, planes);
     if (geometry == MRT_GEOMETRY_CYLINDER)
-        return polarised ? tk::mwg_kernel_of<MRT_GEOMETRY_CYLINDER, true>(records)
-                         : tk::mwg_kernel_of<MRT_GEOMETRY_CYLINDER, false>(records);
+        return tk::mwg_kernel_geom<MRT_GEOMETRY_CYLINDER>(records, polarised, planes);
     return nullptr;
 }
 

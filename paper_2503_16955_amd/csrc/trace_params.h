@@ -158,7 +158,7 @@ constexpr int kMaxQeNodes = 1024;
 const void *serve_kernel_ptr(int precision);
 // Kernel of the paper's event model (FP64) for a geometry (nullptr for an
 // unknown one): (TraceParams), like the trace kernels.
-const void *mwg_kernel_ptr(int geometry, bool records, bool polarised);
+const void *mwg_kernel_ptr(int geometry, bool records, bool polarised, bool planes);
 // Kernel for the extended inputs: an energy-dependent rocking curve, a
 // finite source spot, user ray arrays (every kind read at run time).
 const void *ext_kernel_ptr(int precision, bool records);

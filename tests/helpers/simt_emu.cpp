@@ -144,9 +144,9 @@ void trace_body(const TraceParams &P, void *queue) {
     trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(typename T::Queue *)queue);
 }
 
-template <bool REC, bool POL>
+template <bool REC, bool POL, bool PLANES = false>
 void mwg_body(const TraceParams &P, void *queue) {
-    using T = MwgTracer<kAny, REC, POL>;
+    using T = MwgTracer<kAny, REC, POL, PLANES>;
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
     mwg_loop<T>(P, P.lut, P.bin_cdf, claim, *(typename T::Queue *)queue);
 }
@@ -201,7 +201,10 @@ int emu_trace_mwg(TraceParams *P, int n_waves, long long max_meetings) {
         QueueMem q;
         int e = run_wave([&] {
             const bool rec = P->records_mode != MRT_RECORDS_NONE;
-            if (P->user_p) { if (rec) mwg_body<true, true>(*P, q.b); else mwg_body<false, true>(*P, q.b); }
+            if (P->has_planes) {
+                if (P->user_p) { if (rec) mwg_body<true, true, true>(*P, q.b); else mwg_body<false, true, true>(*P, q.b); }
+                else { if (rec) mwg_body<true, false, true>(*P, q.b); else mwg_body<false, false, true>(*P, q.b); }
+            } else if (P->user_p) { if (rec) mwg_body<true, true>(*P, q.b); else mwg_body<false, true>(*P, q.b); }
             else { if (rec) mwg_body<true, false>(*P, q.b); else mwg_body<false, false>(*P, q.b); }
         }, max_meetings);
         if (e) return e;

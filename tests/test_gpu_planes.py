@@ -4,8 +4,10 @@ in per-ray parity with the oracle (FP64) on both geometries and the
 tabulated curve, sampled at the full 1e8-ray von Hamos size; the
 second-order identity (photons of 2E on 2d/2 trace like photons of E on 2d)
 on the device; an empty plane list takes the plain kernel's decisions;
-FP32-mixed agrees with FP64 statistically; the paper's event model and the
-request server refuse planes."""
+FP32-mixed agrees with FP64 statistically; the paper's event model with
+plane sets (sets and sides drawn by their shares) in parity, with and without
+polarisation, and its second-order identity on the device; the request
+server refuses planes."""
 import copy
 
 import numpy as np
@@ -98,15 +100,53 @@ def test_planes_fp32_mixed_agree_with_fp64():
         assert abs(a[f] - b[f]) < 5 * np.sqrt(a[f] + b[f]) + 1e-3 * b[f], (f, a[f], b[f])
 
 
-def test_planes_refused_by_the_papers_model_and_the_server():
-    w = _von_hamos_orders()
-    m = copy.deepcopy(w)
-    m["event_model"] = {"kind": "mwg"}
-    with pytest.raises(mrt.MosaicRTError):
-        mrt.trace(m, n_rays=1000)
+def test_planes_refused_by_the_server():
     with mrt.Server(hbm_budget_bytes=1 << 28, max_slots=2) as srv:
         with pytest.raises(mrt.MosaicRTError):
-            srv.submit(w, n_rays=1000)
+            srv.submit(_von_hamos_orders(), n_rays=1000)
+
+
+def _mwg(w, burn_in=150):
+    w = copy.deepcopy(w)
+    w["event_model"] = {"kind": "mwg", "burn_in": burn_in, "psi_nodes": 128}
+    return w
+
+
+def test_planes_in_the_papers_model_parity():
+    g, o = assert_parity(_mwg(_von_hamos_orders()), 100_000)
+    assert o["counters"]["reflections"] > 500
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    td = w["crystal"]["two_d"]
+    g, o = assert_parity(_mwg(_planes(w, 0.3, [(td / 2, 0.5, 1.0, 0.0), (td / 3, 0.2, 0.7, -3e-6)])),
+                         60_000, first=11)
+    assert o["counters"]["reflections"] > 300
+
+
+def test_planes_with_polarisation_in_the_papers_model():
+    w = _mwg(_von_hamos_orders(0.8))
+    n = 60_000
+    _, k, _ = oracle.source_sample(w, np.arange(n))
+    a = np.random.default_rng(12).normal(size=k.shape)
+    a -= np.sum(a * k, axis=1)[:, None] * k
+    p = a / np.linalg.norm(a, axis=1)[:, None]
+    g, o = assert_parity(w, n, rays={"polarisations": p})
+    assert o["counters"]["reflections"] > 300
+
+
+def test_papers_model_second_order_at_twice_the_energy_on_the_device():
+    import torch
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    w = _mwg(_planes(w, extra=[(w["crystal"]["two_d"] / 2, 1.0, 1.0, w["rocking_curve"]["shift"])]))
+    n = 200_000
+    e = torch.as_tensor(np.random.default_rng(5).uniform(7.9, 8.1, n), device="cuda")
+    a = mrt.trace(w, n_rays=n, records="all", rays={"energies": e})
+    b = mrt.trace(w, n_rays=n, records="all", rays={"energies": 2 * e})
+    ra, rb = mrt.records_to_numpy(a["records"]), mrt.records_to_numpy(b["records"])
+    ra["energy"] = rb["energy"]
+    assert ra.tobytes() == rb.tobytes()
+    assert a["counters"]["reflections"] > 500
 
 
 def test_planes_full_size_sampled():

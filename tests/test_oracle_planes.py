@@ -11,6 +11,7 @@ run (the same random numbers decide it).  A width scale of 2 on the second
 order equals the first order's Gaussian curve of twice the FWHM up to
 rounding (compared ray by ray with the decision margins)."""
 import copy
+import math
 
 import numpy as np
 import pytest
@@ -116,12 +117,71 @@ def test_invalid_planes_rejected(bad):
         oracle.trace(w, n=10)
 
 
-def test_planes_rejected_with_the_papers_model_and_energy_dependence():
-    w = _planes(W.get("flat_hopg"))
-    w["event_model"] = {"kind": "mwg"}
-    with pytest.raises(ValueError):
-        oracle.trace(w, n=10)
+def test_planes_rejected_with_energy_dependence():
     w = _planes(W.get("flat_hopg"))
     w["rocking_curve"]["energy_dependence"] = [(8.0, 0.0, 1.0)]
     with pytest.raises(ValueError):
         oracle.trace(w, n=10)
+
+
+# ---- the paper's event model (sets and sides drawn by their shares) --------
+
+def _mwg(w, burn_in=100):
+    w = copy.deepcopy(w)
+    w["event_model"] = {"kind": "mwg", "burn_in": burn_in, "psi_nodes": 128}
+    return w
+
+
+def test_papers_model_empty_plane_list_takes_the_same_decisions():
+    w = _mwg(W.get("von_hamos_hapg"))
+    n = 30000
+    A = _rec(w, n)
+    B = _rec(_planes(w), n)
+    n_ties, bad, _ = parity.compare(A["records"], B["records"], np.minimum(A["margins"], B["margins"]))
+    assert len(bad) == 0 and n_ties <= 2
+    assert A["records"]["n_refl"].sum() > 200
+
+
+def test_papers_model_second_order_at_twice_the_energy():
+    # a von Mises-Fisher mosaic of 0.4 deg: the density vanishes (underflows)
+    # at the other order's Bragg angle, so each energy sees one set only
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 4
+    w = _mwg(_planes(w, extra=[(w["crystal"]["two_d"] / 2, 1.0, 1.0, w["rocking_curve"]["shift"])]))
+    n = 20000
+    _, _, e = oracle.source_sample(w, np.arange(n))
+    a = _rec(w, n, rays={"energies": e})["records"]
+    b = _rec(w, n, rays={"energies": 2 * e})["records"]
+    a2 = a.copy()
+    a2["energy"] = b["energy"]
+    assert np.array_equal(b["energy"], 2 * a["energy"])
+    assert a2.tobytes() == b.tobytes()
+    assert a["n_refl"].sum() > 100
+
+
+def test_papers_model_without_antiparallel_planes_reflects_once():
+    w = W.get("flat_hopg")
+    w["crystal"]["max_refl"] = 8
+    w["crystal"]["thickness"] = 0.2
+    n = 60000
+    on = _rec(_mwg(_planes(w, hbar=1.0)), n)["records"]
+    off = _rec(_mwg(_planes(w, hbar=0.0)), n)["records"]
+    assert (on["n_refl"] >= 2).sum() > 20
+    assert off["n_refl"].max() == 1
+    assert np.array_equal(off["n_refl"] == 1, on["n_refl"] >= 1)
+
+
+def test_papers_model_set_shares():
+    # two identical sets at strengths 1 and 0.5: a third of the reflections
+    # come from the second, which is otherwise the main set at 1.5 times its
+    # peak (reflection counts agree within counting statistics)
+    w = W.get("flat_hopg")
+    td, rc = w["crystal"]["two_d"], w["rocking_curve"]
+    a = _mwg(_planes(w, extra=[(td, 0.5, 1.0, rc["shift"])]))
+    b = _mwg(copy.deepcopy(w))
+    b["rocking_curve"]["peak"] = 1.5 * rc["peak"]
+    n = 200000
+    ra = oracle.trace(a, n=n)["counters"]["reflections"]
+    rb = oracle.trace(b, n=n)["counters"]["reflections"]
+    assert ra > 2000
+    assert abs(ra - rb) < 4 * math.sqrt(ra + rb), (ra, rb)

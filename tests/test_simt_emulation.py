@@ -264,7 +264,7 @@ def _user_rays(w, n, seed):
 
 @pytest.mark.parametrize("case", ["gaussian_spot", "disk_spot", "user_rays", "user_energies",
                                   "mwg_spot", "mwg_user_rays", "mwg_polarised",
-                                  "mwg_polarised_oblique"])
+                                  "mwg_polarised_oblique", "mwg_planes", "mwg_planes_polarised"])
 def test_source_spot_and_user_ray_loops(emu, case):
     """The extended-input kernels (FP64) run under the emulator with a source
     spot or user ray arrays: every ray matches the oracle's record; the
@@ -285,6 +285,14 @@ def test_source_spot_and_user_ray_loops(emu, case):
     elif case == "mwg_polarised":
         _, k, _ = oracle.source_sample(w, np.arange(n), seed=seed)
         rays = {"polarisations": _random_polarisations(k, 2)}
+    elif case in ("mwg_planes", "mwg_planes_polarised"):
+        # H-bar at 0.6 and a second order, with a line at twice the energy
+        w["crystal"]["planes"] = {"hbar_ratio": 0.6,
+                                  "extra": [(w["crystal"]["two_d"] / 2, 0.7, 1.4, 4e-6)]}
+        w["source"]["lines"] = list(w["source"]["lines"]) + [(2 * 8.048, 0.004, 0.4)]
+        if case == "mwg_planes_polarised":
+            _, k, _ = oracle.source_sample(w, np.arange(n), seed=seed)
+            rays = {"polarisations": _random_polarisations(k, 4)}
     elif case == "mwg_polarised_oblique":
         # unit vectors with a component along k: only the normal part counts
         a = np.random.default_rng(3).normal(size=(n, 3))
