@@ -886,13 +886,21 @@ static void mwg_events_planes(const trace_ctx *X, uint64_t ray, double E, double
                               int *status, double *m) {
     const orc_crystal *c = X->c;
     const orc_planes *pl = c->planes;
-    int nset = 1 + pl->n_extra;
+    const orc_irc *q = X->irc;
+    int nset = 1 + (pl ? pl->n_extra : 0);
+    double hbar = pl ? pl->hbar_ratio : 1.0;
     double ab[4], shift[4], scale[4], strength[4];
     for (int j = 0; j < nset; ++j) {
         ab[j] = orc_bragg_angle(E, j ? pl->two_d[j - 1] : c->two_d);
-        shift[j] = j ? pl->shift[j - 1] : X->irc->shift;
+        shift[j] = j ? pl->shift[j - 1] : q->shift;
         scale[j] = j ? pl->width_scale[j - 1] : 1.0;
         strength[j] = j ? pl->strength[j - 1] : 1.0;
+    }
+    if (q->n_dep > 0) {
+        /* the energy-dependent curve (sec. 2.2.1) is the main set's shift
+           Delta_M(E) and width scale s(E) */
+        shift[0] = interp_clamped(q->dep_kev, q->dep_shift, q->n_dep, E);
+        scale[0] = interp_clamped(q->dep_kev, q->dep_scale, q->n_dep, E);
     }
     uint32_t n_events = 0, n_refl = 0;
     for (;;) {
@@ -917,7 +925,7 @@ static void mwg_events_planes(const trace_ctx *X, uint64_t ray, double E, double
                 double beta = ab[j] + shift[j];
                 double qc = X->q * (strength[j] * scale[j]) * cos(beta);
                 sh[j] = qc * psi_int(X, alpha, beta, pol ? &phi_h : NULL);
-                sa[j] = pl->hbar_ratio * qc * psi_int(X, -alpha, beta, pol ? &phi_a : NULL);
+                sa[j] = hbar * qc * psi_int(X, -alpha, beta, pol ? &phi_a : NULL);
             }
             sum += sh[j];
             sum += sa[j];
@@ -1073,7 +1081,7 @@ static void trace_one(const trace_ctx *X, uint64_t ray, orc_record *rec, double 
     int status = ORC_TRUNCATED;
 
     if (X->mwg) {
-        if (c->planes)
+        if (c->planes || X->irc->n_dep > 0)
             mwg_events_planes(X, ray, E, p, k, polarised ? pol : NULL, &n_events, &n_refl, &status, &m);
         else
             mwg_events(X, ray, alpha_b, p, k, polarised ? pol : NULL, &n_events, &n_refl, &status, &m);
@@ -1283,7 +1291,6 @@ static int validate(const orc_source *s, const orc_crystal *c, const orc_mosaic 
         return -14;
     for (int i = 0; i < irc->n_dep; ++i)
         if (!(irc->dep_scale[i] > 0.0) || (i && !(irc->dep_kev[i] > irc->dep_kev[i - 1]))) return -14;
-    if (irc->n_dep > 0 && model && model->kind == ORC_MODEL_MWG) return -15;
     if (c->planes) {
         const orc_planes *pl = c->planes;
         if (!(pl->hbar_ratio >= 0.0) || pl->n_extra < 0 || pl->n_extra > 3) return -17;

@@ -134,8 +134,6 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     if (!mwg && opt.mwg_irc_off != 0) return fail(MRT_EINVAL, "options: mwg_irc_off needs the MWG event model");
     if (mwg) {
         if (opt.precision != MRT_FP64) return fail(MRT_EINVAL, "options: the MWG event model runs in FP64");
-        if (rocking_curve->n_dep > 0)
-            return fail(MRT_EINVAL, "the MWG event model takes no energy-dependent rocking curve");
         if (!(mosaic->fwhm > 0.0)) return fail(MRT_EINVAL, "the MWG event model needs a mosaic fwhm > 0");
         if (opt.mwg_burn_in < MRT_MWG_NO_BURN_IN) return fail(MRT_EINVAL, "options: mwg_burn_in must be >= -1");
         if (opt.psi_nodes < 0 || opt.psi_nodes > mrt::kMaxPsiNodes)
@@ -212,7 +210,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
 
     const bool rec = opt.records_mode != MRT_RECORDS_NONE;
     const void *kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec, source->polarisations != nullptr,
-                                                   crystal->planes != nullptr)
+                                                   crystal->planes != nullptr || rocking_curve->n_dep > 0)
                          : mrt::uses_ext(source, crystal, rocking_curve)
                              ? mrt::ext_kernel_ptr(opt.precision, rec)
                              : mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,

@@ -27,7 +27,8 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
     // factor (Eqs. SimpleReflXsectionPol, ReflXsectionPol).  PLANES: the
     // antiparallel planes' strength and further plane sets (sec. 2.2.3,
     // closing paragraphs): the attenuation sums every set and side, and the
-    // reflecting set and side are drawn by their shares.
+    // reflecting set and side are drawn by their shares; also the
+    // energy-dependent curve, as the main set's per-photon shift and scale.
     using B = Tracer<double, GEOM, kAny, kAny, REC, true, POL>;
     using RayT = typename B::RayT;
 
@@ -259,10 +260,12 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             if (j < P.n_planes) {
                 const double sj = j ? kHC / (P.plane_2d[j] * ry.E) : ry.sa;
                 if (sj < 1.0 && (int)ry.nrefl < P.max_refl) {
-                    const double beta = ::asin(sj) + P.plane_shift[j];
+                    double shift, scale;
+                    set_curve(P, ry, j, shift, scale);
+                    const double beta = ::asin(sj) + shift;
                     double ia;
                     const double ih = sigma_pair(P, ry, N, sn, alpha, beta, ia);
-                    const double qc = P.q * (P.plane_a[j] * P.plane_scale[j]) * cos_(beta);
+                    const double qc = P.q * (P.plane_a[j] * scale) * cos_(beta);
                     sh[j] = qc * ih;
                     sa[j] = P.hbar * qc * ia;
                 }
@@ -307,6 +310,18 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
         return -1;
     }
     static constexpr int kSets = 4;
+    // Set j's curve shift and width scale; an energy-dependent curve
+    // (sec. 2.2.1) gives the main set Delta_M(E) and s(E).
+    static __device__ __forceinline__ void set_curve(const TraceParams &P, const RayT &ry, int j,
+                                                     double &shift, double &scale) {
+        if (j == 0 && P.dep_n > 0) {
+            shift = B::interp(P.dep, P.dep + P.dep_n, P.dep_n, ry.E);
+            scale = B::interp(P.dep, P.dep + 2 * P.dep_n, P.dep_n, ry.E);
+        } else {
+            shift = P.plane_shift[j];
+            scale = P.plane_scale[j];
+        }
+    }
 
     // ---- the sampler's target: the integrand of Eq. ReflXsection --------
     // f(psi, Delta) = r(Delta - Delta_M) cos(b) W(v), b = alpha_B + Delta,
@@ -364,8 +379,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
         double ab, shift = P.shift, scale = 1.0;
         if constexpr (PLANES) {
             ab = ::asin(pset ? kHC / (P.plane_2d[pset] * ry.E) : ry.sa);
-            shift = P.plane_shift[pset];
-            scale = P.plane_scale[pset];
+            set_curve(P, ry, pset, shift, scale);
         } else {
             ab = ::asin(ry.sa);
         }

@@ -201,7 +201,7 @@ int emu_trace_mwg(TraceParams *P, int n_waves, long long max_meetings) {
         QueueMem q;
         int e = run_wave([&] {
             const bool rec = P->records_mode != MRT_RECORDS_NONE;
-            if (P->has_planes) {
+            if (P->has_planes || P->dep_n > 0) {
                 if (P->user_p) { if (rec) mwg_body<true, true, true>(*P, q.b); else mwg_body<false, true, true>(*P, q.b); }
                 else { if (rec) mwg_body<true, false, true>(*P, q.b); else mwg_body<false, false, true>(*P, q.b); }
             } else if (P->user_p) { if (rec) mwg_body<true, true>(*P, q.b); else mwg_body<false, true>(*P, q.b); }

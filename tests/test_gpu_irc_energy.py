@@ -84,3 +84,13 @@ def test_server_refuses_energy_dependent_curves():
     with mrt.Server(hbm_budget_bytes=1 << 28, max_slots=2) as srv:
         with pytest.raises(mrt.MosaicRTError):
             srv.submit(_dep(W.get("von_hamos_hapg")), n_rays=1000)
+
+
+def test_papers_model_parity():
+    # the paper's event model with the energy-dependent curve (sec. 2.2.1):
+    # per photon beta = alpha_B + Delta_M(E) and strength s(E) int r / h
+    for name, n in (("von_hamos_hapg", 100_000), ("flat_hopg", 60_000)):
+        w = _dep(W.get(name))
+        w["event_model"] = {"kind": "mwg", "burn_in": 200, "psi_nodes": 256}
+        g, o = assert_parity(w, n)
+        assert o["counters"]["reflections"] > 300

@@ -81,8 +81,40 @@ def test_energy_dependence_needs_increasing_energies_and_positive_scales():
         w["rocking_curve"]["energy_dependence"] = table
         with pytest.raises(ValueError):
             oracle.trace(w, n=10)
-    w = W.get("flat_hopg")
-    w["rocking_curve"]["energy_dependence"] = [(8.0, 0.0, 1.0)]
-    w["event_model"] = {"kind": "mwg"}
-    with pytest.raises(ValueError):
-        oracle.trace(w, n=10)
+
+
+# ---- the paper's event model ---------------------------------------------------
+
+def _mwg(w, burn_in=100):
+    w = copy.deepcopy(w)
+    w["event_model"] = {"kind": "mwg", "burn_in": burn_in, "psi_nodes": 128}
+    return w
+
+
+def _rec_m(w, n):
+    return oracle.trace(w, n=n, records=True, margins=True, images=False)
+
+
+def test_papers_model_constant_tables_take_the_plain_decisions():
+    import parity
+    w = _mwg(W.get("von_hamos_hapg"))
+    w["rocking_curve"]["shift"] = 6e-6
+    d = copy.deepcopy(w)
+    d["rocking_curve"]["energy_dependence"] = [(7.0, 6e-6, 1.0), (9.0, 6e-6, 1.0)]
+    A, B = _rec_m(w, 30000), _rec_m(d, 30000)
+    n_ties, bad, _ = parity.compare(A["records"], B["records"], np.minimum(A["margins"], B["margins"]))
+    assert len(bad) == 0 and n_ties <= 2
+    assert A["records"]["n_refl"].sum() > 200
+
+
+def test_papers_model_scale_two_is_the_gaussian_of_twice_the_width():
+    import parity
+    w = _mwg(W.get("flat_hopg"))
+    d = copy.deepcopy(w)
+    d["rocking_curve"]["energy_dependence"] = [(7.5, 0.0, 2.0)]
+    wide = copy.deepcopy(w)
+    wide["rocking_curve"]["fwhm"] = 2 * w["rocking_curve"]["fwhm"]
+    A, B = _rec_m(d, 40000), _rec_m(wide, 40000)
+    n_ties, bad, _ = parity.compare(A["records"], B["records"], np.minimum(A["margins"], B["margins"]))
+    assert len(bad) == 0 and n_ties <= 2
+    assert B["records"]["n_refl"].sum() > _rec_m(w, 40000)["records"]["n_refl"].sum()

@@ -264,7 +264,8 @@ def _user_rays(w, n, seed):
 
 @pytest.mark.parametrize("case", ["gaussian_spot", "disk_spot", "user_rays", "user_energies",
                                   "mwg_spot", "mwg_user_rays", "mwg_polarised",
-                                  "mwg_polarised_oblique", "mwg_planes", "mwg_planes_polarised"])
+                                  "mwg_polarised_oblique", "mwg_planes", "mwg_planes_polarised",
+                                  "mwg_energy_dependent"])
 def test_source_spot_and_user_ray_loops(emu, case):
     """The extended-input kernels (FP64) run under the emulator with a source
     spot or user ray arrays: every ray matches the oracle's record; the
@@ -285,6 +286,8 @@ def test_source_spot_and_user_ray_loops(emu, case):
     elif case == "mwg_polarised":
         _, k, _ = oracle.source_sample(w, np.arange(n), seed=seed)
         rays = {"polarisations": _random_polarisations(k, 2)}
+    elif case == "mwg_energy_dependent":
+        w["rocking_curve"]["energy_dependence"] = [(7.9, -20e-6, 0.7), (8.05, 5e-6, 1.6)]
     elif case in ("mwg_planes", "mwg_planes_polarised"):
         # H-bar at 0.6 and a second order, with a line at twice the energy
         w["crystal"]["planes"] = {"hbar_ratio": 0.6,
