@@ -112,10 +112,11 @@ def roofline(op_costs, profiling, w, precision, per_step, cus):
             "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
 
 
-def mwg_kernel_name(w, records=False, polarised=False):
+def mwg_kernel_name(w, records=False, polarised=False, planes=False):
     g = KIND["geometry"][w["crystal"]["geometry"]]
     b = lambda x: "true" if x else "false"
-    return f"void mrt::tk::mwg_kernel<{g}, {b(records)}, {b(polarised)}>(mrt::TraceParams)"
+    return (f"void mrt::tk::mwg_kernel<{g}, {b(records)}, {b(polarised)}, {b(planes)}>"
+            "(mrt::TraceParams)")
 
 
 def roofline_mwg(op_costs, profiling, w, per_step, cus, psi_nodes, burn_in):
