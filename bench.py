@@ -185,6 +185,41 @@ def mwg_model(mrt, op_costs, profiling, w, n, steps, warmup, burn_in, psi_nodes,
     return out
 
 
+def stress(mrt, W, op_costs, profiling, precision, cus, rays_per_step, steps):
+    """The stress workload (100 um HOPG, Lorentzian 0.8 deg mosaic,
+    Darwin-Prins table curve, 1024-bin spectrum, up to 8 reflections, 4096^2
+    detector): ray ids [0, steps x rays_per_step) in both precisions, their
+    rooflines, FP32-mixed against FP64 (chi^2 per pixel of the images; the
+    fraction of detected rays on another pixel, from records of 1e7 rays)."""
+    import torch
+    w = W.get("flat_stress")
+    out = {"workload": "flat_stress: flat HOPG(002) 100 um, Lorentzian mosaic 0.8 deg, "
+                       "Darwin-Prins table rocking curve, 1024-bin spectrum, max 8 reflections, "
+                       "4096x4096 px", "rays": rays_per_step * steps}
+    imgs = {}
+    for prec in ("fp64", "fp32_mixed"):
+        c, e = mrt.alloc_images(w)
+        ps, gms, _ = run_precision(mrt, w, prec, steps, 1, rays_per_step, c, e)
+        out[prec] = {"value": round(rays_per_step * steps / (gms * 1e-3), 1), "unit": "rays/s",
+                     "ms_per_step": round(gms / steps, 4),
+                     "events_per_s": round(sum(x["events"] for x in ps) / (gms * 1e-3), 1),
+                     "roofline": roofline(op_costs, profiling, w, prec, ps, cus)}
+        imgs[prec] = mrt.image_to_numpy(c)[0]
+        del c, e
+    out["fp32_vs_fp64_chi2_per_px"] = round(
+        precision.chi2_per_pixel(imgs["fp32_mixed"], imgs["fp64"]), 5)
+    n = 10_000_000
+    r64 = mrt.trace(w, n_rays=n, precision="fp64", records="all")["records"]
+    r32 = mrt.trace(w, n_rays=n, precision="fp32_mixed", records="all")["records"]
+    i64, i32 = r64.view(torch.int32), r32.view(torch.int32)
+    d64, d32 = r64[:, 103] == 1, r32[:, 103] == 1
+    moved = (d64 != d32) | (d64 & ((i64[:, 22] != i32[:, 22]) | (i64[:, 23] != i32[:, 23])))
+    out["detected_rays_moved_fraction"] = float(moved.sum().item()) / max(1, int(d64.sum().item()))
+    del r64, r32, i64, i32
+    log(f"stress: fp64 {out['fp64']['value']:.3e}, fp32_mixed {out['fp32_mixed']['value']:.3e} rays/s")
+    return out
+
+
 def extended_inputs(mrt, W, op_costs, w, n, steps, warmup, counts, energy, cus, plain):
     """The extended-input kernels on the benchmark workload: the paper's
     10 um Gaussian XFEL spot (sec. 4.2); the spot with every ray polarised
@@ -392,6 +427,8 @@ def main():
     ap.add_argument("--mwg-psi-nodes", type=int, default=256)
     ap.add_argument("--mwg-cpu-rays", type=int, default=20_000_000)
     ap.add_argument("--no-mwg", action="store_true")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the stress workload (2e9 rays per precision)")
     ap.add_argument("--no-extended", action="store_true",
                     help="skip the extended-input kernels (spot, polarisation, planes)")
     ap.add_argument("--shard-of", type=int, default=8,
@@ -451,6 +488,9 @@ def main():
             "speedup_vs_fp64": round(gpu_ms64 / gms, 3),
             "roofline": roofline(op_costs, profiling, w, "fp32_mixed", pm, info["compute_units"]),
         }
+    if not a.no_stress and not a.no_mixed:
+        res["stress"] = stress(mrt, W, op_costs, profiling, precision, info["compute_units"],
+                               1_000_000_000, 2)
     if not a.no_extended and not a.no_mixed:
         res["extended"] = extended_inputs(
             mrt, W, op_costs, w, n, a.steps, a.warmup, counts, energy, info["compute_units"],

@@ -9,9 +9,9 @@ R=$(cd "$(dirname "$0")/.." && pwd)
 OUT=$(mkdir -p "$1" && cd "$1" && pwd)
 export TMPDIR=/tmp PYTHONPATH=$R
 cd /tmp
-B="python3 $R/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-serving --shard-of 0 --no-extended"
-B1="python3 $R/bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-serving --shard-of 0 --no-extended"
-S="python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-mixed --serving-requests 64 --shard-of 0 --no-extended"
+B="python3 $R/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-serving --shard-of 0 --no-extended --no-stress"
+B1="python3 $R/bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-serving --shard-of 0 --no-extended --no-stress"
+S="python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-mixed --serving-requests 64 --shard-of 0 --no-extended --no-stress"
 C="python3 -m paper_2503_16955_amd.profiling copy --mib 256"
 step() {   # name, time limit (s), command...
     local name=$1 lim=$2; shift 2
