@@ -35,6 +35,7 @@ struct Rec {
     uint32_t *d_counts = nullptr;
     unsigned long long *d_energy = nullptr;
     double *d_tables = nullptr;
+    bool ext = false;              // uses the extended inputs
     mrt_counters counters{};
 };
 
@@ -85,6 +86,8 @@ struct mrt_server {
     std::deque<Round> inflight;
     const void *kernel = nullptr;
     int grid = 0;
+    const void *kernel_ext = nullptr;   // for rounds holding extended-input requests
+    int grid_ext = 0;
     std::chrono::steady_clock::time_point t0;
     mrt_server_stats stats{};
 
@@ -137,6 +140,7 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     P.lut = nl ? r.d_tables : nullptr;
     P.bin_cdf = P.spectrum == MRT_SPECTRUM_TABLE ? r.d_tables + nl : nullptr;
     P.qe = P.qe_n > 0 ? r.d_tables + P.qe_at : nullptr;
+    P.dep = P.dep_n > 0 ? r.d_tables + P.dep_at : nullptr;
     P.dev_counters = S->d_counters + (size_t)slot * mrt::kNumCounters;
     P.records_mode = MRT_RECORDS_NONE;
     P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : 8u;
@@ -220,45 +224,66 @@ void fail_items(mrt_server *S, const std::vector<mrt::serve::Item> &items) {
 // Stage a round in buffer b (lock held): one item per request (the round's
 // pieces of a request are contiguous), chunks of about a quarter of a wave's
 // share of the round in whole waves of rays, as the one-call path sizes them.
+// Stage a round's items in buffer b: the plain requests' items first, then
+// those of requests using the extended inputs, each group with its own
+// prefix sums and chunk size (the groups are traced by two launches, so that
+// every request runs the kernel a separate mrt_trace call would use).
 void stage_round(mrt_server *S, const std::vector<mrt::serve::Item> &items, int b, uint32_t *n_out,
-                 uint64_t *total_out) {
+                 uint64_t *total_out, uint32_t *n_ext_out, uint64_t *total_ext_out) {
     mrt::ServeItem *h = S->h_items[b];
     uint32_t n = 0;
-    uint64_t total = 0;
-    for (const auto &it : items) {
-        mrt::ServeItem *last = n ? &h[n - 1] : nullptr;
-        if (last && last->slot == it.slot && last->first + last->count == it.first) {
-            last->count += it.count;
-        } else {
-            h[n++] = mrt::ServeItem{it.first, it.count, total, it.slot, 0u};
+    uint64_t tot[2] = {0, 0};
+    uint32_t cnt[2] = {0, 0};
+    for (int g = 0; g < 2; ++g) {
+        const uint32_t start = n;
+        for (const auto &it : items) {
+            if ((int)S->recs.at(it.ticket).ext != g) continue;
+            mrt::ServeItem *last = n > start ? &h[n - 1] : nullptr;
+            if (last && last->slot == it.slot && last->first + last->count == it.first) {
+                last->count += it.count;
+            } else {
+                h[n++] = mrt::ServeItem{it.first, it.count, tot[g], it.slot, 0u};
+            }
+            tot[g] += it.count;
         }
-        total += it.count;
+        cnt[g] = n - start;
+        const uint64_t waves = (uint64_t)(g ? S->grid_ext : S->grid) * 4u;
+        uint64_t chunk = (tot[g] / (waves * 4u) + 63u) / 64u * 64u;
+        chunk = std::max<uint64_t>(64u, std::min<uint64_t>(2048u, chunk));
+        for (uint32_t k = start; k < n; ++k) h[k].chunk = (uint32_t)chunk;
     }
-    const uint64_t waves = (uint64_t)S->grid * 4u;
-    uint64_t chunk = (total / (waves * 4u) + 63u) / 64u * 64u;
-    chunk = std::max<uint64_t>(64u, std::min<uint64_t>(2048u, chunk));
-    for (uint32_t i = 0; i < n; ++i) h[i].chunk = (uint32_t)chunk;
     // the chunk cursors follow the items, zeroed by the same copy
     std::memset(h + n, 0, n * sizeof(unsigned long long));
-    *n_out = n;
-    *total_out = total;
+    *n_out = cnt[0];
+    *total_out = tot[0];
+    *n_ext_out = cnt[1];
+    *total_ext_out = tot[1];
 }
 
 // Enqueue a staged round on its stream (lock not held): wait for the latest
 // admission uploads, copy the items and zeroed cursors, launch, then snapshot
 // every slot's counters once the round before it (other) has ended too.
-hipError_t launch_round(mrt_server *S, int b, uint32_t n, uint64_t total, bool wait_setup,
-                        hipEvent_t other) {
+hipError_t launch_round(mrt_server *S, int b, uint32_t n, uint64_t total, uint32_t n_ext,
+                        uint64_t total_ext, bool wait_setup, hipEvent_t other) {
     hipStream_t st = S->streams[b];
+    const uint32_t n_all = n + n_ext;
     hipError_t e = wait_setup ? hipStreamWaitEvent(st, S->ev_setup, 0) : hipSuccess;
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->d_items[b], S->h_items[b],
-                           n * (sizeof(mrt::ServeItem) + sizeof(unsigned long long)),
+                           n_all * (sizeof(mrt::ServeItem) + sizeof(unsigned long long)),
                            hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(S->ev0[b], st);
-    unsigned long long *cursors = (unsigned long long *)(S->d_items[b] + n);
-    void *args[] = {&S->d_slots, &S->d_items[b], &n, &total, &cursors};
-    if (e == hipSuccess) e = hipLaunchKernel(S->kernel, dim3((unsigned)S->grid), dim3(256), args, 0, st);
+    unsigned long long *cursors = (unsigned long long *)(S->d_items[b] + n_all);
+    if (e == hipSuccess && n) {
+        void *args[] = {&S->d_slots, &S->d_items[b], &n, &total, &cursors};
+        e = hipLaunchKernel(S->kernel, dim3((unsigned)S->grid), dim3(256), args, 0, st);
+    }
+    if (e == hipSuccess && n_ext) {
+        mrt::ServeItem *items_ext = S->d_items[b] + n;
+        unsigned long long *cursors_ext = cursors + n;
+        void *args[] = {&S->d_slots, &items_ext, &n_ext, &total_ext, &cursors_ext};
+        e = hipLaunchKernel(S->kernel_ext, dim3((unsigned)S->grid_ext), dim3(256), args, 0, st);
+    }
     if (e == hipSuccess && other) e = hipStreamWaitEvent(st, other, 0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(S->h_counters[b], S->d_counters,
@@ -319,11 +344,11 @@ void engine(mrt_server *S) {
             const int b = S->inflight.empty() ? 0 : 1 - S->inflight.back().buf;
             hipEvent_t other = S->inflight.empty() ? nullptr : S->ev1[S->inflight.back().buf];
             const bool wait_setup = S->setup_recorded;
-            uint32_t n = 0;
-            uint64_t total = 0;
-            stage_round(S, items, b, &n, &total);
+            uint32_t n = 0, n_ext = 0;
+            uint64_t total = 0, total_ext = 0;
+            stage_round(S, items, b, &n, &total, &n_ext, &total_ext);
             lk.unlock();
-            const hipError_t e = launch_round(S, b, n, total, wait_setup, other);
+            const hipError_t e = launch_round(S, b, n, total, n_ext, total_ext, wait_setup, other);
             lk.lock();
             if (e != hipSuccess) {
                 fail_items(S, items);
@@ -387,11 +412,16 @@ mrt_status mrt_server_create(const mrt_server_config *config, mrt_server **out) 
     S->cfg.round_rays = round_rays;
     S->cfg.chunk = chunk;
     S->device = dev;
-    S->kernel = mrt::serve_kernel_ptr(c.precision);
+    S->kernel = mrt::serve_kernel_ptr(c.precision, false);
+    S->kernel_ext = mrt::serve_kernel_ptr(c.precision, true);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->kernel, 256, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     S->grid = per_cu * prop.multiProcessorCount;
+    per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, S->kernel_ext, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    S->grid_ext = per_cu * prop.multiProcessorCount;
     const size_t ms = (size_t)c.max_slots;
     bool ok = hipStreamCreateWithFlags(&S->setup, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreate(&S->ev_ref) == hipSuccess && hipEventCreate(&S->ev_setup) == hipSuccess &&
@@ -427,10 +457,8 @@ mrt_status mrt_server_submit(mrt_server *S, const mrt_request *q, uint64_t *tick
                                   fail);
     if (st != MRT_OK) return st;
     if (q->n_rays == 0) return fail(MRT_EINVAL, "n_rays must be > 0");
-    if (mrt::uses_ext(q->source, q->crystal, q->rocking_curve))
-        return fail(MRT_EINVAL, "energy-dependent rocking curves, source spots, user ray arrays and "
-                                "further reflecting planes are traced by mrt_trace, not served");
     Rec r;
+    r.ext = mrt::uses_ext(q->source, q->crystal, q->rocking_curve);
     mrt::build_params(q->source, q->crystal, q->mosaic, q->rocking_curve, q->detector, r.P,
                       r.tables);
     r.nx = q->detector->nx;

@@ -152,10 +152,11 @@ int launch_zero(void *ptr_u32, size_t n_words, void *stream);
 int launch_calibration_map(const uint32_t *counts, const uint64_t *energy, size_t n, double *map,
                            void *stream);
 constexpr int kMaxQeNodes = 1024;
-// Serving kernel of a precision: (const TraceParams *slots, const ServeItem
-// *items, uint32_t n_items, uint64_t total, unsigned long long *cursors), one
-// zeroed cursor per item.
-const void *serve_kernel_ptr(int precision);
+// Serving kernel of a precision (ext: the instance with the extended
+// inputs): (const TraceParams *slots, const ServeItem *items, uint32_t
+// n_items, uint64_t total, unsigned long long *cursors), one zeroed cursor
+// per item.
+const void *serve_kernel_ptr(int precision, bool ext);
 // Kernel of the paper's event model (FP64) for a geometry (nullptr for an
 // unknown one): (TraceParams), like the trace kernels.
 const void *mwg_kernel_ptr(int geometry, bool records, bool polarised, bool planes);

@@ -504,12 +504,21 @@ class Server:
         self._h = h
         self.precision = precision
 
-    def submit(self, w, n_rays=None, seed=None, max_events=0):
+    def submit(self, w, n_rays=None, seed=None, max_events=0, rays=None):
+        """Queue workload `w`; `rays`: user ray arrays as in trace() (rows for
+        the request's rays [0, n_rays)), written (their stream synchronised)
+        before the call and kept alive by the caller until the request is
+        done; the server reads them from its own stream."""
         S = Structs(w)
+        n = int(w["n_rays"] if n_rays is None else n_rays)
+        if rays:
+            import torch
+            dev = next(iter(rays.values())).device
+            for key, ptr in _user_rays(rays, n, dev).items():
+                setattr(S.source, key, ptr)
         q = MrtRequest(C.pointer(S.source), C.pointer(S.crystal), C.pointer(S.mosaic),
                        C.pointer(S.rocking_curve), C.pointer(S.detector),
-                       int(w["n_rays"] if n_rays is None else n_rays),
-                       int(w["seed"] if seed is None else seed), int(max_events), 0)
+                       n, int(w["seed"] if seed is None else seed), int(max_events), 0)
         t = C.c_uint64()
         _check(self._L.mrt_server_submit(self._h, C.byref(q), C.byref(t)))
         return int(t.value)

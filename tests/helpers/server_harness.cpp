@@ -85,7 +85,7 @@ int launch_zero(void *p, size_t words, void *stream) {
     ((hipStream_t)stream)->push([p, words] { memset(p, 0, words * 4); });
     return 0;
 }
-const void *serve_kernel_ptr(int) { return (const void *)&serve; }
+const void *serve_kernel_ptr(int, bool) { return (const void *)&serve; }
 }  // namespace mrt
 
 extern "C" {

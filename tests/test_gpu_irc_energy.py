@@ -2,7 +2,7 @@
 2.2.1) on the GPU, through the C-ABI: FP64 parity with the oracle on both
 geometries and every curve kind; the FP32-mixed kernel equals the plain one
 with constant tables and agrees with FP64 statistically otherwise; the
-request server refuses such curves."""
+request server serves such curves (its tests sit with the server's)."""
 import copy
 
 import numpy as np
@@ -78,12 +78,6 @@ def test_fp32_mixed_agrees_with_fp64():
     for f in ("reflections", "detected", "exit_reflected"):
         assert abs(a[f] - b[f]) < 5 * np.sqrt(a[f] + b[f]) + 1e-3 * b[f], (f, a[f], b[f])
     assert a["refined"] < 0.01 * a["events"]
-
-
-def test_server_refuses_energy_dependent_curves():
-    with mrt.Server(hbm_budget_bytes=1 << 28, max_slots=2) as srv:
-        with pytest.raises(mrt.MosaicRTError):
-            srv.submit(_dep(W.get("von_hamos_hapg")), n_rays=1000)
 
 
 def test_papers_model_parity():

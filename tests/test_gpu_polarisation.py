@@ -6,7 +6,7 @@ no mosaic spread sigma polarisations give the unpolarised kernel's records
 bit for bit; FP32-mixed agrees with FP64 statistically; the paper's event
 model with polarisation (Eqs. SimpleReflXsectionPol, ReflXsectionPol) in
 parity on both geometries and two more mosaics, and sampled at 1e8 rays;
-the request server refuses the extended inputs."""
+the request server serves them (its tests sit with the server's)."""
 import copy
 
 import numpy as np
@@ -98,16 +98,6 @@ def test_polarisation_fp32_mixed_agrees_with_fp64():
     b = mrt.trace(w, n_rays=n, precision="fp64", rays={"polarisations": pt})["counters"]
     for f in ("reflections", "detected", "exit_reflected"):
         assert abs(a[f] - b[f]) < 5 * np.sqrt(a[f] + b[f]) + 1e-3 * b[f], (f, a[f], b[f])
-
-
-def test_polarisation_refused_by_the_server():
-    import torch
-    with mrt.Server(hbm_budget_bytes=1 << 28, max_slots=2) as srv:
-        w = W.get("von_hamos_hapg")
-        w["source"]["spot"] = dict(kind="disk", u=[1.0, 0.0, 0.0], v=[0.0, 0.97294474, 0.23103794],
-                                   sigma=[0.01, 0.0])
-        with pytest.raises(mrt.MosaicRTError):
-            srv.submit(w, n_rays=1000)
 
 
 def _mwg(w, burn_in=200):

@@ -128,3 +128,57 @@ def test_poisson_arrivals_latency_recorded():
         assert srv.stats()["used_bytes"] == 0
         print(f"[serve] p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms",
               flush=True)
+
+
+def _served_extended_mix():
+    """Plain requests among requests with a Gaussian spot, an energy-dependent
+    curve, further planes and user polarisations (with user energies)."""
+    import torch
+    vh = W.get("von_hamos_hapg")
+    spot = W.with_spot(vh)
+    dep = copy.deepcopy(vh)
+    dep["rocking_curve"]["energy_dependence"] = [(7.8, -30e-6, 0.6), (8.05, 20e-6, 1.5),
+                                                 (8.2, 45e-6, 2.2)]
+    planes = copy.deepcopy(vh)
+    planes["source"]["lines"] = list(planes["source"]["lines"]) + [(2 * 8.048, 0.004, 0.4)]
+    planes["crystal"]["planes"] = {"hbar_ratio": 0.5,
+                                   "extra": [(vh["crystal"]["two_d"] / 2, 0.6, 1.5, 5e-6)]}
+    n_pol = 300_000
+    import oracle
+    _, k, _ = oracle.source_sample(vh, np.arange(n_pol))
+    a = np.random.default_rng(21).normal(size=k.shape)
+    a -= np.sum(a * k, axis=1)[:, None] * k
+    pol = torch.as_tensor(a / np.linalg.norm(a, axis=1)[:, None], device="cuda").contiguous()
+    en = torch.as_tensor(np.random.default_rng(22).uniform(7.95, 8.15, n_pol), device="cuda")
+    torch.cuda.synchronize()
+    return [(vh, 700_000, 3, None), (spot, 900_000, 4, None), (dep, 500_000, 5, None),
+            (W.get("flat_hopg"), 400_000, 6, None), (planes, 800_000, 7, None),
+            (vh, n_pol, 8, {"polarisations": pol, "energies": en}), (spot, 1_100_000, 9, None)]
+
+
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
+def test_extended_inputs_served_equal_alone(precision):
+    """Requests with extended inputs run in the same rounds as plain ones
+    (one launch per group and round) and each gives exactly the images and
+    counters of the same request traced alone."""
+    reqs = _served_extended_mix()
+    with mrt.Server(hbm_budget_bytes=1 << 30, max_slots=16, precision=precision,
+                    round_rays=1 << 18, chunk=2048) as srv:
+        tickets = [srv.submit(w, n_rays=n, seed=s, rays=r) for w, n, s, r in reqs]
+        results = [srv.wait(t, timeout_ms=WAIT_MS) for t in tickets]
+        st = srv.stats()
+        assert st["rounds"] > 3 and st["rays_traced"] == sum(n for _, n, _, _ in reqs)
+        for (w, n, s, rays), res in zip(reqs, results):
+            print(f"[serve-ext] {precision} {w['name']} n={n} rays={bool(rays)}", flush=True)
+            assert res["state"] == "done", res["state"]
+            alone = mrt.trace(w, n_rays=n, seed=s, precision=precision, rays=rays)
+            ac, ae = mrt.image_to_numpy(alone["counts"], alone["energy"])
+            assert np.array_equal(res["counts"].cpu().numpy().view(np.uint32), ac)
+            assert np.array_equal(res["energy"].cpu().numpy().view(np.uint64), ae)
+            for f in ("emitted", "missed", "absorbed", "exit_reflected", "exit_transmitted",
+                      "truncated", "detected", "events", "reflections", "refined"):
+                assert res["counters"][f] == alone["counters"][f], f
+            assert alone["counters"]["reflections"] > 100
+        for t in tickets:
+            srv.release(t)
+        assert srv.stats()["used_bytes"] == 0

@@ -6,7 +6,8 @@ paper's own event model, at oracle sizes with ragged launches and an offset
 first ray id, and sampled at the full 1e8-ray von Hamos size.  Per-ray
 records exact (doubles within 1e-12 relative), images bit-exact except
 counted ties.  The FP32-mixed kernel takes the same source and agrees with
-FP64 statistically; the request server refuses these inputs."""
+FP64 statistically; the request server serves
+them (its tests sit with the server's)."""
 import copy
 
 import numpy as np
@@ -106,12 +107,6 @@ def test_user_rays_fp32_mixed_agree_with_fp64():
     b = mrt.trace(w, n_rays=n, precision="fp64", rays=dict(energies=e))["counters"]
     for f in ("reflections", "detected", "exit_reflected"):
         assert abs(a[f] - b[f]) < 5 * np.sqrt(a[f] + b[f]) + 1e-3 * b[f], (f, a[f], b[f])
-
-
-def test_server_refuses_spots_and_user_rays():
-    with mrt.Server(hbm_budget_bytes=1 << 28, max_slots=2) as srv:
-        with pytest.raises(mrt.MosaicRTError):
-            srv.submit(W.with_spot(W.get("von_hamos_hapg")), n_rays=1000)
 
 
 def _sampled_check(w, g, n, ids, rays_host=None):

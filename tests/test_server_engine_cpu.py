@@ -142,6 +142,39 @@ def test_every_ray_of_every_request_exactly_once(lib):
     assert lib.harness_free_bytes() == DEVICE_BYTES      # everything returned
 
 
+def test_mixed_plain_and_extended_requests_each_ray_once(lib):
+    """Requests using extended inputs (here a source spot) share rounds with
+    plain ones: the round is staged as two item groups traced by two
+    launches, and still every ray of every request is traced exactly once."""
+    lib.harness_init(DEVICE_BYTES, 0)
+    plain = W.get("flat_hopg")
+    spot = W.with_spot(W.get("flat_hopg"))
+    px = plain["detector"]["nx"] * plain["detector"]["ny"]
+    reqs = [(plain, 3000, 21), (spot, 5000, 22), (plain, 777, 23), (spot, 64, 24), (spot, 20_001, 25)]
+    s = Srv(lib)
+    try:
+        tickets = []
+        for w, n, seed in reqs:
+            st, t = s.submit(w, n, seed)
+            assert st == 0
+            tickets.append(t)
+        for t, (w, n, seed) in zip(tickets, reqs):
+            st, r = s.wait(t)
+            assert st == 0 and r.state == mrt.REQ_DONE, (st, r.state)
+            c, e = _images(r)
+            ec, ee, cnt = expected(n, seed, px)
+            assert np.array_equal(c, ec) and np.array_equal(e, ee)
+            for k, v in cnt.items():
+                assert getattr(r.counters, k) == v, k
+        st = s.stats()
+        assert st.rays_traced == sum(n for _, n, _ in reqs)
+        # some rounds held both groups, so there were more launches than rounds
+        assert lib.harness_launches() > st.rounds
+    finally:
+        s.destroy()
+    assert lib.harness_free_bytes() == DEVICE_BYTES
+
+
 def test_failed_launch_fails_its_round_only(lib):
     lib.harness_init(DEVICE_BYTES, 1)
     w = W.get("flat_hopg")
