@@ -296,6 +296,14 @@ def alloc_images(w, device="cuda", energy=True):
     return counts, en
 
 
+def uses_extended_inputs(w, rays=None):
+    """Whether workload `w` (with user ray arrays `rays`) runs the
+    extended-input kernels: a source spot, user arrays, an energy-dependent
+    curve or further planes."""
+    return bool(rays) or (w["source"].get("spot") or {}).get("kind", "point") != "point" \
+        or bool(w["rocking_curve"].get("energy_dependence")) or w["crystal"].get("planes") is not None
+
+
 def _user_rays(rays, n, device):
     """Device pointers of the user ray arrays (float64, contiguous, rows for
     the n rays of the call): origins (n, 3), directions (n, 3), energies (n,)."""
