@@ -1,6 +1,7 @@
 #!/bin/bash
 # rocprofv3 runs behind profiles/: the kernel trace of the benchmark's trace
-# kernels, the kernel trace of a serving run, HBM byte counters of the trace
+# kernels, the kernel trace of a serving run, that of the extended-input
+# kernels, HBM byte counters of the trace
 # kernels and of a plain 256 MiB copy (the scale reference), and SQ
 # instruction counters.  Each pass is a run of its own (counters are not
 # multiplexed).  Usage: profile_kernels.sh OUT_DIR   (run from anywhere)
@@ -12,6 +13,7 @@ cd /tmp
 B="python3 $R/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-serving --shard-of 0 --no-extended --no-stress"
 B1="python3 $R/bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-serving --shard-of 0 --no-extended --no-stress"
 S="python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-mixed --serving-requests 64 --shard-of 0 --no-extended --no-stress"
+E="python3 $R/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-serving --no-mwg --shard-of 0 --no-stress"
 C="python3 -m paper_2503_16955_amd.profiling copy --mib 256"
 step() {   # name, time limit (s), command...
     local name=$1 lim=$2; shift 2
@@ -24,6 +26,7 @@ step() {   # name, time limit (s), command...
 }
 step trace 240 rocprofv3 --kernel-trace --stats --output-format csv -d "$OUT/prof_trace" -o trace -- $B
 step serve 240 rocprofv3 --kernel-trace --stats --output-format csv -d "$OUT/prof_serve" -o serve -- $S
+step ext 240 rocprofv3 --kernel-trace --stats --output-format csv -d "$OUT/prof_ext" -o ext -- $E
 step fetch 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d "$OUT/prof_fetch" -o fetch -- $B1
 step write 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d "$OUT/prof_write" -o write -- $B1
 step cfetch 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d "$OUT/prof_cfetch" -o cfetch -- $C
