@@ -137,6 +137,15 @@ void serve_body(const TraceParams *slots, const ServeItem *items, uint32_t n, ui
                                                     *(RayQueue<R, false> *)queue);
 }
 
+// The extended serving kernel's body (spots, user arrays and polarisations,
+// energy-dependent curves, further planes).
+template <class R>
+void serve_body_ext(const TraceParams *slots, const ServeItem *items, uint32_t n, uint64_t total,
+                    unsigned long long *cursors, uint32_t wave, uint32_t n_waves, void *queue) {
+    using T = Tracer<R, kAny, kAny, kAny, false, true>;
+    serve_waves<T>(slots, items, n, total, cursors, wave, n_waves, *(typename T::Queue *)queue);
+}
+
 template <class R, bool REC, bool EXT = false>
 void trace_body(const TraceParams &P, void *queue) {
     using T = Tracer<R, kAny, kAny, kAny, REC, EXT>;
@@ -240,20 +249,39 @@ void emu_set_records(TraceParams *P, mrt_hit_record *records, uint64_t cap) {
     P->rec_cap = cap;
 }
 
+int emu_serve_group(const TraceParams *slots, const ServeItem *items, uint32_t n, int n_waves,
+                    int precision, long long max_meetings, bool ext);
+
 // Run the serving kernel body with n_waves waves (one after another) over a
 // round's items; 0 on success.
 int emu_serve(const TraceParams *slots, const ServeItem *items, uint32_t n, int n_waves,
               int precision, long long max_meetings) {
+    return emu_serve_group(slots, items, n, n_waves, precision, max_meetings, false);
+}
+
+// The same with the extended serving kernel's body.
+int emu_serve_ext(const TraceParams *slots, const ServeItem *items, uint32_t n, int n_waves,
+                  int precision, long long max_meetings) {
+    return emu_serve_group(slots, items, n, n_waves, precision, max_meetings, true);
+}
+
+int emu_serve_group(const TraceParams *slots, const ServeItem *items, uint32_t n, int n_waves,
+                    int precision, long long max_meetings, bool ext) {
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; ++i) total += items[i].count;
     std::vector<unsigned long long> cursors(n ? n : 1, 0ull);
     for (int w = 0; w < n_waves; ++w) {
         QueueMem q;
         int e = run_wave([&] {
-            if (precision == MRT_FP64)
-                serve_body<double>(slots, items, n, total, cursors.data(), (uint32_t)w, (uint32_t)n_waves, q.b);
+            const uint32_t wv = (uint32_t)w, nw = (uint32_t)n_waves;
+            if (ext && precision == MRT_FP64)
+                serve_body_ext<double>(slots, items, n, total, cursors.data(), wv, nw, q.b);
+            else if (ext)
+                serve_body_ext<float>(slots, items, n, total, cursors.data(), wv, nw, q.b);
+            else if (precision == MRT_FP64)
+                serve_body<double>(slots, items, n, total, cursors.data(), wv, nw, q.b);
             else
-                serve_body<float>(slots, items, n, total, cursors.data(), (uint32_t)w, (uint32_t)n_waves, q.b);
+                serve_body<float>(slots, items, n, total, cursors.data(), wv, nw, q.b);
         }, max_meetings);
         if (e) return e;
     }

@@ -58,6 +58,7 @@ def emu(tmp_path_factory):
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32]
     L.emu_trace.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_longlong]
     L.emu_serve.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int, C.c_int, C.c_longlong]
+    L.emu_serve_ext.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int, C.c_int, C.c_longlong]
     L.emu_build_mwg.argtypes = [C.c_void_p] * 3 + [C.c_int] * 3 + [C.c_void_p, C.c_void_p, C.c_int,
                                                                    C.c_int]
     L.emu_trace_mwg.argtypes = [C.c_void_p, C.c_int, C.c_longlong]
@@ -397,3 +398,51 @@ def test_polarisation_loop(emu, case):
         c = j.counters()
         for f in ("reflections", "absorbed"):
             assert abs(c[f] - o[f]) < 5 * np.sqrt(c[f] + o[f]) + 5, (f, c[f], o[f])
+
+
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
+def test_served_extended_requests_equal_requests_alone(emu, precision):
+    """The extended serving loop (a spot, an energy-dependent curve, further
+    planes, user polarisations) over a round of interleaved half ranges
+    gives each request the images and counters of its one-call trace."""
+    import copy
+    import oracle
+    from paper_2503_16955_amd import workloads as W
+    prec = mrt.PRECISION[precision]
+    vh = W.get("von_hamos_hapg")
+    dep = copy.deepcopy(vh)
+    dep["rocking_curve"]["energy_dependence"] = [(7.8, -30e-6, 0.6), (8.2, 45e-6, 2.2)]
+    planes = copy.deepcopy(vh)
+    planes["crystal"]["planes"] = {"hbar_ratio": 0.5,
+                                   "extra": [(vh["crystal"]["two_d"] / 2, 0.6, 1.5, 5e-6)]}
+    n_pol = 2500
+    _, k, _ = oracle.source_sample(vh, np.arange(n_pol))
+    a = np.random.default_rng(3).normal(size=k.shape)
+    a -= np.sum(a * k, axis=1)[:, None] * k
+    pol = {"polarisations": a / np.linalg.norm(a, axis=1)[:, None]}
+    jobs = [(W.with_spot(vh), 3000, 5, None), (dep, 2500, 6, None), (planes, 3000, 7, None),
+            (vh, n_pol, 8, pol)]
+    alone = []
+    for w, n, s, r in jobs:
+        j = Job(emu, w, n, s, rays=r)
+        assert emu.emu_trace(j.P, WAVES, prec, MAX_MEETINGS) == 0, w["name"]
+        alone.append(j)
+    served = [Job(emu, w, n, s, rays=r) for w, n, s, r in jobs]
+    ps = len(served[0].P)
+    slots = (C.c_char * (ps * len(served)))()
+    for i, j in enumerate(served):
+        C.memmove(C.addressof(slots) + i * ps, j.P, ps)
+    items = [(0, j.n // 2, i) for i, j in enumerate(served)]
+    items += [(j.n // 2, j.n - j.n // 2, i) for i, j in enumerate(served)]
+    it = np.zeros(len(items), dtype=[("first", "<u8"), ("count", "<u8"), ("start", "<u8"),
+                                     ("slot", "<i4"), ("chunk", "<u4")])
+    start = 0
+    for q, (f, c, i) in enumerate(items):
+        it[q] = (f, c, start, i, 64 * (1 + q % 4))
+        start += c
+    assert emu.emu_serve_ext(slots, it.ctypes.data, len(it), 3 * WAVES, prec, MAX_MEETINGS) == 0
+    for a, b, (w, n, s, r) in zip(alone, served, jobs):
+        assert np.array_equal(a.counts, b.counts), (w["name"], n)
+        assert np.array_equal(a.energy, b.energy), (w["name"], n)
+        assert a.counters() == b.counters(), (w["name"], n)
+        assert a.counters()["reflections"] > 0, w["name"]
