@@ -14,6 +14,11 @@ SOURCES = ["trace_f64_flat.hip", "trace_f64_cyl.hip", "trace_f32_flat.hip", "tra
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+         # multiply-adds fuse only within one source expression, never
+         # across statements: every kernel instance that inlines the same
+         # code then rounds it the same way, so FP32-mixed results do not
+         # depend on which instance (one-call, extended, serving) traced them
+         "-ffp-contract=on",
          # no packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          # keep loop-invariant constants out of registers: hoisting them out

@@ -129,6 +129,8 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     if (opt.grid_blocks < 0) return fail(MRT_EINVAL, "options: grid_blocks must be >= 0");
     if (opt.refill_idle < 0 || opt.refill_idle > 64)
         return fail(MRT_EINVAL, "options: refill_idle must lie in [0, 64]");
+    if (opt.exact_decisions != 0 && opt.exact_decisions != 1)
+        return fail(MRT_EINVAL, "options: exact_decisions must be 0 or 1");
     const bool mwg = opt.event_model == MRT_MODEL_MWG;
     if (opt.event_model != MRT_MODEL_STEPPING && !mwg) return fail(MRT_EINVAL, "options: unknown event model");
     if (!mwg && opt.mwg_irc_off != 0) return fail(MRT_EINVAL, "options: mwg_irc_off needs the MWG event model");
@@ -141,6 +143,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
         if (opt.mwg_batch < 0 || opt.mwg_batch > 64) return fail(MRT_EINVAL, "options: mwg_batch must lie in [0, 64]");
         if (opt.max_events > 0x7fffffffu) return fail(MRT_EINVAL, "options: the MWG event model needs max_events < 2^31");
         if (opt.mwg_irc_off != 0 && opt.mwg_irc_off != 1) return fail(MRT_EINVAL, "options: mwg_irc_off must be 0 or 1");
+        if (opt.exact_decisions) return fail(MRT_EINVAL, "options: exact_decisions applies to the stepping model");
     }
 
     int dev = 0, cus = 0;
@@ -163,6 +166,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     P.key1 = (uint32_t)(seed >> 32);
     P.max_events = opt.max_events ? opt.max_events : (1u << 20);
     P.records_mode = opt.records_mode;
+    P.exact = opt.exact_decisions ? 1u : 0u;
     P.rec_cap = records_capacity;
     P.counts = d_counts;
     P.energy = (unsigned long long *)d_energy_mev;
@@ -211,7 +215,7 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     const bool rec = opt.records_mode != MRT_RECORDS_NONE;
     const void *kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec, source->polarisations != nullptr,
                                                    crystal->planes != nullptr || rocking_curve->n_dep > 0)
-                         : mrt::uses_ext(source, crystal, rocking_curve)
+                         : mrt::uses_ext(source, crystal, rocking_curve) || opt.exact_decisions
                              ? mrt::ext_kernel_ptr(opt.precision, rec)
                              : mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
                                                      rocking_curve->kind, rec);

@@ -415,11 +415,11 @@ struct Tracer {
             return __builtin_amdgcn_exp2f(-P.f32.g_k_log2e * a2);
         } else if (irc_is(P, MRT_IRC_PSEUDO_VOIGT)) {
             const float h2 = P.f32.pv_h2;
-            return P.f32.pv_a * h2 * __builtin_amdgcn_rcpf(h2 + a2) +
+            return P.f32.pv_a * h2 * __builtin_amdgcn_rcpf(__builtin_fmaf(a, a, h2)) +
                    P.f32.pv_b * __builtin_amdgcn_exp2f(-P.f32.g_k_log2e * a2);
         } else {
             const float h2 = P.f32.lor_h2;
-            return h2 * __builtin_amdgcn_rcpf(h2 + a2);
+            return h2 * __builtin_amdgcn_rcpf(__builtin_fmaf(a, a, h2));
         }
     }
     // Bounds of x (lo, hi of |x|; slo, shi of x) from the FP32 estimate;
@@ -477,6 +477,9 @@ struct Tracer {
     static __device__ __forceinline__ int filter(const TraceParams &P, double akn, float saf,
                                                  float caf, float u_acc, float shift,
                                                  float inv_s) {
+        if constexpr (EXT) {
+            if (P.exact) return -1;   // every decision by the FP64 evaluation
+        }
         float lo, hi, slo, shi;
         if (!x_bounds(akn, saf, caf, shift, inv_s, lo, hi, slo, shi)) return -1;
         if (irc_is(P, MRT_IRC_TABLE)) {
@@ -502,6 +505,13 @@ struct Tracer {
                                                         float inv_s, float &r_lo, float &r_hi) {
         r_lo = 0.0f;
         r_hi = 1.0f;
+        if constexpr (EXT) {
+            // no bound: a plane sum is then always evaluated exactly
+            if (P.exact) {
+                r_hi = INFINITY;
+                return;
+            }
+        }
         float lo, hi, slo, shi;
         if (!x_bounds(akn, saf, caf, shift, inv_s, lo, hi, slo, shi)) return;
         if (irc_is(P, MRT_IRC_TABLE)) {

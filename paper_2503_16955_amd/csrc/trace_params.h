@@ -116,6 +116,8 @@ struct TraceParams {
     uint32_t chunk;               // ray ids a wave claims at a time
     uint32_t refill_idle;         // refill a wave once this many lanes are idle
     int32_t records_mode;
+    uint32_t exact;               // every acceptance decision in FP64 (extended kernels)
+    uint32_t pad_run;
     uint64_t rec_cap;
     uint32_t *counts;
     unsigned long long *energy;

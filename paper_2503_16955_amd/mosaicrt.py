@@ -99,7 +99,7 @@ class MrtOptions(C.Structure):
                 ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
                 ("refill_idle", C.c_int32), ("event_model", C.c_int32),
                 ("mwg_burn_in", C.c_int32), ("psi_nodes", C.c_int32), ("mwg_batch", C.c_int32),
-                ("mwg_irc_off", C.c_int32)]
+                ("mwg_irc_off", C.c_int32), ("exact_decisions", C.c_int32), ("reserved_", C.c_int32)]
 
 
 MODEL = {"stepping": 0, "mwg": 1}
@@ -329,7 +329,7 @@ def _user_rays(rays, n, device):
 def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_events=0,
           accumulate=False, counts=None, energy=None, want_energy=True, record_buf=None,
           grid_blocks=0, block_threads=0, refill_idle=0, mwg_batch=0, rays=None, stream=None,
-          sync=True):
+          sync=True, exact_decisions=False):
     """Trace rays [first, first + n_rays) of workload `w` with ``mrt_trace``.
 
     counts / energy: torch device tensors to fill (allocated when None).
@@ -337,7 +337,9 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
     ``origins`` (n, 3; global mm), ``directions`` (n, 3; unit) and
     ``energies`` (n,; keV), row i for ray first + i; each one given replaces
     the sampled field; ``polarisations`` (n, 3; unit, normal to the
-    direction) turns on polarisation tracking.  records: None, "all" or "detected".  The event model comes from
+    direction) turns on polarisation tracking.  records: None, "all" or "detected".
+    exact_decisions=True takes every acceptance decision in FP64 (no FP32
+    bound; same results, slower).  The event model comes from
     w["event_model"] (see model_options).  sync=True waits for the stream and
     returns the counters (and the kernel time); sync=False enqueues only.
     Returns a dict with ``counts``, ``energy``, ``records`` (uint8 device
@@ -364,7 +366,8 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
     opt = MrtOptions(precision=prec, records_mode=mode, max_events=int(max_events),
                      accumulate=1 if accumulate else 0, grid_blocks=int(grid_blocks),
                      block_threads=int(block_threads), refill_idle=int(refill_idle),
-                     mwg_batch=int(mwg_batch), **model_options(w))
+                     mwg_batch=int(mwg_batch), exact_decisions=1 if exact_decisions else 0,
+                     **model_options(w))
     cnt = MrtCounters()
     if stream is None:
         stream = torch.cuda.current_stream(counts.device)

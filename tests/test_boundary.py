@@ -48,7 +48,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(mrt.MrtMosaic) == 24
     assert C.sizeof(mrt.MrtRockingCurve) == 104
     assert C.sizeof(mrt.MrtDetector) == 136
-    assert C.sizeof(mrt.MrtOptions) == 48
+    assert C.sizeof(mrt.MrtOptions) == 56
     assert C.sizeof(mrt.MrtCounters) == 96
     assert mrt.RECORD_DTYPE.itemsize == 104
 

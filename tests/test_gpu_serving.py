@@ -159,11 +159,11 @@ def _served_extended_mix():
 @pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
 def test_extended_inputs_served_equal_alone(precision):
     """Requests with extended inputs run in the same rounds as plain ones
-    (one launch per group and round).  In FP64 and for the plain requests
-    each gives exactly the images and counters of the same request traced
-    alone.  The FP32-mixed extended kernels of the server and of a separate
-    call are separate compilations whose FP32 geometry may round apart on a
-    ray: there at most 1e-5 of the rays (and 4) may land elsewhere."""
+    (one launch per group and round).  Each gives exactly the images and
+    counters of the same request traced alone, in both precisions: the
+    serving and one-call kernels are separate compilations of the same
+    loop, and with multiply-adds fused only inside a source expression they
+    round every FP32 operation alike."""
     reqs = _served_extended_mix()
     fields = ("emitted", "missed", "absorbed", "exit_reflected", "exit_transmitted",
               "truncated", "detected", "events", "reflections", "refined")
@@ -179,16 +179,13 @@ def test_extended_inputs_served_equal_alone(precision):
             ac, ae = mrt.image_to_numpy(alone["counts"], alone["energy"])
             c = res["counts"].cpu().numpy().view(np.uint32)
             e = res["energy"].cpu().numpy().view(np.uint64)
-            exact = precision == "fp64" or not mrt.uses_extended_inputs(w, rays)
             n_px = int(np.sum((c != ac) | (e != ae)))
             print(f"[serve-ext] {precision} {w['name']} n={n} rays={bool(rays)} "
                   f"pixels apart {n_px}", flush=True)
-            allow = 0 if exact else max(4, int(1e-5 * n))
-            assert n_px <= 2 * allow
+            assert n_px == 0
             for f in fields:
-                a, b = res["counters"][f], alone["counters"][f]
-                tol = 0 if exact else (allow * 64 if f == "events" else allow)
-                assert abs(a - b) <= tol, (f, a, b)
+                assert res["counters"][f] == alone["counters"][f], (f, res["counters"][f],
+                                                                    alone["counters"][f])
             assert alone["counters"]["reflections"] > 100
         for t in tickets:
             srv.release(t)
