@@ -168,13 +168,8 @@ def load():
     # the library does, so loading the library first would put a second HIP
     # runtime in the process, and torch's would then find no GPU.
     import torch  # noqa: F401
-    L = C.CDLL(LIB_PATH)
+    L = _declare_trace(C.CDLL(LIB_PATH))
     P = C.POINTER
-    L.mrt_trace.restype = C.c_int
-    L.mrt_trace.argtypes = [P(MrtSource), P(MrtCrystal), P(MrtMosaic), P(MrtRockingCurve),
-                            P(MrtDetector), C.c_uint64, C.c_uint64, C.c_uint64, P(MrtOptions),
-                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, P(MrtCounters),
-                            C.c_void_p]
     L.mrt_get_device_info.restype = C.c_int
     L.mrt_get_device_info.argtypes = [P(MrtDeviceInfo)]
     L.mrt_last_error.restype = C.c_char_p
@@ -184,6 +179,19 @@ def load():
     L.mrt_calibration_map.restype = C.c_int
     L.mrt_calibration_map.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]
     _lib = L
+    return L
+
+
+def _declare_trace(L):
+    """Signatures of the trace entry points of library `L`."""
+    P = C.POINTER
+    L.mrt_trace.restype = C.c_int
+    L.mrt_trace.argtypes = [P(MrtSource), P(MrtCrystal), P(MrtMosaic), P(MrtRockingCurve),
+                            P(MrtDetector), C.c_uint64, C.c_uint64, C.c_uint64, P(MrtOptions),
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, P(MrtCounters),
+                            C.c_void_p]
+    L.mrt_last_error.restype = C.c_char_p
+    L.mrt_last_error.argtypes = []
     return L
 
 

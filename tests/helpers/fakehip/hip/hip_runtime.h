@@ -23,16 +23,40 @@
 #include <thread>
 
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorLaunchFailure = 719 };
+enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorNotReady = 600, hipErrorLaunchFailure = 719 };
 enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
 #define hipStreamNonBlocking 1
+#define hipEventDisableTiming 2
+#define hipHostMallocDefault 0
 struct dim3 {
     unsigned x, y, z;
     dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
 struct hipDeviceProp_t {
     int multiProcessorCount;
+    int clockRate;
+    size_t sharedMemPerBlock;
+    char name[256];
+    char gcnArchName[256];
 };
+inline const char *hipGetErrorString(hipError_t e) { return e ? "fake HIP error" : "no error"; }
+inline hipError_t hipGetLastError() { return hipSuccess; }
+
+// Device variables are host memory here; the symbol's address is the
+// variable's own.
+#define __device__
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) {
+    *p = const_cast<void *>(sym);
+    return hipSuccess;
+}
+
+// What the library under test did: host waits for a stream or an event,
+// device allocations, pinned host allocations.
+inline std::atomic<long> fake_host_waits{0};
+inline std::atomic<long> fake_device_allocs{0};
+inline std::atomic<long> fake_pinned_allocs{0};
 
 struct ihipStream_t {
     std::mutex mu;
@@ -103,6 +127,7 @@ inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, const voi
     return hipSuccess;
 }
 inline hipError_t fake_alloc(void **p, size_t bytes) {
+    fake_device_allocs.fetch_add(1);
     if (fake_alloc_budget.fetch_sub((long)bytes) < (long)bytes) {
         fake_alloc_budget.fetch_add((long)bytes);
         *p = nullptr;
@@ -126,7 +151,11 @@ inline hipError_t hipFreeAsync(void *p, hipStream_t s) {
     s->push([p] { fake_free(p); });
     return hipSuccess;
 }
-inline hipError_t hipHostMalloc(void **p, size_t b, unsigned) { *p = calloc(1, b); return hipSuccess; }
+inline hipError_t hipHostMalloc(void **p, size_t b, unsigned) {
+    fake_pinned_allocs.fetch_add(1);
+    *p = calloc(1, b);
+    return hipSuccess;
+}
 inline hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
 inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t st) {
     st->push([d, s, n] { memcpy(d, s, n); });
@@ -142,6 +171,7 @@ inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
 }
 inline hipError_t hipStreamDestroy(hipStream_t s) { delete s; return hipSuccess; }
 inline hipError_t hipEventCreate(hipEvent_t *e) { *e = new ihipEvent_t(); return hipSuccess; }
+inline hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { return hipEventCreate(e); }
 inline hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
     uint64_t gen;
@@ -160,7 +190,12 @@ inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
     });
     return hipSuccess;
 }
+inline hipError_t hipEventQuery(hipEvent_t e) {
+    std::lock_guard<std::mutex> lk(e->mu);
+    return e->reached >= e->recorded ? hipSuccess : hipErrorNotReady;
+}
 inline hipError_t hipEventSynchronize(hipEvent_t e) {
+    fake_host_waits.fetch_add(1);
     std::unique_lock<std::mutex> lk(e->mu);
     const uint64_t want = e->recorded;
     e->cv.wait(lk, [&] { return e->reached >= want; });
@@ -183,7 +218,7 @@ inline hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
 inline hipError_t hipStreamSynchronize(hipStream_t s) {
     ihipEvent_t e;
     hipEventRecord(&e, s);
-    return hipEventSynchronize(&e);
+    return hipEventSynchronize(&e);   // counted there
 }
 inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
     std::lock_guard<std::mutex> la(a->mu);
