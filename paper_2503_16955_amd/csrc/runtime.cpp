@@ -263,6 +263,33 @@ mrt_status enqueue(Launch &L, hipStream_t stream, mrt_counters *h_counters, bool
     return MRT_OK;
 }
 
+// ---- scratch of the entry point that allocates nothing --------------------
+// Counters, chunk cursor and tables of mrt_trace_noalloc: one copy of this
+// array per device, held until the process ends.  In host code the name
+// `scratch` only identifies the symbol; its device address, which differs
+// per device, comes from hipGetSymbolAddress (once per device, with that
+// device current) and is the only way host code refers to its memory.
+constexpr size_t kNoAllocScratchBytes = 128 * 1024;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices];
+
+mrt_status noalloc_scratch(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(MRT_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(MRT_EDEVICE, "hipGetSymbolAddress(scratch) gave NULL");
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return MRT_OK;
+}
+
 // ---- pinned staging of host tables ---------------------------------------
 // A call's tables go to the device by an asynchronous copy from pinned host
 // memory owned by the library; an event recorded after the copy on the
@@ -394,6 +421,36 @@ mrt_status mrt_trace(const mrt_source *source, const mrt_crystal *crystal,
     st = enqueue(L, stream, h_counters, true);
     release(MRT_OK);
     return st;
+}
+
+mrt_status mrt_trace_noalloc(const mrt_source *source, const mrt_crystal *crystal,
+                             const mrt_mosaic *mosaic, const mrt_rocking_curve *rocking_curve,
+                             const mrt_detector *detector, uint64_t first_ray_id, uint64_t n_rays,
+                             uint64_t seed, const mrt_options *options, uint32_t *d_counts,
+                             uint64_t *d_energy_mev, mrt_hit_record *d_records,
+                             uint64_t records_capacity, mrt_counters *h_counters,
+                             void *hip_stream) {
+    mrt::clear_error();
+    Launch L;
+    mrt_status st = prepare(source, crystal, mosaic, rocking_curve, detector, first_ray_id, n_rays,
+                            seed, options, d_counts, d_energy_mev, d_records, records_capacity, L);
+    if (st != MRT_OK) return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const size_t bytes = scratch_bytes(L);
+    if (bytes > kNoAllocScratchBytes)
+        return fail(MRT_ECAPACITY, "counters and tables need %zu bytes, the static scratch holds %zu",
+                    bytes, kNoAllocScratchBytes);
+    void *ptr = nullptr;
+    if ((st = noalloc_scratch(L.dev, &ptr)) != MRT_OK) return st;
+    bind_scratch(L, ptr);
+    if (!L.tables.empty()) {
+        // from the (pageable) host vector, which dies with this call
+        hipError_t e = hipMemcpyAsync(L.dtab, L.tables.data(), L.tables.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "table upload");
+    }
+    return enqueue(L, stream, h_counters, false);
 }
 
 }  // extern "C"

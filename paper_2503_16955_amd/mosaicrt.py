@@ -141,7 +141,7 @@ RECORD_BYTES = 104
 assert RECORD_DTYPE.itemsize == RECORD_BYTES
 
 # Every symbol the header declares.
-EXPORTS = ("mrt_trace", "mrt_get_device_info", "mrt_last_error", "mrt_version",
+EXPORTS = ("mrt_trace", "mrt_trace_noalloc", "mrt_get_device_info", "mrt_last_error", "mrt_version",
            "mrt_calibration_map")
 
 
@@ -190,6 +190,9 @@ def _declare_trace(L):
                             P(MrtDetector), C.c_uint64, C.c_uint64, C.c_uint64, P(MrtOptions),
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, P(MrtCounters),
                             C.c_void_p]
+    if hasattr(L, "mrt_trace_noalloc"):
+        L.mrt_trace_noalloc.restype = C.c_int
+        L.mrt_trace_noalloc.argtypes = L.mrt_trace.argtypes
     L.mrt_last_error.restype = C.c_char_p
     L.mrt_last_error.argtypes = []
     return L
@@ -337,7 +340,7 @@ def _user_rays(rays, n, device):
 def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_events=0,
           accumulate=False, counts=None, energy=None, want_energy=True, record_buf=None,
           grid_blocks=0, block_threads=0, refill_idle=0, mwg_batch=0, rays=None, stream=None,
-          sync=True, exact_decisions=False):
+          sync=True, exact_decisions=False, noalloc=False):
     """Trace rays [first, first + n_rays) of workload `w` with ``mrt_trace``.
 
     counts / energy: torch device tensors to fill (allocated when None).
@@ -347,7 +350,8 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
     the sampled field; ``polarisations`` (n, 3; unit, normal to the
     direction) turns on polarisation tracking.  records: None, "all" or "detected".
     exact_decisions=True takes every acceptance decision in FP64 (no FP32
-    bound; same results, slower).  The event model comes from
+    bound; same results, slower).  noalloc=True calls ``mrt_trace_noalloc``
+    (static device scratch; no allocation by the library).  The event model comes from
     w["event_model"] (see model_options).  sync=True waits for the stream and
     returns the counters (and the kernel time); sync=False enqueues only.
     Returns a dict with ``counts``, ``energy``, ``records`` (uint8 device
@@ -379,7 +383,8 @@ def trace(w, n_rays=None, first=0, seed=None, precision=None, records=None, max_
     cnt = MrtCounters()
     if stream is None:
         stream = torch.cuda.current_stream(counts.device)
-    st = L.mrt_trace(*S.refs(), int(first), n, seed, C.byref(opt),
+    entry = L.mrt_trace_noalloc if noalloc else L.mrt_trace
+    st = entry(*S.refs(), int(first), n, seed, C.byref(opt),
                      C.c_void_p(counts.data_ptr()),
                      C.c_void_p(energy.data_ptr()) if energy is not None else None,
                      C.c_void_p(rec.data_ptr()) if rec is not None else None, cap,

@@ -154,3 +154,30 @@ def test_counters_make_the_call_wait(lib):
     # the fake kernel adds n to `events` and the table size to `detected`
     assert cnt.events == 1234 and cnt.detected == len(c.lut) + len(c.w["source"]["bin_weights"]) + 1
     assert cnt.emitted == 1234
+
+
+def test_noalloc_entry_allocates_nothing(lib):
+    """mrt_trace_noalloc takes its counters, cursor and tables from the
+    static scratch array: no device or pinned allocation in any call, the
+    same scratch for every call, and each kernel reads its own call's
+    tables (the second call's smaller table over the first's)."""
+    L = lib
+    s = L.harness_stream()
+    big, small = Call(_small_stress(), n=2000), Call(_small_stress(n_table=900), n=500)
+    runs0 = L.harness_runs()
+    _, dev0, pinned0 = _counts(L)
+    for c in (big, small):
+        cnt = mrt.MrtCounters()
+        assert c.run(L, s, cnt, entry="mrt_trace_noalloc") == 0, L.mrt_last_error()
+        n_tab = len(c.lut) + len(c.w["source"]["bin_weights"]) + 1
+        # counters start from zero in each call (the scratch keeps the last)
+        assert cnt.events == c.n and cnt.detected == n_tab and cnt.kernel_ms == 0.0
+        c.scribble()
+    # and without counters: no wait, nothing allocated either
+    assert Call(_small_stress(n_table=900), n=300).run(L, s, None, entry="mrt_trace_noalloc") == 0
+    L.harness_sync(s)
+    _, dev1, pinned1 = _counts(L)
+    assert (dev1, pinned1) == (dev0, pinned0)
+    assert L.harness_runs() == runs0 + 3
+    for i, c in ((runs0, big), (runs0 + 1, small)):
+        assert np.array_equal(_seen(L, i)[:len(c.lut)], c.lut)
