@@ -27,6 +27,12 @@
 #include "device_math.h"
 #include "trace_params.h"
 
+// Bounds assertions of the loop's indices: compiled out for the device; the
+// CPU emulation of the kernels defines it to check every index it computes.
+#ifndef MRT_DEV_CHECK
+#define MRT_DEV_CHECK(cond) ((void)0)
+#endif
+
 namespace mrt {
 namespace tk {
 
@@ -148,9 +154,11 @@ struct RayQueue : QueueEntry<R, REC>, QueuePol<R, POL> {
         }
     }
     __device__ __forceinline__ void put(uint32_t i, RayT &r) {
+        MRT_DEV_CHECK(i < kQueue);
         fields(r, [&](auto *a, auto &v) { a[i] = v; });
     }
     __device__ __forceinline__ void take(uint32_t i, RayT &r) {
+        MRT_DEV_CHECK(i < kQueue);
         fields(r, [&](auto *a, auto &v) { v = a[i]; });
     }
     // After a batch: lanes with `parked` set take back their ray from slot
@@ -160,6 +168,7 @@ struct RayQueue : QueueEntry<R, REC>, QueuePol<R, POL> {
     // candidate at a time.
     __device__ __forceinline__ void unpark(uint32_t lane, bool parked, bool queue, uint32_t rank,
                                            RayT &r) {
+        MRT_DEV_CHECK(lane < kQueue && (!queue || rank < kQueue));
         fields(r, [&](auto *a, auto &v) {
             const auto t = a[lane];
             wave_sync();
@@ -766,6 +775,7 @@ struct Tracer {
                 if (slot < P.rec_cap) idx = (int64_t)slot;
             }
             if (idx < 0) return;
+            MRT_DEV_CHECK((uint64_t)idx < P.rec_cap);
             mrt_hit_record *r = &P.records[idx];
             const double nan = __builtin_nan("");
             r->ray_id = ry.id;
@@ -834,6 +844,7 @@ struct Tracer {
                         detected = true;
                         end = h;
                         const size_t px = (size_t)pj * (size_t)P.nx + (size_t)pi;
+                        MRT_DEV_CHECK(pi < P.nx && pj < P.ny && P.counts != nullptr);
                         atomicAdd(&P.counts[px], 1u);
                         if (P.energy) {
                             const double ew = P.qe_n > 0 ? __dmul_rn(ry.E, qe_weight(P, ry.E)) : ry.E;
@@ -1033,6 +1044,7 @@ __device__ __forceinline__ void trace_loop(const TraceParams &P, const double *l
             const uint32_t take = queued < nidle ? queued : nidle;
             head += take;
             queued -= take;
+            MRT_DEV_CHECK(head + queued <= kQueue);
         }
         const uint64_t act0 = ballot(active);
         if (act0 == 0) {
@@ -1105,7 +1117,7 @@ struct RangeClaim {
 // wave operation, so the compiler cannot split the wave across the
 // back-edge (the counter flush that ends trace_loop is lane-0-only).
 // ---------------------------------------------------------------------------
-template <class T, class Q>
+template <class T, bool kDefer = false, class Q>
 __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slots,
                                             const ServeItem *__restrict__ items, uint32_t n_items,
                                             uint64_t total, unsigned long long *__restrict__ cursors,
@@ -1122,9 +1134,10 @@ __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slot
     for (uint32_t k = 0; k < n_items; ++k) {
         const uint32_t i = lo + k < n_items ? lo + k : lo + k - n_items;
         const ServeItem it = items[i];
+        MRT_DEV_CHECK(i < n_items && it.slot >= 0);
         const TraceParams &P = slots[it.slot];
         RangeClaim claim{&cursors[i], it.first, it.count, it.chunk};
-        trace_loop<T, false>(P, P.lut, P.bin_cdf, claim, q);
+        trace_loop<T, kDefer>(P, P.lut, P.bin_cdf, claim, q);
     }
 }
 

@@ -10,6 +10,10 @@
 
 #include <cmath>
 
+// Every index assertion of the device loops is checked here.
+void simt_check_failed(const char *cond, const char *file, int line);
+#define MRT_DEV_CHECK(cond) ((cond) ? (void)0 : simt_check_failed(#cond, __FILE__, __LINE__))
+
 #define __device__
 #define __host__
 #define __global__

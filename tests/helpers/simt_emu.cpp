@@ -107,6 +107,10 @@ int run_wave(const std::function<void()> &body, long long max_meetings) {
 }  // namespace
 
 uint64_t simt_ballot(bool p) { return meet(kBallot, p ? 1 : 0); }
+void simt_check_failed(const char *cond, const char *file, int line) {
+    fprintf(stderr, "device-code check failed: %s (%s:%d)\n", cond, file, line);
+    abort();
+}
 uint32_t simt_readfirstlane(uint32_t v) { return (uint32_t)meet(kFirst, v); }
 int simt_lane() { return g_wave ? g_wave->lane : 0; }
 
@@ -129,21 +133,24 @@ using namespace mrt;
 using namespace mrt::tk;
 
 // `queue` is the wave's LDS ray queue: memory shared by the wave's lanes.
-template <class R>
+// kDefer: the serving loop with the one-call kernels' deferred detector work
+// (the device's serving kernels run without it).
+template <class R, bool kDefer = false>
 void serve_body(const TraceParams *slots, const ServeItem *items, uint32_t n, uint64_t total,
                 unsigned long long *cursors, uint32_t wave, uint32_t n_waves, void *queue) {
     // the serving kernel's body, with the wave index it would compute
-    serve_waves<Tracer<R, kAny, kAny, kAny, false>>(slots, items, n, total, cursors, wave, n_waves,
-                                                    *(RayQueue<R, false> *)queue);
+    serve_waves<Tracer<R, kAny, kAny, kAny, false>, kDefer>(slots, items, n, total, cursors, wave,
+                                                            n_waves, *(RayQueue<R, false> *)queue);
 }
 
 // The extended serving kernel's body (spots, user arrays and polarisations,
 // energy-dependent curves, further planes).
-template <class R>
+template <class R, bool kDefer = false>
 void serve_body_ext(const TraceParams *slots, const ServeItem *items, uint32_t n, uint64_t total,
                     unsigned long long *cursors, uint32_t wave, uint32_t n_waves, void *queue) {
     using T = Tracer<R, kAny, kAny, kAny, false, true>;
-    serve_waves<T>(slots, items, n, total, cursors, wave, n_waves, *(typename T::Queue *)queue);
+    serve_waves<T, kDefer>(slots, items, n, total, cursors, wave, n_waves,
+                           *(typename T::Queue *)queue);
 }
 
 template <class R, bool REC, bool EXT = false>
@@ -250,7 +257,13 @@ void emu_set_records(TraceParams *P, mrt_hit_record *records, uint64_t cap) {
 }
 
 int emu_serve_group(const TraceParams *slots, const ServeItem *items, uint32_t n, int n_waves,
-                    int precision, long long max_meetings, bool ext);
+                    int precision, long long max_meetings, bool ext, bool defer = false);
+
+// The serving loops with deferred detector work (ext: the extended loop).
+int emu_serve_defer(const TraceParams *slots, const ServeItem *items, uint32_t n, int n_waves,
+                    int precision, long long max_meetings, int ext) {
+    return emu_serve_group(slots, items, n, n_waves, precision, max_meetings, ext != 0, true);
+}
 
 // Run the serving kernel body with n_waves waves (one after another) over a
 // round's items; 0 on success.
@@ -266,7 +279,7 @@ int emu_serve_ext(const TraceParams *slots, const ServeItem *items, uint32_t n, 
 }
 
 int emu_serve_group(const TraceParams *slots, const ServeItem *items, uint32_t n, int n_waves,
-                    int precision, long long max_meetings, bool ext) {
+                    int precision, long long max_meetings, bool ext, bool defer) {
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; ++i) total += items[i].count;
     std::vector<unsigned long long> cursors(n ? n : 1, 0ull);
@@ -274,7 +287,13 @@ int emu_serve_group(const TraceParams *slots, const ServeItem *items, uint32_t n
         QueueMem q;
         int e = run_wave([&] {
             const uint32_t wv = (uint32_t)w, nw = (uint32_t)n_waves;
-            if (ext && precision == MRT_FP64)
+            const bool f64 = precision == MRT_FP64;
+            if (defer) {
+                if (ext && f64) serve_body_ext<double, true>(slots, items, n, total, cursors.data(), wv, nw, q.b);
+                else if (ext) serve_body_ext<float, true>(slots, items, n, total, cursors.data(), wv, nw, q.b);
+                else if (f64) serve_body<double, true>(slots, items, n, total, cursors.data(), wv, nw, q.b);
+                else serve_body<float, true>(slots, items, n, total, cursors.data(), wv, nw, q.b);
+            } else if (ext && precision == MRT_FP64)
                 serve_body_ext<double>(slots, items, n, total, cursors.data(), wv, nw, q.b);
             else if (ext)
                 serve_body_ext<float>(slots, items, n, total, cursors.data(), wv, nw, q.b);

@@ -36,9 +36,9 @@ MAX_MEETINGS = 10 ** 9
 ASM_FMA = 'asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "s"(c));'
 
 
-@pytest.fixture(scope="module")
-def emu(tmp_path_factory):
-    d = tmp_path_factory.mktemp("simt")
+def build_emu(d, extra_flags=()):
+    """Compile the emulator with the device sources copied into directory d;
+    returns the library's path."""
     for f in ("trace_impl.h", "trace_params.h", "device_math.h", "math_tables.h", "params.h",
               "params.cpp"):
         shutil.copy(os.path.join(CSRC, f), d / f)
@@ -47,23 +47,34 @@ def emu(tmp_path_factory):
     assert dm.count(ASM_FMA) == 1, "device_math.h: the inline asm this test replaces has changed"
     (d / "device_math.h").write_text(dm.replace(ASM_FMA, "r = __builtin_fma(p, z, c);"))
     lib = d / "libsimt_emu.so"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", *extra_flags,
                            "-I", os.path.join(HERE, "helpers", "fakedev"), "-I", str(d),
                            "-I", os.path.join(ROOT, "include"),
                            os.path.join(HERE, "helpers", "simt_emu.cpp"), str(d / "params.cpp"),
                            "-o", str(lib)])
-    L = C.CDLL(str(lib))
+    return lib
+
+
+def declare(L):
+    """Signatures of the emulator's entry points."""
     L.emu_build_params.argtypes = [C.c_void_p] * 7 + [C.c_int, C.c_void_p]
     L.emu_set_run.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32]
     L.emu_trace.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_longlong]
     L.emu_serve.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int, C.c_int, C.c_longlong]
     L.emu_serve_ext.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int, C.c_int, C.c_longlong]
+    L.emu_serve_defer.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_int, C.c_int,
+                                  C.c_longlong, C.c_int]
     L.emu_build_mwg.argtypes = [C.c_void_p] * 3 + [C.c_int] * 3 + [C.c_void_p, C.c_void_p, C.c_int,
                                                                    C.c_int]
     L.emu_trace_mwg.argtypes = [C.c_void_p, C.c_int, C.c_longlong]
     L.emu_set_records.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64]
     return L
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    return declare(C.CDLL(str(build_emu(tmp_path_factory.mktemp("simt")))))
 
 
 class Job:
@@ -102,6 +113,62 @@ def _jobs():
     for w, n, s in mix():
         out.append((w, n if n < 5000 else max(1, int(n * SCALE)), s))
     return out
+
+
+def _round(served, ragged=False):
+    """Slots and items of a round: each request split into two ray ranges,
+    the halves of all requests interleaved (the kernel takes any items; the
+    server sends one per request).  ragged: chunks that are not multiples of
+    the 64-ray batch."""
+    ps = len(served[0].P)
+    slots = (C.c_char * (ps * len(served)))()
+    for i, j in enumerate(served):
+        C.memmove(C.addressof(slots) + i * ps, j.P, ps)
+    items = [(0, j.n // 2, i) for i, j in enumerate(served)]
+    items += [(j.n // 2, j.n - j.n // 2, i) for i, j in enumerate(served)]
+    items = [x for x in items if x[1] > 0]
+    it = np.zeros(len(items), dtype=[("first", "<u8"), ("count", "<u8"), ("start", "<u8"),
+                                     ("slot", "<i4"), ("chunk", "<u4")])
+    start = 0
+    for k, (f, c, i) in enumerate(items):
+        it[k] = (f, c, start, i, (37 + 29 * k) if ragged else 64 * (1 + k % 4))
+        start += c
+    return slots, it
+
+
+def served_with_deferral(L, precision, ragged, ext, limit=None):
+    """The serving loop with the one-call kernels' deferral of the ended
+    rays' detector work (off in the device's serving kernels) over a round
+    of the mix (ext: the extended requests) equals each request's one-call
+    trace; every index the loop computes is checked on the way."""
+    prec = mrt.PRECISION[precision]
+    jobs = _ext_jobs() if ext else [(w, n, s, None) for w, n, s in _jobs()]
+    jobs = jobs[:limit]
+    alone = []
+    for w, n, s, r in jobs:
+        j = Job(L, w, n, s, rays=r)
+        assert L.emu_trace(j.P, WAVES, prec, MAX_MEETINGS) == 0, w["name"]
+        alone.append(j)
+    served = [Job(L, w, n, s, rays=r) for w, n, s, r in jobs]
+    slots, it = _round(served, ragged)
+    assert L.emu_serve_defer(slots, it.ctypes.data, len(it), 3 * WAVES, prec, MAX_MEETINGS,
+                             1 if ext else 0) == 0
+    for a, b, (w, n, s, r) in zip(alone, served, jobs):
+        assert np.array_equal(a.counts, b.counts), (w["name"], n)
+        assert np.array_equal(a.energy, b.energy), (w["name"], n)
+        assert a.counters() == b.counters(), (w["name"], n)
+    return alone
+
+
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
+@pytest.mark.parametrize("ragged", [False, True])
+@pytest.mark.parametrize("ext", [False, True])
+def test_served_mix_with_deferred_detector_work(emu, precision, ragged, ext):
+    """Every wave stays in lockstep, every index is in bounds, and each
+    request equals its one-call trace, over requests with different
+    detector sizes, also with ragged chunks."""
+    alone = served_with_deferral(emu, precision, ragged, ext)
+    assert ext or len({j.counts.size for j in alone}) > 1
 
 
 @pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
@@ -405,10 +472,29 @@ def test_served_extended_requests_equal_requests_alone(emu, precision):
     """The extended serving loop (a spot, an energy-dependent curve, further
     planes, user polarisations) over a round of interleaved half ranges
     gives each request the images and counters of its one-call trace."""
+    prec = mrt.PRECISION[precision]
+    jobs = _ext_jobs()
+    alone = []
+    for w, n, s, r in jobs:
+        j = Job(emu, w, n, s, rays=r)
+        assert emu.emu_trace(j.P, WAVES, prec, MAX_MEETINGS) == 0, w["name"]
+        alone.append(j)
+    served = [Job(emu, w, n, s, rays=r) for w, n, s, r in jobs]
+    slots, it = _round(served)
+    assert emu.emu_serve_ext(slots, it.ctypes.data, len(it), 3 * WAVES, prec, MAX_MEETINGS) == 0
+    for a, b, (w, n, s, r) in zip(alone, served, jobs):
+        assert np.array_equal(a.counts, b.counts), (w["name"], n)
+        assert np.array_equal(a.energy, b.energy), (w["name"], n)
+        assert a.counters() == b.counters(), (w["name"], n)
+        assert a.counters()["reflections"] > 0, w["name"]
+
+
+def _ext_jobs():
+    """Requests with a spot, an energy-dependent curve, further planes and
+    user polarisations."""
     import copy
     import oracle
     from paper_2503_16955_amd import workloads as W
-    prec = mrt.PRECISION[precision]
     vh = W.get("von_hamos_hapg")
     dep = copy.deepcopy(vh)
     dep["rocking_curve"]["energy_dependence"] = [(7.8, -30e-6, 0.6), (8.2, 45e-6, 2.2)]
@@ -420,29 +506,5 @@ def test_served_extended_requests_equal_requests_alone(emu, precision):
     a = np.random.default_rng(3).normal(size=k.shape)
     a -= np.sum(a * k, axis=1)[:, None] * k
     pol = {"polarisations": a / np.linalg.norm(a, axis=1)[:, None]}
-    jobs = [(W.with_spot(vh), 3000, 5, None), (dep, 2500, 6, None), (planes, 3000, 7, None),
+    return [(W.with_spot(vh), 3000, 5, None), (dep, 2500, 6, None), (planes, 3000, 7, None),
             (vh, n_pol, 8, pol)]
-    alone = []
-    for w, n, s, r in jobs:
-        j = Job(emu, w, n, s, rays=r)
-        assert emu.emu_trace(j.P, WAVES, prec, MAX_MEETINGS) == 0, w["name"]
-        alone.append(j)
-    served = [Job(emu, w, n, s, rays=r) for w, n, s, r in jobs]
-    ps = len(served[0].P)
-    slots = (C.c_char * (ps * len(served)))()
-    for i, j in enumerate(served):
-        C.memmove(C.addressof(slots) + i * ps, j.P, ps)
-    items = [(0, j.n // 2, i) for i, j in enumerate(served)]
-    items += [(j.n // 2, j.n - j.n // 2, i) for i, j in enumerate(served)]
-    it = np.zeros(len(items), dtype=[("first", "<u8"), ("count", "<u8"), ("start", "<u8"),
-                                     ("slot", "<i4"), ("chunk", "<u4")])
-    start = 0
-    for q, (f, c, i) in enumerate(items):
-        it[q] = (f, c, start, i, 64 * (1 + q % 4))
-        start += c
-    assert emu.emu_serve_ext(slots, it.ctypes.data, len(it), 3 * WAVES, prec, MAX_MEETINGS) == 0
-    for a, b, (w, n, s, r) in zip(alone, served, jobs):
-        assert np.array_equal(a.counts, b.counts), (w["name"], n)
-        assert np.array_equal(a.energy, b.energy), (w["name"], n)
-        assert a.counters() == b.counters(), (w["name"], n)
-        assert a.counters()["reflections"] > 0, w["name"]
