@@ -409,10 +409,15 @@ struct Tracer {
 
     // ---- acceptance filter ------------------------------------------------
     // The decision u_acc < r(x) / R_max with x = Delta - Delta_M is first
-    // taken from an FP32 estimate of x whose error is below kFilterErr (the
-    // float forms of sin(Delta) = c cos(alpha_B) - sqrt(1 - c^2) sin(alpha_B)
-    // and of the arcsine series have a worst case of ~3.5e-7 rad, from c's
-    // rounding, v_sqrt_f32 and the truncated series), bounding r over
+    // taken from an FP32 estimate of x whose error is below kFilterErr.  The
+    // estimate (sin(Delta) = c cos(alpha_B) - sqrt(1 - c^2) sin(alpha_B) in
+    // float, then the arcsine series) errs by at most 3.2e-7 rad: the
+    // rounding of c = |k.n| to float (3e-8) is multiplied by
+    // cos(alpha_B) + c sin(alpha_B) / sqrt(1 - c^2), up to ~10 at the
+    // sqrt(1 - c^2) >= 0.1 cutoff, which steep Bragg angles reach; v_sqrt_f32
+    // and the truncated series add little.  Measured over Bragg angles of
+    // 1-84 deg with the hardware estimates moved by an ulp either way: 3.1e-7.
+    // It bounds r over
     // [|x| - kFilterErr, |x| + kFilterErr] with a relative margin for the
     // FP32 curve.  Returns 1 (accept), 0 (reject) or -1 when u_acc falls in
     // that band, in which case the exact FP64 evaluation decides; the result
@@ -435,20 +440,32 @@ struct Tracer {
     // false when there is none.  With EXT the curve is read at x / s: the
     // bounds are scaled by 1/s (inv_s, rounded to float) and widened by 2^-20
     // relative, which covers the float roundings of inv_s and of the products.
+    // sin(Delta) = c cos(alpha_B) - sqrt(1 - c^2) sin(alpha_B) in FP32 from
+    // c = |k.n|; false when the normal lies within ~6 deg of k (no bound).
+    static __device__ __forceinline__ bool sin_delta_f32(double akn, float saf, float caf,
+                                                         float &z) {
+        const float c = (float)akn;
+        const float cw = __builtin_amdgcn_sqrtf(__builtin_fmaf(-c, c, 1.0f));
+        if (!(cw >= 0.1f)) return false;
+        z = __builtin_fmaf(c, caf, -cw * saf);
+        return true;
+    }
+    // asin(z) for |z| <= 1/4: its series to z^9 (truncation below 6e-9)
+    static __device__ __forceinline__ float asin_small_f32(float z) {
+        const float w = z * z;
+        float p = 35.0f / 1152.0f;
+        p = __builtin_fmaf(p, w, 5.0f / 112.0f);
+        p = __builtin_fmaf(p, w, 3.0f / 40.0f);
+        p = __builtin_fmaf(p, w, 1.0f / 6.0f);
+        return __builtin_fmaf(z * w, p, z);
+    }
     static __device__ __forceinline__ bool x_bounds(double akn, float saf, float caf, float shift,
                                                     float inv_s, float &lo, float &hi, float &slo,
                                                     float &shi) {
-        const float c = (float)akn;
-        const float cw = __builtin_amdgcn_sqrtf(__builtin_fmaf(-c, c, 1.0f));
-        if (!(cw >= 0.1f)) return false;   // normal within ~6 deg of k: no bound
-        const float z = __builtin_fmaf(c, caf, -cw * saf);
+        float z;
+        if (!sin_delta_f32(akn, saf, caf, z)) return false;
         if (__builtin_fabsf(z) <= 0.25f) {
-            const float w = z * z;
-            float p = 35.0f / 1152.0f;
-            p = __builtin_fmaf(p, w, 5.0f / 112.0f);
-            p = __builtin_fmaf(p, w, 3.0f / 40.0f);
-            p = __builtin_fmaf(p, w, 1.0f / 6.0f);
-            const float x = __builtin_fmaf(z * w, p, z) - shift;
+            const float x = asin_small_f32(z) - shift;
             slo = x - kFilterErr;
             shi = x + kFilterErr;
             const float ax = __builtin_fabsf(x);

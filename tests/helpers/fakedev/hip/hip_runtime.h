@@ -69,10 +69,19 @@ inline double __dsub_rn(double a, double b) { return a - b; }
 inline double __dmul_rn(double a, double b) { return a * b; }
 inline double __ddiv_rn(double a, double b) { return a / b; }
 inline double __builtin_amdgcn_rsq(double x) { return 1.0 / std::sqrt(x); }
-inline float __builtin_amdgcn_rcpf(float x) { return 1.0f / x; }
+// The hardware's FP32 reciprocal, square root and exp2 are within 1 ulp, not
+// correctly rounded.  `simt_ulp_bias` (-1, 0, +1) moves their results one
+// float toward -inf / +inf, so a test can bracket the device's answers.
+inline thread_local int simt_ulp_bias = 0;
+inline float simt_biased(float r) {
+    if (simt_ulp_bias > 0) return std::nextafter(r, INFINITY);
+    if (simt_ulp_bias < 0) return std::nextafter(r, -INFINITY);
+    return r;
+}
+inline float __builtin_amdgcn_rcpf(float x) { return simt_biased(1.0f / x); }
 inline float __builtin_amdgcn_rsqf(float x) { return 1.0f / std::sqrt(x); }
-inline float __builtin_amdgcn_sqrtf(float x) { return std::sqrt(x); }
-inline float __builtin_amdgcn_exp2f(float x) { return std::exp2(x); }
+inline float __builtin_amdgcn_sqrtf(float x) { return simt_biased(std::sqrt(x)); }
+inline float __builtin_amdgcn_exp2f(float x) { return simt_biased(std::exp2(x)); }
 inline float __builtin_amdgcn_logf(float x) { return std::log2(x); }
 inline float __builtin_amdgcn_sinf(float x) { return (float)std::sin(6.283185307179586 * (double)x); }
 inline float __builtin_amdgcn_cosf(float x) { return (float)std::cos(6.283185307179586 * (double)x); }

@@ -197,6 +197,48 @@ int emu_build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic
 }
 int emu_params_size() { return (int)sizeof(TraceParams); }
 
+// The FP32 acceptance filter as compiled here (Tracer::sin_delta_f32,
+// asin_small_f32, x_bounds and filter), for case i: c = akn[i] = |k.n|,
+// s = sa[i] = sin(alpha_B), u = u[i], and the curve read at
+// (Delta - shift) / scale.  Outputs per case: the FP32 estimate of x before
+// its error band (NaN when sin(Delta) > 1/4 or there is no bound), the
+// reference x in long double, the bounds (lo, hi, slo, shi), whether there
+// are bounds, the filter's decision (1, 0, -1) and the exact decisions of
+// the FP32-mixed and FP64 paths (u < r(x) / R_max, x from FP64 asin), and
+// the FP64 path's r(x) / R_max.  `bias` moves the hardware FP32 estimates by
+// one ulp (simt_ulp_bias).
+void emu_filter_cases(const TraceParams *P, const double *lut, int n, const double *akn,
+                      const double *sa, const double *u, double shift, double scale, int bias,
+                      float *x_est, double *x_ref, float *bounds, int *has, int *dec, int *dec32,
+                      int *dec64, double *ratio) {
+    using T32 = Tracer<float, kAny, kAny, kAny, false, true>;
+    using T64 = Tracer<double, kAny, kAny, kAny, false, true>;
+    simt_ulp_bias = bias;
+    const bool ext = scale != 1.0 || shift != P->shift;
+    const float shf = ext ? (float)shift : P->f32.shift;
+    const float inv_sf = ext ? (float)(1.0 / scale) : 1.0f;
+    for (int i = 0; i < n; ++i) {
+        const double s = sa[i];
+        const float saf = (float)s;
+        const float caf = (float)std::sqrt(std::fma(-s, s, 1.0));
+        float z = 0.0f;
+        x_est[i] = T32::sin_delta_f32(akn[i], saf, caf, z) && std::fabs(z) <= 0.25f
+                       ? T32::asin_small_f32(z) - shf
+                       : NAN;
+        const long double xr = ((asinl((long double)akn[i]) - asinl((long double)s)) -
+                                (long double)shift) / (long double)scale;
+        x_ref[i] = (double)xr;
+        float *b = bounds + 4 * i;
+        has[i] = T32::x_bounds(akn[i], saf, caf, shf, inv_sf, b[0], b[1], b[2], b[3]) ? 1 : 0;
+        dec[i] = T32::filter(*P, akn[i], saf, caf, (float)u[i], shf, inv_sf);
+        const double x = ((std::asin(akn[i]) - std::asin(s)) - shift) / scale;
+        dec32[i] = u[i] < T32::irc_ratio(*P, lut, x) ? 1 : 0;
+        ratio[i] = T64::irc_ratio(*P, lut, x);
+        dec64[i] = u[i] < ratio[i] ? 1 : 0;
+    }
+    simt_ulp_bias = 0;
+}
+
 // The paper's event model: its parameters, with the psi table appended at
 // tables_out[n_used...] (host memory the emulated kernel reads in place).
 int emu_build_mwg(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_curve *r,
