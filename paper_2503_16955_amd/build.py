@@ -9,6 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmosaicrt.so")
+# VALU issue-rate microbenchmark behind the roofline's slot weights (a
+# program of its own, run by the profiling scripts)
+RATES_EXE = os.path.join(HERE, "valu_rates")
 SOURCES = ["trace_f64_flat.hip", "trace_f64_cyl.hip", "trace_f32_flat.hip", "trace_f32_cyl.hip",
            "trace_mwg.hip", "trace_ext.hip", "serve.hip", "launch.hip", "params.cpp", "runtime.cpp", "server.cpp"]
 
@@ -51,7 +54,19 @@ def build(verbose=False, extra_flags=(), jobs=None):
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    build_rates(verbose)
     return LIB
+
+
+def build_rates(verbose=False):
+    cmd = [HIPCC, "-O3", "-std=c++17", "--offload-arch=gfx950", "-ffp-contract=off",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           os.path.join(CSRC, "valu_rates.hip"), "-o", RATES_EXE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(RATES_EXE + ".tmp", RATES_EXE)
+    return RATES_EXE
 
 
 if __name__ == "__main__":

@@ -2,13 +2,17 @@
 library's kernels compile them for gfx950, and the algorithmic work of a
 trace in VALU issue slots.
 
-gfx950 issues VALU instructions at different rates by class (measured with
-a throughput microbenchmark on MI355X: per CU and clock, 32-bit ALU and FP32
-arithmetic 128 lanes, FP64 arithmetic and 32-bit integer multiplies 64 lanes,
-v_mad_u64_u32 ~36 lanes, FP32 transcendentals 32, FP64 rcp/rsq ~21).  One
-issue slot is one lane of the 64-lane-per-clock class, so the peak is
-256 CUs x 64 x 2.4 GHz = 39.32 T slots/s and an instruction costs
-SLOT_WEIGHT of its class.
+gfx950 issues VALU instructions at different rates by class.  The rates
+come from the throughput microbenchmark ``csrc/valu_rates.hip`` (its table
+is profiles/valu_issue_rates_gfx950.md): measured on MI355X, FP32
+arithmetic (fma, mul, add) runs at about twice the FP64 FMA's lane rate,
+32-bit integer, logic, compare, select and conversion instructions and the
+32-bit integer multiplies at about 1.25 times it, v_mad_u64_u32 at 1.1
+times, FP32 transcendentals at 0.62 times and v_rcp_f64 at 0.31 times.  One
+issue slot is one FP64 FMA lane, so the peak is 256 CUs x 64 x 2.4 GHz =
+39.32 T slots/s (the published 78.6 TFLOP/s FP64 peak over 2 flops) and an
+instruction costs SLOT_WEIGHT of its class: the FP64 FMA's measured rate
+over its class's.
 
 ``OP_COSTS`` was counted by ``derive()``: each probe kernel in
 ``csrc/op_cost_probe.hip`` applies one operation inside a loop (constants
@@ -27,11 +31,18 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# Issue slots per VALU instruction class on gfx950 (see the module doc).
-SLOT_WEIGHT = {"alu32": 0.5, "alu64": 1.0, "mad64": 1.75, "trans32": 2.0, "trans64": 3.0}
+# Issue slots per VALU instruction class on gfx950 (see the module doc):
+# the measured FP64 FMA rate over the class's (fp32 0.49-0.54, alu32
+# 0.79-0.85, mul32 0.79-0.84, mad64 0.89-0.91, trans32 1.60-1.62, trans64
+# 3.14-3.26 over the microbenchmark's runs).  64-bit integer instructions
+# other than v_mad_u64_u32 are not measured and are priced like FP64.
+SLOT_WEIGHT = {"fp32": 0.5, "alu32": 0.8, "mul32": 0.8, "alu64": 1.0, "mad64": 0.9,
+               "trans32": 1.6, "trans64": 3.2}
 _TRANS32 = ("v_exp_f32", "v_log_f32", "v_sqrt_f32", "v_rsq_f32", "v_rcp_f32", "v_sin_f32",
             "v_cos_f32")
 _TRANS64 = ("v_rcp_f64", "v_rsq_f64", "v_sqrt_f64")
+_FP32_ARITH = re.compile(r"^v_(fma|fmac|mac|mad|mul|add|sub|subrev|max|min|med3|ldexp|fmamk|"
+                         r"fmaak)_f32$")
 
 
 def slot_class(op):
@@ -43,14 +54,17 @@ def slot_class(op):
         return "trans64"
     if op.startswith(("v_mad_u64_u32", "v_mad_i64_i32")):
         return "mad64"
-    if ("f64" in op or "b64" in op or "u64" in op or "i64" in op
-            or op.startswith(("v_mul_hi_u32", "v_mul_lo_u32", "v_mul_hi_i32"))):
+    if op.startswith(("v_mul_hi_u32", "v_mul_lo_u32", "v_mul_hi_i32")):
+        return "mul32"
+    if "f64" in op or "b64" in op or "u64" in op or "i64" in op:
         return "alu64"
+    if _FP32_ARITH.match(op):
+        return "fp32"
     return "alu32"
 
 
 # Issue slots per operation in the trace kernels' code, as counted by derive().
-OP_COSTS = {'f64': {'log': 28.5, 'exp': 30.0, 'expm1': 37.0, 'sqrt': 15.0, 'rsqrt': 10.0, 'rcp': 7.0, 'div': 13.0, 'sincos': 22.0, 'sin': 127.5, 'cos': 127.5, 'asin': 86.5}, 'f32': {'log': 2.5, 'exp': 2.5, 'expm1': 13.0, 'sqrt': 2.0, 'rsqrt': 2.0, 'rcp': 2.0, 'div': 7.0, 'sincos': 4.0}, 'filter': {'gaussian': 26.5, 'pseudo_voigt': 33.5, 'table': 17.5, 'lorentzian': 26.5, 'box': 18.0}, 'philox': 51.5}
+OP_COSTS = {'f64': {'log': 33.0, 'exp': 36.6, 'expm1': 44.8, 'sqrt': 15.8, 'rsqrt': 10.2, 'rcp': 7.2, 'div': 13.2, 'sincos': 23.2, 'sin': 139.2, 'cos': 139.2, 'asin': 96.8}, 'f32': {'log': 2.1, 'exp': 2.1, 'expm1': 16.6, 'sqrt': 1.6, 'rsqrt': 1.6, 'rcp': 1.6, 'div': 7.8, 'sincos': 3.2}, 'filter': {'gaussian': 29.8, 'pseudo_voigt': 36.0, 'table': 20.4, 'lorentzian': 29.8, 'box': 21.2}, 'philox': 44.4}
 
 PROBES = {
     ("f64", "log"): ("log_f64", "glue_f64"), ("f64", "exp"): ("exp_f64", "glue_f64"),
@@ -139,13 +153,15 @@ def mix(precision, geometry, mosaic, irc, spectrum, mosaic_eta=0.0):
     'reflection' (reflected direction and new exit distance) and 'detected'
     (detector plane, pixel, two integer atomics).  Plain arithmetic, compares
     and selects count one instruction each, in the precision of the path
-    (FP64 1 slot, FP32 0.5), except the FP64 energy and k.n of both paths."""
+    (FP64 1 slot, FP32 0.5), except the FP64 energy and k.n of both paths.
+    A word becomes an FP64 uniform in a conversion and an FMA, an FP32 one
+    in a shift, a conversion and an FMA."""
     D = OP_COSTS["f64"]
     R = OP_COSTS["f64"] if precision == "fp64" else OP_COSTS["f32"]
-    a = SLOT_WEIGHT["alu64"] if precision == "fp64" else SLOT_WEIGHT["alu32"]
+    a = SLOT_WEIGHT["alu64"] if precision == "fp64" else SLOT_WEIGHT["fp32"]
     d = SLOT_WEIGHT["alu64"]
     ph = OP_COSTS["philox"]
-    U = 2 * d if precision == "fp64" else 3 * SLOT_WEIGHT["alu32"]   # word -> uniform
+    U = 2 * d if precision == "fp64" else 2 * SLOT_WEIGHT["alu32"] + SLOT_WEIGHT["fp32"]
     cyl = geometry == "cylinder"
     if cyl:
         exit_d = 2 * R["sqrt"] + 6 * R["div"] + 45 * a
@@ -297,7 +313,7 @@ def algorithmic_ops_ext(workload, precision, counters, spot=False, pol=False, pl
     base = algorithmic_ops(workload, precision, counters)
     D = OP_COSTS["f64"]
     R = OP_COSTS["f64"] if precision == "fp64" else OP_COSTS["f32"]
-    a = SLOT_WEIGHT["alu64"] if precision == "fp64" else SLOT_WEIGHT["alu32"]
+    a = SLOT_WEIGHT["alu64"] if precision == "fp64" else SLOT_WEIGHT["fp32"]
     d = SLOT_WEIGHT["alu64"]
     c = counters
     extra = 0.0
@@ -313,7 +329,7 @@ def algorithmic_ops_ext(workload, precision, counters, spot=False, pol=False, pl
         ended = c["absorbed"] + c["exit_reflected"] + c["exit_transmitted"]
         tilts = max(0, c["events"] - ended)
         F = OP_COSTS["f32"]
-        f = SLOT_WEIGHT["alu32"]
+        f = SLOT_WEIGHT["fp32"]
         irc = workload["rocking_curve"]["kind"]
         per_set = d + 2 * d + F["sqrt"] + 2 * f + OP_COSTS["filter"][irc] + 4 * f
         extra += tilts * (planes * per_set + 4 * f + 6 * d)

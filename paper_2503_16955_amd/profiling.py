@@ -88,20 +88,41 @@ def _copy_kib(d, counter):
     return max(vals) if vals else None
 
 
-def summarize(trace_dir, pmc_dirs, copy_fetch, copy_write, copy_mib, command, out_md, label):
+def dispatch_stats(trace_dir, skip_first=1):
+    """Per kernel, from the dispatch records of a rocprofv3 kernel trace:
+    (calls kept, average, min, max duration in ns) after dropping each
+    kernel's first `skip_first` dispatches (the warm-up launches, which run
+    on a cold device and would bias the average)."""
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    per = collections.defaultdict(list)
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                per[r["Kernel_Name"]].append((int(r["Start_Timestamp"]),
+                                              int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = {}
+    for k, v in per.items():
+        v.sort()
+        d = [x for _, x in v[skip_first:]] or [x for _, x in v]
+        out[k] = (len(d), sum(d) / len(d), min(d), max(d), len(v))
+    return out
+
+
+def summarize(trace_dir, pmc_dirs, copy_fetch, copy_write, copy_mib, command, out_md, label,
+              skip_first=1):
     lines = [f"# rocprofv3: {label}", "", "Commands (from /tmp on one MI355X, gfx950):", "", "```"]
     lines += command.strip().splitlines()
     lines += ["```", ""]
-    # kernel trace statistics
-    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    # kernel trace statistics, without each kernel's warm-up dispatches
+    stats = dispatch_stats(trace_dir, skip_first)
     if stats:
-        lines += ["Kernel trace (durations in microseconds):", "",
-                  "| kernel | calls | average us | min us | max us | % |", "|---|---|---|---|---|---|"]
-        with open(stats[0]) as fh:
-            for r in csv.DictReader(fh):
-                lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
-                             f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
-                             f"{float(r['Percentage']):.2f} |")
+        lines += [f"Kernel trace (durations in microseconds; each kernel's first {skip_first} "
+                  "dispatch(es), the warm-up, left out):", "",
+                  "| kernel | dispatches | kept | average us | min us | max us |",
+                  "|---|---|---|---|---|---|"]
+        for k, (n, avg, lo, hi, total) in sorted(stats.items(), key=lambda kv: -kv[1][1] * kv[1][0]):
+            lines.append(f"| `{k[:90]}` | {total} | {n} | {avg / 1e3:.1f} | {lo / 1e3:.1f} | "
+                         f"{hi / 1e3:.1f} |")
         lines.append("")
     # counters
     agg = collections.defaultdict(list)
@@ -156,13 +177,16 @@ def main():
     s.add_argument("--out", required=True)
     s.add_argument("--label", required=True)
     s.add_argument("--traffic-json", default=None)
+    s.add_argument("--skip-first", type=int, default=1,
+                   help="warm-up dispatches of each kernel left out of its statistics")
     a = ap.parse_args()
     if a.cmd == "copy":
         copy_reference(a.mib)
         return
     with open(a.command_file) as fh:
         command = fh.read()
-    t = summarize(a.trace, a.pmc, a.copy_fetch, a.copy_write, a.copy_mib, command, a.out, a.label)
+    t = summarize(a.trace, a.pmc, a.copy_fetch, a.copy_write, a.copy_mib, command, a.out, a.label,
+                  a.skip_first)
     if a.traffic_json:
         with open(a.traffic_json, "w") as fh:
             json.dump(t, fh, indent=1)

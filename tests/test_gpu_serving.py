@@ -57,6 +57,29 @@ def test_mix_equals_alone(precision):
         assert srv.stats()["used_bytes"] == 0
 
 
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp64"])
+def test_design_requests_served_equal_alone(precision):
+    """The benchmark's own spectrometer-design requests (varied radius,
+    mosaic kind and width, thickness and energy window, each with its own
+    seed), the first 48 with their ray counts scaled by 1/100 (1e3-1e6,
+    ragged): served together through 16 slots, each equals its one-call
+    trace bit for bit."""
+    reqs = [(w, max(1, w["n_rays"] // 100), w["seed"]) for w in W.serving_requests()[:48]]
+    with mrt.Server(hbm_budget_bytes=1 << 30, max_slots=16, precision=precision,
+                    round_rays=1 << 20) as srv:
+        tickets = [srv.submit(w, n_rays=n, seed=s) for w, n, s in reqs]
+        results = [srv.wait(t, timeout_ms=WAIT_MS) for t in tickets]
+        st = srv.stats()
+        print(f"[serve-design] {precision}: {len(reqs)} requests, "
+              f"{sum(n for _, n, _ in reqs)} rays, {st['rounds']} rounds", flush=True)
+        assert st["rounds"] > 3
+        for (w, n, s), r in zip(reqs, results):
+            _check_equal(r, w, n, s, precision)
+        for t in tickets:
+            srv.release(t)
+        assert srv.stats()["used_bytes"] == 0
+
+
 def test_budget_admission_in_arrival_order():
     w = W.get("von_hamos_hapg")
     per = 2048 * 512 * 12
