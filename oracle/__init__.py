@@ -21,7 +21,7 @@ MISS, ABSORBED, EXIT_REFLECTED, EXIT_TRANSMITTED, TRUNCATED = range(5)
 _SPEC = {"uniform": 0, "lines": 1, "table": 2}
 _GEOM = {"flat": 0, "cylinder": 1}
 _MDF = {"gaussian_vmf": 0, "lorentzian": 1, "pseudo_voigt": 2, "wrapped_lorentzian": 3,
-        "spherical_wrapped_lorentzian": 4}
+        "spherical_wrapped_lorentzian": 4, "gaussian": 5}
 _IRC = {"gaussian": 0, "pseudo_voigt": 1, "table": 2, "lorentzian": 3, "box": 4}
 _MODEL = {"stepping": 0, "mwg": 1}
 _SPOT = {"point": 0, "gaussian": 1, "disk": 2}

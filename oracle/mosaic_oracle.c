@@ -223,6 +223,19 @@ static void lorentz_tilt(double gamma, double q, double *ct, double *st) {
     *st = T * c;
 }
 
+static void gauss_tilt(double gamma, double u, double *ct, double *st) {
+    /* The regular Gaussian of Eq. Gaussian (Delta -> theta, Lambda ->
+       Gamma) as an isotropic tilt: a bivariate normal in the tangent plane
+       with standard deviation s = Gamma / (2 sqrt(2 ln 2)) on each axis, so
+       that every one-dimensional marginal is Eq. Gaussian; its radius
+       T = s sqrt(-2 ln u) (Rayleigh), mapped to the sphere by tan(theta) = T. */
+    double s = gamma / (2.0 * sqrt(2.0 * log(2.0)));
+    double T = s * sqrt(-2.0 * log(u));
+    double c = 1.0 / sqrt(1.0 + T * T);
+    *ct = c;
+    *st = T * c;
+}
+
 void orc_mdf_sample(const orc_mosaic *m, double u2, double u3,
                     const double N[3], const double e1[3], const double e2[3],
                     double n_out[3]) {
@@ -261,6 +274,9 @@ void orc_mdf_sample(const orc_mosaic *m, double u2, double u3,
             if (v > 2.0) v = 2.0;
             break;
         }
+        case ORC_MDF_GAUSSIAN:
+            gauss_tilt(gamma, u2, &ct, &st);
+            break;
         }
         if (v >= 0.0) {
             ct = 1.0 - v;
@@ -544,6 +560,17 @@ static double cauchy_density(double gamma, double v) {
     return g / (ORC_TWO_PI * q * sqrt(q));
 }
 
+static double gauss_density(double gamma, double v) {
+    /* the Gaussian tilt of gauss_tilt: planar density
+       exp(-T^2 / (2 s^2)) / (2 pi s^2) at T = tan(theta), times the
+       gnomonic area ratio 1 / cos^3(theta); zero on the far hemisphere */
+    double c = 1.0 - v;
+    if (!(c > 0.0)) return 0.0;
+    double s = gamma / (2.0 * sqrt(2.0 * log(2.0)));
+    double T2 = v * (2.0 - v) / (c * c);
+    return exp(-T2 / (2.0 * s * s)) / (ORC_TWO_PI * s * s * c * c * c);
+}
+
 double orc_mdf_density(const orc_mosaic *m, double v) {
     double gamma = m->fwhm;
     switch (m->kind) {
@@ -566,6 +593,8 @@ double orc_mdf_density(const orc_mosaic *m, double v) {
         double A = 2.0 * sh * sh;
         return A * (A + 2.0) / (2.0 * ORC_TWO_PI * (A + v) * (A + v));
     }
+    case ORC_MDF_GAUSSIAN:
+        return gauss_density(gamma, v);
     }
     return 0.0;
 }

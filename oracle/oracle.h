@@ -33,7 +33,8 @@ extern "C" {
 enum { ORC_SPEC_UNIFORM = 0, ORC_SPEC_LINES = 1, ORC_SPEC_TABLE = 2 };
 enum { ORC_GEOM_FLAT = 0, ORC_GEOM_CYLINDER = 1 };
 enum { ORC_MDF_VMF = 0, ORC_MDF_LORENTZ = 1, ORC_MDF_PVOIGT = 2,
-       ORC_MDF_WRAPPED_LORENTZ = 3, ORC_MDF_SPHERICAL_WRAPPED_LORENTZ = 4 };
+       ORC_MDF_WRAPPED_LORENTZ = 3, ORC_MDF_SPHERICAL_WRAPPED_LORENTZ = 4,
+       ORC_MDF_GAUSSIAN = 5 };
 enum { ORC_IRC_GAUSS = 0, ORC_IRC_PVOIGT = 1, ORC_IRC_TABLE = 2,
        ORC_IRC_LORENTZ = 3, ORC_IRC_BOX = 4 };
 enum { ORC_MODEL_STEPPING = 0, ORC_MODEL_MWG = 1 };
