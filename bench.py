@@ -315,7 +315,7 @@ def cpu_baseline(w, n):
                          "sample": f"ray ids [0, {n1}), {dt1:.2f} s"}}, r
 
 
-def precision_report(mrt, precision, w, c64, c32, n, steps, oracle_result, n_oracle):
+def precision_report(mrt, precision, w, c64, c32, n, steps, oracle_result, n_oracle, detected):
     """FP32-mixed against FP64 at the same rays (centroid and FWHM per line:
     shared noise shows small differences; their chi-square per pixel is a
     difference measure), FP32-mixed at an independent seed against FP64
@@ -327,6 +327,12 @@ def precision_report(mrt, precision, w, c64, c32, n, steps, oracle_result, n_ora
     a64, _ = mrt.image_to_numpy(c64)
     a32, _ = mrt.image_to_numpy(c32)
     rays = n * steps
+    # the images must be the ones the timed steps made (nothing traced into
+    # them since): each holds exactly the detected rays of its steps
+    for img, det, name in ((a64, detected[0], "fp64"), (a32, detected[1], "fp32_mixed")):
+        if int(img.sum(dtype=np.uint64)) != det:
+            raise RuntimeError(f"precision report: the {name} image holds {int(img.sum())} "
+                               f"counts, its steps detected {det}")
     cmp = precision.compare_images(w, a32, a64, lines)
     cmp["chi2_per_px_same_seed"] = cmp.pop("chi2_per_px")
     i32 = independent_image(mrt, w, "fp32_mixed", n, steps)
@@ -369,10 +375,12 @@ def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None, round_rays
     given inter-arrival gaps; a consumer thread takes each finished request
     from the completion queue and releases it at once.  Returns per-request
     latencies (ms, server clock), rays, the span from first submission to last
-    completion (s) and the server's stats."""
+    completion (s), the server's stats and (workload, counters) of every
+    request."""
     import threading
     n = len(reqs)
     done = []
+    by_ticket = {}
     srv = mrt.Server(hbm_budget_bytes=budget, max_slots=max_slots, precision=precision,
                      round_rays=round_rays)
 
@@ -381,6 +389,7 @@ def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None, round_rays
             t, r = srv.wait_any(views=False)
             if r["state"] != "done":
                 raise RuntimeError(f"request {t} ended {r['state']} (status {r['status']})")
+            r["ticket"] = t
             done.append(r)
             srv.release(t)
 
@@ -390,7 +399,7 @@ def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None, round_rays
         for i, w in enumerate(reqs):
             if gaps_s is not None and i:
                 time.sleep(gaps_s[i])
-            srv.submit(w)
+            by_ticket[srv.submit(w)] = w
         th.join()
         st = srv.stats()
     finally:
@@ -399,7 +408,7 @@ def serving_run(mrt, reqs, precision, budget, max_slots, gaps_s=None, round_rays
         raise RuntimeError("serving: not every request finished")
     lat = [r["done_ms"] - r["submit_ms"] for r in done]
     span = (max(r["done_ms"] for r in done) - min(r["submit_ms"] for r in done)) * 1e-3
-    return lat, span, st
+    return lat, span, st, [(by_ticket[r["ticket"]], r["counters"]) for r in done]
 
 
 def sequential_run(mrt, reqs, precision):
@@ -422,7 +431,7 @@ def sequential_run(mrt, reqs, precision):
     return ev0.elapsed_time(ev1) * 1e-3, events
 
 
-def serving(mrt, W, n_requests, budget, max_slots, load, seed=4, round_rays=0):
+def serving(mrt, W, op_costs, cus, n_requests, budget, max_slots, load, seed=4, round_rays=0):
     """The serving workload (design requests of varied geometry and ray
     count): for each precision, the saturated throughput (all requests queued
     at once), then Poisson arrivals at `load` times that throughput with
@@ -439,11 +448,24 @@ def serving(mrt, W, n_requests, budget, max_slots, load, seed=4, round_rays=0):
         for w in reqs:
             w["precision"] = prec
         seq_s, seq_events = sequential_run(mrt, reqs, prec)
-        lat0, span0, st0 = serving_run(mrt, reqs, prec, budget, max_slots, round_rays=round_rays)
+        lat0, span0, st0, per_req = serving_run(mrt, reqs, prec, budget, max_slots,
+                                                round_rays=round_rays)
         sat = rays / span0
         rate = load * sat / (rays / n_requests)           # requests per second
         gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n_requests)
-        lat, span, st = serving_run(mrt, reqs, prec, budget, max_slots, gaps, round_rays)
+        lat, span, st, _ = serving_run(mrt, reqs, prec, budget, max_slots, gaps, round_rays)
+        # the serving kernel's ALU roofline: the priced work of every
+        # request (its own counters and kinds) over the time the device was
+        # tracing rounds (the union of the rounds' HIP-event intervals), and
+        # over the whole saturated run
+        ops = sum(op_costs.algorithmic_ops(w, prec, c) for w, c in per_req)
+        peak = cus * LANES_PER_CU_PER_CLK * PEAK_CLOCK_HZ / 1e12
+        busy = st0["busy_ms"] * 1e-3
+        serve_roof = {"bound": "alu", "achieved": round(ops / busy / 1e12, 4), "peak": round(peak, 4),
+                      "unit": "TOP/s", "frac": round(ops / busy / 1e12 / peak, 4),
+                      "frac_whole_run": round(ops / span0 / 1e12 / peak, 4),
+                      "kernel": f"serve_kernel<{'double' if prec == 'fp64' else 'float'}>",
+                      "ops": round(ops, 1), "busy_s": round(busy, 4)}
         out[prec] = {
             "one_call_per_request_rays_per_s": round(rays / seq_s, 1),
             "events_per_ray": round(seq_events / rays, 3),
@@ -455,6 +477,7 @@ def serving(mrt, W, n_requests, budget, max_slots, load, seed=4, round_rays=0):
             "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "max_ms": round(float(np.max(lat)), 2),
             "rounds": int(st["rounds"]),
+            "roofline": serve_roof,
         }
         log(f"serving {prec}: saturated {sat:.3e} rays/s, Poisson {rate:.1f}/s: "
             f"p50 {out[prec]['p50_ms']} ms p99 {out[prec]['p99_ms']} ms")
@@ -557,10 +580,14 @@ def main():
         ns = -(-n // a.shard_of)
         sh = {"gpus_modelled": a.shard_of, "rays_per_step": ns,
               "note": "ray ids [0, n/G) of the same workload on this GPU; no image reduce"}
-        for prec, (c_, e_) in (("fp64", (counts, energy)), ("fp32_mixed", (counts32, energy32))):
+        for prec in ("fp64", "fp32_mixed"):
             if prec == "fp32_mixed" and a.no_mixed:
                 continue
+            # images of its own: the precision report below compares the
+            # full-size FP64 and FP32-mixed images
+            c_, e_ = mrt.alloc_images(w)
             ps, gms, _ = run_precision(mrt, w, prec, a.steps, a.warmup, ns, c_, e_, a.refill)
+            del c_, e_
             sh[prec] = {"value": round(ns * a.steps / (gms * 1e-3), 1), "unit": "rays/s",
                         "ms_per_step": round(gms / a.steps, 4)}
         res["shard"] = sh
@@ -572,14 +599,15 @@ def main():
         log(f"paper's model: {res['mwg_model']['value']:.3e} rays/s, "
             f"{res['mwg_model']['ms_per_step']} ms per step")
     res["serving"] = None if a.no_serving else serving(
-        mrt, W, a.serving_requests, a.serving_budget_mib << 20, 64, a.serving_load,
-        round_rays=a.serving_round_rays)
+        mrt, W, op_costs, info["compute_units"], a.serving_requests, a.serving_budget_mib << 20, 64,
+        a.serving_load, round_rays=a.serving_round_rays)
     orc = None
     if not a.no_cpu_baseline:
         res["cpu_baseline"], orc = cpu_baseline(w, a.cpu_rays)
     if not a.no_mixed and w["source"]["spectrum"] == "lines" and w["crystal"]["geometry"] == "cylinder":
-        res["precision"] = precision_report(mrt, precision, w, counts, counts32, n, a.steps, orc,
-                                            a.cpu_rays)
+        res["precision"] = precision_report(
+            mrt, precision, w, counts, counts32, n, a.steps, orc, a.cpu_rays,
+            (sum(c["detected"] for c in per64), sum(c["detected"] for c in pm)))
     print(json.dumps(res), flush=True)
 
 

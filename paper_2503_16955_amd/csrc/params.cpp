@@ -99,7 +99,7 @@ mrt_status validate(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic 
         }
     }
     // mosaic
-    if (m->kind < 0 || m->kind > 4) return fail(MRT_EINVAL, "mosaic: unknown kind");
+    if (m->kind < 0 || m->kind > 5) return fail(MRT_EINVAL, "mosaic: unknown kind");
     if (!(m->fwhm >= 0.0) || !std::isfinite(m->fwhm)) return fail(MRT_EINVAL, "mosaic: fwhm must be >= 0");
     if (!(m->eta >= 0.0 && m->eta <= 1.0)) return fail(MRT_EINVAL, "mosaic: eta must lie in [0, 1]");
     // rocking curve
@@ -249,6 +249,8 @@ void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocki
     const double sh = std::sinh(gamma / 4.0);
     P.swl_a = 2.0 * sh * sh;
     P.swl_norm = P.swl_a * (P.swl_a + 2.0) / (4.0 * kPi);
+    P.gau_inv2s2 = 1.0 / (2.0 * sv * sv);
+    P.gau_norm = 1.0 / (2.0 * kPi * sv * sv);
     // nodes psi_j = pi (j / M)^3, dense near psi = 0
     double prev = 0.0;
     for (int j = 0; j <= psi_nodes; ++j) {
@@ -266,8 +268,7 @@ void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocki
 }
 
 bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve *r) {
-    return r->n_dep > 0 || c->planes || s->spot_kind != MRT_SPOT_POINT || s->origins || s->directions ||
-           s->energies || s->polarisations;
+    return r->n_dep > 0 || c->planes || s->polarisations;
 }
 
 void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m,
@@ -393,6 +394,7 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
         const double sv = m->fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
         P.vmf_s2 = sv * sv;
         P.vmf_floor = std::exp(-2.0 / P.vmf_s2);
+        P.gau_2s2 = 2.0 * sv * sv;   // tan^2(theta) = 2 s^2 (-ln u) for the Gaussian tilt
         const double g = m->fwhm / 2.0;
         P.lor_g = g;
         P.wl_half_g2 = g * g / 2.0;

@@ -28,8 +28,9 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
                   std::vector<double> &tables);
 
 // True when the run needs the extended-input kernels: an energy-dependent
-// rocking curve, a source spot, user ray arrays (polarisations included) or
-// further reflecting planes.
+// rocking curve, user polarisations or further reflecting planes (the
+// per-event work they change).  Source spots and user origins, directions
+// and energies only change a ray's start, which every kernel takes.
 bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve *r);
 
 // The paper's event model: fill its part of the parameter block (sampler

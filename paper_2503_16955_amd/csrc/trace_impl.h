@@ -330,6 +330,12 @@ struct Tracer {
                 scale = R(1);
             }
             st = scale * dm::sqrt(arg);
+        } else if (mdf_is(P, MRT_MOSAIC_GAUSSIAN)) {
+            // regular Gaussian (Eq. Gaussian) as a tangent-plane bivariate
+            // normal: tan^2(theta) = 2 s^2 (-ln u), Rayleigh in the radius
+            const R t2 = -par<R>(P.gau_2s2, P.f32.gau_2s2) * dm::log_pos(u2);
+            ct = dm::rsqrt(R(1) + t2);
+            st = dm::sqrt(t2) * ct;
         } else if (mdf_is(P, MRT_MOSAIC_WRAPPED_LORENTZIAN)) {
             // Eq. WL: density in v proportional to 1 / (g^2 + 2 v)
             R v;
@@ -875,12 +881,10 @@ struct Tracer {
         return detected;
     }
 
-    // The photon energy: the user's array (EXT), else drawn from the spectrum.
+    // The photon energy: the user's array, else drawn from the spectrum.
     static __device__ __forceinline__ double ray_energy(const TraceParams &P, const double *cdf,
                                                         const dm::Words &a, uint64_t ray) {
-        if constexpr (EXT) {
-            if (P.user_e) return P.user_e[ray - P.first];
-        }
+        if (P.user_e) return P.user_e[ray - P.first];
         return energy(P, cdf, a, ray);
     }
     // Offset (x, y) of a ray's origin in the spot plane from uniforms u, v:
@@ -904,11 +908,14 @@ struct Tracer {
     // Start a ray: source direction and front-face entry.  On a hit, the
     // energy, Bragg angle and first exit distance follow and true is
     // returned; a miss is retired here (record written) and false returned.
+    // Every instance takes the source spot and the user's origins and
+    // directions, by a wave-uniform branch once per ray start: they change
+    // nothing after it.
     static __device__ __forceinline__ bool start(const TraceParams &P, const double *cdf,
                                                  uint64_t ray, RayT &ry) {
         const dm::Words a = dm::philox(P.key0, P.key1, 0u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
         V3<R> o, k;
-        if constexpr (EXT) {
+        if (P.user_o || P.user_k || P.spot_kind != MRT_SPOT_POINT) {
             const size_t i = (size_t)(ray - P.first);
             double od[3] = {P.so[0], P.so[1], P.so[2]};
             if (P.user_o) {
@@ -1206,10 +1213,10 @@ __global__ void __launch_bounds__(256) trace_kernel_ext(const TraceParams P) {
 #define MRT_TRACE_TABLE(FN, R, GEOM)                                                          \
     const void *FN(int mdf, int irc, bool rec) {                                               \
         using namespace tk;                                                                   \
-        static const void *const t[5][5][2] = {                                               \
+        static const void *const t[6][5][2] = {                                               \
             MRT_ROW(R, GEOM, 0), MRT_ROW(R, GEOM, 1), MRT_ROW(R, GEOM, 2), MRT_ROW(R, GEOM, 3), \
-            MRT_ROW(R, GEOM, 4)};                                                             \
-        if (mdf < 0 || mdf > 4 || irc < 0 || irc > 4) return nullptr;                         \
+            MRT_ROW(R, GEOM, 4), MRT_ROW(R, GEOM, 5)};                                        \
+        if (mdf < 0 || mdf > 5 || irc < 0 || irc > 4) return nullptr;                         \
         return t[mdf][irc][rec ? 1 : 0];                                                      \
     }
 #define MRT_PAIR(R, GEOM, M, I) \

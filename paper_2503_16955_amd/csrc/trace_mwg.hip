@@ -62,6 +62,13 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
                    (1.0 - P.m_eta) * density<MRT_MOSAIC_GAUSSIAN_VMF>(P, v);
         } else if constexpr (K == MRT_MOSAIC_WRAPPED_LORENTZIAN) {
             return P.wl_norm / (P.wl_g2 + 2.0 * v);
+        } else if constexpr (K == MRT_MOSAIC_GAUSSIAN) {
+            // the tangent-plane Gaussian at tan^2(theta) = v (2 - v) / c^2,
+            // times the gnomonic area ratio 1 / c^3; zero on the far side
+            const double c = 1.0 - v;
+            if (!(c > 0.0)) return 0.0;
+            const double ic = dm::rcp(c);
+            return P.gau_norm * (ic * ic * ic) * ::exp(-P.gau_inv2s2 * (v * (2.0 - v)) * (ic * ic));
         } else {
             const double d = P.swl_a + v;
             return P.swl_norm / (d * d);
@@ -73,6 +80,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
         case MRT_MOSAIC_LORENTZIAN: return density<MRT_MOSAIC_LORENTZIAN>(P, v);
         case MRT_MOSAIC_PSEUDO_VOIGT: return density<MRT_MOSAIC_PSEUDO_VOIGT>(P, v);
         case MRT_MOSAIC_WRAPPED_LORENTZIAN: return density<MRT_MOSAIC_WRAPPED_LORENTZIAN>(P, v);
+        case MRT_MOSAIC_GAUSSIAN: return density<MRT_MOSAIC_GAUSSIAN>(P, v);
         default: return density<MRT_MOSAIC_SPHERICAL_WRAPPED_LORENTZIAN>(P, v);
         }
     }
@@ -132,6 +140,9 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             break;
         case MRT_MOSAIC_WRAPPED_LORENTZIAN:
             psi_pair<MRT_MOSAIC_WRAPPED_LORENTZIAN, C2>(P, alpha, beta, ih, ia, i2h, i2a);
+            break;
+        case MRT_MOSAIC_GAUSSIAN:
+            psi_pair<MRT_MOSAIC_GAUSSIAN, C2>(P, alpha, beta, ih, ia, i2h, i2a);
             break;
         default:
             psi_pair<MRT_MOSAIC_SPHERICAL_WRAPPED_LORENTZIAN, C2>(P, alpha, beta, ih, ia, i2h, i2a);

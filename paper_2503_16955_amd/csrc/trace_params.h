@@ -23,7 +23,8 @@ constexpr int kMaxTableBytes = 64 * 1024;
 #define MRT_F32_SCALARS(X)                                                                    \
     X(vmax) X(hl) X(hw) X(T) X(R2) X(Ro2) X(inv_mu0) X(inv_mu_tot) X(p_a) X(inv_1mpa)          \
     X(m_eta) X(inv_eta) X(inv_1meta) X(vmf_s2) X(vmf_floor) X(lor_g) X(wl_half_g2) X(wl_z)     \
-    X(swl_k) X(swl_d) X(shift) X(g_k) X(g_k_log2e) X(pv_a) X(pv_b) X(pv_h2) X(lor_h2)          \
+    X(swl_k) X(swl_d) X(gau_2s2) X(shift) X(g_k) X(g_k_log2e) X(pv_a) X(pv_b) X(pv_h2)         \
+    X(lor_h2)                                                                                  \
     X(box_half) X(lut_x0) X(lut_x1) X(pitch) X(half_nx) X(half_ny)
 #define MRT_F32_VECTORS(X) \
     X(so) X(sa) X(sb1) X(sb2) X(N) X(e1) X(e2) X(ax) X(op) X(om) X(dP) X(dn) X(du) X(dv)
@@ -77,6 +78,7 @@ struct TraceParams {
     double lor_g;                 // Gamma / 2
     double wl_half_g2, wl_z;      // g^2 / 2 and ln((g^2 + 4) / g^2)
     double swl_k, swl_d;          // 4 sinh^2(Gamma / 4) and cosh(Gamma / 2) + 1
+    double gau_2s2;               // 2 s^2, s = Gamma / (2 sqrt(2 ln 2)): the Gaussian tilt
 
     // ---- rocking curve (sec. 2.2.1), all as r(x) / R_max
     int32_t irc, lut_n;
@@ -99,6 +101,7 @@ struct TraceParams {
     double cau_g2, cau_norm;      // (Gamma/2)^2 and (Gamma/2) / (2 pi)
     double wl_g2, wl_norm;        // (Gamma/2)^2 and 1 / (pi ln((g^2 + 4) / g^2))
     double swl_a, swl_norm;       // 2 sinh^2(Gamma/4) and A (A + 2) / (4 pi)
+    double gau_inv2s2, gau_norm;  // 1 / (2 s^2) and 1 / (2 pi s^2)
     const double *psi_tab;        // (sin(psi_j / 2), psi_j - psi_{j-1}), j = 0..M (device)
     const double *psi_cos2;       // cos(2 psi_j), j = 0..M (device; after psi_tab)
 

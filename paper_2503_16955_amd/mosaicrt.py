@@ -24,7 +24,7 @@ SPECTRUM = {"uniform": 0, "lines": 1, "table": 2}
 GEOMETRY = {"flat": 0, "cylinder": 1}
 SPOT = {"point": 0, "gaussian": 1, "disk": 2}
 MOSAIC = {"gaussian_vmf": 0, "lorentzian": 1, "pseudo_voigt": 2, "wrapped_lorentzian": 3,
-          "spherical_wrapped_lorentzian": 4}
+          "spherical_wrapped_lorentzian": 4, "gaussian": 5}
 ROCKING = {"gaussian": 0, "pseudo_voigt": 1, "table": 2, "lorentzian": 3, "box": 4}
 PRECISION = {"fp64": 0, "fp32_mixed": 1}
 RECORDS = {None: 0, "none": 0, "all": 1, "detected": 2}
@@ -309,9 +309,10 @@ def alloc_images(w, device="cuda", energy=True):
 
 def uses_extended_inputs(w, rays=None):
     """Whether workload `w` (with user ray arrays `rays`) runs the
-    extended-input kernels: a source spot, user arrays, an energy-dependent
-    curve or further planes."""
-    return bool(rays) or (w["source"].get("spot") or {}).get("kind", "point") != "point" \
+    extended-input kernels: user polarisations, an energy-dependent curve or
+    further planes (source spots and user origins, directions and energies
+    run in the kernels specialised for the kinds)."""
+    return (rays or {}).get("polarisations") is not None \
         or bool(w["rocking_curve"].get("energy_dependence")) or w["crystal"].get("planes") is not None
 
 

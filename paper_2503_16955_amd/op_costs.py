@@ -191,6 +191,8 @@ def mix(precision, geometry, mosaic, irc, spectrum, mosaic_eta=0.0):
                + R["sqrt"] + a)
     elif mosaic == "wrapped_lorentzian":
         mdf = R["expm1"] + R["sqrt"] + 7 * a
+    elif mosaic == "gaussian":
+        mdf = R["log"] + R["rsqrt"] + R["sqrt"] + 4 * a
     else:
         mdf = R["div"] + R["sqrt"] + 7 * a
     kn = 3 * d if precision == "fp64" else 9 * d
@@ -229,7 +231,8 @@ def _density_cost(mosaic):
     cau = D["sqrt"] + D["div"] + 7 * a
     return {"gaussian_vmf": vmf, "lorentzian": cau, "pseudo_voigt": vmf + cau + 3 * a,
             "wrapped_lorentzian": D["div"] + 2 * a,
-            "spherical_wrapped_lorentzian": D["div"] + 3 * a}[mosaic]
+            "spherical_wrapped_lorentzian": D["div"] + 3 * a,
+            "gaussian": D["rcp"] + D["exp"] + 9 * a}[mosaic]
 
 
 def _irc_cost(irc):

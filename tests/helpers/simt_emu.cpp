@@ -357,9 +357,8 @@ int emu_trace(TraceParams *P, int n_waves, int precision, long long max_meetings
         int e = run_wave([&] {
             const bool rec = P->records_mode != MRT_RECORDS_NONE;
             // the extended-input kernel: energy-dependent rocking curve,
-            // source spot, user ray arrays
-            if (P->dep_n > 0 || P->spot_kind != MRT_SPOT_POINT || P->user_o || P->user_k || P->user_e ||
-                P->user_p || P->has_planes) {
+            // polarisations, further planes (the kernel the device takes)
+            if (P->dep_n > 0 || P->user_p || P->has_planes) {
                 if (precision == MRT_FP64) { if (rec) trace_body<double, true, true>(*P, q.b); else trace_body<double, false, true>(*P, q.b); }
                 else { if (rec) trace_body<float, true, true>(*P, q.b); else trace_body<float, false, true>(*P, q.b); }
             } else if (precision == MRT_FP64) { if (rec) trace_body<double, true>(*P, q.b); else trace_body<double, false>(*P, q.b); }

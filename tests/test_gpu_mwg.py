@@ -52,6 +52,7 @@ MOSAICS = {
     "pseudo_voigt": dict(kind="pseudo_voigt", fwhm=0.3 * DEG, eta=0.4),
     "wrapped_lorentzian": dict(kind="wrapped_lorentzian", fwhm=0.2 * DEG, eta=0.0),
     "spherical_wrapped_lorentzian": dict(kind="spherical_wrapped_lorentzian", fwhm=0.3 * DEG, eta=0.0),
+    "gaussian": dict(kind="gaussian", fwhm=0.3 * DEG, eta=0.0),
 }
 IRCS = {
     "gaussian": dict(kind="gaussian", peak=0.5, shift=10e-6, fwhm=50e-6),

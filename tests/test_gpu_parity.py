@@ -101,6 +101,7 @@ MOSAICS = {
     "wrapped_lorentzian": dict(kind="wrapped_lorentzian", fwhm=0.1 * W.DEG, eta=0.0),
     "spherical_wrapped_lorentzian": dict(kind="spherical_wrapped_lorentzian", fwhm=0.3 * W.DEG,
                                          eta=0.0),
+    "gaussian": dict(kind="gaussian", fwhm=0.4 * W.DEG, eta=0.0),
 }
 
 
@@ -487,6 +488,34 @@ def test_fp32_mixed_matches_fp64_statistically():
           f"fp64 {control:.4f}", flush=True)
     assert same < 0.05
     assert 0.95 <= chi2 <= 1.05 and 0.95 <= control <= 1.05
+
+
+def test_vmf_and_regular_gaussian_mosaic_give_the_same_spectrum():
+    """Fig. MF_vs_G: the von Mises-Fisher distribution of Eq. MF and the
+    regular Gaussian, both of mosaicity 1 deg, give practically the same
+    spectrum.  Von Hamos crystal, one 8.048 keV line (sigma 2 eV), 2e8
+    FP32-mixed rays each, independent seeds: the line's centroid and width
+    (over +-60 px: the 1 deg mosaic widens it to ~30 px) agree and the
+    images are indistinguishable by chi-square per pixel.  (The Gaussian's
+    kernel is checked ray by ray against the oracle in test_mosaic_kinds.)"""
+    n = 200_000_000
+    imgs = {}
+    for kind, seed in (("gaussian_vmf", 11), ("gaussian", 12)):
+        w = W.get("von_hamos_hapg")
+        w["source"].update(lines=[(8.048, 0.002, 1.0)], background_w=0.0)
+        w["mosaic"] = dict(kind=kind, fwhm=1.0 * W.DEG, eta=0.0)
+        r = mrt.trace(w, n_rays=n, seed=seed, precision="fp32_mixed")
+        imgs[kind] = mrt.image_to_numpy(r["counts"])[0]
+    a, b = imgs["gaussian_vmf"], imgs["gaussian"]
+    pa, pb = parity.projected_profile(a), parity.projected_profile(b)
+    col = _line_column(w, 8.048)
+    ca, cb = parity.centroid(pa, col, half=60), parity.centroid(pb, col, half=60)
+    fa, fb = parity.fwhm(pa, col, half=60), parity.fwhm(pb, col, half=60)
+    print(f"[mf-vs-g] centroid {ca:.3f} / {cb:.3f} px, fwhm {fa:.3f} / {fb:.3f} px", flush=True)
+    assert abs(ca - cb) < 0.05 and abs(fa - fb) < 0.02 * fa
+    chi2 = parity.chi2_per_pixel(b, a)
+    print(f"[mf-vs-g] chi2/px {chi2:.4f}", flush=True)
+    assert 0.95 <= chi2 <= 1.05
 
 
 def _line_column(w, e_kev):

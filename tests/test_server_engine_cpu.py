@@ -143,12 +143,14 @@ def test_every_ray_of_every_request_exactly_once(lib):
 
 
 def test_mixed_plain_and_extended_requests_each_ray_once(lib):
-    """Requests using extended inputs (here a source spot) share rounds with
-    plain ones: the round is staged as two item groups traced by two
-    launches, and still every ray of every request is traced exactly once."""
+    """Requests using extended inputs (here an energy-dependent rocking
+    curve) share rounds with plain ones: the round is staged as two item
+    groups traced by two launches, and still every ray of every request is
+    traced exactly once.  (A source spot alone runs in the plain group.)"""
     lib.harness_init(DEVICE_BYTES, 0)
     plain = W.get("flat_hopg")
-    spot = W.with_spot(W.get("flat_hopg"))
+    spot = W.get("flat_hopg")
+    spot["rocking_curve"]["energy_dependence"] = [(7.8, 0.0, 1.0), (8.2, 5e-6, 1.2)]
     px = plain["detector"]["nx"] * plain["detector"]["ny"]
     reqs = [(plain, 3000, 21), (spot, 5000, 22), (plain, 777, 23), (spot, 64, 24), (spot, 20_001, 25)]
     s = Srv(lib)
