@@ -275,6 +275,54 @@ def extended_inputs(mrt, W, op_costs, w, n, steps, warmup, cus, plain):
     return out
 
 
+def burn_in_study(mrt, W, precision, n, burn_ins=(0, 100, 500, 1500), half=40):
+    """The paper's burn-in figure (sec. 2.2.4, Fig. BurnIn): the instrument
+    function of an 8.5 keV point source on a von Hamos spectrometer aimed at
+    8.5 keV (Lorentzian mosaic 0.14 deg, Voigt curve 50.7 / 10.0 urad), in
+    the stepping model (exact at any burn-in: it draws each crystallite
+    directly) and in the paper's event model at several burn-ins of its
+    Metropolis-within-Gibbs sampler, n rays each at independent seeds, FP64.
+    Per run: the line's centroid and FWHM over +-half pixels of the focus
+    and the chi-square per pixel against the stepping image (1 for
+    independent images of one mean; the stepping model at another seed is
+    the control), with the kernel time."""
+    import copy
+    w = W.get("von_hamos_burn_in")
+    col = precision.von_hamos_line_column(w, 8.5)
+
+    def run(wl, seed):
+        r = mrt.trace(wl, n_rays=n, seed=seed, precision="fp64", want_energy=False)
+        img = mrt.image_to_numpy(r["counts"])[0]
+        del r["counts"]
+        return img, r["counters"]["kernel_ms"]
+
+    ref, ms_ref = run(w, 100)
+    pref = precision.dispersive_profile(ref)
+
+    def summary(img, ms):
+        p = precision.dispersive_profile(img)
+        c, f = precision.centroid(p, col, half), precision.fwhm(p, col, half)
+        return {"kernel_ms": round(ms, 3), "centroid_px": round(c, 4),
+                "centroid_shift_px": round(c - precision.centroid(pref, col, half), 4),
+                "fwhm_px": round(f, 4),
+                "fwhm_change": round(f / precision.fwhm(pref, col, half) - 1.0, 5),
+                "chi2_per_px": round(precision.chi2_per_pixel(img, ref), 4)}
+
+    out = {"workload": "von_hamos_burn_in: 8.5 keV point source, von Hamos R=80 mm aimed at "
+                       "8.5 keV, Lorentzian mosaic 0.14 deg, Voigt curve 50.7/10.0 urad, FP64",
+           "rays": n, "focus_col": round(col, 3),
+           "stepping": {"kernel_ms": round(ms_ref, 3),
+                        "centroid_px": round(precision.centroid(pref, col, half), 4),
+                        "fwhm_px": round(precision.fwhm(pref, col, half), 4)}}
+    out["stepping_control"] = summary(*run(w, 101))
+    for b in burn_ins:
+        wm = copy.deepcopy(w)
+        wm["event_model"] = {"kind": "mwg", "burn_in": b, "psi_nodes": 256}
+        out[f"mwg_burn_in_{b}"] = summary(*run(wm, 200 + b))
+        log(f"burn-in {b}: {out[f'mwg_burn_in_{b}']}")
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -505,6 +553,9 @@ def main():
     ap.add_argument("--mwg-psi-nodes", type=int, default=256)
     ap.add_argument("--mwg-cpu-rays", type=int, default=20_000_000)
     ap.add_argument("--no-mwg", action="store_true")
+    ap.add_argument("--no-burn-in", action="store_true",
+                    help="skip the burn-in study (stepping vs the paper's model, Fig. BurnIn)")
+    ap.add_argument("--burn-in-rays", type=int, default=100_000_000)
     ap.add_argument("--no-stress", action="store_true",
                     help="skip the stress workload (2e9 rays per precision)")
     ap.add_argument("--no-extended", action="store_true",
@@ -598,6 +649,8 @@ def main():
                                      0 if a.no_cpu_baseline else a.mwg_cpu_rays, value)
         log(f"paper's model: {res['mwg_model']['value']:.3e} rays/s, "
             f"{res['mwg_model']['ms_per_step']} ms per step")
+    if not a.no_burn_in and not a.no_mwg:
+        res["burn_in_study"] = burn_in_study(mrt, W, precision, a.burn_in_rays)
     res["serving"] = None if a.no_serving else serving(
         mrt, W, op_costs, info["compute_units"], a.serving_requests, a.serving_budget_mib << 20, 64,
         a.serving_load, round_rays=a.serving_round_rays)

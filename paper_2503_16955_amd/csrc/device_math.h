@@ -44,11 +44,14 @@ __device__ __forceinline__ Words philox(uint32_t k0, uint32_t k1, uint32_t c0, u
     return Words{c0, c1, c2, c3};
 }
 
-// Uniforms in the open interval (0, 1).
-__device__ __forceinline__ double u01_f64(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
-// 23 random bits, exact in float: ((w >> 9) + 1/2) 2^-23.
+// Uniforms in the open interval (0, 1): (w + 1/2) 2^-32 as one fused
+// multiply-add (exact: 33 significant bits).
+__device__ __forceinline__ double u01_f64(uint32_t w) { return __builtin_fma((double)w, 0x1p-32, 0x1p-33); }
+// 23 random bits, exact in float: ((w >> 9) + 1/2) 2^-23, as one fused
+// multiply-add of the exactly converted w >> 9 (the result has 24
+// significant bits, so nothing rounds).
 __device__ __forceinline__ float u01_f32(uint32_t w) {
-    return (float)(((w >> 9) << 1) | 1u) * 0x1p-24f;
+    return __builtin_fmaf((float)(w >> 9), 0x1p-23f, 0x1p-24f);
 }
 
 // Polynomial step p z + c as the three-operand v_fma_f64 with the constant

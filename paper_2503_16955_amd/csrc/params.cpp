@@ -275,25 +275,52 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
                   const mrt_rocking_curve *r, const mrt_detector *d, TraceParams &P,
                   std::vector<double> &tables) {
     std::memset(&P, 0, sizeof P);
-    // local origin
-    double O[3];
+    // Crystal-local frame: origin O and rows of the rotation `rot` (the
+    // local axes in global coordinates).  FLAT: x along e1, y along
+    // e2 = normal x e1, z along the normal.  CYLINDER: z along the axis,
+    // x along ref_dir (azimuth 0), y along axis x ref_dir.  In it the flat
+    // crystal's frame and the cylinder's axis are the coordinate axes, which
+    // the kernels use as constants.
+    double O[3], X[3], Y[3], Z[3];
     if (c->geometry == MRT_GEOMETRY_FLAT) {
-        for (int i = 0; i < 3; ++i) O[i] = c->centre[i];
+        for (int i = 0; i < 3; ++i) { O[i] = c->centre[i]; X[i] = c->e1[i]; Z[i] = c->normal[i]; }
+        cross3(c->normal, c->e1, Y);
     } else {
-        for (int i = 0; i < 3; ++i) O[i] = c->axis_pt[i] + c->z_c * c->axis_dir[i];
+        for (int i = 0; i < 3; ++i) {
+            O[i] = c->axis_pt[i] + c->z_c * c->axis_dir[i];
+            X[i] = c->ref_dir[i];
+            Z[i] = c->axis_dir[i];
+        }
+        cross3(c->axis_dir, c->ref_dir, Y);
     }
-    for (int i = 0; i < 3; ++i) P.origin[i] = O[i];
+    for (int i = 0; i < 3; ++i) {
+        P.origin[i] = O[i];
+        P.rot[0][i] = X[i];
+        P.rot[1][i] = Y[i];
+        P.rot[2][i] = Z[i];
+    }
+    // local coordinates of a global direction / position
+    auto dir = [&](const double *g, double *l) {
+        for (int r = 0; r < 3; ++r) l[r] = P.rot[r][0] * g[0] + P.rot[r][1] * g[1] + P.rot[r][2] * g[2];
+    };
+    auto pos = [&](const double *g, double *l) {
+        const double d[3] = {g[0] - O[0], g[1] - O[1], g[2] - O[2]};
+        dir(d, l);
+    };
 
     // source
-    for (int i = 0; i < 3; ++i) {
-        P.so[i] = s->origin[i] - O[i];
-        P.sa[i] = s->axis[i];
-        P.sb1[i] = s->b1[i];
+    pos(s->origin, P.so);
+    dir(s->axis, P.sa);
+    dir(s->b1, P.sb1);
+    {
+        double b2[3];
+        cross3(s->axis, s->b1, b2);
+        dir(b2, P.sb2);
     }
-    cross3(s->axis, s->b1, P.sb2);
     P.spot_kind = s->spot_kind;
     if (s->spot_kind != MRT_SPOT_POINT) {
-        for (int i = 0; i < 3; ++i) { P.spot_u[i] = s->spot_u[i]; P.spot_v[i] = s->spot_v[i]; }
+        dir(s->spot_u, P.spot_u);
+        dir(s->spot_v, P.spot_v);
         P.spot_sigma[0] = s->spot_sigma[0];
         P.spot_sigma[1] = s->spot_kind == MRT_SPOT_GAUSSIAN ? s->spot_sigma[1] : 0.0;
     }
@@ -326,19 +353,14 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
     P.hl = c->length / 2.0;
     P.hw = c->width / 2.0;
     P.T = c->thickness;
-    if (c->geometry == MRT_GEOMETRY_FLAT) {
-        for (int i = 0; i < 3; ++i) { P.N[i] = c->normal[i]; P.e1[i] = c->e1[i]; }
-        cross3(c->normal, c->e1, P.e2);
-    } else {
-        double b2[3];
-        cross3(c->axis_dir, c->ref_dir, b2);
+    if (c->geometry != MRT_GEOMETRY_FLAT) {
+        // outward normals of the two azimuth edges, in the local x-y plane
         const double half = c->width / (2.0 * c->radius);
         const double pp = c->phi_c + half, pm = c->phi_c - half;
-        for (int i = 0; i < 3; ++i) {
-            P.ax[i] = c->axis_dir[i];
-            P.op[i] = -std::sin(pp) * c->ref_dir[i] + std::cos(pp) * b2[i];
-            P.om[i] = std::sin(pm) * c->ref_dir[i] - std::cos(pm) * b2[i];
-        }
+        P.op[0] = -std::sin(pp);
+        P.op[1] = std::cos(pp);
+        P.om[0] = std::sin(pm);
+        P.om[1] = -std::cos(pm);
         P.R = c->radius;
         P.R2 = c->radius * c->radius;
         const double ro = c->radius + c->thickness;
@@ -455,12 +477,10 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
     }
 
     // detector
-    for (int i = 0; i < 3; ++i) {
-        P.dP[i] = d->centre[i] - O[i];
-        P.dn[i] = d->normal[i];
-        P.du[i] = d->u[i];
-        P.dv[i] = d->v[i];
-    }
+    pos(d->centre, P.dP);
+    dir(d->normal, P.dn);
+    dir(d->u, P.du);
+    dir(d->v, P.dv);
     P.nx = d->nx;
     P.ny = d->ny;
     P.pitch = d->pitch;

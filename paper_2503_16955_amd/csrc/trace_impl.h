@@ -207,35 +207,32 @@ struct Tracer {
         else return IRC == k;
     }
 
-    // ---- crystal geometry (sec. 2.2) ------------------------------------
+    // ---- crystal geometry (sec. 2.2), in the crystal-local frame ----------
+    // Flat: front face z = 0 with the normal +z toward the source, length
+    // along x, width along y.  Cylinder: axis z, radius rho = |(x, y)|.
+    // (x, y)-plane dot product with an edge normal (whose z is 0).
+    static __device__ __forceinline__ R dot_xy(V3<R> a, const double *d, const float *f) {
+        const V3<R> b = par3<R>(d, f);
+        return a.x * b.x + a.y * b.y;
+    }
     // Front-face entry; false on a miss.
     static __device__ __forceinline__ bool entry(const TraceParams &P, V3<R> o, V3<R> k, R &t) {
         if (is_flat(P)) {
-            const V3<R> N = par3<R>(P.N, P.f32.N);
-            const R zeta = dot(o, N), kn = dot(k, N);
-            if (!(kn < R(0))) return false;
-            t = -zeta / kn;
+            if (!(k.z < R(0))) return false;
+            t = -o.z / k.z;
             if (!(t > R(0))) return false;
-            const V3<R> h = axpy(o, t, k);
-            const R xi = dot(h, par3<R>(P.e1, P.f32.e1)), eta = dot(h, par3<R>(P.e2, P.f32.e2));
-            return __builtin_fabs(xi) <= par<R>(P.hl, P.f32.hl) && __builtin_fabs(eta) <= par<R>(P.hw, P.f32.hw);
+            const R hx = o.x + t * k.x, hy = o.y + t * k.y;
+            return __builtin_fabs(hx) <= par<R>(P.hl, P.f32.hl) && __builtin_fabs(hy) <= par<R>(P.hw, P.f32.hw);
         } else {
-            const V3<R> ax = par3<R>(P.ax, P.f32.ax);
-            const R ka = dot(k, ax);
-            const V3<R> kp = axpy(k, -ka, ax);
-            const R zo = dot(o, ax);
-            const V3<R> rho = axpy(o, -zo, ax);
-            const R a = dot(kp, kp), b = dot(rho, kp);
-            const R cc = dot(rho, rho) - par<R>(P.R2, P.f32.R2);
+            const R a = k.x * k.x + k.y * k.y, b = o.x * k.x + o.y * k.y;
+            const R cc = o.x * o.x + o.y * o.y - par<R>(P.R2, P.f32.R2);
             if (!(cc < R(0)) || !(a > R(0))) return false;
             const R disc = b * b - a * cc;
             const R sq = dm::sqrt(disc);
             t = b >= R(0) ? -cc / (b + sq) : (-b + sq) / a;
             const V3<R> h = axpy(o, t, k);
-            const R zh = dot(h, ax);
-            const V3<R> rh = axpy(h, -zh, ax);
-            return __builtin_fabs(zh) <= par<R>(P.hl, P.f32.hl) && dot(rh, par3<R>(P.op, P.f32.op)) <= R(0) &&
-                   dot(rh, par3<R>(P.om, P.f32.om)) <= R(0);
+            return __builtin_fabs(h.z) <= par<R>(P.hl, P.f32.hl) && dot_xy(h, P.op, P.f32.op) <= R(0) &&
+                   dot_xy(h, P.om, P.f32.om) <= R(0);
         }
     }
 
@@ -244,9 +241,8 @@ struct Tracer {
     static __device__ __forceinline__ R exit_distance(const TraceParams &P, V3<R> p, V3<R> k) {
         R t = R(INFINITY);
         if (is_flat(P)) {
-            const V3<R> N = par3<R>(P.N, P.f32.N), e1 = par3<R>(P.e1, P.f32.e1), e2 = par3<R>(P.e2, P.f32.e2);
-            const R zeta = dot(p, N), xi = dot(p, e1), eta = dot(p, e2);
-            const R kn = dot(k, N), k1 = dot(k, e1), k2 = dot(k, e2);
+            const R zeta = p.z, xi = p.x, eta = p.y;
+            const R kn = k.z, k1 = k.x, k2 = k.y;
             const R hl = par<R>(P.hl, P.f32.hl), hw = par<R>(P.hw, P.f32.hw), T = par<R>(P.T, P.f32.T);
             if (kn > R(0)) t = fminr(t, -zeta / kn);
             if (kn < R(0)) t = fminr(t, (-T - zeta) / kn);
@@ -255,10 +251,8 @@ struct Tracer {
             if (k2 > R(0)) t = fminr(t, (hw - eta) / k2);
             if (k2 < R(0)) t = fminr(t, (-hw - eta) / k2);
         } else {
-            const V3<R> ax = par3<R>(P.ax, P.f32.ax);
-            const R z = dot(p, ax), ka = dot(k, ax);
-            const V3<R> rho = axpy(p, -z, ax), kp = axpy(k, -ka, ax);
-            const R a = dot(kp, kp), b = dot(rho, kp), r2 = dot(rho, rho);
+            const R z = p.z, ka = k.z;
+            const R a = k.x * k.x + k.y * k.y, b = p.x * k.x + p.y * k.y, r2 = p.x * p.x + p.y * p.y;
             if (a > R(0)) {
                 const R co = r2 - par<R>(P.Ro2, P.f32.Ro2);
                 R disc = b * b - a * co;
@@ -275,10 +269,9 @@ struct Tracer {
             const R hl = par<R>(P.hl, P.f32.hl);
             if (ka > R(0)) t = fminr(t, (hl - z) / ka);
             if (ka < R(0)) t = fminr(t, (-hl - z) / ka);
-            const V3<R> op = par3<R>(P.op, P.f32.op), om = par3<R>(P.om, P.f32.om);
-            const R kop = dot(k, op), kom = dot(k, om);
-            if (kop > R(0)) t = fminr(t, -dot(rho, op) / kop);
-            if (kom > R(0)) t = fminr(t, -dot(rho, om) / kom);
+            const R kop = dot_xy(k, P.op, P.f32.op), kom = dot_xy(k, P.om, P.f32.om);
+            if (kop > R(0)) t = fminr(t, -dot_xy(p, P.op, P.f32.op) / kop);
+            if (kom > R(0)) t = fminr(t, -dot_xy(p, P.om, P.f32.om) / kom);
         }
         return t > R(0) ? t : R(0);
     }
@@ -301,8 +294,26 @@ struct Tracer {
         ct = q * rs;
         st = g * dm::sqrt(om) * rs;
     }
-    static __device__ __forceinline__ V3<R> mosaic_normal(const TraceParams &P, R u2, R u3, V3<R> N,
-                                                          V3<R> e1, V3<R> e2) {
+    // Local surface frame at a point: N toward the source side, e1 along
+    // the length axis (flat) or the cylinder axis, e2 = N x e1.  Flat: the
+    // coordinate axes z, x, y.  Cylinder: N = (nx, ny, 0) points to the
+    // axis, e1 = z, e2 = (ny, -nx, 0).
+    struct Frame {
+        R nx, ny;   // the cylinder's N (unused for the flat crystal)
+    };
+    static __device__ __forceinline__ Frame frame(const TraceParams &P, V3<R> p) {
+        if (is_flat(P)) return Frame{R(0), R(0)};
+        const R inv = dm::rsqrt(p.x * p.x + p.y * p.y);
+        return Frame{-p.x * inv, -p.y * inv};
+    }
+    // The surface normal alone, as a vector.
+    static __device__ __forceinline__ V3<R> normal_at(const TraceParams &P, V3<R> p) {
+        if (is_flat(P)) return V3<R>{R(0), R(0), R(1)};
+        const Frame f = frame(P, p);
+        return V3<R>{f.nx, f.ny, R(0)};
+    }
+    static __device__ __forceinline__ V3<R> mosaic_normal(const TraceParams &P, R u2, R u3,
+                                                          Frame f) {
         R ct, st;
         if (mdf_is(P, MRT_MOSAIC_GAUSSIAN_VMF)) {
             vmf(P, u2, ct, st);
@@ -357,27 +368,10 @@ struct Tracer {
         }
         R sx, cx;
         dm::sincos_turns(u3, &sx, &cx);
-        return V3<R>{ct * N.x + st * (cx * e1.x + sx * e2.x),
-                     ct * N.y + st * (cx * e1.y + sx * e2.y),
-                     ct * N.z + st * (cx * e1.z + sx * e2.z)};
-    }
-
-    // Local surface frame at p: N toward the source side, e1 along the length
-    // axis (flat) or the cylinder axis, e2 = N x e1.
-    static __device__ __forceinline__ void frame(const TraceParams &P, V3<R> p, V3<R> &N, V3<R> &e1,
-                                                 V3<R> &e2) {
-        if (is_flat(P)) {
-            N = par3<R>(P.N, P.f32.N);
-            e1 = par3<R>(P.e1, P.f32.e1);
-            e2 = par3<R>(P.e2, P.f32.e2);
-        } else {
-            const V3<R> ax = par3<R>(P.ax, P.f32.ax);
-            const V3<R> rho = axpy(p, -dot(p, ax), ax);
-            const R inv = dm::rsqrt(dot(rho, rho));
-            N = V3<R>{-rho.x * inv, -rho.y * inv, -rho.z * inv};
-            e1 = ax;
-            e2 = cross(N, e1);
-        }
+        // n = ct N + st (cx e1 + sx e2)
+        if (is_flat(P)) return V3<R>{st * cx, st * sx, ct};
+        const R ss = st * sx;
+        return V3<R>{ct * f.nx + ss * f.ny, ct * f.ny - ss * f.nx, st * cx};
     }
 
     // ---- rocking curve (sec. 2.2.1): r(x) / R_max at x = Delta - Delta_M ---
@@ -598,9 +592,7 @@ struct Tracer {
         if (!(ry.sa < 1.0)) return -1;         // no Bragg angle: never reflects
         const R u_acc = (u1 - pa) * par<R>(P.inv_1mpa, P.f32.inv_1mpa);
 
-        V3<R> N, e1, e2;
-        frame(P, ry.p, N, e1, e2);
-        const V3<R> n = mosaic_normal(P, uni<R>(w.w2), uni<R>(w.w3), N, e1, e2);
+        const V3<R> n = mosaic_normal(P, uni<R>(w.w2), uni<R>(w.w3), frame(P, ry.p));
         // Bragg deviation in FP64, k.n accumulated in FP64 from the components
         const double kn = (double)ry.k.x * (double)n.x + (double)ry.k.y * (double)n.y +
                           (double)ry.k.z * (double)n.z;
@@ -803,15 +795,16 @@ struct Tracer {
             const double nan = __builtin_nan("");
             r->ray_id = ry.id;
             r->energy_kev = ry.E;
-            r->entry[0] = miss ? nan : (double)ry.entry.x + P.origin[0];
-            r->entry[1] = miss ? nan : (double)ry.entry.y + P.origin[1];
-            r->entry[2] = miss ? nan : (double)ry.entry.z + P.origin[2];
-            r->end[0] = miss ? nan : (double)end.x + P.origin[0];
-            r->end[1] = miss ? nan : (double)end.y + P.origin[1];
-            r->end[2] = miss ? nan : (double)end.z + P.origin[2];
-            r->dir[0] = ry.k.x;
-            r->dir[1] = ry.k.y;
-            r->dir[2] = ry.k.z;
+            // global coordinates: origin + local vector through the rotation
+            const double ex = ry.entry.x, ey = ry.entry.y, ez = ry.entry.z;
+            const double qx = end.x, qy = end.y, qz = end.z;
+            const double kx = ry.k.x, ky = ry.k.y, kz = ry.k.z;
+            for (int c = 0; c < 3; ++c) {
+                const double rx = P.rot[0][c], ryy = P.rot[1][c], rz = P.rot[2][c];
+                r->entry[c] = miss ? nan : P.origin[c] + (rx * ex + ryy * ey + rz * ez);
+                r->end[c] = miss ? nan : P.origin[c] + (rx * qx + ryy * qy + rz * qz);
+                r->dir[c] = rx * kx + ryy * ky + rz * kz;
+            }
             r->pix_i = pi;
             r->pix_j = pj;
             r->n_events = ry.nev;
@@ -881,6 +874,11 @@ struct Tracer {
         return detected;
     }
 
+    // Local components of a global direction (rows of the frame's rotation).
+    static __device__ __forceinline__ void local(const TraceParams &P, const double *g, double *l) {
+        for (int r = 0; r < 3; ++r) l[r] = P.rot[r][0] * g[0] + P.rot[r][1] * g[1] + P.rot[r][2] * g[2];
+    }
+
     // The photon energy: the user's array, else drawn from the spectrum.
     static __device__ __forceinline__ double ray_energy(const TraceParams &P, const double *cdf,
                                                         const dm::Words &a, uint64_t ray) {
@@ -920,7 +918,9 @@ struct Tracer {
             double od[3] = {P.so[0], P.so[1], P.so[2]};
             if (P.user_o) {
                 // user origins, global coordinates
-                for (int c = 0; c < 3; ++c) od[c] = P.user_o[3 * i + c] - P.origin[c];
+                const double g[3] = {P.user_o[3 * i] - P.origin[0], P.user_o[3 * i + 1] - P.origin[1],
+                                     P.user_o[3 * i + 2] - P.origin[2]};
+                local(P, g, od);
             } else if (P.spot_kind != MRT_SPOT_POINT) {
                 // finite source spot (sec. 4.2): words 1, 2 of the source's second draw
                 const dm::Words b = dm::philox(P.key0, P.key1, 1u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
@@ -929,9 +929,13 @@ struct Tracer {
                 for (int c = 0; c < 3; ++c) od[c] += x * P.spot_u[c] + y * P.spot_v[c];
             }
             o = V3<R>{cvt<R>(od[0]), cvt<R>(od[1]), cvt<R>(od[2])};
-            k = P.user_k ? V3<R>{cvt<R>(P.user_k[3 * i]), cvt<R>(P.user_k[3 * i + 1]),
-                                 cvt<R>(P.user_k[3 * i + 2])}
-                         : direction(P, a);
+            if (P.user_k) {
+                double kd[3];
+                local(P, &P.user_k[3 * i], kd);
+                k = V3<R>{cvt<R>(kd[0]), cvt<R>(kd[1]), cvt<R>(kd[2])};
+            } else {
+                k = direction(P, a);
+            }
         } else {
             o = par3<R>(P.so, P.f32.so);
             k = direction(P, a);
@@ -943,8 +947,9 @@ struct Tracer {
         if constexpr (POL) {
             if (P.user_p) {
                 const size_t i = (size_t)(ray - P.first);
-                ry.pol = V3<R>{cvt<R>(P.user_p[3 * i]), cvt<R>(P.user_p[3 * i + 1]),
-                               cvt<R>(P.user_p[3 * i + 2])};
+                double pd[3];
+                local(P, &P.user_p[3 * i], pd);
+                ry.pol = V3<R>{cvt<R>(pd[0]), cvt<R>(pd[1]), cvt<R>(pd[2])};
             } else {
                 ry.pol = V3<R>{R(0), R(0), R(0)};
             }

@@ -180,8 +180,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
         ++ry.nev;
         const int exit_status = ry.nrefl ? MRT_EXIT_REFLECTED : MRT_EXIT_TRANSMITTED;
         const double dist = B::exit_distance(P, ry.p, ry.k);
-        V3<double> N, e1, e2;
-        B::frame(P, ry.p, N, e1, e2);
+        const V3<double> N = B::normal_at(P, ry.p);
         double sn = -dot(ry.k, N);
         sn = sn > 1.0 ? 1.0 : (sn < -1.0 ? -1.0 : sn);
         const double alpha = ::asin(sn);

@@ -1,8 +1,10 @@
 // Launch parameters of the trace kernels, prepared on the host from the
-// public structs.  All geometry is expressed relative to a crystal-local
-// origin (the flat crystal's front-face centre, or the point of the cylinder
-// axis at z_c), which keeps coordinates small so that the FP32 path keeps
-// nanometre resolution inside the crystal.
+// public structs.  All geometry is expressed in a crystal-local frame: its
+// origin is the flat crystal's front-face centre, or the point of the
+// cylinder axis at z_c, which keeps coordinates small so that the FP32 path
+// keeps nanometre resolution inside the crystal; its axes are the flat
+// crystal's (e1, e2, normal), or (ref_dir, axis x ref_dir, axis) for the
+// cylinder, so the kernels use those directions as the coordinate axes.
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -27,7 +29,7 @@ constexpr int kMaxTableBytes = 64 * 1024;
     X(lor_h2)                                                                                  \
     X(box_half) X(lut_x0) X(lut_x1) X(pitch) X(half_nx) X(half_ny)
 #define MRT_F32_VECTORS(X) \
-    X(so) X(sa) X(sb1) X(sb2) X(N) X(e1) X(e2) X(ax) X(op) X(om) X(dP) X(dn) X(du) X(dv)
+    X(so) X(sa) X(sb1) X(sb2) X(op) X(om) X(dP) X(dn) X(du) X(dv)
 
 struct TraceParamsF32 {
 #define MRT_F32_S(n) float n;
@@ -54,12 +56,11 @@ struct TraceParams {
     const double *user_o, *user_k, *user_e;   // user ray arrays (device) or NULL
     const double *user_p;         // user polarisations (device) or NULL
 
-    // ---- crystal (sec. 2.2)
+    // ---- crystal (sec. 2.2), in the local frame: flat normal z, length
+    // axis x, width axis y; cylinder axis z through the local origin
     int32_t geometry, max_refl;
-    double N[3], e1[3], e2[3];    // flat frame
     double hl, hw, T;             // half length, half width, thickness
-    double ax[3];                 // cylinder axis (through the local origin)
-    double op[3], om[3];          // outward normals of the two azimuth edges
+    double op[3], om[3];          // outward normals of the two azimuth edges (z = 0)
     double R, R2, Ro2;            // front radius, R^2, (R + T)^2
     double mu0, inv_mu0, inv_mu_tot, p_a, inv_1mpa;
     double two_d;                 // lattice spacing 2d (Angstrom)
@@ -69,6 +70,7 @@ struct TraceParams {
     double plane_ratio[4];        // 2d / 2d_j
     double hbar, plane_tot;       // H-bar / H ratio; sum_j a_j max(1, hbar)
     double origin[3];             // local origin in global coordinates
+    double rot[3][3];             // rows: the local axes in global coordinates
 
     // ---- mosaic (sec. 2.2.2)
     int32_t mdf, pad1;

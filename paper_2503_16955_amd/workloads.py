@@ -116,6 +116,24 @@ def von_hamos_hapg():
                 detector=det, n_rays=100_000_000, seed=1, precision="fp64")
 
 
+def von_hamos_burn_in():
+    """The instrument-function study of the paper's burn-in figure (sec.
+    2.2.4, Fig. BurnIn): a point source of 8.5 keV photons on a von Hamos
+    spectrometer whose central energy is 8.5 keV; graphite with a Lorentzian
+    mosaic of 0.14 deg and a Voigt rocking curve of 50.7 / 10.0 urad
+    Gaussian / Lorentzian FWHM (peak 0.5), up to 4 reflections.  The radius
+    (80 mm), crystal size and detector are the von Hamos workload's, which
+    the figure does not give."""
+    src, cr, det = _von_hamos_geometry(angle=placement_angle(8.5))
+    src.update(spectrum=SPEC_UNIFORM, e_min=8.5, e_max=8.5)
+    cr.update(max_refl=4)
+    return dict(name="von_hamos_burn_in", source=src, crystal=cr,
+                mosaic=dict(kind="lorentzian", fwhm=0.14 * DEG, eta=0.0),
+                rocking_curve=dict(kind="pseudo_voigt", peak=0.5, shift=0.0,
+                                   fwhm_g=50.7e-6, fwhm_l=10.0e-6),
+                detector=det, n_rays=10_000_000, seed=21, precision="fp64")
+
+
 def von_hamos_precision():
     w = von_hamos_hapg()
     w.update(name="von_hamos_precision", n_rays=1_000_000_000, precision="fp32_mixed")
@@ -140,6 +158,7 @@ WORKLOADS = {
     "von_hamos_hapg": von_hamos_hapg,
     "von_hamos_precision": von_hamos_precision,
     "flat_stress": flat_stress,
+    "von_hamos_burn_in": von_hamos_burn_in,
 }
 
 

@@ -1,12 +1,16 @@
 // Accuracy of the FP64 device math (device_math.h compiled for the host)
 // against long-double references: worst error in ulps of log over uniform
 // words and over 80 binades, and of sin/cos of turns (the reference reduced
-// exactly in quarter turns as well).  Prints "log L sin S cos C".
+// exactly in quarter turns as well).  Also every FP32 uniform u01_f32(w)
+// against its definition ((w >> 9) 2 + 1) 2^-24 in exact arithmetic, over all
+// 2^23 values of w >> 9, and the FP64 uniform (w + 1/2) 2^-32 on 2^24 words.
+// Prints "log L sin S cos C u01_f32_mismatches M" (M counts both uniforms).
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include "device_math.h"
 using namespace mrt;
 static double ulp_err(double got, long double ref) {
@@ -45,7 +49,23 @@ int main() {
         double e = ulp_err(dm::log_pos(x), logl((long double)x));
         if (e > worst_log) { worst_log = e; wl_x = x; }
     }
-    printf("log %.4f sin %.4f cos %.4f\n", worst_log, worst_sin, worst_cos);
+    long mismatches = 0;
+    for (uint32_t k = 0; k < (1u << 23); ++k) {
+        const uint32_t w = (k << 9) | (k & 0x1ffu);   // low bits do not matter
+        const double want = (double)(2u * k + 1u) * 0x1p-24;
+        const float got = dm::u01_f32(w);
+        if ((double)got != want || !(got > 0.0f && got < 1.0f)) ++mismatches;
+    }
+    // and the FP64 uniform (w + 1/2) 2^-32, on 2^24 words spread over the range
+    for (uint64_t k = 0; k < (1u << 24); ++k) {
+        const uint32_t w = (uint32_t)(k * 257u + (k >> 12));
+        const long double want = ((long double)w + 0.5L) * 0x1p-32L;
+        if ((long double)dm::u01_f64(w) != want) ++mismatches;
+    }
+    for (uint32_t w : {0u, 1u, 0xffffffffu, 0x80000000u})
+        if ((long double)dm::u01_f64(w) != ((long double)w + 0.5L) * 0x1p-32L) ++mismatches;
+    printf("log %.4f sin %.4f cos %.4f u01_f32_mismatches %ld\n", worst_log, worst_sin, worst_cos,
+           mismatches);
     (void)wl_x;
     (void)ws_x;
 }

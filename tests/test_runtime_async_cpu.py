@@ -173,9 +173,12 @@ def test_noalloc_entry_allocates_nothing(lib):
         # counters start from zero in each call (the scratch keeps the last)
         assert cnt.events == c.n and cnt.detected == n_tab and cnt.kernel_ms == 0.0
         c.scribble()
-    # and without counters: no wait, nothing allocated either
-    assert Call(_small_stress(n_table=900), n=300).run(L, s, None, entry="mrt_trace_noalloc") == 0
+    # and without counters: no wait, nothing allocated either (the call's
+    # host images stay alive until the stream has run)
+    last = Call(_small_stress(n_table=900), n=300)
+    assert last.run(L, s, None, entry="mrt_trace_noalloc") == 0
     L.harness_sync(s)
+    del last
     _, dev1, pinned1 = _counts(L)
     assert (dev1, pinned1) == (dev0, pinned0)
     assert L.harness_runs() == runs0 + 3
