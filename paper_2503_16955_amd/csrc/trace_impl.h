@@ -516,12 +516,12 @@ struct Tracer {
             if (lo > half * (1.0f + 0x1p-20f)) return 0;
             return -1;
         } else {
-            // r / R_max is even and decreasing in |x|
+            // r / R_max is even and decreasing in |x|; most candidates are
+            // rejected by the upper bound alone, before the lower one
             const float r_hi = ratio_f32(P, lo) * 1.0001f + 1e-30f;
-            const float r_lo = hi < INFINITY ? ratio_f32(P, hi) * 0.9999f : 0.0f;
-            if (u_acc < r_lo) return 1;
             if (u_acc >= r_hi) return 0;
-            return -1;
+            const float r_lo = hi < INFINITY ? ratio_f32(P, hi) * 0.9999f : 0.0f;
+            return u_acc < r_lo ? 1 : -1;
         }
     }
     // Bounds [r_lo, r_hi] of r(x) / R_max, which lies in [0, 1] ([0, 1]

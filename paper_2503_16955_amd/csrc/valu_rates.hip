@@ -30,21 +30,21 @@ constexpr int kUnroll = 4;
 constexpr int kOpsPerTrip = kChains * kUnroll;
 
 enum Op { kXorAdd32, kFma32, kFma64, kMul32, kMad64, kExpLog32, kRcp32, kSqrt32, kRcp64,
-          kAddMulF32, kMulHi32, kCvt32, kCmpSel32, kNumOps };
+          kAddMulF32, kMulHi32, kCvt32, kCmpSel32, kBitop3, kNumOps };
 const char *kNames[kNumOps] = {
     "v_xor_b32 + v_add_u32 (32-bit integer ALU)", "v_fma_f32", "v_fma_f64", "v_mul_lo_u32",
     "v_mad_u64_u32", "v_exp_f32 + v_log_f32", "v_rcp_f32", "v_sqrt_f32", "v_rcp_f64",
     "v_mul_f32 + v_add_f32", "v_mul_hi_u32", "v_xor_b32 + v_cvt_f32_u32 + v_cvt_u32_f32",
-    "v_cmp_gt_u32 + v_cndmask_b32"};
+    "v_cmp_gt_u32 + v_cndmask_b32", "v_bitop3_b32 (three-input XOR)"};
 // VALU instructions per chain step
-const int kInstPerStep[kNumOps] = {2, 1, 1, 1, 1, 2, 1, 1, 1, 2, 1, 3, 2};
+const int kInstPerStep[kNumOps] = {2, 1, 1, 1, 1, 2, 1, 1, 1, 2, 1, 3, 2, 1};
 
 template <int OP>
 __global__ void __launch_bounds__(256) rate_kernel(uint64_t *out, int iters, uint32_t a0,
                                                    uint32_t b0) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if constexpr (OP == kXorAdd32 || OP == kMul32 || OP == kMulHi32 || OP == kCvt32 ||
-                  OP == kCmpSel32) {
+                  OP == kCmpSel32 || OP == kBitop3) {
         uint32_t x[kChains];
         for (int j = 0; j < kChains; ++j) x[j] = t * 2654435761u + (uint32_t)j | 1u;
         for (int i = 0; i < iters; ++i) {
@@ -56,6 +56,8 @@ __global__ void __launch_bounds__(256) rate_kernel(uint64_t *out, int iters, uin
                     else if constexpr (OP == kMul32) x[j] = x[j] * x[j];
                     else if constexpr (OP == kMulHi32) x[j] = __umulhi(x[j], x[j]);
                     else if constexpr (OP == kCvt32) x[j] = (uint32_t)(float)(x[j] ^ a0);
+                    else if constexpr (OP == kBitop3)
+                        x[j] = __builtin_amdgcn_bitop3_b32(x[j], a0, x[(j + 1) % kChains], 0x96);
                     else x[j] = x[j] > a0 ? x[j] : b0;
                 }
         }
@@ -166,6 +168,7 @@ int main() {
     r[kMulHi32] = measure<kMulHi32>(out, blocks, cus, 1000);
     r[kCvt32] = measure<kCvt32>(out, blocks, cus, 700);
     r[kCmpSel32] = measure<kCmpSel32>(out, blocks, cus, 1000);
+    r[kBitop3] = measure<kBitop3>(out, blocks, cus, 2000);
     (void)hipFree(out);
     std::printf("%s, %d CUs, peak clock %d kHz; 32 workgroups of 256 threads per CU\n\n",
                 prop.gcnArchName, cus, prop.clockRate);

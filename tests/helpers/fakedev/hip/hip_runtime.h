@@ -64,6 +64,17 @@ inline long long __double_as_longlong(double x) { long long r; memcpy(&r, &x, 8)
 inline double __longlong_as_double(long long x) { double r; memcpy(&r, &x, 8); return r; }
 
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
+// Three-input bitwise operation by truth table: result bit i is bit
+// (a_i << 2 | b_i << 1 | c_i) of imm (0x96 is the three-input XOR, whose
+// table does not depend on the order of the inputs).
+inline uint32_t __builtin_amdgcn_bitop3_b32(uint32_t a, uint32_t b, uint32_t c, unsigned imm) {
+    uint32_t r = 0;
+    for (int i = 0; i < 32; ++i) {
+        const unsigned idx = (((a >> i) & 1u) << 2) | (((b >> i) & 1u) << 1) | ((c >> i) & 1u);
+        r |= ((imm >> idx) & 1u) << i;
+    }
+    return r;
+}
 inline double __dadd_rn(double a, double b) { return a + b; }
 inline double __dsub_rn(double a, double b) { return a - b; }
 inline double __dmul_rn(double a, double b) { return a * b; }

@@ -20,7 +20,7 @@ WANT = {0: {"v_xor_b32_e32": 32, "v_add_u32_e32": 32}, 1: {"v_fma_f32": 32},
         7: {"v_sqrt_f32_e32": 32}, 8: {"v_rcp_f64_e32": 32},
         9: {"v_mul_f32_e32": 32, "v_add_f32_e32": 32}, 10: {"v_mul_hi_u32": 32},
         11: {"v_xor_b32_e32": 32, "v_cvt_f32_u32_e32": 32, "v_cvt_u32_f32_e32": 32},
-        12: {"v_cmp_lt_u32_e32": 32, "v_cndmask_b32_e32": 32}}
+        12: {"v_cmp_lt_u32_e32": 32, "v_cndmask_b32_e32": 32}, 13: {"v_bitop3_b32": 32}}
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="needs hipcc")
