@@ -107,7 +107,7 @@ def roofline(op_costs, profiling, w, precision, per_step, cus):
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
             "unit": "TOP/s", "frac": round(achieved / peak, 4),
             "traffic": profiling.traffic_per_launch(name),
-            "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; 32-bit ops cost 1/2)",
+            "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; measured relative costs, FP32 arithmetic 0.5)",
             "ops_per_launch": int(sum(ops) / len(ops)),
             "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
 
@@ -128,7 +128,7 @@ def roofline_mwg(op_costs, profiling, w, per_step, cus, psi_nodes, burn_in):
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
             "unit": "TOP/s", "frac": round(achieved / peak, 4),
             "traffic": profiling.traffic_per_launch(name),
-            "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; 32-bit ops cost 1/2)",
+            "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; measured relative costs, FP32 arithmetic 0.5)",
             "ops_per_launch": int(sum(ops) / len(ops)),
             "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
 

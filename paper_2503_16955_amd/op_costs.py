@@ -3,13 +3,13 @@ library's kernels compile them for gfx950, and the algorithmic work of a
 trace in VALU issue slots.
 
 gfx950 issues VALU instructions at different rates by class.  The rates
-come from the throughput microbenchmark ``csrc/valu_rates.hip`` (its table
-is profiles/valu_issue_rates_gfx950.md): measured on MI355X, FP32
+come from the throughput microbenchmark ``csrc/valu_rates.hip`` (its tables
+are in profiles/valu_issue_rates_gfx950.md): measured on MI355X, FP32
 arithmetic (fma, mul, add) runs at about twice the FP64 FMA's lane rate,
 32-bit integer, logic, compare, select, conversion and three-input bitwise
-instructions and the 32-bit integer multiplies at about 1.2 times it,
-v_mad_u64_u32 at 1.1 times, FP32 transcendentals at 0.6 times and
-v_rcp_f64 at 0.3 times.  One
+instructions and the 32-bit integer multiplies at about 1.1 times it,
+v_mad_u64_u32 at 1.05 times, FP32 transcendentals at 0.55 times and
+v_rcp_f64 at 0.28 times.  One
 issue slot is one FP64 FMA lane, so the peak is 256 CUs x 64 x 2.4 GHz =
 39.32 T slots/s (the published 78.6 TFLOP/s FP64 peak over 2 flops) and an
 instruction costs SLOT_WEIGHT of its class: the FP64 FMA's measured rate
@@ -34,13 +34,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # Issue slots per VALU instruction class on gfx950 (see the module doc):
 # the measured FP64 FMA rate over the class's, averaged over three runs of
-# the microbenchmark and rounded to 0.05 (per run: fp32 0.45-0.54, alu32
-# 0.79-0.87 (integer, logic, compare, select, conversion, bitop3), mul32
-# 0.79-0.85, mad64 0.89-0.92, trans32 1.60-1.72, trans64 3.14-3.44).  64-bit
+# the microbenchmark and rounded to 0.05 (per run: fp32 0.46-0.53, alu32
+# 0.88-0.91 (integer, logic, compare, select, conversion, bitop3), mul32
+# 0.87-0.89, mad64 0.94-0.95, trans32 1.76-1.81, trans64 3.53-3.62).  64-bit
 # integer instructions other than v_mad_u64_u32 are not measured and are
 # priced like FP64.
-SLOT_WEIGHT = {"fp32": 0.5, "alu32": 0.85, "mul32": 0.85, "alu64": 1.0, "mad64": 0.9,
-               "trans32": 1.65, "trans64": 3.3}
+SLOT_WEIGHT = {"fp32": 0.5, "alu32": 0.9, "mul32": 0.9, "alu64": 1.0, "mad64": 0.95,
+               "trans32": 1.8, "trans64": 3.6}
 _TRANS32 = ("v_exp_f32", "v_log_f32", "v_sqrt_f32", "v_rsq_f32", "v_rcp_f32", "v_sin_f32",
             "v_cos_f32")
 _TRANS64 = ("v_rcp_f64", "v_rsq_f64", "v_sqrt_f64")
@@ -67,7 +67,7 @@ def slot_class(op):
 
 
 # Issue slots per operation in the trace kernels' code, as counted by derive().
-OP_COSTS = {'f64': {'log': 33.75, 'exp': 37.7, 'expm1': 46.1, 'sqrt': 16.0, 'rsqrt': 10.3, 'rcp': 7.3, 'div': 13.3, 'sincos': 23.4, 'sin': 141.15, 'cos': 141.15, 'asin': 98.65}, 'f32': {'log': 2.15, 'exp': 2.15, 'expm1': 17.2, 'sqrt': 1.65, 'rsqrt': 1.65, 'rcp': 1.65, 'div': 8.05, 'sincos': 3.3}, 'filter': {'gaussian': 30.85, 'pseudo_voigt': 37.15, 'table': 21.0, 'lorentzian': 30.85, 'box': 21.85}, 'philox': 29.05}
+OP_COSTS = {'f64': {'log': 34.5, 'exp': 38.8, 'expm1': 47.4, 'sqrt': 16.4, 'rsqrt': 10.6, 'rcp': 7.6, 'div': 13.6, 'sincos': 23.6, 'sin': 143.1, 'cos': 143.1, 'asin': 100.9}, 'f32': {'log': 2.3, 'exp': 2.3, 'expm1': 17.8, 'sqrt': 1.8, 'rsqrt': 1.8, 'rcp': 1.8, 'div': 8.4, 'sincos': 3.6}, 'filter': {'gaussian': 32.0, 'pseudo_voigt': 38.6, 'table': 21.7, 'lorentzian': 32.0, 'box': 22.6}, 'philox': 30.7}
 
 PROBES = {
     ("f64", "log"): ("log_f64", "glue_f64"), ("f64", "exp"): ("exp_f64", "glue_f64"),
