@@ -238,11 +238,13 @@ def independent_image(mrt, w, precision, n, steps, offset=1000):
 
 
 def extended_inputs(mrt, W, op_costs, w, n, steps, warmup, cus, plain):
-    """The extended-input kernels on the benchmark workload: the paper's
-    10 um Gaussian XFEL spot (sec. 4.2); the spot with every ray polarised
-    along the source's b1 (normal to the cone axis; a 2.4 GB device array);
-    the spot with the antiparallel planes at 0.8 and the (004) order at 0.3.
-    `plain` maps precision to the tuned kernel's rays/s."""
+    """The extended inputs on the benchmark workload: the paper's 10 um
+    Gaussian XFEL spot (sec. 4.2), which runs in the kernels specialised
+    for the kinds; the spot with every ray polarised along the source's b1
+    (normal to the cone axis; a 2.4 GB device array) and the spot with the
+    antiparallel planes at 0.8 and the (004) order at 0.3, which run in
+    trace_kernel_ext (every kind read at run time).  `plain` maps precision
+    to the tuned kernel's rays/s on the plain workload."""
     import torch
     spot = W.with_spot(w)
     b1 = torch.as_tensor(w["source"]["b1"], dtype=torch.float64, device="cuda")
@@ -252,7 +254,8 @@ def extended_inputs(mrt, W, op_costs, w, n, steps, warmup, cus, plain):
                                    "extra": [(w["crystal"]["two_d"] / 2, 0.3, 1.0, 0.0)]}
     peak = cus * LANES_PER_CU_PER_CLK * PEAK_CLOCK_HZ / 1e12
     counts, energy = mrt.alloc_images(w)      # images of its own
-    out = {"note": "trace_kernel_ext (every kind read at run time) on the benchmark workload"}
+    out = {"note": "the benchmark workload with a spot (tuned kernels), and with polarisations "
+                   "or plane sets (trace_kernel_ext, every kind read at run time)"}
     for label, wl, rays, priced in (("xfel_spot", spot, None, dict(spot=True)),
                                     ("xfel_spot_polarised", spot, pol, dict(spot=True, pol=True)),
                                     ("xfel_spot_planes", planes, None, dict(spot=True, planes=1))):

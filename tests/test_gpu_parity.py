@@ -112,6 +112,17 @@ def test_mosaic_kinds(kind):
     assert o["counters"]["reflections"] > 100
 
 
+@pytest.mark.parametrize("kind", sorted(MOSAICS))
+def test_mosaic_kinds_on_cylinder(kind):
+    # the von Hamos crystal, whose crystallites tilt about the local normal
+    # of the cylinder (x, y, 0) / rho in the crystal's own frame
+    w = W.get("von_hamos_hapg")
+    w["mosaic"] = dict(MOSAICS[kind])
+    w["name"] = f"von_hamos_hapg/{kind}"
+    g, o = assert_parity(w, 60_000)
+    assert o["counters"]["reflections"] > 100
+
+
 IRCS = {
     "gaussian": dict(kind="gaussian", peak=0.5, shift=0.0, fwhm=50e-6),
     "gaussian_shifted": dict(kind="gaussian", peak=0.8, shift=30e-6, fwhm=80e-6),
