@@ -117,17 +117,20 @@ __device__ __forceinline__ double rsqrt(double x) {
 // and r = m inv - 1, |r| <= 2^-8, from one FMA; then
 //   log x = e ln 2 + (-log inv) + log1p(r),
 // log1p by its series to r^8, the high parts e ln2_hi (exact: ln2_hi has 32
-// significant bits) and -log(inv)_hi summed first.  Within 2^-7 of 1 the
-// table is bypassed (r = x - 1, exact) so that small logarithms keep their
-// relative accuracy.  About 1 ulp.
+// significant bits) and -log(inv)_hi summed first.  The first interval has
+// inv = 1 and -log(inv) = 0, the last inv = 1/2 and -log(inv) = ln2_hi +
+// ln2_lo, the same split as e ln 2: within 2^-8 of 1 (e = 0 above 1, e = -1
+// below) r = x - 1 exactly and the high and low parts cancel to zero, so
+// small logarithms keep their relative accuracy without a separate branch
+// (there r reaches 2^-7, and the series' truncation stays below 2^-56
+// relative).  About 1 ulp.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double log_pos(double x) {
     const uint64_t b = (uint64_t)__double_as_longlong(x);
     const int e = (int)(b >> 52) - 1023;
     const double m = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
     const LogEntry t = kLogTable[(b >> 45) & 127];
-    const bool near1 = __builtin_fabs(x - 1.0) <= 0x1p-7;
-    const double r = near1 ? x - 1.0 : fma(m, (double)t.inv, -1.0);
+    const double r = fma(m, (double)t.inv, -1.0);
     double p = -1.0 / 8.0;
     p = poly_step(p, r, 1.0 / 7.0);
     p = poly_step(p, r, -1.0 / 6.0);
@@ -136,9 +139,9 @@ __device__ __forceinline__ double log_pos(double x) {
     p = poly_step(p, r, 1.0 / 3.0);
     p = poly_step(p, r, -1.0 / 2.0);
     const double l1p = fma(r * r, p, r);
-    const double de = near1 ? 0.0 : (double)e;
-    const double hi = near1 ? 0.0 : fma(de, 0x1.62e42feep-1, t.nlog_hi);
-    const double lo = near1 ? 0.0 : fma(de, 0x1.a39ef35793c76p-33, (double)t.nlog_lo);
+    const double de = (double)e;
+    const double hi = fma(de, 0x1.62e42feep-1, t.nlog_hi);
+    const double lo = fma(de, 0x1.a39ef35793c76p-33, t.nlog_lo);
     return hi + (lo + l1p);
 }
 

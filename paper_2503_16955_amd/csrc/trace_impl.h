@@ -1192,11 +1192,9 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
     // one ray queue per wave (at most 4 waves per workgroup)
     __shared__ RayQueue<R, REC> queues[4];
     RayQueue<R, REC> &q = queues[uniform(threadIdx.x >> 6)];
-    // The kernels defer the ended rays' detector and record work to the
-    // refill, except the FP64 cylinder (von Hamos) kernels, which were 4%
-    // slower with it (FP32-mixed: 2-16% faster; FP64 flat: 8-10% faster).
-    constexpr bool kDefer = !T::kF64 || GEOM == MRT_GEOMETRY_FLAT;
-    trace_loop<T, kDefer>(Q, Q.lut, Q.bin_cdf, claim, q);
+    // The ended rays' detector and record work waits for the refill
+    // (FP32-mixed: 2-16% faster; FP64: 2-10% faster).
+    trace_loop<T, true>(Q, Q.lut, Q.bin_cdf, claim, q);
 }
 
 // The same loop with the extended inputs (energy-dependent rocking curve,

@@ -1,6 +1,6 @@
 // Accuracy of the FP64 device math (device_math.h compiled for the host)
 // against long-double references: worst error in ulps of log over uniform
-// words and over 80 binades, and of sin/cos of turns (the reference reduced
+// words, over 80 binades and densely near 1, and of sin/cos of turns (the reference reduced
 // exactly in quarter turns as well).  Also every FP32 uniform u01_f32(w)
 // against its definition ((w >> 9) 2 + 1) 2^-24 in exact arithmetic, over all
 // 2^23 values of w >> 9, and the FP64 uniform (w + 1/2) 2^-32 on 2^24 words.
@@ -49,6 +49,26 @@ int main() {
         double e = ulp_err(dm::log_pos(x), logl((long double)x));
         if (e > worst_log) { worst_log = e; wl_x = x; }
     }
+    // log near 1, where its value is small and must keep its relative
+    // accuracy: every binade of |x - 1| from 2^-1 to 2^-53 on both sides, and
+    // the first thousand doubles on either side of 1
+    for (int j = 1; j <= 53; ++j) {
+        for (int i = 0; i < 2000; ++i) {
+            s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+            const double d = std::ldexp(1.0 + (double)(s >> 11) * 0x1p-53, -j);
+            for (double x : {1.0 + d, 1.0 - d}) {
+                if (!(x > 0.0) || x == 1.0) continue;
+                double e = ulp_err(dm::log_pos(x), logl((long double)x));
+                if (e > worst_log) { worst_log = e; wl_x = x; }
+            }
+        }
+    }
+    for (int k = 1; k <= 1000; ++k)
+        for (double x : {1.0 + k * 0x1p-52, 1.0 - k * 0x1p-53}) {
+            double e = ulp_err(dm::log_pos(x), logl((long double)x));
+            if (e > worst_log) { worst_log = e; wl_x = x; }
+        }
+    if (dm::log_pos(1.0) != 0.0) worst_log = 1e30;
     long mismatches = 0;
     for (uint32_t k = 0; k < (1u << 23); ++k) {
         const uint32_t w = (k << 9) | (k & 0x1ffu);   // low bits do not matter

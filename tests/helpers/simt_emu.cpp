@@ -157,7 +157,10 @@ template <class R, bool REC, bool EXT = false>
 void trace_body(const TraceParams &P, void *queue) {
     using T = Tracer<R, kAny, kAny, kAny, REC, EXT>;
     RangeClaim claim{P.chunk_counter, P.first, P.n, P.chunk};
-    trace_loop<T, !T::kF64>(P, P.lut, P.bin_cdf, claim, *(typename T::Queue *)queue);
+    // as the kernels: the one-call kernels defer the ended rays' detector
+    // work, the extended ones in FP32-mixed only
+    constexpr bool kDefer = EXT ? !T::kF64 : true;
+    trace_loop<T, kDefer>(P, P.lut, P.bin_cdf, claim, *(typename T::Queue *)queue);
 }
 
 template <bool REC, bool POL, bool PLANES = false>
