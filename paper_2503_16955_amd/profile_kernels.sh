@@ -2,8 +2,9 @@
 # rocprofv3 runs behind profiles/: the kernel trace of the benchmark's trace
 # kernels, the kernel trace of a serving run, that of the extended-input
 # kernels, HBM byte counters of the trace
-# kernels and of a plain 256 MiB copy (the scale reference), and SQ
-# instruction counters; then the VALU issue-rate microbenchmark
+# kernels and of a plain 256 MiB copy (the scale reference), SQ
+# instruction and lane-activity counters and the detector's atomics; then
+# the VALU issue-rate microbenchmark
 # (valu_rates, built by build.py) behind the roofline's slot weights.  Each pass is a run of its own (counters are not
 # multiplexed).  Usage: profile_kernels.sh OUT_DIR   (run from anywhere)
 set -u
@@ -40,6 +41,8 @@ step cfetch 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d "$OUT/prof_cfe
 step cwrite 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d "$OUT/prof_cwrite" -o cwrite -- $C
 step sq1 120 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_SMEM SQ_INSTS_LDS SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES --output-format csv -d "$OUT/prof_sq1" -o sq1 -- $B1
 step sq2 120 rocprofv3 --pmc SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_CVT SQ_INSTS_VALU_TRANS_F32 --output-format csv -d "$OUT/prof_sq2" -o sq2 -- $B1
+step sq3 120 rocprofv3 --pmc SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_FMA_F32 SQ_INSTS_BRANCH SQ_WAIT_INST_ANY SQ_INSTS_VSKIPPED --output-format csv -d "$OUT/prof_sq3" -o sq3 -- $B1
+step atom 120 rocprofv3 --pmc TCC_ATOMIC_sum TCC_EA0_ATOMIC_sum TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum TA_FLAT_ATOMIC_WAVEFRONTS_sum --output-format csv -d "$OUT/prof_atom" -o atom -- $B1
 echo "== valu_rates $(date +%T)"
 timeout -k 10 120 "$R/paper_2503_16955_amd/valu_rates" > "$OUT/valu_rates.md" 2>&1 || exit $?
 echo "done $(date +%T)"
