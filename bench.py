@@ -492,7 +492,7 @@ def serving(mrt, W, op_costs, cus, n_requests, budget, max_slots, load, seed=4, 
     rays = sum(w["n_rays"] for w in reqs)
     out = {"requests": n_requests, "total_rays": rays, "hbm_budget_bytes": budget,
            "max_slots": max_slots, "load": load,
-           "mix": "von Hamos R 60-120 mm, mosaic FWHM 0.05-0.8 deg (Gaussian / Lorentzian / "
+           "mix": "von Hamos R 60-120 mm, mosaic FWHM 0.05-0.8 deg (von Mises-Fisher / Lorentzian / "
                   "pseudo-Voigt), 20-100 um, 0.1-0.4 keV windows at 7.5-8.5 keV, "
                   "rays log-uniform 1e5-1e8"}
     for prec in ("fp32_mixed", "fp64"):

@@ -52,6 +52,8 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t a) {
 }
 
 inline unsigned int atomicAdd(unsigned int *p, unsigned int v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+#define __HIP_MEMORY_SCOPE_AGENT 3
+template <class T> inline T __hip_atomic_load(T *p, int order, int) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
 inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v) {
     return __atomic_fetch_add(p, v, __ATOMIC_RELAXED);
 }
