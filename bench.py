@@ -109,7 +109,8 @@ def roofline(op_costs, profiling, w, precision, per_step, cus):
             "traffic": profiling.traffic_per_launch(name),
             "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; measured relative costs, FP32 arithmetic 0.5)",
             "ops_per_launch": int(sum(ops) / len(ops)),
-            "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
+            "kernel_ms_avg": round(sum(ms) / len(ms), 4),
+            "issue": profiling.issue_ratios(name, sum(ops) / len(ops), sum(ms) / len(ms), cus)}
 
 
 def mwg_kernel_name(w, records=False, polarised=False, planes=False):
@@ -130,7 +131,8 @@ def roofline_mwg(op_costs, profiling, w, per_step, cus, psi_nodes, burn_in):
             "traffic": profiling.traffic_per_launch(name),
             "kernel": name, "op": "VALU issue slot (one FP64-FMA lane; measured relative costs, FP32 arithmetic 0.5)",
             "ops_per_launch": int(sum(ops) / len(ops)),
-            "kernel_ms_avg": round(sum(ms) / len(ms), 4)}
+            "kernel_ms_avg": round(sum(ms) / len(ms), 4),
+            "issue": profiling.issue_ratios(name, sum(ops) / len(ops), sum(ms) / len(ms), cus)}
 
 
 def mwg_model(mrt, op_costs, profiling, w, n, steps, warmup, burn_in, psi_nodes, cus, cpu_rays,

@@ -6,7 +6,8 @@
 * ``python -m paper_2503_16955_amd.profiling summarize ...`` turns rocprofv3
   CSV outputs (kernel trace with stats, and one ``--pmc`` pass per counter
   group) into a short markdown summary and ``hbm_traffic.json`` (HBM bytes
-  per launch of each trace kernel, scaled by the copy reference).
+  per launch of each trace kernel, scaled by the copy reference, and the
+  VALU-issue, lane-activity and atomic counters per launch).
 * ``sources_sha256()`` fingerprints the kernel sources and build flags;
   ``hbm_traffic.json`` records it, and a reader treats the traffic as
   unknown once the kernels have changed since the counters were taken.
@@ -53,6 +54,45 @@ def traffic_per_launch(kernel_name):
         return None
     k = t.get("kernels", {}).get(kernel_name)
     return None if k is None else k["hbm_bytes_per_launch"]
+
+
+# SQ and L2 counters kept per kernel beside the traffic (means per dispatch)
+ISSUE_COUNTERS = ("SQ_INSTS_VALU", "SQ_THREAD_CYCLES_VALU", "TCC_ATOMIC_sum")
+
+
+def counters_per_launch(kernel_name):
+    """{counter: mean per dispatch} of ISSUE_COUNTERS for a kernel from
+    hbm_traffic.json, or None when missing or taken from other sources."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_sha256():
+        return None
+    k = t.get("kernels", {}).get(kernel_name)
+    if k is None or not all(c in k.get("counters", {}) for c in ISSUE_COUNTERS):
+        return None
+    return k["counters"]
+
+
+def issue_ratios(kernel_name, useful_lane_ops, kernel_ms, cus):
+    """The survey's reported ratios for one launch from the profiled
+    counters: VALU issue fraction = SQ_INSTS_VALU / (t x CUs x 2.4 GHz) (one
+    wave64 VALU instruction per CU and clock), lane efficiency = the priced
+    lane-slots / (SQ_INSTS_VALU x 64), active lanes per VALU instruction =
+    SQ_THREAD_CYCLES_VALU / SQ_INSTS_VALU, and L2 atomics per second.  None
+    when the counters are missing or stale."""
+    c = counters_per_launch(kernel_name)
+    if c is None or not c["SQ_INSTS_VALU"]:
+        return None
+    t = kernel_ms * 1e-3
+    v = c["SQ_INSTS_VALU"]
+    return {"valu_issue_frac": round(v / (t * cus * 2.4e9), 4),
+            "lane_efficiency": round(useful_lane_ops / (v * 64.0), 4),
+            "lanes_per_valu_inst": round(c["SQ_THREAD_CYCLES_VALU"] / v, 2),
+            "atomics_per_s": round(c["TCC_ATOMIC_sum"] / t, 1),
+            "source": "rocprofv3 counters of profiles/trace_kernel_von_hamos_1e8.md"}
 
 
 def copy_reference(mib):
@@ -155,6 +195,10 @@ def summarize(trace_dir, pmc_dirs, copy_fetch, copy_write, copy_mib, command, ou
                 traffic["kernels"][k] = {"fetch_kib": sum(f) / len(f), "write_kib": sum(w) / len(w),
                                          "fetch_scale": sf, "write_scale": sw,
                                          "hbm_bytes_per_launch": b}
+                cs = {c: sum(agg[(k, c)]) / len(agg[(k, c)]) for c in ISSUE_COUNTERS
+                      if agg.get((k, c))}
+                if cs:
+                    traffic["kernels"][k]["counters"] = cs
                 lines.append(f"HBM traffic of `{k[:90]}`: {b / 1e6:.2f} MB per launch.")
         lines.append("")
     with open(out_md, "w") as fh:
