@@ -245,7 +245,7 @@ def extended_inputs(mrt, W, op_costs, w, n, steps, warmup, cus, plain):
     for the kinds; the spot with every ray polarised along the source's b1
     (normal to the cone axis; a 2.4 GB device array) and the spot with the
     antiparallel planes at 0.8 and the (004) order at 0.3, which run in
-    trace_kernel_ext (every kind read at run time).  `plain` maps precision
+    the extended kernels (trace_kernel_ext).  `plain` maps precision
     to the tuned kernel's rays/s on the plain workload."""
     import torch
     spot = W.with_spot(w)
@@ -257,7 +257,7 @@ def extended_inputs(mrt, W, op_costs, w, n, steps, warmup, cus, plain):
     peak = cus * LANES_PER_CU_PER_CLK * PEAK_CLOCK_HZ / 1e12
     counts, energy = mrt.alloc_images(w)      # images of its own
     out = {"note": "the benchmark workload with a spot (tuned kernels), and with polarisations "
-                   "or plane sets (trace_kernel_ext, every kind read at run time)"}
+                   "or plane sets (trace_kernel_ext)"}
     for label, wl, rays, priced in (("xfel_spot", spot, None, dict(spot=True)),
                                     ("xfel_spot_polarised", spot, pol, dict(spot=True, pol=True)),
                                     ("xfel_spot_planes", planes, None, dict(spot=True, planes=1))):

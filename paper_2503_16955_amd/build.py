@@ -13,7 +13,9 @@ LIB = os.path.join(HERE, "libmosaicrt.so")
 # program of its own, run by the profiling scripts)
 RATES_EXE = os.path.join(HERE, "valu_rates")
 SOURCES = ["trace_f64_flat.hip", "trace_f64_cyl.hip", "trace_f32_flat.hip", "trace_f32_cyl.hip",
-           "trace_mwg.hip", "trace_ext.hip", "serve.hip", "launch.hip", "params.cpp", "runtime.cpp", "server.cpp"]
+           "trace_ext_f64_flat.hip", "trace_ext_f64_cyl.hip", "trace_ext_f32_flat.hip",
+           "trace_ext_f32_cyl.hip", "trace_mwg.hip", "serve.hip", "launch.hip", "params.cpp",
+           "runtime.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

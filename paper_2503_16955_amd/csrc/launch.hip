@@ -12,11 +12,23 @@ const void *trace_table_f64_cyl(int mdf, int irc, bool rec);
 const void *trace_table_f32_flat(int mdf, int irc, bool rec);
 const void *trace_table_f32_cyl(int mdf, int irc, bool rec);
 
+const void *ext_table_f64_flat(int mdf, int irc, bool rec);
+const void *ext_table_f64_cyl(int mdf, int irc, bool rec);
+const void *ext_table_f32_flat(int mdf, int irc, bool rec);
+const void *ext_table_f32_cyl(int mdf, int irc, bool rec);
+
 const void *trace_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records) {
     const bool flat = geometry == MRT_GEOMETRY_FLAT;
     if (precision == MRT_FP64)
         return flat ? trace_table_f64_flat(mdf, irc, records) : trace_table_f64_cyl(mdf, irc, records);
     return flat ? trace_table_f32_flat(mdf, irc, records) : trace_table_f32_cyl(mdf, irc, records);
+}
+
+const void *ext_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records) {
+    const bool flat = geometry == MRT_GEOMETRY_FLAT;
+    if (precision == MRT_FP64)
+        return flat ? ext_table_f64_flat(mdf, irc, records) : ext_table_f64_cyl(mdf, irc, records);
+    return flat ? ext_table_f32_flat(mdf, irc, records) : ext_table_f32_cyl(mdf, irc, records);
 }
 
 namespace {

@@ -157,7 +157,8 @@ mrt_status prepare(const mrt_source *source, const mrt_crystal *crystal, const m
     L.kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec, source->polarisations != nullptr,
                                          crystal->planes != nullptr || rocking_curve->n_dep > 0)
                : mrt::uses_ext(source, crystal, rocking_curve) || opt.exact_decisions
-                   ? mrt::ext_kernel_ptr(opt.precision, rec)
+                   ? mrt::ext_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
+                                         rocking_curve->kind, rec)
                    : mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
                                            rocking_curve->kind, rec);
     if (!L.kernel) return fail(MRT_EINVAL, "no kernel for this combination of kinds");

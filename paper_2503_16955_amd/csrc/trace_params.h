@@ -167,9 +167,10 @@ const void *serve_kernel_ptr(int precision, bool ext);
 // Kernel of the paper's event model (FP64) for a geometry (nullptr for an
 // unknown one): (TraceParams), like the trace kernels.
 const void *mwg_kernel_ptr(int geometry, bool records, bool polarised, bool planes);
-// Kernel for the extended inputs: an energy-dependent rocking curve, a
-// finite source spot, user ray arrays (every kind read at run time).
-const void *ext_kernel_ptr(int precision, bool records);
+// Kernel for the extended inputs (an energy-dependent rocking curve,
+// polarisations, further plane sets) of a precision / geometry / mosaic /
+// rocking-curve / records combination (nullptr for an unknown kind).
+const void *ext_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records);
 constexpr int kMaxPsiNodes = 2048;
 
 }  // namespace mrt

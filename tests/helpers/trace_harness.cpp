@@ -43,7 +43,7 @@ std::function<void()> bind_trace(void **args) {
 
 namespace mrt {
 const void *trace_kernel_ptr(int, int, int, int, bool) { return &g_kernel_tag; }
-const void *ext_kernel_ptr(int, bool) { return &g_kernel_tag; }
+const void *ext_kernel_ptr(int, int, int, int, bool) { return &g_kernel_tag; }
 const void *mwg_kernel_ptr(int, bool, bool, bool) { return &g_kernel_tag; }
 int launch_zero(void *p, size_t words, void *stream) {
     ((hipStream_t)stream)->push([p, words] { memset(p, 0, words * 4); });
