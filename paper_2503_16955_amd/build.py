@@ -14,8 +14,8 @@ LIB = os.path.join(HERE, "libmosaicrt.so")
 RATES_EXE = os.path.join(HERE, "valu_rates")
 SOURCES = ["trace_f64_flat.hip", "trace_f64_cyl.hip", "trace_f32_flat.hip", "trace_f32_cyl.hip",
            "trace_ext_f64_flat.hip", "trace_ext_f64_cyl.hip", "trace_ext_f32_flat.hip",
-           "trace_ext_f32_cyl.hip", "trace_mwg.hip", "serve.hip", "launch.hip", "params.cpp",
-           "runtime.cpp", "server.cpp"]
+           "trace_ext_f32_cyl.hip", "trace_mwg.hip", "serve_f64.hip", "serve_f32.hip", "launch.hip",
+           "params.cpp", "runtime.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

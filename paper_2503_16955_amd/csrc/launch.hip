@@ -17,6 +17,13 @@ const void *ext_table_f64_cyl(int mdf, int irc, bool rec);
 const void *ext_table_f32_flat(int mdf, int irc, bool rec);
 const void *ext_table_f32_cyl(int mdf, int irc, bool rec);
 
+const void *serve_kernel_ptr_f64(bool ext);
+const void *serve_kernel_ptr_f32(bool ext);
+
+const void *serve_kernel_ptr(int precision, bool ext) {
+    return precision == MRT_FP64 ? serve_kernel_ptr_f64(ext) : serve_kernel_ptr_f32(ext);
+}
+
 const void *trace_kernel_ptr(int precision, int geometry, int mdf, int irc, bool records) {
     const bool flat = geometry == MRT_GEOMETRY_FLAT;
     if (precision == MRT_FP64)

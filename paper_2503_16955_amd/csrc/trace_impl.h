@@ -1158,11 +1158,11 @@ struct RangeClaim {
 // wave operation, so the compiler cannot split the wave across the
 // back-edge (the counter flush that ends trace_loop is lane-0-only).
 // ---------------------------------------------------------------------------
-template <class T, bool kDefer = false, class Q>
+template <class Run>
 __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slots,
                                             const ServeItem *__restrict__ items, uint32_t n_items,
                                             uint64_t total, unsigned long long *__restrict__ cursors,
-                                            uint32_t wave, uint32_t n_waves, Q &q) {
+                                            uint32_t wave, uint32_t n_waves, const Run &run) {
     if (n_items == 0 || n_waves == 0) return;
     // first item: the last one whose start is at or before the position
     const uint64_t pos = (uint64_t)wave * total / n_waves;
@@ -1178,9 +1178,56 @@ __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slot
         MRT_DEV_CHECK(i < n_items && it.slot >= 0);
         const TraceParams &P = slots[it.slot];
         RangeClaim claim{&cursors[i], it.first, it.count, it.chunk};
-        trace_loop<T, kDefer>(P, P.lut, P.bin_cdf, claim, q);
+        run(P, claim);
     }
 }
+
+// The loop of one Tracer T (kinds as T fixes them) over an item's rays.
+template <class T, bool kDefer, class Q>
+struct LoopRun {
+    Q &q;
+    __device__ __forceinline__ void operator()(const TraceParams &P, RangeClaim &claim) const {
+        trace_loop<T, kDefer>(P, P.lut, P.bin_cdf, claim, q);
+    }
+};
+
+// The loop specialised for an item's geometry, mosaic and rocking-curve
+// kinds (wave-uniform scalar loads from its parameter block), chosen by a
+// uniform switch per item: the serving kernel then runs the plain kernels'
+// code for every request.
+template <class R, bool kDefer, int G, int M, int I, class Q>
+__device__ __forceinline__ void run_kinds(const TraceParams &P, RangeClaim &c, Q &q) {
+    trace_loop<Tracer<R, G, M, I, false>, kDefer>(P, P.lut, P.bin_cdf, c, q);
+}
+template <class R, bool kDefer, int G, int M, class Q>
+__device__ __forceinline__ void run_irc(const TraceParams &P, RangeClaim &c, Q &q) {
+    switch (P.irc) {
+    case 0: run_kinds<R, kDefer, G, M, 0>(P, c, q); break;
+    case 1: run_kinds<R, kDefer, G, M, 1>(P, c, q); break;
+    case 2: run_kinds<R, kDefer, G, M, 2>(P, c, q); break;
+    case 3: run_kinds<R, kDefer, G, M, 3>(P, c, q); break;
+    default: run_kinds<R, kDefer, G, M, 4>(P, c, q); break;
+    }
+}
+template <class R, bool kDefer, int G, class Q>
+__device__ __forceinline__ void run_mdf(const TraceParams &P, RangeClaim &c, Q &q) {
+    switch (P.mdf) {
+    case 0: run_irc<R, kDefer, G, 0>(P, c, q); break;
+    case 1: run_irc<R, kDefer, G, 1>(P, c, q); break;
+    case 2: run_irc<R, kDefer, G, 2>(P, c, q); break;
+    case 3: run_irc<R, kDefer, G, 3>(P, c, q); break;
+    case 4: run_irc<R, kDefer, G, 4>(P, c, q); break;
+    default: run_irc<R, kDefer, G, 5>(P, c, q); break;
+    }
+}
+template <class R, bool kDefer, class Q>
+struct KindRun {
+    Q &q;
+    __device__ __forceinline__ void operator()(const TraceParams &P, RangeClaim &claim) const {
+        if (P.geometry == MRT_GEOMETRY_FLAT) run_mdf<R, kDefer, MRT_GEOMETRY_FLAT>(P, claim, q);
+        else run_mdf<R, kDefer, MRT_GEOMETRY_CYLINDER>(P, claim, q);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Persistent trace kernel of one call (sec. 2; rays [P.first, P.first + P.n)).

@@ -138,9 +138,12 @@ using namespace mrt::tk;
 template <class R, bool kDefer = false>
 void serve_body(const TraceParams *slots, const ServeItem *items, uint32_t n, uint64_t total,
                 unsigned long long *cursors, uint32_t wave, uint32_t n_waves, void *queue) {
-    // the serving kernel's body, with the wave index it would compute
-    serve_waves<Tracer<R, kAny, kAny, kAny, false>, kDefer>(slots, items, n, total, cursors, wave,
-                                                            n_waves, *(RayQueue<R, false> *)queue);
+    // the serving kernel's body, with the wave index it would compute (the
+    // device kernel runs each item in the loop specialised for its kinds,
+    // the same template code; here the loop reads the kinds at run time)
+    using T = Tracer<R, kAny, kAny, kAny, false>;
+    serve_waves(slots, items, n, total, cursors, wave, n_waves,
+                LoopRun<T, kDefer, RayQueue<R, false>>{*(RayQueue<R, false> *)queue});
 }
 
 // The extended serving kernel's body (spots, user arrays and polarisations,
@@ -149,8 +152,8 @@ template <class R, bool kDefer = false>
 void serve_body_ext(const TraceParams *slots, const ServeItem *items, uint32_t n, uint64_t total,
                     unsigned long long *cursors, uint32_t wave, uint32_t n_waves, void *queue) {
     using T = Tracer<R, kAny, kAny, kAny, false, true>;
-    serve_waves<T, kDefer>(slots, items, n, total, cursors, wave, n_waves,
-                           *(typename T::Queue *)queue);
+    serve_waves(slots, items, n, total, cursors, wave, n_waves,
+                LoopRun<T, kDefer, typename T::Queue>{*(typename T::Queue *)queue});
 }
 
 template <class R, bool REC, bool EXT = false>
