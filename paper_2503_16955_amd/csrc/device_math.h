@@ -146,6 +146,30 @@ __device__ __forceinline__ double log_pos(double x) {
 }
 
 // ---------------------------------------------------------------------------
+// exp(x) for x <= 0 (the mosaic densities, the rocking curves' Gaussians), by
+// the table method: k = rint(128 x / ln 2), r = x - k ln2 / 128 in two FMAs
+// (ln2_hi / 128 has 32 significant bits, so k ln2_hi / 128 is exact for
+// |k| < 2^21), |r| <= ln 2 / 256; exp(r) - 1 by its series to r^5 (truncation
+// below 2^-60); the table's 2^(j / 128) = hi + lo for j = k mod 128; the
+// power 2^(k div 128) by ldexp, which also gives the subnormal and zero
+// results.  Arguments below -1100 give 0.  About 1 ulp.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_nonpos(double x) {
+    x = x > -1100.0 ? x : -1100.0;
+    const double kd = __builtin_rint(x * 0x1.71547652b82fep+7);   // 128 / ln 2
+    const int k = (int)kd;
+    double r = fma(-kd, 0x1.62e42feep-8, x);
+    r = fma(-kd, 0x1.a39ef35793c76p-40, r);
+    double p = 1.0 / 120.0;
+    p = poly_step(p, r, 1.0 / 24.0);
+    p = poly_step(p, r, 1.0 / 6.0);
+    p = poly_step(p, r, 0.5);
+    const double em1 = fma(r * r, p, r);   // exp(r) - 1
+    const ExpEntry t = kExpTable[k & 127];
+    return __builtin_ldexp(t.hi + fma(t.hi, em1, t.lo), k >> 7);
+}
+
+// ---------------------------------------------------------------------------
 // sin and cos of 2 pi u (u in turns, u in [0, 1)).  u = q / 256 + r exactly
 // (|r| <= 1/512); with a = 2 pi r, |a| <= 0.0123, sin a and cos a by their
 // series to a^7 and a^6, then the angle-addition formulas with the table's

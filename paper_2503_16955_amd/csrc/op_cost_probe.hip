@@ -25,7 +25,7 @@ using namespace mrt;
 
 PROBE(glue_f64, double, x * 0.5)
 PROBE(log_f64, double, dm::log_pos(x) * 0.5)
-PROBE(exp_f64, double, ::exp(x) * 0.5)
+PROBE(exp_f64, double, dm::exp_nonpos(-x) * 0.5)
 PROBE(expm1_f64, double, ::expm1(x) * 0.5)
 PROBE(sqrt_f64, double, dm::sqrt(x) * 0.5)
 PROBE(rsqrt_f64, double, dm::rsqrt(x) * 0.5)

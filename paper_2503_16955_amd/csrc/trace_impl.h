@@ -377,13 +377,13 @@ struct Tracer {
     // ---- rocking curve (sec. 2.2.1): r(x) / R_max at x = Delta - Delta_M ---
     static __device__ __forceinline__ R irc_ratio(const TraceParams &P, const double *lut, double x) {
         if (irc_is(P, MRT_IRC_GAUSSIAN)) {
-            if constexpr (kF64) return ::exp(-P.g_k * x * x);
+            if constexpr (kF64) return dm::exp_nonpos(-P.g_k * x * x);
             else return dm::exp_((float)(-P.g_k * x * x));
         } else if (irc_is(P, MRT_IRC_PSEUDO_VOIGT)) {
             // eta L(x)/R(0) + (1 - eta) G(x)/R(0) = A h^2/(h^2 + x^2) + B exp(-k x^2)
             const double x2 = x * x;
             if constexpr (kF64) {
-                return P.pv_a * dm::div(P.pv_h2, P.pv_h2 + x2) + P.pv_b * ::exp(-P.g_k * x2);
+                return P.pv_a * dm::div(P.pv_h2, P.pv_h2 + x2) + P.pv_b * dm::exp_nonpos(-P.g_k * x2);
             } else {
                 const float h2 = P.f32.pv_h2, xf = (float)x2;
                 return P.f32.pv_a * h2 * dm::rcp(h2 + xf) +
@@ -1122,20 +1122,28 @@ __device__ __forceinline__ void trace_loop(const TraceParams &P, const double *l
     flush(P, cnt);
 }
 
-// Chunks of one call's ray range, claimed from a global cursor.  The cursor
-// only grows, so a plain read at or past the end proves the range exhausted
-// without the atomic: a serving wave visits every item of its round, and
-// the read-modify-writes of waves arriving at finished items serialised on
-// the items' cursors (FP32-mixed serving 8% faster without them).
-struct RangeClaim {
+// Chunks of a ray range, claimed from a global cursor.  kPeek (serving):
+// the cursor only grows, so a plain read at or past the end proves the range
+// exhausted without the atomic.  A serving wave visits every item of its
+// round, and the read-modify-writes of waves arriving at finished items
+// serialised on the items' cursors (FP32-mixed serving 8% faster without
+// them).  The one-call kernels claim without it: their ranges run out once,
+// and the extra read changed the scheduling of their event loop (FP32-mixed
+// 5% slower).
+template <bool kPeek>
+struct ClaimRange {
     unsigned long long *cursor;
     uint64_t first, n;
     uint32_t chunk;
     __device__ __forceinline__ bool operator()(uint64_t &next, uint64_t &end) {
         unsigned long long base = 0;
         if (__lane_id() == 0) {
-            base = __hip_atomic_load(cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (base < n) base = atomicAdd(cursor, (unsigned long long)chunk);
+            if constexpr (kPeek) {
+                base = __hip_atomic_load(cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (base < n) base = atomicAdd(cursor, (unsigned long long)chunk);
+            } else {
+                base = atomicAdd(cursor, (unsigned long long)chunk);
+            }
         }
         base = uniform64(base);
         if (base >= n) return false;
@@ -1144,6 +1152,8 @@ struct RangeClaim {
         return true;
     }
 };
+using RangeClaim = ClaimRange<false>;   // one call's range
+using ItemClaim = ClaimRange<true>;     // a serving item's range
 
 // ---------------------------------------------------------------------------
 // Serving: the waves of one launch trace a round's items (one per request,
@@ -1177,7 +1187,7 @@ __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slot
         const ServeItem it = items[i];
         MRT_DEV_CHECK(i < n_items && it.slot >= 0);
         const TraceParams &P = slots[it.slot];
-        RangeClaim claim{&cursors[i], it.first, it.count, it.chunk};
+        ItemClaim claim{&cursors[i], it.first, it.count, it.chunk};
         run(P, claim);
     }
 }
@@ -1186,7 +1196,7 @@ __device__ __forceinline__ void serve_waves(const TraceParams *__restrict__ slot
 template <class T, bool kDefer, class Q>
 struct LoopRun {
     Q &q;
-    __device__ __forceinline__ void operator()(const TraceParams &P, RangeClaim &claim) const {
+    __device__ __forceinline__ void operator()(const TraceParams &P, ItemClaim &claim) const {
         trace_loop<T, kDefer>(P, P.lut, P.bin_cdf, claim, q);
     }
 };
@@ -1196,11 +1206,11 @@ struct LoopRun {
 // uniform switch per item: the serving kernel then runs the plain kernels'
 // code for every request.
 template <class R, bool kDefer, int G, int M, int I, class Q>
-__device__ __forceinline__ void run_kinds(const TraceParams &P, RangeClaim &c, Q &q) {
+__device__ __forceinline__ void run_kinds(const TraceParams &P, ItemClaim &c, Q &q) {
     trace_loop<Tracer<R, G, M, I, false>, kDefer>(P, P.lut, P.bin_cdf, c, q);
 }
 template <class R, bool kDefer, int G, int M, class Q>
-__device__ __forceinline__ void run_irc(const TraceParams &P, RangeClaim &c, Q &q) {
+__device__ __forceinline__ void run_irc(const TraceParams &P, ItemClaim &c, Q &q) {
     switch (P.irc) {
     case 0: run_kinds<R, kDefer, G, M, 0>(P, c, q); break;
     case 1: run_kinds<R, kDefer, G, M, 1>(P, c, q); break;
@@ -1210,7 +1220,7 @@ __device__ __forceinline__ void run_irc(const TraceParams &P, RangeClaim &c, Q &
     }
 }
 template <class R, bool kDefer, int G, class Q>
-__device__ __forceinline__ void run_mdf(const TraceParams &P, RangeClaim &c, Q &q) {
+__device__ __forceinline__ void run_mdf(const TraceParams &P, ItemClaim &c, Q &q) {
     switch (P.mdf) {
     case 0: run_irc<R, kDefer, G, 0>(P, c, q); break;
     case 1: run_irc<R, kDefer, G, 1>(P, c, q); break;
@@ -1223,7 +1233,7 @@ __device__ __forceinline__ void run_mdf(const TraceParams &P, RangeClaim &c, Q &
 template <class R, bool kDefer, class Q>
 struct KindRun {
     Q &q;
-    __device__ __forceinline__ void operator()(const TraceParams &P, RangeClaim &claim) const {
+    __device__ __forceinline__ void operator()(const TraceParams &P, ItemClaim &claim) const {
         if (P.geometry == MRT_GEOMETRY_FLAT) run_mdf<R, kDefer, MRT_GEOMETRY_FLAT>(P, claim, q);
         else run_mdf<R, kDefer, MRT_GEOMETRY_CYLINDER>(P, claim, q);
     }

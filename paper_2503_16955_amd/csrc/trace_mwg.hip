@@ -51,12 +51,14 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
     // ---- mosaic densities per steradian at v = 1 - cos(theta) ----------
     template <int K> static __device__ __forceinline__ double density(const TraceParams &P, double v) {
         if constexpr (K == MRT_MOSAIC_GAUSSIAN_VMF) {
-            return P.vmf_norm * ::exp(-P.vmf_kappa * v);
+            return P.vmf_norm * dm::exp_nonpos(-P.vmf_kappa * v);
         } else if constexpr (K == MRT_MOSAIC_LORENTZIAN) {
             const double c = 1.0 - v;
             if (!(c > 0.0)) return 0.0;
+            // q^(-3/2) from one reciprocal square root
             const double q = v * (2.0 - v) + P.cau_g2 * c * c;
-            return P.cau_norm / (q * ::sqrt(q));
+            const double rq = dm::rsqrt(q);
+            return P.cau_norm * (rq * rq * rq);
         } else if constexpr (K == MRT_MOSAIC_PSEUDO_VOIGT) {
             return P.m_eta * density<MRT_MOSAIC_LORENTZIAN>(P, v) +
                    (1.0 - P.m_eta) * density<MRT_MOSAIC_GAUSSIAN_VMF>(P, v);
@@ -68,7 +70,8 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             const double c = 1.0 - v;
             if (!(c > 0.0)) return 0.0;
             const double ic = dm::rcp(c);
-            return P.gau_norm * (ic * ic * ic) * ::exp(-P.gau_inv2s2 * (v * (2.0 - v)) * (ic * ic));
+            return P.gau_norm * (ic * ic * ic) *
+                   dm::exp_nonpos(-P.gau_inv2s2 * (v * (2.0 - v)) * (ic * ic));
         } else {
             const double d = P.swl_a + v;
             return P.swl_norm / (d * d);

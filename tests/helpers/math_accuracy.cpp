@@ -1,10 +1,11 @@
 // Accuracy of the FP64 device math (device_math.h compiled for the host)
 // against long-double references: worst error in ulps of log over uniform
-// words, over 80 binades and densely near 1, and of sin/cos of turns (the reference reduced
+// words, over 80 binades and densely near 1, of exp over non-positive
+// arguments (normal and subnormal results), and of sin/cos of turns (the reference reduced
 // exactly in quarter turns as well).  Also every FP32 uniform u01_f32(w)
 // against its definition ((w >> 9) 2 + 1) 2^-24 in exact arithmetic, over all
 // 2^23 values of w >> 9, and the FP64 uniform (w + 1/2) 2^-32 on 2^24 words.
-// Prints "log L sin S cos C u01_f32_mismatches M" (M counts both uniforms).
+// Prints "log L sin S cos C exp X u01_f32_mismatches M" (M counts both uniforms).
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdio>
@@ -69,6 +70,33 @@ int main() {
             if (e > worst_log) { worst_log = e; wl_x = x; }
         }
     if (dm::log_pos(1.0) != 0.0) worst_log = 1e30;
+    // exp for non-positive arguments: uniform over [-708, 0] (normal
+    // results), every binade of |x| from 2^-60 to 2^9, and the subnormal
+    // range in absolute terms; exp(0) = 1, exp(-1100) = 0
+    double worst_exp = 0;
+    for (long i = 0; i < n_wide; ++i) {
+        s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+        const double x = -708.0 * (double)(s >> 11) * 0x1p-53;
+        double e = ulp_err(dm::exp_nonpos(x), expl((long double)x));
+        if (e > worst_exp) worst_exp = e;
+    }
+    for (int j = -60; j <= 9; ++j)
+        for (int i = 0; i < 2000; ++i) {
+            s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+            const double x = -std::ldexp(1.0 + (double)(s >> 11) * 0x1p-53, j);
+            if (x < -708.0) continue;
+            double e = ulp_err(dm::exp_nonpos(x), expl((long double)x));
+            if (e > worst_exp) worst_exp = e;
+        }
+    for (int i = 0; i < 100000; ++i) {
+        const double x = -708.4 - 37.0 * i / 100000.0;
+        const long double ref = expl((long double)x);
+        const long double err = fabsl((long double)dm::exp_nonpos(x) - ref);
+        if (err > 2.0L * 0x1p-1074L + ref * 0x1p-52L) worst_exp = 1e30;
+    }
+    if (dm::exp_nonpos(0.0) != 1.0 || dm::exp_nonpos(-1100.0) != 0.0 ||
+        dm::exp_nonpos(-1e300) != 0.0)
+        worst_exp = 1e30;
     long mismatches = 0;
     for (uint32_t k = 0; k < (1u << 23); ++k) {
         const uint32_t w = (k << 9) | (k & 0x1ffu);   // low bits do not matter
@@ -84,8 +112,8 @@ int main() {
     }
     for (uint32_t w : {0u, 1u, 0xffffffffu, 0x80000000u})
         if ((long double)dm::u01_f64(w) != ((long double)w + 0.5L) * 0x1p-32L) ++mismatches;
-    printf("log %.4f sin %.4f cos %.4f u01_f32_mismatches %ld\n", worst_log, worst_sin, worst_cos,
-           mismatches);
+    printf("log %.4f sin %.4f cos %.4f exp %.4f u01_f32_mismatches %ld\n", worst_log, worst_sin,
+           worst_cos, worst_exp, mismatches);
     (void)wl_x;
     (void)ws_x;
 }

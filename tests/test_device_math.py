@@ -1,4 +1,5 @@
-"""The FP64 device math routines (table log, sin/cos of turns, in
+"""The FP64 device math routines (table log, exp of non-positive arguments,
+sin/cos of turns, in
 device_math.h) compiled for the host and compared with long-double
 references: a few ulps at most, far inside the 1e-12 per-ray parity
 contract; and the FP32 uniform equal to its definition for every word."""
@@ -25,4 +26,5 @@ def test_fp64_log_and_sincos_within_two_ulps(tmp_path):
     err = dict(zip(out[0::2], map(float, out[1::2])))
     assert err["log"] <= 2.0, err
     assert err["sin"] <= 2.5 and err["cos"] <= 2.5, err
+    assert err["exp"] <= 2.0, err
     assert err["u01_f32_mismatches"] == 0
