@@ -78,8 +78,10 @@ def counters_per_launch(kernel_name):
 
 def issue_ratios(kernel_name, useful_lane_ops, kernel_ms, cus):
     """The survey's reported ratios for one launch from the profiled
-    counters: VALU issue fraction = SQ_INSTS_VALU / (t x CUs x 2.4 GHz) (one
-    wave64 VALU instruction per CU and clock), lane efficiency = the priced
+    counters: VALU instructions per CU and clock at 2.4 GHz = SQ_INSTS_VALU
+    / (t x CUs x 2.4 GHz) (FP64 and integer instructions issue at most one
+    wave64 instruction per CU and clock, FP32 arithmetic up to two, so this
+    is a rate rather than a fraction), lane efficiency = the priced
     lane-slots / (SQ_INSTS_VALU x 64), active lanes per VALU instruction =
     SQ_THREAD_CYCLES_VALU / SQ_INSTS_VALU, and L2 atomics per second.  None
     when the counters are missing or stale."""
@@ -88,7 +90,7 @@ def issue_ratios(kernel_name, useful_lane_ops, kernel_ms, cus):
         return None
     t = kernel_ms * 1e-3
     v = c["SQ_INSTS_VALU"]
-    return {"valu_issue_frac": round(v / (t * cus * 2.4e9), 4),
+    return {"valu_insts_per_cu_clock": round(v / (t * cus * 2.4e9), 4),
             "lane_efficiency": round(useful_lane_ops / (v * 64.0), 4),
             "lanes_per_valu_inst": round(c["SQ_THREAD_CYCLES_VALU"] / v, 2),
             "atomics_per_s": round(c["TCC_ATOMIC_sum"] / t, 1),

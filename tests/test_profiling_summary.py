@@ -72,7 +72,7 @@ def test_traffic_counters_and_warm_up(run):
 def test_reported_ratios(run):
     r = profiling.issue_ratios(K, useful_lane_ops=2.56e11, kernel_ms=10.0, cus=256)
     # 6e9 wave instructions in 10 ms against 256 CUs x 2.4 GHz
-    assert r["valu_issue_frac"] == pytest.approx(6.0e9 / (0.010 * 256 * 2.4e9), rel=1e-3)
+    assert r["valu_insts_per_cu_clock"] == pytest.approx(6.0e9 / (0.010 * 256 * 2.4e9), rel=1e-3)
     assert r["lane_efficiency"] == pytest.approx(2.56e11 / (6.0e9 * 64), rel=1e-3)
     assert r["lanes_per_valu_inst"] == pytest.approx(53.33, abs=0.01)
     assert r["atomics_per_s"] == pytest.approx(2.0e8)
