@@ -154,10 +154,10 @@ mrt_status prepare(const mrt_source *source, const mrt_crystal *crystal, const m
     L.pixels = (size_t)detector->nx * (size_t)detector->ny;
 
     const bool rec = opt.records_mode != MRT_RECORDS_NONE;
+    const bool ext = !mwg && (mrt::uses_ext(source, crystal, rocking_curve) || opt.exact_decisions);
     L.kernel = mwg ? mrt::mwg_kernel_ptr(crystal->geometry, rec, source->polarisations != nullptr,
                                          crystal->planes != nullptr || rocking_curve->n_dep > 0)
-               : mrt::uses_ext(source, crystal, rocking_curve) || opt.exact_decisions
-                   ? mrt::ext_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
+               : ext ? mrt::ext_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
                                          rocking_curve->kind, rec)
                    : mrt::trace_kernel_ptr(opt.precision, crystal->geometry, mosaic->kind,
                                            rocking_curve->kind, rec);
@@ -172,7 +172,8 @@ mrt_status prepare(const mrt_source *source, const mrt_crystal *crystal, const m
             per_cu = 1;
         L.grid = cus * per_cu;
     }
-    P.refill_idle = opt.refill_idle > 0 ? (uint32_t)opt.refill_idle : 8u;
+    P.refill_idle = opt.refill_idle > 0 ? (uint32_t)opt.refill_idle
+                                        : mrt::default_refill(mwg || ext);
     // chunk size: enough chunks for every wave to claim several
     const uint64_t waves = (uint64_t)L.grid * (uint64_t)(L.block / 64);
     uint64_t chunk = n_rays / (waves * 8);
