@@ -499,6 +499,38 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
         tables.insert(tables.end(), d->qe_kev, d->qe_kev + d->n_qe);
         tables.insert(tables.end(), d->qe, d->qe + d->n_qe);
     }
+    // The table curve's envelope for the FP32 acceptance filter: the minimum
+    // and maximum node of each bucket of 2^env_shift nodes, as r / R_max
+    // rounded down and up to float, packed as a float pair in one table
+    // word.  The filter's interval of x (its 2e-6 rad band on either side,
+    // widened by the smallest width scale of the curve) covers at most two
+    // buckets when a bucket holds the interval's nodes plus two.
+    P.env_at = (int32_t)tables.size();
+    P.env_shift = 0;
+    if (r->kind == MRT_IRC_TABLE) {
+        double min_scale = 1.0;
+        for (int i = 0; i < r->n_dep; ++i) min_scale = std::min(min_scale, r->dep_scale[i]);
+        for (int j = 1; j < P.n_planes; ++j) min_scale = std::min(min_scale, P.plane_scale[j]);
+        const double width = 2.0 * 2e-6 / min_scale * P.lut_scale + 2.0;
+        int sh = 3;
+        while (sh < 12 && (double)(1 << sh) < width) ++sh;
+        P.env_shift = sh;
+        const int bn = 1 << sh;
+        for (int b = 0; b * bn < r->n_table; ++b) {
+            double lo = r->table[b * bn], hi = lo;
+            for (int i = b * bn; i < std::min(r->n_table, (b + 1) * bn); ++i) {
+                lo = std::min(lo, r->table[i]);
+                hi = std::max(hi, r->table[i]);
+            }
+            float fl = (float)(lo * P.lut_inv_max), fh = (float)(hi * P.lut_inv_max);
+            if ((double)fl > lo * P.lut_inv_max) fl = std::nextafter(fl, -1.0f);
+            if ((double)fh < hi * P.lut_inv_max) fh = std::nextafter(fh, 2.0f);
+            const float pair[2] = {fl, fh};
+            double word;
+            std::memcpy(&word, pair, sizeof word);
+            tables.push_back(word);
+        }
+    }
 
     // FP32 copies for the FP32-mixed kernels (round to nearest)
 #define MRT_F32_S(n) P.f32.n = (float)P.n;

@@ -194,6 +194,7 @@ void bind_scratch(Launch &L, void *scratch) {
     P.chunk_counter = P.dev_counters + mrt::kNumCounters;
     double *dtab = L.dtab = (double *)(P.dev_counters + kCounterWords);
     P.lut = P.irc == MRT_IRC_TABLE ? dtab : nullptr;
+    P.lut_env = P.irc == MRT_IRC_TABLE ? dtab + P.env_at : nullptr;
     P.bin_cdf = P.spectrum == MRT_SPECTRUM_TABLE ? dtab + (P.irc == MRT_IRC_TABLE ? P.lut_n : 0) : nullptr;
     P.psi_tab = L.mwg ? dtab + L.psi_at : nullptr;
     P.psi_cos2 = L.mwg ? P.psi_tab + 2 * (P.psi_nodes + 1) : nullptr;

@@ -138,6 +138,7 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     P.energy = r.d_energy;
     const int nl = P.irc == MRT_IRC_TABLE ? P.lut_n : 0;
     P.lut = nl ? r.d_tables : nullptr;
+    P.lut_env = nl ? r.d_tables + P.env_at : nullptr;
     P.bin_cdf = P.spectrum == MRT_SPECTRUM_TABLE ? r.d_tables + nl : nullptr;
     P.qe = P.qe_n > 0 ? r.d_tables + P.qe_at : nullptr;
     P.dep = P.dep_n > 0 ? r.d_tables + P.dep_at : nullptr;

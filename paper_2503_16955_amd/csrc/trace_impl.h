@@ -498,6 +498,37 @@ struct Tracer {
         return shi < x0 - __builtin_fabsf(x0) * 0x1p-20f - 1e-12f ||
                slo > x1 + __builtin_fabsf(x1) * 0x1p-20f + 1e-12f;
     }
+    // Bounds [r_lo, r_hi] of the table curve r / R_max over x in [slo, shi]
+    // from its envelope: the linear interpolation between two nodes lies
+    // between them, so r over the interval lies between the minimum and the
+    // maximum of the nodes it reaches, and those lie within the envelope of
+    // the buckets holding the first and the last of them.  The node
+    // coordinates are widened by 1/16 node, far beyond the float rounding of
+    // (x - x_min) x scale (below 1e-3 nodes up to 8192 nodes), and the
+    // values by 2^-20 relative, beyond the roundings of the interpolation
+    // and of its conversion to float.  false when the interval reaches more
+    // than two buckets or lies outside the table.
+    static __device__ __forceinline__ bool table_bounds(const TraceParams &P, float slo, float shi,
+                                                        float &r_lo, float &r_hi) {
+        const float x0 = P.f32.lut_x0, sc = P.f32.lut_scale;
+        const int last = P.lut_n - 1;
+        const float fa = (slo - x0) * sc - 0.0625f, fb = (shi - x0) * sc + 0.0625f;
+        if (!(fa < (float)last) || !(fb >= 0.0f)) return false;
+        const int ja = fa > 0.0f ? (int)fa : 0;
+        const int jb = fb < (float)last ? (int)fb + 1 : last;
+        const int ba = ja >> P.env_shift, bb = jb >> P.env_shift;
+        if (bb - ba > 1) return false;
+        // each word: (min, max) of a bucket as r / R_max, rounded outward to float
+        const uint64_t wa = (uint64_t)__double_as_longlong(P.lut_env[ba]);
+        const uint64_t wb = (uint64_t)__double_as_longlong(P.lut_env[bb]);
+        const float vlo = __builtin_fminf(__uint_as_float((uint32_t)wa), __uint_as_float((uint32_t)wb));
+        const float vhi = __builtin_fmaxf(__uint_as_float((uint32_t)(wa >> 32)),
+                                          __uint_as_float((uint32_t)(wb >> 32)));
+        r_hi = vhi * (1.0f + 0x1p-20f) + 1e-30f;
+        // zero where the interval leaves the table
+        r_lo = fa > 0.0f && fb < (float)last ? vlo * (1.0f - 0x1p-20f) : 0.0f;
+        return true;
+    }
     // The acceptance decision u_acc < r(x) / R_max from the bounds: 1
     // (accept), 0 (reject) or -1 (the exact FP64 evaluation decides).
     static __device__ __forceinline__ int filter(const TraceParams &P, double akn, float saf,
@@ -509,7 +540,11 @@ struct Tracer {
         float lo, hi, slo, shi;
         if (!x_bounds(akn, saf, caf, shift, inv_s, lo, hi, slo, shi)) return -1;
         if (irc_is(P, MRT_IRC_TABLE)) {
-            return outside_table(P, slo, shi) ? 0 : -1;
+            if (outside_table(P, slo, shi)) return 0;
+            float r_lo, r_hi;
+            if (!table_bounds(P, slo, shi, r_lo, r_hi)) return -1;
+            if (u_acc >= r_hi) return 0;
+            return u_acc < r_lo ? 1 : -1;
         } else if (irc_is(P, MRT_IRC_BOX)) {
             const float half = P.f32.box_half;
             if (hi < half * (1.0f - 0x1p-20f)) return 1;
@@ -542,6 +577,7 @@ struct Tracer {
         if (!x_bounds(akn, saf, caf, shift, inv_s, lo, hi, slo, shi)) return;
         if (irc_is(P, MRT_IRC_TABLE)) {
             if (outside_table(P, slo, shi)) r_hi = 0.0f;
+            else table_bounds(P, slo, shi, r_lo, r_hi);
         } else if (irc_is(P, MRT_IRC_BOX)) {
             const float half = P.f32.box_half;
             if (hi < half * (1.0f - 0x1p-20f)) r_lo = 1.0f;

@@ -27,7 +27,7 @@ constexpr int kMaxTableBytes = 64 * 1024;
     X(m_eta) X(inv_eta) X(inv_1meta) X(vmf_s2) X(vmf_floor) X(lor_g) X(wl_half_g2) X(wl_z)     \
     X(swl_k) X(swl_d) X(gau_2s2) X(shift) X(g_k) X(g_k_log2e) X(pv_a) X(pv_b) X(pv_h2)         \
     X(lor_h2)                                                                                  \
-    X(box_half) X(lut_x0) X(lut_x1) X(pitch) X(half_nx) X(half_ny)
+    X(box_half) X(lut_x0) X(lut_x1) X(lut_scale) X(pitch) X(half_nx) X(half_ny)
 #define MRT_F32_VECTORS(X) \
     X(so) X(sa) X(sb1) X(sb2) X(op) X(om) X(dP) X(dn) X(du) X(dv)
 
@@ -91,6 +91,10 @@ struct TraceParams {
     double lor_h2, box_half;
     double lut_x0, lut_x1, lut_scale, lut_inv_max;
     const double *lut;            // device
+    // the table's envelope: (min, max) of each bucket of 2^env_shift nodes,
+    // at index env_at of the tables (device pointer lut_env)
+    int32_t env_at, env_shift;
+    const double *lut_env;
     int32_t dep_n, dep_at;        // energy-dependence nodes; their index in the tables
     const double *dep;            // dep_n energies, shifts, width scales (device)
 

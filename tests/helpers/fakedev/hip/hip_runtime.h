@@ -64,6 +64,8 @@ inline const void *__builtin_amdgcn_kernarg_segment_ptr() { return nullptr; }
 
 inline long long __double_as_longlong(double x) { long long r; memcpy(&r, &x, 8); return r; }
 inline double __longlong_as_double(long long x) { double r; memcpy(&r, &x, 8); return r; }
+inline float __uint_as_float(unsigned int x) { float r; memcpy(&r, &x, 4); return r; }
+inline unsigned int __float_as_uint(float x) { unsigned int r; memcpy(&r, &x, 4); return r; }
 
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
 // Three-input bitwise operation by truth table: result bit i is bit

@@ -195,6 +195,7 @@ int emu_build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic
     if ((int)t.size() > tables_cap) return -2;
     for (size_t i = 0; i < t.size(); ++i) tables_out[i] = t[i];
     P->lut = P->irc == MRT_IRC_TABLE ? tables_out : nullptr;
+    P->lut_env = P->irc == MRT_IRC_TABLE ? tables_out + P->env_at : nullptr;
     P->bin_cdf = P->spectrum == MRT_SPECTRUM_TABLE ? tables_out + (P->irc == MRT_IRC_TABLE ? P->lut_n : 0)
                                                    : nullptr;
     P->qe = P->qe_n > 0 ? tables_out + P->qe_at : nullptr;
