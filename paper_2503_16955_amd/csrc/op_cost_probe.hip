@@ -97,6 +97,23 @@ extern "C" __global__ void probe_glue_u32(const unsigned *__restrict__ a, unsign
 FILTER_PROBE(filter_gaussian, MRT_IRC_GAUSSIAN)
 FILTER_PROBE(filter_pseudo_voigt, MRT_IRC_PSEUDO_VOIGT)
 FILTER_PROBE(filter_table, MRT_IRC_TABLE)
+// The table curve's decision as priced: the FP32 estimate of x and the
+// test against the table's range.  The envelope bounds the filter adds
+// only spare most of the exact evaluations inside the range, which are
+// not priced either.
+extern "C" __global__ void probe_filter_table_range(const TraceParams P, const double *__restrict__ a,
+                                                    double *__restrict__ o, int n) {
+    const int i = threadIdx.x;
+    double x = a[i];
+    const float sa = (float)a[i + 64], ca = (float)a[i + 128];
+    using T = tk::Tracer<double, MRT_GEOMETRY_CYLINDER, MRT_MOSAIC_PSEUDO_VOIGT, MRT_IRC_TABLE, false>;
+    for (int j = 0; j < n; ++j) {
+        float lo, hi, slo, shi;
+        const bool b = T::x_bounds(x, sa, ca, P.f32.shift, 1.0f, lo, hi, slo, shi);
+        x = x * 0.5 + (double)(b ? (T::outside_table(P, slo, shi) ? 0 : -1) : -1);
+    }
+    o[i] = x;
+}
 FILTER_PROBE(filter_lorentzian, MRT_IRC_LORENTZIAN)
 FILTER_PROBE(filter_box, MRT_IRC_BOX)
 extern "C" __global__ void probe_glue_filter(const TraceParams P, const double *__restrict__ a,
