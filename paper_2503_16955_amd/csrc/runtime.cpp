@@ -307,7 +307,7 @@ struct Stage {
 };
 std::mutex g_stage_mu;
 std::vector<Stage *> g_stages;
-constexpr size_t kStageBytes = (size_t)mrt::kMaxTableBytes + 3 * ((size_t)mrt::kMaxPsiNodes + 1) * sizeof(double);
+constexpr size_t kStageBytes = (size_t)mrt::kMaxStagedTableBytes + 3 * ((size_t)mrt::kMaxPsiNodes + 1) * sizeof(double);
 
 mrt_status stage_acquire(int dev, size_t bytes, Stage **out) {
     if (bytes > kStageBytes) return fail(MRT_EINVAL, "tables of %zu bytes exceed the staging size", bytes);

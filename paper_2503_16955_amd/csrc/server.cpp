@@ -72,7 +72,7 @@ struct mrt_server {
     // the slot (rewritten only when the slot is reassigned, by which time the
     // previous request's rounds, which waited for its uploads, are done)
     mrt::TraceParams *h_params = nullptr;
-    double *h_tables = nullptr;                 // max_slots x kMaxTableBytes
+    double *h_tables = nullptr;                 // max_slots x kMaxStagedTableBytes
     double busy_end = 0.0;                      // end of the last completed round (ms)
     mrt::TraceParams *d_slots = nullptr;
     unsigned long long *d_counters = nullptr;   // max_slots x kNumCounters
@@ -145,7 +145,7 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     P.dev_counters = S->d_counters + (size_t)slot * mrt::kNumCounters;
     P.records_mode = MRT_RECORDS_NONE;
     P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : mrt::default_refill(r.ext);
-    double *ht = S->h_tables + (size_t)slot * (mrt::kMaxTableBytes / sizeof(double));
+    double *ht = S->h_tables + (size_t)slot * (mrt::kMaxStagedTableBytes / sizeof(double));
     if (!r.tables.empty()) {
         std::memcpy(ht, r.tables.data(), r.tables.size() * sizeof(double));
         e = hipMemcpyAsync(r.d_tables, ht, r.tables.size() * sizeof(double),
@@ -427,7 +427,7 @@ mrt_status mrt_server_create(const mrt_server_config *config, mrt_server **out) 
     bool ok = hipStreamCreateWithFlags(&S->setup, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreate(&S->ev_ref) == hipSuccess && hipEventCreate(&S->ev_setup) == hipSuccess &&
               hipHostMalloc((void **)&S->h_params, sizeof(mrt::TraceParams) * ms, 0) == hipSuccess &&
-              hipHostMalloc((void **)&S->h_tables, (size_t)mrt::kMaxTableBytes * ms, 0) == hipSuccess &&
+              hipHostMalloc((void **)&S->h_tables, (size_t)mrt::kMaxStagedTableBytes * ms, 0) == hipSuccess &&
               hipMalloc((void **)&S->d_slots, sizeof(mrt::TraceParams) * ms) == hipSuccess &&
               hipMalloc((void **)&S->d_counters, sizeof(unsigned long long) * mrt::kNumCounters * ms) ==
                   hipSuccess;
@@ -462,6 +462,10 @@ mrt_status mrt_server_submit(mrt_server *S, const mrt_request *q, uint64_t *tick
     r.ext = mrt::uses_ext(q->source, q->crystal, q->rocking_curve);
     mrt::build_params(q->source, q->crystal, q->mosaic, q->rocking_curve, q->detector, r.P,
                       r.tables);
+    // the slot's staging holds the validated tables plus the curve's envelope
+    if (r.tables.size() * sizeof(double) > (size_t)mrt::kMaxStagedTableBytes)
+        return fail(MRT_EINVAL, "tables of %zu bytes exceed the staging size",
+                    r.tables.size() * sizeof(double));
     r.nx = q->detector->nx;
     r.ny = q->detector->ny;
     r.n_rays = q->n_rays;

@@ -17,6 +17,9 @@ constexpr int kMaxLines = 8;
 // Largest tables (rocking-curve values plus spectrum CDF), kept small enough
 // to stay cache-resident while the kernels read them.
 constexpr int kMaxTableBytes = 64 * 1024;
+// The library's own tables: the user's (at most kMaxTableBytes) plus the
+// table curve's envelope, one word per bucket of at least 8 nodes.
+constexpr int kMaxStagedTableBytes = kMaxTableBytes + kMaxTableBytes / 8;
 
 // Parameters the FP32-mixed kernels use in FP32 arithmetic.  The host keeps an
 // FP32 copy of each (rounded to nearest, as a device conversion would round

@@ -19,6 +19,7 @@
 #include <condition_variable>
 #include <deque>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <thread>
 
@@ -151,13 +152,37 @@ inline hipError_t hipFreeAsync(void *p, hipStream_t s) {
     s->push([p] { fake_free(p); });
     return hipSuccess;
 }
+// Pinned blocks by start address, so that a copy reading past the end of
+// one is counted (fake_pinned_overruns).
+inline std::mutex fake_pinned_mu;
+inline std::map<const char *, size_t> fake_pinned_blocks;
+inline std::atomic<long> fake_pinned_overruns{0};
 inline hipError_t hipHostMalloc(void **p, size_t b, unsigned) {
     fake_pinned_allocs.fetch_add(1);
     *p = calloc(1, b);
+    std::lock_guard<std::mutex> g(fake_pinned_mu);
+    fake_pinned_blocks[(const char *)*p] = b;
     return hipSuccess;
 }
-inline hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
+inline hipError_t hipHostFree(void *p) {
+    {
+        std::lock_guard<std::mutex> g(fake_pinned_mu);
+        fake_pinned_blocks.erase((const char *)p);
+    }
+    free(p);
+    return hipSuccess;
+}
+inline void fake_check_pinned(const void *s, size_t n) {
+    std::lock_guard<std::mutex> g(fake_pinned_mu);
+    auto it = fake_pinned_blocks.upper_bound((const char *)s);
+    if (it == fake_pinned_blocks.begin()) return;
+    --it;
+    const char *c = (const char *)s;
+    if (c < it->first + it->second && c + n > it->first + it->second) fake_pinned_overruns.fetch_add(1);
+}
 inline hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind, hipStream_t st) {
+    fake_check_pinned(s, n);
+    fake_check_pinned(d, n);
     st->push([d, s, n] { memcpy(d, s, n); });
     return hipSuccess;
 }

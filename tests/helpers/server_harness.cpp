@@ -100,4 +100,5 @@ long harness_free_bytes() { return fake_alloc_budget.load(); }
 void harness_gate(int open) { g_gate = open; }
 long harness_launches() { return g_launches.load(); }
 const char *harness_last_error() { return g_err.c_str(); }
+long harness_pinned_overruns() { return fake_pinned_overruns.load(); }
 }

@@ -246,6 +246,22 @@ void emu_filter_cases(const TraceParams *P, const double *lut, int n, const doub
     simt_ulp_bias = 0;
 }
 
+// The table curve's envelope as the filter reads it: the bucket shift, and
+// for an x interval [slo, shi] the bounds table_bounds gives (returns its
+// result), with the exact FP64 ratio at n_x points of the interval.
+int emu_table_bounds(const TraceParams *P, float slo, float shi, float *r_lo, float *r_hi,
+                     int n_x, double *x_out, double *ratio_out, int *env_shift) {
+    using T = Tracer<double, kAny, kAny, kAny, false, true>;
+    *env_shift = P->env_shift;
+    const bool ok = T::table_bounds(*P, slo, shi, *r_lo, *r_hi);
+    for (int i = 0; i < n_x; ++i) {
+        const double x = (double)slo + ((double)shi - (double)slo) * (double)i / (double)(n_x - 1);
+        x_out[i] = x;
+        ratio_out[i] = T::irc_ratio(*P, P->lut, x);
+    }
+    return ok ? 1 : 0;
+}
+
 // The paper's event model: its parameters, with the psi table appended at
 // tables_out[n_used...] (host memory the emulated kernel reads in place).
 int emu_build_mwg(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocking_curve *r,

@@ -143,3 +143,40 @@ def test_filter_bounds_and_decisions(emu, kind):
             n_decided += int(taken.sum())
     assert worst <= ERR_STATED, worst
     assert n_decided > 100_000
+
+
+def test_table_envelope_bounds_the_curve(emu):
+    """The table curve's envelope (the minimum and maximum node of each
+    bucket, rounded outward to float): over random x intervals of the
+    filter's width, around the peak, in the tails and across the table's
+    ends, the bounds hold the exact FP64 ratio at every sampled x; the
+    buckets are sized so that such an interval reaches at most two."""
+    w = _workload("table")
+    job = T.Job(emu, w, 64, 0)
+    f, i = C.c_float, C.c_int
+    emu.emu_table_bounds.argtypes = [C.c_void_p, f, f, C.POINTER(f), C.POINTER(f), i,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i)]
+    emu.emu_table_bounds.restype = i
+    rc = w["rocking_curve"]
+    x0, x1 = rc["x_min"], rc["x_max"]
+    rng = np.random.default_rng(77)
+    m = 33
+    xs, rs = np.zeros(m), np.zeros(m)
+    lo, hi, sh = f(), f(), i()
+    taken = 0
+    centres = np.concatenate([rng.uniform(x0 - 2e-5, x1 + 2e-5, 3000),
+                              rng.normal(0.0, 3e-5, 3000), [x0, x1, x0 + 1e-7, x1 - 1e-7]])
+    for c in centres:
+        half = rng.choice([2e-6, 2e-6 / 0.6, 5e-7])
+        slo, shi = np.float32(c - half), np.float32(c + half)
+        ok = emu.emu_table_bounds(job.P, slo, shi, C.byref(lo), C.byref(hi), m,
+                                  xs.ctypes.data_as(C.POINTER(C.c_double)),
+                                  rs.ctypes.data_as(C.POINTER(C.c_double)), C.byref(sh))
+        if not ok:
+            # only intervals beyond the table's ends go without bounds
+            assert shi < x0 or slo > x1 or half > 2.1e-6 or c < x0 + 1e-5 or c > x1 - 1e-5, c
+            continue
+        taken += 1
+        assert np.all(rs <= hi.value) and np.all(rs >= lo.value), (c, half, lo.value, hi.value)
+    assert taken > 5000
+    assert 3 <= sh.value <= 12

@@ -40,6 +40,7 @@ def lib(tmp_path_factory):
     L.harness_gate.argtypes = [C.c_int]
     L.harness_launches.restype = C.c_long
     L.harness_last_error.restype = C.c_char_p
+    L.harness_pinned_overruns.restype = C.c_long
     return L
 
 
@@ -189,6 +190,43 @@ def test_failed_launch_fails_its_round_only(lib):
         st2, r2 = s.wait(t2)
         assert st2 == 0 and r2.state == mrt.REQ_DONE and r2.rays_done == 3000
         assert lib.mrt_server_release(s.h, t1) == 0 and lib.mrt_server_release(s.h, t2) == 0
+    finally:
+        s.destroy()
+    assert lib.harness_free_bytes() == DEVICE_BYTES
+
+
+def test_largest_table_curve_in_every_slot(lib):
+    """A table rocking curve at the largest size the boundary admits (8192
+    nodes, 64 KiB) carries its filter envelope on top; its staging holds
+    both, in every slot at once, and one node more is refused at submit."""
+    lib.harness_init(DEVICE_BYTES, 0)
+    w = W.get("flat_hopg")
+    px = w["detector"]["nx"] * w["detector"]["ny"]
+    # nodes 0.24 mrad apart: the envelope's buckets are the smallest (8
+    # nodes), so it is the largest (1024 words)
+    x = np.linspace(-1.0, 1.0, 8192)
+    table = 0.9 * np.exp(-(x / 0.2) ** 2) + 1e-3
+    rc = w["rocking_curve"] = dict(kind="table", peak=float(table.max()), shift=0.0,
+                                   table=table.tolist(), x_min=-1.0, x_max=1.0)
+    s = Srv(lib, slots=4)
+    try:
+        tickets = []
+        # several rounds each, so that all four slots hold one at a time
+        for k in range(4):
+            st, t = s.submit(w, 30_000 + k, 40 + k)
+            assert st == 0, lib.harness_last_error()
+            tickets.append(t)
+        for k, t in enumerate(tickets):
+            st, r = s.wait(t)
+            assert st == 0 and r.state == mrt.REQ_DONE and r.rays_done == 30_000 + k
+            c, e = _images(r)
+            ec, ee, _ = expected(30_000 + k, 40 + k, px)
+            assert np.array_equal(c, ec) and np.array_equal(e, ee)
+            assert lib.mrt_server_release(s.h, t) == 0
+        assert lib.harness_pinned_overruns() == 0
+        rc["table"] = rc["table"] + [1e-3]
+        st, _ = s.submit(w, 100, 1)
+        assert st == mrt.EINVAL
     finally:
         s.destroy()
     assert lib.harness_free_bytes() == DEVICE_BYTES
