@@ -45,9 +45,13 @@ __device__ __forceinline__ Words philox(uint32_t k0, uint32_t k1, uint32_t c0, u
     return Words{c0, c1, c2, c3};
 }
 
-// Uniforms in the open interval (0, 1): (w + 1/2) 2^-32 as one fused
-// multiply-add (exact: 33 significant bits).
-__device__ __forceinline__ double u01_f64(uint32_t w) { return __builtin_fma((double)w, 0x1p-32, 0x1p-33); }
+// Uniforms in the open interval (0, 1): (w + 1/2) 2^-32 = (2w + 1) 2^-33,
+// the odd integer 2w + 1 from one FMA with the inline constants 2 and 1, and
+// the power of two by ldexp (both exact: 33 significant bits).  (The single
+// FMA w 2^-32 + 2^-33 needs its two 64-bit constants moved into vector
+// registers at every use.)
+__device__ __forceinline__ double odd_u01(uint32_t w) { return __builtin_fma((double)w, 2.0, 1.0); }
+__device__ __forceinline__ double u01_f64(uint32_t w) { return __builtin_ldexp(odd_u01(w), -33); }
 // 23 random bits, exact in float: ((w >> 9) + 1/2) 2^-23, as one fused
 // multiply-add of the exactly converted w >> 9 (the result has 24
 // significant bits, so nothing rounds).
@@ -125,9 +129,10 @@ __device__ __forceinline__ double rsqrt(double x) {
 // (there r reaches 2^-7, and the series' truncation stays below 2^-56
 // relative).  About 1 ulp.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double log_pos(double x) {
+// log of x 2^-bias (bias 0: log x): the scale enters only the exponent.
+__device__ __forceinline__ double log_scaled(double x, int bias) {
     const uint64_t b = (uint64_t)__double_as_longlong(x);
-    const int e = (int)(b >> 52) - 1023;
+    const int e = (int)(b >> 52) - (1023 + bias);
     const double m = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
     const LogEntry t = kLogTable[(b >> 45) & 127];
     const double r = fma(m, (double)t.inv, -1.0);
@@ -144,6 +149,10 @@ __device__ __forceinline__ double log_pos(double x) {
     const double lo = fma(de, 0x1.a39ef35793c76p-33, t.nlog_lo);
     return hi + (lo + l1p);
 }
+__device__ __forceinline__ double log_pos(double x) { return log_scaled(x, 0); }
+// log u01_f64(w), bit for bit: the same mantissa as 2w + 1, the exponent 33
+// lower, so the power of two never needs applying.
+__device__ __forceinline__ double log_u01(uint32_t w) { return log_scaled(odd_u01(w), 33); }
 
 // ---------------------------------------------------------------------------
 // exp(x) for x <= 0 (the mosaic densities, the rocking curves' Gaussians), by
@@ -175,10 +184,8 @@ __device__ __forceinline__ double exp_nonpos(double x) {
 // series to a^7 and a^6, then the angle-addition formulas with the table's
 // sin and cos of 2 pi q / 256 (exact at the quadrant points).  About 1 ulp.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sincos_turns(double u, double *sn, double *cs) {
-    const double q = __builtin_rint(256.0 * u);
-    const double r = fma(-0x1p-8, q, u);
-    const double a = fma(r, 0x1.921fb54442d18p+2, r * 0x1.1a62633145c07p-52);
+// The series and the table step for a = 2 pi r and the table index q mod 256.
+__device__ __forceinline__ void sincos_reduced(double a, int qi, double *sn, double *cs) {
     const double z = a * a;
     double ps = -1.0 / 5040.0;
     ps = poly_step(ps, z, 1.0 / 120.0);
@@ -188,10 +195,28 @@ __device__ __forceinline__ void sincos_turns(double u, double *sn, double *cs) {
     pc = poly_step(pc, z, 1.0 / 24.0);
     pc = poly_step(pc, z, -0.5);
     const double cm = z * pc;   // cos a - 1
-    const SinCosEntry t = kSinCosTable[(int)q & 255];
+    const SinCosEntry t = kSinCosTable[qi & 255];
     // the table value is added last, to the small corrections
     *sn = t.s + fma(t.s, cm, t.c * sa);
     *cs = t.c + fma(t.c, cm, -(t.s * sa));
+}
+__device__ __forceinline__ void sincos_turns(double u, double *sn, double *cs) {
+    const double q = __builtin_rint(256.0 * u);
+    const double r = fma(-0x1p-8, q, u);
+    sincos_reduced(fma(r, 0x1.921fb54442d18p+2, r * 0x1.1a62633145c07p-52), (int)q, sn, cs);
+}
+// sincos_turns(u01_f64(w)), bit for bit, with the reduction in integers: u =
+// (2w + 1) 2^-33 lies within 1/512 of q / 256 for q = round(256 u), never
+// halfway (2w + 1 is odd), so q = (w >> 24) + bit 23 of w, the table index
+// is (w + 2^23) >> 24 mod 256, and r = u - q / 256 = (2d + 1) 2^-33 with d
+// the low 24 bits of w read as a signed integer.  2 pi r is then formed from
+// t = 2d + 1 and the constants scaled by 2^-33, which rounds exactly as the
+// products with r do.
+__device__ __forceinline__ void sincos_u01(uint32_t w, double *sn, double *cs) {
+    const int d = (int)(w << 8) >> 8;
+    const double t = (double)(2 * d + 1);
+    sincos_reduced(fma(t, 0x1.921fb54442d18p-31, t * 0x1.1a62633145c07p-85),
+                   (int)((w + 0x800000u) >> 24), sn, cs);
 }
 
 // ---------------------------------------------------------------------------

@@ -70,6 +70,16 @@ template <class R> __device__ __forceinline__ V3<R> par3(const double *d, const 
 template <class R> __device__ __forceinline__ R uni(uint32_t w);
 template <> __device__ __forceinline__ double uni<double>(uint32_t w) { return dm::u01_f64(w); }
 template <> __device__ __forceinline__ float uni<float>(uint32_t w) { return dm::u01_f32(w); }
+// log uni<R>(w), and sin and cos of the turn uni<R>(w); FP64 without forming
+// the uniform (the same values bit for bit)
+template <class R> __device__ __forceinline__ R log_uni(uint32_t w) {
+    if constexpr (sizeof(R) == 8) return dm::log_u01(w);
+    else return dm::log_pos(dm::u01_f32(w));
+}
+template <class R> __device__ __forceinline__ void sincos_uni(uint32_t w, R *sn, R *cs) {
+    if constexpr (sizeof(R) == 8) dm::sincos_u01(w, sn, cs);
+    else dm::sincos_turns(dm::u01_f32(w), sn, cs);
+}
 
 // Per-lane ray state.
 template <class R, bool REC> struct RayEntry {};
@@ -312,7 +322,7 @@ struct Tracer {
         const Frame f = frame(P, p);
         return V3<R>{f.nx, f.ny, R(0)};
     }
-    static __device__ __forceinline__ V3<R> mosaic_normal(const TraceParams &P, R u2, R u3,
+    static __device__ __forceinline__ V3<R> mosaic_normal(const TraceParams &P, R u2, uint32_t w3,
                                                           Frame f) {
         R ct, st;
         if (mdf_is(P, MRT_MOSAIC_GAUSSIAN_VMF)) {
@@ -367,7 +377,7 @@ struct Tracer {
             st = R(0);
         }
         R sx, cx;
-        dm::sincos_turns(u3, &sx, &cx);
+        sincos_uni<R>(w3, &sx, &cx);   // azimuth uniform in turns
         // n = ct N + st (cx e1 + sx e2)
         if (is_flat(P)) return V3<R>{st * cx, st * sx, ct};
         const R ss = st * sx;
@@ -604,9 +614,13 @@ struct Tracer {
                                        (uint32_t)(ry.id >> 32), 1u);
         ++ry.nev;
         const int exit_status = ry.nrefl ? MRT_EXIT_REFLECTED : MRT_EXIT_TRANSMITTED;
-        if ((int)ry.nrefl >= P.max_refl) {
-            // reflection budget spent: Beer-Lambert absorption only
-            const R l = -dm::log_pos(uni<R>(w.w0)) * par<R>(P.inv_mu0, P.f32.inv_mu0);
+        // free path to the next event at the majorant rate (Eq. AnyEvent),
+        // or once the reflection budget is spent to the absorption at mu0
+        const bool spent = (int)ry.nrefl >= P.max_refl;
+        const R nlog = -log_uni<R>(w.w0);
+        if (spent) {
+            // Beer-Lambert absorption only
+            const R l = nlog * par<R>(P.inv_mu0, P.f32.inv_mu0);
             if (l < ry.dist) {
                 ry.p = axpy(ry.p, l, ry.k);
                 return MRT_ABSORBED;
@@ -614,8 +628,7 @@ struct Tracer {
             ry.p = axpy(ry.p, ry.dist, ry.k);
             return exit_status;
         }
-        // free path to the next event at the majorant rate (Eq. AnyEvent)
-        const R l = -dm::log_pos(uni<R>(w.w0)) * par<R>(P.inv_mu_tot, P.f32.inv_mu_tot);
+        const R l = nlog * par<R>(P.inv_mu_tot, P.f32.inv_mu_tot);
         if (l >= ry.dist) {
             ry.p = axpy(ry.p, ry.dist, ry.k);
             return exit_status;
@@ -628,7 +641,7 @@ struct Tracer {
         if (!(ry.sa < 1.0)) return -1;         // no Bragg angle: never reflects
         const R u_acc = (u1 - pa) * par<R>(P.inv_1mpa, P.f32.inv_1mpa);
 
-        const V3<R> n = mosaic_normal(P, uni<R>(w.w2), uni<R>(w.w3), frame(P, ry.p));
+        const V3<R> n = mosaic_normal(P, uni<R>(w.w2), w.w3, frame(P, ry.p));
         // Bragg deviation in FP64, k.n accumulated in FP64 from the components
         const double kn = (double)ry.k.x * (double)n.x + (double)ry.k.y * (double)n.y +
                           (double)ry.k.z * (double)n.z;
@@ -787,7 +800,7 @@ struct Tracer {
         const R ct = R(1) - v;
         const R st = dm::sqrt(v * (R(2) - v));
         R sp, cp;
-        dm::sincos_turns(uni<R>(a.w1), &sp, &cp);
+        sincos_uni<R>(a.w1, &sp, &cp);
         const V3<R> ax = par3<R>(P.sa, P.f32.sa), b1 = par3<R>(P.sb1, P.f32.sb1), b2 = par3<R>(P.sb2, P.f32.sb2);
         return V3<R>{ct * ax.x + st * (cp * b1.x + sp * b2.x),
                      ct * ax.y + st * (cp * b1.y + sp * b2.y),
@@ -805,8 +818,8 @@ struct Tracer {
             if (pick >= P.n_lines) return P.e_min + s3 * P.e_span;
             const dm::Words b = dm::philox(P.key0, P.key1, 1u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
             double sg, cg;
-            dm::sincos_turns(dm::u01_f64(b.w0), &sg, &cg);
-            return P.line_e[pick] + P.line_sig[pick] * dm::sqrt(-2.0 * dm::log_pos(s3)) * cg;
+            dm::sincos_u01(b.w0, &sg, &cg);
+            return P.line_e[pick] + P.line_sig[pick] * dm::sqrt(-2.0 * dm::log_u01(a.w3)) * cg;
         }
         // largest bin b with cdf[b] <= s2, uniform inside the bin
         int lo = 0, hi = P.n_bins - 1;
@@ -926,19 +939,20 @@ struct Tracer {
         if (P.user_e) return P.user_e[ray - P.first];
         return energy(P, cdf, a, ray);
     }
-    // Offset (x, y) of a ray's origin in the spot plane from uniforms u, v:
-    // Gaussian, sigma_x sqrt(-2 ln u) (cos, sin)(2 pi v) (Box-Muller), or
-    // uniform over the disk of radius sigma_x, sigma_x sqrt(u) (cos, sin)(2 pi v).
-    static __device__ __forceinline__ void spot_offset(const TraceParams &P, double u, double v,
-                                                       double &x, double &y) {
+    // Offset (x, y) of a ray's origin in the spot plane from the uniforms u,
+    // v of words wu, wv: Gaussian, sigma_x sqrt(-2 ln u) (cos, sin)(2 pi v)
+    // (Box-Muller), or uniform over the disk of radius sigma_x, sigma_x
+    // sqrt(u) (cos, sin)(2 pi v).
+    static __device__ __forceinline__ void spot_offset(const TraceParams &P, uint32_t wu,
+                                                       uint32_t wv, double &x, double &y) {
         double s, c;
-        dm::sincos_turns(v, &s, &c);
+        dm::sincos_u01(wv, &s, &c);
         if (P.spot_kind == MRT_SPOT_GAUSSIAN) {
-            const double r = dm::sqrt(-2.0 * dm::log_pos(u));
+            const double r = dm::sqrt(-2.0 * dm::log_u01(wu));
             x = P.spot_sigma[0] * r * c;
             y = P.spot_sigma[1] * r * s;
         } else {
-            const double r = P.spot_sigma[0] * dm::sqrt(u);
+            const double r = P.spot_sigma[0] * dm::sqrt(dm::u01_f64(wu));
             x = r * c;
             y = r * s;
         }
@@ -966,7 +980,7 @@ struct Tracer {
                 // finite source spot (sec. 4.2): words 1, 2 of the source's second draw
                 const dm::Words b = dm::philox(P.key0, P.key1, 1u, (uint32_t)ray, (uint32_t)(ray >> 32), 0u);
                 double x, y;
-                spot_offset(P, dm::u01_f64(b.w1), dm::u01_f64(b.w2), x, y);
+                spot_offset(P, b.w1, b.w2, x, y);
                 for (int c = 0; c < 3; ++c) od[c] += x * P.spot_u[c] + y * P.spot_v[c];
             }
             o = V3<R>{cvt<R>(od[0]), cvt<R>(od[1]), cvt<R>(od[2])};

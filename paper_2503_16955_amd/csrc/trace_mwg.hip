@@ -217,7 +217,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             sig_a = qc * ia;
         }
         const double mu = P.mu0 + sig_h + sig_a;
-        const double l = -dm::log_pos(dm::u01_f64(w.w0)) / mu;
+        const double l = -dm::log_u01(w.w0) / mu;
         if (l >= dist) {
             ry.p = axpy(ry.p, dist, ry.k);
             return exit_status;
@@ -287,7 +287,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             }
         }
         const double mu = P.mu0 + sum;
-        const double l = -dm::log_pos(dm::u01_f64(w.w0)) / mu;
+        const double l = -dm::log_u01(w.w0) / mu;
         if (l >= dist) {
             ry.p = axpy(ry.p, dist, ry.k);
             return exit_status;

@@ -5,7 +5,10 @@
 // exactly in quarter turns as well).  Also every FP32 uniform u01_f32(w)
 // against its definition ((w >> 9) 2 + 1) 2^-24 in exact arithmetic, over all
 // 2^23 values of w >> 9, and the FP64 uniform (w + 1/2) 2^-32 on 2^24 words.
-// Prints "log L sin S cos C exp X u01_f32_mismatches M" (M counts both uniforms).
+// And log_u01 and sincos_u01 (the forms fed by the word) bit for bit equal
+// to log_pos and sincos_turns of the word's uniform.  Prints "log L sin S cos
+// C exp X u01_f32_mismatches M u01_identity_mismatches I" (M counts both
+// uniforms).
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdio>
@@ -112,8 +115,26 @@ int main() {
     }
     for (uint32_t w : {0u, 1u, 0xffffffffu, 0x80000000u})
         if ((long double)dm::u01_f64(w) != ((long double)w + 0.5L) * 0x1p-32L) ++mismatches;
-    printf("log %.4f sin %.4f cos %.4f exp %.4f u01_f32_mismatches %ld\n", worst_log, worst_sin,
-           worst_cos, worst_exp, mismatches);
+    // the uniform-fed forms against the general ones on the uniform, bit for
+    // bit: 2^24 words spread over the range, every word within 64 of the
+    // points where the integer reduction changes (bit 23 set or clear, the
+    // top byte wrapping), and the ends
+    long identity = 0;
+    auto same = [](double a, double b) { return std::memcmp(&a, &b, sizeof a) == 0; };
+    auto check = [&](uint32_t w) {
+        const double u = dm::u01_f64(w);
+        if (!same(dm::log_u01(w), dm::log_pos(u))) ++identity;
+        double s1, c1, s2, c2;
+        dm::sincos_u01(w, &s1, &c1);
+        dm::sincos_turns(u, &s2, &c2);
+        if (!same(s1, s2) || !same(c1, c2)) ++identity;
+    };
+    for (uint64_t k = 0; k < (1u << 24); ++k) check((uint32_t)(k * 257u + (k >> 12)));
+    for (uint32_t top = 0; top < 256; ++top)
+        for (uint32_t edge : {0u, 0x7fffffu, 0x800000u, 0xffffffu})
+            for (int d = -64; d <= 64; ++d) check((top << 24) + edge + (uint32_t)d);
+    printf("log %.4f sin %.4f cos %.4f exp %.4f u01_f32_mismatches %ld u01_identity_mismatches %ld\n",
+           worst_log, worst_sin, worst_cos, worst_exp, mismatches, identity);
     (void)wl_x;
     (void)ws_x;
 }

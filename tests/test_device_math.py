@@ -2,7 +2,9 @@
 sin/cos of turns, in
 device_math.h) compiled for the host and compared with long-double
 references: a few ulps at most, far inside the 1e-12 per-ray parity
-contract; and the FP32 uniform equal to its definition for every word."""
+contract; the FP32 uniform equal to its definition for every word; and
+the word-fed log and sin/cos (log_u01, sincos_u01) bit for bit equal to the
+general routines on the word's uniform."""
 import os
 import shutil
 import subprocess
@@ -28,3 +30,4 @@ def test_fp64_log_and_sincos_within_two_ulps(tmp_path):
     assert err["sin"] <= 2.5 and err["cos"] <= 2.5, err
     assert err["exp"] <= 2.0, err
     assert err["u01_f32_mismatches"] == 0
+    assert err["u01_identity_mismatches"] == 0
