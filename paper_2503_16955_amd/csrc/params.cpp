@@ -251,20 +251,24 @@ void build_mwg_params(const mrt_crystal *c, const mrt_mosaic *m, const mrt_rocki
     P.swl_norm = P.swl_a * (P.swl_a + 2.0) / (4.0 * kPi);
     P.gau_inv2s2 = 1.0 / (2.0 * sv * sv);
     P.gau_norm = 1.0 / (2.0 * kPi * sv * sv);
-    // nodes psi_j = pi (j / M)^3, dense near psi = 0
-    double prev = 0.0;
-    for (int j = 0; j <= psi_nodes; ++j) {
+    // nodes psi_j = pi (j / M)^3, dense near psi = 0: (sin^2(psi_j / 2),
+    // w_j) with the trapezoid weight w_j = (psi_{j+1} - psi_{j-1}) / 2 (the
+    // missing neighbour of an end node taken as the node itself)
+    auto node = [psi_nodes](int j) {
         const double t = (double)j / (double)psi_nodes;
-        const double pj = kPi * t * t * t;
-        psi.push_back(std::sin(pj / 2.0));
-        psi.push_back(pj - prev);
-        prev = pj;
-    }
-    // then cos(2 psi_j), j = 0..M, for the polarised cross-section
+        return kPi * t * t * t;
+    };
+    std::vector<double> w(psi_nodes + 1);
     for (int j = 0; j <= psi_nodes; ++j) {
-        const double t = (double)j / (double)psi_nodes;
-        psi.push_back(std::cos(2.0 * kPi * t * t * t));
+        const double lo = j > 0 ? node(j) - node(j - 1) : 0.0;
+        const double hi = j < psi_nodes ? node(j + 1) - node(j) : 0.0;
+        w[j] = (lo + hi) / 2.0;
+        const double b = std::sin(node(j) / 2.0);
+        psi.push_back(b * b);
+        psi.push_back(w[j]);
     }
+    // then w_j cos(2 psi_j), j = 0..M, for the polarised cross-section
+    for (int j = 0; j <= psi_nodes; ++j) psi.push_back(w[j] * std::cos(2.0 * node(j)));
 }
 
 bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve *r) {

@@ -91,36 +91,63 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
     // ---- psi integrals of Eq. SimpleReflXsection for alpha and -alpha ----
     // Trapezoid rule over psi_j = pi (j / M)^3 on [0, pi], doubled (the
     // integrand is even); v = 2 sin^2((a - beta)/2) + 2 cos(a) cos(beta)
-    // sin^2(psi/2) by Eq. ThetaPsi.  The table holds (sin(psi_j / 2),
-    // psi_j - psi_{j-1}) per node; its index is wave-uniform (scalar loads).
-    // With polarisation (C2) the same rule also sums W cos(2 psi) on [0, pi]
-    // (i2h, i2a; the table cos(2 psi_j) follows the node table): W is even,
-    // so int W G over [-pi, pi] with G = 1 - S cos^2(phi' - psi) is
-    // (1 - S/2) int W - S cos(2 phi') int_0^pi W cos(2 psi).
+    // sin^2(psi/2) by Eq. ThetaPsi.  The table holds (sin^2(psi_j / 2), w_j)
+    // per node, w_j the node's trapezoid weight (half the sum of its two
+    // intervals); its index is wave-uniform (scalar loads).  The von
+    // Mises-Fisher density exp(-kappa v) at v = v0 + b is exp(-kappa v0)
+    // exp(-kappa b): one exponential per node serves the H and the anti-H
+    // planes (also for the pseudo-Voigt mosaic's vMF part).  With
+    // polarisation (C2) the same rule also sums W cos(2 psi) on [0, pi] (i2h,
+    // i2a; the table w_j cos(2 psi_j) follows the node table): W is even, so
+    // int W G over [-pi, pi] with G = 1 - S cos^2(phi' - psi) is (1 - S/2)
+    // int W - S cos(2 phi') int_0^pi W cos(2 psi).
     template <int K, bool C2>
     static __device__ __forceinline__ void psi_pair(const TraceParams &P, double alpha, double beta,
                                                     double &ih, double &ia, double &i2h,
                                                     double &i2a) {
+        constexpr bool kVmf = K == MRT_MOSAIC_GAUSSIAN_VMF || K == MRT_MOSAIC_PSEUDO_VOIGT;
         const double sh = sin_((alpha - beta) / 2.0), sa = sin_((-alpha - beta) / 2.0);
         const double v0h = 2.0 * sh * sh, v0a = 2.0 * sa * sa;
         const double cc = 2.0 * cos_(alpha) * cos_(beta);
-        double fh = density<K>(P, v0h), fa = density<K>(P, v0a), sum_h = 0.0, sum_a = 0.0;
-        double c2p = 1.0, s2h = 0.0, s2a = 0.0;   // cos(2 psi_0) = 1
-        const double *tab = P.psi_tab;
-        for (int j = 1; j <= P.psi_nodes; ++j) {
-            const double b = tab[2 * j], dpsi = tab[2 * j + 1];
-            const double bb = cc * b * b;
-            const double gh = density<K>(P, v0h + bb), ga = density<K>(P, v0a + bb);
-            sum_h += dpsi * (fh + gh) / 2.0;
-            sum_a += dpsi * (fa + ga) / 2.0;
-            if constexpr (C2) {
-                const double c2 = P.psi_cos2[j];
-                s2h += dpsi * (fh * c2p + gh * c2) / 2.0;
-                s2a += dpsi * (fa * c2p + ga * c2) / 2.0;
-                c2p = c2;
+        double eh = 0.0, ea = 0.0;   // the vMF parts at v0h, v0a
+        if constexpr (kVmf) {
+            const double c = K == MRT_MOSAIC_PSEUDO_VOIGT ? (1.0 - P.m_eta) * P.vmf_norm : P.vmf_norm;
+            eh = c * dm::exp_nonpos(-P.vmf_kappa * v0h);
+            ea = c * dm::exp_nonpos(-P.vmf_kappa * v0a);
+        }
+        // the densities at v0h + b and v0a + b
+        auto node = [&](double b, double &gh, double &ga) {
+            if constexpr (kVmf) {
+                const double e = dm::exp_nonpos(-P.vmf_kappa * b);
+                gh = eh * e;
+                ga = ea * e;
+                if constexpr (K == MRT_MOSAIC_PSEUDO_VOIGT) {
+                    gh = fma(P.m_eta, density<MRT_MOSAIC_LORENTZIAN>(P, v0h + b), gh);
+                    ga = fma(P.m_eta, density<MRT_MOSAIC_LORENTZIAN>(P, v0a + b), ga);
+                }
+            } else {
+                gh = density<K>(P, v0h + b);
+                ga = density<K>(P, v0a + b);
             }
-            fh = gh;
-            fa = ga;
+        };
+        const double *tab = P.psi_tab;
+        double gh, ga;
+        node(0.0, gh, ga);
+        double sum_h = tab[1] * gh, sum_a = tab[1] * ga, s2h = 0.0, s2a = 0.0;
+        if constexpr (C2) {
+            s2h = P.psi_cos2[0] * gh;
+            s2a = P.psi_cos2[0] * ga;
+        }
+        for (int j = 1; j <= P.psi_nodes; ++j) {
+            const double b2 = tab[2 * j], wj = tab[2 * j + 1];
+            node(cc * b2, gh, ga);
+            sum_h = fma(wj, gh, sum_h);
+            sum_a = fma(wj, ga, sum_a);
+            if constexpr (C2) {
+                const double wc = P.psi_cos2[j];
+                s2h = fma(wc, gh, s2h);
+                s2a = fma(wc, ga, s2a);
+            }
         }
         ih = 2.0 * sum_h;
         ia = 2.0 * sum_a;

@@ -111,8 +111,8 @@ struct TraceParams {
     double wl_g2, wl_norm;        // (Gamma/2)^2 and 1 / (pi ln((g^2 + 4) / g^2))
     double swl_a, swl_norm;       // 2 sinh^2(Gamma/4) and A (A + 2) / (4 pi)
     double gau_inv2s2, gau_norm;  // 1 / (2 s^2) and 1 / (2 pi s^2)
-    const double *psi_tab;        // (sin(psi_j / 2), psi_j - psi_{j-1}), j = 0..M (device)
-    const double *psi_cos2;       // cos(2 psi_j), j = 0..M (device; after psi_tab)
+    const double *psi_tab;        // (sin^2(psi_j / 2), trapezoid weight w_j), j = 0..M (device)
+    const double *psi_cos2;       // w_j cos(2 psi_j), j = 0..M (device; after psi_tab)
 
     // ---- detector (sec. 2.3), local coordinates
     double dP[3], dn[3], du[3], dv[3];

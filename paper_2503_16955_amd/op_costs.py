@@ -238,6 +238,20 @@ def _density_cost(mosaic):
             "gaussian": D["rcp"] + D["exp"] + 9 * a}[mosaic]
 
 
+def _node_cost(mosaic):
+    """Issue slots of one node of the psi quadrature: the density at v0 + b
+    for the H and the anti-H planes.  The vMF density splits as exp(-kappa
+    v0) exp(-kappa b), so one exponential and two products serve both sides
+    (for the pseudo-Voigt mosaic's vMF part too)."""
+    D, a = OP_COSTS["f64"], SLOT_WEIGHT["alu64"]
+    vmf = D["exp"] + 3 * a
+    if mosaic == "gaussian_vmf":
+        return vmf
+    if mosaic == "pseudo_voigt":
+        return vmf + 2 * (a + _density_cost("lorentzian") + a)
+    return 2 * (a + _density_cost(mosaic))
+
+
 def _irc_cost(irc):
     D, a = OP_COSTS["f64"], SLOT_WEIGHT["alu64"]
     return {"gaussian": D["exp"] + 3 * a, "pseudo_voigt": D["div"] + D["exp"] + 8 * a,
@@ -262,8 +276,10 @@ def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False):
     frame = (D["rsqrt"] + 18 * a) if cyl else 0.0
     W = _density_cost(mosaic)
     sc = D["sincos"]
+    # per node: b = 2 cos(a) cos(beta) sin^2(psi_j / 2), the densities, and
+    # the weighted sums (two FMAs)
     quad = (2 * D["asin"] + 4 * sc + 10 * a + 2 * W
-            + psi_nodes * (2 * W + 8 * a) + sc + 3 * a)
+            + psi_nodes * (_node_cost(mosaic) + 3 * a) + sc + 3 * a)
     event = (OP_COSTS["philox"] + 3 * 2 * a + exit_d + frame + 5 * a + quad
              + D["log"] + 2 * D["div"] + 14 * a)
     R = _irc_cost(irc)
@@ -274,14 +290,14 @@ def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False):
                   + orient)
     if pol:
         # Eq. SimpleReflXsectionPol: the sum of W cos(2 psi) beside the plain
-        # one on every node (a table load, a product and an FMA per side), the
+        # one on every node (an FMA per side with the weighted table), the
         # polarisation's frame (u, k x u, two dots, their normalisation) and
         # sin^2(2 beta) per event; Eq. ReflXsectionPol: the frame once per
         # reflection and, per sweep, G in both target evaluations and
         # sin^2(2 b) in the Delta move; the polarisation's update after the
         # reflection
         frame_p = 6 * D["div"] + 30 * a + D["sqrt"] + D["div"] + 4 * a
-        event += psi_nodes * 4 * a + frame_p + sc + 8 * a
+        event += psi_nodes * 2 * a + frame_p + sc + 8 * a
         sweep_extra = 2 * 6 * a + 3 * a
         sweep += sweep_extra
         reflection += frame_p + burn_in * sweep_extra + 14 * a + D["sqrt"] + 3 * D["div"]
