@@ -115,16 +115,44 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             eh = c * dm::exp_nonpos(-P.vmf_kappa * v0h);
             ea = c * dm::exp_nonpos(-P.vmf_kappa * v0a);
         }
-        // the densities at v0h + b and v0a + b
-        auto node = [&](double b, double &gh, double &ga) {
+        // The Lorentzian density cau_norm q^(-3/2), zero from v = 1 on, with
+        // q(v) = v (2 - v) + g^2 (1 - v)^2 = g^2 + (1 - g^2)(2v - v^2): at v =
+        // v0 + cc t, t = sin^2(psi_j / 2), a quadratic q = l0 + l1 t + l2 t^2
+        // with l0 = q(v0), l1 = 2 (1 - g^2) cc (1 - v0), l2 = -(1 - g^2) cc^2
+        // (the two terms in t differ in sign by at most a factor 2 below v =
+        // 1, so nothing cancels), and v < 1 while cc t < 1 - v0.
+        constexpr bool kLor = K == MRT_MOSAIC_LORENTZIAN || K == MRT_MOSAIC_PSEUDO_VOIGT;
+        struct Lor {
+            double l0, l1, l2, room;
+        };
+        auto lor_at = [&](double v0) {
+            const double k = 1.0 - P.cau_g2, c0 = 1.0 - v0;
+            return Lor{v0 * (2.0 - v0) + P.cau_g2 * c0 * c0, 2.0 * k * cc * c0, -k * (cc * cc), c0};
+        };
+        const double lor_scale = K == MRT_MOSAIC_PSEUDO_VOIGT ? P.m_eta * P.cau_norm : P.cau_norm;
+        auto lor = [&](const Lor &L, double t, double b) {
+            const double rq = dm::rsqrt(fma(fma(L.l2, t, L.l1), t, L.l0));
+            return b < L.room ? (lor_scale * rq) * (rq * rq) : 0.0;
+        };
+        Lor lh{}, la{};
+        if constexpr (kLor) {
+            lh = lor_at(v0h);
+            la = lor_at(v0a);
+        }
+        // the densities at v0h + cc t and v0a + cc t
+        auto node = [&](double t, double &gh, double &ga) {
+            const double b = cc * t;
             if constexpr (kVmf) {
                 const double e = dm::exp_nonpos(-P.vmf_kappa * b);
                 gh = eh * e;
                 ga = ea * e;
                 if constexpr (K == MRT_MOSAIC_PSEUDO_VOIGT) {
-                    gh = fma(P.m_eta, density<MRT_MOSAIC_LORENTZIAN>(P, v0h + b), gh);
-                    ga = fma(P.m_eta, density<MRT_MOSAIC_LORENTZIAN>(P, v0a + b), ga);
+                    gh += lor(lh, t, b);
+                    ga += lor(la, t, b);
                 }
+            } else if constexpr (kLor) {
+                gh = lor(lh, t, b);
+                ga = lor(la, t, b);
             } else {
                 gh = density<K>(P, v0h + b);
                 ga = density<K>(P, v0a + b);
@@ -139,8 +167,8 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             s2a = P.psi_cos2[0] * ga;
         }
         for (int j = 1; j <= P.psi_nodes; ++j) {
-            const double b2 = tab[2 * j], wj = tab[2 * j + 1];
-            node(cc * b2, gh, ga);
+            const double t = tab[2 * j], wj = tab[2 * j + 1];
+            node(t, gh, ga);
             sum_h = fma(wj, gh, sum_h);
             sum_a = fma(wj, ga, sum_a);
             if constexpr (C2) {

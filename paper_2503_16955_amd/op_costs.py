@@ -242,13 +242,19 @@ def _node_cost(mosaic):
     """Issue slots of one node of the psi quadrature: the density at v0 + b
     for the H and the anti-H planes.  The vMF density splits as exp(-kappa
     v0) exp(-kappa b), so one exponential and two products serve both sides
-    (for the pseudo-Voigt mosaic's vMF part too)."""
+    (for the pseudo-Voigt mosaic's vMF part too).  The Lorentzian's q is a
+    quadratic in the node's sin^2(psi/2) (two FMAs), then q^(-3/2) from one
+    reciprocal square root and three products, the range test and its
+    select."""
     D, a = OP_COSTS["f64"], SLOT_WEIGHT["alu64"]
     vmf = D["exp"] + 3 * a
+    lor = D["rsqrt"] + 8 * a
     if mosaic == "gaussian_vmf":
         return vmf
+    if mosaic == "lorentzian":
+        return 2 * lor
     if mosaic == "pseudo_voigt":
-        return vmf + 2 * (a + _density_cost("lorentzian") + a)
+        return vmf + 2 * (lor + a)
     return 2 * (a + _density_cost(mosaic))
 
 
