@@ -238,16 +238,30 @@ def _density_cost(mosaic):
             "gaussian": D["rcp"] + D["exp"] + 9 * a}[mosaic]
 
 
-def _node_cost(mosaic):
+def vmf_live_fraction(fwhm, psi_nodes):
+    """Share of the quadrature's nodes psi_j = pi (j/M)^3 at which the vMF
+    factor exp(-kappa b), b = cc sin^2(psi_j / 2), can be nonzero (kappa b <=
+    746), taken at the largest cc = 2 cos(alpha) cos(beta), 2: the fewest
+    nodes, so the exponentials are never over-priced."""
+    import math
+    sv = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    kappa = 1.0 / (sv * sv)
+    live = sum(1 for j in range(1, psi_nodes + 1)
+               if kappa * 2.0 * math.sin(math.pi * (j / psi_nodes) ** 3 / 2.0) ** 2 <= 746.0)
+    return live / psi_nodes
+
+
+def _node_cost(mosaic, live=1.0):
     """Issue slots of one node of the psi quadrature: the density at v0 + b
     for the H and the anti-H planes.  The vMF density splits as exp(-kappa
     v0) exp(-kappa b), so one exponential and two products serve both sides
-    (for the pseudo-Voigt mosaic's vMF part too).  The Lorentzian's q is a
-    quadratic in the node's sin^2(psi/2) (two FMAs), then q^(-3/2) from one
-    reciprocal square root and three products, the range test and its
-    select."""
+    (for the pseudo-Voigt mosaic's vMF part too); past kappa b = 746 the
+    exponential is exactly zero and skipped (`live`: the share of nodes
+    before that).  The Lorentzian's q is a quadratic in the node's
+    sin^2(psi/2) (two FMAs), then q^(-3/2) from one reciprocal square root
+    and three products, the range test and its select."""
     D, a = OP_COSTS["f64"], SLOT_WEIGHT["alu64"]
-    vmf = D["exp"] + 3 * a
+    vmf = live * D["exp"] + 4 * a
     lor = D["rsqrt"] + 8 * a
     if mosaic == "gaussian_vmf":
         return vmf
@@ -264,7 +278,7 @@ def _irc_cost(irc):
             "lorentzian": D["div"] + 3 * a, "box": 2 * a, "table": 15 * a}[irc]
 
 
-def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False):
+def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False, vmf_live=1.0):
     """Operation mix per unit of the paper's event model, in issue slots.
 
     Units: 'ray' and 'entered' as in mix() (FP64); 'event' (one free path:
@@ -274,7 +288,8 @@ def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False):
     the sampler, each one Philox, a psi move and a Delta move re-evaluating
     only the factors they change, then the crystallite's orientation and the
     reflection); 'detected' as in mix().  Sines and cosines are priced as
-    the table-driven sin/cos of turns."""
+    the table-driven sin/cos of turns; `vmf_live`: the share of quadrature
+    nodes whose vMF exponential can be nonzero (vmf_live_fraction)."""
     D, a = OP_COSTS["f64"], SLOT_WEIGHT["alu64"]
     base = mix("fp64", geometry, "gaussian_vmf", "gaussian", spectrum)
     cyl = geometry == "cylinder"
@@ -285,7 +300,7 @@ def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False):
     # per node: b = 2 cos(a) cos(beta) sin^2(psi_j / 2), the densities, and
     # the weighted sums (two FMAs)
     quad = (2 * D["asin"] + 4 * sc + 10 * a + 2 * W
-            + psi_nodes * (_node_cost(mosaic) + 3 * a) + sc + 3 * a)
+            + psi_nodes * (_node_cost(mosaic, vmf_live) + 3 * a) + sc + 3 * a)
     event = (OP_COSTS["philox"] + 3 * 2 * a + exit_d + frame + 5 * a + quad
              + D["log"] + 2 * D["div"] + 14 * a)
     R = _irc_cost(irc)
@@ -318,7 +333,8 @@ def algorithmic_ops_mwg(workload, counters, psi_nodes, burn_in, pol=False):
     cap skip it, which over-prices them slightly); `pol`: with polarisation."""
     m = workload["mosaic"]
     M = mix_mwg(workload["crystal"]["geometry"], m["kind"], workload["rocking_curve"]["kind"],
-                workload["source"]["spectrum"], psi_nodes, burn_in, pol)
+                workload["source"]["spectrum"], psi_nodes, burn_in, pol,
+                vmf_live_fraction(m["fwhm"], psi_nodes))
     c = counters
     entered = c["emitted"] - c["missed"]
     return (c["emitted"] * M["ray"] + entered * M["entered"] + c["events"] * M["event"]

@@ -68,3 +68,18 @@ def test_polarised_model_pricing_adds_work_per_event_and_sweep():
     assert b["event"] > a["event"] and b["sweep"] > a["sweep"]
     assert b["reflection"] - a["reflection"] > 500 * (b["sweep"] - a["sweep"])
     assert b["ray"] == a["ray"] and b["detected"] == a["detected"]
+
+
+def test_vmf_live_share_of_the_quadrature():
+    """The share of psi nodes whose vMF exponential is priced grows with the
+    mosaic width and stays in (0, 1]; past it exp(-kappa b) is exactly zero
+    (pinned in test_device_math)."""
+    import math
+    deg = math.pi / 180.0
+    shares = [op_costs.vmf_live_fraction(f * deg, 256) for f in (0.02, 0.1, 0.4, 0.8, 5.0, 60.0)]
+    assert all(0.0 < x <= 1.0 for x in shares)
+    assert shares == sorted(shares) and shares[0] < shares[-1] == 1.0
+    # fewer priced exponentials price the quadrature lower
+    a = op_costs.mix_mwg("cylinder", "pseudo_voigt", "pseudo_voigt", "lines", 256, 500, vmf_live=0.2)
+    b = op_costs.mix_mwg("cylinder", "pseudo_voigt", "pseudo_voigt", "lines", 256, 500, vmf_live=1.0)
+    assert a["quadrature"] < b["quadrature"]
