@@ -106,13 +106,14 @@ __device__ __forceinline__ double sqrt(double x) {
     return x == 0.0 ? 0.0 : g;
 }
 
+// 1/sqrt(x) from the hardware seed y (about 2^-24 off) by one third-order
+// step: with e = 1 - x y^2, 1/sqrt(x) = y (1 - e)^(-1/2) = y (1 + e/2 +
+// 3e^2/8 + ...), the e^3 term below 2^-70.  Five operations and a chain of
+// four, where two Newton steps take seven and six.
 __device__ __forceinline__ double rsqrt(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    double e = fma(-h * y, y, 0.5);
-    y = fma(y, e, y);
-    e = fma(-h * y, y, 0.5);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 // ---------------------------------------------------------------------------

@@ -67,7 +67,12 @@ inline double __longlong_as_double(long long x) { double r; memcpy(&r, &x, 8); r
 inline float __uint_as_float(unsigned int x) { float r; memcpy(&r, &x, 4); return r; }
 inline unsigned int __float_as_uint(float x) { unsigned int r; memcpy(&r, &x, 4); return r; }
 
-inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
+// The hardware's FP64 reciprocal and reciprocal square root are seeds about
+// 2^-24 off (v_rsq_f64 measured at 5.5e-8 relative); `simt_seed_rel` gives
+// the emulated seeds that relative error, so a test can check the routines
+// that refine them.
+inline thread_local double simt_seed_rel = 0.0;
+inline double __builtin_amdgcn_rcp(double x) { return (1.0 / x) * (1.0 + simt_seed_rel); }
 // Three-input bitwise operation by truth table: result bit i is bit
 // (a_i << 2 | b_i << 1 | c_i) of imm (0x96 is the three-input XOR, whose
 // table does not depend on the order of the inputs).
@@ -83,7 +88,7 @@ inline double __dadd_rn(double a, double b) { return a + b; }
 inline double __dsub_rn(double a, double b) { return a - b; }
 inline double __dmul_rn(double a, double b) { return a * b; }
 inline double __ddiv_rn(double a, double b) { return a / b; }
-inline double __builtin_amdgcn_rsq(double x) { return 1.0 / std::sqrt(x); }
+inline double __builtin_amdgcn_rsq(double x) { return (1.0 / std::sqrt(x)) * (1.0 + simt_seed_rel); }
 // The hardware's FP32 reciprocal, square root and exp2 are within 1 ulp, not
 // correctly rounded.  `simt_ulp_bias` (-1, 0, +1) moves their results one
 // float toward -inf / +inf, so a test can bracket the device's answers.

@@ -6,9 +6,10 @@
 // against its definition ((w >> 9) 2 + 1) 2^-24 in exact arithmetic, over all
 // 2^23 values of w >> 9, and the FP64 uniform (w + 1/2) 2^-32 on 2^24 words.
 // And log_u01 and sincos_u01 (the forms fed by the word) bit for bit equal
-// to log_pos and sincos_turns of the word's uniform.  Prints "log L sin S cos
-// C exp X u01_f32_mismatches M u01_identity_mismatches I" (M counts both
-// uniforms).
+// to log_pos and sincos_turns of the word's uniform.  And rcp, div, sqrt and
+// rsqrt from seeds 2^-23 off.  Prints "log L sin S cos C exp X
+// u01_f32_mismatches M u01_identity_mismatches I rcp R sqrt Q rsqrt T" (M
+// counts both uniforms, R covers rcp and div).
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdio>
@@ -122,6 +123,23 @@ int main() {
     }
     for (uint32_t w : {0u, 1u, 0xffffffffu, 0x80000000u})
         if ((long double)dm::u01_f64(w) != ((long double)w + 0.5L) * 0x1p-32L) ++mismatches;
+    // reciprocal, quotient, square root and reciprocal square root from
+    // seeds exact and 2^-23 off either way (twice the hardware's), over 80
+    // binades
+    double worst_rcp = 0, worst_sqrt = 0, worst_rsqrt = 0;
+    for (double rel : {0.0, 0x1p-23, -0x1p-23}) {
+        simt_seed_rel = rel;
+        for (long i = 0; i < n_wide; ++i) {
+            s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+            const double x = std::ldexp(1.0 + (double)(s >> 11) * 0x1p-53, (int)(s % 80) - 40);
+            const double y = std::ldexp(1.0 + (double)(s >> 23) * 0x1p-41, (int)((s >> 7) % 40) - 20);
+            worst_rcp = std::fmax(worst_rcp, ulp_err(dm::rcp(x), 1.0L / (long double)x));
+            worst_rcp = std::fmax(worst_rcp, ulp_err(dm::div(y, x), (long double)y / (long double)x));
+            worst_sqrt = std::fmax(worst_sqrt, ulp_err(dm::sqrt(x), sqrtl((long double)x)));
+            worst_rsqrt = std::fmax(worst_rsqrt, ulp_err(dm::rsqrt(x), 1.0L / sqrtl((long double)x)));
+        }
+    }
+    simt_seed_rel = 0.0;
     // the uniform-fed forms against the general ones on the uniform, bit for
     // bit: 2^24 words spread over the range, every word within 64 of the
     // points where the integer reduction changes (bit 23 set or clear, the
@@ -140,8 +158,10 @@ int main() {
     for (uint32_t top = 0; top < 256; ++top)
         for (uint32_t edge : {0u, 0x7fffffu, 0x800000u, 0xffffffu})
             for (int d = -64; d <= 64; ++d) check((top << 24) + edge + (uint32_t)d);
-    printf("log %.4f sin %.4f cos %.4f exp %.4f u01_f32_mismatches %ld u01_identity_mismatches %ld\n",
-           worst_log, worst_sin, worst_cos, worst_exp, mismatches, identity);
+    printf("log %.4f sin %.4f cos %.4f exp %.4f u01_f32_mismatches %ld u01_identity_mismatches %ld "
+           "rcp %.4f sqrt %.4f rsqrt %.4f\n",
+           worst_log, worst_sin, worst_cos, worst_exp, mismatches, identity, worst_rcp, worst_sqrt,
+           worst_rsqrt);
     (void)wl_x;
     (void)ws_x;
 }

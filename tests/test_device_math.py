@@ -4,7 +4,8 @@ device_math.h) compiled for the host and compared with long-double
 references: a few ulps at most, far inside the 1e-12 per-ray parity
 contract; the FP32 uniform equal to its definition for every word; and
 the word-fed log and sin/cos (log_u01, sincos_u01) bit for bit equal to the
-general routines on the word's uniform."""
+general routines on the word's uniform; and the reciprocal, quotient, square
+root and reciprocal square root within an ulp or so from seeds 2^-23 off."""
 import os
 import shutil
 import subprocess
@@ -31,3 +32,5 @@ def test_fp64_log_and_sincos_within_two_ulps(tmp_path):
     assert err["exp"] <= 2.0, err
     assert err["u01_f32_mismatches"] == 0
     assert err["u01_identity_mismatches"] == 0
+    # from hardware seeds 2^-23 off (twice v_rsq_f64's measured error)
+    assert err["rcp"] <= 1.0 and err["sqrt"] <= 1.0 and err["rsqrt"] <= 1.5, err
