@@ -71,11 +71,11 @@ __device__ __forceinline__ double poly_step(double p, double z, double c) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 reciprocal, quotient, square root and reciprocal square root from the
-// hardware seeds (v_rcp_f64, v_rsq_f64) by Newton-Raphson and Goldschmidt
-// iterations (Markstein, "IA-64 and Elementary Functions", ch. 8), with a
-// final residual correction.  Arguments are positive normal numbers; sqrt
-// also returns 0 for 0.
+// FP64 reciprocal, quotient and square root from the hardware seeds
+// (v_rcp_f64, v_rsq_f64) by Newton-Raphson and Goldschmidt iterations
+// (Markstein, "IA-64 and Elementary Functions", ch. 8), with a final
+// residual correction; the reciprocal square root by one third-order step
+// (below).  Arguments are positive normal numbers; sqrt also returns 0 for 0.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double rcp(double d) {
     double r = __builtin_amdgcn_rcp(d);
