@@ -419,10 +419,15 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
         const double proj = pc * (1.0 - 2.0 * x.sp * x.sp) + ps * (2.0 * x.sp * x.cp);
         return f * (1.0 - x.s2b * proj * proj);
     }
+    // (sa, ca: sin and cos of alpha.)  Without polarisation cos(b) comes
+    // from the same sin/cos as sin((alpha - b) / 2): with d = (alpha - b) / 2,
+    // cos(b) = cos(alpha) (1 - 2 sin^2 d) + sin(alpha) 2 sin(d) cos(d).  The
+    // two terms cancel only as b nears 90 deg, where the relative error grows
+    // as 1 / cos(b) (a few ulps at cos(b) = 0.05).
     static __device__ __forceinline__ void at_delta(const TraceParams &P, const double *lut,
-                                                    double alpha, double ab, double delta,
-                                                    double shift, double scale, bool polar,
-                                                    Point &x) {
+                                                    double alpha, double sa, double ca, double ab,
+                                                    double delta, double shift, double scale,
+                                                    bool polar, Point &x) {
         const double b = ab + delta;
         // a further plane set reads the curve at (Delta - its shift) / its scale
         x.r = B::irc_ratio(P, lut, scale == 1.0 ? delta - shift : (delta - shift) / scale);
@@ -431,10 +436,13 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             sincos_(b, &sb, &x.cb);
             const double s2 = 2.0 * sb * x.cb;
             x.s2b = s2 * s2;
+            x.sab = sin_((alpha - b) / 2.0);
         } else {
-            x.cb = cos_(b);
+            double sd, cd;
+            sincos_((alpha - b) / 2.0, &sd, &cd);
+            x.sab = sd;
+            x.cb = fma(ca, fma(-2.0 * sd, sd, 1.0), 2.0 * sa * sd * cd);
         }
-        x.sab = sin_((alpha - b) / 2.0);
     }
 
     // ---- Metropolis-within-Gibbs draw and the reflection -----------------
@@ -473,7 +481,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             if (polar && ca > 0.0) pol_frame(ry.pol, Ns, ry.k, sa, ca, pc, ps);
         }
         Point x;
-        at_delta(P, lut, alpha, ab, delta, shift, scale, polar, x);
+        at_delta(P, lut, alpha, sa, ca, ab, delta, shift, scale, polar, x);
         x.sp = 0.0;   // sin(0 / 2)
         x.cp = 1.0;
         double f = value(P, x, ca, polar, pc, ps);
@@ -494,7 +502,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             const double dn = delta + w_delta * (2.0 * dm::u01_f64(w.w2) - 1.0);
             if (!P.irc_off && dn >= lo && dn <= hi) {   // the IRC disabled: Delta stays
                 y = x;
-                at_delta(P, lut, alpha, ab, dn, shift, scale, polar, y);
+                at_delta(P, lut, alpha, sa, ca, ab, dn, shift, scale, polar, y);
                 fn = value(P, y, ca, polar, pc, ps);
                 if (dm::u01_f64(w.w3) * f < fn || f == 0.0) {
                     delta = dn;

@@ -304,10 +304,12 @@ def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False, vmf_
     event = (OP_COSTS["philox"] + 3 * 2 * a + exit_d + frame + 5 * a + quad
              + D["log"] + 2 * D["div"] + 14 * a)
     R = _irc_cost(irc)
+    # a Delta move takes cos(b) from the half angle's sin/cos (one sincos
+    # and five operations)
     sweep = (OP_COSTS["philox"] + 4 * 2 * a + 9 * a + sc + (W + 8 * a) + 3 * a
-             + 7 * a + R + 2 * sc + 4 * a + (W + 8 * a) + 3 * a)
+             + 7 * a + R + sc + 9 * a + (W + 8 * a) + 3 * a)
     orient = 2 * sc + 3 * D["div"] + 15 * a + 9 * a + 5 * a + 15 * a + 11 * a + D["sqrt"] + 3 * D["div"]
-    reflection = (D["asin"] + sc + D["div"] + sc + R + 2 * sc + 3 * a + W + burn_in * sweep
+    reflection = (D["asin"] + sc + D["div"] + sc + R + sc + 5 * a + 3 * a + W + burn_in * sweep
                   + orient)
     if pol:
         # Eq. SimpleReflXsectionPol: the sum of W cos(2 psi) beside the plain
@@ -319,9 +321,12 @@ def mix_mwg(geometry, mosaic, irc, spectrum, psi_nodes, burn_in, pol=False, vmf_
         # reflection
         frame_p = 6 * D["div"] + 30 * a + D["sqrt"] + D["div"] + 4 * a
         event += psi_nodes * 2 * a + frame_p + sc + 8 * a
-        sweep_extra = 2 * 6 * a + 3 * a
+        # (the polarised Delta move keeps the sin/cos of b beside the half
+        # angle's sine)
+        sweep_extra = 2 * 6 * a + 3 * a + sc - 5 * a
         sweep += sweep_extra
-        reflection += frame_p + burn_in * sweep_extra + 14 * a + D["sqrt"] + 3 * D["div"]
+        reflection += (frame_p + sc - 5 * a + burn_in * sweep_extra + 14 * a + D["sqrt"]
+                       + 3 * D["div"])
     return {"ray": base["ray"], "entered": base["entered"], "event": event,
             "reflection": reflection, "detected": base["detected"], "sweep": sweep,
             "quadrature": quad}
