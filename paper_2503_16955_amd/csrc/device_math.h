@@ -12,6 +12,14 @@
 
 #include "math_tables.h"
 
+// Pointer qualifier for read-only device tables read at wave-uniform
+// indices: the constant address space, whose uniform loads the compiler
+// issues as scalar loads.  (Host builds of the device code for tests define
+// it empty.)
+#ifndef MRT_CONST_AS
+#define MRT_CONST_AS __attribute__((address_space(4)))
+#endif
+
 namespace mrt {
 namespace dm {
 

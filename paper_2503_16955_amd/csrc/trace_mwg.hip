@@ -163,13 +163,16 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
                 ga = density<K>(P, v0a + b);
             }
         };
-        const double *tab = P.psi_tab;
+        // the node tables through the constant address space: their
+        // indices are wave-uniform, so the reads are scalar loads
+        const MRT_CONST_AS double *tab = (const MRT_CONST_AS double *)P.psi_tab;
+        const MRT_CONST_AS double *tc2 = (const MRT_CONST_AS double *)P.psi_cos2;
         double gh, ga;
         node(0.0, gh, ga);
         double sum_h = tab[1] * gh, sum_a = tab[1] * ga, s2h = 0.0, s2a = 0.0;
         if constexpr (C2) {
-            s2h = P.psi_cos2[0] * gh;
-            s2a = P.psi_cos2[0] * ga;
+            s2h = tc2[0] * gh;
+            s2a = tc2[0] * ga;
         }
         for (int j = 1; j <= P.psi_nodes; ++j) {
             const double t = tab[2 * j], wj = tab[2 * j + 1];
@@ -177,7 +180,7 @@ struct MwgTracer : Tracer<double, GEOM, kAny, kAny, REC, true, POL> {
             sum_h = fma(wj, gh, sum_h);
             sum_a = fma(wj, ga, sum_a);
             if constexpr (C2) {
-                const double wc = P.psi_cos2[j];
+                const double wc = tc2[j];
                 s2h = fma(wc, gh, s2h);
                 s2a = fma(wc, ga, s2a);
             }

@@ -21,6 +21,7 @@ void simt_check_failed(const char *cond, const char *file, int line);
 #define __launch_bounds__(...)
 #define __shared__
 #define __constant__
+#define MRT_CONST_AS
 
 struct simt_dim3 {
     unsigned x, y, z;
