@@ -60,11 +60,13 @@ __device__ __forceinline__ Words philox(uint32_t k0, uint32_t k1, uint32_t c0, u
 // registers at every use.)
 __device__ __forceinline__ double odd_u01(uint32_t w) { return __builtin_fma((double)w, 2.0, 1.0); }
 __device__ __forceinline__ double u01_f64(uint32_t w) { return __builtin_ldexp(odd_u01(w), -33); }
-// 23 random bits, exact in float: ((w >> 9) + 1/2) 2^-23, as one fused
-// multiply-add of the exactly converted w >> 9 (the result has 24
-// significant bits, so nothing rounds).
+// 23 random bits, exact in float: ((w >> 9) + 1/2) 2^-23.  One funnel
+// shift places w >> 9 under the exponent of 1.0 (the float 1 + (w >> 9)
+// 2^-23), and subtracting 1 - 2^-24 leaves (2 (w >> 9) + 1) 2^-24 exactly
+// (the operands are within a factor 2, and the result has 24 significant
+// bits): two instructions for the shift, conversion and FMA.
 __device__ __forceinline__ float u01_f32(uint32_t w) {
-    return __builtin_fmaf((float)(w >> 9), 0x1p-23f, 0x1p-24f);
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u)) - 0x1.fffffep-1f;
 }
 
 // Polynomial step p z + c as the three-operand v_fma_f64 with the constant

@@ -85,6 +85,10 @@ inline uint32_t __builtin_amdgcn_bitop3_b32(uint32_t a, uint32_t b, uint32_t c, 
     }
     return r;
 }
+// Funnel shift: the low 32 bits of the 64-bit (a:b) shifted right by s mod 32.
+inline uint32_t __builtin_amdgcn_alignbit(uint32_t a, uint32_t b, uint32_t s) {
+    return (uint32_t)(((((uint64_t)a) << 32) | b) >> (s & 31u));
+}
 inline double __dadd_rn(double a, double b) { return a + b; }
 inline double __dsub_rn(double a, double b) { return a - b; }
 inline double __dmul_rn(double a, double b) { return a * b; }
