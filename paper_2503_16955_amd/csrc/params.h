@@ -32,10 +32,13 @@ void build_params(const mrt_source *s, const mrt_crystal *c, const mrt_mosaic *m
 // per-event work they change).  Source spots and user origins, directions
 // and energies only change a ray's start, which every kernel takes.
 bool uses_ext(const mrt_source *s, const mrt_crystal *c, const mrt_rocking_curve *r);
-// Default refill threshold (lanes idle before a wave refills): 12 for the
-// plain kernels (2-4% faster than 8 on the flat and von Hamos workloads),
-// 8 for the extended kernels and the paper's model (2-5% faster than 12).
-inline uint32_t default_refill(bool ext_or_mwg) { return ext_or_mwg ? 8u : 12u; }
+// Default refill threshold (lanes idle before a wave refills): for the
+// plain kernels 14 in FP64 (1% faster than 12 on the von Hamos workload,
+// equal on the flat one) and 12 in FP32-mixed (2-4% faster than 8), 8 for
+// the extended kernels and the paper's model (2-5% faster than 12).
+inline uint32_t default_refill(bool ext_or_mwg, bool f64) {
+    return ext_or_mwg ? 8u : (f64 ? 14u : 12u);
+}
 
 // The paper's event model: fill its part of the parameter block (sampler
 // sweeps, quadrature intervals, batch, reflection strength, density

@@ -173,7 +173,7 @@ mrt_status prepare(const mrt_source *source, const mrt_crystal *crystal, const m
         L.grid = cus * per_cu;
     }
     P.refill_idle = opt.refill_idle > 0 ? (uint32_t)opt.refill_idle
-                                        : mrt::default_refill(mwg || ext);
+                                        : mrt::default_refill(mwg || ext, opt.precision == MRT_FP64);
     // chunk size: enough chunks for every wave to claim several
     const uint64_t waves = (uint64_t)L.grid * (uint64_t)(L.block / 64);
     uint64_t chunk = n_rays / (waves * 8);

@@ -144,7 +144,7 @@ bool admit_one(mrt_server *S, uint64_t ticket) {
     P.dep = P.dep_n > 0 ? r.d_tables + P.dep_at : nullptr;
     P.dev_counters = S->d_counters + (size_t)slot * mrt::kNumCounters;
     P.records_mode = MRT_RECORDS_NONE;
-    P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : mrt::default_refill(r.ext);
+    P.refill_idle = S->cfg.refill_idle > 0 ? (uint32_t)S->cfg.refill_idle : mrt::default_refill(r.ext, S->cfg.precision == MRT_FP64);
     double *ht = S->h_tables + (size_t)slot * (mrt::kMaxStagedTableBytes / sizeof(double));
     if (!r.tables.empty()) {
         std::memcpy(ht, r.tables.data(), r.tables.size() * sizeof(double));
