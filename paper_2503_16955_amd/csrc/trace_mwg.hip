@@ -659,8 +659,15 @@ __device__ __forceinline__ void mwg_loop(const TraceParams &P, const double *lut
     flush(P, cnt);
 }
 
+// At least 4 waves per SIMD for the instances without polarisation or plane
+// sets: held to 128 VGPRs they spill about 27 to scratch outside the
+// quadrature and sampler loops, and the extra wave per SIMD hides more of
+// the loops' latency (von Hamos 2%, flat 5% faster).  The others keep the
+// compiler's choice (they need 160-210 VGPRs).
+template <bool POL, bool PLANES>
+constexpr int kMwgMinWaves = POL || PLANES ? 1 : 4;
 template <int GEOM, bool REC, bool POL, bool PLANES = false>
-__global__ void __launch_bounds__(256) mwg_kernel(const TraceParams P) {
+__global__ void __launch_bounds__(256, (kMwgMinWaves<POL, PLANES>)) mwg_kernel(const TraceParams P) {
     using T = MwgTracer<GEOM, REC, POL, PLANES>;
     const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
     RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
