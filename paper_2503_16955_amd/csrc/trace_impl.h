@@ -1303,8 +1303,13 @@ struct KindRun {
 // counter of the scalar parameter loads; the stress workload ran 10-11%
 // faster without it in both precisions.
 // ---------------------------------------------------------------------------
+// At least 6 waves per SIMD for the FP64 flat-crystal instances (about 80
+// VGPRs, a few spilled): flat HOPG and the stress workload 2-3% faster; the
+// FP64 cylinder instances ran 2% slower so bound, and keep 5.
+template <class R, int GEOM>
+constexpr int kTraceMinWaves = sizeof(R) == 8 && GEOM == MRT_GEOMETRY_FLAT ? 6 : 1;
 template <class R, int GEOM, int MDF, int IRC, bool REC>
-__global__ void __launch_bounds__(256) trace_kernel(const TraceParams P) {
+__global__ void __launch_bounds__(256, (kTraceMinWaves<R, GEOM>)) trace_kernel(const TraceParams P) {
     using T = Tracer<R, GEOM, MDF, IRC, REC>;
     const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
     RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
