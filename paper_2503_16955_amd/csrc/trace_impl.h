@@ -1325,8 +1325,14 @@ __global__ void __launch_bounds__(256, (kTraceMinWaves<R, GEOM>)) trace_kernel(c
 // polarisations, further plane sets), specialised for the kinds like the
 // plain kernels (reading the kinds at run time made these kernels 6-17%
 // slower).
+// One wave per SIMD more than the compiler's choice: 5 in FP64 (at most 96
+// VGPRs), 6 in FP32-mixed (at most 80).  Plane sets run 5% (FP64) and 3.5%
+// faster, polarisation 0.5% and 3.3%, the energy-dependent curve 2.9%
+// slower in FP64 and 0.6% faster in FP32-mixed (von Hamos, 5e7 rays).
+template <class R>
+constexpr int kExtMinWaves = sizeof(R) == 8 ? 5 : 6;
 template <class R, int GEOM, int MDF, int IRC, bool REC>
-__global__ void __launch_bounds__(256) trace_kernel_ext(const TraceParams P) {
+__global__ void __launch_bounds__(256, (kExtMinWaves<R>)) trace_kernel_ext(const TraceParams P) {
     using T = Tracer<R, GEOM, MDF, IRC, REC, true>;
     const TraceParams &Q = *(const TraceParams *)__builtin_amdgcn_kernarg_segment_ptr();
     RangeClaim claim{Q.chunk_counter, Q.first, Q.n, Q.chunk};
